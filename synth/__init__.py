@@ -1,0 +1,20 @@
+"""Seeded synthetic inputs for the space-time heat-equation workloads.
+
+This package only *draws* problem data (coefficient fields, sources, initial
+data) with numpy's PCG64 generator.  It contains none of the solver's
+arithmetic: no spatial operator, no time stepping, no transform.  Both the CPU
+oracle and the GPU library consume what it produces, and neither imports the
+other.
+"""
+from .workloads import (  # noqa: F401
+    Problem,
+    heat1d_random,
+    heat2d_gaussians,
+    heat3d_lognormal,
+    batch2d,
+    lognormal_field,
+    manufactured_u,
+    small_problem,
+    batch2d_problem,
+    CONFIG_BUILDERS,
+)
