@@ -1,0 +1,151 @@
+/*
+ * stp.h -- C ABI of the MI355X space-time parabolic solver.
+ *
+ * Solves the implicit-Euler discretisation (eq. (2.1) of Neumueller & Smears,
+ * "Time-parallel iterative solvers for parabolic evolution equations")
+ *
+ *     (u_n - u_{n-1}) + tau A_n u_n = tau F_n,   n = 1..N,   u_0 = u0,
+ *
+ * of  u_t - div(kappa(t,x) grad u) = F  on the unit d-cube (d = 1, 2, 3) with
+ * homogeneous Dirichlet conditions, by the inexact Uzawa iteration (eq. (3.1))
+ * on the symmetric saddle-point reformulation (eq. (2.7)), preconditioned by
+ * the block-diagonal A-tilde (eq. (3.2)) and the DST-in-time Schur complement
+ * preconditioner H-tilde (eqs. (4.4)-(4.6)).  All N time slabs are processed
+ * together in every kernel launch on one GPU.
+ *
+ * Spatial discretisation (the paper leaves it abstract): n interior nodes per
+ * axis, h = 1/(n+1), lumped mass M = I, conservative 3/5/7-point stencil
+ *     (A u)_i = h^-2 sum_{faces f of i} kappa_f (u_i - u_nb(f)),
+ * with kappa_f the arithmetic mean of the two nodal values the face joins.
+ *
+ * Memory layout of every grid vector: slab-major, x fastest:
+ *     v[((s * n + z) * n + y) * n + x]     (s = time slab n-1, 0-based)
+ * Vectors on the time-global space hold N * n^d float64 values.
+ *
+ * Conventions for every entry point
+ *   - Pointers documented "device" must point to GPU memory of the device that
+ *     is current when stp_create is called; "host" pointers to CPU memory.
+ *   - All work is enqueued on the HIP stream given to stp_create (NULL = the
+ *     null stream).  stp_apply_* are asynchronous; stp_uzawa_solve returns
+ *     after the solve has finished.
+ *   - Errors are reported by the return code only (no exceptions cross the
+ *     ABI); stp_last_error() gives a human-readable detail for the calling
+ *     thread.  On error no output buffer is written unless stated otherwise.
+ *   - Input and output buffers of one call must not overlap.
+ */
+#ifndef STP_H
+#define STP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STP_OK = 0,
+  STP_EINVAL = -1,       /* invalid argument (sizes, pointers, tau, kappa)      */
+  STP_ENOMEM = -2,       /* device allocation failed / workspace too small       */
+  STP_EDEVICE = -3,      /* a HIP call failed                                    */
+  STP_ENOTCONV = -4,     /* max_iter reached; u, p hold the last iterate         */
+  STP_EDIVERGED = -5,    /* non-finite or exploding residual; last finite iterate is not kept */
+  STP_EUNSUPPORTED = -6  /* valid request this build does not implement          */
+} stp_status;
+
+#define STP_MAX_RANK 4      /* max separable terms of kappa(t,x)               */
+#define STP_MAX_LEVELS 16
+
+enum { STP_PREC_F64 = 0,    /* everything in float64                                      */
+       STP_PREC_F32 = 1,    /* preconditioner (V-cycles, DST, H-blocks) in float32        */
+       STP_PREC_BF16 = 2 }; /* preconditioner vectors stored as bfloat16, float32 math     */
+
+enum { STP_SPATIAL_AUTO = 0,   /* exact tridiagonal solves in 1-D, multigrid in 2-D/3-D   */
+       STP_SPATIAL_MG = 1,     /* nu V-cycles of geometric multigrid (needs n = 2^L - 1)  */
+       STP_SPATIAL_EXACT = 2,  /* exact spatial solves (1-D only)                          */
+       STP_SPATIAL_NONE = 3 }; /* operators only: stp_apply_precond / stp_uzawa_solve
+                                  return STP_EUNSUPPORTED; any n allowed                   */
+
+enum { STP_OP_B = 0,        /* y = B x = (K + A) x, eq. (2.3); x, y: N*n^d              */
+       STP_OP_SADDLE = 1 }; /* [y_p; y_u] = saddle [x_p; x_u], eq. (2.7); 2*N*n^d each  */
+
+enum { STP_PC_A = 0,        /* z = A-tilde^{-1} r, eq. (3.2)                            */
+       STP_PC_H = 1 };      /* z = H-tilde^{-1} r = Phi^{-1} Hhat_approx^{-1} Phi^{-T} r, eq. (4.6) */
+
+typedef struct stp_ctx stp_ctx;
+
+typedef struct {
+  int dim;  /* 1, 2 or 3 */
+  int n;    /* interior nodes per axis (>= 1); multigrid needs n = 2^L - 1 */
+} stp_grid;
+
+/* kappa(t_n, x) = sum_{r<rank} tcoef[r*N + (n-1)] * fields[r](x), every value > 0. */
+typedef struct {
+  int rank;              /* 1..STP_MAX_RANK                                          */
+  const double* fields;  /* device, rank x (n+2)^dim nodal values incl. boundary,
+                            x fastest; borrowed until stp_destroy                     */
+  const double* tcoef;   /* host, rank x N; copied by stp_create                      */
+} stp_kappa;
+
+typedef struct {
+  int precision;        /* STP_PREC_*                                                */
+  int spatial;          /* STP_SPATIAL_*                                             */
+  int nu_A, nu_H;       /* V-cycles per spatial preconditioner application (>= 1)    */
+  double omega;         /* Uzawa damping (eq. (3.1)); <= 0 selects the default 0.8   */
+  double tol;           /* stop at ||f - B u||_2 <= tol ||f||_2                      */
+  int max_iter;         /* maximum number of u-updates                               */
+  const double* kref_coef; /* host, rank values: kappa_ref = sum_r kref_coef[r] fields[r]
+                              for the reference operator A of eq. (2.2); NULL = time mean */
+  int check_every;      /* iterations enqueued between host checks of the stop flag  */
+  int use_graph;        /* 1: replay each iteration as a captured HIP graph          */
+} stp_options;
+
+typedef struct {
+  int iters;            /* number of u-updates performed (j of the returned u_j)     */
+  double rel_res;       /* ||f - B u_j||_2 / ||f||_2 of the returned u_j             */
+  double omega_used;
+  double t_solve_ms;    /* device time of the iteration loop (HIP events)            */
+  int status;           /* stp_status of the solve                                   */
+} stp_stats;
+
+/* Fill *opt with defaults: F64, AUTO, nu = 1, omega 0.8, tol 1e-8, max_iter 500,
+   time-mean kappa_ref, check_every 8, graphs on. */
+void stp_default_options(stp_options* opt);
+
+/* Device bytes stp_create needs as workspace for this problem and options. */
+size_t stp_workspace_bytes(const stp_grid* g, int N, int rank, const stp_options* opt);
+
+/* Set up one problem (Section 2 problem statement): grid, N steps of length tau,
+ * kappa, source F (device, N x n^d: F_n on the interior nodes) and initial datum
+ * u0 (device, n^d).  F, u0 and kappa->fields are borrowed until stp_destroy.
+ * workspace: device buffer of >= stp_workspace_bytes (256-byte aligned), or NULL
+ * to let the library allocate (and free) its own.  hip_stream: hipStream_t or NULL.
+ * Errors: EINVAL (dim not 1..3, n < 1, N < 1, tau <= 0 or not finite, rank out of
+ * range, NULL pointers, some kappa <= 0), EUNSUPPORTED (MG with n != 2^L - 1,
+ * EXACT with dim > 1, nu != 1), ENOMEM, EDEVICE. */
+stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau,
+                      const stp_kappa* kappa, const double* F, const double* u0,
+                      const stp_options* opt, void* workspace, size_t ws_bytes,
+                      void* hip_stream);
+
+/* y = op x on device buffers (layouts above), float64. */
+stp_status stp_apply_operator(stp_ctx* ctx, int op, const double* x, double* y);
+
+/* z = preconditioner^{-1} r on device float64 buffers (N x n^d), computed in the
+ * context's precision. */
+stp_status stp_apply_precond(stp_ctx* ctx, int which, const double* r, double* z);
+
+/* Inexact Uzawa iteration, eq. (3.1), from the initial guess held in u and p
+ * (device, N x n^d float64 each, both required; zero them to start from zero).
+ * On return u = u_j with j = st->iters, p = p_{j+1}.  Returns OK, ENOTCONV
+ * (max_iter reached, the last iterate is returned) or EDIVERGED (the iterate
+ * is not meaningful).  st may be NULL. */
+stp_status stp_uzawa_solve(stp_ctx* ctx, double* u, double* p, stp_stats* st);
+
+void stp_destroy(stp_ctx* ctx);
+const char* stp_status_string(stp_status s);
+const char* stp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STP_H */

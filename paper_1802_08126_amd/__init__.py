@@ -1,0 +1,32 @@
+"""MI355X-native space-time parallel solver for linear parabolic equations.
+
+Implements the inexact Uzawa iteration on the symmetric saddle-point form of
+implicit Euler with the DST-in-time Schur complement preconditioner
+(Neumueller & Smears, "Time-parallel iterative solvers for parabolic evolution
+equations", Sections 2-4) as hand-written HIP kernels for gfx950 behind the C
+ABI of include/stp.h.  This package is the ctypes binding of that library.
+"""
+from .binding import (  # noqa: F401
+    STP_OP_B,
+    STP_OP_SADDLE,
+    STP_PC_A,
+    STP_PC_H,
+    STP_OK,
+    STP_EINVAL,
+    STP_ENOMEM,
+    STP_EDEVICE,
+    STP_ENOTCONV,
+    STP_EDIVERGED,
+    STP_EUNSUPPORTED,
+    SpaceTimeSolver,
+    StpError,
+    from_problem,
+    lib_path,
+    load,
+    stp_apply_operator,
+    stp_apply_precond,
+    stp_create,
+    stp_destroy,
+    stp_uzawa_solve,
+    stp_workspace_bytes,
+)

@@ -1,0 +1,249 @@
+"""ctypes binding of libstp.so (include/stp.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch supplies device memory and the stream.  The module-level functions
+carry the C names; ``SpaceTimeSolver`` wraps one context.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libstp.so")
+_lib = None
+
+STP_OK, STP_EINVAL, STP_ENOMEM, STP_EDEVICE, STP_ENOTCONV, STP_EDIVERGED, STP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STP_PREC = {"f64": 0, "f32": 1, "bf16": 2}
+STP_SPATIAL = {"auto": 0, "mg": 1, "exact": 2, "none": 3}
+STP_OP_B, STP_OP_SADDLE = 0, 1
+STP_PC_A, STP_PC_H = 0, 1
+STP_MAX_RANK = 4
+
+
+class StpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class stp_grid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int)]
+
+
+class stp_kappa(C.Structure):
+    _fields_ = [("rank", C.c_int), ("fields", C.c_void_p), ("tcoef", C.POINTER(C.c_double))]
+
+
+class stp_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("spatial", C.c_int), ("nu_A", C.c_int), ("nu_H", C.c_int),
+                ("omega", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int),
+                ("kref_coef", C.POINTER(C.c_double)), ("check_every", C.c_int), ("use_graph", C.c_int)]
+
+
+class stp_stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("rel_res", C.c_double), ("omega_used", C.c_double),
+                ("t_solve_ms", C.c_double), ("status", C.c_int)]
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load() -> C.CDLL:
+    """Load libstp.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"libstp.so not built at {_LIB_PATH}; run python -m paper_1802_08126_amd.build_lib")
+    lib = C.CDLL(_LIB_PATH)
+    lib.stp_default_options.argtypes = [C.POINTER(stp_options)]
+    lib.stp_default_options.restype = None
+    lib.stp_workspace_bytes.argtypes = [C.POINTER(stp_grid), C.c_int, C.c_int, C.POINTER(stp_options)]
+    lib.stp_workspace_bytes.restype = C.c_size_t
+    lib.stp_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(stp_grid), C.c_int, C.c_double,
+                               C.POINTER(stp_kappa), C.c_void_p, C.c_void_p, C.POINTER(stp_options),
+                               C.c_void_p, C.c_size_t, C.c_void_p]
+    lib.stp_create.restype = C.c_int
+    lib.stp_apply_operator.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+    lib.stp_apply_operator.restype = C.c_int
+    lib.stp_apply_precond.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+    lib.stp_apply_precond.restype = C.c_int
+    lib.stp_uzawa_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(stp_stats)]
+    lib.stp_uzawa_solve.restype = C.c_int
+    lib.stp_destroy.argtypes = [C.c_void_p]
+    lib.stp_destroy.restype = None
+    lib.stp_status_string.argtypes = [C.c_int]
+    lib.stp_status_string.restype = C.c_char_p
+    lib.stp_last_error.argtypes = []
+    lib.stp_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status, what):
+    if status != STP_OK:
+        lib = load()
+        raise StpError(status, f"{what}: {lib.stp_status_string(status).decode()}: {lib.stp_last_error().decode()}")
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if tuple(t.shape) != tuple(shape) and t.numel() != int(np.prod(shape)):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def make_options(precision="f64", spatial="auto", omega=0.8, tol=1e-8, max_iter=500, kref_coef=None,
+                 check_every=8, use_graph=True, nu_A=1, nu_H=1):
+    o = stp_options()
+    load().stp_default_options(C.byref(o))
+    o.precision = STP_PREC[precision]
+    o.spatial = STP_SPATIAL[spatial]
+    o.nu_A, o.nu_H = nu_A, nu_H
+    o.omega = omega
+    o.tol = tol
+    o.max_iter = max_iter
+    o.check_every = check_every
+    o.use_graph = 1 if use_graph else 0
+    keep = None
+    if kref_coef is not None:
+        keep = (C.c_double * len(kref_coef))(*[float(v) for v in kref_coef])
+        o.kref_coef = C.cast(keep, C.POINTER(C.c_double))
+    return o, keep
+
+
+# --- C-named entry points ------------------------------------------------------
+
+def stp_workspace_bytes(dim, n, N, rank, **opts) -> int:
+    o, _keep = make_options(**opts)
+    g = stp_grid(dim, n)
+    return int(load().stp_workspace_bytes(C.byref(g), N, rank, C.byref(o)))
+
+
+def stp_create(dim, n, N, tau, kfields, tcoef, F, u0, workspace=None, stream=None, **opts):
+    """Returns (ctx handle, keepalive tuple).  kfields, F, u0 are CUDA float64 tensors
+    (borrowed: keep them alive until stp_destroy); tcoef is host (rank x N)."""
+    lib = load()
+    tcoef = np.ascontiguousarray(np.asarray(tcoef, dtype=np.float64))
+    R = tcoef.shape[0]
+    if tcoef.shape != (R, N) or not (1 <= R <= STP_MAX_RANK):
+        raise ValueError(f"tcoef must be (rank, N) with rank <= {STP_MAX_RANK}, got {tcoef.shape}")
+    npts = n ** dim
+    kf = _dev_f64(kfields, (R,) + (n + 2,) * dim, "kfields")
+    Fp = _dev_f64(F, (N,) + (n,) * dim, "F")
+    up = _dev_f64(u0, (n,) * dim, "u0")
+    if kfields.numel() != R * (n + 2) ** dim or F.numel() != N * npts or u0.numel() != npts:
+        raise ValueError("kfields/F/u0 sizes do not match (dim, n, N, rank)")
+    o, keep = make_options(**opts)
+    g = stp_grid(dim, n)
+    tc = tcoef.ctypes.data_as(C.POINTER(C.c_double))
+    kap = stp_kappa(R, kf, tc)
+    ctx = C.c_void_p()
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+    st = lib.stp_create(C.byref(ctx), C.byref(g), N, float(tau), C.byref(kap), Fp, up, C.byref(o),
+                        ws_ptr, ws_bytes, _stream_ptr(stream))
+    _check(st, "stp_create")
+    return ctx, (kfields, F, u0, tcoef, keep, workspace)
+
+
+def stp_apply_operator(ctx, op, x, y):
+    _check(load().stp_apply_operator(ctx, op, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())),
+           "stp_apply_operator")
+
+
+def stp_apply_precond(ctx, which, r, z):
+    _check(load().stp_apply_precond(ctx, which, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr())),
+           "stp_apply_precond")
+
+
+def stp_uzawa_solve(ctx, u, p):
+    st = stp_stats()
+    status = load().stp_uzawa_solve(ctx, C.c_void_p(u.data_ptr()), C.c_void_p(p.data_ptr()), C.byref(st))
+    return status, st
+
+
+def stp_destroy(ctx):
+    if ctx:
+        load().stp_destroy(ctx)
+
+
+# --- convenience wrapper ------------------------------------------------------------
+
+class SpaceTimeSolver:
+    """One problem on one GPU.  Tensors are float64 CUDA tensors laid out as in stp.h."""
+
+    def __init__(self, dim, n, N, tau, kfields, tcoef, F, u0, stream=None, workspace=None, **opts):
+        import torch
+        self.dim, self.n, self.N = dim, n, N
+        self.shape = (N,) + (n,) * dim
+        self.device = F.device
+        self.stream = stream
+        with torch.cuda.device(self.device):
+            self.ctx, self._keep = stp_create(dim, n, N, tau, kfields, tcoef, F, u0,
+                                              workspace=workspace, stream=stream, **opts)
+
+    def _vec(self, x, k=1):
+        shape = (k,) + self.shape if k > 1 else self.shape
+        _dev_f64(x, shape, "vector")
+        return x
+
+    def apply_operator(self, op, x, y=None):
+        import torch
+        k = 2 if op == STP_OP_SADDLE else 1
+        self._vec(x, k)
+        y = torch.empty_like(x) if y is None else self._vec(y, k)
+        stp_apply_operator(self.ctx, op, x, y)
+        return y
+
+    def apply_precond(self, which, r, z=None):
+        import torch
+        self._vec(r)
+        z = torch.empty_like(r) if z is None else self._vec(z)
+        stp_apply_precond(self.ctx, which, r, z)
+        return z
+
+    def solve(self, u=None, p=None, raise_on_error=False):
+        """Run the Uzawa iteration from (u, p) (zeros if None).  Returns (u, p, stats dict)."""
+        import torch
+        u = torch.zeros(self.shape, dtype=torch.float64, device=self.device) if u is None else self._vec(u)
+        p = torch.zeros(self.shape, dtype=torch.float64, device=self.device) if p is None else self._vec(p)
+        status, st = stp_uzawa_solve(self.ctx, u, p)
+        info = dict(status=status, iters=st.iters, rel_res=st.rel_res, omega=st.omega_used, ms=st.t_solve_ms)
+        if raise_on_error and status != STP_OK:
+            _check(status, "stp_uzawa_solve")
+        if status not in (STP_OK, STP_ENOTCONV, STP_EDIVERGED):
+            _check(status, "stp_uzawa_solve")
+        return u, p, info
+
+    def close(self):
+        if self.ctx:
+            stp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def from_problem(prob, device="cuda", **opts):
+    """Build a solver from a ``synth.Problem`` (copies its arrays to the device)."""
+    import torch
+    kf = torch.as_tensor(np.ascontiguousarray(prob.kfields), dtype=torch.float64, device=device)
+    F = torch.as_tensor(np.ascontiguousarray(prob.F), dtype=torch.float64, device=device)
+    u0 = torch.as_tensor(np.ascontiguousarray(prob.u0), dtype=torch.float64, device=device)
+    return SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0, **opts)

@@ -1,0 +1,715 @@
+// Host side of the space-time Uzawa solver: problem setup, multigrid
+// hierarchy, workspace planning, the iteration driver and the C ABI of stp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "stp.h"
+#include "stp_kernels.h"
+
+using namespace stp;
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static stp_status fail(stp_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      return fail(STP_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),     \
+                  __FILE__, __LINE__);                                                    \
+  } while (0)
+
+#define LAUNCH_CHECK()                                                                    \
+  do {                                                                                    \
+    hipError_t _e = hipGetLastError();                                                    \
+    if (_e != hipSuccess)                                                                 \
+      return fail(STP_EDEVICE, "kernel launch failed: %s (%s:%d)", hipGetErrorString(_e), \
+                  __FILE__, __LINE__);                                                    \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Level {
+  int n;
+  double h;
+  Geom g;
+  double* kraw;      // unscaled nodal fields (float64), R x nnodes
+  void* kscaled;     // TC fields scaled by 0.5/h^2
+  void *b, *x, *t, *e;  // TS work vectors (levels >= 1); x, t also on level 0
+};
+
+struct Bump {
+  char* base = nullptr;
+  size_t off = 0, cap = 0;
+  bool dry = true;
+  void* take(size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    void* p = dry ? nullptr : base + off;
+    off += bytes;
+    return p;
+  }
+};
+
+size_t ts_bytes(int prec) { return prec == STP_PREC_F64 ? 8 : (prec == STP_PREC_F32 ? 4 : 2); }
+size_t tc_bytes(int prec) { return prec == STP_PREC_F64 ? 8 : 4; }
+
+long ipow(long a, int d) {
+  long r = 1;
+  for (int i = 0; i < d; ++i) r *= a;
+  return r;
+}
+
+dim3 grid_pts(long npts, int S) {
+  const long bx = (npts + kBlock - 1) / kBlock;
+  const int gy = std::min(S, 65535);
+  const int gz = (S + 65534) / 65535;
+  return dim3(unsigned(bx), unsigned(gy), unsigned(gz));
+}
+
+struct SolverBase;
+
+}  // namespace
+
+struct stp_ctx {
+  int dim = 0, n = 0, N = 0, R = 0;
+  double tau = 0;
+  stp_options opt{};
+  int spatial = STP_SPATIAL_MG;
+  double omega = 0.8;
+  hipStream_t stream = nullptr;
+  const double* F = nullptr;
+  const double* u0 = nullptr;
+  const double* fields = nullptr;
+  std::vector<double> tcoef;   // R x N
+  std::vector<double> abar;    // R
+  std::vector<Level> lv;
+  Geom g0{};
+  // device memory
+  void* ws = nullptr;
+  bool own_ws = false;
+  DevState* state = nullptr;
+  DevState* state_host = nullptr;  // pinned
+  double* partial = nullptr;
+  long npartial = 0;
+  double* kap64 = nullptr;         // fine scaled fields, float64
+  double* cA64 = nullptr;          // N x kMaxRank, tau*tcoef
+  void* cA = nullptr;              // TC, N x kMaxRank
+  void* sigH = nullptr;            // TC, N
+  void* cH = nullptr;              // TC, N x kMaxRank
+  void* cMid = nullptr;            // TC, kMaxRank
+  void* sinT = nullptr;            // TC, N x N: sinT[k][n] = sin((2k+1)(n+1)pi/2N)  (Phi^{-T})
+  void* sinM = nullptr;            // TC, N x N: sinM[n][k] = same value            (Phi^{-1})
+  void *W1 = nullptr, *W2 = nullptr;
+  void* tri = nullptr;             // TC scratch for exact 1-D solves, 2 x N x n
+  double fnorm = 0;
+  SolverBase* impl = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+struct SolverBase {
+  virtual ~SolverBase() {}
+  virtual stp_status precA(const void* b, double* acc64, void* out) = 0;
+  virtual stp_status precH(void* W1, void* W2, double* acc64, void* out, double alpha) = 0;
+  virtual stp_status iteration(double* u, double* p) = 0;
+  virtual stp_status setup_tables() = 0;
+  virtual stp_status cast_in(const double* a, void* b, long n) = 0;
+  virtual stp_status cast_out(const void* a, double* b, long n) = 0;
+};
+
+template <typename TS, typename TC>
+struct Solver : SolverBase {
+  stp_ctx* c;
+  explicit Solver(stp_ctx* ctx) : c(ctx) {}
+
+  TC omegaJ() const { return c->dim == 1 ? TC(2.0 / 3.0) : (c->dim == 2 ? TC(4.0 / 5.0) : TC(6.0 / 7.0)); }
+
+  LevelOp fam(int l, int which) const {
+    LevelOp L;
+    L.kap = c->lv[l].kscaled;
+    L.R = c->R;
+    L.S = c->N;
+    L.uniform = 0;
+    if (which == 0) {          // A family: tau_n A_n
+      L.sig = nullptr;
+      L.c = c->cA;
+    } else if (which == 1) {   // H family: mu_k I + tau A_ref
+      L.sig = c->sigH;
+      L.c = c->cH;
+    } else {                   // middle: (2/N) tau A_ref
+      L.sig = nullptr;
+      L.c = c->cMid;
+      L.uniform = 1;
+    }
+    return L;
+  }
+
+  const int* st() const { return &c->state->done; }
+
+  template <int D>
+  stp_status vcycle_d(int l, int which, const TS* b, TS* out, double* acc64) {
+    Level& L = c->lv[l];
+    const LevelOp op = fam(l, which);
+    const dim3 gr = grid_pts(L.g.npts, c->N);
+    const int last = int(c->lv.size()) - 1;
+    if (l == last) {
+      const long tot = long(c->N) * L.g.npts;
+      if (acc64) {
+        // coarsest level is never the top level of a multi-level cycle, except n = 1
+        TS* tmp = (TS*)L.t;
+        hipLaunchKernelGGL((k_coarsest<D, TS, TC>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           c->stream, L.g, op, b, tmp, st());
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_cast_add64<TS>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
+                           tot, (const TS*)tmp, acc64, st());
+      } else {
+        hipLaunchKernelGGL((k_coarsest<D, TS, TC>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           c->stream, L.g, op, b, out, st());
+      }
+      LAUNCH_CHECK();
+      return STP_OK;
+    }
+    Level& C = c->lv[l + 1];
+    TS* x = (TS*)L.x;
+    TS* t = (TS*)L.t;
+    hipLaunchKernelGGL((k_jacobi0<D, TS, TC>), gr, dim3(kBlock), 0, c->stream, L.g, op, omegaJ(), b, x, st());
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_resid<D, TS, TC>), gr, dim3(kBlock), 0, c->stream, L.g, op, b, (const TS*)x, t, st());
+    LAUNCH_CHECK();
+    const dim3 grc = grid_pts(C.g.npts, c->N);
+    hipLaunchKernelGGL((k_restrict<D, TS, TC>), grc, dim3(kBlock), 0, c->stream, L.g, C.g, c->N, (const TS*)t,
+                       (TS*)C.b, st());
+    LAUNCH_CHECK();
+    stp_status s = vcycle_d<D>(l + 1, which, (const TS*)C.b, (TS*)C.e, nullptr);
+    if (s != STP_OK) return s;
+    hipLaunchKernelGGL((k_prolong_add<D, TS, TC>), gr, dim3(kBlock), 0, c->stream, L.g, C.g, c->N, (const TS*)C.e,
+                       x, st());
+    LAUNCH_CHECK();
+    if (acc64)
+      hipLaunchKernelGGL((k_jacobi<D, TS, TC, EPI_ADD64>), gr, dim3(kBlock), 0, c->stream, L.g, op, omegaJ(), b,
+                         (const TS*)x, (TS*)nullptr, acc64, st());
+    else
+      hipLaunchKernelGGL((k_jacobi<D, TS, TC, EPI_STORE>), gr, dim3(kBlock), 0, c->stream, L.g, op, omegaJ(), b,
+                         (const TS*)x, out, (double*)nullptr, st());
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
+  stp_status spatial_solve(int which, const TS* b, TS* out, double* acc64) {
+    if (c->spatial == STP_SPATIAL_EXACT) {
+      const LevelOp op = fam(0, which);
+      const dim3 gr(unsigned((c->N + 63) / 64));
+      if (acc64)
+        hipLaunchKernelGGL((k_tridiag<TS, TC, EPI_ADD64>), gr, dim3(64), 0, c->stream, c->lv[0].g, op, b, (TS*)nullptr,
+                           acc64, (TC*)c->tri, st());
+      else
+        hipLaunchKernelGGL((k_tridiag<TS, TC, EPI_STORE>), gr, dim3(64), 0, c->stream, c->lv[0].g, op, b, out,
+                           (double*)nullptr, (TC*)c->tri, st());
+      LAUNCH_CHECK();
+      return STP_OK;
+    }
+    switch (c->dim) {
+      case 1: return vcycle_d<1>(0, which, b, out, acc64);
+      case 2: return vcycle_d<2>(0, which, b, out, acc64);
+      default: return vcycle_d<3>(0, which, b, out, acc64);
+    }
+  }
+
+  stp_status apply_mid(const TS* x, TS* y) {
+    const LevelOp op = fam(0, 2);
+    const dim3 gr = grid_pts(c->g0.npts, c->N);
+    switch (c->dim) {
+      case 1: hipLaunchKernelGGL((k_apply_level<1, TS, TC>), gr, dim3(kBlock), 0, c->stream, c->g0, op, x, y, st()); break;
+      case 2: hipLaunchKernelGGL((k_apply_level<2, TS, TC>), gr, dim3(kBlock), 0, c->stream, c->g0, op, x, y, st()); break;
+      default: hipLaunchKernelGGL((k_apply_level<3, TS, TC>), gr, dim3(kBlock), 0, c->stream, c->g0, op, x, y, st()); break;
+    }
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
+  // out (or acc64 += alpha*) = T applied along time to in
+  stp_status time_transform(const void* T, const TS* in, TS* out, double* acc64, double alpha) {
+    const long npts = c->g0.npts;
+    const int per_block = 4 * kDstKpt;
+    const dim3 gr(unsigned((npts + 63) / 64), unsigned((c->N + per_block - 1) / per_block));
+    if (acc64)
+      hipLaunchKernelGGL((k_time_dense<TS, TS, TC, 1>), gr, dim3(kBlock), 0, c->stream, npts, c->N, (const TC*)T, in,
+                         (TS*)nullptr, acc64, alpha, st());
+    else
+      hipLaunchKernelGGL((k_time_dense<TS, TS, TC, 0>), gr, dim3(kBlock), 0, c->stream, npts, c->N, (const TC*)T, in,
+                         out, (double*)nullptr, alpha, st());
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
+  stp_status precA(const void* b, double* acc64, void* out) override {
+    return spatial_solve(0, (const TS*)b, (TS*)out, acc64);
+  }
+
+  // H-tilde^{-1}: W1 holds r (TS) on entry; result into acc64 (+= alpha * z) or out (TS).
+  stp_status precH(void* W1v, void* W2v, double* acc64, void* out, double alpha) override {
+    TS* W1 = (TS*)W1v;
+    TS* W2 = (TS*)W2v;
+    stp_status s;
+    if ((s = time_transform(c->sinT, W1, W2, nullptr, 1.0)) != STP_OK) return s;   // rhat = Phi^{-T} r
+    if ((s = spatial_solve(1, W2, W1, nullptr)) != STP_OK) return s;                  // x = H~_k^{-1} rhat
+    if ((s = apply_mid(W1, W2)) != STP_OK) return s;                                  // y = (2/N) tau A x
+    if ((s = spatial_solve(1, W2, W1, nullptr)) != STP_OK) return s;                  // yhat = H~_k^{-1} y
+    return time_transform(c->sinM, W1, (TS*)out, acc64, alpha);                       // Phi^{-1} yhat
+  }
+
+  template <int D>
+  stp_status iteration_d(double* u, double* p) {
+    const dim3 gr = grid_pts(c->g0.npts, c->N);
+    TimeOp t{c->kap64, c->cA64, c->R, c->N};
+    hipLaunchKernelGGL((k_resid_p<D, TS>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, (const double*)u,
+                       (const double*)p, c->F, c->u0, (TS*)c->W1, st());
+    LAUNCH_CHECK();
+    stp_status s = spatial_solve(0, (const TS*)c->W1, nullptr, p);   // p += A~^{-1} r_p
+    if (s != STP_OK) return s;
+    hipLaunchKernelGGL((k_resid_u<D, TS>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, (const double*)u,
+                       (const double*)p, c->F, c->u0, (TS*)c->W1, c->partial, st());
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial, c->npartial,
+                       c->state, c->opt.tol, c->opt.max_iter);
+    LAUNCH_CHECK();
+    return precH(c->W1, c->W2, u, nullptr, c->omega);                  // u += omega H~^{-1} r_u
+  }
+
+  stp_status iteration(double* u, double* p) override {
+    switch (c->dim) {
+      case 1: return iteration_d<1>(u, p);
+      case 2: return iteration_d<2>(u, p);
+      default: return iteration_d<3>(u, p);
+    }
+  }
+
+  stp_status cast_in(const double* a, void* b, long n) override {
+    hipLaunchKernelGGL((k_cast_from64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n,
+                       a, (TS*)b);
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+  stp_status cast_out(const void* a, double* b, long n) override {
+    hipLaunchKernelGGL((k_cast_to64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n,
+                       (const TS*)a, b);
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
+  stp_status setup_tables() override {
+    const int N = c->N, R = c->R;
+    std::vector<TC> cA(size_t(N) * kMaxRank, TC(0)), cH(size_t(N) * kMaxRank, TC(0)), sig(N), mid(kMaxRank, TC(0));
+    std::vector<double> cA64(size_t(N) * kMaxRank, 0.0);
+    for (int s = 0; s < N; ++s)
+      for (int r = 0; r < R; ++r) {
+        cA64[size_t(s) * kMaxRank + r] = c->tau * c->tcoef[size_t(r) * N + s];
+        cA[size_t(s) * kMaxRank + r] = TC(c->tau * c->tcoef[size_t(r) * N + s]);
+        cH[size_t(s) * kMaxRank + r] = TC(c->tau * c->abar[r]);
+      }
+    for (int k = 0; k < N; ++k) sig[k] = TC(2.0 * std::sin((2.0 * k + 1.0) * M_PI / (4.0 * N)));
+    for (int r = 0; r < R; ++r) mid[r] = TC((2.0 / N) * c->tau * c->abar[r]);
+    std::vector<TC> sT(size_t(N) * N), sM(size_t(N) * N);
+    for (int k = 0; k < N; ++k)
+      for (int m = 0; m < N; ++m) {
+        // sin((2k+1)(m+1) pi / (2N)) with the angle reduced exactly in integers
+        const long q = (long(2 * k + 1) * long(m + 1)) % (4L * N);
+        const double v = std::sin(double(q) * M_PI / (2.0 * N));
+        sT[size_t(k) * N + m] = TC(v);   // row k (frequency), column m (time)
+        sM[size_t(m) * N + k] = TC(v);   // row m (time), column k (frequency)
+      }
+    HIP_TRY(hipMemcpyAsync(c->cA64, cA64.data(), cA64.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->cA, cA.data(), cA.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->cH, cH.data(), cH.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->sigH, sig.data(), sig.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->cMid, mid.data(), mid.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->sinT, sT.data(), sT.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->sinM, sM.data(), sM.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+    // level fields: restrict unscaled float64 fields, then scale by 0.5/h^2 into TC
+    for (size_t l = 0; l < c->lv.size(); ++l) {
+      Level& L = c->lv[l];
+      const long nn = L.g.nnodes;
+      if (l > 0) {
+        Level& F = c->lv[l - 1];
+        for (int r = 0; r < R; ++r) {
+          const dim3 gr(unsigned((nn + kBlock - 1) / kBlock));
+          switch (c->dim) {
+            case 1: hipLaunchKernelGGL(k_restrict_kappa<1>, gr, dim3(kBlock), 0, c->stream, F.n, L.n, F.kraw + r * F.g.nnodes, L.kraw + r * nn); break;
+            case 2: hipLaunchKernelGGL(k_restrict_kappa<2>, gr, dim3(kBlock), 0, c->stream, F.n, L.n, F.kraw + r * F.g.nnodes, L.kraw + r * nn); break;
+            default: hipLaunchKernelGGL(k_restrict_kappa<3>, gr, dim3(kBlock), 0, c->stream, F.n, L.n, F.kraw + r * F.g.nnodes, L.kraw + r * nn); break;
+          }
+          LAUNCH_CHECK();
+        }
+      }
+      const double sc = 0.5 / (L.h * L.h);
+      const long tot = nn * R;
+      hipLaunchKernelGGL((k_scale_copy<TC>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
+                         tot, (const double*)L.kraw, sc, (TC*)L.kscaled);
+      LAUNCH_CHECK();
+      if (l == 0) {
+        hipLaunchKernelGGL((k_scale_copy<double>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           c->stream, tot, (const double*)L.kraw, sc, c->kap64);
+        LAUNCH_CHECK();
+      }
+    }
+    return STP_OK;
+  }
+};
+
+// Plan (dry run) or carve (real run) the workspace.
+size_t plan(stp_ctx* c, Bump& bp) {
+  const int prec = c->opt.precision;
+  const size_t tsb = ts_bytes(prec), tcb = tc_bytes(prec);
+  const long N = c->N;
+  c->state = (DevState*)bp.take(sizeof(DevState));
+  c->npartial = long(grid_pts(c->g0.npts, c->N).x) * grid_pts(c->g0.npts, c->N).y * grid_pts(c->g0.npts, c->N).z;
+  c->partial = (double*)bp.take(size_t(c->npartial) * 8);
+  c->kap64 = (double*)bp.take(size_t(c->R) * c->g0.nnodes * 8);
+  c->cA64 = (double*)bp.take(size_t(N) * kMaxRank * 8);
+  c->cA = bp.take(size_t(N) * kMaxRank * tcb);
+  c->cH = bp.take(size_t(N) * kMaxRank * tcb);
+  c->sigH = bp.take(size_t(N) * tcb);
+  c->cMid = bp.take(size_t(kMaxRank) * tcb);
+  c->sinT = bp.take(size_t(N) * N * tcb);
+  c->sinM = bp.take(size_t(N) * N * tcb);
+  c->W1 = bp.take(size_t(N) * c->g0.npts * tsb);
+  c->W2 = bp.take(size_t(N) * c->g0.npts * tsb);
+  if (c->spatial == STP_SPATIAL_EXACT) c->tri = bp.take(size_t(2) * N * c->n * tcb);
+  for (size_t l = 0; l < c->lv.size(); ++l) {
+    Level& L = c->lv[l];
+    L.kraw = (l == 0) ? nullptr : (double*)bp.take(size_t(c->R) * L.g.nnodes * 8);
+    L.kscaled = bp.take(size_t(c->R) * L.g.nnodes * tcb);
+    const size_t vb = size_t(N) * L.g.npts * tsb;
+    if (c->spatial == STP_SPATIAL_EXACT || c->spatial == STP_SPATIAL_NONE) {
+      L.b = L.x = L.t = L.e = nullptr;
+      continue;
+    }
+    const bool last = (l + 1 == c->lv.size());
+    L.b = (l == 0) ? nullptr : bp.take(vb);
+    L.e = (l == 0) ? nullptr : bp.take(vb);
+    L.x = last ? nullptr : bp.take(vb);
+    L.t = (!last || l == 0) ? bp.take(vb) : nullptr;
+  }
+  return bp.off + 256;
+}
+
+stp_status build_levels(stp_ctx* c) {
+  c->lv.clear();
+  int n = c->n;
+  while (true) {
+    Level L{};
+    L.n = n;
+    L.h = 1.0 / (n + 1);
+    L.g.n = n;
+    L.g.npts = ipow(n, c->dim);
+    L.g.nnodes = ipow(n + 2, c->dim);
+    c->lv.push_back(L);
+    if (c->spatial == STP_SPATIAL_EXACT || c->spatial == STP_SPATIAL_NONE || n == 1) break;
+    if (n % 2 == 0) return fail(STP_EUNSUPPORTED, "multigrid needs n = 2^L - 1 interior nodes per axis (got %d)", c->n);
+    n = (n - 1) / 2;
+    if (int(c->lv.size()) >= STP_MAX_LEVELS) return fail(STP_EUNSUPPORTED, "too many multigrid levels");
+  }
+  c->g0 = c->lv[0].g;
+  return STP_OK;
+}
+
+stp_status validate(const stp_grid* g, int N, double tau, const stp_kappa* kappa, const double* F, const double* u0,
+                    const stp_options* opt) {
+  if (!g || !kappa || !opt) return fail(STP_EINVAL, "NULL grid, kappa or options");
+  if (g->dim < 1 || g->dim > 3) return fail(STP_EINVAL, "dim must be 1, 2 or 3 (got %d)", g->dim);
+  if (g->n < 1) return fail(STP_EINVAL, "n must be >= 1 (got %d)", g->n);
+  if (N < 1) return fail(STP_EINVAL, "N must be >= 1 (got %d)", N);
+  if (!(tau > 0) || !std::isfinite(tau)) return fail(STP_EINVAL, "tau must be finite and > 0");
+  if (kappa->rank < 1 || kappa->rank > STP_MAX_RANK) return fail(STP_EINVAL, "kappa rank must be 1..%d", STP_MAX_RANK);
+  if (!kappa->fields || !kappa->tcoef) return fail(STP_EINVAL, "NULL kappa fields or tcoef");
+  if (!F || !u0) return fail(STP_EINVAL, "NULL F or u0");
+  if (opt->precision < STP_PREC_F64 || opt->precision > STP_PREC_BF16) return fail(STP_EINVAL, "bad precision");
+  if (opt->nu_A != 1 || opt->nu_H != 1) return fail(STP_EUNSUPPORTED, "only nu_A = nu_H = 1 is implemented");
+  if (opt->spatial < STP_SPATIAL_AUTO || opt->spatial > STP_SPATIAL_NONE) return fail(STP_EINVAL, "bad spatial mode");
+  if (opt->spatial == STP_SPATIAL_EXACT && g->dim != 1) return fail(STP_EUNSUPPORTED, "exact spatial solves are 1-D only");
+  if (!(opt->tol >= 0)) return fail(STP_EINVAL, "tol must be >= 0");
+  if (opt->max_iter < 0) return fail(STP_EINVAL, "max_iter must be >= 0");
+  long npts = ipow(g->n, g->dim);
+  if (double(npts) * double(N) > 4.0e12) return fail(STP_EINVAL, "problem too large");
+  return STP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void stp_default_options(stp_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = STP_PREC_F64;
+  o->spatial = STP_SPATIAL_AUTO;
+  o->nu_A = o->nu_H = 1;
+  o->omega = 0.8;
+  o->tol = 1e-8;
+  o->max_iter = 500;
+  o->kref_coef = nullptr;
+  o->check_every = 8;
+  o->use_graph = 1;
+}
+
+const char* stp_status_string(stp_status s) {
+  switch (s) {
+    case STP_OK: return "ok";
+    case STP_EINVAL: return "invalid argument";
+    case STP_ENOMEM: return "out of memory";
+    case STP_EDEVICE: return "device error";
+    case STP_ENOTCONV: return "not converged";
+    case STP_EDIVERGED: return "diverged";
+    case STP_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* stp_last_error(void) { return g_last_error.c_str(); }
+
+static int resolve_spatial(int dim, int spatial) {
+  if (spatial == STP_SPATIAL_AUTO) return dim == 1 ? STP_SPATIAL_EXACT : STP_SPATIAL_MG;
+  return spatial;
+}
+
+size_t stp_workspace_bytes(const stp_grid* g, int N, int rank, const stp_options* opt) {
+  if (!g || !opt || g->dim < 1 || g->dim > 3 || g->n < 1 || N < 1 || rank < 1 || rank > STP_MAX_RANK) return 0;
+  stp_ctx c;
+  c.dim = g->dim;
+  c.n = g->n;
+  c.N = N;
+  c.R = rank;
+  c.opt = *opt;
+  c.spatial = resolve_spatial(g->dim, opt->spatial);
+  if (build_levels(&c) != STP_OK) return 0;
+  Bump bp;
+  return plan(&c, bp);
+}
+
+stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau, const stp_kappa* kappa, const double* F,
+                      const double* u0, const stp_options* opt_in, void* workspace, size_t ws_bytes,
+                      void* hip_stream) {
+  if (!out) return fail(STP_EINVAL, "NULL output context pointer");
+  *out = nullptr;
+  stp_options opt;
+  if (opt_in) opt = *opt_in;
+  else stp_default_options(&opt);
+  stp_status s = validate(g, N, tau, kappa, F, u0, &opt);
+  if (s != STP_OK) return s;
+  std::unique_ptr<stp_ctx> c(new stp_ctx());
+  c->dim = g->dim;
+  c->n = g->n;
+  c->N = N;
+  c->R = kappa->rank;
+  c->tau = tau;
+  c->opt = opt;
+  c->spatial = resolve_spatial(g->dim, opt.spatial);
+  c->omega = opt.omega > 0 ? opt.omega : 0.8;
+  c->stream = (hipStream_t)hip_stream;
+  c->F = F;
+  c->u0 = u0;
+  c->fields = kappa->fields;
+  c->tcoef.assign(kappa->tcoef, kappa->tcoef + size_t(c->R) * N);
+  c->abar.assign(c->R, 0.0);
+  if (opt.kref_coef) {
+    for (int r = 0; r < c->R; ++r) c->abar[r] = opt.kref_coef[r];
+  } else {
+    for (int r = 0; r < c->R; ++r) {
+      double sum = 0;
+      for (int n = 0; n < N; ++n) sum += c->tcoef[size_t(r) * N + n];
+      c->abar[r] = sum / N;
+    }
+  }
+  if ((s = build_levels(c.get())) != STP_OK) return s;
+  Bump dry;
+  const size_t need = plan(c.get(), dry);
+  if (workspace) {
+    if (ws_bytes < need) return fail(STP_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(STP_EINVAL, "workspace not 256-byte aligned");
+    c->ws = workspace;
+  } else {
+    if (hipMalloc(&c->ws, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(STP_ENOMEM, "hipMalloc of %zu bytes failed", need);
+    }
+    c->own_ws = true;
+  }
+  Bump real;
+  real.dry = false;
+  real.base = (char*)c->ws;
+  real.cap = need;
+  plan(c.get(), real);
+  c->lv[0].kraw = const_cast<double*>(c->fields);  // level 0 reads the caller's fields
+  HIP_TRY(hipHostMalloc((void**)&c->state_host, sizeof(DevState), hipHostMallocDefault));
+  HIP_TRY(hipEventCreate(&c->ev0));
+  HIP_TRY(hipEventCreate(&c->ev1));
+  switch (opt.precision) {
+    case STP_PREC_F64: c->impl = new Solver<double, double>(c.get()); break;
+    case STP_PREC_F32: c->impl = new Solver<float, float>(c.get()); break;
+    default: c->impl = new Solver<bf16, float>(c.get()); break;
+  }
+  if ((s = c->impl->setup_tables()) != STP_OK) return s;
+  // kappa(t_n, x) > 0 at every node and step, and for the reference coefficient
+  {
+    const long nn = c->g0.nnodes;
+    const long nb = (nn + kBlock - 1) / kBlock;
+    std::vector<double> cref(kMaxRank, 0.0);
+    for (int r = 0; r < c->R; ++r) cref[r] = c->abar[r];
+    double* dref = (double*)c->partial;                    // reuse partials as scratch
+    if (c->npartial < nb + kMaxRank) {
+      // not enough scratch: use a temporary allocation
+      HIP_TRY(hipMallocAsync((void**)&dref, size_t(nb + kMaxRank) * 8, c->stream));
+    }
+    double* part = dref + kMaxRank;
+    HIP_TRY(hipMemcpyAsync(dref, cref.data(), kMaxRank * 8, hipMemcpyHostToDevice, c->stream));
+    std::vector<double> h(nb);
+    double mn = 1e300;
+    for (int pass = 0; pass < 2; ++pass) {
+      const double* coef = pass == 0 ? c->cA64 : dref;
+      hipLaunchKernelGGL(k_kappa_min, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, nn, c->R, pass == 0 ? N : 1,
+                         c->fields, coef, part);
+      LAUNCH_CHECK();
+      HIP_TRY(hipMemcpyAsync(h.data(), part, size_t(nb) * 8, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      mn = std::min(mn, *std::min_element(h.begin(), h.end()));
+    }
+    if (dref != c->partial) HIP_TRY(hipFreeAsync(dref, c->stream));
+    if (!(mn > 0)) return fail(STP_EINVAL, "kappa must be > 0 at every node and step (min %.3e)", mn);
+  }
+  // ||f||
+  {
+    const dim3 gr = grid_pts(c->g0.npts, N);
+    hipLaunchKernelGGL(k_fnorm, gr, dim3(kBlock), 0, c->stream, c->g0, N, tau, F, u0, c->partial);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial, c->npartial,
+                       &c->state->fnorm);
+    LAUNCH_CHECK();
+    DevState hs{};
+    HIP_TRY(hipMemcpyAsync(&hs, c->state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->fnorm = std::sqrt(hs.fnorm);
+  }
+  *out = c.release();
+  return STP_OK;
+}
+
+void stp_destroy(stp_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  delete c->impl;
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  if (c->state_host) (void)hipHostFree(c->state_host);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+stp_status stp_apply_operator(stp_ctx* c, int op, const double* x, double* y) {
+  if (!c || !x || !y) return fail(STP_EINVAL, "NULL argument");
+  const dim3 gr = grid_pts(c->g0.npts, c->N);
+  TimeOp t{c->kap64, c->cA64, c->R, c->N};
+  const long nv = long(c->N) * c->g0.npts;
+  if (op == STP_OP_B) {
+    switch (c->dim) {
+      case 1: hipLaunchKernelGGL(k_apply_B<1>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, y); break;
+      case 2: hipLaunchKernelGGL(k_apply_B<2>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, y); break;
+      default: hipLaunchKernelGGL(k_apply_B<3>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, y); break;
+    }
+  } else if (op == STP_OP_SADDLE) {
+    switch (c->dim) {
+      case 1: hipLaunchKernelGGL(k_apply_saddle<1>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, x + nv, y, y + nv); break;
+      case 2: hipLaunchKernelGGL(k_apply_saddle<2>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, x + nv, y, y + nv); break;
+      default: hipLaunchKernelGGL(k_apply_saddle<3>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, x + nv, y, y + nv); break;
+    }
+  } else {
+    return fail(STP_EINVAL, "unknown operator %d", op);
+  }
+  LAUNCH_CHECK();
+  return STP_OK;
+}
+
+stp_status stp_apply_precond(stp_ctx* c, int which, const double* r, double* z) {
+  if (!c || !r || !z) return fail(STP_EINVAL, "NULL argument");
+  if (which != STP_PC_A && which != STP_PC_H) return fail(STP_EINVAL, "unknown preconditioner %d", which);
+  if (c->spatial == STP_SPATIAL_NONE) return fail(STP_EUNSUPPORTED, "context created without a spatial solver");
+  const long nv = long(c->N) * c->g0.npts;
+  // the state flag must read "running" for the kernels to execute
+  HIP_TRY(hipMemsetAsync(c->state, 0, sizeof(int) * 2, c->stream));
+  stp_status s;
+  if ((s = c->impl->cast_in(r, c->W1, nv)) != STP_OK) return s;
+  if (which == STP_PC_A) {
+    HIP_TRY(hipMemsetAsync(z, 0, size_t(nv) * 8, c->stream));
+    return c->impl->precA(c->W1, z, nullptr);
+  }
+  HIP_TRY(hipMemsetAsync(z, 0, size_t(nv) * 8, c->stream));
+  return c->impl->precH(c->W1, c->W2, z, nullptr, 1.0);
+}
+
+stp_status stp_uzawa_solve(stp_ctx* c, double* u, double* p, stp_stats* stats) {
+  if (!c || !u || !p) return fail(STP_EINVAL, "NULL argument (u and p are required)");
+  if (c->spatial == STP_SPATIAL_NONE) return fail(STP_EUNSUPPORTED, "context created without a spatial solver");
+  DevState init{};
+  init.fnorm = c->fnorm;
+  HIP_TRY(hipMemcpyAsync(c->state, &init, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipEventRecord(c->ev0, c->stream));
+  const int chunk = std::max(1, c->opt.check_every);
+  stp_status s = STP_OK;
+  int launched = 0;
+  DevState hs{};
+  while (true) {
+    for (int q = 0; q < chunk; ++q) {
+      if ((s = c->impl->iteration(u, p)) != STP_OK) return s;
+      ++launched;
+    }
+    HIP_TRY(hipMemcpyAsync(c->state_host, c->state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    hs = *c->state_host;
+    if (hs.done) break;
+    if (launched > c->opt.max_iter + 2 * chunk + 2) return fail(STP_EDEVICE, "iteration state did not terminate");
+  }
+  HIP_TRY(hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(hipEventSynchronize(c->ev1));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  stp_status res = hs.done == 1 ? STP_OK : (hs.done == 2 ? STP_EDIVERGED : STP_ENOTCONV);
+  if (stats) {
+    stats->iters = hs.iter;
+    stats->rel_res = hs.rel;
+    stats->omega_used = c->omega;
+    stats->t_solve_ms = ms;
+    stats->status = res;
+  }
+  if (res == STP_EDIVERGED) fail(res, "residual diverged at iteration %d (rel %.3e)", hs.iter, hs.rel);
+  if (res == STP_ENOTCONV) fail(res, "max_iter %d reached (rel %.3e)", c->opt.max_iter, hs.rel);
+  return res;
+}
+
+}  // extern "C"

@@ -1,0 +1,698 @@
+// Device kernels of the space-time Uzawa solver (gfx950, wave64).
+//
+// Vectors are slab-major [s][z][y][x] on the n^d interior nodes; coefficient
+// fields are nodal on the (n+2)^d nodes including the boundary.  Every kernel
+// covers all time slabs in one launch: blockIdx.x walks the points of a slab,
+// blockIdx.y (+ gridDim.y * blockIdx.z) the slabs.
+//
+// Operator of a slab s on a multigrid level:
+//     L_s x = sigma_s x + sum_r c_{s,r} A(kappa_r) x,
+// evaluated face by face with face weight w = sum_r c_{s,r} (k_r[i] + k_r[nb]),
+// where k_r = kappa_r * 0.5 / h^2 is stored pre-scaled per level.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stp {
+
+constexpr int kMaxRank = 4;
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// storage types
+// ---------------------------------------------------------------------------
+struct bf16 {
+  uint16_t v;
+};
+
+__device__ __forceinline__ float bf16_to_f(bf16 a) { return __uint_as_float(uint32_t(a.v) << 16); }
+__device__ __forceinline__ bf16 f_to_bf16(float f) {
+  // round to nearest even; NaN stays NaN
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{uint16_t((u >> 16) | 0x40u)};
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return bf16{uint16_t(u >> 16)};
+}
+
+template <typename TC, typename TS> __device__ __forceinline__ TC ld(const TS* p, long i) { return TC(p[i]); }
+template <> __device__ __forceinline__ float ld<float, bf16>(const bf16* p, long i) { return bf16_to_f(p[i]); }
+template <> __device__ __forceinline__ double ld<double, bf16>(const bf16* p, long i) { return double(bf16_to_f(p[i])); }
+
+template <typename TS, typename TC> __device__ __forceinline__ void st(TS* p, long i, TC v) { p[i] = TS(v); }
+template <> __device__ __forceinline__ void st<bf16, float>(bf16* p, long i, float v) { p[i] = f_to_bf16(v); }
+template <> __device__ __forceinline__ void st<bf16, double>(bf16* p, long i, double v) { p[i] = f_to_bf16(float(v)); }
+
+// ---------------------------------------------------------------------------
+// geometry helpers
+// ---------------------------------------------------------------------------
+struct Geom {
+  int n;        // interior nodes per axis
+  long npts;    // n^d
+  long nnodes;  // (n+2)^d
+};
+
+__device__ __forceinline__ int slab_index() { return blockIdx.y + gridDim.y * blockIdx.z; }
+
+template <int D>
+__device__ __forceinline__ void decode(long i, int n, int& x, int& y, int& z) {
+  if (D == 1) {
+    x = int(i); y = 0; z = 0;
+  } else if (D == 2) {
+    y = int(i / n); x = int(i - long(y) * n); z = 0;
+  } else {
+    long yz = i / n;
+    x = int(i - yz * n);
+    z = int(yz / n);
+    y = int(yz - long(z) * n);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ long node_of(int x, int y, int z, int n) {
+  const long nn = n + 2;
+  if (D == 1) return x + 1;
+  if (D == 2) return (long(y) + 1) * nn + x + 1;
+  return ((long(z) + 1) * nn + y + 1) * nn + x + 1;
+}
+
+// Per-slab operator table entry, read once per block (uniform).
+template <typename TC>
+struct SlabOp {
+  TC sigma;
+  TC c[kMaxRank];
+};
+
+template <typename TC>
+__device__ __forceinline__ SlabOp<TC> load_op(const TC* sig, const TC* c, int s, int R) {
+  SlabOp<TC> op;
+  op.sigma = sig ? sig[s] : TC(0);
+#pragma unroll
+  for (int r = 0; r < kMaxRank; ++r) op.c[r] = (r < R) ? c[s * kMaxRank + r] : TC(0);
+  return op;
+}
+
+template <typename TC>
+__device__ __forceinline__ TC kmix(const TC* kap, long nnodes, long node, const SlabOp<TC>& op, int R) {
+  TC k = op.c[0] * kap[node];
+#pragma unroll
+  for (int r = 1; r < kMaxRank; ++r)
+    if (r < R) k += op.c[r] * kap[r * nnodes + node];
+  return k;
+}
+
+// Stencil pieces at interior point (x,y,z): returns diag D and sum_nb w*x_nb.
+template <int D, typename TC, typename TV>
+__device__ __forceinline__ void stencil(const TV* __restrict__ xs, long i, int x, int y, int z, const Geom& g,
+                                        const TC* __restrict__ kap, const SlabOp<TC>& op, int R, TC& diag,
+                                        TC& offsum) {
+  const int n = g.n;
+  const long nn = n + 2;
+  const long node = node_of<D>(x, y, z, n);
+  const TC kc = kmix(kap, g.nnodes, node, op, R);
+  TC dsum = op.sigma, osum = 0;
+  // x neighbours
+  {
+    TC w = kc + kmix(kap, g.nnodes, node - 1, op, R);
+    dsum += w;
+    if (x > 0) osum += w * ld<TC>(xs, i - 1);
+    w = kc + kmix(kap, g.nnodes, node + 1, op, R);
+    dsum += w;
+    if (x < n - 1) osum += w * ld<TC>(xs, i + 1);
+  }
+  if (D >= 2) {
+    TC w = kc + kmix(kap, g.nnodes, node - nn, op, R);
+    dsum += w;
+    if (y > 0) osum += w * ld<TC>(xs, i - n);
+    w = kc + kmix(kap, g.nnodes, node + nn, op, R);
+    dsum += w;
+    if (y < n - 1) osum += w * ld<TC>(xs, i + n);
+  }
+  if (D >= 3) {
+    const long plane = long(n) * n;
+    const long nplane = nn * nn;
+    TC w = kc + kmix(kap, g.nnodes, node - nplane, op, R);
+    dsum += w;
+    if (z > 0) osum += w * ld<TC>(xs, i - plane);
+    w = kc + kmix(kap, g.nnodes, node + nplane, op, R);
+    dsum += w;
+    if (z < n - 1) osum += w * ld<TC>(xs, i + plane);
+  }
+  diag = dsum;
+  offsum = osum;
+}
+
+// Diagonal only.
+template <int D, typename TC>
+__device__ __forceinline__ TC diag_at(int x, int y, int z, const Geom& g, const TC* __restrict__ kap,
+                                      const SlabOp<TC>& op, int R) {
+  const int n = g.n;
+  const long nn = n + 2;
+  const long node = node_of<D>(x, y, z, n);
+  const TC kc = kmix(kap, g.nnodes, node, op, R);
+  TC dsum = op.sigma + TC(2 * D) * kc;
+  dsum += kmix(kap, g.nnodes, node - 1, op, R) + kmix(kap, g.nnodes, node + 1, op, R);
+  if (D >= 2) dsum += kmix(kap, g.nnodes, node - nn, op, R) + kmix(kap, g.nnodes, node + nn, op, R);
+  if (D >= 3) dsum += kmix(kap, g.nnodes, node - nn * nn, op, R) + kmix(kap, g.nnodes, node + nn * nn, op, R);
+  return dsum;
+}
+
+__device__ __forceinline__ int done_flag(const int* st) { return *st; }
+
+// Block-wide sum of a double (wave64 shuffles + LDS), result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kBlock / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// time-global operators (float64)
+// ---------------------------------------------------------------------------
+struct TimeOp {
+  const double* kap;   // fine-level scaled fields (float64)
+  const double* cA;    // N x kMaxRank: tau * tcoef (operator tau_n A_n)
+  int R;
+  int N;
+};
+
+// y = B x = K x + A x
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_apply_B(Geom g, TimeOp t, const double* __restrict__ x,
+                                                    double* __restrict__ y) {
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (s >= t.N || i >= g.npts) return;
+  int px, py, pz;
+  decode<D>(i, g.n, px, py, pz);
+  const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
+  const double* xs = x + long(s) * g.npts;
+  double dg, off;
+  stencil<D, double>(xs, i, px, py, pz, g, t.kap, op, t.R, dg, off);
+  const double xc = xs[i];
+  const double xprev = s > 0 ? xs[i - g.npts] : 0.0;
+  y[long(s) * g.npts + i] = (xc - xprev) + (dg * xc - off);
+}
+
+// saddle [p;u] -> [A p - K u ; -K^T p - (K + K^T + A) u]
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_apply_saddle(Geom g, TimeOp t, const double* __restrict__ p,
+                                                         const double* __restrict__ u, double* __restrict__ yp,
+                                                         double* __restrict__ yu) {
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (s >= t.N || i >= g.npts) return;
+  int px, py, pz;
+  decode<D>(i, g.n, px, py, pz);
+  const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
+  const long o = long(s) * g.npts;
+  double dg, off;
+  stencil<D, double>(p + o, i, px, py, pz, g, t.kap, op, t.R, dg, off);
+  const double Ap = dg * p[o + i] - off;
+  stencil<D, double>(u + o, i, px, py, pz, g, t.kap, op, t.R, dg, off);
+  const double Au = dg * u[o + i] - off;
+  const double uc = u[o + i];
+  const double um = s > 0 ? u[o - g.npts + i] : 0.0;
+  const double up = s + 1 < t.N ? u[o + g.npts + i] : 0.0;
+  const double pc = p[o + i];
+  const double pp = s + 1 < t.N ? p[o + g.npts + i] : 0.0;
+  yp[o + i] = Ap - (uc - um);
+  yu[o + i] = -(pc - pp) - (2.0 * uc - um - up) - Au;
+}
+
+// a1: r_p = K u - A p - f,  f_s = tau F_s (+ u0 on the first slab); stored in TS.
+template <int D, typename TS>
+__global__ void __launch_bounds__(kBlock) k_resid_p(Geom g, TimeOp t, double tau, const double* __restrict__ u,
+                                                    const double* __restrict__ p, const double* __restrict__ F,
+                                                    const double* __restrict__ u0, TS* __restrict__ r,
+                                                    const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (s >= t.N || i >= g.npts) return;
+  int px, py, pz;
+  decode<D>(i, g.n, px, py, pz);
+  const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
+  const long o = long(s) * g.npts;
+  double dg, off;
+  stencil<D, double>(p + o, i, px, py, pz, g, t.kap, op, t.R, dg, off);
+  const double Ap = dg * p[o + i] - off;
+  const double Ku = u[o + i] - (s > 0 ? u[o - g.npts + i] : 0.0);
+  double f = tau * F[o + i];
+  if (s == 0) f += u0[i];
+  st<TS, double>(r, o + i, Ku - Ap - f);
+}
+
+// a3: e = f - B u (stop residual, squared norm per block), r_u = e - K^T (u + p).
+template <int D, typename TS>
+__global__ void __launch_bounds__(kBlock) k_resid_u(Geom g, TimeOp t, double tau, const double* __restrict__ u,
+                                                    const double* __restrict__ p, const double* __restrict__ F,
+                                                    const double* __restrict__ u0, TS* __restrict__ r,
+                                                    double* __restrict__ partial, const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  double e2 = 0.0;
+  if (s < t.N && i < g.npts) {
+    int px, py, pz;
+    decode<D>(i, g.n, px, py, pz);
+    const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
+    const long o = long(s) * g.npts;
+    double dg, off;
+    stencil<D, double>(u + o, i, px, py, pz, g, t.kap, op, t.R, dg, off);
+    const double uc = u[o + i];
+    const double Au = dg * uc - off;
+    const double um = s > 0 ? u[o - g.npts + i] : 0.0;
+    double f = tau * F[o + i];
+    if (s == 0) f += u0[i];
+    const double e = f - (uc - um) - Au;
+    const double w = uc + p[o + i];
+    const double wn = s + 1 < t.N ? u[o + g.npts + i] + p[o + g.npts + i] : 0.0;
+    st<TS, double>(r, o + i, e - (w - wn));
+    e2 = e * e;
+  }
+  const double bs = block_sum(e2);
+  if (threadIdx.x == 0) partial[long(slab_index()) * gridDim.x + blockIdx.x] = bs;
+}
+
+// ||f||^2 partials (setup)
+__global__ void __launch_bounds__(kBlock) k_fnorm(Geom g, int N, double tau, const double* __restrict__ F,
+                                                  const double* __restrict__ u0, double* __restrict__ partial) {
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (s < N && i < g.npts) {
+    double f = tau * F[long(s) * g.npts + i];
+    if (s == 0) f += u0[i];
+    v = f * f;
+  }
+  const double bs = block_sum(v);
+  if (threadIdx.x == 0) partial[long(slab_index()) * gridDim.x + blockIdx.x] = bs;
+}
+
+// Solver state shared by the iteration kernels and the host.
+struct DevState {
+  int done;       // 0 running, 1 converged, 2 diverged, 3 max_iter
+  int iter;       // current iteration index j
+  double rel;     // ||f - B u_j|| / ||f||
+  double fnorm;
+  double res0;
+};
+
+// Deterministic reduction of the residual partials and the stop decision.
+__global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ partial, long count,
+                                                     DevState* st, double tol, int max_iter) {
+  if (st->done) return;
+  double v = 0.0;
+  for (long q = threadIdx.x; q < count; q += kBlock) v += partial[q];
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) {
+    const double res = sqrt(s);
+    const double rel = res / st->fnorm;
+    st->rel = rel;
+    if (st->iter == 0) st->res0 = res;
+    if (!(rel == rel) || rel > 1e300 || (st->iter > 0 && res > 1e8 * st->res0 && res > 1e8 * st->fnorm * tol)) {
+      st->done = 2;
+    } else if (rel <= tol) {
+      st->done = 1;
+    } else if (st->iter >= max_iter) {
+      st->done = 3;
+    } else {
+      st->iter = st->iter + 1;
+    }
+  }
+}
+
+__global__ void k_sum_to(const double* __restrict__ partial, long count, double* out) {
+  double v = 0.0;
+  for (long q = threadIdx.x; q < count; q += kBlock) v += partial[q];
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// ---------------------------------------------------------------------------
+// spatial kernels on a multigrid level (storage TS, compute TC)
+// ---------------------------------------------------------------------------
+struct LevelOp {
+  const void* kap;     // scaled fields, TC
+  const void* sig;     // per-slab sigma (TC) or null
+  const void* c;       // per-slab coefficients, S x kMaxRank (TC)
+  int R;
+  int S;               // number of slabs
+  int uniform;         // 1: slab 0's (sigma, c) serve all slabs
+};
+
+template <typename TC>
+__device__ __forceinline__ SlabOp<TC> level_op(const LevelOp& L, int s) {
+  const int so = L.uniform ? 0 : s;
+  return load_op<TC>((const TC*)L.sig, (const TC*)L.c, so, L.R);
+}
+
+// x = omega_J D^{-1} b  (first smoothing sweep from a zero guess)
+template <int D, typename TS, typename TC>
+__global__ void __launch_bounds__(kBlock) k_jacobi0(Geom g, LevelOp L, TC omega, const TS* __restrict__ b,
+                                                    TS* __restrict__ x, const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (s >= L.S || i >= g.npts) return;
+  int px, py, pz;
+  decode<D>(i, g.n, px, py, pz);
+  const SlabOp<TC> op = level_op<TC>(L, s);
+  const TC dg = diag_at<D, TC>(px, py, pz, g, (const TC*)L.kap, op, L.R);
+  const long o = long(s) * g.npts + i;
+  st<TS, TC>(x, o, omega * ld<TC>(b, o) / dg);
+}
+
+// t = b - L x
+template <int D, typename TS, typename TC>
+__global__ void __launch_bounds__(kBlock) k_resid(Geom g, LevelOp L, const TS* __restrict__ b,
+                                                  const TS* __restrict__ x, TS* __restrict__ t,
+                                                  const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (s >= L.S || i >= g.npts) return;
+  int px, py, pz;
+  decode<D>(i, g.n, px, py, pz);
+  const SlabOp<TC> op = level_op<TC>(L, s);
+  const TS* xs = x + long(s) * g.npts;
+  TC dg, off;
+  stencil<D, TC>(xs, i, px, py, pz, g, (const TC*)L.kap, op, L.R, dg, off);
+  const long o = long(s) * g.npts + i;
+  st<TS, TC>(t, o, ld<TC>(b, o) - (dg * ld<TC>(xs, i) - off));
+}
+
+// Epilogue of the last smoothing sweep: write out, or add into a float64 vector.
+enum Epi { EPI_STORE = 0, EPI_ADD64 = 1 };
+
+// out = x + omega_J D^{-1} (b - L x)
+template <int D, typename TS, typename TC, int EPI>
+__global__ void __launch_bounds__(kBlock) k_jacobi(Geom g, LevelOp L, TC omega, const TS* __restrict__ b,
+                                                   const TS* __restrict__ x, TS* __restrict__ out,
+                                                   double* __restrict__ acc64, const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (s >= L.S || i >= g.npts) return;
+  int px, py, pz;
+  decode<D>(i, g.n, px, py, pz);
+  const SlabOp<TC> op = level_op<TC>(L, s);
+  const TS* xs = x + long(s) * g.npts;
+  TC dg, off;
+  stencil<D, TC>(xs, i, px, py, pz, g, (const TC*)L.kap, op, L.R, dg, off);
+  const long o = long(s) * g.npts + i;
+  const TC xc = ld<TC>(xs, i);
+  const TC v = xc + omega * (ld<TC>(b, o) - (dg * xc - off)) / dg;
+  if (EPI == EPI_STORE) st<TS, TC>(out, o, v);
+  else acc64[o] += double(v);
+}
+
+// Full-weighting restriction: coarse point <- tensor (1/4,1/2,1/4) of fine points.
+template <int D, typename TS, typename TC>
+__global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, int S, const TS* __restrict__ t,
+                                                     TS* __restrict__ bc, const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (s >= S || i >= gc.npts) return;
+  int cx, cy, cz;
+  decode<D>(i, gc.n, cx, cy, cz);
+  const int nf = gf.n;
+  // coarse interior index I (0-based) <-> fine 0-based index 2I+1
+  const int fx = 2 * cx + 1, fy = 2 * cy + 1, fz = 2 * cz + 1;
+  const TS* ts = t + long(s) * gf.npts;
+  const TC w[3] = {TC(0.25), TC(0.5), TC(0.25)};
+  TC acc = 0;
+  for (int dz = (D >= 3 ? -1 : 0); dz <= (D >= 3 ? 1 : 0); ++dz)
+    for (int dy = (D >= 2 ? -1 : 0); dy <= (D >= 2 ? 1 : 0); ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        TC wt = w[dx + 1];
+        if (D >= 2) wt *= w[dy + 1];
+        if (D >= 3) wt *= w[dz + 1];
+        const long fi = (D == 1) ? long(fx + dx)
+                        : (D == 2) ? long(fy + dy) * nf + fx + dx
+                                   : (long(fz + dz) * nf + fy + dy) * nf + fx + dx;
+        acc += wt * ld<TC>(ts, fi);
+      }
+  st<TS, TC>(bc, long(s) * gc.npts + i, acc);
+}
+
+// x += P e  (multilinear interpolation; zero on the boundary)
+template <int D, typename TS, typename TC>
+__global__ void __launch_bounds__(kBlock) k_prolong_add(Geom gf, Geom gc, int S, const TS* __restrict__ e,
+                                                        TS* __restrict__ x, const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (s >= S || i >= gf.npts) return;
+  int fx, fy, fz;
+  decode<D>(i, gf.n, fx, fy, fz);
+  const int nc = gc.n;
+  const TS* es = e + long(s) * gc.npts;
+  // along one axis, fine 1-based node j = f+1: even j -> coarse j/2 (weight 1);
+  // odd j -> coarse (j-1)/2 and (j+1)/2 (weight 1/2); coarse 1-based 0 and nc+1 are boundary.
+  int lo[3], cnt[3];
+  int f[3] = {fx, fy, fz};
+  for (int a = 0; a < D; ++a) {
+    const int j = f[a] + 1;
+    if ((j & 1) == 0) { lo[a] = j / 2; cnt[a] = 1; }
+    else { lo[a] = (j - 1) / 2; cnt[a] = 2; }
+  }
+  TC acc = 0;
+  for (int az = 0; az < (D >= 3 ? cnt[2] : 1); ++az)
+    for (int ay = 0; ay < (D >= 2 ? cnt[1] : 1); ++ay)
+      for (int ax = 0; ax < cnt[0]; ++ax) {
+        const int cx = lo[0] + ax;
+        const int cy = D >= 2 ? lo[1] + ay : 1;
+        const int cz = D >= 3 ? lo[2] + az : 1;
+        if (cx < 1 || cx > nc) continue;
+        if (D >= 2 && (cy < 1 || cy > nc)) continue;
+        if (D >= 3 && (cz < 1 || cz > nc)) continue;
+        TC wt = (cnt[0] == 2 ? TC(0.5) : TC(1));
+        if (D >= 2) wt *= (cnt[1] == 2 ? TC(0.5) : TC(1));
+        if (D >= 3) wt *= (cnt[2] == 2 ? TC(0.5) : TC(1));
+        const long ci = (D == 1) ? long(cx - 1)
+                        : (D == 2) ? long(cy - 1) * nc + (cx - 1)
+                                   : (long(cz - 1) * nc + (cy - 1)) * nc + (cx - 1);
+        acc += wt * ld<TC>(es, ci);
+      }
+  const long o = long(s) * gf.npts + i;
+  st<TS, TC>(x, o, ld<TC>(x, o) + acc);
+}
+
+// Coarsest level (one node): x = b / D
+template <int D, typename TS, typename TC>
+__global__ void __launch_bounds__(kBlock) k_coarsest(Geom g, LevelOp L, const TS* __restrict__ b,
+                                                     TS* __restrict__ x, const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  const long q = long(blockIdx.x) * kBlock + threadIdx.x;  // slab * npts + i
+  if (q >= long(L.S) * g.npts) return;
+  const int s = int(q / g.npts);
+  const long i = q - long(s) * g.npts;
+  int px, py, pz;
+  decode<D>(i, g.n, px, py, pz);
+  const SlabOp<TC> op = level_op<TC>(L, s);
+  const TC dg = diag_at<D, TC>(px, py, pz, g, (const TC*)L.kap, op, L.R);
+  st<TS, TC>(x, q, ld<TC>(b, q) / dg);
+}
+
+// y = L x on a level (used for the middle reference operator of the H-blocks).
+template <int D, typename TS, typename TC>
+__global__ void __launch_bounds__(kBlock) k_apply_level(Geom g, LevelOp L, const TS* __restrict__ x,
+                                                        TS* __restrict__ y, const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (s >= L.S || i >= g.npts) return;
+  int px, py, pz;
+  decode<D>(i, g.n, px, py, pz);
+  const SlabOp<TC> op = level_op<TC>(L, s);
+  const TS* xs = x + long(s) * g.npts;
+  TC dg, off;
+  stencil<D, TC>(xs, i, px, py, pz, g, (const TC*)L.kap, op, L.R, dg, off);
+  st<TS, TC>(y, long(s) * g.npts + i, dg * ld<TC>(xs, i) - off);
+}
+
+// Exact 1-D solve per slab (Thomas algorithm), one thread per slab.
+template <typename TS, typename TC, int EPI>
+__global__ void __launch_bounds__(64) k_tridiag(Geom g, LevelOp L, const TS* __restrict__ b, TS* __restrict__ out,
+                                                double* __restrict__ acc64, TC* __restrict__ scratch,
+                                                const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= L.S) return;
+  const int n = g.n;
+  const SlabOp<TC> op = level_op<TC>(L, s);
+  const TC* kap = (const TC*)L.kap;
+  TC* cp = scratch + long(s) * n;   // modified super-diagonal
+  const TS* bs = b + long(s) * n;
+  // row i (0-based interior), node i+1: diag = sigma + w_left + w_right, off = -w
+  TC wl = kmix(kap, g.nnodes, 0, op, L.R) + kmix(kap, g.nnodes, 1, op, L.R);
+  TC prev_d = 0, prev_y = 0;
+  // forward sweep: store c'_i in scratch, y'_i in out (as TC via acc in registers -> store in TS buffer is lossy;
+  // keep y' in a second half of scratch)
+  TC* yp = scratch + long(L.S) * n + long(s) * n;
+  for (int i = 0; i < n; ++i) {
+    const TC kc = kmix(kap, g.nnodes, i + 1, op, L.R);
+    const TC wr = kc + kmix(kap, g.nnodes, i + 2, op, L.R);
+    const TC dg = op.sigma + wl + wr;
+    const TC a = -wl;          // sub-diagonal (coupling to i-1)
+    const TC cup = -wr;        // super-diagonal (coupling to i+1)
+    TC denom = dg;
+    TC rhs = ld<TC>(bs, i);
+    if (i > 0) {
+      denom = dg - a * prev_d;
+      rhs = rhs - a * prev_y;
+    }
+    prev_d = (i < n - 1) ? cup / denom : TC(0);
+    prev_y = rhs / denom;
+    cp[i] = prev_d;
+    yp[i] = prev_y;
+    wl = wr;
+  }
+  TC xv = 0;
+  for (int i = n - 1; i >= 0; --i) {
+    xv = yp[i] - (i < n - 1 ? cp[i] * xv : TC(0));
+    const long o = long(s) * n + i;
+    if (EPI == EPI_STORE) st<TS, TC>(out, o, xv);
+    else acc64[o] += double(xv);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dense transform along the time axis:  out[k][i] (=|+=) alpha * sum_m T[k][m] in[m][i]
+// ---------------------------------------------------------------------------
+constexpr int kDstKpt = 8;   // outputs per thread
+
+template <typename TSi, typename TSo, typename TC, int ACC64>
+__global__ void __launch_bounds__(kBlock) k_time_dense(long npts, int N, const TC* __restrict__ T,
+                                                       const TSi* __restrict__ in, TSo* __restrict__ out,
+                                                       double* __restrict__ out64, double alpha,
+                                                       const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long i = long(blockIdx.x) * 64 + lane;
+  const int k0 = (blockIdx.y * 4 + wv) * kDstKpt;
+  if (k0 >= N) return;
+  TC acc[kDstKpt];
+#pragma unroll
+  for (int q = 0; q < kDstKpt; ++q) acc[q] = 0;
+  if (i < npts) {
+    for (int m = 0; m < N; ++m) {
+      const TC v = ld<TC>(in, long(m) * npts + i);
+#pragma unroll
+      for (int q = 0; q < kDstKpt; ++q)
+        if (k0 + q < N) acc[q] += T[long(k0 + q) * N + m] * v;
+    }
+#pragma unroll
+    for (int q = 0; q < kDstKpt; ++q) {
+      if (k0 + q >= N) break;
+      const long o = long(k0 + q) * npts + i;
+      if (ACC64) out64[o] += alpha * double(acc[q]);
+      else st<TSo, TC>(out, o, TC(alpha) * acc[q]);
+    }
+  }
+}
+
+// elementwise helpers
+template <typename TS>
+__global__ void k_cast_from64(long n, const double* __restrict__ a, TS* __restrict__ b) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) st<TS, double>(b, i, a[i]);
+}
+template <typename TS>
+__global__ void k_cast_to64(long n, const TS* __restrict__ a, double* __restrict__ b) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) b[i] = ld<double>(a, i);
+}
+
+template <typename TS>
+__global__ void k_cast_add64(long n, const TS* __restrict__ a, double* __restrict__ b, const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) b[i] += ld<double>(a, i);
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------
+// coarse nodal field <- per-axis (1/4,1/2,1/4) at interior coarse nodes, injection on the boundary
+template <int D>
+__global__ void k_restrict_kappa(int nf, int nc, const double* __restrict__ kf, double* __restrict__ kc) {
+  const long nnc = nc + 2, nnf = nf + 2;
+  long total = nnc;
+  if (D >= 2) total *= nnc;
+  if (D >= 3) total *= nnc;
+  const long q = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (q >= total) return;
+  int I[3] = {0, 0, 0};
+  long rem = q;
+  I[0] = int(rem % nnc); rem /= nnc;
+  if (D >= 2) { I[1] = int(rem % nnc); rem /= nnc; }
+  if (D >= 3) { I[2] = int(rem); }
+  double acc = 0.0;
+  int lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= D) { lo[a] = hi[a] = 0; continue; }
+    const bool bnd = (I[a] == 0 || I[a] == nc + 1);
+    lo[a] = bnd ? 0 : -1;
+    hi[a] = bnd ? 0 : 1;
+  }
+  for (int dz = lo[2]; dz <= hi[2]; ++dz)
+    for (int dy = lo[1]; dy <= hi[1]; ++dy)
+      for (int dx = lo[0]; dx <= hi[0]; ++dx) {
+        const int d[3] = {dx, dy, dz};
+        double w = 1.0;
+        long fi = 0;
+        for (int a = D - 1; a >= 0; --a) {
+          const bool bnd = (I[a] == 0 || I[a] == nc + 1);
+          const double wa = bnd ? 1.0 : (d[a] == 0 ? 0.5 : 0.25);
+          w *= wa;
+          const int fa = 2 * I[a] + d[a];
+          fi = fi * nnf + fa;
+        }
+        acc += w * kf[fi];
+      }
+  kc[q] = acc;
+}
+
+template <typename TC>
+__global__ void k_scale_copy(long n, const double* __restrict__ a, double s, TC* __restrict__ b) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) b[i] = TC(a[i] * s);
+}
+
+// min over slabs s < S and nodes of sum_r coef[s][r] * fields[r][node]  (block partials)
+__global__ void k_kappa_min(long nnodes, int R, int S, const double* __restrict__ fields,
+                            const double* __restrict__ coef, double* __restrict__ partial) {
+  __shared__ double red[kBlock];
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  double m = 1e300;
+  if (i < nnodes) {
+    double f[kMaxRank];
+    for (int r = 0; r < kMaxRank; ++r) f[r] = r < R ? fields[r * nnodes + i] : 0.0;
+    for (int s = 0; s < S; ++s) {
+      double k = 0.0;
+      for (int r = 0; r < R; ++r) k += coef[s * kMaxRank + r] * f[r];
+      m = fmin(m, k);
+    }
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+}  // namespace stp
