@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark of the space-time inexact Uzawa solver on one MI355X.
+
+Workload: 2-D heat equation, 255 x 255 interior nodes, N_t = 256 steps, T = 1,
+kappa = 1 + 0.5 sin(2 pi t) cos(pi x), source = 8 space-time Gaussians,
+u0 = random sine modes (k <= 16); seeded synthetic data.  The GPU path runs
+in float64 (the workload's precision); the float32-preconditioner variant is
+reported next to it.
+
+A step is one inexact Uzawa iteration (eq. (3.1)) over all N_t slabs: both
+residuals, the A-tilde^{-1} V-cycles, the two DSTs and the H-tilde^{-1}
+V-cycles.  K steps are timed as one solve with tol = 0 and max_iter = K (K
+updates plus the final residual evaluation).  Inputs are resident in HBM
+before the timed region starts.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def algorithmic_bytes(kernel: str, level: int, dims, ts: int) -> float | None:
+    """Minimum HBM bytes one launch of ``kernel`` must move (every input read
+    once, every output written once), for the solver's level sizes.
+
+    dims: dict with N (slabs), npts per level list, nnodes per level list, R.
+    """
+    N = dims["N"]
+    npts = dims["npts"]
+    nn = dims["nnodes"]
+    R = dims["R"]
+    tc = 8 if ts == 8 else 4
+    n_l = npts[level] if level < len(npts) else None
+    kap = lambda l, b: R * nn[l] * b  # noqa: E731
+    k = kernel.split("<")[0]
+    if k == "k_resid_tile":        # u, p, F in; r out (the other slab's u, p rows are the same arrays)
+        return N * npts[0] * (3 * 8 + ts) + kap(0, 8)
+    if k == "k_mg_down":           # b in (fine), bc out (coarse)
+        return N * (n_l + npts[level + 1]) * ts + kap(level, tc)
+    if k == "k_mg_up":
+        if "ADD64" in kernel:      # b, e in; float64 p read and written
+            return N * (n_l + npts[level + 1]) * ts + N * n_l * 16 + kap(level, tc)
+        return N * (2 * n_l + npts[level + 1]) * ts + kap(level, tc)
+    if k == "k_apply_tile":
+        return N * n_l * 2 * ts + kap(level, tc)
+    if k == "k_time_fft" or k == "k_time_dense":
+        if "MODE_A6, 1" in kernel or (k == "k_time_dense" and ", 1>" in kernel):
+            return N * npts[0] * (ts + 16)
+        return N * npts[0] * 2 * ts
+    return None
+
+
+def gpu_run(args):
+    import numpy as np
+    import torch
+
+    import paper_1802_08126_amd as stp
+    import synth
+
+    torch.cuda.set_device(0)
+    prob = synth.CONFIG_BUILDERS[args.workload]()
+    dev = "cuda:0"
+    kf = torch.as_tensor(np.ascontiguousarray(prob.kfields), dtype=torch.float64, device=dev)
+    F = torch.as_tensor(np.ascontiguousarray(prob.F), dtype=torch.float64, device=dev)
+    u0 = torch.as_tensor(np.ascontiguousarray(prob.u0), dtype=torch.float64, device=dev)
+    shape = (prob.N,) + (prob.n,) * prob.dim
+    dofs = prob.N * prob.npts
+    levels = []
+    n = prob.n
+    while True:
+        levels.append(n)
+        if n == 1 or prob.dim == 1:
+            break
+        n = (n - 1) // 2
+    dims = dict(N=prob.N, R=prob.R, npts=[m ** prob.dim for m in levels] + [1],
+                nnodes=[(m + 2) ** prob.dim for m in levels] + [1])
+    results = {}
+    for prec in (["f64", "f32"] if not args.only_f64 else ["f64"]):
+        s = stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0,
+                                precision=prec, omega=args.omega, tol=0.0, max_iter=args.warmup,
+                                check_every=args.check_every)
+        u = torch.zeros(shape, dtype=torch.float64, device=dev)
+        p = torch.zeros(shape, dtype=torch.float64, device=dev)
+        # warmup
+        s.solve(u, p)
+        torch.cuda.synchronize()
+        # timed region: exactly --steps iterations
+        s.close()
+        s = stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0,
+                                precision=prec, omega=args.omega, tol=0.0, max_iter=args.steps,
+                                check_every=args.check_every)
+        u.zero_()
+        p.zero_()
+        if prec == "f64":
+            s.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, info = s.solve(u, p)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rep = s.timing_report() if prec == "f64" else None
+        if prec == "f64":
+            s.timing(False)
+        assert info["iters"] == args.steps, info
+        sec = t1 - t0
+        results[prec] = dict(sec=sec, ms_per_step=1e3 * sec / args.steps, value=dofs * args.steps / sec,
+                             device_ms=info["ms"], kernels=rep)
+        s.close()
+        # time to tolerance from a zero guess
+        if not args.skip_tol:
+            s = stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0,
+                                    precision=prec, omega=args.omega, tol=args.tol, max_iter=2000,
+                                    check_every=args.check_every)
+            u.zero_()
+            p.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, info = s.solve(u, p)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            results[prec]["tol"] = dict(tol=args.tol, iters=info["iters"], sec=t1 - t0, rel_res=info["rel_res"],
+                                        status=info["status"])
+            s.close()
+    return prob, dims, results
+
+
+def roofline(rep, dims, ts, steps):
+    """Dominant kernel (largest summed device time) and its achieved HBM rate."""
+    if not rep:
+        return None, []
+    rep = sorted(rep, key=lambda r: -r["total_ms"])
+    total = sum(r["total_ms"] for r in rep)
+    top = rep[0]
+    b = algorithmic_bytes(top["kernel"], top["level"], dims, ts)
+    table = [dict(kernel=r["kernel"], level=r["level"], launches=r["launches"], avg_us=1e3 * r["avg_ms"],
+                  share=r["total_ms"] / total) for r in rep[:12]]
+    if b is None:
+        return None, table
+    achieved = b / (top["avg_ms"] * 1e-3) / 1e9
+    return dict(bound="hbm", kernel=top["kernel"], level=top["level"], achieved=achieved, peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
+                bytes_per_launch=b, avg_launch_us=1e3 * top["avg_ms"]), table
+
+
+def cpu_baseline(workload):
+    """The oracle's inexact Uzawa iteration timed on the host (one iteration)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import uzawa
+
+    prob = synth.CONFIG_BUILDERS[workload]()
+    stamps = []
+
+    def cb(j, u, p, r):
+        stamps.append(time.perf_counter())
+    with threadpool_limits(limits=1):
+        uzawa.uzawa(prob, omega=0.8, tol=0.0, max_iter=1, callback=cb)
+    sec = float(np.diff(stamps)[0])
+    return dict(value=prob.N * prob.npts / sec, unit="DoF-it/s", cores=1, kind="oracle",
+                sample=f"one inexact Uzawa iteration of the CPU float64 oracle (numpy, 1 thread) on "
+                       f"{workload}: {sec:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="heat2d_255_N256")
+    ap.add_argument("--omega", type=float, default=0.8)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--check-every", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-tol", action="store_true")
+    ap.add_argument("--only-f64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU time sharding is a design "
+              "(see DESIGN.md), not an implementation.  Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    prob, dims, res = gpu_run(args)
+    r64 = res["f64"]
+    roof, table = roofline(r64["kernels"], dims, 8, args.steps)
+    out = {
+        "metric": "space-time DoF-iterations/sec (u DoFs x Uzawa iterations / s), 1 GPU",
+        "value": r64["value"],
+        "unit": "DoF-it/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dim": prob.dim, "n_interior": prob.n, "N_t": prob.N,
+                   "dofs": prob.N * prob.npts, "omega": args.omega, "spatial": "mg V(1,1) Jacobi",
+                   "parallelism": "all time slabs batched in every launch"},
+        "roofline": roof,
+        "kernels_f64": table,
+    }
+    if "tol" in r64:
+        out["time_to_tol_f64"] = r64["tol"]
+    if "f32" in res:
+        r32 = res["f32"]
+        out["mixed_f32_precond"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
+                                    "dtype": "f32 preconditioner / f64 outer",
+                                    "speedup_vs_f64": r32["value"] / r64["value"]}
+        if "tol" in r32:
+            out["mixed_f32_precond"]["time_to_tol"] = r32["tol"]
+            if "tol" in r64:
+                out["mixed_f32_precond"]["time_to_tol_speedup"] = r64["tol"]["sec"] / r32["tol"]["sec"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

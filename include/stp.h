@@ -142,6 +142,18 @@ stp_status stp_apply_precond(stp_ctx* ctx, int which, const double* r, double* z
 stp_status stp_uzawa_solve(stp_ctx* ctx, double* u, double* p, stp_stats* st);
 
 void stp_destroy(stp_ctx* ctx);
+
+/* Profiling aid.  While enabled, every kernel launch of the context is
+ * bracketed by a pair of HIP events on the context's stream (a small
+ * overhead per launch).  stp_timing_enable(ctx, 1) clears earlier records;
+ * stp_timing_count synchronizes the stream, folds the records into entries
+ * keyed by (kernel, multigrid level) and returns the number of entries (-1 on
+ * error); stp_timing_get reads entry idx: kernel name (valid until the next
+ * stp_timing_* call), level, number of launches and summed device time. */
+stp_status stp_timing_enable(stp_ctx* ctx, int enable);
+int stp_timing_count(stp_ctx* ctx);
+stp_status stp_timing_get(stp_ctx* ctx, int idx, const char** name, int* level, long* launches,
+                          double* total_ms);
 const char* stp_status_string(stp_status s);
 const char* stp_last_error(void);
 

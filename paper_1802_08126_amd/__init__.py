@@ -27,6 +27,8 @@ from .binding import (  # noqa: F401
     stp_apply_precond,
     stp_create,
     stp_destroy,
+    stp_timing_enable,
+    stp_timing_report,
     stp_uzawa_solve,
     stp_workspace_bytes,
 )

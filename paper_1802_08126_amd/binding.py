@@ -79,6 +79,13 @@ def load() -> C.CDLL:
     lib.stp_status_string.restype = C.c_char_p
     lib.stp_last_error.argtypes = []
     lib.stp_last_error.restype = C.c_char_p
+    lib.stp_timing_enable.argtypes = [C.c_void_p, C.c_int]
+    lib.stp_timing_enable.restype = C.c_int
+    lib.stp_timing_count.argtypes = [C.c_void_p]
+    lib.stp_timing_count.restype = C.c_int
+    lib.stp_timing_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_int),
+                                   C.POINTER(C.c_long), C.POINTER(C.c_double)]
+    lib.stp_timing_get.restype = C.c_int
     _lib = lib
     return lib
 
@@ -175,6 +182,26 @@ def stp_uzawa_solve(ctx, u, p):
     return status, st
 
 
+def stp_timing_enable(ctx, enable=True):
+    _check(load().stp_timing_enable(ctx, 1 if enable else 0), "stp_timing_enable")
+
+
+def stp_timing_report(ctx):
+    """List of dicts (kernel, level, launches, total_ms, avg_ms) since stp_timing_enable."""
+    lib = load()
+    n = lib.stp_timing_count(ctx)
+    if n < 0:
+        _check(STP_EDEVICE, "stp_timing_count")
+    out = []
+    for i in range(n):
+        name, lev, cnt, ms = C.c_char_p(), C.c_int(), C.c_long(), C.c_double()
+        _check(lib.stp_timing_get(ctx, i, C.byref(name), C.byref(lev), C.byref(cnt), C.byref(ms)), "stp_timing_get")
+        kern = name.value.decode().strip("()")
+        out.append(dict(kernel=kern, level=lev.value, launches=cnt.value, total_ms=ms.value,
+                        avg_ms=ms.value / max(cnt.value, 1)))
+    return out
+
+
 def stp_destroy(ctx):
     if ctx:
         load().stp_destroy(ctx)
@@ -227,6 +254,12 @@ class SpaceTimeSolver:
         if status not in (STP_OK, STP_ENOTCONV, STP_EDIVERGED):
             _check(status, "stp_uzawa_solve")
         return u, p, info
+
+    def timing(self, enable=True):
+        stp_timing_enable(self.ctx, enable)
+
+    def timing_report(self):
+        return stp_timing_report(self.ctx)
 
     def close(self):
         if self.ctx:

@@ -13,6 +13,7 @@
 
 #include "stp.h"
 #include "stp_kernels.h"
+#include "stp_tiles.h"
 
 using namespace stp;
 
@@ -20,6 +21,8 @@ using namespace stp;
 // error reporting
 // ---------------------------------------------------------------------------
 static thread_local std::string g_last_error;
+struct stp_ctx;
+static inline void kt_end(stp_ctx* c);
 
 static stp_status fail(stp_status s, const char* fmt, ...) {
   char buf[512];
@@ -41,6 +44,7 @@ static stp_status fail(stp_status s, const char* fmt, ...) {
 
 #define LAUNCH_CHECK()                                                                    \
   do {                                                                                    \
+    kt_end(&*c);                                                                          \
     hipError_t _e = hipGetLastError();                                                    \
     if (_e != hipSuccess)                                                                 \
       return fail(STP_EDEVICE, "kernel launch failed: %s (%s:%d)", hipGetErrorString(_e), \
@@ -91,6 +95,51 @@ dim3 grid_pts(long npts, int S) {
 
 struct SolverBase;
 
+// Optional per-launch device timing (HIP events on the context's stream).
+struct KTimer {
+  bool on = false;
+  int level = 0;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec {
+    const char* name;
+    int level;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  const char* pend_name = nullptr;
+  int pend_level = 0;
+  hipEvent_t pend_a = nullptr;
+  struct Agg {
+    std::string name;
+    int level;
+    long count;
+    double ms;
+  };
+  std::vector<Agg> agg;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+
+// Columns per block and LDS bytes of the FFT time transform (C = 0: use the dense path).
+void fft_layout(int N, size_t tcb, int& C, size_t& lds) {
+  C = 0;
+  lds = 0;
+  if (N < 1 || (N & (N - 1)) != 0 || N > 4096) return;
+  C = std::max(1, std::min(16, 4096 / N));
+  lds = (size_t(2) * N * C + size_t(4) * N) * tcb;
+  if (lds > 160 * 1024) {
+    C = 0;
+    lds = 0;
+  }
+}
+
 }  // namespace
 
 struct stp_ctx {
@@ -113,7 +162,9 @@ struct stp_ctx {
   DevState* state = nullptr;
   DevState* state_host = nullptr;  // pinned
   double* partial = nullptr;
-  long npartial = 0;
+  long npartial = 0;               // capacity of the partial-sum buffer
+  long npart_resid = 0;            // partials written by the residual kernel (tile grid)
+  long npart_points = 0;           // partials written by point-grid reductions
   double* kap64 = nullptr;         // fine scaled fields, float64
   double* cA64 = nullptr;          // N x kMaxRank, tau*tcoef
   void* cA = nullptr;              // TC, N x kMaxRank
@@ -122,12 +173,44 @@ struct stp_ctx {
   void* cMid = nullptr;            // TC, kMaxRank
   void* sinT = nullptr;            // TC, N x N: sinT[k][n] = sin((2k+1)(n+1)pi/2N)  (Phi^{-T})
   void* sinM = nullptr;            // TC, N x N: sinM[n][k] = same value            (Phi^{-1})
+  void* tw = nullptr;              // TC, 2N: exp(-2 pi i m / N)   (re block, im block)
+  void* tw4 = nullptr;             // TC, 2N: exp(-i pi m / (2N))
+  int fft_cols = 0;                // columns per block of the FFT path (0: dense path)
+  size_t fft_lds = 0;
   void *W1 = nullptr, *W2 = nullptr;
   void* tri = nullptr;             // TC scratch for exact 1-D solves, 2 x N x n
   double fnorm = 0;
   SolverBase* impl = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  KTimer kt;
 };
+
+static inline void kt_begin(stp_ctx* c, const char* name) {
+  if (!c->kt.on) return;
+  hipEvent_t a = c->kt.get();
+  if (!a) return;
+  (void)hipEventRecord(a, c->stream);
+  c->kt.pend_name = name;
+  c->kt.pend_level = c->kt.level;
+  c->kt.pend_a = a;
+}
+
+static inline void kt_end(stp_ctx* c) {
+  if (!c->kt.on || !c->kt.pend_name) return;
+  hipEvent_t b = c->kt.get();
+  if (b) {
+    (void)hipEventRecord(b, c->stream);
+    c->kt.recs.push_back({c->kt.pend_name, c->kt.pend_level, c->kt.pend_a, b});
+  }
+  c->kt.pend_name = nullptr;
+}
+
+// Every kernel launch goes through KLAUNCH (optional timing) and LAUNCH_CHECK.
+#define KLAUNCH(kern, ...)                 \
+  do {                                     \
+    kt_begin(&*c, #kern);                  \
+    hipLaunchKernelGGL(kern, __VA_ARGS__); \
+  } while (0)
 
 namespace {
 
@@ -172,62 +255,54 @@ struct Solver : SolverBase {
 
   template <int D>
   stp_status vcycle_d(int l, int which, const TS* b, TS* out, double* acc64) {
+    c->kt.level = l;
     Level& L = c->lv[l];
     const LevelOp op = fam(l, which);
-    const dim3 gr = grid_pts(L.g.npts, c->N);
     const int last = int(c->lv.size()) - 1;
+    const int gy = std::min(c->N, 65535), gz = (c->N + 65534) / 65535;
     if (l == last) {
+      // single-node level: x = b / D
       const long tot = long(c->N) * L.g.npts;
+      const dim3 gr(unsigned((tot + kBlock - 1) / kBlock));
       if (acc64) {
-        // coarsest level is never the top level of a multi-level cycle, except n = 1
         TS* tmp = (TS*)L.t;
-        hipLaunchKernelGGL((k_coarsest<D, TS, TC>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           c->stream, L.g, op, b, tmp, st());
+        KLAUNCH((k_coarsest<D, TS, TC>), gr, dim3(kBlock), 0, c->stream, L.g, op, b, tmp, st());
         LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_cast_add64<TS>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
-                           tot, (const TS*)tmp, acc64, st());
+        KLAUNCH((k_cast_add64<TS>), gr, dim3(kBlock), 0, c->stream, tot, (const TS*)tmp, acc64, st());
       } else {
-        hipLaunchKernelGGL((k_coarsest<D, TS, TC>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           c->stream, L.g, op, b, out, st());
+        KLAUNCH((k_coarsest<D, TS, TC>), gr, dim3(kBlock), 0, c->stream, L.g, op, b, out, st());
       }
       LAUNCH_CHECK();
       return STP_OK;
     }
     Level& C = c->lv[l + 1];
-    TS* x = (TS*)L.x;
-    TS* t = (TS*)L.t;
-    hipLaunchKernelGGL((k_jacobi0<D, TS, TC>), gr, dim3(kBlock), 0, c->stream, L.g, op, omegaJ(), b, x, st());
-    LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_resid<D, TS, TC>), gr, dim3(kBlock), 0, c->stream, L.g, op, b, (const TS*)x, t, st());
-    LAUNCH_CHECK();
-    const dim3 grc = grid_pts(C.g.npts, c->N);
-    hipLaunchKernelGGL((k_restrict<D, TS, TC>), grc, dim3(kBlock), 0, c->stream, L.g, C.g, c->N, (const TS*)t,
-                       (TS*)C.b, st());
+    const dim3 grd(unsigned(tiles_for<D, DownTile<D>>(C.n)), unsigned(gy), unsigned(gz));
+    KLAUNCH((k_mg_down<D, TS, TC>), grd, dim3(kBlock), 0, c->stream, L.g, C.g, op, omegaJ(), b, (TS*)C.b, st());
     LAUNCH_CHECK();
     stp_status s = vcycle_d<D>(l + 1, which, (const TS*)C.b, (TS*)C.e, nullptr);
     if (s != STP_OK) return s;
-    hipLaunchKernelGGL((k_prolong_add<D, TS, TC>), gr, dim3(kBlock), 0, c->stream, L.g, C.g, c->N, (const TS*)C.e,
-                       x, st());
-    LAUNCH_CHECK();
+    c->kt.level = l;
+    const dim3 gru(unsigned(tiles_for<D, UpTile<D>>(L.n)), unsigned(gy), unsigned(gz));
     if (acc64)
-      hipLaunchKernelGGL((k_jacobi<D, TS, TC, EPI_ADD64>), gr, dim3(kBlock), 0, c->stream, L.g, op, omegaJ(), b,
-                         (const TS*)x, (TS*)nullptr, acc64, st());
+      KLAUNCH((k_mg_up<D, TS, TC, EPI_ADD64>), gru, dim3(kBlock), 0, c->stream, L.g, C.g, op, omegaJ(), b,
+              (const TS*)C.e, (TS*)nullptr, acc64, st());
     else
-      hipLaunchKernelGGL((k_jacobi<D, TS, TC, EPI_STORE>), gr, dim3(kBlock), 0, c->stream, L.g, op, omegaJ(), b,
-                         (const TS*)x, out, (double*)nullptr, st());
+      KLAUNCH((k_mg_up<D, TS, TC, EPI_STORE>), gru, dim3(kBlock), 0, c->stream, L.g, C.g, op, omegaJ(), b,
+              (const TS*)C.e, out, (double*)nullptr, st());
     LAUNCH_CHECK();
     return STP_OK;
   }
 
   stp_status spatial_solve(int which, const TS* b, TS* out, double* acc64) {
     if (c->spatial == STP_SPATIAL_EXACT) {
+      c->kt.level = 0;
       const LevelOp op = fam(0, which);
       const dim3 gr(unsigned((c->N + 63) / 64));
       if (acc64)
-        hipLaunchKernelGGL((k_tridiag<TS, TC, EPI_ADD64>), gr, dim3(64), 0, c->stream, c->lv[0].g, op, b, (TS*)nullptr,
+        KLAUNCH((k_tridiag<TS, TC, EPI_ADD64>), gr, dim3(64), 0, c->stream, c->lv[0].g, op, b, (TS*)nullptr,
                            acc64, (TC*)c->tri, st());
       else
-        hipLaunchKernelGGL((k_tridiag<TS, TC, EPI_STORE>), gr, dim3(64), 0, c->stream, c->lv[0].g, op, b, out,
+        KLAUNCH((k_tridiag<TS, TC, EPI_STORE>), gr, dim3(64), 0, c->stream, c->lv[0].g, op, b, out,
                            (double*)nullptr, (TC*)c->tri, st());
       LAUNCH_CHECK();
       return STP_OK;
@@ -240,27 +315,48 @@ struct Solver : SolverBase {
   }
 
   stp_status apply_mid(const TS* x, TS* y) {
+    c->kt.level = 0;
     const LevelOp op = fam(0, 2);
-    const dim3 gr = grid_pts(c->g0.npts, c->N);
+    const int gy = std::min(c->N, 65535), gz = (c->N + 65534) / 65535;
     switch (c->dim) {
-      case 1: hipLaunchKernelGGL((k_apply_level<1, TS, TC>), gr, dim3(kBlock), 0, c->stream, c->g0, op, x, y, st()); break;
-      case 2: hipLaunchKernelGGL((k_apply_level<2, TS, TC>), gr, dim3(kBlock), 0, c->stream, c->g0, op, x, y, st()); break;
-      default: hipLaunchKernelGGL((k_apply_level<3, TS, TC>), gr, dim3(kBlock), 0, c->stream, c->g0, op, x, y, st()); break;
+      case 1: KLAUNCH((k_apply_tile<1, TS, TC>), dim3(unsigned(tiles_for<1, UpTile<1>>(c->n)), gy, gz), dim3(kBlock), 0, c->stream, c->g0, op, x, y, st()); break;
+      case 2: KLAUNCH((k_apply_tile<2, TS, TC>), dim3(unsigned(tiles_for<2, UpTile<2>>(c->n)), gy, gz), dim3(kBlock), 0, c->stream, c->g0, op, x, y, st()); break;
+      default: KLAUNCH((k_apply_tile<3, TS, TC>), dim3(unsigned(tiles_for<3, UpTile<3>>(c->n)), gy, gz), dim3(kBlock), 0, c->stream, c->g0, op, x, y, st()); break;
     }
     LAUNCH_CHECK();
     return STP_OK;
   }
 
-  // out (or acc64 += alpha*) = T applied along time to in
-  stp_status time_transform(const void* T, const TS* in, TS* out, double* acc64, double alpha) {
+  // out (or acc64 += alpha*) = T applied along time to in; mode 0: Phi^{-T}, 1: Phi^{-1}
+  stp_status time_transform(int mode, const TS* in, TS* out, double* acc64, double alpha) {
+    c->kt.level = 0;
     const long npts = c->g0.npts;
+    if (c->fft_cols > 0) {
+      const int C = c->fft_cols;
+      const dim3 gr(unsigned((npts + C - 1) / C));
+      const size_t lds = c->fft_lds;
+      const TC* tw = (const TC*)c->tw;
+      const TC* tw4 = (const TC*)c->tw4;
+      if (mode == 0)
+        KLAUNCH((k_time_fft<TS, TC, MODE_A4, 0>), gr, dim3(kBlock), lds, c->stream, npts, c->N, C, tw, tw4,
+                           in, out, (double*)nullptr, alpha, st());
+      else if (acc64)
+        KLAUNCH((k_time_fft<TS, TC, MODE_A6, 1>), gr, dim3(kBlock), lds, c->stream, npts, c->N, C, tw, tw4,
+                           in, (TS*)nullptr, acc64, alpha, st());
+      else
+        KLAUNCH((k_time_fft<TS, TC, MODE_A6, 0>), gr, dim3(kBlock), lds, c->stream, npts, c->N, C, tw, tw4,
+                           in, out, (double*)nullptr, alpha, st());
+      LAUNCH_CHECK();
+      return STP_OK;
+    }
+    const void* T = mode == 0 ? c->sinT : c->sinM;
     const int per_block = 4 * kDstKpt;
     const dim3 gr(unsigned((npts + 63) / 64), unsigned((c->N + per_block - 1) / per_block));
     if (acc64)
-      hipLaunchKernelGGL((k_time_dense<TS, TS, TC, 1>), gr, dim3(kBlock), 0, c->stream, npts, c->N, (const TC*)T, in,
+      KLAUNCH((k_time_dense<TS, TS, TC, 1>), gr, dim3(kBlock), 0, c->stream, npts, c->N, (const TC*)T, in,
                          (TS*)nullptr, acc64, alpha, st());
     else
-      hipLaunchKernelGGL((k_time_dense<TS, TS, TC, 0>), gr, dim3(kBlock), 0, c->stream, npts, c->N, (const TC*)T, in,
+      KLAUNCH((k_time_dense<TS, TS, TC, 0>), gr, dim3(kBlock), 0, c->stream, npts, c->N, (const TC*)T, in,
                          out, (double*)nullptr, alpha, st());
     LAUNCH_CHECK();
     return STP_OK;
@@ -275,26 +371,29 @@ struct Solver : SolverBase {
     TS* W1 = (TS*)W1v;
     TS* W2 = (TS*)W2v;
     stp_status s;
-    if ((s = time_transform(c->sinT, W1, W2, nullptr, 1.0)) != STP_OK) return s;   // rhat = Phi^{-T} r
+    if ((s = time_transform(0, W1, W2, nullptr, 1.0)) != STP_OK) return s;          // rhat = Phi^{-T} r
     if ((s = spatial_solve(1, W2, W1, nullptr)) != STP_OK) return s;                  // x = H~_k^{-1} rhat
     if ((s = apply_mid(W1, W2)) != STP_OK) return s;                                  // y = (2/N) tau A x
     if ((s = spatial_solve(1, W2, W1, nullptr)) != STP_OK) return s;                  // yhat = H~_k^{-1} y
-    return time_transform(c->sinM, W1, (TS*)out, acc64, alpha);                       // Phi^{-1} yhat
+    return time_transform(1, W1, (TS*)out, acc64, alpha);                             // Phi^{-1} yhat
   }
 
   template <int D>
   stp_status iteration_d(double* u, double* p) {
-    const dim3 gr = grid_pts(c->g0.npts, c->N);
+    c->kt.level = 0;
+    const int gy = std::min(c->N, 65535), gz = (c->N + 65534) / 65535;
+    const dim3 gr(unsigned(tiles_for<D, UpTile<D>>(c->n)), unsigned(gy), unsigned(gz));
     TimeOp t{c->kap64, c->cA64, c->R, c->N};
-    hipLaunchKernelGGL((k_resid_p<D, TS>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, (const double*)u,
-                       (const double*)p, c->F, c->u0, (TS*)c->W1, st());
+    KLAUNCH((k_resid_tile<D, TS, 0>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, (const double*)u,
+            (const double*)p, c->F, c->u0, (TS*)c->W1, (double*)nullptr, st());
     LAUNCH_CHECK();
     stp_status s = spatial_solve(0, (const TS*)c->W1, nullptr, p);   // p += A~^{-1} r_p
     if (s != STP_OK) return s;
-    hipLaunchKernelGGL((k_resid_u<D, TS>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, (const double*)u,
-                       (const double*)p, c->F, c->u0, (TS*)c->W1, c->partial, st());
+    c->kt.level = 0;
+    KLAUNCH((k_resid_tile<D, TS, 1>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, (const double*)u,
+            (const double*)p, c->F, c->u0, (TS*)c->W1, c->partial, st());
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial, c->npartial,
+    KLAUNCH(k_finalize, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial, c->npart_resid,
                        c->state, c->opt.tol, c->opt.max_iter);
     LAUNCH_CHECK();
     return precH(c->W1, c->W2, u, nullptr, c->omega);                  // u += omega H~^{-1} r_u
@@ -309,13 +408,13 @@ struct Solver : SolverBase {
   }
 
   stp_status cast_in(const double* a, void* b, long n) override {
-    hipLaunchKernelGGL((k_cast_from64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n,
+    KLAUNCH((k_cast_from64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n,
                        a, (TS*)b);
     LAUNCH_CHECK();
     return STP_OK;
   }
   stp_status cast_out(const void* a, double* b, long n) override {
-    hipLaunchKernelGGL((k_cast_to64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n,
+    KLAUNCH((k_cast_to64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n,
                        (const TS*)a, b);
     LAUNCH_CHECK();
     return STP_OK;
@@ -323,6 +422,14 @@ struct Solver : SolverBase {
 
   stp_status setup_tables() override {
     const int N = c->N, R = c->R;
+    if (c->fft_lds > 65536) {
+      HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A4, 0>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(c->fft_lds)));
+      HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 0>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(c->fft_lds)));
+      HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 1>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(c->fft_lds)));
+    }
     std::vector<TC> cA(size_t(N) * kMaxRank, TC(0)), cH(size_t(N) * kMaxRank, TC(0)), sig(N), mid(kMaxRank, TC(0));
     std::vector<double> cA64(size_t(N) * kMaxRank, 0.0);
     for (int s = 0; s < N; ++s)
@@ -347,8 +454,22 @@ struct Solver : SolverBase {
     HIP_TRY(hipMemcpyAsync(c->cH, cH.data(), cH.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->sigH, sig.data(), sig.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->cMid, mid.data(), mid.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->sinT, sT.data(), sT.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->sinM, sM.data(), sM.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+    if (c->fft_cols > 0) {
+      std::vector<TC> tw(2 * size_t(N)), tw4(2 * size_t(N));
+      for (int m = 0; m < N; ++m) {
+        tw[m] = TC(std::cos(2.0 * M_PI * m / N));
+        tw[N + m] = TC(-std::sin(2.0 * M_PI * m / N));
+        tw4[m] = TC(std::cos(M_PI * m / (2.0 * N)));
+        tw4[N + m] = TC(-std::sin(M_PI * m / (2.0 * N)));
+      }
+      HIP_TRY(hipMemcpyAsync(c->tw, tw.data(), tw.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(c->tw4, tw4.data(), tw4.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));   // host vectors go out of scope
+    } else {
+      HIP_TRY(hipMemcpyAsync(c->sinT, sT.data(), sT.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(c->sinM, sM.data(), sM.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+    }
     // level fields: restrict unscaled float64 fields, then scale by 0.5/h^2 into TC
     for (size_t l = 0; l < c->lv.size(); ++l) {
       Level& L = c->lv[l];
@@ -358,20 +479,20 @@ struct Solver : SolverBase {
         for (int r = 0; r < R; ++r) {
           const dim3 gr(unsigned((nn + kBlock - 1) / kBlock));
           switch (c->dim) {
-            case 1: hipLaunchKernelGGL(k_restrict_kappa<1>, gr, dim3(kBlock), 0, c->stream, F.n, L.n, F.kraw + r * F.g.nnodes, L.kraw + r * nn); break;
-            case 2: hipLaunchKernelGGL(k_restrict_kappa<2>, gr, dim3(kBlock), 0, c->stream, F.n, L.n, F.kraw + r * F.g.nnodes, L.kraw + r * nn); break;
-            default: hipLaunchKernelGGL(k_restrict_kappa<3>, gr, dim3(kBlock), 0, c->stream, F.n, L.n, F.kraw + r * F.g.nnodes, L.kraw + r * nn); break;
+            case 1: KLAUNCH(k_restrict_kappa<1>, gr, dim3(kBlock), 0, c->stream, F.n, L.n, F.kraw + r * F.g.nnodes, L.kraw + r * nn); break;
+            case 2: KLAUNCH(k_restrict_kappa<2>, gr, dim3(kBlock), 0, c->stream, F.n, L.n, F.kraw + r * F.g.nnodes, L.kraw + r * nn); break;
+            default: KLAUNCH(k_restrict_kappa<3>, gr, dim3(kBlock), 0, c->stream, F.n, L.n, F.kraw + r * F.g.nnodes, L.kraw + r * nn); break;
           }
           LAUNCH_CHECK();
         }
       }
       const double sc = 0.5 / (L.h * L.h);
       const long tot = nn * R;
-      hipLaunchKernelGGL((k_scale_copy<TC>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
+      KLAUNCH((k_scale_copy<TC>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
                          tot, (const double*)L.kraw, sc, (TC*)L.kscaled);
       LAUNCH_CHECK();
       if (l == 0) {
-        hipLaunchKernelGGL((k_scale_copy<double>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+        KLAUNCH((k_scale_copy<double>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                            c->stream, tot, (const double*)L.kraw, sc, c->kap64);
         LAUNCH_CHECK();
       }
@@ -384,9 +505,18 @@ struct Solver : SolverBase {
 size_t plan(stp_ctx* c, Bump& bp) {
   const int prec = c->opt.precision;
   const size_t tsb = ts_bytes(prec), tcb = tc_bytes(prec);
+  fft_layout(c->N, tcb, c->fft_cols, c->fft_lds);
   const long N = c->N;
   c->state = (DevState*)bp.take(sizeof(DevState));
-  c->npartial = long(grid_pts(c->g0.npts, c->N).x) * grid_pts(c->g0.npts, c->N).y * grid_pts(c->g0.npts, c->N).z;
+  {
+    long tiles = c->dim == 1 ? tiles_for<1, UpTile<1>>(c->n)
+                 : c->dim == 2 ? tiles_for<2, UpTile<2>>(c->n) : tiles_for<3, UpTile<3>>(c->n);
+    const dim3 gp = grid_pts(c->g0.npts, c->N);   // the setup reduction uses the point grid
+    const long gyz = long(std::min(c->N, 65535)) * ((c->N + 65534) / 65535);
+    c->npart_resid = tiles * gyz;
+    c->npart_points = long(gp.x) * gp.y * gp.z;
+    c->npartial = std::max(c->npart_resid, c->npart_points);
+  }
   c->partial = (double*)bp.take(size_t(c->npartial) * 8);
   c->kap64 = (double*)bp.take(size_t(c->R) * c->g0.nnodes * 8);
   c->cA64 = (double*)bp.take(size_t(N) * kMaxRank * 8);
@@ -394,8 +524,13 @@ size_t plan(stp_ctx* c, Bump& bp) {
   c->cH = bp.take(size_t(N) * kMaxRank * tcb);
   c->sigH = bp.take(size_t(N) * tcb);
   c->cMid = bp.take(size_t(kMaxRank) * tcb);
-  c->sinT = bp.take(size_t(N) * N * tcb);
-  c->sinM = bp.take(size_t(N) * N * tcb);
+  if (c->fft_cols > 0) {
+    c->tw = bp.take(size_t(2) * N * tcb);
+    c->tw4 = bp.take(size_t(2) * N * tcb);
+  } else {
+    c->sinT = bp.take(size_t(N) * N * tcb);
+    c->sinM = bp.take(size_t(N) * N * tcb);
+  }
   c->W1 = bp.take(size_t(N) * c->g0.npts * tsb);
   c->W2 = bp.take(size_t(N) * c->g0.npts * tsb);
   if (c->spatial == STP_SPATIAL_EXACT) c->tri = bp.take(size_t(2) * N * c->n * tcb);
@@ -411,8 +546,8 @@ size_t plan(stp_ctx* c, Bump& bp) {
     const bool last = (l + 1 == c->lv.size());
     L.b = (l == 0) ? nullptr : bp.take(vb);
     L.e = (l == 0) ? nullptr : bp.take(vb);
-    L.x = last ? nullptr : bp.take(vb);
-    L.t = (!last || l == 0) ? bp.take(vb) : nullptr;
+    L.x = nullptr;
+    L.t = (last && l == 0) ? bp.take(vb) : nullptr;   // single-level hierarchy: scratch for the coarse solve
   }
   return bp.off + 256;
 }
@@ -593,7 +728,7 @@ stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau, const
     double mn = 1e300;
     for (int pass = 0; pass < 2; ++pass) {
       const double* coef = pass == 0 ? c->cA64 : dref;
-      hipLaunchKernelGGL(k_kappa_min, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, nn, c->R, pass == 0 ? N : 1,
+      KLAUNCH(k_kappa_min, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, nn, c->R, pass == 0 ? N : 1,
                          c->fields, coef, part);
       LAUNCH_CHECK();
       HIP_TRY(hipMemcpyAsync(h.data(), part, size_t(nb) * 8, hipMemcpyDeviceToHost, c->stream));
@@ -606,9 +741,9 @@ stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau, const
   // ||f||
   {
     const dim3 gr = grid_pts(c->g0.npts, N);
-    hipLaunchKernelGGL(k_fnorm, gr, dim3(kBlock), 0, c->stream, c->g0, N, tau, F, u0, c->partial);
+    KLAUNCH(k_fnorm, gr, dim3(kBlock), 0, c->stream, c->g0, N, tau, F, u0, c->partial);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial, c->npartial,
+    KLAUNCH(k_sum_to, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial, c->npart_points,
                        &c->state->fnorm);
     LAUNCH_CHECK();
     DevState hs{};
@@ -629,6 +764,7 @@ void stp_destroy(stp_ctx* c) {
   if (c->state_host) (void)hipHostFree(c->state_host);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->kt.pool) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -639,15 +775,15 @@ stp_status stp_apply_operator(stp_ctx* c, int op, const double* x, double* y) {
   const long nv = long(c->N) * c->g0.npts;
   if (op == STP_OP_B) {
     switch (c->dim) {
-      case 1: hipLaunchKernelGGL(k_apply_B<1>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, y); break;
-      case 2: hipLaunchKernelGGL(k_apply_B<2>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, y); break;
-      default: hipLaunchKernelGGL(k_apply_B<3>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, y); break;
+      case 1: KLAUNCH(k_apply_B<1>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, y); break;
+      case 2: KLAUNCH(k_apply_B<2>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, y); break;
+      default: KLAUNCH(k_apply_B<3>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, y); break;
     }
   } else if (op == STP_OP_SADDLE) {
     switch (c->dim) {
-      case 1: hipLaunchKernelGGL(k_apply_saddle<1>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, x + nv, y, y + nv); break;
-      case 2: hipLaunchKernelGGL(k_apply_saddle<2>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, x + nv, y, y + nv); break;
-      default: hipLaunchKernelGGL(k_apply_saddle<3>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, x + nv, y, y + nv); break;
+      case 1: KLAUNCH(k_apply_saddle<1>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, x + nv, y, y + nv); break;
+      case 2: KLAUNCH(k_apply_saddle<2>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, x + nv, y, y + nv); break;
+      default: KLAUNCH(k_apply_saddle<3>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, x + nv, y, y + nv); break;
     }
   } else {
     return fail(STP_EINVAL, "unknown operator %d", op);
@@ -684,8 +820,10 @@ stp_status stp_uzawa_solve(stp_ctx* c, double* u, double* p, stp_stats* stats) {
   stp_status s = STP_OK;
   int launched = 0;
   DevState hs{};
+  const int max_launch = c->opt.max_iter + 1;   // iterations 0..max_iter each evaluate the stop test
   while (true) {
-    for (int q = 0; q < chunk; ++q) {
+    const int todo = std::min(chunk, max_launch - launched);
+    for (int q = 0; q < todo; ++q) {
       if ((s = c->impl->iteration(u, p)) != STP_OK) return s;
       ++launched;
     }
@@ -693,7 +831,7 @@ stp_status stp_uzawa_solve(stp_ctx* c, double* u, double* p, stp_stats* stats) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     hs = *c->state_host;
     if (hs.done) break;
-    if (launched > c->opt.max_iter + 2 * chunk + 2) return fail(STP_EDEVICE, "iteration state did not terminate");
+    if (launched >= max_launch) return fail(STP_EDEVICE, "iteration state did not terminate");
   }
   HIP_TRY(hipEventRecord(c->ev1, c->stream));
   HIP_TRY(hipEventSynchronize(c->ev1));
@@ -710,6 +848,48 @@ stp_status stp_uzawa_solve(stp_ctx* c, double* u, double* p, stp_stats* stats) {
   if (res == STP_EDIVERGED) fail(res, "residual diverged at iteration %d (rel %.3e)", hs.iter, hs.rel);
   if (res == STP_ENOTCONV) fail(res, "max_iter %d reached (rel %.3e)", c->opt.max_iter, hs.rel);
   return res;
+}
+
+stp_status stp_timing_enable(stp_ctx* c, int enable) {
+  if (!c) return fail(STP_EINVAL, "NULL context");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->kt.recs.clear();
+  c->kt.agg.clear();
+  c->kt.used = 0;
+  c->kt.pend_name = nullptr;
+  c->kt.on = enable != 0;
+  return STP_OK;
+}
+
+int stp_timing_count(stp_ctx* c) {
+  if (!c) return -1;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return -1;
+  for (const auto& r : c->kt.recs) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+    bool found = false;
+    for (auto& a : c->kt.agg)
+      if (a.level == r.level && a.name == r.name) {
+        a.count += 1;
+        a.ms += ms;
+        found = true;
+        break;
+      }
+    if (!found) c->kt.agg.push_back({std::string(r.name), r.level, 1, double(ms)});
+  }
+  c->kt.recs.clear();
+  c->kt.used = 0;
+  return int(c->kt.agg.size());
+}
+
+stp_status stp_timing_get(stp_ctx* c, int idx, const char** name, int* level, long* launches, double* total_ms) {
+  if (!c || idx < 0 || idx >= int(c->kt.agg.size())) return fail(STP_EINVAL, "bad timing index");
+  const auto& a = c->kt.agg[idx];
+  if (name) *name = a.name.c_str();
+  if (level) *level = a.level;
+  if (launches) *launches = a.count;
+  if (total_ms) *total_ms = a.ms;
+  return STP_OK;
 }
 
 }  // extern "C"

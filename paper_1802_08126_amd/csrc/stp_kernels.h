@@ -603,6 +603,140 @@ __global__ void __launch_bounds__(kBlock) k_time_dense(long npts, int N, const T
   }
 }
 
+// ---------------------------------------------------------------------------
+// fast transforms along time for N = 2^m (length-N complex FFT in LDS)
+//
+//   MODE_A4:  out[k] = sum_n sin((2k+1)(n+1) pi / 2N) in[n]            (Phi^{-T})
+//             s_m = in[N-1-m] * w4^m,  W = FFT(s),  Y_{2m} = Re W_m,
+//             Y_{2m+1} = Re W_{N-1-m},  out[k] = (-1)^k Y_k
+//   MODE_A6:  out[n] = sum_k sin((2k+1)(n+1) pi / 2N) in[k]            (Phi^{-1})
+//             z_k = (-1)^k in[k];  v_m = z_{2m}, v_{N-1-m} = z_{2m+1};
+//             X = Re(w4^m FFT(v)_m);  out[n] = X_{N-1-n}
+// with w4 = exp(-i pi / 2N).  The FFT is a Stockham autosort with radix-4
+// stages (and one radix-2 stage when log2 N is odd); each block holds C
+// columns (consecutive spatial points) of all N time samples in LDS.
+// ---------------------------------------------------------------------------
+enum { MODE_A4 = 0, MODE_A6 = 1 };
+
+template <typename TC, int R, int MAXB>
+__device__ __forceinline__ void fft_stage(TC* re, TC* im, const TC* twr, const TC* twi, int N, int Ns, int C,
+                                          int col, int jg, int G) {
+  const int nb = N / R;
+  TC orr[MAXB * R], oii[MAXB * R];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = jg + b * G;
+    if (j < nb) {
+      const int k = j & (Ns - 1);
+      TC vr[R], vi[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const TC ar = re[(j + r * nb) * C + col], ai = im[(j + r * nb) * C + col];
+        if (r == 0) {
+          vr[r] = ar; vi[r] = ai;
+        } else {
+          const int ti = (k * r) * (N / (Ns * R));
+          const TC wr = twr[ti], wi = twi[ti];
+          vr[r] = ar * wr - ai * wi;
+          vi[r] = ar * wi + ai * wr;
+        }
+      }
+      if constexpr (R == 2) {
+        orr[b * R + 0] = vr[0] + vr[1]; oii[b * R + 0] = vi[0] + vi[1];
+        orr[b * R + 1] = vr[0] - vr[1]; oii[b * R + 1] = vi[0] - vi[1];
+      } else {
+        // radix-4 DFT with e^{-2 pi i/4} = -i
+        const TC s0r = vr[0] + vr[2], s0i = vi[0] + vi[2];
+        const TC d0r = vr[0] - vr[2], d0i = vi[0] - vi[2];
+        const TC s1r = vr[1] + vr[3], s1i = vi[1] + vi[3];
+        const TC d1r = vr[1] - vr[3], d1i = vi[1] - vi[3];
+        orr[b * R + 0] = s0r + s1r; oii[b * R + 0] = s0i + s1i;
+        orr[b * R + 2] = s0r - s1r; oii[b * R + 2] = s0i - s1i;
+        // q = 1: d0 - i d1 ; q = 3: d0 + i d1
+        orr[b * R + 1] = d0r + d1i; oii[b * R + 1] = d0i - d1r;
+        orr[b * R + 3] = d0r - d1i; oii[b * R + 3] = d0i + d1r;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = jg + b * G;
+    if (j < nb) {
+      const int k = j & (Ns - 1);
+      const int idxD = (j - k) * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        re[(idxD + q * Ns) * C + col] = orr[b * R + q];
+        im[(idxD + q * Ns) * C + col] = oii[b * R + q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// tw: 2N values (re[0..N), im[0..N)) of w_N^m; tw4: same for w_{4N}^m.
+template <typename TS, typename TC, int MODE, int ACC64>
+__global__ void __launch_bounds__(kBlock) k_time_fft(long npts, int N, int C, const TC* __restrict__ tw,
+                                                     const TC* __restrict__ tw4, const TS* __restrict__ in,
+                                                     TS* __restrict__ out, double* __restrict__ out64,
+                                                     double alpha, const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TC* re = reinterpret_cast<TC*>(smem_raw);
+  TC* im = re + N * C;
+  TC* twr = im + N * C;
+  TC* twi = twr + N;
+  TC* t4r = twi + N;
+  TC* t4i = t4r + N;
+  const int t = threadIdx.x;
+  for (int q = t; q < N; q += kBlock) {
+    twr[q] = tw[q]; twi[q] = tw[N + q];
+    t4r[q] = tw4[q]; t4i[q] = tw4[N + q];
+  }
+  __syncthreads();
+  const int col = t % C, jg = t / C, G = kBlock / C;
+  const long i = long(blockIdx.x) * C + col;
+  const bool valid = (jg < G) && (i < npts);
+  for (int n = jg; n < N; n += G) {
+    const TC v = valid ? ld<TC>(in, long(n) * npts + i) : TC(0);
+    if (MODE == MODE_A4) {
+      const int m = N - 1 - n;
+      re[m * C + col] = v * t4r[m];
+      im[m * C + col] = v * t4i[m];
+    } else {
+      const int pos = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
+      re[pos * C + col] = (n & 1) ? -v : v;
+      im[pos * C + col] = TC(0);
+    }
+  }
+  __syncthreads();
+  int Ns = 1;
+  while (Ns < N) {
+    if ((N / Ns) % 4 == 0) {
+      fft_stage<TC, 4, 4>(re, im, twr, twi, N, Ns, C, col, jg, G);
+      Ns *= 4;
+    } else {
+      fft_stage<TC, 2, 8>(re, im, twr, twi, N, Ns, C, col, jg, G);
+      Ns *= 2;
+    }
+  }
+  if (!valid) return;
+  for (int n = jg; n < N; n += G) {
+    TC v;
+    if (MODE == MODE_A4) {
+      const int m = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
+      v = (n & 1) ? -re[m * C + col] : re[m * C + col];
+    } else {
+      const int m = N - 1 - n;
+      v = t4r[m] * re[m * C + col] - t4i[m] * im[m * C + col];
+    }
+    const long o = long(n) * npts + i;
+    if (ACC64) out64[o] += alpha * double(v);
+    else st<TS, TC>(out, o, TC(alpha) * v);
+  }
+}
+
 // elementwise helpers
 template <typename TS>
 __global__ void k_cast_from64(long n, const double* __restrict__ a, TS* __restrict__ b) {
