@@ -165,6 +165,7 @@ struct stp_ctx {
   long npartial = 0;               // capacity of the partial-sum buffer
   long npart_resid = 0;            // partials written by the residual kernel (tile grid)
   long npart_points = 0;           // partials written by point-grid reductions
+  int sb_resid = 1;                // slabs per block of the residual kernels
   double* kap64 = nullptr;         // fine scaled fields, float64
   double* cA64 = nullptr;          // N x kMaxRank, tau*tcoef
   void* cA = nullptr;              // TC, N x kMaxRank
@@ -183,6 +184,11 @@ struct stp_ctx {
   SolverBase* impl = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   KTimer kt;
+  // one Uzawa iteration captured as a HIP graph (valid for the (u, p) it was captured with)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double* g_u = nullptr;
+  double* g_p = nullptr;
 };
 
 static inline void kt_begin(stp_ctx* c, const char* name) {
@@ -209,6 +215,11 @@ static inline void kt_end(stp_ctx* c) {
 #define KLAUNCH(kern, ...)                 \
   do {                                     \
     kt_begin(&*c, #kern);                  \
+    hipLaunchKernelGGL(kern, __VA_ARGS__); \
+  } while (0)
+#define KLAUNCH_NAMED(name, kern, ...)     \
+  do {                                     \
+    kt_begin(&*c, name);                   \
     hipLaunchKernelGGL(kern, __VA_ARGS__); \
   } while (0)
 
@@ -253,6 +264,20 @@ struct Solver : SolverBase {
 
   const int* st() const { return &c->state->done; }
 
+  // slabs per block for a launch over `tiles` tiles and S slabs: enough blocks
+  // to fill the chip several times over, otherwise runs of up to 16 slabs
+  static int pick_sb(long tiles, int S) {
+    long sb = (tiles * S) / 2048;
+    return int(std::max(1L, std::min(16L, sb)));
+  }
+  static dim3 grid_runs(long tiles, int S, int sb) {
+    const long runs = (S + sb - 1) / sb;
+    const long gy = std::min(runs, 65535L);
+    const long gz = (runs + 65534) / 65535;
+    return dim3(unsigned(tiles), unsigned(gy), unsigned(gz));
+  }
+  int rm() const { return c->R <= 1 ? 1 : (c->R <= 2 ? 2 : 4); }
+
   template <int D>
   stp_status vcycle_d(int l, int which, const TS* b, TS* out, double* acc64) {
     c->kt.level = l;
@@ -276,19 +301,31 @@ struct Solver : SolverBase {
       return STP_OK;
     }
     Level& C = c->lv[l + 1];
-    const dim3 grd(unsigned(tiles_for<D, DownTile<D>>(C.n)), unsigned(gy), unsigned(gz));
-    KLAUNCH((k_mg_down<D, TS, TC>), grd, dim3(kBlock), 0, c->stream, L.g, C.g, op, omegaJ(), b, (TS*)C.b, st());
+    switch (rm()) {
+      case 1: return vcycle_rm<D, 1>(l, which, op, L, C, b, out, acc64);
+      case 2: return vcycle_rm<D, 2>(l, which, op, L, C, b, out, acc64);
+      default: return vcycle_rm<D, 4>(l, which, op, L, C, b, out, acc64);
+    }
+  }
+
+  template <int D, int RM>
+  stp_status vcycle_rm(int l, int which, const LevelOp& op, Level& L, Level& C, const TS* b, TS* out, double* acc64) {
+    const long td = tiles_for<D, DownTile<D>>(C.n);
+    const int sbd = pick_sb(td, c->N);
+    KLAUNCH((k_mg_down<D, TS, TC, RM>), grid_runs(td, c->N, sbd), dim3(kBlock), 0, c->stream, L.g, C.g, op, omegaJ(),
+            b, (TS*)C.b, sbd, st());
     LAUNCH_CHECK();
     stp_status s = vcycle_d<D>(l + 1, which, (const TS*)C.b, (TS*)C.e, nullptr);
     if (s != STP_OK) return s;
     c->kt.level = l;
-    const dim3 gru(unsigned(tiles_for<D, UpTile<D>>(L.n)), unsigned(gy), unsigned(gz));
+    const long tu = tiles_for<D, UpTile<D>>(L.n);
+    const int sbu = pick_sb(tu, c->N);
     if (acc64)
-      KLAUNCH((k_mg_up<D, TS, TC, EPI_ADD64>), gru, dim3(kBlock), 0, c->stream, L.g, C.g, op, omegaJ(), b,
-              (const TS*)C.e, (TS*)nullptr, acc64, st());
+      KLAUNCH((k_mg_up<D, TS, TC, RM, EPI_ADD64>), grid_runs(tu, c->N, sbu), dim3(kBlock), 0, c->stream, L.g, C.g, op,
+              omegaJ(), b, (const TS*)C.e, (TS*)nullptr, acc64, sbu, st());
     else
-      KLAUNCH((k_mg_up<D, TS, TC, EPI_STORE>), gru, dim3(kBlock), 0, c->stream, L.g, C.g, op, omegaJ(), b,
-              (const TS*)C.e, out, (double*)nullptr, st());
+      KLAUNCH((k_mg_up<D, TS, TC, RM, EPI_STORE>), grid_runs(tu, c->N, sbu), dim3(kBlock), 0, c->stream, L.g, C.g, op,
+              omegaJ(), b, (const TS*)C.e, out, (double*)nullptr, sbu, st());
     LAUNCH_CHECK();
     return STP_OK;
   }
@@ -317,11 +354,22 @@ struct Solver : SolverBase {
   stp_status apply_mid(const TS* x, TS* y) {
     c->kt.level = 0;
     const LevelOp op = fam(0, 2);
-    const int gy = std::min(c->N, 65535), gz = (c->N + 65534) / 65535;
     switch (c->dim) {
-      case 1: KLAUNCH((k_apply_tile<1, TS, TC>), dim3(unsigned(tiles_for<1, UpTile<1>>(c->n)), gy, gz), dim3(kBlock), 0, c->stream, c->g0, op, x, y, st()); break;
-      case 2: KLAUNCH((k_apply_tile<2, TS, TC>), dim3(unsigned(tiles_for<2, UpTile<2>>(c->n)), gy, gz), dim3(kBlock), 0, c->stream, c->g0, op, x, y, st()); break;
-      default: KLAUNCH((k_apply_tile<3, TS, TC>), dim3(unsigned(tiles_for<3, UpTile<3>>(c->n)), gy, gz), dim3(kBlock), 0, c->stream, c->g0, op, x, y, st()); break;
+      case 1: return apply_mid_d<1>(op, x, y);
+      case 2: return apply_mid_d<2>(op, x, y);
+      default: return apply_mid_d<3>(op, x, y);
+    }
+  }
+
+  template <int D>
+  stp_status apply_mid_d(const LevelOp& op, const TS* x, TS* y) {
+    const long tiles = tiles_for<D, UpTile<D>>(c->n);
+    const int sb = pick_sb(tiles, c->N);
+    const dim3 gr = grid_runs(tiles, c->N, sb);
+    switch (rm()) {
+      case 1: KLAUNCH((k_apply_tile<D, TS, TC, 1>), gr, dim3(kBlock), 0, c->stream, c->g0, op, x, y, sb, st()); break;
+      case 2: KLAUNCH((k_apply_tile<D, TS, TC, 2>), gr, dim3(kBlock), 0, c->stream, c->g0, op, x, y, sb, st()); break;
+      default: KLAUNCH((k_apply_tile<D, TS, TC, 4>), gr, dim3(kBlock), 0, c->stream, c->g0, op, x, y, sb, st()); break;
     }
     LAUNCH_CHECK();
     return STP_OK;
@@ -331,6 +379,17 @@ struct Solver : SolverBase {
   stp_status time_transform(int mode, const TS* in, TS* out, double* acc64, double alpha) {
     c->kt.level = 0;
     const long npts = c->g0.npts;
+    if (c->N >= 4 && c->N <= 256 && (c->N & (c->N - 1)) == 0) {
+      switch (c->N) {
+        case 4: return fft2<1, 1>(mode, in, out, acc64, alpha);
+        case 8: return fft2<2, 1>(mode, in, out, acc64, alpha);
+        case 16: return fft2<2, 2>(mode, in, out, acc64, alpha);
+        case 32: return fft2<3, 2>(mode, in, out, acc64, alpha);
+        case 64: return fft2<3, 3>(mode, in, out, acc64, alpha);
+        case 128: return fft2<4, 3>(mode, in, out, acc64, alpha);
+        default: return fft2<4, 4>(mode, in, out, acc64, alpha);
+      }
+    }
     if (c->fft_cols > 0) {
       const int C = c->fft_cols;
       const dim3 gr(unsigned((npts + C - 1) / C));
@@ -362,6 +421,27 @@ struct Solver : SolverBase {
     return STP_OK;
   }
 
+  template <int L1, int L2>
+  stp_status fft2(int mode, const TS* in, TS* out, double* acc64, double alpha) {
+    constexpr int C = kBlock / (1 << L1);
+    const long npts = c->g0.npts;
+    const dim3 gr(unsigned((npts + C - 1) / C));
+    const size_t lds = size_t(1 << (L1 + L2)) * C * sizeof(TC);
+    const TC* tw = (const TC*)c->tw;
+    const TC* tw4 = (const TC*)c->tw4;
+    if (mode == 0)
+      KLAUNCH((k_time_fft2<TS, TC, MODE_A4, 0, L1, L2>), gr, dim3(kBlock), lds, c->stream, npts, tw, tw4, in, out,
+              (double*)nullptr, alpha, st());
+    else if (acc64)
+      KLAUNCH((k_time_fft2<TS, TC, MODE_A6, 1, L1, L2>), gr, dim3(kBlock), lds, c->stream, npts, tw, tw4, in,
+              (TS*)nullptr, acc64, alpha, st());
+    else
+      KLAUNCH((k_time_fft2<TS, TC, MODE_A6, 0, L1, L2>), gr, dim3(kBlock), lds, c->stream, npts, tw, tw4, in, out,
+              (double*)nullptr, alpha, st());
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
   stp_status precA(const void* b, double* acc64, void* out) override {
     return spatial_solve(0, (const TS*)b, (TS*)out, acc64);
   }
@@ -378,21 +458,32 @@ struct Solver : SolverBase {
     return time_transform(1, W1, (TS*)out, acc64, alpha);                             // Phi^{-1} yhat
   }
 
+  template <int D, int WHICH>
+  stp_status resid_launch(const dim3& gr, const TimeOp& t, const double* u, const double* p, int sb) {
+    double* part = WHICH == 1 ? c->partial : nullptr;
+    const char* nm = WHICH == 0 ? "k_resid_tile<a1>" : "k_resid_tile<a3>";
+    switch (rm()) {
+      case 1: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, 1>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, u, p, c->F, c->u0, (TS*)c->W1, part, sb, st()); break;
+      case 2: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, 2>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, u, p, c->F, c->u0, (TS*)c->W1, part, sb, st()); break;
+      default: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, 4>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, u, p, c->F, c->u0, (TS*)c->W1, part, sb, st()); break;
+    }
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
   template <int D>
   stp_status iteration_d(double* u, double* p) {
     c->kt.level = 0;
-    const int gy = std::min(c->N, 65535), gz = (c->N + 65534) / 65535;
-    const dim3 gr(unsigned(tiles_for<D, UpTile<D>>(c->n)), unsigned(gy), unsigned(gz));
+    const long tiles = tiles_for<D, UpTile<D>>(c->n);
+    const int sb = c->sb_resid;
+    const dim3 gr = grid_runs(tiles, c->N, sb);
     TimeOp t{c->kap64, c->cA64, c->R, c->N};
-    KLAUNCH((k_resid_tile<D, TS, 0>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, (const double*)u,
-            (const double*)p, c->F, c->u0, (TS*)c->W1, (double*)nullptr, st());
-    LAUNCH_CHECK();
-    stp_status s = spatial_solve(0, (const TS*)c->W1, nullptr, p);   // p += A~^{-1} r_p
+    stp_status s;
+    if ((s = resid_launch<D, 0>(gr, t, u, p, sb)) != STP_OK) return s;
+    s = spatial_solve(0, (const TS*)c->W1, nullptr, p);   // p += A~^{-1} r_p
     if (s != STP_OK) return s;
     c->kt.level = 0;
-    KLAUNCH((k_resid_tile<D, TS, 1>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, (const double*)u,
-            (const double*)p, c->F, c->u0, (TS*)c->W1, c->partial, st());
-    LAUNCH_CHECK();
+    if ((s = resid_launch<D, 1>(gr, t, u, p, sb)) != STP_OK) return s;
     KLAUNCH(k_finalize, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial, c->npart_resid,
                        c->state, c->opt.tol, c->opt.max_iter);
     LAUNCH_CHECK();
@@ -454,6 +545,18 @@ struct Solver : SolverBase {
     HIP_TRY(hipMemcpyAsync(c->cH, cH.data(), cH.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->sigH, sig.data(), sig.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->cMid, mid.data(), mid.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+    {
+      double wd[32];
+      float wf[32];
+      for (int k = 0; k < 16; ++k) {
+        wd[k] = std::cos(2.0 * M_PI * k / 16.0);
+        wd[16 + k] = -std::sin(2.0 * M_PI * k / 16.0);
+        wf[k] = float(wd[k]);
+        wf[16 + k] = float(wd[16 + k]);
+      }
+      HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_w16d), wd, sizeof(wd)));
+      HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_w16f), wf, sizeof(wf)));
+    }
     if (c->fft_cols > 0) {
       std::vector<TC> tw(2 * size_t(N)), tw4(2 * size_t(N));
       for (int m = 0; m < N; ++m) {
@@ -513,7 +616,13 @@ size_t plan(stp_ctx* c, Bump& bp) {
                  : c->dim == 2 ? tiles_for<2, UpTile<2>>(c->n) : tiles_for<3, UpTile<3>>(c->n);
     const dim3 gp = grid_pts(c->g0.npts, c->N);   // the setup reduction uses the point grid
     const long gyz = long(std::min(c->N, 65535)) * ((c->N + 65534) / 65535);
-    c->npart_resid = tiles * gyz;
+    {
+      long sb = (tiles * c->N) / 2048;
+      c->sb_resid = int(std::max(1L, std::min(16L, sb)));
+    }
+    const long runs = (c->N + c->sb_resid - 1) / c->sb_resid;
+    c->npart_resid = tiles * std::min(runs, 65535L) * ((runs + 65534) / 65535);
+    (void)gyz;
     c->npart_points = long(gp.x) * gp.y * gp.z;
     c->npartial = std::max(c->npart_resid, c->npart_points);
   }
@@ -765,6 +874,8 @@ void stp_destroy(stp_ctx* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   for (hipEvent_t e : c->kt.pool) (void)hipEventDestroy(e);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
@@ -809,6 +920,41 @@ stp_status stp_apply_precond(stp_ctx* c, int which, const double* r, double* z) 
   return c->impl->precH(c->W1, c->W2, z, nullptr, 1.0);
 }
 
+// Capture one iteration on a private stream (capture is not possible on the
+// null stream); the instantiated graph is replayed on the context's stream.
+static stp_status capture_iteration(stp_ctx* c, double* u, double* p) {
+  if (c->gexec && c->g_u == u && c->g_p == p) return STP_OK;
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipStream_t saved = c->stream;
+  c->stream = c->cap_stream;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  stp_status s = STP_OK;
+  if (e == hipSuccess) {
+    s = c->impl->iteration(u, p);
+    e = hipStreamEndCapture(c->cap_stream, &graph);
+  }
+  c->stream = saved;
+  if (s != STP_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return fail(STP_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    c->gexec = nullptr;
+    return fail(STP_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+  }
+  c->g_u = u;
+  c->g_p = p;
+  return STP_OK;
+}
+
 stp_status stp_uzawa_solve(stp_ctx* c, double* u, double* p, stp_stats* stats) {
   if (!c || !u || !p) return fail(STP_EINVAL, "NULL argument (u and p are required)");
   if (c->spatial == STP_SPATIAL_NONE) return fail(STP_EUNSUPPORTED, "context created without a spatial solver");
@@ -821,10 +967,13 @@ stp_status stp_uzawa_solve(stp_ctx* c, double* u, double* p, stp_stats* stats) {
   int launched = 0;
   DevState hs{};
   const int max_launch = c->opt.max_iter + 1;   // iterations 0..max_iter each evaluate the stop test
+  const bool graph = c->opt.use_graph && !c->kt.on;
+  if (graph && (s = capture_iteration(c, u, p)) != STP_OK) return s;
   while (true) {
     const int todo = std::min(chunk, max_launch - launched);
     for (int q = 0; q < todo; ++q) {
-      if ((s = c->impl->iteration(u, p)) != STP_OK) return s;
+      if (graph) HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
+      else if ((s = c->impl->iteration(u, p)) != STP_OK) return s;
       ++launched;
     }
     HIP_TRY(hipMemcpyAsync(c->state_host, c->state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));

@@ -737,6 +737,156 @@ __global__ void __launch_bounds__(kBlock) k_time_fft(long npts, int N, int C, co
   }
 }
 
+// ---------------------------------------------------------------------------
+// two-step ("four-step") FFT variant for N = N1 * N2 <= 256 (N1 = 2^L1 >= N2 = 2^L2):
+//   step 1: thread (col, n2) runs an N1-point DFT in registers over the samples
+//           x[N2 n1 + n2] loaded straight from global memory, then twiddles by
+//           w_N^{n2 k1};
+//   step 2: one transpose through LDS;
+//   step 3: thread (col, k1) runs an N2-point DFT in registers and writes
+//           X[k1 + N1 k2] straight to global memory.
+// The pre/post-processing of MODE_A4 / MODE_A6 (see above) is folded into the
+// load and store addressing.  c_w16 holds w_16^k (set by the host).
+// ---------------------------------------------------------------------------
+__constant__ double c_w16d[32];   // re[0..16), im[16..32)
+__constant__ float c_w16f[32];
+
+template <typename TC> __device__ __forceinline__ TC w16re(int k);
+template <typename TC> __device__ __forceinline__ TC w16im(int k);
+template <> __device__ __forceinline__ double w16re<double>(int k) { return c_w16d[k]; }
+template <> __device__ __forceinline__ double w16im<double>(int k) { return c_w16d[16 + k]; }
+template <> __device__ __forceinline__ float w16re<float>(int k) { return c_w16f[k]; }
+template <> __device__ __forceinline__ float w16im<float>(int k) { return c_w16f[16 + k]; }
+
+template <int P>
+__host__ __device__ constexpr int brev(int i) {
+  int r = 0;
+  for (int b = 1, rb = P >> 1; b < P; b <<= 1, rb >>= 1)
+    if (i & b) r |= rb;
+  return r;
+}
+
+// in-register radix-2 DIT DFT of size P <= 16 (forward, exp(-2 pi i/P)), natural order out
+template <int P, typename TC>
+__device__ __forceinline__ void dft_reg(TC (&xr)[P], TC (&xi)[P]) {
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int j = brev<P>(i);
+    if (j > i) {
+      TC t = xr[i]; xr[i] = xr[j]; xr[j] = t;
+      t = xi[i]; xi[i] = xi[j]; xi[j] = t;
+    }
+  }
+#pragma unroll
+  for (int half = 1; half < P; half <<= 1) {
+#pragma unroll
+    for (int base = 0; base < P; base += 2 * half) {
+#pragma unroll
+      for (int j = 0; j < half; ++j) {
+        const int a = base + j, b = a + half;
+        TC tr, ti;
+        if (j == 0) {
+          tr = xr[b]; ti = xi[b];
+        } else {
+          const int tw = j * (16 / (2 * half));
+          const TC wr = w16re<TC>(tw), wi = w16im<TC>(tw);
+          tr = xr[b] * wr - xi[b] * wi;
+          ti = xr[b] * wi + xi[b] * wr;
+        }
+        xr[b] = xr[a] - tr; xi[b] = xi[a] - ti;
+        xr[a] = xr[a] + tr; xi[a] = xi[a] + ti;
+      }
+    }
+  }
+}
+
+// tw / tw4: 2N tables as in k_time_fft.  Dynamic LDS: N * C * sizeof(TC)
+// (real and imaginary parts pass through it one after the other).
+template <typename TS, typename TC, int MODE, int ACC64, int L1, int L2>
+__global__ void __launch_bounds__(kBlock) k_time_fft2(long npts, const TC* __restrict__ tw,
+                                                      const TC* __restrict__ tw4, const TS* __restrict__ in,
+                                                      TS* __restrict__ out, double* __restrict__ out64, double alpha,
+                                                      const int* __restrict__ state) {
+  if (state && done_flag(state)) return;
+  constexpr int N1 = 1 << L1, N2 = 1 << L2, N = N1 * N2;
+  constexpr int C = kBlock / N1;             // columns per block
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TC* lds = reinterpret_cast<TC*>(smem_raw);  // [k1][n2][col]
+  const int t = threadIdx.x;
+  const int col = t % C, j = t / C;          // j = n2 (step 1, if < N2) or k1 (step 3)
+  const long i = long(blockIdx.x) * C + col;
+  const bool valid = i < npts;
+  TC xr[N1], xi[N1];
+  const bool act1 = j < N2;
+  if (act1) {
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int m = N2 * n1 + j;             // FFT input index
+      int row;
+      TC sgn = TC(1);
+      if (MODE == MODE_A4) {
+        row = N - 1 - m;
+      } else {
+        if (m < N / 2) row = 2 * m;
+        else { row = 2 * (N - 1 - m) + 1; sgn = TC(-1); }
+      }
+      const TC v = valid ? sgn * ld<TC>(in, long(row) * npts + i) : TC(0);
+      if (MODE == MODE_A4) {
+        xr[n1] = v * tw4[m];
+        xi[n1] = v * tw4[N + m];
+      } else {
+        xr[n1] = v;
+        xi[n1] = TC(0);
+      }
+    }
+    dft_reg<N1, TC>(xr, xi);
+    // twiddle w_N^{n2 k1}
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) {
+      const int q = (j * k1) & (N - 1);
+      const TC wr = tw[q], wi = tw[N + q];
+      const TC a = xr[k1], b = xi[k1];
+      xr[k1] = a * wr - b * wi;
+      xi[k1] = a * wi + b * wr;
+    }
+  }
+  // transpose through LDS: real parts, then imaginary parts
+  TC yr[N2], yi[N2];
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+    if (act1) {
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) lds[(k1 * N2 + j) * C + col] = part == 0 ? xr[k1] : xi[k1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) {
+      const TC v = lds[(j * N2 + n2) * C + col];
+      if (part == 0) yr[n2] = v;
+      else yi[n2] = v;
+    }
+    __syncthreads();
+  }
+  if (N2 > 1) dft_reg<N2, TC>(yr, yi);
+  if (!valid) return;
+#pragma unroll
+  for (int k2 = 0; k2 < N2; ++k2) {
+    const int k = j + N1 * k2;               // FFT output index
+    int row;
+    TC v;
+    if (MODE == MODE_A4) {
+      if (k < N / 2) { row = 2 * k; v = yr[k2]; }
+      else { row = 2 * (N - 1 - k) + 1; v = -yr[k2]; }
+    } else {
+      row = N - 1 - k;
+      v = tw4[k] * yr[k2] - tw4[N + k] * yi[k2];
+    }
+    const long o = long(row) * npts + i;
+    if (ACC64) out64[o] += alpha * double(v);
+    else st<TS, TC>(out, o, TC(alpha) * v);
+  }
+}
+
 // elementwise helpers
 template <typename TS>
 __global__ void k_cast_from64(long n, const double* __restrict__ a, TS* __restrict__ b) {

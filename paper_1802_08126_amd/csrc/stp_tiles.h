@@ -7,8 +7,14 @@
 // face weight is kappa_s[i] + kappa_s[nb] and the diagonal is
 // sigma_s + sum over the 2d faces.
 //
-// Node coordinates are 1-based with 0 and n+1 on the boundary; interior
+// Node coordinates are 1-based with 0 and n+1 on the boundary; the interior
 // vector entry of node j sits at offset j-1 per axis.
+//
+// The kernels are written to keep the per-point instruction count low (they
+// would otherwise be issue-bound rather than HBM-bound): boxes are walked with
+// an incremental, division-free iterator, bounds tests are single unsigned
+// compares, offsets inside a slab are 32-bit, and the Jacobi divisions use
+// the hardware reciprocal refined by Newton steps.
 #pragma once
 #include "stp_kernels.h"
 
@@ -20,94 +26,169 @@ struct Box {
   static constexpr int Y = (D >= 2 ? EY : 1);
   static constexpr int Z = (D >= 3 ? EZ : 1);
   static constexpr int size = X * Y * Z;
-  __device__ static __forceinline__ void coords(int q, int& x, int& y, int& z) {
-    x = q % X;
-    y = (q / X) % Y;
-    z = q / (X * Y);
-  }
   __device__ static __forceinline__ int idx(int x, int y, int z) { return (z * Y + y) * X + x; }
 };
 
-// offsets of the 2d neighbours inside a box (x-, x+, y-, y+, z-, z+)
-template <int D, typename B>
-__device__ __forceinline__ int nb_off(int k) {
-  switch (k) {
-    case 0: return -1;
-    case 1: return 1;
-    case 2: return -B::X;
-    case 3: return B::X;
-    case 4: return -B::X * B::Y;
-    default: return B::X * B::Y;
+// Walks the linear positions q = threadIdx.x, threadIdx.x + kBlock, ... of a
+// box, keeping (x, y, z) up to date with adds and one conditional subtract
+// per axis instead of divisions.
+template <typename B>
+struct BoxIter {
+  static constexpr int DX = kBlock % B::X;
+  static constexpr int DR = kBlock / B::X;
+  static constexpr int DY = DR % B::Y;
+  static constexpr int DZ = DR / B::Y;
+  int q, x, y, z;
+  __device__ __forceinline__ BoxIter() {
+    q = threadIdx.x;
+    x = q % B::X;
+    const int r = q / B::X;
+    y = r % B::Y;
+    z = r / B::Y;
   }
+  __device__ __forceinline__ bool ok() const { return q < B::size; }
+  __device__ __forceinline__ void next() {
+    q += kBlock;
+    x += DX;
+    int cy = 0;
+    if (x >= B::X) { x -= B::X; cy = 1; }
+    y += DY + cy;
+    int cz = 0;
+    if (y >= B::Y) { y -= B::Y; cz = 1; }
+    z += DZ + cz;
+  }
+};
+
+template <typename B>
+__host__ __device__ constexpr int nit() {
+  return (B::size + kBlock - 1) / kBlock;
 }
 
-template <int D>
-__device__ __forceinline__ long node_index(int jx, int jy, int jz, long nn) {
-  if (D == 1) return jx;
-  if (D == 2) return long(jy) * nn + jx;
-  return (long(jz) * nn + jy) * nn + jx;
+// Fully unrolled walk over a box (compile-time trip count); `continue` in the
+// body moves on to the next position.
+#define STP_BOX_FOR(B, it)                                                  \
+  _Pragma("unroll") for (BoxIter<B> it; it.q < int(threadIdx.x) + nit<B>() * kBlock; it.next()) \
+    if (it.ok())
+
+// offsets of the 2d neighbours inside a box (x-, x+, y-, y+, z-, z+)
+template <typename B>
+__device__ __forceinline__ constexpr int nb_off(int k) {
+  return k == 0 ? -1 : k == 1 ? 1 : k == 2 ? -B::X : k == 3 ? B::X : k == 4 ? -B::X * B::Y : B::X * B::Y;
 }
 
-template <int D>
-__device__ __forceinline__ long vec_index(int jx, int jy, int jz, long n) {
-  // interior node (1-based) -> vector offset within a slab
-  if (D == 1) return jx - 1;
-  if (D == 2) return long(jy - 1) * n + (jx - 1);
-  return (long(jz - 1) * n + (jy - 1)) * n + (jx - 1);
-}
+__device__ __forceinline__ bool in_range(int j, int lo, int hi) { return unsigned(j - lo) <= unsigned(hi - lo); }
 
 template <int D>
 __device__ __forceinline__ bool in_nodes(int jx, int jy, int jz, int n) {
-  bool ok = jx >= 0 && jx <= n + 1;
-  if (D >= 2) ok = ok && jy >= 0 && jy <= n + 1;
-  if (D >= 3) ok = ok && jz >= 0 && jz <= n + 1;
+  bool ok = in_range(jx, 0, n + 1);
+  if (D >= 2) ok = ok && in_range(jy, 0, n + 1);
+  if (D >= 3) ok = ok && in_range(jz, 0, n + 1);
   return ok;
 }
 
 template <int D>
 __device__ __forceinline__ bool interior(int jx, int jy, int jz, int n) {
-  bool ok = jx >= 1 && jx <= n;
-  if (D >= 2) ok = ok && jy >= 1 && jy <= n;
-  if (D >= 3) ok = ok && jz >= 1 && jz <= n;
+  bool ok = in_range(jx, 1, n);
+  if (D >= 2) ok = ok && in_range(jy, 1, n);
+  if (D >= 3) ok = ok && in_range(jz, 1, n);
   return ok;
 }
 
-// Stage kappa_s over box KB whose origin is node (ox, oy, oz).
+// node (incl. boundary) -> offset in a nodal field; interior node -> vector offset
+template <int D>
+__device__ __forceinline__ int node_off(int jx, int jy, int jz, int n) {
+  const int nn = n + 2;
+  if (D == 1) return jx;
+  if (D == 2) return jy * nn + jx;
+  return (jz * nn + jy) * nn + jx;
+}
+template <int D>
+__device__ __forceinline__ int vec_off(int jx, int jy, int jz, int n) {
+  if (D == 1) return jx - 1;
+  if (D == 2) return (jy - 1) * n + (jx - 1);
+  return ((jz - 1) * n + (jy - 1)) * n + (jx - 1);
+}
+
+// reciprocal: hardware estimate + Newton refinement (float64), hardware (float32)
+__device__ __forceinline__ double rcp_fast(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_fast(float d) { return __builtin_amdgcn_rcpf(d); }
+
+// Stage kappa_s over box KB whose origin is node (ox, oy, oz).  All global
+// loads of the thread are issued before the first LDS store.
 template <int D, typename KB, typename TC>
 __device__ __forceinline__ void stage_kappa(TC* sk, const TC* __restrict__ kap, long nnodes, int n, int ox, int oy,
                                             int oz, const SlabOp<TC>& op, int R) {
-  const long nn = n + 2;
-  for (int q = threadIdx.x; q < KB::size; q += kBlock) {
-    int x, y, z;
-    KB::coords(q, x, y, z);
-    const int jx = ox + x, jy = oy + y, jz = oz + z;
-    TC v = 0;
-    if (in_nodes<D>(jx, jy, jz, n)) v = kmix(kap, nnodes, node_index<D>(jx, jy, jz, nn), op, R);
-    sk[q] = v;
+  constexpr int NI = nit<KB>();
+  TC v[NI];
+  BoxIter<KB> it;
+#pragma unroll
+  for (int k = 0; k < NI; ++k) {
+    v[k] = 0;
+    if (it.ok()) {
+      const int jx = ox + it.x, jy = oy + it.y, jz = oz + it.z;
+      if (in_nodes<D>(jx, jy, jz, n)) {
+        const int o = node_off<D>(jx, jy, jz, n);
+        v[k] = op.c[0] * kap[o];
+#pragma unroll
+        for (int r = 1; r < kMaxRank; ++r)
+          if (r < R) v[k] += op.c[r] * kap[r * nnodes + o];
+      }
+    }
+    it.next();
+  }
+#pragma unroll
+  for (int k = 0; k < NI; ++k) {
+    const int q = threadIdx.x + k * kBlock;
+    if (q < KB::size) sk[q] = v[k];
   }
 }
 
-// diagonal and off-diagonal sum at box position q of box XB, whose kappa box KB
-// is shifted by one node in every active axis.
-template <int D, typename XB, typename KB, typename TC>
-__device__ __forceinline__ TC diag_box(const TC* sk, int x, int y, int z, TC sigma) {
-  const int kq = KB::idx(x + 1, D >= 2 ? y + 1 : 0, D >= 3 ? z + 1 : 0);
+// Load a TS vector over box B (origin node (ox, oy, oz)) into registers,
+// zero outside the interior.
+template <int D, typename B, typename TS, typename TC>
+__device__ __forceinline__ void prefetch_box(TC (&v)[nit<B>()], const TS* __restrict__ xs, int n, int ox, int oy,
+                                             int oz) {
+  BoxIter<B> it;
+#pragma unroll
+  for (int k = 0; k < nit<B>(); ++k) {
+    v[k] = 0;
+    if (it.ok()) {
+      const int jx = ox + it.x, jy = oy + it.y, jz = oz + it.z;
+      if (interior<D>(jx, jy, jz, n)) v[k] = ld<TC>(xs, vec_off<D>(jx, jy, jz, n));
+    }
+    it.next();
+  }
+}
+
+// diagonal at x-box position xq; the kappa box is one node larger on each side
+template <int D, typename KB, typename TC>
+__device__ __forceinline__ TC diag_at_k(const TC* sk, int kq, TC sigma) {
   const TC kc = sk[kq];
   TC d = sigma + TC(2 * D) * kc;
 #pragma unroll
-  for (int k = 0; k < 2 * D; ++k) d += sk[kq + nb_off<D, KB>(k)];
+  for (int k = 0; k < 2 * D; ++k) d += sk[kq + nb_off<KB>(k)];
   return d;
 }
 
 template <int D, typename XB, typename KB, typename TC>
-__device__ __forceinline__ TC offsum_box(const TC* sk, const TC* sx, int x, int y, int z) {
-  const int kq = KB::idx(x + 1, D >= 2 ? y + 1 : 0, D >= 3 ? z + 1 : 0);
-  const int xq = XB::idx(x, y, z);
+__device__ __forceinline__ TC offsum_at(const TC* sk, const TC* sx, int kq, int xq) {
   const TC kc = sk[kq];
   TC o = 0;
 #pragma unroll
-  for (int k = 0; k < 2 * D; ++k) o += (kc + sk[kq + nb_off<D, KB>(k)]) * sx[xq + nb_off<D, XB>(k)];
+  for (int k = 0; k < 2 * D; ++k) o += (kc + sk[kq + nb_off<KB>(k)]) * sx[xq + nb_off<XB>(k)];
   return o;
+}
+
+// kappa-box position of x-box position (x, y, z) when KB is one node larger
+template <int D, typename KB>
+__device__ __forceinline__ int kpos(int x, int y, int z) {
+  return KB::idx(x + 1, D >= 2 ? y + 1 : 0, D >= 3 ? z + 1 : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -143,12 +224,83 @@ __device__ __forceinline__ void tile_origin(int n, int& tx, int& ty, int& tz) {
 }
 
 // ---------------------------------------------------------------------------
-// multigrid: pre-smooth from zero, residual and full-weighting restriction
-//   x1 = omega D^{-1} b,  r = b - L x1,  bc = R r
+// slab pipelining
+//
+// A block processes one spatial tile for a run of consecutive slabs
+// [s0, s0 + sb): the slab-independent coefficient fields of the tile are
+// loaded into registers once, and the next slab's vectors are prefetched into
+// registers while the current slab is computed from LDS, so global-memory
+// latency overlaps with work.  blockIdx.y (+ gridDim.y * blockIdx.z) numbers
+// the slab runs.
 // ---------------------------------------------------------------------------
-template <int D, typename TS, typename TC>
+__device__ __forceinline__ int rank_bound_ok(int r, int R) { return r < R; }
+
+// raw fields r < R over box KB (origin node ox, oy, oz); zero elsewhere
+template <int D, typename KB, typename TC, int RM>
+__device__ __forceinline__ void load_kraw(TC (&kr)[nit<KB>()][RM], const TC* __restrict__ kap, long nnodes, int R,
+                                          int n, int ox, int oy, int oz) {
+  BoxIter<KB> it;
+#pragma unroll
+  for (int k = 0; k < nit<KB>(); ++k) {
+#pragma unroll
+    for (int r = 0; r < RM; ++r) kr[k][r] = 0;
+    if (it.ok()) {
+      const int jx = ox + it.x, jy = oy + it.y, jz = oz + it.z;
+      if (in_nodes<D>(jx, jy, jz, n)) {
+        const int o = node_off<D>(jx, jy, jz, n);
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+          if (r < R) kr[k][r] = kap[r * nnodes + o];
+      }
+    }
+    it.next();
+  }
+}
+
+template <typename KB, typename TC, int RM>
+__device__ __forceinline__ void write_kappa(TC* sk, const TC (&kr)[nit<KB>()][RM], const SlabOp<TC>& op) {
+#pragma unroll
+  for (int k = 0; k < nit<KB>(); ++k) {
+    const int q = threadIdx.x + k * kBlock;
+    if (q < KB::size) {
+      TC v = op.c[0] * kr[k][0];
+#pragma unroll
+      for (int r = 1; r < RM; ++r) v += op.c[r] * kr[k][r];
+      sk[q] = v;
+    }
+  }
+}
+
+template <typename B, typename TC>
+__device__ __forceinline__ void write_box(TC* sx, const TC (&v)[nit<B>()]) {
+#pragma unroll
+  for (int k = 0; k < nit<B>(); ++k) {
+    const int q = threadIdx.x + k * kBlock;
+    if (q < B::size) sx[q] = v[k];
+  }
+}
+
+template <int N_>
+struct Regs {
+  template <typename TC>
+  __device__ static __forceinline__ void copy(TC (&dst)[N_], const TC (&src)[N_]) {
+#pragma unroll
+    for (int k = 0; k < N_; ++k) dst[k] = src[k];
+  }
+};
+
+__device__ __forceinline__ void slab_run(int S, int sb, int& s0, int& s1) {
+  s0 = slab_index() * sb;
+  s1 = min(S, s0 + sb);
+}
+
+// ---------------------------------------------------------------------------
+// multigrid: pre-smooth from zero, residual and full-weighting restriction
+//   x1 = omega D^{-1} b,  r = b - L x1 = (1 - omega) b + sum_nb w x1_nb,  bc = R r
+// ---------------------------------------------------------------------------
+template <int D, typename TS, typename TC, int RM>
 __global__ void __launch_bounds__(kBlock) k_mg_down(Geom gf, Geom gc, LevelOp L, TC omega, const TS* __restrict__ b,
-                                                    TS* __restrict__ bc, const int* __restrict__ state) {
+                                                    TS* __restrict__ bc, int sb, const int* __restrict__ state) {
   if (state && done_flag(state)) return;
   using T = DownTile<D>;
   using KB = Box<D, 2 * T::X + 5, 2 * T::Y + 5, 2 * T::Z + 5>;
@@ -157,81 +309,88 @@ __global__ void __launch_bounds__(kBlock) k_mg_down(Geom gf, Geom gc, LevelOp L,
   using CB = Box<D, T::X, T::Y, T::Z>;
   __shared__ TC sk[KB::size];
   __shared__ TC sx[XB::size];
+  __shared__ TC sb_[XB::size];
   __shared__ TC sr[RB::size];
-  const int s = slab_index();
-  if (s >= L.S) return;
+  int s0, s1;
+  slab_run(L.S, sb, s0, s1);
+  if (s0 >= s1) return;
   const int nf = gf.n, nc = gc.n;
   int tx, ty, tz;
   tile_origin<D, T>(nc, tx, ty, tz);
-  // first coarse node of the tile (1-based); fine node of coarse I is 2I
+  // first coarse node of the tile (1-based); the fine node of coarse I is 2I
   const int Ix = tx * T::X + 1, Iy = D >= 2 ? ty * T::Y + 1 : 1, Iz = D >= 3 ? tz * T::Z + 1 : 1;
   const int rx = 2 * Ix - 1, ry = D >= 2 ? 2 * Iy - 1 : 1, rz = D >= 3 ? 2 * Iz - 1 : 1;   // r-box origin
   const int xx = rx - 1, xy = D >= 2 ? ry - 1 : 1, xz = D >= 3 ? rz - 1 : 1;                // x1-box origin
-  const int kx = xx - 1, ky = D >= 2 ? xy - 1 : 1, kz = D >= 3 ? xz - 1 : 1;                // kappa-box origin
-  const SlabOp<TC> op = level_op<TC>(L, s);
-  stage_kappa<D, KB, TC>(sk, (const TC*)L.kap, gf.nnodes, nf, kx, ky, kz, op, L.R);
-  __syncthreads();
-  const TS* bs = b + long(s) * gf.npts;
-  for (int q = threadIdx.x; q < XB::size; q += kBlock) {
-    int x, y, z;
-    XB::coords(q, x, y, z);
-    const int jx = xx + x, jy = xy + y, jz = xz + z;
-    TC v = 0;
-    if (interior<D>(jx, jy, jz, nf)) {
-      const TC dg = diag_box<D, XB, KB, TC>(sk, x, y, z, op.sigma);
-      v = omega * ld<TC>(bs, vec_index<D>(jx, jy, jz, nf)) / dg;
+  TC kr[nit<KB>()][RM];
+  load_kraw<D, KB, TC, RM>(kr, (const TC*)L.kap, gf.nnodes, L.R, nf, xx - 1, D >= 2 ? xy - 1 : 1,
+                           D >= 3 ? xz - 1 : 1);
+  TC bn[nit<XB>()];
+  prefetch_box<D, XB, TS, TC>(bn, b + long(s0) * gf.npts, nf, xx, xy, xz);
+  const TC one_m_omega = TC(1) - omega;
+  for (int s = s0; s < s1; ++s) {
+    TC bcur[nit<XB>()];
+    Regs<nit<XB>()>::copy(bcur, bn);
+    if (s + 1 < s1) prefetch_box<D, XB, TS, TC>(bn, b + long(s + 1) * gf.npts, nf, xx, xy, xz);
+    const SlabOp<TC> op = level_op<TC>(L, s);
+    write_kappa<KB, TC, RM>(sk, kr, op);
+    __syncthreads();
+    {
+      BoxIter<XB> it;
+#pragma unroll
+      for (int k = 0; k < nit<XB>(); ++k) {
+        if (it.ok()) {
+          const int jx = xx + it.x, jy = xy + it.y, jz = xz + it.z;
+          TC v = 0;
+          if (interior<D>(jx, jy, jz, nf))
+            v = omega * bcur[k] * rcp_fast(diag_at_k<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma));
+          sx[it.q] = v;
+          sb_[it.q] = bcur[k];
+        }
+        it.next();
+      }
     }
-    sx[q] = v;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < RB::size; q += kBlock) {
-    int x, y, z;
-    RB::coords(q, x, y, z);
-    const int jx = rx + x, jy = ry + y, jz = rz + z;
-    TC v = 0;
-    if (interior<D>(jx, jy, jz, nf)) {
-      // box position of this node inside the x1 box is (x+1, y+1, z+1)
-      const int ax = x + 1, ay = D >= 2 ? y + 1 : 0, az = D >= 3 ? z + 1 : 0;
-      const TC dg = diag_box<D, XB, KB, TC>(sk, ax, ay, az, op.sigma);
-      const TC off = offsum_box<D, XB, KB, TC>(sk, sx, ax, ay, az);
-      v = ld<TC>(bs, vec_index<D>(jx, jy, jz, nf)) - (dg * sx[XB::idx(ax, ay, az)] - off);
+    __syncthreads();
+    STP_BOX_FOR(RB, it) {
+      // r-box position (x, y, z) is x1-box position (x+1, y+1, z+1); nodes outside
+      // the domain have b = x1 = 0 (their r is never restricted)
+      const int ax = it.x + 1, ay = D >= 2 ? it.y + 1 : 0, az = D >= 3 ? it.z + 1 : 0;
+      const int xq = XB::idx(ax, ay, az);
+      sr[it.q] = one_m_omega * sb_[xq] + offsum_at<D, XB, KB, TC>(sk, sx, kpos<D, KB>(ax, ay, az), xq);
     }
-    sr[q] = v;
-  }
-  __syncthreads();
-  TS* bcs = bc + long(s) * gc.npts;
-  for (int q = threadIdx.x; q < CB::size; q += kBlock) {
-    int x, y, z;
-    CB::coords(q, x, y, z);
-    const int Jx = Ix + x, Jy = Iy + y, Jz = Iz + z;
-    if (!interior<D>(Jx, Jy, Jz, nc)) continue;
-    // fine node 2J sits at r-box position 2x+1 per axis
-    const int cx = 2 * x + 1, cy = D >= 2 ? 2 * y + 1 : 0, cz = D >= 3 ? 2 * z + 1 : 0;
-    TC acc = 0;
+    __syncthreads();
+    TS* bcs = bc + long(s) * gc.npts;
+    STP_BOX_FOR(CB, it) {
+      const int Jx = Ix + it.x, Jy = Iy + it.y, Jz = Iz + it.z;
+      if (!interior<D>(Jx, Jy, Jz, nc)) continue;
+      // fine node 2J sits at r-box position 2x+1 per axis
+      const int c = RB::idx(2 * it.x + 1, D >= 2 ? 2 * it.y + 1 : 0, D >= 3 ? 2 * it.z + 1 : 0);
+      TC acc = 0;
 #pragma unroll
-    for (int dz = (D >= 3 ? -1 : 0); dz <= (D >= 3 ? 1 : 0); ++dz)
+      for (int dz = (D >= 3 ? -1 : 0); dz <= (D >= 3 ? 1 : 0); ++dz)
 #pragma unroll
-      for (int dy = (D >= 2 ? -1 : 0); dy <= (D >= 2 ? 1 : 0); ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          TC w = (dx == 0 ? TC(0.5) : TC(0.25));
+        for (int dy = (D >= 2 ? -1 : 0); dy <= (D >= 2 ? 1 : 0); ++dy) {
+          TC w = 1;
           if (D >= 2) w *= (dy == 0 ? TC(0.5) : TC(0.25));
           if (D >= 3) w *= (dz == 0 ? TC(0.5) : TC(0.25));
-          acc += w * sr[RB::idx(cx + dx, cy + dy, cz + dz)];
+          const int row = c + dz * RB::X * RB::Y + dy * RB::X;
+          acc += w * (TC(0.25) * sr[row - 1] + TC(0.5) * sr[row] + TC(0.25) * sr[row + 1]);
         }
-    st<TS, TC>(bcs, vec_index<D>(Jx, Jy, Jz, nc), acc);
+      st<TS, TC>(bcs, vec_off<D>(Jx, Jy, Jz, nc), acc);
+    }
+    // the next slab writes sk only after every thread has passed the barrier
+    // that ends its x1 phase, and sr only after two more barriers
   }
 }
 
 // ---------------------------------------------------------------------------
 // multigrid: coarse correction and post-smoothing
-//   x2 = omega D^{-1} b + P e,   x = x2 + omega D^{-1} (b - L x2)
+//   x2 = omega D^{-1} b + P e,   x = (1 - omega) x2 + omega D^{-1} (b + sum_nb w x2_nb)
 // epilogue: store x (TS) or add it into a float64 vector
 // ---------------------------------------------------------------------------
-template <int D, typename TS, typename TC, int EPI>
+template <int D, typename TS, typename TC, int RM, int EPI>
 __global__ void __launch_bounds__(kBlock) k_mg_up(Geom gf, Geom gc, LevelOp L, TC omega, const TS* __restrict__ b,
                                                   const TS* __restrict__ e, TS* __restrict__ out,
-                                                  double* __restrict__ acc64, const int* __restrict__ state) {
+                                                  double* __restrict__ acc64, int sb, const int* __restrict__ state) {
   if (state && done_flag(state)) return;
   using T = UpTile<D>;
   using KB = Box<D, T::X + 4, T::Y + 4, T::Z + 4>;
@@ -240,202 +399,251 @@ __global__ void __launch_bounds__(kBlock) k_mg_up(Geom gf, Geom gc, LevelOp L, T
   using TB = Box<D, T::X, T::Y, T::Z>;
   __shared__ TC sk[KB::size];
   __shared__ TC sx[XB::size];
-  __shared__ TC sb[XB::size];
+  __shared__ TC sb_[XB::size];
   __shared__ TC se[EB::size];
-  const int s = slab_index();
-  if (s >= L.S) return;
+  int s0, s1;
+  slab_run(L.S, sb, s0, s1);
+  if (s0 >= s1) return;
   const int nf = gf.n, nc = gc.n;
   int tx, ty, tz;
   tile_origin<D, T>(nf, tx, ty, tz);
   const int jx0 = tx * T::X + 1, jy0 = D >= 2 ? ty * T::Y + 1 : 1, jz0 = D >= 3 ? tz * T::Z + 1 : 1;
   const int xx = jx0 - 1, xy = D >= 2 ? jy0 - 1 : 1, xz = D >= 3 ? jz0 - 1 : 1;   // x2-box origin
-  const int kx = xx - 1, ky = D >= 2 ? xy - 1 : 1, kz = D >= 3 ? xz - 1 : 1;      // kappa-box origin
   const int ex = xx / 2, ey = D >= 2 ? xy / 2 : 1, ez = D >= 3 ? xz / 2 : 1;      // first coarse node
-  const SlabOp<TC> op = level_op<TC>(L, s);
-  stage_kappa<D, KB, TC>(sk, (const TC*)L.kap, gf.nnodes, nf, kx, ky, kz, op, L.R);
-  const TS* es = e + long(s) * gc.npts;
-  for (int q = threadIdx.x; q < EB::size; q += kBlock) {
-    int x, y, z;
-    EB::coords(q, x, y, z);
-    const int Jx = ex + x, Jy = ey + y, Jz = ez + z;
-    se[q] = interior<D>(Jx, Jy, Jz, nc) ? ld<TC>(es, vec_index<D>(Jx, Jy, Jz, nc)) : TC(0);
-  }
-  __syncthreads();
-  const TS* bs = b + long(s) * gf.npts;
-  for (int q = threadIdx.x; q < XB::size; q += kBlock) {
-    int x, y, z;
-    XB::coords(q, x, y, z);
-    const int jx = xx + x, jy = xy + y, jz = xz + z;
-    TC v = 0, bv = 0;
-    if (interior<D>(jx, jy, jz, nf)) {
-      bv = ld<TC>(bs, vec_index<D>(jx, jy, jz, nf));
-      const TC dg = diag_box<D, XB, KB, TC>(sk, x, y, z, op.sigma);
-      // multilinear interpolation from coarse nodes floor(j/2), ceil(j/2)
-      const int lx = (jx >> 1) - ex, ly = D >= 2 ? (jy >> 1) - ey : 0, lz = D >= 3 ? (jz >> 1) - ez : 0;
-      const int ox = jx & 1, oy = D >= 2 ? (jy & 1) : 0, oz = D >= 3 ? (jz & 1) : 0;
-      TC pe = 0;
-#pragma unroll
-      for (int az = 0; az <= (D >= 3 ? 1 : 0); ++az)
-#pragma unroll
-        for (int ay = 0; ay <= (D >= 2 ? 1 : 0); ++ay)
-#pragma unroll
-          for (int ax = 0; ax <= 1; ++ax) {
-            if ((ax && !ox) || (ay && !oy) || (az && !oz)) continue;
-            TC w = ox ? TC(0.5) : TC(1);
-            if (D >= 2) w *= oy ? TC(0.5) : TC(1);
-            if (D >= 3) w *= oz ? TC(0.5) : TC(1);
-            pe += w * se[EB::idx(lx + ax, ly + ay, lz + az)];
-          }
-      v = omega * bv / dg + pe;
+  TC kr[nit<KB>()][RM];
+  load_kraw<D, KB, TC, RM>(kr, (const TC*)L.kap, gf.nnodes, L.R, nf, xx - 1, D >= 2 ? xy - 1 : 1,
+                           D >= 3 ? xz - 1 : 1);
+  TC bn[nit<XB>()];
+  TC en[nit<EB>()];
+  prefetch_box<D, XB, TS, TC>(bn, b + long(s0) * gf.npts, nf, xx, xy, xz);
+  prefetch_box<D, EB, TS, TC>(en, e + long(s0) * gc.npts, nc, ex, ey, ez);
+  const TC one_m_omega = TC(1) - omega;
+  for (int s = s0; s < s1; ++s) {
+    TC bcur[nit<XB>()];
+    Regs<nit<XB>()>::copy(bcur, bn);
+    const SlabOp<TC> op = level_op<TC>(L, s);
+    write_kappa<KB, TC, RM>(sk, kr, op);
+    write_box<EB, TC>(se, en);
+    if (s + 1 < s1) {
+      prefetch_box<D, XB, TS, TC>(bn, b + long(s + 1) * gf.npts, nf, xx, xy, xz);
+      prefetch_box<D, EB, TS, TC>(en, e + long(s + 1) * gc.npts, nc, ex, ey, ez);
     }
-    sx[q] = v;
-    sb[q] = bv;
-  }
-  __syncthreads();
-  const long o = long(s) * gf.npts;
-  for (int q = threadIdx.x; q < TB::size; q += kBlock) {
-    int x, y, z;
-    TB::coords(q, x, y, z);
-    const int jx = jx0 + x, jy = jy0 + y, jz = jz0 + z;
-    if (!interior<D>(jx, jy, jz, nf)) continue;
-    const int ax = x + 1, ay = D >= 2 ? y + 1 : 0, az = D >= 3 ? z + 1 : 0;
-    const int xq = XB::idx(ax, ay, az);
-    const TC dg = diag_box<D, XB, KB, TC>(sk, ax, ay, az, op.sigma);
-    const TC off = offsum_box<D, XB, KB, TC>(sk, sx, ax, ay, az);
-    const TC x2 = sx[xq];
-    const TC v = x2 + omega * (sb[xq] - (dg * x2 - off)) / dg;
-    const long vi = o + vec_index<D>(jx, jy, jz, nf);
-    if (EPI == EPI_STORE) st<TS, TC>(out, vi, v);
-    else acc64[vi] += double(v);
+    __syncthreads();
+    {
+      BoxIter<XB> it;
+#pragma unroll
+      for (int k = 0; k < nit<XB>(); ++k) {
+        if (it.ok()) {
+          const int jx = xx + it.x, jy = xy + it.y, jz = xz + it.z;
+          TC v = 0;
+          if (interior<D>(jx, jy, jz, nf)) {
+            const TC wd = omega * rcp_fast(diag_at_k<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma));
+            // multilinear interpolation from coarse nodes floor(j/2) and, for odd j, floor(j/2)+1
+            const int lx = (jx >> 1) - ex, ly = D >= 2 ? (jy >> 1) - ey : 0, lz = D >= 3 ? (jz >> 1) - ez : 0;
+            const int ox = jx & 1, oy = D >= 2 ? (jy & 1) : 0, oz = D >= 3 ? (jz & 1) : 0;
+            const int e0 = EB::idx(lx, ly, lz);
+            auto px = [&](int base) -> TC { return ox ? TC(0.5) * (se[base] + se[base + 1]) : se[base]; };
+            TC pe;
+            if (D == 1) {
+              pe = px(e0);
+            } else if (D == 2) {
+              pe = oy ? TC(0.5) * (px(e0) + px(e0 + EB::X)) : px(e0);
+            } else {
+              auto pxy = [&](int base) -> TC { return oy ? TC(0.5) * (px(base) + px(base + EB::X)) : px(base); };
+              pe = oz ? TC(0.5) * (pxy(e0) + pxy(e0 + EB::X * EB::Y)) : pxy(e0);
+            }
+            v = wd * bcur[k] + pe;
+          }
+          sx[it.q] = v;
+          sb_[it.q] = bcur[k];
+        }
+        it.next();
+      }
+    }
+    __syncthreads();
+    TS* os = out ? out + long(s) * gf.npts : nullptr;
+    double* as = acc64 ? acc64 + long(s) * gf.npts : nullptr;
+    STP_BOX_FOR(TB, it) {
+      const int jx = jx0 + it.x, jy = jy0 + it.y, jz = jz0 + it.z;
+      if (!interior<D>(jx, jy, jz, nf)) continue;
+      const int ax = it.x + 1, ay = D >= 2 ? it.y + 1 : 0, az = D >= 3 ? it.z + 1 : 0;
+      const int xq = XB::idx(ax, ay, az);
+      const int kq = kpos<D, KB>(ax, ay, az);
+      const TC off = offsum_at<D, XB, KB, TC>(sk, sx, kq, xq);
+      const TC wd = omega * rcp_fast(diag_at_k<D, KB, TC>(sk, kq, op.sigma));
+      const TC v = one_m_omega * sx[xq] + wd * (sb_[xq] + off);
+      const int vo = vec_off<D>(jx, jy, jz, nf);
+      if (EPI == EPI_STORE) st<TS, TC>(os, vo, v);
+      else as[vo] += double(v);
+    }
+    __syncthreads();   // sk and se are rewritten for the next slab
   }
 }
 
 // ---------------------------------------------------------------------------
-// y = L x (tile version; the middle reference operator of the H-blocks)
+// y = L x (tile version; the middle reference operator of the H-blocks,
+// whose coefficients are the same for every slab)
 // ---------------------------------------------------------------------------
-template <int D, typename TS, typename TC>
+template <int D, typename TS, typename TC, int RM>
 __global__ void __launch_bounds__(kBlock) k_apply_tile(Geom g, LevelOp L, const TS* __restrict__ xv,
-                                                       TS* __restrict__ yv, const int* __restrict__ state) {
+                                                       TS* __restrict__ yv, int sb, const int* __restrict__ state) {
   if (state && done_flag(state)) return;
   using T = UpTile<D>;
   using KB = Box<D, T::X + 2, T::Y + 2, T::Z + 2>;
-  using XB = KB;
   using TB = Box<D, T::X, T::Y, T::Z>;
   __shared__ TC sk[KB::size];
-  __shared__ TC sx[XB::size];
-  const int s = slab_index();
-  if (s >= L.S) return;
+  __shared__ TC sx[KB::size];
+  int s0, s1;
+  slab_run(L.S, sb, s0, s1);
+  if (s0 >= s1) return;
   const int n = g.n;
   int tx, ty, tz;
   tile_origin<D, T>(n, tx, ty, tz);
   const int jx0 = tx * T::X + 1, jy0 = D >= 2 ? ty * T::Y + 1 : 1, jz0 = D >= 3 ? tz * T::Z + 1 : 1;
   const int ox = jx0 - 1, oy = D >= 2 ? jy0 - 1 : 1, oz = D >= 3 ? jz0 - 1 : 1;
-  const SlabOp<TC> op = level_op<TC>(L, s);
-  const TS* xs = xv + long(s) * g.npts;
-  const long nn = n + 2;
-  for (int q = threadIdx.x; q < KB::size; q += kBlock) {
-    int x, y, z;
-    KB::coords(q, x, y, z);
-    const int jx = ox + x, jy = oy + y, jz = oz + z;
-    TC kv = 0, v = 0;
-    if (in_nodes<D>(jx, jy, jz, n)) {
-      kv = kmix((const TC*)L.kap, g.nnodes, node_index<D>(jx, jy, jz, nn), op, L.R);
-      if (interior<D>(jx, jy, jz, n)) v = ld<TC>(xs, vec_index<D>(jx, jy, jz, n));
+  TC xn[nit<KB>()];
+  prefetch_box<D, KB, TS, TC>(xn, xv + long(s0) * g.npts, n, ox, oy, oz);
+  TC kr[nit<KB>()][RM];
+  load_kraw<D, KB, TC, RM>(kr, (const TC*)L.kap, g.nnodes, L.R, n, ox, oy, oz);
+  int cur = -1;
+  for (int s = s0; s < s1; ++s) {
+    const int so = L.uniform ? 0 : s;
+    if (so != cur) {
+      write_kappa<KB, TC, RM>(sk, kr, level_op<TC>(L, s));
+      cur = so;
     }
-    sk[q] = kv;
-    sx[q] = v;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < TB::size; q += kBlock) {
-    int x, y, z;
-    TB::coords(q, x, y, z);
-    const int jx = jx0 + x, jy = jy0 + y, jz = jz0 + z;
-    if (!interior<D>(jx, jy, jz, n)) continue;
-    const int ax = x + 1, ay = D >= 2 ? y + 1 : 0, az = D >= 3 ? z + 1 : 0;
-    const int kq = KB::idx(ax, ay, az);
-    const TC kc = sk[kq];
-    TC dg = op.sigma, off = 0;
+    write_box<KB, TC>(sx, xn);
+    const TC sigma = level_op<TC>(L, s).sigma;
+    if (s + 1 < s1) prefetch_box<D, KB, TS, TC>(xn, xv + long(s + 1) * g.npts, n, ox, oy, oz);
+    __syncthreads();
+    TS* ys = yv + long(s) * g.npts;
+    STP_BOX_FOR(TB, it) {
+      const int jx = jx0 + it.x, jy = jy0 + it.y, jz = jz0 + it.z;
+      if (!interior<D>(jx, jy, jz, n)) continue;
+      const int kq = KB::idx(it.x + 1, D >= 2 ? it.y + 1 : 0, D >= 3 ? it.z + 1 : 0);
+      const TC kc = sk[kq];
+      TC dg = sigma, off = 0;
 #pragma unroll
-    for (int k = 0; k < 2 * D; ++k) {
-      const TC w = kc + sk[kq + nb_off<D, KB>(k)];
-      dg += w;
-      off += w * sx[kq + nb_off<D, KB>(k)];
+      for (int k = 0; k < 2 * D; ++k) {
+        const TC w = kc + sk[kq + nb_off<KB>(k)];
+        dg += w;
+        off += w * sx[kq + nb_off<KB>(k)];
+      }
+      st<TS, TC>(ys, vec_off<D>(jx, jy, jz, n), dg * sx[kq] - off);
     }
-    st<TS, TC>(yv, long(s) * g.npts + vec_index<D>(jx, jy, jz, n), dg * sx[kq] - off);
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// time-global residuals (float64), tile versions
+// time-global residuals (float64), tile versions marching forward in time
 //   WHICH = 0 (a1):  r = (u_s - u_{s-1}) - tau A_s p_s - f_s
 //   WHICH = 1 (a3):  e = f_s - (u_s - u_{s-1}) - tau A_s u_s,
 //                    r = e - ((u+p)_s - (u+p)_{s+1}),  block partial of e^2
+// f_s = tau F_s (+ u0 on the first slab).  The tile values of u_s are kept
+// in registers and serve as u_{s-1} of the next slab.
 // ---------------------------------------------------------------------------
-template <int D, typename TS, int WHICH>
+template <int D, typename TS, int WHICH, int RM>
 __global__ void __launch_bounds__(kBlock) k_resid_tile(Geom g, TimeOp t, double tau, const double* __restrict__ u,
                                                        const double* __restrict__ p, const double* __restrict__ F,
                                                        const double* __restrict__ u0, TS* __restrict__ r,
-                                                       double* __restrict__ partial, const int* __restrict__ state) {
+                                                       double* __restrict__ partial, int sb,
+                                                       const int* __restrict__ state) {
   if (state && done_flag(state)) return;
   using T = UpTile<D>;
   using KB = Box<D, T::X + 2, T::Y + 2, T::Z + 2>;
   using TB = Box<D, T::X, T::Y, T::Z>;
+  constexpr int NT = nit<TB>();
   __shared__ double sk[KB::size];
   __shared__ double sx[KB::size];
-  const int s = slab_index();
+  int s0, s1;
+  slab_run(t.N, sb, s0, s1);
   double e2 = 0.0;
-  if (s < t.N) {
+  if (s0 < s1) {
     const int n = g.n;
     int tx, ty, tz;
     tile_origin<D, T>(n, tx, ty, tz);
     const int jx0 = tx * T::X + 1, jy0 = D >= 2 ? ty * T::Y + 1 : 1, jz0 = D >= 3 ? tz * T::Z + 1 : 1;
     const int ox = jx0 - 1, oy = D >= 2 ? jy0 - 1 : 1, oz = D >= 3 ? jz0 - 1 : 1;
-    const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
-    const long o = long(s) * g.npts;
-    const double* xs = (WHICH == 0 ? p : u) + o;   // operand of the stencil
-    const long nn = n + 2;
-    for (int q = threadIdx.x; q < KB::size; q += kBlock) {
-      int x, y, z;
-      KB::coords(q, x, y, z);
-      const int jx = ox + x, jy = oy + y, jz = oz + z;
-      double kv = 0, v = 0;
-      if (in_nodes<D>(jx, jy, jz, n)) {
-        kv = kmix(t.kap, g.nnodes, node_index<D>(jx, jy, jz, nn), op, t.R);
-        if (interior<D>(jx, jy, jz, n)) v = xs[vec_index<D>(jx, jy, jz, n)];
-      }
-      sk[q] = kv;
-      sx[q] = v;
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < TB::size; q += kBlock) {
-      int x, y, z;
-      TB::coords(q, x, y, z);
-      const int jx = jx0 + x, jy = jy0 + y, jz = jz0 + z;
-      if (!interior<D>(jx, jy, jz, n)) continue;
-      const int ax = x + 1, ay = D >= 2 ? y + 1 : 0, az = D >= 3 ? z + 1 : 0;
-      const int kq = KB::idx(ax, ay, az);
-      const double kc = sk[kq];
-      double dg = 0, off = 0;
+    const double* X = WHICH == 0 ? p : u;   // operand of the stencil
+    // per-thread tile offsets (-1: not an interior node of this tile)
+    int vo[NT];
+    {
+      BoxIter<TB> it;
 #pragma unroll
-      for (int k = 0; k < 2 * D; ++k) {
-        const double w = kc + sk[kq + nb_off<D, KB>(k)];
-        dg += w;
-        off += w * sx[kq + nb_off<D, KB>(k)];
+      for (int k = 0; k < NT; ++k) {
+        const int jx = jx0 + it.x, jy = jy0 + it.y, jz = jz0 + it.z;
+        vo[k] = (it.ok() && interior<D>(jx, jy, jz, n)) ? vec_off<D>(jx, jy, jz, n) : -1;
+        it.next();
       }
-      const double Ax = dg * sx[kq] - off;
-      const long vi = vec_index<D>(jx, jy, jz, n);
-      const double uc = WHICH == 0 ? u[o + vi] : sx[kq];
-      const double um = s > 0 ? u[o - g.npts + vi] : 0.0;
-      double f = tau * F[o + vi];
-      if (s == 0) f += u0[vi];
-      if (WHICH == 0) {
-        st<TS, double>(r, o + vi, (uc - um) - Ax - f);
-      } else {
-        const double e = f - (uc - um) - Ax;
-        const double w = uc + p[o + vi];
-        const double wn = s + 1 < t.N ? u[o + g.npts + vi] + p[o + g.npts + vi] : 0.0;
-        st<TS, double>(r, o + vi, e - (w - wn));
-        e2 += e * e;
+    }
+    auto load_pts = [&](double (&v)[NT], const double* base) {
+#pragma unroll
+      for (int k = 0; k < NT; ++k) v[k] = vo[k] >= 0 ? base[vo[k]] : 0.0;
+    };
+    double kr[nit<KB>()][RM];
+    load_kraw<D, KB, double, RM>(kr, t.kap, g.nnodes, t.R, n, ox, oy, oz);
+    double xn[nit<KB>()];
+    prefetch_box<D, KB, double, double>(xn, X + long(s0) * g.npts, n, ox, oy, oz);
+    // pointwise values of the current and the next slab
+    double um[NT], uc[NT], un[NT], pc[NT], pn[NT], Fc[NT], Fn[NT];
+    if (s0 > 0) load_pts(um, u + long(s0 - 1) * g.npts);
+    else {
+#pragma unroll
+      for (int k = 0; k < NT; ++k) um[k] = 0.0;
+    }
+    load_pts(uc, u + long(s0) * g.npts);
+    load_pts(Fc, F + long(s0) * g.npts);
+    if (WHICH == 1) load_pts(pc, p + long(s0) * g.npts);
+    for (int s = s0; s < s1; ++s) {
+      const long o = long(s) * g.npts;
+      write_kappa<KB, double, RM>(sk, kr, load_op<double>(nullptr, t.cA, s, t.R));
+      write_box<KB, double>(sx, xn);
+      const bool more = s + 1 < t.N;          // slab s+1 exists
+      if (more) {
+        const long o1 = o + g.npts;
+        if (s + 1 < s1) prefetch_box<D, KB, double, double>(xn, X + o1, n, ox, oy, oz);
+        load_pts(un, u + o1);
+        if (s + 1 < s1) load_pts(Fn, F + o1);
+        if (WHICH == 1) load_pts(pn, p + o1);
+      }
+      __syncthreads();
+      TS* rs = r + o;
+      BoxIter<TB> it;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        if (vo[k] >= 0) {
+          const int kq = KB::idx(it.x + 1, D >= 2 ? it.y + 1 : 0, D >= 3 ? it.z + 1 : 0);
+          const double kc = sk[kq];
+          double dg = 0, off = 0;
+#pragma unroll
+          for (int q = 0; q < 2 * D; ++q) {
+            const double w = kc + sk[kq + nb_off<KB>(q)];
+            dg += w;
+            off += w * sx[kq + nb_off<KB>(q)];
+          }
+          const double Ax = dg * sx[kq] - off;
+          double f = tau * Fc[k];
+          if (s == 0) f += u0[vo[k]];
+          if (WHICH == 0) {
+            st<TS, double>(rs, vo[k], (uc[k] - um[k]) - Ax - f);
+          } else {
+            const double e = f - (uc[k] - um[k]) - Ax;
+            const double wn = more ? un[k] + pn[k] : 0.0;
+            st<TS, double>(rs, vo[k], e - ((uc[k] + pc[k]) - wn));
+            e2 += e * e;
+          }
+        }
+        it.next();
+      }
+      __syncthreads();
+      // march: the current slab becomes the previous one
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        um[k] = uc[k];
+        uc[k] = un[k];
+        Fc[k] = Fn[k];
+        if (WHICH == 1) pc[k] = pn[k];
       }
     }
   }
