@@ -45,18 +45,19 @@ def algorithmic_bytes(kernel: str, level: int, dims, ts: int) -> float | None:
     n_l = npts[level] if level < len(npts) else None
     kap = lambda l, b: R * nn[l] * b  # noqa: E731
     k = kernel.split("<")[0]
+    add64 = "add64" in kernel
     if k == "k_resid_tile":        # u, p, F in; r out (the other slab's u, p rows are the same arrays)
         return N * npts[0] * (3 * 8 + ts) + kap(0, 8)
     if k == "k_mg_down":           # b in (fine), bc out (coarse)
         return N * (n_l + npts[level + 1]) * ts + kap(level, tc)
     if k == "k_mg_up":
-        if "ADD64" in kernel:      # b, e in; float64 p read and written
+        if add64:                  # b, e in; float64 p read and written
             return N * (n_l + npts[level + 1]) * ts + N * n_l * 16 + kap(level, tc)
         return N * (2 * n_l + npts[level + 1]) * ts + kap(level, tc)
     if k == "k_apply_tile":
         return N * n_l * 2 * ts + kap(level, tc)
-    if k == "k_time_fft" or k == "k_time_dense":
-        if "MODE_A6, 1" in kernel or (k == "k_time_dense" and ", 1>" in kernel):
+    if k in ("k_time_fft", "k_time_fft2", "k_time_dense"):   # one step-count group (level = group 0)
+        if add64:                  # in (TS); float64 u read and written
             return N * npts[0] * (ts + 16)
         return N * npts[0] * 2 * ts
     return None

@@ -127,6 +127,41 @@ stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau,
                       const stp_options* opt, void* workspace, size_t ws_bytes,
                       void* hip_stream);
 
+/* Batches.  A batch context holds P >= 1 independent problems of the same
+ * spatial dimension; grids, step counts, tau, kappa rank and data may differ
+ * from problem to problem.  Each step of an iteration is one merged launch per
+ * kernel variant that serves every problem of the batch, so many small solves
+ * fill the GPU together.  The problems are exactly those of stp_create
+ * (Section 2 problem statement), each solved by its own inexact Uzawa iteration
+ * (eq. (3.1)) with its own stop test; a problem that has stopped is skipped by
+ * later launches.
+ *
+ * stp_workspace_bytes_batch: device bytes stp_create_batch needs for P
+ * problems (grids[i], N[i], rank[i]); 0 when an argument is invalid.
+ *
+ * stp_create_batch: arrays of length P, all host arrays; F[i], u0[i] and
+ * kappa[i].fields are device pointers borrowed until stp_destroy, as in
+ * stp_create.  opt applies to every problem; opt->kref_coef must be NULL when
+ * P > 1 (each problem then takes the time mean of its own kappa).  Errors as
+ * stp_create, plus EUNSUPPORTED when the dimensions differ.
+ *
+ * stp_uzawa_solve_batch: u[i], p[i] (device, N[i] x n_i^d float64 each, the
+ * initial guesses) are overwritten as by stp_uzawa_solve; stats (host array of
+ * P, or NULL) receives per-problem results.  Returns the worst status over the
+ * batch (EDIVERGED before ENOTCONV before OK).
+ *
+ * A context made by stp_create is a batch of one; stp_apply_operator and
+ * stp_apply_precond accept only such contexts (EUNSUPPORTED otherwise). */
+size_t stp_workspace_bytes_batch(int P, const stp_grid* grids, const int* N, const int* rank,
+                                 const stp_options* opt);
+stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const int* N,
+                            const double* tau, const stp_kappa* kappa, const double* const* F,
+                            const double* const* u0, const stp_options* opt, void* workspace,
+                            size_t ws_bytes, void* hip_stream);
+stp_status stp_uzawa_solve_batch(stp_ctx* ctx, double* const* u, double* const* p, stp_stats* stats);
+/* Number of problems in the context (0 for NULL). */
+int stp_batch_size(stp_ctx* ctx);
+
 /* y = op x on device buffers (layouts above), float64. */
 stp_status stp_apply_operator(stp_ctx* ctx, int op, const double* x, double* y);
 

@@ -18,17 +18,23 @@ from .binding import (  # noqa: F401
     STP_ENOTCONV,
     STP_EDIVERGED,
     STP_EUNSUPPORTED,
+    BatchSolver,
     SpaceTimeSolver,
     StpError,
     from_problem,
+    problem_dict,
     lib_path,
     load,
     stp_apply_operator,
     stp_apply_precond,
+    stp_batch_size,
     stp_create,
+    stp_create_batch,
     stp_destroy,
     stp_timing_enable,
     stp_timing_report,
     stp_uzawa_solve,
+    stp_uzawa_solve_batch,
     stp_workspace_bytes,
+    stp_workspace_bytes_batch,
 )

@@ -79,6 +79,19 @@ def load() -> C.CDLL:
     lib.stp_status_string.restype = C.c_char_p
     lib.stp_last_error.argtypes = []
     lib.stp_last_error.restype = C.c_char_p
+    lib.stp_workspace_bytes_batch.argtypes = [C.c_int, C.POINTER(stp_grid), C.POINTER(C.c_int),
+                                              C.POINTER(C.c_int), C.POINTER(stp_options)]
+    lib.stp_workspace_bytes_batch.restype = C.c_size_t
+    lib.stp_create_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(stp_grid), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_double), C.POINTER(stp_kappa), C.POINTER(C.c_void_p),
+                                     C.POINTER(C.c_void_p), C.POINTER(stp_options), C.c_void_p, C.c_size_t,
+                                     C.c_void_p]
+    lib.stp_create_batch.restype = C.c_int
+    lib.stp_uzawa_solve_batch.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                          C.POINTER(stp_stats)]
+    lib.stp_uzawa_solve_batch.restype = C.c_int
+    lib.stp_batch_size.argtypes = [C.c_void_p]
+    lib.stp_batch_size.restype = C.c_int
     lib.stp_timing_enable.argtypes = [C.c_void_p, C.c_int]
     lib.stp_timing_enable.restype = C.c_int
     lib.stp_timing_count.argtypes = [C.c_void_p]
@@ -164,6 +177,75 @@ def stp_create(dim, n, N, tau, kfields, tcoef, F, u0, workspace=None, stream=Non
                         ws_ptr, ws_bytes, _stream_ptr(stream))
     _check(st, "stp_create")
     return ctx, (kfields, F, u0, tcoef, keep, workspace)
+
+
+def stp_workspace_bytes_batch(specs, **opts) -> int:
+    """specs: list of (dim, n, N, rank)."""
+    P = len(specs)
+    o, _keep = make_options(**opts)
+    grids = (stp_grid * P)(*[stp_grid(d, n) for d, n, _, _ in specs])
+    Ns = (C.c_int * P)(*[N for _, _, N, _ in specs])
+    rk = (C.c_int * P)(*[r for _, _, _, r in specs])
+    return int(load().stp_workspace_bytes_batch(P, grids, Ns, rk, C.byref(o)))
+
+
+def stp_create_batch(problems, workspace=None, stream=None, **opts):
+    """problems: list of dicts with keys dim, n, N, tau, kfields, tcoef, F, u0 (as in
+    stp_create).  Returns (ctx handle, keepalive tuple)."""
+    lib = load()
+    P = len(problems)
+    if P < 1:
+        raise ValueError("empty batch")
+    grids = (stp_grid * P)()
+    Ns = (C.c_int * P)()
+    taus = (C.c_double * P)()
+    kaps = (stp_kappa * P)()
+    Fs = (C.c_void_p * P)()
+    u0s = (C.c_void_p * P)()
+    keep = []
+    for i, q in enumerate(problems):
+        dim, n, N = q["dim"], q["n"], q["N"]
+        tcoef = np.ascontiguousarray(np.asarray(q["tcoef"], dtype=np.float64))
+        R = tcoef.shape[0]
+        if tcoef.shape != (R, N) or not (1 <= R <= STP_MAX_RANK):
+            raise ValueError(f"problem {i}: tcoef must be (rank, N) with rank <= {STP_MAX_RANK}, got {tcoef.shape}")
+        npts = n ** dim
+        kf, F, u0 = q["kfields"], q["F"], q["u0"]
+        if kf.numel() != R * (n + 2) ** dim or F.numel() != N * npts or u0.numel() != npts:
+            raise ValueError(f"problem {i}: kfields/F/u0 sizes do not match (dim, n, N, rank)")
+        grids[i] = stp_grid(dim, n)
+        Ns[i] = N
+        taus[i] = float(q["tau"])
+        kaps[i] = stp_kappa(R, _dev_f64(kf, (R,) + (n + 2,) * dim, "kfields"),
+                            tcoef.ctypes.data_as(C.POINTER(C.c_double)))
+        Fs[i] = _dev_f64(F, (N,) + (n,) * dim, "F").value
+        u0s[i] = _dev_f64(u0, (n,) * dim, "u0").value
+        keep.append((kf, F, u0, tcoef))
+    o, okeep = make_options(**opts)
+    ctx = C.c_void_p()
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+    st = lib.stp_create_batch(C.byref(ctx), P, grids, Ns, taus, kaps, Fs, u0s, C.byref(o), ws_ptr, ws_bytes,
+                              _stream_ptr(stream))
+    _check(st, "stp_create_batch")
+    return ctx, (keep, okeep, workspace)
+
+
+def stp_uzawa_solve_batch(ctx, us, ps):
+    """Returns (worst status, list of stp_stats)."""
+    P = len(us)
+    if len(ps) != P:
+        raise ValueError("u and p lists differ in length")
+    ua = (C.c_void_p * P)(*[t.data_ptr() for t in us])
+    pa = (C.c_void_p * P)(*[t.data_ptr() for t in ps])
+    sts = (stp_stats * P)()
+    status = load().stp_uzawa_solve_batch(ctx, ua, pa, sts)
+    return status, list(sts)
+
+
+def stp_batch_size(ctx) -> int:
+    return int(load().stp_batch_size(ctx))
 
 
 def stp_apply_operator(ctx, op, x, y):
@@ -271,6 +353,62 @@ class SpaceTimeSolver:
             self.close()
         except Exception:
             pass
+
+
+class BatchSolver:
+    """Many independent problems of one spatial dimension in one context: every
+    step of an iteration is a merged launch over the whole batch."""
+
+    def __init__(self, problems, stream=None, workspace=None, **opts):
+        import torch
+        self.shapes = [(q["N"],) + (q["n"],) * q["dim"] for q in problems]
+        self.device = problems[0]["F"].device
+        with torch.cuda.device(self.device):
+            self.ctx, self._keep = stp_create_batch(problems, workspace=workspace, stream=stream, **opts)
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def solve(self, us=None, ps=None):
+        """Solve every problem from (us[i], ps[i]) (zeros if None).  Returns (us, ps, infos, status)."""
+        import torch
+        z = lambda sh: torch.zeros(sh, dtype=torch.float64, device=self.device)  # noqa: E731
+        us = [z(sh) for sh in self.shapes] if us is None else list(us)
+        ps = [z(sh) for sh in self.shapes] if ps is None else list(ps)
+        for i, sh in enumerate(self.shapes):
+            _dev_f64(us[i], sh, f"u[{i}]")
+            _dev_f64(ps[i], sh, f"p[{i}]")
+        status, sts = stp_uzawa_solve_batch(self.ctx, us, ps)
+        if status not in (STP_OK, STP_ENOTCONV, STP_EDIVERGED):
+            _check(status, "stp_uzawa_solve_batch")
+        infos = [dict(status=s.status, iters=s.iters, rel_res=s.rel_res, omega=s.omega_used, ms=s.t_solve_ms)
+                 for s in sts]
+        return us, ps, infos, status
+
+    def timing(self, enable=True):
+        stp_timing_enable(self.ctx, enable)
+
+    def timing_report(self):
+        return stp_timing_report(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            stp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def problem_dict(prob, device="cuda"):
+    """Device copy of a ``synth.Problem`` in the form stp_create_batch takes."""
+    import torch
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)  # noqa: E731
+    return dict(dim=prob.dim, n=prob.n, N=prob.N, tau=prob.tau, kfields=t(prob.kfields), tcoef=prob.tcoef,
+                F=t(prob.F), u0=t(prob.u0))
 
 
 def from_problem(prob, device="cuda", **opts):

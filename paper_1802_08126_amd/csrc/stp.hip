@@ -1,5 +1,11 @@
 // Host side of the space-time Uzawa solver: problem setup, multigrid
-// hierarchy, workspace planning, the iteration driver and the C ABI of stp.h.
+// hierarchy, workspace planning, merged (batched) launch tables, the
+// iteration driver with HIP-graph replay, and the C ABI of stp.h.
+//
+// A context holds a batch of P >= 1 independent problems of one spatial
+// dimension.  Every step of an Uzawa iteration is one merged launch per
+// kernel instantiation ("site") that serves all problems at once; a site is a
+// table of jobs, one per problem, that the kernels search by block index.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -9,6 +15,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "stp.h"
@@ -52,7 +59,7 @@ static stp_status fail(stp_status s, const char* fmt, ...) {
   } while (0)
 
 // ---------------------------------------------------------------------------
-// context
+// problem, sites, context
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -60,14 +67,15 @@ struct Level {
   int n;
   double h;
   Geom g;
-  double* kraw;      // unscaled nodal fields (float64), R x nnodes
-  void* kscaled;     // TC fields scaled by 0.5/h^2
-  void *b, *x, *t, *e;  // TS work vectors (levels >= 1); x, t also on level 0
+  double* kraw;    // unscaled nodal fields (float64), R x nnodes (level 0: the caller's)
+  void* kscaled;   // TC fields scaled by 0.5/h^2
+  void* b;         // TS right-hand side of the level (levels >= 1)
+  void* e;         // TS correction produced on the level (levels >= 1)
 };
 
 struct Bump {
   char* base = nullptr;
-  size_t off = 0, cap = 0;
+  size_t off = 0;
   bool dry = true;
   void* take(size_t bytes) {
     off = (off + 255) & ~size_t(255);
@@ -93,7 +101,97 @@ dim3 grid_pts(long npts, int S) {
   return dim3(unsigned(bx), unsigned(gy), unsigned(gz));
 }
 
-struct SolverBase;
+enum { TP_FFT2 = 0, TP_STOCKHAM = 1, TP_DENSE = 2 };
+
+// Transform path for N: two-step register FFT (4 <= N <= 256, power of two),
+// Stockham LDS FFT (other powers of two up to 4096), dense otherwise.
+void transform_path(int N, size_t tcb, int& path, int& C, size_t& lds) {
+  C = 0;
+  lds = 0;
+  const bool pow2 = N >= 1 && (N & (N - 1)) == 0;
+  if (pow2 && N >= 4 && N <= 256) {
+    path = TP_FFT2;
+    return;
+  }
+  if (pow2 && N <= 4096) {
+    C = std::max(1, std::min(16, 4096 / N));
+    lds = (size_t(2) * N * C + size_t(4) * N) * tcb;
+    if (lds <= 160 * 1024) {
+      path = TP_STOCKHAM;
+      return;
+    }
+  }
+  C = 0;
+  lds = 0;
+  path = TP_DENSE;
+}
+
+struct Problem {
+  int dim = 0, n = 0, N = 0, R = 0;
+  double tau = 0;
+  const double* F = nullptr;
+  const double* u0 = nullptr;
+  const double* fields = nullptr;
+  std::vector<double> tcoef;   // R x N
+  std::vector<double> abar;    // R
+  std::vector<Level> lv;
+  Geom g0{};
+  int tpath = TP_DENSE;
+  int fft_cols = 0;
+  size_t fft_lds = 0;
+  long resid_tiles = 0;
+  int sb_resid = 1;
+  long npart = 0;               // residual partials (one per residual block)
+  long nfnorm = 0;              // partials of the setup reduction of ||f||
+  // device memory
+  DevState* state = nullptr;
+  double* partial = nullptr;
+  double* kap64 = nullptr;      // finest-level scaled fields, float64
+  double* cA64 = nullptr;       // N x kMaxRank: tau * tcoef
+  void* cA = nullptr;           // TC, N x kMaxRank
+  void* sigH = nullptr;         // TC, N: mu_k
+  void* cH = nullptr;           // TC, N x kMaxRank: tau * abar
+  void* cMid = nullptr;         // TC, kMaxRank: (2/N) tau abar
+  void* sinT = nullptr;         // TC, N x N (dense path)
+  void* sinM = nullptr;
+  void* tw = nullptr;           // TC, 2N
+  void* tw4 = nullptr;          // TC, 2N
+  void* W1 = nullptr;           // TS, N x n^d
+  void* W2 = nullptr;
+  void* tri = nullptr;          // TC scratch of exact 1-D solves, 2 x N x n
+  double fnorm = 0;
+};
+
+template <typename J>
+struct Site {
+  std::vector<J> jobs;
+  J* dev = nullptr;
+  long blocks = 0;
+  int key = 0;     // transform sites: N (-1: dense)
+  int epi = 0;
+  void add(J j, long nb) {
+    j.block0 = blocks;
+    blocks += nb;
+    jobs.push_back(j);
+  }
+};
+
+struct VCycle {
+  std::vector<Site<TileJob>> down, up;   // by level l = 0 .. Lmax-2
+  std::vector<Site<PointJob>> coarse;    // by coarsest level index 0 .. Lmax-1
+  Site<PointJob> tri;                    // exact 1-D solves
+};
+
+enum { VC_A = 0, VC_H1 = 1, VC_H2 = 2 };
+
+struct Sites {
+  Site<ResidJob> resid[2];
+  VCycle vc[3];
+  Site<TileJob> mid;
+  std::vector<Site<TimeJob>> a4, a6;
+  std::vector<FinJob> fin;
+  FinJob* fin_dev = nullptr;
+};
 
 // Optional per-launch device timing (HIP events on the context's stream).
 struct KTimer {
@@ -127,68 +225,27 @@ struct KTimer {
   }
 };
 
-// Columns per block and LDS bytes of the FFT time transform (C = 0: use the dense path).
-void fft_layout(int N, size_t tcb, int& C, size_t& lds) {
-  C = 0;
-  lds = 0;
-  if (N < 1 || (N & (N - 1)) != 0 || N > 4096) return;
-  C = std::max(1, std::min(16, 4096 / N));
-  lds = (size_t(2) * N * C + size_t(4) * N) * tcb;
-  if (lds > 160 * 1024) {
-    C = 0;
-    lds = 0;
-  }
-}
+struct SolverBase;
 
 }  // namespace
 
 struct stp_ctx {
-  int dim = 0, n = 0, N = 0, R = 0;
-  double tau = 0;
+  int P = 0, dim = 0, prec = 0, spatial = STP_SPATIAL_MG, rm = 1;
   stp_options opt{};
-  int spatial = STP_SPATIAL_MG;
   double omega = 0.8;
   hipStream_t stream = nullptr;
-  const double* F = nullptr;
-  const double* u0 = nullptr;
-  const double* fields = nullptr;
-  std::vector<double> tcoef;   // R x N
-  std::vector<double> abar;    // R
-  std::vector<Level> lv;
-  Geom g0{};
-  // device memory
+  std::vector<Problem> pr;
   void* ws = nullptr;
   bool own_ws = false;
-  DevState* state = nullptr;
-  DevState* state_host = nullptr;  // pinned
-  double* partial = nullptr;
-  long npartial = 0;               // capacity of the partial-sum buffer
-  long npart_resid = 0;            // partials written by the residual kernel (tile grid)
-  long npart_points = 0;           // partials written by point-grid reductions
-  int sb_resid = 1;                // slabs per block of the residual kernels
-  double* kap64 = nullptr;         // fine scaled fields, float64
-  double* cA64 = nullptr;          // N x kMaxRank, tau*tcoef
-  void* cA = nullptr;              // TC, N x kMaxRank
-  void* sigH = nullptr;            // TC, N
-  void* cH = nullptr;              // TC, N x kMaxRank
-  void* cMid = nullptr;            // TC, kMaxRank
-  void* sinT = nullptr;            // TC, N x N: sinT[k][n] = sin((2k+1)(n+1)pi/2N)  (Phi^{-T})
-  void* sinM = nullptr;            // TC, N x N: sinM[n][k] = same value            (Phi^{-1})
-  void* tw = nullptr;              // TC, 2N: exp(-2 pi i m / N)   (re block, im block)
-  void* tw4 = nullptr;             // TC, 2N: exp(-i pi m / (2N))
-  int fft_cols = 0;                // columns per block of the FFT path (0: dense path)
-  size_t fft_lds = 0;
-  void *W1 = nullptr, *W2 = nullptr;
-  void* tri = nullptr;             // TC scratch for exact 1-D solves, 2 x N x n
-  double fnorm = 0;
+  size_t tables_off = 0;
+  size_t tables_bytes = 0;
+  DevState* state_host = nullptr;   // pinned, P entries
+  Sites sites;
   SolverBase* impl = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   KTimer kt;
-  // one Uzawa iteration captured as a HIP graph (valid for the (u, p) it was captured with)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
-  double* g_u = nullptr;
-  double* g_p = nullptr;
 };
 
 static inline void kt_begin(stp_ctx* c, const char* name) {
@@ -212,27 +269,397 @@ static inline void kt_end(stp_ctx* c) {
 }
 
 // Every kernel launch goes through KLAUNCH (optional timing) and LAUNCH_CHECK.
-#define KLAUNCH(kern, ...)                 \
-  do {                                     \
-    kt_begin(&*c, #kern);                  \
-    hipLaunchKernelGGL(kern, __VA_ARGS__); \
-  } while (0)
 #define KLAUNCH_NAMED(name, kern, ...)     \
   do {                                     \
     kt_begin(&*c, name);                   \
     hipLaunchKernelGGL(kern, __VA_ARGS__); \
   } while (0)
+#define KLAUNCH(kern, ...) KLAUNCH_NAMED(#kern, kern, __VA_ARGS__)
 
 namespace {
 
+// slabs per block for a launch over `tiles` tiles and S slabs: enough blocks
+// to fill the chip several times over, otherwise runs of up to 16 slabs
+int pick_sb(long tiles, int S) {
+  long sb = (tiles * S) / 2048;
+  return int(std::max(1L, std::min(16L, sb)));
+}
+
+long tiles_down_d(int dim, int nc) {
+  return dim == 1 ? tiles_for<1, DownTile<1>>(nc) : dim == 2 ? tiles_for<2, DownTile<2>>(nc)
+                                                             : tiles_for<3, DownTile<3>>(nc);
+}
+long tiles_up_d(int dim, int n) {
+  return dim == 1 ? tiles_for<1, UpTile<1>>(n) : dim == 2 ? tiles_for<2, UpTile<2>>(n) : tiles_for<3, UpTile<3>>(n);
+}
+
+LevelOp family_op(const Problem& q, int l, int fam) {
+  LevelOp L;
+  L.kap = q.lv[l].kscaled;
+  L.R = q.R;
+  L.S = q.N;
+  L.uniform = 0;
+  if (fam == 0) {          // A family: tau_n A_n
+    L.sig = nullptr;
+    L.c = q.cA;
+  } else if (fam == 1) {   // H family: mu_k I + tau A_ref
+    L.sig = q.sigH;
+    L.c = q.cH;
+  } else {                 // middle: (2/N) tau A_ref
+    L.sig = nullptr;
+    L.c = q.cMid;
+    L.uniform = 1;
+  }
+  return L;
+}
+
+// Plan (dry run) or carve (real run) one problem's buffers.
+void plan_problem(int prec, int spatial, Problem& q, Bump& bp) {
+  const size_t tsb = ts_bytes(prec), tcb = tc_bytes(prec);
+  const long N = q.N;
+  transform_path(q.N, tcb, q.tpath, q.fft_cols, q.fft_lds);
+  q.resid_tiles = tiles_up_d(q.dim, q.n);
+  q.sb_resid = pick_sb(q.resid_tiles, q.N);
+  q.npart = q.resid_tiles * ((q.N + q.sb_resid - 1) / q.sb_resid);
+  const dim3 gp = grid_pts(q.g0.npts, q.N);
+  q.nfnorm = long(gp.x) * gp.y * gp.z;
+  q.state = (DevState*)bp.take(sizeof(DevState));
+  q.partial = (double*)bp.take(size_t(std::max(q.npart, q.nfnorm)) * 8);
+  q.kap64 = (double*)bp.take(size_t(q.R) * q.g0.nnodes * 8);
+  q.cA64 = (double*)bp.take(size_t(N) * kMaxRank * 8);
+  q.cA = bp.take(size_t(N) * kMaxRank * tcb);
+  q.cH = bp.take(size_t(N) * kMaxRank * tcb);
+  q.sigH = bp.take(size_t(N) * tcb);
+  q.cMid = bp.take(size_t(kMaxRank) * tcb);
+  q.tw = q.tw4 = q.sinT = q.sinM = nullptr;
+  if (q.tpath == TP_DENSE) {
+    q.sinT = bp.take(size_t(N) * N * tcb);
+    q.sinM = bp.take(size_t(N) * N * tcb);
+  } else {
+    q.tw = bp.take(size_t(2) * N * tcb);
+    q.tw4 = bp.take(size_t(2) * N * tcb);
+  }
+  q.W1 = bp.take(size_t(N) * q.g0.npts * tsb);
+  q.W2 = bp.take(size_t(N) * q.g0.npts * tsb);
+  q.tri = (spatial == STP_SPATIAL_EXACT) ? bp.take(size_t(2) * N * q.n * tcb) : nullptr;
+  for (size_t l = 0; l < q.lv.size(); ++l) {
+    Level& L = q.lv[l];
+    L.kraw = (l == 0) ? const_cast<double*>(q.fields) : (double*)bp.take(size_t(q.R) * L.g.nnodes * 8);
+    L.kscaled = bp.take(size_t(q.R) * L.g.nnodes * tcb);
+    const size_t vb = size_t(N) * L.g.npts * tsb;
+    L.b = (l == 0) ? nullptr : bp.take(vb);
+    L.e = (l == 0) ? nullptr : bp.take(vb);
+  }
+}
+
+stp_status build_levels(int spatial, Problem& q) {
+  q.lv.clear();
+  int n = q.n;
+  while (true) {
+    Level L{};
+    L.n = n;
+    L.h = 1.0 / (n + 1);
+    L.g.n = n;
+    L.g.npts = ipow(n, q.dim);
+    L.g.nnodes = ipow(n + 2, q.dim);
+    q.lv.push_back(L);
+    if (spatial == STP_SPATIAL_EXACT || spatial == STP_SPATIAL_NONE || n == 1) break;
+    if (n % 2 == 0) return fail(STP_EUNSUPPORTED, "multigrid needs n = 2^L - 1 interior nodes per axis (got %d)", q.n);
+    n = (n - 1) / 2;
+    if (int(q.lv.size()) >= STP_MAX_LEVELS) return fail(STP_EUNSUPPORTED, "too many multigrid levels");
+  }
+  q.g0 = q.lv[0].g;
+  return STP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sites of the iteration (merged launches over the batch)
+// ---------------------------------------------------------------------------
+// top-level input / output of a V-cycle instance for one problem
+struct VTop {
+  const void* in;
+  void* out;       // TS output (or null)
+  double* acc64;   // float64 accumulation target (or null)
+};
+
+void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top) {
+  int Lmax = 0;
+  for (auto& q : c->pr) Lmax = std::max(Lmax, int(q.lv.size()));
+  vc.down.assign(std::max(0, Lmax - 1), Site<TileJob>());
+  vc.up.assign(std::max(0, Lmax - 1), Site<TileJob>());
+  vc.coarse.assign(Lmax, Site<PointJob>());
+  vc.tri = Site<PointJob>();
+  for (size_t i = 0; i < c->pr.size(); ++i) {
+    Problem& q = c->pr[i];
+    const VTop& T = top[i];
+    const bool acc = fam == 0;   // the A-tilde cycle adds into p; the H cycles store
+    if (c->spatial == STP_SPATIAL_EXACT) {
+      PointJob j{};
+      j.total = q.N;
+      j.g = q.lv[0].g;
+      j.op = family_op(q, 0, fam);
+      j.b = T.in;
+      j.out = T.out;
+      j.acc64 = T.acc64;
+      j.scratch = q.tri;
+      j.state = &q.state->done;
+      vc.tri.add(j, (q.N + 63) / 64);
+      vc.tri.epi = acc ? EPI_ADD64 : EPI_STORE;
+      continue;
+    }
+    const int Lq = int(q.lv.size());
+    for (int l = 0; l + 1 < Lq; ++l) {
+      TileJob d{};
+      d.gf = q.lv[l].g;
+      d.gc = q.lv[l + 1].g;
+      d.op = family_op(q, l, fam);
+      d.b = (l == 0) ? T.in : q.lv[l].b;
+      d.out = q.lv[l + 1].b;
+      d.state = &q.state->done;
+      d.tiles = int(tiles_down_d(q.dim, q.lv[l + 1].n));
+      d.sb = pick_sb(d.tiles, q.N);
+      vc.down[l].add(d, long(d.tiles) * ((q.N + d.sb - 1) / d.sb));
+      TileJob u{};
+      u.gf = q.lv[l].g;
+      u.gc = q.lv[l + 1].g;
+      u.op = d.op;
+      u.b = d.b;
+      u.e = q.lv[l + 1].e;
+      u.out = (l == 0) ? T.out : q.lv[l].e;
+      u.acc64 = (l == 0) ? T.acc64 : nullptr;
+      u.state = d.state;
+      u.tiles = int(tiles_up_d(q.dim, q.lv[l].n));
+      u.sb = pick_sb(u.tiles, q.N);
+      vc.up[l].add(u, long(u.tiles) * ((q.N + u.sb - 1) / u.sb));
+      vc.up[l].epi = (l == 0 && acc) ? EPI_ADD64 : EPI_STORE;
+    }
+    const int cl = Lq - 1;
+    PointJob pj{};
+    pj.g = q.lv[cl].g;
+    pj.total = long(q.N) * pj.g.npts;
+    pj.op = family_op(q, cl, fam);
+    pj.b = (cl == 0) ? T.in : q.lv[cl].b;
+    pj.out = (cl == 0) ? T.out : q.lv[cl].e;
+    pj.acc64 = (cl == 0) ? T.acc64 : nullptr;
+    pj.state = &q.state->done;
+    vc.coarse[cl].add(pj, (pj.total + kBlock - 1) / kBlock);
+    vc.coarse[cl].epi = (cl == 0 && acc) ? EPI_ADD64 : EPI_STORE;
+  }
+}
+
+int fft2_l1(int N) {
+  int L1 = 0;
+  while ((1 << (2 * L1)) < N) ++L1;   // N1 = 2^ceil(log2(N)/2)
+  return L1;
+}
+
+void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, const std::vector<const void*>& in,
+                      const std::vector<void*>& out, const std::vector<double*>& acc64, double alpha) {
+  sites.clear();
+  for (size_t i = 0; i < c->pr.size(); ++i) {
+    Problem& q = c->pr[i];
+    // sites are keyed by N for the FFT paths and share one dense site
+    const int key = q.tpath == TP_DENSE ? -1 : q.N;
+    Site<TimeJob>* s = nullptr;
+    for (auto& t : sites)
+      if (t.key == key) s = &t;
+    if (!s) {
+      sites.emplace_back();
+      s = &sites.back();
+      s->key = key;
+      s->epi = (mode == 1) ? 1 : 0;
+    }
+    TimeJob j{};
+    j.npts = q.g0.npts;
+    j.N = q.N;
+    j.tw = q.tw;
+    j.tw4 = q.tw4;
+    j.T = mode == 0 ? q.sinT : q.sinM;
+    j.in = in[i];
+    j.out = out[i];
+    j.acc64 = acc64[i];
+    j.alpha = alpha;
+    j.state = &q.state->done;
+    long nb;
+    if (q.tpath == TP_FFT2) {
+      const int Cc = kBlock >> fft2_l1(q.N);
+      nb = (j.npts + Cc - 1) / Cc;
+    } else if (q.tpath == TP_STOCKHAM) {
+      nb = (j.npts + q.fft_cols - 1) / q.fft_cols;
+    } else {
+      j.bx = int((j.npts + 63) / 64);
+      nb = long(j.bx) * ((q.N + 4 * kDstKpt - 1) / (4 * kDstKpt));
+    }
+    s->add(j, nb);
+  }
+}
+
+void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<double*>& p) {
+  Sites& S = c->sites;
+  const size_t P = c->pr.size();
+  for (int w = 0; w < 2; ++w) {
+    S.resid[w] = Site<ResidJob>();
+    for (size_t i = 0; i < P; ++i) {
+      Problem& q = c->pr[i];
+      ResidJob j{};
+      j.tiles = int(q.resid_tiles);
+      j.sb = q.sb_resid;
+      j.g = q.g0;
+      j.t = TimeOp{q.kap64, q.cA64, q.R, q.N};
+      j.tau = q.tau;
+      j.u = u[i];
+      j.p = p[i];
+      j.F = q.F;
+      j.u0 = q.u0;
+      j.r = q.W1;
+      j.partial = q.partial;
+      j.state = &q.state->done;
+      S.resid[w].add(j, q.npart);
+    }
+  }
+  std::vector<VTop> topA(P), topH(P);
+  std::vector<const void*> in4(P), in6(P);
+  std::vector<void*> out4(P), out6(P, nullptr);
+  std::vector<double*> acc4(P, nullptr), acc6(P);
+  for (size_t i = 0; i < P; ++i) {
+    Problem& q = c->pr[i];
+    topA[i] = VTop{q.W1, nullptr, p[i]};       // p += A~^{-1} r_p
+    topH[i] = VTop{q.W2, q.W1, nullptr};       // x = H~_k^{-1} rhat,  yhat = H~_k^{-1} y   (W2 -> W1)
+    in4[i] = q.W1;                             // rhat = Phi^{-T} r_u   (W1 -> W2)
+    out4[i] = q.W2;
+    in6[i] = q.W1;                             // u += omega Phi^{-1} yhat
+    acc6[i] = u[i];
+  }
+  build_vcycle(c, S.vc[VC_A], 0, topA);
+  build_vcycle(c, S.vc[VC_H1], 1, topH);
+  build_vcycle(c, S.vc[VC_H2], 1, topH);
+  S.mid = Site<TileJob>();
+  for (size_t i = 0; i < P; ++i) {
+    Problem& q = c->pr[i];
+    TileJob j{};
+    j.gf = q.g0;
+    j.op = family_op(q, 0, 2);
+    j.b = q.W1;                                // y = (2/N) tau A x   (W1 -> W2)
+    j.out = q.W2;
+    j.state = &q.state->done;
+    j.tiles = int(tiles_up_d(q.dim, q.n));
+    j.sb = pick_sb(j.tiles, q.N);
+    S.mid.add(j, long(j.tiles) * ((q.N + j.sb - 1) / j.sb));
+  }
+  build_transforms(c, S.a4, 0, in4, out4, acc4, 1.0);
+  build_transforms(c, S.a6, 1, in6, out6, acc6, c->omega);
+  S.fin.clear();
+  for (size_t i = 0; i < P; ++i) {
+    Problem& q = c->pr[i];
+    S.fin.push_back(FinJob{q.partial, q.npart, q.state, c->opt.tol, c->opt.max_iter});
+  }
+}
+
+template <typename J>
+size_t site_bytes(const Site<J>& s) {
+  return ((s.jobs.size() * sizeof(J)) + 255) & ~size_t(255);
+}
+
+template <typename F>
+void for_each_site(Sites& S, F&& f) {
+  f(S.resid[0]);
+  f(S.resid[1]);
+  for (auto& v : S.vc) {
+    for (auto& x : v.down) f(x);
+    for (auto& x : v.up) f(x);
+    for (auto& x : v.coarse) f(x);
+    f(v.tri);
+  }
+  f(S.mid);
+  for (auto& x : S.a4) f(x);
+  for (auto& x : S.a6) f(x);
+}
+
+size_t tables_bytes(Sites& S) {
+  size_t b = 0;
+  for_each_site(S, [&](auto& s) { b += site_bytes(s); });
+  b += ((S.fin.size() * sizeof(FinJob)) + 255) & ~size_t(255);
+  return b;
+}
+
+void carve_tables(Sites& S, char* base) {
+  size_t off = 0;
+  for_each_site(S, [&](auto& s) {
+    using J = typename std::decay<decltype(s.jobs[0])>::type;
+    s.dev = s.jobs.empty() ? nullptr : reinterpret_cast<J*>(base + off);
+    off += site_bytes(s);
+  });
+  S.fin_dev = reinterpret_cast<FinJob*>(base + off);
+}
+
+template <typename J>
+stp_status upload_site(stp_ctx* c, Site<J>& s) {
+  if (s.jobs.empty()) return STP_OK;
+  HIP_TRY(hipMemcpyAsync(s.dev, s.jobs.data(), s.jobs.size() * sizeof(J), hipMemcpyHostToDevice, c->stream));
+  return STP_OK;
+}
+
+stp_status upload_all(stp_ctx* c) {
+  stp_status st = STP_OK;
+  for_each_site(c->sites, [&](auto& s) {
+    if (st == STP_OK) st = upload_site(c, s);
+  });
+  if (st != STP_OK) return st;
+  HIP_TRY(hipMemcpyAsync(c->sites.fin_dev, c->sites.fin.data(), c->sites.fin.size() * sizeof(FinJob),
+                         hipMemcpyHostToDevice, c->stream));
+  return STP_OK;
+}
+
+// Point the per-solve jobs at the caller's u and p (and the transform of
+// Phi^{-1} at accumulation target acc with factor alpha); tables are
+// uploaded on the context's stream.
+stp_status bind_solution(stp_ctx* c, const std::vector<double*>& u, const std::vector<double*>& p,
+                         const std::vector<double*>& acc, double alpha) {
+  Sites& S = c->sites;
+  const size_t P = c->pr.size();
+  auto owner = [&](const int* st) -> size_t {
+    for (size_t i = 0; i < P; ++i)
+      if (st == &c->pr[i].state->done) return i;
+    return 0;
+  };
+  for (int w = 0; w < 2; ++w)
+    for (auto& j : S.resid[w].jobs) {
+      const size_t i = owner(j.state);
+      j.u = u[i];
+      j.p = p[i];
+    }
+  VCycle& A = S.vc[VC_A];
+  if (!A.up.empty())
+    for (auto& j : A.up[0].jobs) j.acc64 = p[owner(j.state)];
+  if (!A.coarse.empty())
+    for (auto& j : A.coarse[0].jobs) j.acc64 = p[owner(j.state)];
+  for (auto& j : A.tri.jobs) j.acc64 = p[owner(j.state)];
+  for (auto& s : S.a6)
+    for (auto& j : s.jobs) {
+      j.acc64 = acc[owner(j.state)];
+      j.alpha = alpha;
+    }
+  stp_status st;
+  if ((st = upload_site(c, S.resid[0])) != STP_OK) return st;
+  if ((st = upload_site(c, S.resid[1])) != STP_OK) return st;
+  if (!A.up.empty() && (st = upload_site(c, A.up[0])) != STP_OK) return st;
+  if (!A.coarse.empty() && (st = upload_site(c, A.coarse[0])) != STP_OK) return st;
+  if ((st = upload_site(c, A.tri)) != STP_OK) return st;
+  for (auto& s : S.a6)
+    if ((st = upload_site(c, s)) != STP_OK) return st;
+  return STP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// typed execution
+// ---------------------------------------------------------------------------
 struct SolverBase {
   virtual ~SolverBase() {}
-  virtual stp_status precA(const void* b, double* acc64, void* out) = 0;
-  virtual stp_status precH(void* W1, void* W2, double* acc64, void* out, double alpha) = 0;
-  virtual stp_status iteration(double* u, double* p) = 0;
-  virtual stp_status setup_tables() = 0;
+  virtual stp_status setup_problem(Problem& q) = 0;
+  virtual stp_status iteration() = 0;
+  virtual stp_status run_vcycle(int which) = 0;
+  virtual stp_status run_precH() = 0;
   virtual stp_status cast_in(const double* a, void* b, long n) = 0;
-  virtual stp_status cast_out(const void* a, double* b, long n) = 0;
 };
 
 template <typename TS, typename TC>
@@ -242,322 +669,253 @@ struct Solver : SolverBase {
 
   TC omegaJ() const { return c->dim == 1 ? TC(2.0 / 3.0) : (c->dim == 2 ? TC(4.0 / 5.0) : TC(6.0 / 7.0)); }
 
-  LevelOp fam(int l, int which) const {
-    LevelOp L;
-    L.kap = c->lv[l].kscaled;
-    L.R = c->R;
-    L.S = c->N;
-    L.uniform = 0;
-    if (which == 0) {          // A family: tau_n A_n
-      L.sig = nullptr;
-      L.c = c->cA;
-    } else if (which == 1) {   // H family: mu_k I + tau A_ref
-      L.sig = c->sigH;
-      L.c = c->cH;
-    } else {                   // middle: (2/N) tau A_ref
-      L.sig = nullptr;
-      L.c = c->cMid;
-      L.uniform = 1;
-    }
-    return L;
-  }
-
-  const int* st() const { return &c->state->done; }
-
-  // slabs per block for a launch over `tiles` tiles and S slabs: enough blocks
-  // to fill the chip several times over, otherwise runs of up to 16 slabs
-  static int pick_sb(long tiles, int S) {
-    long sb = (tiles * S) / 2048;
-    return int(std::max(1L, std::min(16L, sb)));
-  }
-  static dim3 grid_runs(long tiles, int S, int sb) {
-    const long runs = (S + sb - 1) / sb;
-    const long gy = std::min(runs, 65535L);
-    const long gz = (runs + 65534) / 65535;
-    return dim3(unsigned(tiles), unsigned(gy), unsigned(gz));
-  }
-  int rm() const { return c->R <= 1 ? 1 : (c->R <= 2 ? 2 : 4); }
-
   template <int D>
-  stp_status vcycle_d(int l, int which, const TS* b, TS* out, double* acc64) {
-    c->kt.level = l;
-    Level& L = c->lv[l];
-    const LevelOp op = fam(l, which);
-    const int last = int(c->lv.size()) - 1;
-    const int gy = std::min(c->N, 65535), gz = (c->N + 65534) / 65535;
-    if (l == last) {
-      // single-node level: x = b / D
-      const long tot = long(c->N) * L.g.npts;
-      const dim3 gr(unsigned((tot + kBlock - 1) / kBlock));
-      if (acc64) {
-        TS* tmp = (TS*)L.t;
-        KLAUNCH((k_coarsest<D, TS, TC>), gr, dim3(kBlock), 0, c->stream, L.g, op, b, tmp, st());
+  stp_status coarse_site(Site<PointJob>& s, int level) {
+    c->kt.level = level;
+    if (s.epi == EPI_ADD64)
+      KLAUNCH_NAMED("k_coarsest<add64>", (k_coarsest<D, TS, TC, EPI_ADD64>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
+                    c->stream, s.dev, int(s.jobs.size()));
+    else
+      KLAUNCH_NAMED("k_coarsest<store>", (k_coarsest<D, TS, TC, EPI_STORE>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
+                    c->stream, s.dev, int(s.jobs.size()));
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
+  template <int D, int RM>
+  stp_status vcycle_dr(VCycle& vc) {
+    const int nl = int(vc.down.size());
+    stp_status st;
+    if (!vc.coarse.empty() && !vc.coarse[0].jobs.empty())   // single-node problems
+      if ((st = coarse_site<D>(vc.coarse[0], 0)) != STP_OK) return st;
+    for (int l = 0; l < nl; ++l) {
+      c->kt.level = l;
+      Site<TileJob>& s = vc.down[l];
+      if (!s.jobs.empty()) {
+        KLAUNCH_NAMED("k_mg_down", (k_mg_down<D, TS, TC, RM>), dim3(unsigned(s.blocks)), dim3(kBlock), 0, c->stream,
+                      s.dev, int(s.jobs.size()), omegaJ());
         LAUNCH_CHECK();
-        KLAUNCH((k_cast_add64<TS>), gr, dim3(kBlock), 0, c->stream, tot, (const TS*)tmp, acc64, st());
-      } else {
-        KLAUNCH((k_coarsest<D, TS, TC>), gr, dim3(kBlock), 0, c->stream, L.g, op, b, out, st());
       }
+      if (!vc.coarse[l + 1].jobs.empty())
+        if ((st = coarse_site<D>(vc.coarse[l + 1], l + 1)) != STP_OK) return st;
+    }
+    for (int l = nl - 1; l >= 0; --l) {
+      c->kt.level = l;
+      Site<TileJob>& s = vc.up[l];
+      if (s.jobs.empty()) continue;
+      if (s.epi == EPI_ADD64)
+        KLAUNCH_NAMED("k_mg_up<add64>", (k_mg_up<D, TS, TC, RM, EPI_ADD64>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
+                      c->stream, s.dev, int(s.jobs.size()), omegaJ());
+      else
+        KLAUNCH_NAMED("k_mg_up<store>", (k_mg_up<D, TS, TC, RM, EPI_STORE>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
+                      c->stream, s.dev, int(s.jobs.size()), omegaJ());
+      LAUNCH_CHECK();
+    }
+    return STP_OK;
+  }
+
+  stp_status run_vcycle(int which) override {
+    VCycle& vc = c->sites.vc[which];
+    if (c->spatial == STP_SPATIAL_EXACT) {
+      Site<PointJob>& s = vc.tri;
+      c->kt.level = 0;
+      if (s.epi == EPI_ADD64)
+        KLAUNCH_NAMED("k_tridiag<add64>", (k_tridiag<TS, TC, EPI_ADD64>), dim3(unsigned(s.blocks)), dim3(64), 0,
+                      c->stream, s.dev, int(s.jobs.size()));
+      else
+        KLAUNCH_NAMED("k_tridiag<store>", (k_tridiag<TS, TC, EPI_STORE>), dim3(unsigned(s.blocks)), dim3(64), 0,
+                      c->stream, s.dev, int(s.jobs.size()));
       LAUNCH_CHECK();
       return STP_OK;
     }
-    Level& C = c->lv[l + 1];
-    switch (rm()) {
-      case 1: return vcycle_rm<D, 1>(l, which, op, L, C, b, out, acc64);
-      case 2: return vcycle_rm<D, 2>(l, which, op, L, C, b, out, acc64);
-      default: return vcycle_rm<D, 4>(l, which, op, L, C, b, out, acc64);
+    switch (c->dim * 10 + c->rm) {
+      case 11: return vcycle_dr<1, 1>(vc);
+      case 12: return vcycle_dr<1, 2>(vc);
+      case 14: return vcycle_dr<1, 4>(vc);
+      case 21: return vcycle_dr<2, 1>(vc);
+      case 22: return vcycle_dr<2, 2>(vc);
+      case 24: return vcycle_dr<2, 4>(vc);
+      case 31: return vcycle_dr<3, 1>(vc);
+      case 32: return vcycle_dr<3, 2>(vc);
+      default: return vcycle_dr<3, 4>(vc);
     }
   }
 
   template <int D, int RM>
-  stp_status vcycle_rm(int l, int which, const LevelOp& op, Level& L, Level& C, const TS* b, TS* out, double* acc64) {
-    const long td = tiles_for<D, DownTile<D>>(C.n);
-    const int sbd = pick_sb(td, c->N);
-    KLAUNCH((k_mg_down<D, TS, TC, RM>), grid_runs(td, c->N, sbd), dim3(kBlock), 0, c->stream, L.g, C.g, op, omegaJ(),
-            b, (TS*)C.b, sbd, st());
-    LAUNCH_CHECK();
-    stp_status s = vcycle_d<D>(l + 1, which, (const TS*)C.b, (TS*)C.e, nullptr);
-    if (s != STP_OK) return s;
-    c->kt.level = l;
-    const long tu = tiles_for<D, UpTile<D>>(L.n);
-    const int sbu = pick_sb(tu, c->N);
-    if (acc64)
-      KLAUNCH((k_mg_up<D, TS, TC, RM, EPI_ADD64>), grid_runs(tu, c->N, sbu), dim3(kBlock), 0, c->stream, L.g, C.g, op,
-              omegaJ(), b, (const TS*)C.e, (TS*)nullptr, acc64, sbu, st());
-    else
-      KLAUNCH((k_mg_up<D, TS, TC, RM, EPI_STORE>), grid_runs(tu, c->N, sbu), dim3(kBlock), 0, c->stream, L.g, C.g, op,
-              omegaJ(), b, (const TS*)C.e, out, (double*)nullptr, sbu, st());
-    LAUNCH_CHECK();
-    return STP_OK;
-  }
-
-  stp_status spatial_solve(int which, const TS* b, TS* out, double* acc64) {
-    if (c->spatial == STP_SPATIAL_EXACT) {
-      c->kt.level = 0;
-      const LevelOp op = fam(0, which);
-      const dim3 gr(unsigned((c->N + 63) / 64));
-      if (acc64)
-        KLAUNCH((k_tridiag<TS, TC, EPI_ADD64>), gr, dim3(64), 0, c->stream, c->lv[0].g, op, b, (TS*)nullptr,
-                           acc64, (TC*)c->tri, st());
-      else
-        KLAUNCH((k_tridiag<TS, TC, EPI_STORE>), gr, dim3(64), 0, c->stream, c->lv[0].g, op, b, out,
-                           (double*)nullptr, (TC*)c->tri, st());
-      LAUNCH_CHECK();
-      return STP_OK;
-    }
-    switch (c->dim) {
-      case 1: return vcycle_d<1>(0, which, b, out, acc64);
-      case 2: return vcycle_d<2>(0, which, b, out, acc64);
-      default: return vcycle_d<3>(0, which, b, out, acc64);
-    }
-  }
-
-  stp_status apply_mid(const TS* x, TS* y) {
+  stp_status mid_dr() {
+    Site<TileJob>& s = c->sites.mid;
     c->kt.level = 0;
-    const LevelOp op = fam(0, 2);
-    switch (c->dim) {
-      case 1: return apply_mid_d<1>(op, x, y);
-      case 2: return apply_mid_d<2>(op, x, y);
-      default: return apply_mid_d<3>(op, x, y);
-    }
-  }
-
-  template <int D>
-  stp_status apply_mid_d(const LevelOp& op, const TS* x, TS* y) {
-    const long tiles = tiles_for<D, UpTile<D>>(c->n);
-    const int sb = pick_sb(tiles, c->N);
-    const dim3 gr = grid_runs(tiles, c->N, sb);
-    switch (rm()) {
-      case 1: KLAUNCH((k_apply_tile<D, TS, TC, 1>), gr, dim3(kBlock), 0, c->stream, c->g0, op, x, y, sb, st()); break;
-      case 2: KLAUNCH((k_apply_tile<D, TS, TC, 2>), gr, dim3(kBlock), 0, c->stream, c->g0, op, x, y, sb, st()); break;
-      default: KLAUNCH((k_apply_tile<D, TS, TC, 4>), gr, dim3(kBlock), 0, c->stream, c->g0, op, x, y, sb, st()); break;
-    }
+    KLAUNCH_NAMED("k_apply_tile", (k_apply_tile<D, TS, TC, RM>), dim3(unsigned(s.blocks)), dim3(kBlock), 0, c->stream,
+                  s.dev, int(s.jobs.size()));
     LAUNCH_CHECK();
     return STP_OK;
   }
 
-  // out (or acc64 += alpha*) = T applied along time to in; mode 0: Phi^{-T}, 1: Phi^{-1}
-  stp_status time_transform(int mode, const TS* in, TS* out, double* acc64, double alpha) {
-    c->kt.level = 0;
-    const long npts = c->g0.npts;
-    if (c->N >= 4 && c->N <= 256 && (c->N & (c->N - 1)) == 0) {
-      switch (c->N) {
-        case 4: return fft2<1, 1>(mode, in, out, acc64, alpha);
-        case 8: return fft2<2, 1>(mode, in, out, acc64, alpha);
-        case 16: return fft2<2, 2>(mode, in, out, acc64, alpha);
-        case 32: return fft2<3, 2>(mode, in, out, acc64, alpha);
-        case 64: return fft2<3, 3>(mode, in, out, acc64, alpha);
-        case 128: return fft2<4, 3>(mode, in, out, acc64, alpha);
-        default: return fft2<4, 4>(mode, in, out, acc64, alpha);
-      }
+  stp_status run_mid() {
+    switch (c->dim * 10 + c->rm) {
+      case 11: return mid_dr<1, 1>();
+      case 12: return mid_dr<1, 2>();
+      case 14: return mid_dr<1, 4>();
+      case 21: return mid_dr<2, 1>();
+      case 22: return mid_dr<2, 2>();
+      case 24: return mid_dr<2, 4>();
+      case 31: return mid_dr<3, 1>();
+      case 32: return mid_dr<3, 2>();
+      default: return mid_dr<3, 4>();
     }
-    if (c->fft_cols > 0) {
-      const int C = c->fft_cols;
-      const dim3 gr(unsigned((npts + C - 1) / C));
-      const size_t lds = c->fft_lds;
-      const TC* tw = (const TC*)c->tw;
-      const TC* tw4 = (const TC*)c->tw4;
-      if (mode == 0)
-        KLAUNCH((k_time_fft<TS, TC, MODE_A4, 0>), gr, dim3(kBlock), lds, c->stream, npts, c->N, C, tw, tw4,
-                           in, out, (double*)nullptr, alpha, st());
-      else if (acc64)
-        KLAUNCH((k_time_fft<TS, TC, MODE_A6, 1>), gr, dim3(kBlock), lds, c->stream, npts, c->N, C, tw, tw4,
-                           in, (TS*)nullptr, acc64, alpha, st());
-      else
-        KLAUNCH((k_time_fft<TS, TC, MODE_A6, 0>), gr, dim3(kBlock), lds, c->stream, npts, c->N, C, tw, tw4,
-                           in, out, (double*)nullptr, alpha, st());
-      LAUNCH_CHECK();
-      return STP_OK;
-    }
-    const void* T = mode == 0 ? c->sinT : c->sinM;
-    const int per_block = 4 * kDstKpt;
-    const dim3 gr(unsigned((npts + 63) / 64), unsigned((c->N + per_block - 1) / per_block));
-    if (acc64)
-      KLAUNCH((k_time_dense<TS, TS, TC, 1>), gr, dim3(kBlock), 0, c->stream, npts, c->N, (const TC*)T, in,
-                         (TS*)nullptr, acc64, alpha, st());
-    else
-      KLAUNCH((k_time_dense<TS, TS, TC, 0>), gr, dim3(kBlock), 0, c->stream, npts, c->N, (const TC*)T, in,
-                         out, (double*)nullptr, alpha, st());
-    LAUNCH_CHECK();
-    return STP_OK;
   }
 
-  template <int L1, int L2>
-  stp_status fft2(int mode, const TS* in, TS* out, double* acc64, double alpha) {
+  template <int L1, int L2, int MODE, int ACC>
+  stp_status fft2_site(Site<TimeJob>& s) {
     constexpr int C = kBlock / (1 << L1);
-    const long npts = c->g0.npts;
-    const dim3 gr(unsigned((npts + C - 1) / C));
     const size_t lds = size_t(1 << (L1 + L2)) * C * sizeof(TC);
-    const TC* tw = (const TC*)c->tw;
-    const TC* tw4 = (const TC*)c->tw4;
-    if (mode == 0)
-      KLAUNCH((k_time_fft2<TS, TC, MODE_A4, 0, L1, L2>), gr, dim3(kBlock), lds, c->stream, npts, tw, tw4, in, out,
-              (double*)nullptr, alpha, st());
-    else if (acc64)
-      KLAUNCH((k_time_fft2<TS, TC, MODE_A6, 1, L1, L2>), gr, dim3(kBlock), lds, c->stream, npts, tw, tw4, in,
-              (TS*)nullptr, acc64, alpha, st());
-    else
-      KLAUNCH((k_time_fft2<TS, TC, MODE_A6, 0, L1, L2>), gr, dim3(kBlock), lds, c->stream, npts, tw, tw4, in, out,
-              (double*)nullptr, alpha, st());
+    KLAUNCH_NAMED(MODE == MODE_A4 ? "k_time_fft2<a4>" : (ACC ? "k_time_fft2<a6,add64>" : "k_time_fft2<a6>"),
+                  (k_time_fft2<TS, TC, MODE, ACC, L1, L2>), dim3(unsigned(s.blocks)), dim3(kBlock), lds, c->stream,
+                  s.dev, int(s.jobs.size()));
     LAUNCH_CHECK();
     return STP_OK;
   }
 
-  stp_status precA(const void* b, double* acc64, void* out) override {
-    return spatial_solve(0, (const TS*)b, (TS*)out, acc64);
-  }
-
-  // H-tilde^{-1}: W1 holds r (TS) on entry; result into acc64 (+= alpha * z) or out (TS).
-  stp_status precH(void* W1v, void* W2v, double* acc64, void* out, double alpha) override {
-    TS* W1 = (TS*)W1v;
-    TS* W2 = (TS*)W2v;
-    stp_status s;
-    if ((s = time_transform(0, W1, W2, nullptr, 1.0)) != STP_OK) return s;          // rhat = Phi^{-T} r
-    if ((s = spatial_solve(1, W2, W1, nullptr)) != STP_OK) return s;                  // x = H~_k^{-1} rhat
-    if ((s = apply_mid(W1, W2)) != STP_OK) return s;                                  // y = (2/N) tau A x
-    if ((s = spatial_solve(1, W2, W1, nullptr)) != STP_OK) return s;                  // yhat = H~_k^{-1} y
-    return time_transform(1, W1, (TS*)out, acc64, alpha);                             // Phi^{-1} yhat
-  }
-
-  template <int D, int WHICH>
-  stp_status resid_launch(const dim3& gr, const TimeOp& t, const double* u, const double* p, int sb) {
-    double* part = WHICH == 1 ? c->partial : nullptr;
-    const char* nm = WHICH == 0 ? "k_resid_tile<a1>" : "k_resid_tile<a3>";
-    switch (rm()) {
-      case 1: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, 1>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, u, p, c->F, c->u0, (TS*)c->W1, part, sb, st()); break;
-      case 2: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, 2>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, u, p, c->F, c->u0, (TS*)c->W1, part, sb, st()); break;
-      default: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, 4>), gr, dim3(kBlock), 0, c->stream, c->g0, t, c->tau, u, p, c->F, c->u0, (TS*)c->W1, part, sb, st()); break;
+  template <int MODE, int ACC>
+  stp_status fft2_dispatch(Site<TimeJob>& s) {
+    switch (s.key) {
+      case 4: return fft2_site<1, 1, MODE, ACC>(s);
+      case 8: return fft2_site<2, 1, MODE, ACC>(s);
+      case 16: return fft2_site<2, 2, MODE, ACC>(s);
+      case 32: return fft2_site<3, 2, MODE, ACC>(s);
+      case 64: return fft2_site<3, 3, MODE, ACC>(s);
+      case 128: return fft2_site<4, 3, MODE, ACC>(s);
+      default: return fft2_site<4, 4, MODE, ACC>(s);
     }
+  }
+
+  // timing records of transform site g carry "level" g
+  stp_status transform_sites(std::vector<Site<TimeJob>>& sites, int mode) {
+    for (size_t g = 0; g < sites.size(); ++g) {
+      Site<TimeJob>& s = sites[g];
+      c->kt.level = int(g);
+      if (s.jobs.empty()) continue;
+      const int N = s.key;
+      const bool acc = s.epi != 0;
+      if (N < 0) {   // dense
+        if (acc)
+          KLAUNCH_NAMED("k_time_dense<a6,add64>", (k_time_dense<TS, TC, 1>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
+                        c->stream, s.dev, int(s.jobs.size()));
+        else
+          KLAUNCH_NAMED(mode == 0 ? "k_time_dense<a4>" : "k_time_dense<a6>", (k_time_dense<TS, TC, 0>),
+                        dim3(unsigned(s.blocks)), dim3(kBlock), 0, c->stream, s.dev, int(s.jobs.size()));
+        LAUNCH_CHECK();
+        continue;
+      }
+      if (N >= 4 && N <= 256) {
+        stp_status st;
+        if (mode == 0) st = fft2_dispatch<MODE_A4, 0>(s);
+        else if (acc) st = fft2_dispatch<MODE_A6, 1>(s);
+        else st = fft2_dispatch<MODE_A6, 0>(s);
+        if (st != STP_OK) return st;
+        continue;
+      }
+      // Stockham: every job of the site has the same N, hence the same layout
+      int C, path;
+      size_t lds;
+      transform_path(N, sizeof(TC), path, C, lds);
+      if (mode == 0)
+        KLAUNCH_NAMED("k_time_fft<a4>", (k_time_fft<TS, TC, MODE_A4, 0>), dim3(unsigned(s.blocks)), dim3(kBlock), lds,
+                      c->stream, s.dev, int(s.jobs.size()), C);
+      else if (acc)
+        KLAUNCH_NAMED("k_time_fft<a6,add64>", (k_time_fft<TS, TC, MODE_A6, 1>), dim3(unsigned(s.blocks)), dim3(kBlock),
+                      lds, c->stream, s.dev, int(s.jobs.size()), C);
+      else
+        KLAUNCH_NAMED("k_time_fft<a6>", (k_time_fft<TS, TC, MODE_A6, 0>), dim3(unsigned(s.blocks)), dim3(kBlock), lds,
+                      c->stream, s.dev, int(s.jobs.size()), C);
+      LAUNCH_CHECK();
+    }
+    return STP_OK;
+  }
+
+  // H-tilde^{-1}: W1 holds r on entry; Phi^{-1} yhat goes to the a6 targets.
+  stp_status run_precH() override {
+    stp_status s;
+    if ((s = transform_sites(c->sites.a4, 0)) != STP_OK) return s;   // rhat = Phi^{-T} r    (W1 -> W2)
+    if ((s = run_vcycle(VC_H1)) != STP_OK) return s;                  // x = H~_k^{-1} rhat   (W2 -> W1)
+    if ((s = run_mid()) != STP_OK) return s;                          // y = (2/N) tau A x    (W1 -> W2)
+    if ((s = run_vcycle(VC_H2)) != STP_OK) return s;                  // yhat = H~_k^{-1} y   (W2 -> W1)
+    return transform_sites(c->sites.a6, 1);                           // += alpha Phi^{-1} yhat
+  }
+
+  template <int D, int WHICH, int RM>
+  stp_status resid_dr() {
+    Site<ResidJob>& s = c->sites.resid[WHICH];
+    c->kt.level = 0;
+    KLAUNCH_NAMED(WHICH == 0 ? "k_resid_tile<a1>" : "k_resid_tile<a3>", (k_resid_tile<D, TS, WHICH, RM>),
+                  dim3(unsigned(s.blocks)), dim3(kBlock), 0, c->stream, s.dev, int(s.jobs.size()));
     LAUNCH_CHECK();
     return STP_OK;
   }
 
-  template <int D>
-  stp_status iteration_d(double* u, double* p) {
-    c->kt.level = 0;
-    const long tiles = tiles_for<D, UpTile<D>>(c->n);
-    const int sb = c->sb_resid;
-    const dim3 gr = grid_runs(tiles, c->N, sb);
-    TimeOp t{c->kap64, c->cA64, c->R, c->N};
-    stp_status s;
-    if ((s = resid_launch<D, 0>(gr, t, u, p, sb)) != STP_OK) return s;
-    s = spatial_solve(0, (const TS*)c->W1, nullptr, p);   // p += A~^{-1} r_p
-    if (s != STP_OK) return s;
-    c->kt.level = 0;
-    if ((s = resid_launch<D, 1>(gr, t, u, p, sb)) != STP_OK) return s;
-    KLAUNCH(k_finalize, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial, c->npart_resid,
-                       c->state, c->opt.tol, c->opt.max_iter);
-    LAUNCH_CHECK();
-    return precH(c->W1, c->W2, u, nullptr, c->omega);                  // u += omega H~^{-1} r_u
+  template <int WHICH>
+  stp_status run_resid() {
+    switch (c->dim * 10 + c->rm) {
+      case 11: return resid_dr<1, WHICH, 1>();
+      case 12: return resid_dr<1, WHICH, 2>();
+      case 14: return resid_dr<1, WHICH, 4>();
+      case 21: return resid_dr<2, WHICH, 1>();
+      case 22: return resid_dr<2, WHICH, 2>();
+      case 24: return resid_dr<2, WHICH, 4>();
+      case 31: return resid_dr<3, WHICH, 1>();
+      case 32: return resid_dr<3, WHICH, 2>();
+      default: return resid_dr<3, WHICH, 4>();
+    }
   }
 
-  stp_status iteration(double* u, double* p) override {
-    switch (c->dim) {
-      case 1: return iteration_d<1>(u, p);
-      case 2: return iteration_d<2>(u, p);
-      default: return iteration_d<3>(u, p);
-    }
+  stp_status iteration() override {
+    stp_status s;
+    if ((s = run_resid<0>()) != STP_OK) return s;        // r_p = K u - A p - f   -> W1
+    if ((s = run_vcycle(VC_A)) != STP_OK) return s;      // p += A~^{-1} r_p
+    if ((s = run_resid<1>()) != STP_OK) return s;        // r_u -> W1, partials of ||f - B u||^2
+    c->kt.level = 0;
+    KLAUNCH(k_finalize, dim3(unsigned(c->P)), dim3(kBlock), 0, c->stream, (const FinJob*)c->sites.fin_dev);
+    LAUNCH_CHECK();
+    return run_precH();                                  // u += omega H~^{-1} r_u
   }
 
   stp_status cast_in(const double* a, void* b, long n) override {
-    KLAUNCH((k_cast_from64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n,
-                       a, (TS*)b);
-    LAUNCH_CHECK();
-    return STP_OK;
-  }
-  stp_status cast_out(const void* a, double* b, long n) override {
-    KLAUNCH((k_cast_to64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n,
-                       (const TS*)a, b);
+    KLAUNCH((k_cast_from64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n, a, (TS*)b);
     LAUNCH_CHECK();
     return STP_OK;
   }
 
-  stp_status setup_tables() override {
-    const int N = c->N, R = c->R;
-    if (c->fft_lds > 65536) {
-      HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A4, 0>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(c->fft_lds)));
-      HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 0>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(c->fft_lds)));
-      HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 1>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(c->fft_lds)));
-    }
+  stp_status setup_problem(Problem& q) override {
+    const int N = q.N, R = q.R;
     std::vector<TC> cA(size_t(N) * kMaxRank, TC(0)), cH(size_t(N) * kMaxRank, TC(0)), sig(N), mid(kMaxRank, TC(0));
     std::vector<double> cA64(size_t(N) * kMaxRank, 0.0);
     for (int s = 0; s < N; ++s)
       for (int r = 0; r < R; ++r) {
-        cA64[size_t(s) * kMaxRank + r] = c->tau * c->tcoef[size_t(r) * N + s];
-        cA[size_t(s) * kMaxRank + r] = TC(c->tau * c->tcoef[size_t(r) * N + s]);
-        cH[size_t(s) * kMaxRank + r] = TC(c->tau * c->abar[r]);
+        cA64[size_t(s) * kMaxRank + r] = q.tau * q.tcoef[size_t(r) * N + s];
+        cA[size_t(s) * kMaxRank + r] = TC(q.tau * q.tcoef[size_t(r) * N + s]);
+        cH[size_t(s) * kMaxRank + r] = TC(q.tau * q.abar[r]);
       }
     for (int k = 0; k < N; ++k) sig[k] = TC(2.0 * std::sin((2.0 * k + 1.0) * M_PI / (4.0 * N)));
-    for (int r = 0; r < R; ++r) mid[r] = TC((2.0 / N) * c->tau * c->abar[r]);
-    std::vector<TC> sT(size_t(N) * N), sM(size_t(N) * N);
-    for (int k = 0; k < N; ++k)
-      for (int m = 0; m < N; ++m) {
-        // sin((2k+1)(m+1) pi / (2N)) with the angle reduced exactly in integers
-        const long q = (long(2 * k + 1) * long(m + 1)) % (4L * N);
-        const double v = std::sin(double(q) * M_PI / (2.0 * N));
-        sT[size_t(k) * N + m] = TC(v);   // row k (frequency), column m (time)
-        sM[size_t(m) * N + k] = TC(v);   // row m (time), column k (frequency)
-      }
-    HIP_TRY(hipMemcpyAsync(c->cA64, cA64.data(), cA64.size() * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->cA, cA.data(), cA.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->cH, cH.data(), cH.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->sigH, sig.data(), sig.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->cMid, mid.data(), mid.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-    {
-      double wd[32];
-      float wf[32];
-      for (int k = 0; k < 16; ++k) {
-        wd[k] = std::cos(2.0 * M_PI * k / 16.0);
-        wd[16 + k] = -std::sin(2.0 * M_PI * k / 16.0);
-        wf[k] = float(wd[k]);
-        wf[16 + k] = float(wd[16 + k]);
-      }
-      HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_w16d), wd, sizeof(wd)));
-      HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_w16f), wf, sizeof(wf)));
-    }
-    if (c->fft_cols > 0) {
+    for (int r = 0; r < R; ++r) mid[r] = TC((2.0 / N) * q.tau * q.abar[r]);
+    HIP_TRY(hipMemcpyAsync(q.cA64, cA64.data(), cA64.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(q.cA, cA.data(), cA.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(q.cH, cH.data(), cH.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(q.sigH, sig.data(), sig.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(q.cMid, mid.data(), mid.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+    if (q.tpath == TP_DENSE) {
+      std::vector<TC> sT(size_t(N) * N), sM(size_t(N) * N);
+      for (int k = 0; k < N; ++k)
+        for (int m = 0; m < N; ++m) {
+          // sin((2k+1)(m+1) pi / (2N)) with the angle reduced exactly in integers
+          const long qq = (long(2 * k + 1) * long(m + 1)) % (4L * N);
+          const double v = std::sin(double(qq) * M_PI / (2.0 * N));
+          sT[size_t(k) * N + m] = TC(v);
+          sM[size_t(m) * N + k] = TC(v);
+        }
+      HIP_TRY(hipMemcpyAsync(q.sinT, sT.data(), sT.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(q.sinM, sM.data(), sM.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+    } else {
       std::vector<TC> tw(2 * size_t(N)), tw4(2 * size_t(N));
       for (int m = 0; m < N; ++m) {
         tw[m] = TC(std::cos(2.0 * M_PI * m / N));
@@ -565,38 +923,42 @@ struct Solver : SolverBase {
         tw4[m] = TC(std::cos(M_PI * m / (2.0 * N)));
         tw4[N + m] = TC(-std::sin(M_PI * m / (2.0 * N)));
       }
-      HIP_TRY(hipMemcpyAsync(c->tw, tw.data(), tw.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipMemcpyAsync(c->tw4, tw4.data(), tw4.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipStreamSynchronize(c->stream));   // host vectors go out of scope
-    } else {
-      HIP_TRY(hipMemcpyAsync(c->sinT, sT.data(), sT.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipMemcpyAsync(c->sinM, sM.data(), sM.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(q.tw, tw.data(), tw.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(q.tw4, tw4.data(), tw4.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
       HIP_TRY(hipStreamSynchronize(c->stream));
+      if (q.tpath == TP_STOCKHAM && q.fft_lds > 65536) {
+        HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A4, 0>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(q.fft_lds)));
+        HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 0>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(q.fft_lds)));
+        HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 1>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(q.fft_lds)));
+      }
     }
     // level fields: restrict unscaled float64 fields, then scale by 0.5/h^2 into TC
-    for (size_t l = 0; l < c->lv.size(); ++l) {
-      Level& L = c->lv[l];
+    for (size_t l = 0; l < q.lv.size(); ++l) {
+      Level& L = q.lv[l];
       const long nn = L.g.nnodes;
       if (l > 0) {
-        Level& F = c->lv[l - 1];
+        Level& Fl = q.lv[l - 1];
         for (int r = 0; r < R; ++r) {
           const dim3 gr(unsigned((nn + kBlock - 1) / kBlock));
-          switch (c->dim) {
-            case 1: KLAUNCH(k_restrict_kappa<1>, gr, dim3(kBlock), 0, c->stream, F.n, L.n, F.kraw + r * F.g.nnodes, L.kraw + r * nn); break;
-            case 2: KLAUNCH(k_restrict_kappa<2>, gr, dim3(kBlock), 0, c->stream, F.n, L.n, F.kraw + r * F.g.nnodes, L.kraw + r * nn); break;
-            default: KLAUNCH(k_restrict_kappa<3>, gr, dim3(kBlock), 0, c->stream, F.n, L.n, F.kraw + r * F.g.nnodes, L.kraw + r * nn); break;
+          switch (q.dim) {
+            case 1: KLAUNCH(k_restrict_kappa<1>, gr, dim3(kBlock), 0, c->stream, Fl.n, L.n, Fl.kraw + r * Fl.g.nnodes, L.kraw + r * nn); break;
+            case 2: KLAUNCH(k_restrict_kappa<2>, gr, dim3(kBlock), 0, c->stream, Fl.n, L.n, Fl.kraw + r * Fl.g.nnodes, L.kraw + r * nn); break;
+            default: KLAUNCH(k_restrict_kappa<3>, gr, dim3(kBlock), 0, c->stream, Fl.n, L.n, Fl.kraw + r * Fl.g.nnodes, L.kraw + r * nn); break;
           }
           LAUNCH_CHECK();
         }
       }
       const double sc = 0.5 / (L.h * L.h);
       const long tot = nn * R;
-      KLAUNCH((k_scale_copy<TC>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
-                         tot, (const double*)L.kraw, sc, (TC*)L.kscaled);
+      KLAUNCH((k_scale_copy<TC>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, tot,
+              (const double*)L.kraw, sc, (TC*)L.kscaled);
       LAUNCH_CHECK();
       if (l == 0) {
-        KLAUNCH((k_scale_copy<double>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           c->stream, tot, (const double*)L.kraw, sc, c->kap64);
+        KLAUNCH((k_scale_copy<double>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
+                tot, (const double*)L.kraw, sc, q.kap64);
         LAUNCH_CHECK();
       }
     }
@@ -604,86 +966,9 @@ struct Solver : SolverBase {
   }
 };
 
-// Plan (dry run) or carve (real run) the workspace.
-size_t plan(stp_ctx* c, Bump& bp) {
-  const int prec = c->opt.precision;
-  const size_t tsb = ts_bytes(prec), tcb = tc_bytes(prec);
-  fft_layout(c->N, tcb, c->fft_cols, c->fft_lds);
-  const long N = c->N;
-  c->state = (DevState*)bp.take(sizeof(DevState));
-  {
-    long tiles = c->dim == 1 ? tiles_for<1, UpTile<1>>(c->n)
-                 : c->dim == 2 ? tiles_for<2, UpTile<2>>(c->n) : tiles_for<3, UpTile<3>>(c->n);
-    const dim3 gp = grid_pts(c->g0.npts, c->N);   // the setup reduction uses the point grid
-    const long gyz = long(std::min(c->N, 65535)) * ((c->N + 65534) / 65535);
-    {
-      long sb = (tiles * c->N) / 2048;
-      c->sb_resid = int(std::max(1L, std::min(16L, sb)));
-    }
-    const long runs = (c->N + c->sb_resid - 1) / c->sb_resid;
-    c->npart_resid = tiles * std::min(runs, 65535L) * ((runs + 65534) / 65535);
-    (void)gyz;
-    c->npart_points = long(gp.x) * gp.y * gp.z;
-    c->npartial = std::max(c->npart_resid, c->npart_points);
-  }
-  c->partial = (double*)bp.take(size_t(c->npartial) * 8);
-  c->kap64 = (double*)bp.take(size_t(c->R) * c->g0.nnodes * 8);
-  c->cA64 = (double*)bp.take(size_t(N) * kMaxRank * 8);
-  c->cA = bp.take(size_t(N) * kMaxRank * tcb);
-  c->cH = bp.take(size_t(N) * kMaxRank * tcb);
-  c->sigH = bp.take(size_t(N) * tcb);
-  c->cMid = bp.take(size_t(kMaxRank) * tcb);
-  if (c->fft_cols > 0) {
-    c->tw = bp.take(size_t(2) * N * tcb);
-    c->tw4 = bp.take(size_t(2) * N * tcb);
-  } else {
-    c->sinT = bp.take(size_t(N) * N * tcb);
-    c->sinM = bp.take(size_t(N) * N * tcb);
-  }
-  c->W1 = bp.take(size_t(N) * c->g0.npts * tsb);
-  c->W2 = bp.take(size_t(N) * c->g0.npts * tsb);
-  if (c->spatial == STP_SPATIAL_EXACT) c->tri = bp.take(size_t(2) * N * c->n * tcb);
-  for (size_t l = 0; l < c->lv.size(); ++l) {
-    Level& L = c->lv[l];
-    L.kraw = (l == 0) ? nullptr : (double*)bp.take(size_t(c->R) * L.g.nnodes * 8);
-    L.kscaled = bp.take(size_t(c->R) * L.g.nnodes * tcb);
-    const size_t vb = size_t(N) * L.g.npts * tsb;
-    if (c->spatial == STP_SPATIAL_EXACT || c->spatial == STP_SPATIAL_NONE) {
-      L.b = L.x = L.t = L.e = nullptr;
-      continue;
-    }
-    const bool last = (l + 1 == c->lv.size());
-    L.b = (l == 0) ? nullptr : bp.take(vb);
-    L.e = (l == 0) ? nullptr : bp.take(vb);
-    L.x = nullptr;
-    L.t = (last && l == 0) ? bp.take(vb) : nullptr;   // single-level hierarchy: scratch for the coarse solve
-  }
-  return bp.off + 256;
-}
-
-stp_status build_levels(stp_ctx* c) {
-  c->lv.clear();
-  int n = c->n;
-  while (true) {
-    Level L{};
-    L.n = n;
-    L.h = 1.0 / (n + 1);
-    L.g.n = n;
-    L.g.npts = ipow(n, c->dim);
-    L.g.nnodes = ipow(n + 2, c->dim);
-    c->lv.push_back(L);
-    if (c->spatial == STP_SPATIAL_EXACT || c->spatial == STP_SPATIAL_NONE || n == 1) break;
-    if (n % 2 == 0) return fail(STP_EUNSUPPORTED, "multigrid needs n = 2^L - 1 interior nodes per axis (got %d)", c->n);
-    n = (n - 1) / 2;
-    if (int(c->lv.size()) >= STP_MAX_LEVELS) return fail(STP_EUNSUPPORTED, "too many multigrid levels");
-  }
-  c->g0 = c->lv[0].g;
-  return STP_OK;
-}
-
-stp_status validate(const stp_grid* g, int N, double tau, const stp_kappa* kappa, const double* F, const double* u0,
-                    const stp_options* opt) {
-  if (!g || !kappa || !opt) return fail(STP_EINVAL, "NULL grid, kappa or options");
+stp_status validate_one(const stp_grid* g, int N, double tau, const stp_kappa* kappa, const double* F,
+                        const double* u0, const stp_options* opt) {
+  if (!g || !kappa) return fail(STP_EINVAL, "NULL grid or kappa");
   if (g->dim < 1 || g->dim > 3) return fail(STP_EINVAL, "dim must be 1, 2 or 3 (got %d)", g->dim);
   if (g->n < 1) return fail(STP_EINVAL, "n must be >= 1 (got %d)", g->n);
   if (N < 1) return fail(STP_EINVAL, "N must be >= 1 (got %d)", N);
@@ -691,15 +976,60 @@ stp_status validate(const stp_grid* g, int N, double tau, const stp_kappa* kappa
   if (kappa->rank < 1 || kappa->rank > STP_MAX_RANK) return fail(STP_EINVAL, "kappa rank must be 1..%d", STP_MAX_RANK);
   if (!kappa->fields || !kappa->tcoef) return fail(STP_EINVAL, "NULL kappa fields or tcoef");
   if (!F || !u0) return fail(STP_EINVAL, "NULL F or u0");
-  if (opt->precision < STP_PREC_F64 || opt->precision > STP_PREC_BF16) return fail(STP_EINVAL, "bad precision");
-  if (opt->nu_A != 1 || opt->nu_H != 1) return fail(STP_EUNSUPPORTED, "only nu_A = nu_H = 1 is implemented");
-  if (opt->spatial < STP_SPATIAL_AUTO || opt->spatial > STP_SPATIAL_NONE) return fail(STP_EINVAL, "bad spatial mode");
   if (opt->spatial == STP_SPATIAL_EXACT && g->dim != 1) return fail(STP_EUNSUPPORTED, "exact spatial solves are 1-D only");
+  const long npts = ipow(g->n, g->dim);
+  if (double(npts) * double(N) > 4.0e12 || npts > (1L << 31) - 1) return fail(STP_EINVAL, "problem too large");
+  return STP_OK;
+}
+
+stp_status validate_opts(const stp_options* opt) {
+  if (opt->precision < STP_PREC_F64 || opt->precision > STP_PREC_BF16) return fail(STP_EINVAL, "bad precision");
+  if (opt->spatial < STP_SPATIAL_AUTO || opt->spatial > STP_SPATIAL_NONE) return fail(STP_EINVAL, "bad spatial mode");
+  if (opt->nu_A != 1 || opt->nu_H != 1) return fail(STP_EUNSUPPORTED, "only nu_A = nu_H = 1 is implemented");
   if (!(opt->tol >= 0)) return fail(STP_EINVAL, "tol must be >= 0");
   if (opt->max_iter < 0) return fail(STP_EINVAL, "max_iter must be >= 0");
-  long npts = ipow(g->n, g->dim);
-  if (double(npts) * double(N) > 4.0e12) return fail(STP_EINVAL, "problem too large");
   return STP_OK;
+}
+
+int resolve_spatial(int dim, int spatial) {
+  if (spatial == STP_SPATIAL_AUTO) return dim == 1 ? STP_SPATIAL_EXACT : STP_SPATIAL_MG;
+  return spatial;
+}
+
+// Describe the problems of a batch (host only; no device work).
+stp_status describe(stp_ctx* c, int P, const stp_grid* grids, const int* N, const double* tau,
+                    const stp_kappa* kappa, const double* const* F, const double* const* u0) {
+  c->P = P;
+  c->pr.assign(P, Problem());
+  c->dim = grids[0].dim;
+  c->spatial = resolve_spatial(c->dim, c->opt.spatial);
+  int rmax = 1;
+  for (int i = 0; i < P; ++i) {
+    Problem& q = c->pr[i];
+    q.dim = grids[i].dim;
+    if (q.dim != c->dim) return fail(STP_EUNSUPPORTED, "all problems of a batch must have the same dimension");
+    q.n = grids[i].n;
+    q.N = N[i];
+    q.tau = tau ? tau[i] : 0.0;
+    q.R = kappa ? kappa[i].rank : 1;
+    q.F = F ? F[i] : nullptr;
+    q.u0 = u0 ? u0[i] : nullptr;
+    q.fields = kappa ? kappa[i].fields : nullptr;
+    rmax = std::max(rmax, q.R);
+    stp_status s = build_levels(c->spatial, q);
+    if (s != STP_OK) return s;
+  }
+  c->rm = rmax <= 1 ? 1 : (rmax <= 2 ? 2 : 4);
+  return STP_OK;
+}
+
+size_t plan_all(stp_ctx* c, Bump& bp) {
+  for (auto& q : c->pr) plan_problem(c->prec, c->spatial, q, bp);
+  std::vector<double*> nul(c->P, nullptr);
+  build_sites(c, nul, nul);
+  c->tables_off = (bp.off + 255) & ~size_t(255);
+  c->tables_bytes = tables_bytes(c->sites);
+  return c->tables_off + c->tables_bytes + 256;
 }
 
 }  // namespace
@@ -738,62 +1068,66 @@ const char* stp_status_string(stp_status s) {
 
 const char* stp_last_error(void) { return g_last_error.c_str(); }
 
-static int resolve_spatial(int dim, int spatial) {
-  if (spatial == STP_SPATIAL_AUTO) return dim == 1 ? STP_SPATIAL_EXACT : STP_SPATIAL_MG;
-  return spatial;
+size_t stp_workspace_bytes_batch(int P, const stp_grid* grids, const int* N, const int* rank,
+                                 const stp_options* opt) {
+  if (P < 1 || !grids || !N || !rank || !opt) return 0;
+  if (validate_opts(opt) != STP_OK) return 0;
+  for (int i = 0; i < P; ++i) {
+    if (grids[i].dim < 1 || grids[i].dim > 3 || grids[i].n < 1 || N[i] < 1 || rank[i] < 1 || rank[i] > STP_MAX_RANK)
+      return 0;
+    if (opt->spatial == STP_SPATIAL_EXACT && grids[i].dim != 1) return 0;
+  }
+  stp_ctx c;
+  c.opt = *opt;
+  c.prec = opt->precision;
+  c.omega = opt->omega > 0 ? opt->omega : 0.8;
+  std::vector<stp_kappa> kap(P);
+  for (int i = 0; i < P; ++i) kap[i].rank = rank[i];
+  if (describe(&c, P, grids, N, nullptr, kap.data(), nullptr, nullptr) != STP_OK) return 0;
+  Bump bp;
+  return plan_all(&c, bp);
 }
 
 size_t stp_workspace_bytes(const stp_grid* g, int N, int rank, const stp_options* opt) {
-  if (!g || !opt || g->dim < 1 || g->dim > 3 || g->n < 1 || N < 1 || rank < 1 || rank > STP_MAX_RANK) return 0;
-  stp_ctx c;
-  c.dim = g->dim;
-  c.n = g->n;
-  c.N = N;
-  c.R = rank;
-  c.opt = *opt;
-  c.spatial = resolve_spatial(g->dim, opt->spatial);
-  if (build_levels(&c) != STP_OK) return 0;
-  Bump bp;
-  return plan(&c, bp);
+  return stp_workspace_bytes_batch(1, g, &N, &rank, opt);
 }
 
-stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau, const stp_kappa* kappa, const double* F,
-                      const double* u0, const stp_options* opt_in, void* workspace, size_t ws_bytes,
-                      void* hip_stream) {
+stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const int* N, const double* tau,
+                            const stp_kappa* kappa, const double* const* F, const double* const* u0,
+                            const stp_options* opt_in, void* workspace, size_t ws_bytes, void* hip_stream) {
   if (!out) return fail(STP_EINVAL, "NULL output context pointer");
   *out = nullptr;
+  if (P < 1 || !grids || !N || !tau || !kappa || !F || !u0) return fail(STP_EINVAL, "NULL batch argument or P < 1");
   stp_options opt;
   if (opt_in) opt = *opt_in;
   else stp_default_options(&opt);
-  stp_status s = validate(g, N, tau, kappa, F, u0, &opt);
+  stp_status s = validate_opts(&opt);
   if (s != STP_OK) return s;
+  if (opt.kref_coef && P > 1) return fail(STP_EINVAL, "kref_coef must be NULL for a batch of more than one problem");
+  for (int i = 0; i < P; ++i)
+    if ((s = validate_one(&grids[i], N[i], tau[i], &kappa[i], F[i], u0[i], &opt)) != STP_OK) return s;
   std::unique_ptr<stp_ctx> c(new stp_ctx());
-  c->dim = g->dim;
-  c->n = g->n;
-  c->N = N;
-  c->R = kappa->rank;
-  c->tau = tau;
   c->opt = opt;
-  c->spatial = resolve_spatial(g->dim, opt.spatial);
+  c->prec = opt.precision;
   c->omega = opt.omega > 0 ? opt.omega : 0.8;
   c->stream = (hipStream_t)hip_stream;
-  c->F = F;
-  c->u0 = u0;
-  c->fields = kappa->fields;
-  c->tcoef.assign(kappa->tcoef, kappa->tcoef + size_t(c->R) * N);
-  c->abar.assign(c->R, 0.0);
-  if (opt.kref_coef) {
-    for (int r = 0; r < c->R; ++r) c->abar[r] = opt.kref_coef[r];
-  } else {
-    for (int r = 0; r < c->R; ++r) {
-      double sum = 0;
-      for (int n = 0; n < N; ++n) sum += c->tcoef[size_t(r) * N + n];
-      c->abar[r] = sum / N;
+  if ((s = describe(c.get(), P, grids, N, tau, kappa, F, u0)) != STP_OK) return s;
+  for (int i = 0; i < P; ++i) {
+    Problem& q = c->pr[i];
+    q.tcoef.assign(kappa[i].tcoef, kappa[i].tcoef + size_t(q.R) * q.N);
+    q.abar.assign(q.R, 0.0);
+    if (opt.kref_coef) {
+      for (int r = 0; r < q.R; ++r) q.abar[r] = opt.kref_coef[r];
+    } else {
+      for (int r = 0; r < q.R; ++r) {
+        double sum = 0;
+        for (int n = 0; n < q.N; ++n) sum += q.tcoef[size_t(r) * q.N + n];
+        q.abar[r] = sum / q.N;
+      }
     }
   }
-  if ((s = build_levels(c.get())) != STP_OK) return s;
   Bump dry;
-  const size_t need = plan(c.get(), dry);
+  const size_t need = plan_all(c.get(), dry);
   if (workspace) {
     if (ws_bytes < need) return fail(STP_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(STP_EINVAL, "workspace not 256-byte aligned");
@@ -808,10 +1142,8 @@ stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau, const
   Bump real;
   real.dry = false;
   real.base = (char*)c->ws;
-  real.cap = need;
-  plan(c.get(), real);
-  c->lv[0].kraw = const_cast<double*>(c->fields);  // level 0 reads the caller's fields
-  HIP_TRY(hipHostMalloc((void**)&c->state_host, sizeof(DevState), hipHostMallocDefault));
+  for (auto& q : c->pr) plan_problem(c->prec, c->spatial, q, real);
+  HIP_TRY(hipHostMalloc((void**)&c->state_host, sizeof(DevState) * P, hipHostMallocDefault));
   HIP_TRY(hipEventCreate(&c->ev0));
   HIP_TRY(hipEventCreate(&c->ev1));
   switch (opt.precision) {
@@ -819,50 +1151,73 @@ stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau, const
     case STP_PREC_F32: c->impl = new Solver<float, float>(c.get()); break;
     default: c->impl = new Solver<bf16, float>(c.get()); break;
   }
-  if ((s = c->impl->setup_tables()) != STP_OK) return s;
-  // kappa(t_n, x) > 0 at every node and step, and for the reference coefficient
   {
-    const long nn = c->g0.nnodes;
-    const long nb = (nn + kBlock - 1) / kBlock;
-    std::vector<double> cref(kMaxRank, 0.0);
-    for (int r = 0; r < c->R; ++r) cref[r] = c->abar[r];
-    double* dref = (double*)c->partial;                    // reuse partials as scratch
-    if (c->npartial < nb + kMaxRank) {
-      // not enough scratch: use a temporary allocation
-      HIP_TRY(hipMallocAsync((void**)&dref, size_t(nb + kMaxRank) * 8, c->stream));
+    double wd[32];
+    float wf[32];
+    for (int k = 0; k < 16; ++k) {
+      wd[k] = std::cos(2.0 * M_PI * k / 16.0);
+      wd[16 + k] = -std::sin(2.0 * M_PI * k / 16.0);
+      wf[k] = float(wd[k]);
+      wf[16 + k] = float(wd[16 + k]);
     }
-    double* part = dref + kMaxRank;
-    HIP_TRY(hipMemcpyAsync(dref, cref.data(), kMaxRank * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_w16d), wd, sizeof(wd)));
+    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_w16f), wf, sizeof(wf)));
+  }
+  for (auto& q : c->pr) {
+    if ((s = c->impl->setup_problem(q)) != STP_OK) return s;
+    // kappa(t_n, x) > 0 at every node and step, and for the reference coefficient
+    const long nn = q.g0.nnodes;
+    const long nb = (nn + kBlock - 1) / kBlock;
+    double* scratch = nullptr;
+    HIP_TRY(hipMallocAsync((void**)&scratch, size_t(nb + kMaxRank) * 8, c->stream));
+    std::vector<double> cref(kMaxRank, 0.0);
+    for (int r = 0; r < q.R; ++r) cref[r] = q.abar[r];
+    double* part = scratch + kMaxRank;
+    HIP_TRY(hipMemcpyAsync(scratch, cref.data(), kMaxRank * 8, hipMemcpyHostToDevice, c->stream));
     std::vector<double> h(nb);
     double mn = 1e300;
     for (int pass = 0; pass < 2; ++pass) {
-      const double* coef = pass == 0 ? c->cA64 : dref;
-      KLAUNCH(k_kappa_min, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, nn, c->R, pass == 0 ? N : 1,
-                         c->fields, coef, part);
+      KLAUNCH(k_kappa_min, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, nn, q.R, pass == 0 ? q.N : 1, q.fields,
+              pass == 0 ? (const double*)q.cA64 : (const double*)scratch, part);
       LAUNCH_CHECK();
       HIP_TRY(hipMemcpyAsync(h.data(), part, size_t(nb) * 8, hipMemcpyDeviceToHost, c->stream));
       HIP_TRY(hipStreamSynchronize(c->stream));
       mn = std::min(mn, *std::min_element(h.begin(), h.end()));
     }
-    if (dref != c->partial) HIP_TRY(hipFreeAsync(dref, c->stream));
+    HIP_TRY(hipFreeAsync(scratch, c->stream));
     if (!(mn > 0)) return fail(STP_EINVAL, "kappa must be > 0 at every node and step (min %.3e)", mn);
-  }
-  // ||f||
-  {
-    const dim3 gr = grid_pts(c->g0.npts, N);
-    KLAUNCH(k_fnorm, gr, dim3(kBlock), 0, c->stream, c->g0, N, tau, F, u0, c->partial);
+    // ||f||
+    const dim3 gr = grid_pts(q.g0.npts, q.N);
+    KLAUNCH(k_fnorm, gr, dim3(kBlock), 0, c->stream, q.g0, q.N, q.tau, q.F, q.u0, q.partial);
     LAUNCH_CHECK();
-    KLAUNCH(k_sum_to, dim3(1), dim3(kBlock), 0, c->stream, (const double*)c->partial, c->npart_points,
-                       &c->state->fnorm);
+    KLAUNCH(k_sum_to, dim3(1), dim3(kBlock), 0, c->stream, (const double*)q.partial, q.nfnorm, &q.state->fnorm);
     LAUNCH_CHECK();
     DevState hs{};
-    HIP_TRY(hipMemcpyAsync(&hs, c->state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(&hs, q.state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    c->fnorm = std::sqrt(hs.fnorm);
+    q.fnorm = std::sqrt(hs.fnorm);
   }
+  // launch tables (jobs point at null u, p until a solve binds them)
+  std::vector<double*> nul(P, nullptr);
+  build_sites(c.get(), nul, nul);
+  carve_tables(c->sites, (char*)c->ws + c->tables_off);
+  if ((s = upload_all(c.get())) != STP_OK) return s;
+  HIP_TRY(hipStreamSynchronize(c->stream));
   *out = c.release();
   return STP_OK;
 }
+
+stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau, const stp_kappa* kappa, const double* F,
+                      const double* u0, const stp_options* opt, void* workspace, size_t ws_bytes,
+                      void* hip_stream) {
+  if (!g || !kappa) {
+    if (out) *out = nullptr;
+    return fail(STP_EINVAL, "NULL grid or kappa");
+  }
+  return stp_create_batch(out, 1, g, &N, &tau, kappa, &F, &u0, opt, workspace, ws_bytes, hip_stream);
+}
+
+int stp_batch_size(stp_ctx* c) { return c ? c->P : 0; }
 
 void stp_destroy(stp_ctx* c) {
   if (!c) return;
@@ -881,20 +1236,22 @@ void stp_destroy(stp_ctx* c) {
 
 stp_status stp_apply_operator(stp_ctx* c, int op, const double* x, double* y) {
   if (!c || !x || !y) return fail(STP_EINVAL, "NULL argument");
-  const dim3 gr = grid_pts(c->g0.npts, c->N);
-  TimeOp t{c->kap64, c->cA64, c->R, c->N};
-  const long nv = long(c->N) * c->g0.npts;
+  if (c->P != 1) return fail(STP_EUNSUPPORTED, "stp_apply_operator needs a single-problem context");
+  Problem& q = c->pr[0];
+  const dim3 gr = grid_pts(q.g0.npts, q.N);
+  TimeOp t{q.kap64, q.cA64, q.R, q.N};
+  const long nv = long(q.N) * q.g0.npts;
   if (op == STP_OP_B) {
     switch (c->dim) {
-      case 1: KLAUNCH(k_apply_B<1>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, y); break;
-      case 2: KLAUNCH(k_apply_B<2>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, y); break;
-      default: KLAUNCH(k_apply_B<3>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, y); break;
+      case 1: KLAUNCH(k_apply_B<1>, gr, dim3(kBlock), 0, c->stream, q.g0, t, x, y); break;
+      case 2: KLAUNCH(k_apply_B<2>, gr, dim3(kBlock), 0, c->stream, q.g0, t, x, y); break;
+      default: KLAUNCH(k_apply_B<3>, gr, dim3(kBlock), 0, c->stream, q.g0, t, x, y); break;
     }
   } else if (op == STP_OP_SADDLE) {
     switch (c->dim) {
-      case 1: KLAUNCH(k_apply_saddle<1>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, x + nv, y, y + nv); break;
-      case 2: KLAUNCH(k_apply_saddle<2>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, x + nv, y, y + nv); break;
-      default: KLAUNCH(k_apply_saddle<3>, gr, dim3(kBlock), 0, c->stream, c->g0, t, x, x + nv, y, y + nv); break;
+      case 1: KLAUNCH(k_apply_saddle<1>, gr, dim3(kBlock), 0, c->stream, q.g0, t, x, x + nv, y, y + nv); break;
+      case 2: KLAUNCH(k_apply_saddle<2>, gr, dim3(kBlock), 0, c->stream, q.g0, t, x, x + nv, y, y + nv); break;
+      default: KLAUNCH(k_apply_saddle<3>, gr, dim3(kBlock), 0, c->stream, q.g0, t, x, x + nv, y, y + nv); break;
     }
   } else {
     return fail(STP_EINVAL, "unknown operator %d", op);
@@ -907,27 +1264,30 @@ stp_status stp_apply_precond(stp_ctx* c, int which, const double* r, double* z) 
   if (!c || !r || !z) return fail(STP_EINVAL, "NULL argument");
   if (which != STP_PC_A && which != STP_PC_H) return fail(STP_EINVAL, "unknown preconditioner %d", which);
   if (c->spatial == STP_SPATIAL_NONE) return fail(STP_EUNSUPPORTED, "context created without a spatial solver");
-  const long nv = long(c->N) * c->g0.npts;
-  // the state flag must read "running" for the kernels to execute
-  HIP_TRY(hipMemsetAsync(c->state, 0, sizeof(int) * 2, c->stream));
+  if (c->P != 1) return fail(STP_EUNSUPPORTED, "stp_apply_precond needs a single-problem context");
+  Problem& q = c->pr[0];
+  const long nv = long(q.N) * q.g0.npts;
+  // the stop flag must read "running" for the kernels to execute
+  c->state_host[0] = DevState{};
+  c->state_host[0].fnorm = q.fnorm;
+  HIP_TRY(hipMemcpyAsync(q.state, &c->state_host[0], sizeof(DevState), hipMemcpyHostToDevice, c->stream));
   stp_status s;
-  if ((s = c->impl->cast_in(r, c->W1, nv)) != STP_OK) return s;
-  if (which == STP_PC_A) {
-    HIP_TRY(hipMemsetAsync(z, 0, size_t(nv) * 8, c->stream));
-    return c->impl->precA(c->W1, z, nullptr);
-  }
+  // accumulate into z (A: the p target; H: the Phi^{-1} target with factor 1)
+  std::vector<double*> zv(1, z);
+  if ((s = bind_solution(c, zv, zv, zv, 1.0)) != STP_OK) return s;
   HIP_TRY(hipMemsetAsync(z, 0, size_t(nv) * 8, c->stream));
-  return c->impl->precH(c->W1, c->W2, z, nullptr, 1.0);
+  if ((s = c->impl->cast_in(r, q.W1, nv)) != STP_OK) return s;
+  s = which == STP_PC_A ? c->impl->run_vcycle(VC_A) : c->impl->run_precH();
+  if (s != STP_OK) return s;
+  HIP_TRY(hipStreamSynchronize(c->stream));   // the job tables are rebound by the next call
+  return STP_OK;
 }
 
-// Capture one iteration on a private stream (capture is not possible on the
-// null stream); the instantiated graph is replayed on the context's stream.
-static stp_status capture_iteration(stp_ctx* c, double* u, double* p) {
-  if (c->gexec && c->g_u == u && c->g_p == p) return STP_OK;
-  if (c->gexec) {
-    (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
-  }
+// Capture one iteration over the batch on a private stream (capture is not
+// possible on the null stream).  The graph reads the job tables at replay
+// time, so it stays valid when a solve rebinds u and p.
+static stp_status capture_iteration(stp_ctx* c) {
+  if (c->gexec) return STP_OK;
   if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   hipStream_t saved = c->stream;
   c->stream = c->cap_stream;
@@ -935,7 +1295,7 @@ static stp_status capture_iteration(stp_ctx* c, double* u, double* p) {
   hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
   stp_status s = STP_OK;
   if (e == hipSuccess) {
-    s = c->impl->iteration(u, p);
+    s = c->impl->iteration();
     e = hipStreamEndCapture(c->cap_stream, &graph);
   }
   c->stream = saved;
@@ -950,53 +1310,76 @@ static stp_status capture_iteration(stp_ctx* c, double* u, double* p) {
     c->gexec = nullptr;
     return fail(STP_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
   }
-  c->g_u = u;
-  c->g_p = p;
   return STP_OK;
 }
 
-stp_status stp_uzawa_solve(stp_ctx* c, double* u, double* p, stp_stats* stats) {
-  if (!c || !u || !p) return fail(STP_EINVAL, "NULL argument (u and p are required)");
+stp_status stp_uzawa_solve_batch(stp_ctx* c, double* const* u, double* const* p, stp_stats* stats) {
+  if (!c || !u || !p) return fail(STP_EINVAL, "NULL argument");
   if (c->spatial == STP_SPATIAL_NONE) return fail(STP_EUNSUPPORTED, "context created without a spatial solver");
-  DevState init{};
-  init.fnorm = c->fnorm;
-  HIP_TRY(hipMemcpyAsync(c->state, &init, sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+  std::vector<double*> uv(c->P), pv(c->P);
+  for (int i = 0; i < c->P; ++i) {
+    if (!u[i] || !p[i]) return fail(STP_EINVAL, "NULL u or p of problem %d (both are required)", i);
+    uv[i] = u[i];
+    pv[i] = p[i];
+  }
+  stp_status s;
+  for (int i = 0; i < c->P; ++i) {
+    c->state_host[i] = DevState{};
+    c->state_host[i].fnorm = c->pr[i].fnorm;
+    HIP_TRY(hipMemcpyAsync(c->pr[i].state, &c->state_host[i], sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+  }
+  if ((s = bind_solution(c, uv, pv, uv, c->omega)) != STP_OK) return s;
+  const bool graph = c->opt.use_graph && !c->kt.on;
+  if (graph && (s = capture_iteration(c)) != STP_OK) return s;
   HIP_TRY(hipEventRecord(c->ev0, c->stream));
   const int chunk = std::max(1, c->opt.check_every);
-  stp_status s = STP_OK;
-  int launched = 0;
-  DevState hs{};
   const int max_launch = c->opt.max_iter + 1;   // iterations 0..max_iter each evaluate the stop test
-  const bool graph = c->opt.use_graph && !c->kt.on;
-  if (graph && (s = capture_iteration(c, u, p)) != STP_OK) return s;
+  int launched = 0;
   while (true) {
     const int todo = std::min(chunk, max_launch - launched);
     for (int q = 0; q < todo; ++q) {
       if (graph) HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
-      else if ((s = c->impl->iteration(u, p)) != STP_OK) return s;
+      else if ((s = c->impl->iteration()) != STP_OK) return s;
       ++launched;
     }
-    HIP_TRY(hipMemcpyAsync(c->state_host, c->state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+    for (int i = 0; i < c->P; ++i)
+      HIP_TRY(hipMemcpyAsync(&c->state_host[i], c->pr[i].state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    hs = *c->state_host;
-    if (hs.done) break;
+    bool all = true;
+    for (int i = 0; i < c->P; ++i) all = all && c->state_host[i].done != 0;
+    if (all) break;
     if (launched >= max_launch) return fail(STP_EDEVICE, "iteration state did not terminate");
   }
   HIP_TRY(hipEventRecord(c->ev1, c->stream));
   HIP_TRY(hipEventSynchronize(c->ev1));
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-  stp_status res = hs.done == 1 ? STP_OK : (hs.done == 2 ? STP_EDIVERGED : STP_ENOTCONV);
-  if (stats) {
-    stats->iters = hs.iter;
-    stats->rel_res = hs.rel;
-    stats->omega_used = c->omega;
-    stats->t_solve_ms = ms;
-    stats->status = res;
+  stp_status worst = STP_OK;
+  for (int i = 0; i < c->P; ++i) {
+    const DevState& hs = c->state_host[i];
+    const stp_status r = hs.done == 1 ? STP_OK : (hs.done == 2 ? STP_EDIVERGED : STP_ENOTCONV);
+    if (stats) {
+      stats[i].iters = hs.iter;
+      stats[i].rel_res = hs.rel;
+      stats[i].omega_used = c->omega;
+      stats[i].t_solve_ms = ms;
+      stats[i].status = r;
+    }
+    if (r == STP_EDIVERGED) {
+      worst = r;
+      fail(r, "problem %d: residual diverged at iteration %d (rel %.3e)", i, hs.iter, hs.rel);
+    } else if (r == STP_ENOTCONV && worst == STP_OK) {
+      worst = r;
+      fail(r, "problem %d: max_iter %d reached (rel %.3e)", i, c->opt.max_iter, hs.rel);
+    }
   }
-  if (res == STP_EDIVERGED) fail(res, "residual diverged at iteration %d (rel %.3e)", hs.iter, hs.rel);
-  if (res == STP_ENOTCONV) fail(res, "max_iter %d reached (rel %.3e)", c->opt.max_iter, hs.rel);
-  return res;
+  return worst;
+}
+
+stp_status stp_uzawa_solve(stp_ctx* c, double* u, double* p, stp_stats* st) {
+  if (!c || !u || !p) return fail(STP_EINVAL, "NULL argument (u and p are required)");
+  if (c->P != 1) return fail(STP_EUNSUPPORTED, "use stp_uzawa_solve_batch for a batch context");
+  return stp_uzawa_solve_batch(c, &u, &p, st);
 }
 
 stp_status stp_timing_enable(stp_ctx* c, int enable) {

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace stp {
 
 constexpr int kMaxRank = 4;
@@ -76,6 +78,17 @@ __device__ __forceinline__ long node_of(int x, int y, int z, int n) {
 }
 
 // Per-slab operator table entry, read once per block (uniform).
+// Pointers read from a job table are generic (flat) pointers to the compiler,
+// and flat memory instructions count against both the vector-memory and the
+// LDS wait counters, so every LDS wait would also wait for in-flight HBM
+// loads.  Re-deriving each pointer from its integer value in the global
+// address space makes the compiler emit global loads and stores.
+template <typename T>
+__device__ __forceinline__ T* gmem(T* p) {
+  using U = typename std::remove_cv<T>::type;
+  return (T*)((__attribute__((address_space(1))) U*)(uintptr_t)p);
+}
+
 template <typename TC>
 struct SlabOp {
   TC sigma;
@@ -227,61 +240,6 @@ __global__ void __launch_bounds__(kBlock) k_apply_saddle(Geom g, TimeOp t, const
   yu[o + i] = -(pc - pp) - (2.0 * uc - um - up) - Au;
 }
 
-// a1: r_p = K u - A p - f,  f_s = tau F_s (+ u0 on the first slab); stored in TS.
-template <int D, typename TS>
-__global__ void __launch_bounds__(kBlock) k_resid_p(Geom g, TimeOp t, double tau, const double* __restrict__ u,
-                                                    const double* __restrict__ p, const double* __restrict__ F,
-                                                    const double* __restrict__ u0, TS* __restrict__ r,
-                                                    const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
-  const int s = slab_index();
-  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
-  if (s >= t.N || i >= g.npts) return;
-  int px, py, pz;
-  decode<D>(i, g.n, px, py, pz);
-  const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
-  const long o = long(s) * g.npts;
-  double dg, off;
-  stencil<D, double>(p + o, i, px, py, pz, g, t.kap, op, t.R, dg, off);
-  const double Ap = dg * p[o + i] - off;
-  const double Ku = u[o + i] - (s > 0 ? u[o - g.npts + i] : 0.0);
-  double f = tau * F[o + i];
-  if (s == 0) f += u0[i];
-  st<TS, double>(r, o + i, Ku - Ap - f);
-}
-
-// a3: e = f - B u (stop residual, squared norm per block), r_u = e - K^T (u + p).
-template <int D, typename TS>
-__global__ void __launch_bounds__(kBlock) k_resid_u(Geom g, TimeOp t, double tau, const double* __restrict__ u,
-                                                    const double* __restrict__ p, const double* __restrict__ F,
-                                                    const double* __restrict__ u0, TS* __restrict__ r,
-                                                    double* __restrict__ partial, const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
-  const int s = slab_index();
-  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
-  double e2 = 0.0;
-  if (s < t.N && i < g.npts) {
-    int px, py, pz;
-    decode<D>(i, g.n, px, py, pz);
-    const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
-    const long o = long(s) * g.npts;
-    double dg, off;
-    stencil<D, double>(u + o, i, px, py, pz, g, t.kap, op, t.R, dg, off);
-    const double uc = u[o + i];
-    const double Au = dg * uc - off;
-    const double um = s > 0 ? u[o - g.npts + i] : 0.0;
-    double f = tau * F[o + i];
-    if (s == 0) f += u0[i];
-    const double e = f - (uc - um) - Au;
-    const double w = uc + p[o + i];
-    const double wn = s + 1 < t.N ? u[o + g.npts + i] + p[o + g.npts + i] : 0.0;
-    st<TS, double>(r, o + i, e - (w - wn));
-    e2 = e * e;
-  }
-  const double bs = block_sum(e2);
-  if (threadIdx.x == 0) partial[long(slab_index()) * gridDim.x + blockIdx.x] = bs;
-}
-
 // ||f||^2 partials (setup)
 __global__ void __launch_bounds__(kBlock) k_fnorm(Geom g, int N, double tau, const double* __restrict__ F,
                                                   const double* __restrict__ u0, double* __restrict__ partial) {
@@ -306,23 +264,39 @@ struct DevState {
   double res0;
 };
 
-// Deterministic reduction of the residual partials and the stop decision.
-__global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ partial, long count,
-                                                     DevState* st, double tol, int max_iter) {
+// Deterministic reduction of one problem's residual partials and its stop
+// decision; block b handles job b.
+struct FinJob {
+  const double* partial;
+  long count;
+  DevState* st;
+  double tol;
+  int max_iter;
+};
+
+__device__ __forceinline__ FinJob to_global(FinJob j) {
+  j.partial = gmem(j.partial);
+  j.st = gmem(j.st);
+  return j;
+}
+
+__global__ void __launch_bounds__(kBlock) k_finalize(const FinJob* __restrict__ jobs) {
+  const FinJob J = to_global(jobs[blockIdx.x]);
+  DevState* st = J.st;
   if (st->done) return;
   double v = 0.0;
-  for (long q = threadIdx.x; q < count; q += kBlock) v += partial[q];
+  for (long q = threadIdx.x; q < J.count; q += kBlock) v += J.partial[q];
   const double s = block_sum(v);
   if (threadIdx.x == 0) {
     const double res = sqrt(s);
     const double rel = res / st->fnorm;
     st->rel = rel;
     if (st->iter == 0) st->res0 = res;
-    if (!(rel == rel) || rel > 1e300 || (st->iter > 0 && res > 1e8 * st->res0 && res > 1e8 * st->fnorm * tol)) {
+    if (!(rel == rel) || rel > 1e300 || (st->iter > 0 && res > 1e8 * st->res0 && res > 1e8 * st->fnorm * J.tol)) {
       st->done = 2;
-    } else if (rel <= tol) {
+    } else if (rel <= J.tol) {
       st->done = 1;
-    } else if (st->iter >= max_iter) {
+    } else if (st->iter >= J.max_iter) {
       st->done = 3;
     } else {
       st->iter = st->iter + 1;
@@ -355,197 +329,148 @@ __device__ __forceinline__ SlabOp<TC> level_op(const LevelOp& L, int s) {
   return load_op<TC>((const TC*)L.sig, (const TC*)L.c, so, L.R);
 }
 
-// x = omega_J D^{-1} b  (first smoothing sweep from a zero guess)
-template <int D, typename TS, typename TC>
-__global__ void __launch_bounds__(kBlock) k_jacobi0(Geom g, LevelOp L, TC omega, const TS* __restrict__ b,
-                                                    TS* __restrict__ x, const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
-  const int s = slab_index();
-  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
-  if (s >= L.S || i >= g.npts) return;
-  int px, py, pz;
-  decode<D>(i, g.n, px, py, pz);
-  const SlabOp<TC> op = level_op<TC>(L, s);
-  const TC dg = diag_at<D, TC>(px, py, pz, g, (const TC*)L.kap, op, L.R);
-  const long o = long(s) * g.npts + i;
-  st<TS, TC>(x, o, omega * ld<TC>(b, o) / dg);
-}
-
-// t = b - L x
-template <int D, typename TS, typename TC>
-__global__ void __launch_bounds__(kBlock) k_resid(Geom g, LevelOp L, const TS* __restrict__ b,
-                                                  const TS* __restrict__ x, TS* __restrict__ t,
-                                                  const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
-  const int s = slab_index();
-  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
-  if (s >= L.S || i >= g.npts) return;
-  int px, py, pz;
-  decode<D>(i, g.n, px, py, pz);
-  const SlabOp<TC> op = level_op<TC>(L, s);
-  const TS* xs = x + long(s) * g.npts;
-  TC dg, off;
-  stencil<D, TC>(xs, i, px, py, pz, g, (const TC*)L.kap, op, L.R, dg, off);
-  const long o = long(s) * g.npts + i;
-  st<TS, TC>(t, o, ld<TC>(b, o) - (dg * ld<TC>(xs, i) - off));
-}
-
-// Epilogue of the last smoothing sweep: write out, or add into a float64 vector.
+// Epilogue of the last smoothing sweep: write out, or add it into a float64 vector.
 enum Epi { EPI_STORE = 0, EPI_ADD64 = 1 };
 
-// out = x + omega_J D^{-1} (b - L x)
-template <int D, typename TS, typename TC, int EPI>
-__global__ void __launch_bounds__(kBlock) k_jacobi(Geom g, LevelOp L, TC omega, const TS* __restrict__ b,
-                                                   const TS* __restrict__ x, TS* __restrict__ out,
-                                                   double* __restrict__ acc64, const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
-  const int s = slab_index();
-  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
-  if (s >= L.S || i >= g.npts) return;
-  int px, py, pz;
-  decode<D>(i, g.n, px, py, pz);
-  const SlabOp<TC> op = level_op<TC>(L, s);
-  const TS* xs = x + long(s) * g.npts;
-  TC dg, off;
-  stencil<D, TC>(xs, i, px, py, pz, g, (const TC*)L.kap, op, L.R, dg, off);
-  const long o = long(s) * g.npts + i;
-  const TC xc = ld<TC>(xs, i);
-  const TC v = xc + omega * (ld<TC>(b, o) - (dg * xc - off)) / dg;
-  if (EPI == EPI_STORE) st<TS, TC>(out, o, v);
-  else acc64[o] += double(v);
-}
+// ---------------------------------------------------------------------------
+// merged launches
+//
+// A launch serves one or several independent problems (a batch).  Each
+// problem's share is a job: its first block index in the launch, its sizes,
+// operator rows, buffers and stop flag.  A block finds its job by binary
+// search over the first-block indices (uniform, scalar work), so problems of
+// different sizes run in one launch.
+// ---------------------------------------------------------------------------
+struct TileJob {        // multigrid level kernels and the tile operator
+  long block0;
+  int tiles;            // spatial tiles per slab
+  int sb;               // slabs per block
+  Geom gf, gc;          // level (gc: next coarser level)
+  LevelOp op;
+  const void* b;        // input (TS)
+  const void* e;        // coarse correction (TS)
+  void* out;            // output (TS)
+  double* acc64;        // float64 target of EPI_ADD64
+  const int* state;     // the problem's stop flag
+};
 
-// Full-weighting restriction: coarse point <- tensor (1/4,1/2,1/4) of fine points.
-template <int D, typename TS, typename TC>
-__global__ void __launch_bounds__(kBlock) k_restrict(Geom gf, Geom gc, int S, const TS* __restrict__ t,
-                                                     TS* __restrict__ bc, const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
-  const int s = slab_index();
-  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
-  if (s >= S || i >= gc.npts) return;
-  int cx, cy, cz;
-  decode<D>(i, gc.n, cx, cy, cz);
-  const int nf = gf.n;
-  // coarse interior index I (0-based) <-> fine 0-based index 2I+1
-  const int fx = 2 * cx + 1, fy = 2 * cy + 1, fz = 2 * cz + 1;
-  const TS* ts = t + long(s) * gf.npts;
-  const TC w[3] = {TC(0.25), TC(0.5), TC(0.25)};
-  TC acc = 0;
-  for (int dz = (D >= 3 ? -1 : 0); dz <= (D >= 3 ? 1 : 0); ++dz)
-    for (int dy = (D >= 2 ? -1 : 0); dy <= (D >= 2 ? 1 : 0); ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        TC wt = w[dx + 1];
-        if (D >= 2) wt *= w[dy + 1];
-        if (D >= 3) wt *= w[dz + 1];
-        const long fi = (D == 1) ? long(fx + dx)
-                        : (D == 2) ? long(fy + dy) * nf + fx + dx
-                                   : (long(fz + dz) * nf + fy + dy) * nf + fx + dx;
-        acc += wt * ld<TC>(ts, fi);
-      }
-  st<TS, TC>(bc, long(s) * gc.npts + i, acc);
-}
+struct PointJob {       // single-node coarsest levels and exact 1-D solves
+  long block0;
+  long total;           // slabs * points (coarsest) or slabs (1-D solve)
+  Geom g;
+  LevelOp op;
+  const void* b;
+  void* out;
+  double* acc64;
+  void* scratch;
+  const int* state;
+};
 
-// x += P e  (multilinear interpolation; zero on the boundary)
-template <int D, typename TS, typename TC>
-__global__ void __launch_bounds__(kBlock) k_prolong_add(Geom gf, Geom gc, int S, const TS* __restrict__ e,
-                                                        TS* __restrict__ x, const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
-  const int s = slab_index();
-  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
-  if (s >= S || i >= gf.npts) return;
-  int fx, fy, fz;
-  decode<D>(i, gf.n, fx, fy, fz);
-  const int nc = gc.n;
-  const TS* es = e + long(s) * gc.npts;
-  // along one axis, fine 1-based node j = f+1: even j -> coarse j/2 (weight 1);
-  // odd j -> coarse (j-1)/2 and (j+1)/2 (weight 1/2); coarse 1-based 0 and nc+1 are boundary.
-  int lo[3], cnt[3];
-  int f[3] = {fx, fy, fz};
-  for (int a = 0; a < D; ++a) {
-    const int j = f[a] + 1;
-    if ((j & 1) == 0) { lo[a] = j / 2; cnt[a] = 1; }
-    else { lo[a] = (j - 1) / 2; cnt[a] = 2; }
+struct TimeJob {        // transforms along the time axis
+  long block0;
+  long npts;
+  int N;
+  int bx;               // column blocks (dense transform)
+  const void* tw;       // FFT twiddles (2N)
+  const void* tw4;      // quarter-wave twiddles (2N)
+  const void* T;        // dense matrix (N x N)
+  const void* in;
+  void* out;
+  double* acc64;
+  double alpha;
+  const int* state;
+};
+
+__device__ __forceinline__ LevelOp to_global(LevelOp L) {
+  L.kap = gmem(L.kap);
+  L.sig = gmem(L.sig);
+  L.c = gmem(L.c);
+  return L;
+}
+__device__ __forceinline__ TileJob to_global(TileJob j) {
+  j.op = to_global(j.op);
+  j.b = gmem(j.b);
+  j.e = gmem(j.e);
+  j.out = gmem(j.out);
+  j.acc64 = gmem(j.acc64);
+  j.state = gmem(j.state);
+  return j;
+}
+__device__ __forceinline__ PointJob to_global(PointJob j) {
+  j.op = to_global(j.op);
+  j.b = gmem(j.b);
+  j.out = gmem(j.out);
+  j.acc64 = gmem(j.acc64);
+  j.scratch = gmem(j.scratch);
+  j.state = gmem(j.state);
+  return j;
+}
+__device__ __forceinline__ TimeJob to_global(TimeJob j) {
+  j.tw = gmem(j.tw);
+  j.tw4 = gmem(j.tw4);
+  j.T = gmem(j.T);
+  j.in = gmem(j.in);
+  j.out = gmem(j.out);
+  j.acc64 = gmem(j.acc64);
+  j.state = gmem(j.state);
+  return j;
+}
+template <typename J>
+__device__ __forceinline__ int find_job(const J* __restrict__ jobs, int njobs) {
+  int lo = 0, hi = njobs - 1;
+  const long b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
   }
-  TC acc = 0;
-  for (int az = 0; az < (D >= 3 ? cnt[2] : 1); ++az)
-    for (int ay = 0; ay < (D >= 2 ? cnt[1] : 1); ++ay)
-      for (int ax = 0; ax < cnt[0]; ++ax) {
-        const int cx = lo[0] + ax;
-        const int cy = D >= 2 ? lo[1] + ay : 1;
-        const int cz = D >= 3 ? lo[2] + az : 1;
-        if (cx < 1 || cx > nc) continue;
-        if (D >= 2 && (cy < 1 || cy > nc)) continue;
-        if (D >= 3 && (cz < 1 || cz > nc)) continue;
-        TC wt = (cnt[0] == 2 ? TC(0.5) : TC(1));
-        if (D >= 2) wt *= (cnt[1] == 2 ? TC(0.5) : TC(1));
-        if (D >= 3) wt *= (cnt[2] == 2 ? TC(0.5) : TC(1));
-        const long ci = (D == 1) ? long(cx - 1)
-                        : (D == 2) ? long(cy - 1) * nc + (cx - 1)
-                                   : (long(cz - 1) * nc + (cy - 1)) * nc + (cx - 1);
-        acc += wt * ld<TC>(es, ci);
-      }
-  const long o = long(s) * gf.npts + i;
-  st<TS, TC>(x, o, ld<TC>(x, o) + acc);
+  return lo;
 }
 
-// Coarsest level (one node): x = b / D
-template <int D, typename TS, typename TC>
-__global__ void __launch_bounds__(kBlock) k_coarsest(Geom g, LevelOp L, const TS* __restrict__ b,
-                                                     TS* __restrict__ x, const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
-  const long q = long(blockIdx.x) * kBlock + threadIdx.x;  // slab * npts + i
-  if (q >= long(L.S) * g.npts) return;
+// Coarsest level (one node): x = b / D, stored or added into a float64 vector
+template <int D, typename TS, typename TC, int EPI>
+__global__ void __launch_bounds__(kBlock) k_coarsest(const PointJob* __restrict__ jobs, int njobs) {
+  const PointJob J = to_global(jobs[find_job(jobs, njobs)]);
+  if (J.state && done_flag(J.state)) return;
+  const long q = (long(blockIdx.x) - J.block0) * kBlock + threadIdx.x;  // slab * npts + i
+  if (q >= J.total) return;
+  const Geom g = J.g;
   const int s = int(q / g.npts);
   const long i = q - long(s) * g.npts;
   int px, py, pz;
   decode<D>(i, g.n, px, py, pz);
-  const SlabOp<TC> op = level_op<TC>(L, s);
-  const TC dg = diag_at<D, TC>(px, py, pz, g, (const TC*)L.kap, op, L.R);
-  st<TS, TC>(x, q, ld<TC>(b, q) / dg);
+  const SlabOp<TC> op = level_op<TC>(J.op, s);
+  const TC dg = diag_at<D, TC>(px, py, pz, g, (const TC*)J.op.kap, op, J.op.R);
+  const TC v = ld<TC>((const TS*)J.b, q) / dg;
+  if (EPI == EPI_STORE) st<TS, TC>((TS*)J.out, q, v);
+  else J.acc64[q] += double(v);
 }
 
-// y = L x on a level (used for the middle reference operator of the H-blocks).
-template <int D, typename TS, typename TC>
-__global__ void __launch_bounds__(kBlock) k_apply_level(Geom g, LevelOp L, const TS* __restrict__ x,
-                                                        TS* __restrict__ y, const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
-  const int s = slab_index();
-  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
-  if (s >= L.S || i >= g.npts) return;
-  int px, py, pz;
-  decode<D>(i, g.n, px, py, pz);
-  const SlabOp<TC> op = level_op<TC>(L, s);
-  const TS* xs = x + long(s) * g.npts;
-  TC dg, off;
-  stencil<D, TC>(xs, i, px, py, pz, g, (const TC*)L.kap, op, L.R, dg, off);
-  st<TS, TC>(y, long(s) * g.npts + i, dg * ld<TC>(xs, i) - off);
-}
-
-// Exact 1-D solve per slab (Thomas algorithm), one thread per slab.
+// Exact 1-D solve per slab (Thomas algorithm), one thread per slab, 64 per block.
 template <typename TS, typename TC, int EPI>
-__global__ void __launch_bounds__(64) k_tridiag(Geom g, LevelOp L, const TS* __restrict__ b, TS* __restrict__ out,
-                                                double* __restrict__ acc64, TC* __restrict__ scratch,
-                                                const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
-  const int s = blockIdx.x * 64 + threadIdx.x;
+__global__ void __launch_bounds__(64) k_tridiag(const PointJob* __restrict__ jobs, int njobs) {
+  const PointJob J = to_global(jobs[find_job(jobs, njobs)]);
+  if (J.state && done_flag(J.state)) return;
+  const int s = int((long(blockIdx.x) - J.block0) * 64 + threadIdx.x);
+  const LevelOp L = J.op;
   if (s >= L.S) return;
+  const Geom g = J.g;
   const int n = g.n;
   const SlabOp<TC> op = level_op<TC>(L, s);
   const TC* kap = (const TC*)L.kap;
-  TC* cp = scratch + long(s) * n;   // modified super-diagonal
-  const TS* bs = b + long(s) * n;
-  // row i (0-based interior), node i+1: diag = sigma + w_left + w_right, off = -w
+  TC* scratch = (TC*)J.scratch;
+  TC* cp = scratch + long(s) * n;                     // modified super-diagonal
+  TC* yp = scratch + long(L.S) * n + long(s) * n;     // modified right-hand side
+  const TS* bs = (const TS*)J.b + long(s) * n;
+  // row i (0-based interior), node i+1: diag = sigma + w_left + w_right, off-diagonals -w
   TC wl = kmix(kap, g.nnodes, 0, op, L.R) + kmix(kap, g.nnodes, 1, op, L.R);
   TC prev_d = 0, prev_y = 0;
-  // forward sweep: store c'_i in scratch, y'_i in out (as TC via acc in registers -> store in TS buffer is lossy;
-  // keep y' in a second half of scratch)
-  TC* yp = scratch + long(L.S) * n + long(s) * n;
   for (int i = 0; i < n; ++i) {
     const TC kc = kmix(kap, g.nnodes, i + 1, op, L.R);
     const TC wr = kc + kmix(kap, g.nnodes, i + 2, op, L.R);
     const TC dg = op.sigma + wl + wr;
-    const TC a = -wl;          // sub-diagonal (coupling to i-1)
-    const TC cup = -wr;        // super-diagonal (coupling to i+1)
+    const TC a = -wl;
+    const TC cup = -wr;
     TC denom = dg;
     TC rhs = ld<TC>(bs, i);
     if (i > 0) {
@@ -562,8 +487,8 @@ __global__ void __launch_bounds__(64) k_tridiag(Geom g, LevelOp L, const TS* __r
   for (int i = n - 1; i >= 0; --i) {
     xv = yp[i] - (i < n - 1 ? cp[i] * xv : TC(0));
     const long o = long(s) * n + i;
-    if (EPI == EPI_STORE) st<TS, TC>(out, o, xv);
-    else acc64[o] += double(xv);
+    if (EPI == EPI_STORE) st<TS, TC>((TS*)J.out, o, xv);
+    else J.acc64[o] += double(xv);
   }
 }
 
@@ -572,16 +497,20 @@ __global__ void __launch_bounds__(64) k_tridiag(Geom g, LevelOp L, const TS* __r
 // ---------------------------------------------------------------------------
 constexpr int kDstKpt = 8;   // outputs per thread
 
-template <typename TSi, typename TSo, typename TC, int ACC64>
-__global__ void __launch_bounds__(kBlock) k_time_dense(long npts, int N, const TC* __restrict__ T,
-                                                       const TSi* __restrict__ in, TSo* __restrict__ out,
-                                                       double* __restrict__ out64, double alpha,
-                                                       const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
+template <typename TS, typename TC, int ACC64>
+__global__ void __launch_bounds__(kBlock) k_time_dense(const TimeJob* __restrict__ jobs, int njobs) {
+  const TimeJob J = to_global(jobs[find_job(jobs, njobs)]);
+  if (J.state && done_flag(J.state)) return;
+  const long lb = long(blockIdx.x) - J.block0;
+  const int bxi = int(lb % J.bx), byi = int(lb / J.bx);
+  const long npts = J.npts;
+  const int N = J.N;
+  const TC* T = (const TC*)J.T;
+  const TS* in = (const TS*)J.in;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const long i = long(blockIdx.x) * 64 + lane;
-  const int k0 = (blockIdx.y * 4 + wv) * kDstKpt;
+  const long i = long(bxi) * 64 + lane;
+  const int k0 = (byi * 4 + wv) * kDstKpt;
   if (k0 >= N) return;
   TC acc[kDstKpt];
 #pragma unroll
@@ -597,8 +526,8 @@ __global__ void __launch_bounds__(kBlock) k_time_dense(long npts, int N, const T
     for (int q = 0; q < kDstKpt; ++q) {
       if (k0 + q >= N) break;
       const long o = long(k0 + q) * npts + i;
-      if (ACC64) out64[o] += alpha * double(acc[q]);
-      else st<TSo, TC>(out, o, TC(alpha) * acc[q]);
+      if (ACC64) J.acc64[o] += J.alpha * double(acc[q]);
+      else st<TS, TC>((TS*)J.out, o, TC(J.alpha) * acc[q]);
     }
   }
 }
@@ -677,11 +606,13 @@ __device__ __forceinline__ void fft_stage(TC* re, TC* im, const TC* twr, const T
 
 // tw: 2N values (re[0..N), im[0..N)) of w_N^m; tw4: same for w_{4N}^m.
 template <typename TS, typename TC, int MODE, int ACC64>
-__global__ void __launch_bounds__(kBlock) k_time_fft(long npts, int N, int C, const TC* __restrict__ tw,
-                                                     const TC* __restrict__ tw4, const TS* __restrict__ in,
-                                                     TS* __restrict__ out, double* __restrict__ out64,
-                                                     double alpha, const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
+__device__ __forceinline__ void time_fft_body(const TimeJob& J, int C, const TC* __restrict__ tw,
+                                              const TC* __restrict__ tw4, const TS* __restrict__ in,
+                                              TS* __restrict__ out, double* __restrict__ out64) {
+  const long npts = J.npts;
+  const int N = J.N;
+  const double alpha = J.alpha;
+  const long lb = long(blockIdx.x) - J.block0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TC* re = reinterpret_cast<TC*>(smem_raw);
   TC* im = re + N * C;
@@ -696,7 +627,7 @@ __global__ void __launch_bounds__(kBlock) k_time_fft(long npts, int N, int C, co
   }
   __syncthreads();
   const int col = t % C, jg = t / C, G = kBlock / C;
-  const long i = long(blockIdx.x) * C + col;
+  const long i = lb * C + col;
   const bool valid = (jg < G) && (i < npts);
   for (int n = jg; n < N; n += G) {
     const TC v = valid ? ld<TC>(in, long(n) * npts + i) : TC(0);
@@ -735,6 +666,13 @@ __global__ void __launch_bounds__(kBlock) k_time_fft(long npts, int N, int C, co
     if (ACC64) out64[o] += alpha * double(v);
     else st<TS, TC>(out, o, TC(alpha) * v);
   }
+}
+
+template <typename TS, typename TC, int MODE, int ACC64>
+__global__ void __launch_bounds__(kBlock) k_time_fft(const TimeJob* __restrict__ jobs, int njobs, int C) {
+  const TimeJob J = to_global(jobs[find_job(jobs, njobs)]);
+  if (J.state && done_flag(J.state)) return;
+  time_fft_body<TS, TC, MODE, ACC64>(J, C, (const TC*)J.tw, (const TC*)J.tw4, (const TS*)J.in, (TS*)J.out, J.acc64);
 }
 
 // ---------------------------------------------------------------------------
@@ -803,18 +741,19 @@ __device__ __forceinline__ void dft_reg(TC (&xr)[P], TC (&xi)[P]) {
 // tw / tw4: 2N tables as in k_time_fft.  Dynamic LDS: N * C * sizeof(TC)
 // (real and imaginary parts pass through it one after the other).
 template <typename TS, typename TC, int MODE, int ACC64, int L1, int L2>
-__global__ void __launch_bounds__(kBlock) k_time_fft2(long npts, const TC* __restrict__ tw,
-                                                      const TC* __restrict__ tw4, const TS* __restrict__ in,
-                                                      TS* __restrict__ out, double* __restrict__ out64, double alpha,
-                                                      const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
+__device__ __forceinline__ void time_fft2_body(const TimeJob& J, const TC* __restrict__ tw,
+                                               const TC* __restrict__ tw4, const TS* __restrict__ in,
+                                               TS* __restrict__ out, double* __restrict__ out64) {
+  const long npts = J.npts;
+  const double alpha = J.alpha;
+  const long lb = long(blockIdx.x) - J.block0;
   constexpr int N1 = 1 << L1, N2 = 1 << L2, N = N1 * N2;
   constexpr int C = kBlock / N1;             // columns per block
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TC* lds = reinterpret_cast<TC*>(smem_raw);  // [k1][n2][col]
   const int t = threadIdx.x;
   const int col = t % C, j = t / C;          // j = n2 (step 1, if < N2) or k1 (step 3)
-  const long i = long(blockIdx.x) * C + col;
+  const long i = lb * C + col;
   const bool valid = i < npts;
   TC xr[N1], xi[N1];
   const bool act1 = j < N2;
@@ -885,6 +824,13 @@ __global__ void __launch_bounds__(kBlock) k_time_fft2(long npts, const TC* __res
     if (ACC64) out64[o] += alpha * double(v);
     else st<TS, TC>(out, o, TC(alpha) * v);
   }
+}
+
+template <typename TS, typename TC, int MODE, int ACC64, int L1, int L2>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_time_fft2(const TimeJob* __restrict__ jobs, int njobs) {
+  const TimeJob J = to_global(jobs[find_job(jobs, njobs)]);
+  if (J.state && done_flag(J.state)) return;
+  time_fft2_body<TS, TC, MODE, ACC64, L1, L2>(J, (const TC*)J.tw, (const TC*)J.tw4, (const TS*)J.in, (TS*)J.out, J.acc64);
 }
 
 // elementwise helpers

@@ -213,10 +213,10 @@ __host__ __device__ inline long tiles_for(int n) {
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void tile_origin(int n, int& tx, int& ty, int& tz) {
+__device__ __forceinline__ void tile_origin(int n, int tile, int& tx, int& ty, int& tz) {
   const int ntx = (n + T::X - 1) / T::X;
   const int nty = D >= 2 ? (n + T::Y - 1) / T::Y : 1;
-  int t = blockIdx.x;
+  int t = tile;
   tx = t % ntx;
   t /= ntx;
   ty = D >= 2 ? t % nty : 0;
@@ -289,9 +289,45 @@ struct Regs {
   }
 };
 
-__device__ __forceinline__ void slab_run(int S, int sb, int& s0, int& s1) {
-  s0 = slab_index() * sb;
-  s1 = min(S, s0 + sb);
+// the block's job (copied to scalar registers), tile index and slab run [s0, s1)
+template <typename J>
+__device__ __forceinline__ J job_tile_run(const J* __restrict__ jobs, int njobs, int S, int& tile, int& s0, int& s1) {
+  const J job = to_global(jobs[find_job(jobs, njobs)]);
+  const int lb = int(long(blockIdx.x) - job.block0);
+  tile = lb % job.tiles;
+  s0 = (lb / job.tiles) * job.sb;
+  s1 = min(S, s0 + job.sb);
+  return job;
+}
+
+// residual kernels: one job per problem
+struct ResidJob {
+  long block0;
+  int tiles;
+  int sb;
+  Geom g;
+  TimeOp t;
+  double tau;
+  const double* u;
+  const double* p;
+  const double* F;
+  const double* u0;
+  void* r;
+  double* partial;      // one entry per block of the job
+  const int* state;
+};
+
+__device__ __forceinline__ ResidJob to_global(ResidJob j) {
+  j.t.kap = gmem(j.t.kap);
+  j.t.cA = gmem(j.t.cA);
+  j.u = gmem(j.u);
+  j.p = gmem(j.p);
+  j.F = gmem(j.F);
+  j.u0 = gmem(j.u0);
+  j.r = gmem(j.r);
+  j.partial = gmem(j.partial);
+  j.state = gmem(j.state);
+  return j;
 }
 
 // ---------------------------------------------------------------------------
@@ -299,9 +335,8 @@ __device__ __forceinline__ void slab_run(int S, int sb, int& s0, int& s1) {
 //   x1 = omega D^{-1} b,  r = b - L x1 = (1 - omega) b + sum_nb w x1_nb,  bc = R r
 // ---------------------------------------------------------------------------
 template <int D, typename TS, typename TC, int RM>
-__global__ void __launch_bounds__(kBlock) k_mg_down(Geom gf, Geom gc, LevelOp L, TC omega, const TS* __restrict__ b,
-                                                    TS* __restrict__ bc, int sb, const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
+__device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0, int s1, TC omega,
+                                             const TS* __restrict__ b, TS* __restrict__ bc) {
   using T = DownTile<D>;
   using KB = Box<D, 2 * T::X + 5, 2 * T::Y + 5, 2 * T::Z + 5>;
   using XB = Box<D, 2 * T::X + 3, 2 * T::Y + 3, 2 * T::Z + 3>;
@@ -311,12 +346,13 @@ __global__ void __launch_bounds__(kBlock) k_mg_down(Geom gf, Geom gc, LevelOp L,
   __shared__ TC sx[XB::size];
   __shared__ TC sb_[XB::size];
   __shared__ TC sr[RB::size];
-  int s0, s1;
-  slab_run(L.S, sb, s0, s1);
+  const LevelOp L = J.op;
+  s1 = min(s1, L.S);
   if (s0 >= s1) return;
+  const Geom gf = J.gf, gc = J.gc;
   const int nf = gf.n, nc = gc.n;
   int tx, ty, tz;
-  tile_origin<D, T>(nc, tx, ty, tz);
+  tile_origin<D, T>(nc, tile, tx, ty, tz);
   // first coarse node of the tile (1-based); the fine node of coarse I is 2I
   const int Ix = tx * T::X + 1, Iy = D >= 2 ? ty * T::Y + 1 : 1, Iz = D >= 3 ? tz * T::Z + 1 : 1;
   const int rx = 2 * Ix - 1, ry = D >= 2 ? 2 * Iy - 1 : 1, rz = D >= 3 ? 2 * Iz - 1 : 1;   // r-box origin
@@ -382,16 +418,23 @@ __global__ void __launch_bounds__(kBlock) k_mg_down(Geom gf, Geom gc, LevelOp L,
   }
 }
 
+template <int D, typename TS, typename TC, int RM>
+__global__ void __launch_bounds__(kBlock) k_mg_down(const TileJob* __restrict__ jobs, int njobs, TC omega) {
+  int tile, s0, s1;
+  const TileJob J = job_tile_run(jobs, njobs, 1 << 30, tile, s0, s1);
+  if (J.state && done_flag(J.state)) return;
+  mg_down_body<D, TS, TC, RM>(J, tile, s0, s1, omega, (const TS*)J.b, (TS*)J.out);
+}
+
 // ---------------------------------------------------------------------------
 // multigrid: coarse correction and post-smoothing
 //   x2 = omega D^{-1} b + P e,   x = (1 - omega) x2 + omega D^{-1} (b + sum_nb w x2_nb)
 // epilogue: store x (TS) or add it into a float64 vector
 // ---------------------------------------------------------------------------
 template <int D, typename TS, typename TC, int RM, int EPI>
-__global__ void __launch_bounds__(kBlock) k_mg_up(Geom gf, Geom gc, LevelOp L, TC omega, const TS* __restrict__ b,
-                                                  const TS* __restrict__ e, TS* __restrict__ out,
-                                                  double* __restrict__ acc64, int sb, const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
+__device__ __forceinline__ void mg_up_body(const TileJob& J, int tile, int s0, int s1, TC omega,
+                                           const TS* __restrict__ b, const TS* __restrict__ e, TS* __restrict__ out,
+                                           double* __restrict__ acc64) {
   using T = UpTile<D>;
   using KB = Box<D, T::X + 4, T::Y + 4, T::Z + 4>;
   using XB = Box<D, T::X + 2, T::Y + 2, T::Z + 2>;
@@ -401,12 +444,13 @@ __global__ void __launch_bounds__(kBlock) k_mg_up(Geom gf, Geom gc, LevelOp L, T
   __shared__ TC sx[XB::size];
   __shared__ TC sb_[XB::size];
   __shared__ TC se[EB::size];
-  int s0, s1;
-  slab_run(L.S, sb, s0, s1);
+  const LevelOp L = J.op;
+  s1 = min(s1, L.S);
   if (s0 >= s1) return;
+  const Geom gf = J.gf, gc = J.gc;
   const int nf = gf.n, nc = gc.n;
   int tx, ty, tz;
-  tile_origin<D, T>(nf, tx, ty, tz);
+  tile_origin<D, T>(nf, tile, tx, ty, tz);
   const int jx0 = tx * T::X + 1, jy0 = D >= 2 ? ty * T::Y + 1 : 1, jz0 = D >= 3 ? tz * T::Z + 1 : 1;
   const int xx = jx0 - 1, xy = D >= 2 ? jy0 - 1 : 1, xz = D >= 3 ? jz0 - 1 : 1;   // x2-box origin
   const int ex = xx / 2, ey = D >= 2 ? xy / 2 : 1, ez = D >= 3 ? xz / 2 : 1;      // first coarse node
@@ -480,25 +524,33 @@ __global__ void __launch_bounds__(kBlock) k_mg_up(Geom gf, Geom gc, LevelOp L, T
   }
 }
 
+template <int D, typename TS, typename TC, int RM, int EPI>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RM <= 2 ? 4 : 3))) k_mg_up(const TileJob* __restrict__ jobs, int njobs, TC omega) {
+  int tile, s0, s1;
+  const TileJob J = job_tile_run(jobs, njobs, 1 << 30, tile, s0, s1);
+  if (J.state && done_flag(J.state)) return;
+  mg_up_body<D, TS, TC, RM, EPI>(J, tile, s0, s1, omega, (const TS*)J.b, (const TS*)J.e, (TS*)J.out, J.acc64);
+}
+
 // ---------------------------------------------------------------------------
 // y = L x (tile version; the middle reference operator of the H-blocks,
 // whose coefficients are the same for every slab)
 // ---------------------------------------------------------------------------
 template <int D, typename TS, typename TC, int RM>
-__global__ void __launch_bounds__(kBlock) k_apply_tile(Geom g, LevelOp L, const TS* __restrict__ xv,
-                                                       TS* __restrict__ yv, int sb, const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
+__device__ __forceinline__ void apply_tile_body(const TileJob& J, int tile, int s0, int s1, const TS* __restrict__ xv,
+                                                TS* __restrict__ yv) {
   using T = UpTile<D>;
   using KB = Box<D, T::X + 2, T::Y + 2, T::Z + 2>;
   using TB = Box<D, T::X, T::Y, T::Z>;
   __shared__ TC sk[KB::size];
   __shared__ TC sx[KB::size];
-  int s0, s1;
-  slab_run(L.S, sb, s0, s1);
+  const LevelOp L = J.op;
+  s1 = min(s1, L.S);
   if (s0 >= s1) return;
+  const Geom g = J.gf;
   const int n = g.n;
   int tx, ty, tz;
-  tile_origin<D, T>(n, tx, ty, tz);
+  tile_origin<D, T>(n, tile, tx, ty, tz);
   const int jx0 = tx * T::X + 1, jy0 = D >= 2 ? ty * T::Y + 1 : 1, jz0 = D >= 3 ? tz * T::Z + 1 : 1;
   const int ox = jx0 - 1, oy = D >= 2 ? jy0 - 1 : 1, oz = D >= 3 ? jz0 - 1 : 1;
   TC xn[nit<KB>()];
@@ -535,6 +587,14 @@ __global__ void __launch_bounds__(kBlock) k_apply_tile(Geom g, LevelOp L, const 
   }
 }
 
+template <int D, typename TS, typename TC, int RM>
+__global__ void __launch_bounds__(kBlock) k_apply_tile(const TileJob* __restrict__ jobs, int njobs) {
+  int tile, s0, s1;
+  const TileJob J = job_tile_run(jobs, njobs, 1 << 30, tile, s0, s1);
+  if (J.state && done_flag(J.state)) return;
+  apply_tile_body<D, TS, TC, RM>(J, tile, s0, s1, (const TS*)J.b, (TS*)J.out);
+}
+
 // ---------------------------------------------------------------------------
 // time-global residuals (float64), tile versions marching forward in time
 //   WHICH = 0 (a1):  r = (u_s - u_{s-1}) - tau A_s p_s - f_s
@@ -544,25 +604,25 @@ __global__ void __launch_bounds__(kBlock) k_apply_tile(Geom g, LevelOp L, const 
 // in registers and serve as u_{s-1} of the next slab.
 // ---------------------------------------------------------------------------
 template <int D, typename TS, int WHICH, int RM>
-__global__ void __launch_bounds__(kBlock) k_resid_tile(Geom g, TimeOp t, double tau, const double* __restrict__ u,
-                                                       const double* __restrict__ p, const double* __restrict__ F,
-                                                       const double* __restrict__ u0, TS* __restrict__ r,
-                                                       double* __restrict__ partial, int sb,
-                                                       const int* __restrict__ state) {
-  if (state && done_flag(state)) return;
+__device__ __forceinline__ void resid_tile_body(const ResidJob& J, int tile, int s0, int s1,
+                                                const double* __restrict__ u, const double* __restrict__ p,
+                                                const double* __restrict__ F, const double* __restrict__ u0,
+                                                TS* __restrict__ r, double* __restrict__ partial) {
   using T = UpTile<D>;
   using KB = Box<D, T::X + 2, T::Y + 2, T::Z + 2>;
   using TB = Box<D, T::X, T::Y, T::Z>;
   constexpr int NT = nit<TB>();
   __shared__ double sk[KB::size];
   __shared__ double sx[KB::size];
-  int s0, s1;
-  slab_run(t.N, sb, s0, s1);
+  const TimeOp t = J.t;
+  s1 = min(s1, t.N);
+  const Geom g = J.g;
+  const double tau = J.tau;
   double e2 = 0.0;
   if (s0 < s1) {
     const int n = g.n;
     int tx, ty, tz;
-    tile_origin<D, T>(n, tx, ty, tz);
+    tile_origin<D, T>(n, tile, tx, ty, tz);
     const int jx0 = tx * T::X + 1, jy0 = D >= 2 ? ty * T::Y + 1 : 1, jz0 = D >= 3 ? tz * T::Z + 1 : 1;
     const int ox = jx0 - 1, oy = D >= 2 ? jy0 - 1 : 1, oz = D >= 3 ? jz0 - 1 : 1;
     const double* X = WHICH == 0 ? p : u;   // operand of the stencil
@@ -649,8 +709,16 @@ __global__ void __launch_bounds__(kBlock) k_resid_tile(Geom g, TimeOp t, double 
   }
   if (WHICH == 1) {
     const double bs = block_sum(e2);
-    if (threadIdx.x == 0) partial[long(slab_index()) * gridDim.x + blockIdx.x] = bs;
+    if (threadIdx.x == 0) partial[long(blockIdx.x) - J.block0] = bs;
   }
+}
+
+template <int D, typename TS, int WHICH, int RM>
+__global__ void __launch_bounds__(kBlock) k_resid_tile(const ResidJob* __restrict__ jobs, int njobs) {
+  int tile, s0, s1;
+  const ResidJob J = job_tile_run(jobs, njobs, 1 << 30, tile, s0, s1);
+  if (J.state && done_flag(J.state)) return;
+  resid_tile_body<D, TS, WHICH, RM>(J, tile, s0, s1, J.u, J.p, J.F, J.u0, (TS*)J.r, J.partial);
 }
 
 }  // namespace stp

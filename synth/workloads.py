@@ -235,7 +235,8 @@ def small_problem(dim: int, n: int, N: int, seed: int = 7, T: float = 1.0, R: in
 
     kappa(t,x) = 1 + amp * sin(2 pi t + phi) * g(x) with g a rough random nodal
     field in [-1, 1] (R = 2 separable terms; R = 1 drops the second term and
-    uses kappa = 1 + amp sin(2 pi t + phi)).  kappa stays in [1-amp, 1+amp],
+    uses kappa = 1 + amp sin(2 pi t + phi); R = 3, 4 add R - 1 rough fields of
+    weight 1/(R-1) with time frequencies 1 .. R-1).  kappa stays in [1-amp, 1+amp],
     as in the paper-style workloads.  F and u0 are standard normal.
     """
     rng = np.random.default_rng(seed)
@@ -245,10 +246,16 @@ def small_problem(dim: int, n: int, N: int, seed: int = 7, T: float = 1.0, R: in
     if R == 1:
         kf = np.ones((1,) + shape)
         tc = (1.0 + amp * np.sin(2 * np.pi * t + phi))[None, :]
-    else:
+    elif R == 2:
         g = rng.uniform(-1.0, 1.0, size=shape)
         kf = np.stack([np.ones(shape), g])
         tc = np.stack([np.ones(N), amp * np.sin(2 * np.pi * t + phi)])
+    else:
+        # R - 1 rough fields with time frequencies 1 .. R-1, each scaled by 1/(R-1)
+        gs = [rng.uniform(-1.0, 1.0, size=shape) / (R - 1) for _ in range(R - 1)]
+        phis = [phi] + list(rng.uniform(0, 2 * np.pi, size=R - 2))
+        kf = np.stack([np.ones(shape)] + gs)
+        tc = np.stack([np.ones(N)] + [amp * np.sin(2 * np.pi * (r + 1) * t + phis[r]) for r in range(R - 1)])
     F = rng.standard_normal((N,) + (n,) * dim)
     u0 = rng.standard_normal((n,) * dim)
     return Problem(dim, n, N, T, kf, tc, F, u0, name=f"small{dim}d", seed=seed)
