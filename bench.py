@@ -94,6 +94,13 @@ def gpu_run(args):
                                 check_every=args.check_every)
         u = torch.zeros(shape, dtype=torch.float64, device=dev)
         p = torch.zeros(shape, dtype=torch.float64, device=dev)
+        tune = None
+        if not args.no_tune:
+            # the library's autotuner picks slabs per block and the time-transform path
+            heuristic = s.schedule()
+            t0 = time.perf_counter()
+            tune = s.autotune(reps=5, use_cache=False)
+            tune.update(sec=time.perf_counter() - t0, schedule=s.schedule(), heuristic=heuristic)
         # warmup
         s.solve(u, p)
         torch.cuda.synchronize()
@@ -102,6 +109,8 @@ def gpu_run(args):
         s = stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0,
                                 precision=prec, omega=args.omega, tol=0.0, max_iter=args.steps,
                                 check_every=args.check_every)
+        if tune is not None:
+            assert s.autotune(use_cache=True)["from_cache"]
         u.zero_()
         p.zero_()
         s.solve(u, p)                        # captures the iteration graph for (u, p)
@@ -115,7 +124,7 @@ def gpu_run(args):
         assert info["iters"] == args.steps, info
         sec = t1 - t0
         results[prec] = dict(sec=sec, ms_per_step=1e3 * sec / args.steps, value=dofs * args.steps / sec,
-                             device_ms=info["ms"])
+                             device_ms=info["ms"], autotune=tune)
         if prec == "f64":
             # per-kernel device times: a second timed region of the same --steps
             # iterations, launched eagerly with a HIP event pair around every launch
@@ -136,6 +145,8 @@ def gpu_run(args):
             s = stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0,
                                     precision=prec, omega=args.omega, tol=args.tol, max_iter=2000,
                                     check_every=args.check_every)
+            if tune is not None:
+                s.autotune(use_cache=True)
             u.zero_()
             p.zero_()
             torch.cuda.synchronize()
@@ -200,6 +211,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-tol", action="store_true")
     ap.add_argument("--only-f64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in schedule heuristic")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU time sharding is a design "
@@ -227,6 +239,7 @@ def main():
         "roofline": roof,
         "kernels_f64": table,
         "ms_per_step_eager_timed": r64.get("ms_per_step_eager_timed"),
+        "autotune_f64": r64.get("autotune"),
     }
     if "tol" in r64:
         out["time_to_tol_f64"] = r64["tol"]

@@ -178,6 +178,40 @@ stp_status stp_uzawa_solve(stp_ctx* ctx, double* u, double* p, stp_stats* st);
 
 void stp_destroy(stp_ctx* ctx);
 
+/* Autotuner (project-written).  Times, on the context's own buffers and
+ * stream, the candidate schedules of every merged launch of an iteration and
+ * keeps the fastest:
+ *   - slabs per block of each tile launch (residuals, the middle operator of
+ *     the H-blocks, and every multigrid down- and up-sweep level), as a power
+ *     of two times the built-in heuristic, within [1, 16];
+ *   - for every power-of-two step count N <= 4096, the time transform path:
+ *     two-step register FFT (4 <= N <= 256), Stockham LDS FFT with 1..16
+ *     columns per block (as LDS allows), or the dense transform (N <= 64).
+ * Each candidate is timed over reps launches (after one warm-up) with HIP
+ * events; a candidate replaces the current choice only when it is at least 2%
+ * faster.  The tuner allocates (and frees) two scratch vectors per problem for
+ * its launches, leaves the caller's data untouched, and invalidates the
+ * captured iteration graph (the next solve captures again).  The result is
+ * kept in a process-wide cache keyed by precision, dimension, spatial mode,
+ * coefficient rank and the (n, N, rank) of every problem; with use_cache != 0
+ * a cached schedule is applied without timing.  Iterates and results do not
+ * depend on the schedule: only how the work is split among blocks changes.
+ * rep (may be NULL) receives the number of knobs and candidates timed,
+ * whether the cache was used, and the device time of one eager iteration
+ * before and after tuning (0 when taken from the cache).
+ * Errors: EINVAL (NULL ctx), EUNSUPPORTED (spatial NONE), ENOMEM, EDEVICE. */
+typedef struct {
+  int knobs_tuned;
+  int candidates;
+  int from_cache;
+  double iter_ms_before;
+  double iter_ms_after;
+} stp_tune_report;
+stp_status stp_autotune(stp_ctx* ctx, int reps, int use_cache, stp_tune_report* rep);
+/* Human-readable schedule of the context (slabs per block per launch kind,
+ * transform path per step-count group); valid until the next call. */
+const char* stp_schedule_string(stp_ctx* ctx);
+
 /* Profiling aid.  While enabled, every kernel launch of the context is
  * bracketed by a pair of HIP events on the context's stream (a small
  * overhead per launch).  stp_timing_enable(ctx, 1) clears earlier records;

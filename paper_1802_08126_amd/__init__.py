@@ -27,10 +27,12 @@ from .binding import (  # noqa: F401
     load,
     stp_apply_operator,
     stp_apply_precond,
+    stp_autotune,
     stp_batch_size,
     stp_create,
     stp_create_batch,
     stp_destroy,
+    stp_schedule_string,
     stp_timing_enable,
     stp_timing_report,
     stp_uzawa_solve,

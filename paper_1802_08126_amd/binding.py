@@ -47,6 +47,11 @@ class stp_stats(C.Structure):
                 ("t_solve_ms", C.c_double), ("status", C.c_int)]
 
 
+class stp_tune_report(C.Structure):
+    _fields_ = [("knobs_tuned", C.c_int), ("candidates", C.c_int), ("from_cache", C.c_int),
+                ("iter_ms_before", C.c_double), ("iter_ms_after", C.c_double)]
+
+
 def lib_path() -> str:
     return _LIB_PATH
 
@@ -92,6 +97,10 @@ def load() -> C.CDLL:
     lib.stp_uzawa_solve_batch.restype = C.c_int
     lib.stp_batch_size.argtypes = [C.c_void_p]
     lib.stp_batch_size.restype = C.c_int
+    lib.stp_autotune.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(stp_tune_report)]
+    lib.stp_autotune.restype = C.c_int
+    lib.stp_schedule_string.argtypes = [C.c_void_p]
+    lib.stp_schedule_string.restype = C.c_char_p
     lib.stp_timing_enable.argtypes = [C.c_void_p, C.c_int]
     lib.stp_timing_enable.restype = C.c_int
     lib.stp_timing_count.argtypes = [C.c_void_p]
@@ -264,6 +273,18 @@ def stp_uzawa_solve(ctx, u, p):
     return status, st
 
 
+def stp_autotune(ctx, reps=5, use_cache=True):
+    """Tune the launch schedule of the context; returns the report as a dict."""
+    r = stp_tune_report()
+    _check(load().stp_autotune(ctx, int(reps), 1 if use_cache else 0, C.byref(r)), "stp_autotune")
+    return dict(knobs_tuned=r.knobs_tuned, candidates=r.candidates, from_cache=bool(r.from_cache),
+                iter_ms_before=r.iter_ms_before, iter_ms_after=r.iter_ms_after)
+
+
+def stp_schedule_string(ctx) -> str:
+    return load().stp_schedule_string(ctx).decode()
+
+
 def stp_timing_enable(ctx, enable=True):
     _check(load().stp_timing_enable(ctx, 1 if enable else 0), "stp_timing_enable")
 
@@ -343,6 +364,12 @@ class SpaceTimeSolver:
     def timing_report(self):
         return stp_timing_report(self.ctx)
 
+    def autotune(self, reps=5, use_cache=True):
+        return stp_autotune(self.ctx, reps, use_cache)
+
+    def schedule(self):
+        return stp_schedule_string(self.ctx)
+
     def close(self):
         if self.ctx:
             stp_destroy(self.ctx)
@@ -390,6 +417,12 @@ class BatchSolver:
 
     def timing_report(self):
         return stp_timing_report(self.ctx)
+
+    def autotune(self, reps=5, use_cache=True):
+        return stp_autotune(self.ctx, reps, use_cache)
+
+    def schedule(self):
+        return stp_schedule_string(self.ctx)
 
     def close(self):
         if self.ctx:

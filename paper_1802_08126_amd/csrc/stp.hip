@@ -13,7 +13,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -126,6 +128,34 @@ void transform_path(int N, size_t tcb, int& path, int& C, size_t& lds) {
   path = TP_DENSE;
 }
 
+bool is_pow2(int N) { return N >= 1 && (N & (N - 1)) == 0; }
+
+// Stockham LDS bytes for N points and C columns per block
+size_t stockham_lds(int N, int C, size_t tcb) { return (size_t(2) * N * C + size_t(4) * N) * tcb; }
+
+// Schedule knobs of the tile launches.  Each knob scales the slabs per
+// block of every job of its launch sites by 2^e relative to the heuristic.
+enum Knob {
+  KN_R0 = 0,            // residual r_p
+  KN_R1,                // residual r_u (and the stop-test partials)
+  KN_MID,               // middle reference operator of the H-blocks
+  KN_UPA0,              // finest up-sweep of the A-tilde cycle (float64 accumulation)
+  KN_DOWN0,             // down-sweep into level l + 1 (all three cycles)
+  KN_UP0 = KN_DOWN0 + STP_MAX_LEVELS,   // up-sweep on level l, stored output
+  KN_COUNT = KN_UP0 + STP_MAX_LEVELS
+};
+
+struct TransformChoice {
+  int path;
+  int C;      // Stockham columns per block
+};
+
+struct Schedule {
+  int e[KN_COUNT];
+  std::map<int, TransformChoice> tpath;   // per power-of-two step count
+  Schedule() { std::fill(e, e + KN_COUNT, 0); }
+};
+
 struct Problem {
   int dim = 0, n = 0, N = 0, R = 0;
   double tau = 0;
@@ -136,12 +166,9 @@ struct Problem {
   std::vector<double> abar;    // R
   std::vector<Level> lv;
   Geom g0{};
-  int tpath = TP_DENSE;
-  int fft_cols = 0;
-  size_t fft_lds = 0;
+  int tpath = TP_DENSE;         // default transform path (the tuner may choose another)
   long resid_tiles = 0;
-  int sb_resid = 1;
-  long npart = 0;               // residual partials (one per residual block)
+  long npart = 0;               // residual partials (one per block of the a3 residual launch)
   long nfnorm = 0;              // partials of the setup reduction of ||f||
   // device memory
   DevState* state = nullptr;
@@ -167,8 +194,10 @@ struct Site {
   std::vector<J> jobs;
   J* dev = nullptr;
   long blocks = 0;
-  int key = 0;     // transform sites: N (-1: dense)
+  int key = 0;     // transform sites: N (-1: the dense group of other step counts)
   int epi = 0;
+  int path = TP_DENSE, C = 0;   // transform sites: path and Stockham columns
+  size_t lds = 0;
   void add(J j, long nb) {
     j.block0 = blocks;
     blocks += nb;
@@ -246,6 +275,8 @@ struct stp_ctx {
   KTimer kt;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
+  Schedule sched;
+  std::string sched_text;
 };
 
 static inline void kt_begin(stp_ctx* c, const char* name) {
@@ -285,6 +316,13 @@ int pick_sb(long tiles, int S) {
   return int(std::max(1L, std::min(16L, sb)));
 }
 
+// heuristic slabs per block scaled by 2^e, within [1, min(16, S)]
+int sched_sb(long tiles, int S, int e) {
+  long sb = pick_sb(tiles, S);
+  sb = e >= 0 ? (sb << e) : (sb >> (-e));
+  return int(std::max(1L, std::min(long(std::min(16, S)), sb)));
+}
+
 long tiles_down_d(int dim, int nc) {
   return dim == 1 ? tiles_for<1, DownTile<1>>(nc) : dim == 2 ? tiles_for<2, DownTile<2>>(nc)
                                                              : tiles_for<3, DownTile<3>>(nc);
@@ -317,14 +355,17 @@ LevelOp family_op(const Problem& q, int l, int fam) {
 void plan_problem(int prec, int spatial, Problem& q, Bump& bp) {
   const size_t tsb = ts_bytes(prec), tcb = tc_bytes(prec);
   const long N = q.N;
-  transform_path(q.N, tcb, q.tpath, q.fft_cols, q.fft_lds);
+  {
+    int C;
+    size_t lds;
+    transform_path(q.N, tcb, q.tpath, C, lds);
+  }
   q.resid_tiles = tiles_up_d(q.dim, q.n);
-  q.sb_resid = pick_sb(q.resid_tiles, q.N);
-  q.npart = q.resid_tiles * ((q.N + q.sb_resid - 1) / q.sb_resid);
   const dim3 gp = grid_pts(q.g0.npts, q.N);
   q.nfnorm = long(gp.x) * gp.y * gp.z;
   q.state = (DevState*)bp.take(sizeof(DevState));
-  q.partial = (double*)bp.take(size_t(std::max(q.npart, q.nfnorm)) * 8);
+  // residual partials for any slabs-per-block choice (at most one slab per block)
+  q.partial = (double*)bp.take(size_t(std::max(q.resid_tiles * q.N, q.nfnorm)) * 8);
   q.kap64 = (double*)bp.take(size_t(q.R) * q.g0.nnodes * 8);
   q.cA64 = (double*)bp.take(size_t(N) * kMaxRank * 8);
   q.cA = bp.take(size_t(N) * kMaxRank * tcb);
@@ -332,10 +373,13 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp) {
   q.sigH = bp.take(size_t(N) * tcb);
   q.cMid = bp.take(size_t(kMaxRank) * tcb);
   q.tw = q.tw4 = q.sinT = q.sinM = nullptr;
-  if (q.tpath == TP_DENSE) {
+  // tables of every path the step count can take: dense (default path, or
+  // a candidate for N <= 64) and the FFT twiddles (powers of two <= 4096)
+  if (q.tpath == TP_DENSE || q.N <= 64) {
     q.sinT = bp.take(size_t(N) * N * tcb);
     q.sinM = bp.take(size_t(N) * N * tcb);
-  } else {
+  }
+  if (is_pow2(q.N) && q.N <= 4096) {
     q.tw = bp.take(size_t(2) * N * tcb);
     q.tw4 = bp.take(size_t(2) * N * tcb);
   }
@@ -417,7 +461,7 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top)
       d.out = q.lv[l + 1].b;
       d.state = &q.state->done;
       d.tiles = int(tiles_down_d(q.dim, q.lv[l + 1].n));
-      d.sb = pick_sb(d.tiles, q.N);
+      d.sb = sched_sb(d.tiles, q.N, c->sched.e[KN_DOWN0 + l]);
       vc.down[l].add(d, long(d.tiles) * ((q.N + d.sb - 1) / d.sb));
       TileJob u{};
       u.gf = q.lv[l].g;
@@ -429,7 +473,7 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top)
       u.acc64 = (l == 0) ? T.acc64 : nullptr;
       u.state = d.state;
       u.tiles = int(tiles_up_d(q.dim, q.lv[l].n));
-      u.sb = pick_sb(u.tiles, q.N);
+      u.sb = sched_sb(u.tiles, q.N, (l == 0 && acc) ? c->sched.e[KN_UPA0] : c->sched.e[KN_UP0 + l]);
       vc.up[l].add(u, long(u.tiles) * ((q.N + u.sb - 1) / u.sb));
       vc.up[l].epi = (l == 0 && acc) ? EPI_ADD64 : EPI_STORE;
     }
@@ -453,13 +497,33 @@ int fft2_l1(int N) {
   return L1;
 }
 
+// transform path of a site: the dense group, a tuned choice, or the default
+void site_path(stp_ctx* c, Site<TimeJob>& s) {
+  const size_t tcb = tc_bytes(c->prec);
+  if (s.key < 0) {
+    s.path = TP_DENSE;
+    s.C = 0;
+    s.lds = 0;
+    return;
+  }
+  auto it = c->sched.tpath.find(s.key);
+  if (it != c->sched.tpath.end()) {
+    s.path = it->second.path;
+    s.C = it->second.C;
+  } else {
+    size_t lds;
+    transform_path(s.key, tcb, s.path, s.C, lds);
+  }
+  s.lds = s.path == TP_STOCKHAM ? stockham_lds(s.key, s.C, tcb) : 0;
+}
+
 void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, const std::vector<const void*>& in,
                       const std::vector<void*>& out, const std::vector<double*>& acc64, double alpha) {
   sites.clear();
   for (size_t i = 0; i < c->pr.size(); ++i) {
     Problem& q = c->pr[i];
-    // sites are keyed by N for the FFT paths and share one dense site
-    const int key = q.tpath == TP_DENSE ? -1 : q.N;
+    // one site per power-of-two step count up to 4096; one dense site for the rest
+    const int key = (is_pow2(q.N) && q.N <= 4096) ? q.N : -1;
     Site<TimeJob>* s = nullptr;
     for (auto& t : sites)
       if (t.key == key) s = &t;
@@ -468,6 +532,7 @@ void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, c
       s = &sites.back();
       s->key = key;
       s->epi = (mode == 1) ? 1 : 0;
+      site_path(c, *s);
     }
     TimeJob j{};
     j.npts = q.g0.npts;
@@ -481,11 +546,11 @@ void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, c
     j.alpha = alpha;
     j.state = &q.state->done;
     long nb;
-    if (q.tpath == TP_FFT2) {
+    if (s->path == TP_FFT2) {
       const int Cc = kBlock >> fft2_l1(q.N);
       nb = (j.npts + Cc - 1) / Cc;
-    } else if (q.tpath == TP_STOCKHAM) {
-      nb = (j.npts + q.fft_cols - 1) / q.fft_cols;
+    } else if (s->path == TP_STOCKHAM) {
+      nb = (j.npts + s->C - 1) / s->C;
     } else {
       j.bx = int((j.npts + 63) / 64);
       nb = long(j.bx) * ((q.N + 4 * kDstKpt - 1) / (4 * kDstKpt));
@@ -503,7 +568,9 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
       Problem& q = c->pr[i];
       ResidJob j{};
       j.tiles = int(q.resid_tiles);
-      j.sb = q.sb_resid;
+      j.sb = sched_sb(q.resid_tiles, q.N, c->sched.e[w == 0 ? KN_R0 : KN_R1]);
+      const long nb = q.resid_tiles * ((q.N + j.sb - 1) / j.sb);
+      if (w == 1) q.npart = nb;
       j.g = q.g0;
       j.t = TimeOp{q.kap64, q.cA64, q.R, q.N};
       j.tau = q.tau;
@@ -514,7 +581,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
       j.r = q.W1;
       j.partial = q.partial;
       j.state = &q.state->done;
-      S.resid[w].add(j, q.npart);
+      S.resid[w].add(j, nb);
     }
   }
   std::vector<VTop> topA(P), topH(P);
@@ -543,7 +610,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
     j.out = q.W2;
     j.state = &q.state->done;
     j.tiles = int(tiles_up_d(q.dim, q.n));
-    j.sb = pick_sb(j.tiles, q.N);
+    j.sb = sched_sb(j.tiles, q.N, c->sched.e[KN_MID]);
     S.mid.add(j, long(j.tiles) * ((q.N + j.sb - 1) / j.sb));
   }
   build_transforms(c, S.a4, 0, in4, out4, acc4, 1.0);
@@ -580,6 +647,15 @@ size_t tables_bytes(Sites& S) {
   for_each_site(S, [&](auto& s) { b += site_bytes(s); });
   b += ((S.fin.size() * sizeof(FinJob)) + 255) & ~size_t(255);
   return b;
+}
+
+// every launch within the 32-bit work-item count of a dispatch
+bool sites_fit(stp_ctx* c) {
+  bool ok = true;
+  for_each_site(c->sites, [&](auto& s) {
+    if (double(s.blocks) * kBlock > 4294967295.0) ok = false;
+  });
+  return ok;
 }
 
 void carve_tables(Sites& S, char* base) {
@@ -655,6 +731,9 @@ stp_status bind_solution(stp_ctx* c, const std::vector<double*>& u, const std::v
 // ---------------------------------------------------------------------------
 struct SolverBase {
   virtual ~SolverBase() {}
+  virtual stp_status init() = 0;
+  virtual stp_status launch_knob(int knob) = 0;
+  virtual stp_status launch_transform(int g) = 0;
   virtual stp_status setup_problem(Problem& q) = 0;
   virtual stp_status iteration() = 0;
   virtual stp_status run_vcycle(int which) = 0;
@@ -689,29 +768,73 @@ struct Solver : SolverBase {
     if (!vc.coarse.empty() && !vc.coarse[0].jobs.empty())   // single-node problems
       if ((st = coarse_site<D>(vc.coarse[0], 0)) != STP_OK) return st;
     for (int l = 0; l < nl; ++l) {
-      c->kt.level = l;
-      Site<TileJob>& s = vc.down[l];
-      if (!s.jobs.empty()) {
-        KLAUNCH_NAMED("k_mg_down", (k_mg_down<D, TS, TC, RM>), dim3(unsigned(s.blocks)), dim3(kBlock), 0, c->stream,
-                      s.dev, int(s.jobs.size()), omegaJ());
-        LAUNCH_CHECK();
-      }
+      if ((st = down_site<D, RM>(vc.down[l], l)) != STP_OK) return st;
       if (!vc.coarse[l + 1].jobs.empty())
         if ((st = coarse_site<D>(vc.coarse[l + 1], l + 1)) != STP_OK) return st;
     }
-    for (int l = nl - 1; l >= 0; --l) {
-      c->kt.level = l;
-      Site<TileJob>& s = vc.up[l];
-      if (s.jobs.empty()) continue;
-      if (s.epi == EPI_ADD64)
-        KLAUNCH_NAMED("k_mg_up<add64>", (k_mg_up<D, TS, TC, RM, EPI_ADD64>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
-                      c->stream, s.dev, int(s.jobs.size()), omegaJ());
-      else
-        KLAUNCH_NAMED("k_mg_up<store>", (k_mg_up<D, TS, TC, RM, EPI_STORE>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
-                      c->stream, s.dev, int(s.jobs.size()), omegaJ());
-      LAUNCH_CHECK();
-    }
+    for (int l = nl - 1; l >= 0; --l)
+      if ((st = up_site<D, RM>(vc.up[l], l)) != STP_OK) return st;
     return STP_OK;
+  }
+
+  template <int D, int RM>
+  stp_status down_site(Site<TileJob>& s, int l) {
+    if (s.jobs.empty()) return STP_OK;
+    c->kt.level = l;
+    KLAUNCH_NAMED("k_mg_down", (k_mg_down<D, TS, TC, RM>), dim3(unsigned(s.blocks)), dim3(kBlock), 0, c->stream, s.dev,
+                  int(s.jobs.size()), omegaJ());
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
+  template <int D, int RM>
+  stp_status up_site(Site<TileJob>& s, int l) {
+    if (s.jobs.empty()) return STP_OK;
+    c->kt.level = l;
+    if (s.epi == EPI_ADD64)
+      KLAUNCH_NAMED("k_mg_up<add64>", (k_mg_up<D, TS, TC, RM, EPI_ADD64>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
+                    c->stream, s.dev, int(s.jobs.size()), omegaJ());
+    else
+      KLAUNCH_NAMED("k_mg_up<store>", (k_mg_up<D, TS, TC, RM, EPI_STORE>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
+                    c->stream, s.dev, int(s.jobs.size()), omegaJ());
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
+  // one launch of the representative site of a schedule knob
+  template <int D, int RM>
+  stp_status knob_dr(int knob) {
+    switch (knob) {
+      case KN_R0: return resid_dr<D, 0, RM>();
+      case KN_R1: return resid_dr<D, 1, RM>();
+      case KN_MID: return mid_dr<D, RM>();
+      case KN_UPA0: return up_site<D, RM>(c->sites.vc[VC_A].up[0], 0);
+      default:
+        if (knob < KN_UP0) return down_site<D, RM>(c->sites.vc[VC_H1].down[knob - KN_DOWN0], knob - KN_DOWN0);
+        return up_site<D, RM>(c->sites.vc[VC_H1].up[knob - KN_UP0], knob - KN_UP0);
+    }
+  }
+
+  stp_status launch_knob(int knob) override {
+    switch (c->dim * 10 + c->rm) {
+      case 11: return knob_dr<1, 1>(knob);
+      case 12: return knob_dr<1, 2>(knob);
+      case 14: return knob_dr<1, 4>(knob);
+      case 21: return knob_dr<2, 1>(knob);
+      case 22: return knob_dr<2, 2>(knob);
+      case 24: return knob_dr<2, 4>(knob);
+      case 31: return knob_dr<3, 1>(knob);
+      case 32: return knob_dr<3, 2>(knob);
+      default: return knob_dr<3, 4>(knob);
+    }
+  }
+
+  // transform group g: forward (mode 0) and inverse-accumulate (mode 1) launches
+  stp_status launch_transform(int g) override {
+    std::vector<Site<TimeJob>> one4(1, c->sites.a4[g]), one6(1, c->sites.a6[g]);
+    stp_status st = transform_sites(one4, 0);
+    if (st != STP_OK) return st;
+    return transform_sites(one6, 1);
   }
 
   stp_status run_vcycle(int which) override {
@@ -795,9 +918,8 @@ struct Solver : SolverBase {
       Site<TimeJob>& s = sites[g];
       c->kt.level = int(g);
       if (s.jobs.empty()) continue;
-      const int N = s.key;
       const bool acc = s.epi != 0;
-      if (N < 0) {   // dense
+      if (s.path == TP_DENSE) {
         if (acc)
           KLAUNCH_NAMED("k_time_dense<a6,add64>", (k_time_dense<TS, TC, 1>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
                         c->stream, s.dev, int(s.jobs.size()));
@@ -807,7 +929,7 @@ struct Solver : SolverBase {
         LAUNCH_CHECK();
         continue;
       }
-      if (N >= 4 && N <= 256) {
+      if (s.path == TP_FFT2) {
         stp_status st;
         if (mode == 0) st = fft2_dispatch<MODE_A4, 0>(s);
         else if (acc) st = fft2_dispatch<MODE_A6, 1>(s);
@@ -816,9 +938,8 @@ struct Solver : SolverBase {
         continue;
       }
       // Stockham: every job of the site has the same N, hence the same layout
-      int C, path;
-      size_t lds;
-      transform_path(N, sizeof(TC), path, C, lds);
+      const int C = s.C;
+      const size_t lds = s.lds;
       if (mode == 0)
         KLAUNCH_NAMED("k_time_fft<a4>", (k_time_fft<TS, TC, MODE_A4, 0>), dim3(unsigned(s.blocks)), dim3(kBlock), lds,
                       c->stream, s.dev, int(s.jobs.size()), C);
@@ -885,6 +1006,18 @@ struct Solver : SolverBase {
     return STP_OK;
   }
 
+  // the Stockham kernels may take up to the whole LDS of a CU
+  stp_status init() override {
+    const int lds = 160 * 1024;
+    HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A4, 0>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 0>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 1>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    return STP_OK;
+  }
+
   stp_status setup_problem(Problem& q) override {
     const int N = q.N, R = q.R;
     std::vector<TC> cA(size_t(N) * kMaxRank, TC(0)), cH(size_t(N) * kMaxRank, TC(0)), sig(N), mid(kMaxRank, TC(0));
@@ -902,7 +1035,7 @@ struct Solver : SolverBase {
     HIP_TRY(hipMemcpyAsync(q.cH, cH.data(), cH.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(q.sigH, sig.data(), sig.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(q.cMid, mid.data(), mid.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-    if (q.tpath == TP_DENSE) {
+    if (q.sinT) {
       std::vector<TC> sT(size_t(N) * N), sM(size_t(N) * N);
       for (int k = 0; k < N; ++k)
         for (int m = 0; m < N; ++m) {
@@ -915,7 +1048,8 @@ struct Solver : SolverBase {
       HIP_TRY(hipMemcpyAsync(q.sinT, sT.data(), sT.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
       HIP_TRY(hipMemcpyAsync(q.sinM, sM.data(), sM.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
       HIP_TRY(hipStreamSynchronize(c->stream));
-    } else {
+    }
+    if (q.tw) {
       std::vector<TC> tw(2 * size_t(N)), tw4(2 * size_t(N));
       for (int m = 0; m < N; ++m) {
         tw[m] = TC(std::cos(2.0 * M_PI * m / N));
@@ -926,14 +1060,6 @@ struct Solver : SolverBase {
       HIP_TRY(hipMemcpyAsync(q.tw, tw.data(), tw.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
       HIP_TRY(hipMemcpyAsync(q.tw4, tw4.data(), tw4.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
       HIP_TRY(hipStreamSynchronize(c->stream));
-      if (q.tpath == TP_STOCKHAM && q.fft_lds > 65536) {
-        HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A4, 0>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(q.fft_lds)));
-        HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 0>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(q.fft_lds)));
-        HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 1>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(q.fft_lds)));
-      }
     }
     // level fields: restrict unscaled float64 fields, then scale by 0.5/h^2 into TC
     for (size_t l = 0; l < q.lv.size(); ++l) {
@@ -1163,6 +1289,7 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_w16d), wd, sizeof(wd)));
     HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_w16f), wf, sizeof(wf)));
   }
+  if ((s = c->impl->init()) != STP_OK) return s;
   for (auto& q : c->pr) {
     if ((s = c->impl->setup_problem(q)) != STP_OK) return s;
     // kappa(t_n, x) > 0 at every node and step, and for the reference coefficient
@@ -1200,6 +1327,7 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
   // launch tables (jobs point at null u, p until a solve binds them)
   std::vector<double*> nul(P, nullptr);
   build_sites(c.get(), nul, nul);
+  if (!sites_fit(c.get())) return fail(STP_EUNSUPPORTED, "a launch exceeds the dispatch size limit");
   carve_tables(c->sites, (char*)c->ws + c->tables_off);
   if ((s = upload_all(c.get())) != STP_OK) return s;
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1380,6 +1508,262 @@ stp_status stp_uzawa_solve(stp_ctx* c, double* u, double* p, stp_stats* st) {
   if (!c || !u || !p) return fail(STP_EINVAL, "NULL argument (u and p are required)");
   if (c->P != 1) return fail(STP_EUNSUPPORTED, "use stp_uzawa_solve_batch for a batch context");
   return stp_uzawa_solve_batch(c, &u, &p, st);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, Schedule> g_tune_cache;
+
+std::string tune_key(stp_ctx* c) {
+  char b[96];
+  snprintf(b, sizeof(b), "p%d d%d s%d r%d", c->prec, c->dim, c->spatial, c->rm);
+  std::string k = b;
+  for (auto& q : c->pr) {
+    snprintf(b, sizeof(b), "|%d,%d,%d", q.n, q.N, q.R);
+    k += b;
+  }
+  return k;
+}
+
+// slabs per block that knob k with exponent e gives each job (empty: knob unused)
+std::vector<int> knob_sbs(stp_ctx* c, int k, int e) {
+  std::vector<int> v;
+  for (auto& q : c->pr) {
+    const int Lq = int(q.lv.size());
+    const bool mg = c->spatial == STP_SPATIAL_MG;
+    long tiles = -1;
+    if (k == KN_R0 || k == KN_R1) tiles = q.resid_tiles;
+    else if (k == KN_MID) tiles = tiles_up_d(q.dim, q.n);
+    else if (k == KN_UPA0) tiles = (mg && Lq > 1) ? tiles_up_d(q.dim, q.n) : -1;
+    else if (k < KN_UP0) {
+      const int l = k - KN_DOWN0;
+      tiles = (mg && Lq > l + 1) ? tiles_down_d(q.dim, q.lv[l + 1].n) : -1;
+    } else {
+      const int l = k - KN_UP0;
+      tiles = (mg && Lq > l + 1) ? tiles_up_d(q.dim, q.lv[l].n) : -1;
+    }
+    if (tiles > 0) v.push_back(sched_sb(tiles, q.N, e));
+  }
+  return v;
+}
+
+stp_status rebuild(stp_ctx* c, const std::vector<double*>& u, const std::vector<double*>& p) {
+  build_sites(c, u, p);
+  if (tables_bytes(c->sites) > c->tables_bytes) return fail(STP_EDEVICE, "launch tables outgrew their reservation");
+  if (!sites_fit(c)) return fail(STP_EUNSUPPORTED, "a launch exceeds the dispatch size limit");
+  carve_tables(c->sites, (char*)c->ws + c->tables_off);
+  return upload_all(c);
+}
+
+template <typename F>
+stp_status time_ms(stp_ctx* c, int reps, F&& f, double& ms) {
+  stp_status s = f();   // warm-up
+  if (s != STP_OK) return s;
+  HIP_TRY(hipEventRecord(c->ev0, c->stream));
+  for (int r = 0; r < reps; ++r)
+    if ((s = f()) != STP_OK) return s;
+  HIP_TRY(hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(hipEventSynchronize(c->ev1));
+  float t = 0;
+  HIP_TRY(hipEventElapsedTime(&t, c->ev0, c->ev1));
+  ms = double(t) / reps;
+  return STP_OK;
+}
+
+void describe_schedule(stp_ctx* c) {
+  std::string t;
+  char b[128];
+  auto knob_name = [](int k) -> std::string {
+    char nb[32];
+    if (k == KN_R0) return "resid_a1";
+    if (k == KN_R1) return "resid_a3";
+    if (k == KN_MID) return "apply_mid";
+    if (k == KN_UPA0) return "up_add64_L0";
+    if (k < KN_UP0) snprintf(nb, sizeof(nb), "down_L%d", k - KN_DOWN0);
+    else snprintf(nb, sizeof(nb), "up_L%d", k - KN_UP0);
+    return nb;
+  };
+  for (int k = 0; k < KN_COUNT; ++k) {
+    std::vector<int> v = knob_sbs(c, k, c->sched.e[k]);
+    if (v.empty()) continue;
+    snprintf(b, sizeof(b), "%s%s:e=%d,sb=%d", t.empty() ? "" : " ", knob_name(k).c_str(), c->sched.e[k], v[0]);
+    t += b;
+    if (v.size() > 1) t += "..";
+  }
+  for (auto& s : c->sites.a4) {
+    const char* nm = s.path == TP_FFT2 ? "fft2" : (s.path == TP_STOCKHAM ? "stockham" : "dense");
+    if (s.key > 0) snprintf(b, sizeof(b), " dst_N%d:%s", s.key, nm);
+    else snprintf(b, sizeof(b), " dst_other:%s", nm);
+    t += b;
+    if (s.path == TP_STOCKHAM) {
+      snprintf(b, sizeof(b), ",C=%d", s.C);
+      t += b;
+    }
+  }
+  c->sched_text = t;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* stp_schedule_string(stp_ctx* c) {
+  if (!c) return "";
+  describe_schedule(c);
+  return c->sched_text.c_str();
+}
+
+stp_status stp_autotune(stp_ctx* c, int reps, int use_cache, stp_tune_report* rep) {
+  if (!c) return fail(STP_EINVAL, "NULL context");
+  if (c->spatial == STP_SPATIAL_NONE) return fail(STP_EUNSUPPORTED, "context created without a spatial solver");
+  reps = std::max(1, std::min(reps, 100));
+  stp_tune_report r{};
+  const std::string key = tune_key(c);
+  stp_status s;
+  if (use_cache) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      c->sched = it->second;
+      r.from_cache = 1;
+    }
+  }
+  if (c->gexec) {   // the launch shapes change: capture again at the next solve
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  const size_t P = c->pr.size();
+  std::vector<double*> nul(P, nullptr);
+  if (r.from_cache) {
+    if ((s = rebuild(c, nul, nul)) != STP_OK) return s;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (rep) *rep = r;
+    return STP_OK;
+  }
+  // scratch iterates: the tuner runs real launches on the context's buffers
+  size_t total = 0;
+  for (auto& q : c->pr) total += size_t(2) * q.N * q.g0.npts;
+  double* tmp = nullptr;
+  if (hipMalloc((void**)&tmp, total * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(STP_ENOMEM, "autotune: hipMalloc of %zu bytes failed", total * 8);
+  }
+  std::vector<double*> tu(P), tp(P);
+  {
+    size_t off = 0;
+    for (size_t i = 0; i < P; ++i) {
+      const size_t nv = size_t(c->pr[i].N) * c->pr[i].g0.npts;
+      tu[i] = tmp + off;
+      tp[i] = tmp + off + nv;
+      off += 2 * nv;
+    }
+  }
+  const stp_options saved = c->opt;
+  const bool kt_saved = c->kt.on;
+  c->opt.tol = 0.0;                 // no stop test while tuning
+  c->opt.max_iter = 1 << 30;
+  c->kt.on = false;
+  auto body = [&]() -> stp_status {
+    HIP_TRY(hipMemsetAsync(tmp, 0, total * 8, c->stream));
+    for (size_t i = 0; i < P; ++i) {
+      c->state_host[i] = DevState{};
+      c->state_host[i].fnorm = c->pr[i].fnorm;
+      HIP_TRY(hipMemcpyAsync(c->pr[i].state, &c->state_host[i], sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+    }
+    stp_status st;
+    if ((st = rebuild(c, tu, tp)) != STP_OK) return st;
+    auto iter = [&]() { return c->impl->iteration(); };
+    if ((st = iter()) != STP_OK) return st;
+    if ((st = time_ms(c, reps, iter, r.iter_ms_before)) != STP_OK) return st;
+    // tile launches: slabs per block, knob by knob
+    for (int k = 0; k < KN_COUNT; ++k) {
+      const std::vector<int> base = knob_sbs(c, k, 0);
+      if (base.empty()) continue;
+      ++r.knobs_tuned;
+      std::vector<std::vector<int>> seen(1, base);
+      double best_t = 0;
+      if ((st = time_ms(c, reps, [&]() { return c->impl->launch_knob(k); }, best_t)) != STP_OK) return st;
+      ++r.candidates;
+      int best_e = 0;
+      for (int e = -3; e <= 3; ++e) {
+        if (e == 0) continue;
+        const std::vector<int> v = knob_sbs(c, k, e);
+        if (std::find(seen.begin(), seen.end(), v) != seen.end()) continue;
+        seen.push_back(v);
+        c->sched.e[k] = e;
+        if ((st = rebuild(c, tu, tp)) != STP_OK) {
+          c->sched.e[k] = best_e;
+          if (st == STP_EUNSUPPORTED) continue;
+          return st;
+        }
+        double t = 0;
+        if ((st = time_ms(c, reps, [&]() { return c->impl->launch_knob(k); }, t)) != STP_OK) return st;
+        ++r.candidates;
+        if (t < 0.98 * best_t) {   // keep the heuristic unless a choice is clearly faster
+          best_t = t;
+          best_e = e;
+        }
+      }
+      c->sched.e[k] = best_e;
+      if ((st = rebuild(c, tu, tp)) != STP_OK) return st;
+    }
+    // time transforms: path and Stockham columns per power-of-two step count
+    const size_t tcb = tc_bytes(c->prec);
+    for (size_t g = 0; g < c->sites.a4.size(); ++g) {
+      const int N = c->sites.a4[g].key;
+      if (N <= 0) continue;
+      std::vector<TransformChoice> cand;
+      if (N >= 4 && N <= 256) cand.push_back({TP_FFT2, 0});
+      for (int C = 1; C <= 16; C *= 2)
+        if (stockham_lds(N, C, tcb) <= 160 * 1024) cand.push_back({TP_STOCKHAM, C});
+      if (N <= 64) cand.push_back({TP_DENSE, 0});
+      const Site<TimeJob> cur = c->sites.a4[g];
+      TransformChoice best{cur.path, cur.C};
+      double best_t = 0;
+      if ((st = time_ms(c, reps, [&]() { return c->impl->launch_transform(int(g)); }, best_t)) != STP_OK) return st;
+      ++r.knobs_tuned;
+      ++r.candidates;
+      for (const auto& ch : cand) {
+        if (ch.path == best.path && ch.C == best.C) continue;
+        c->sched.tpath[N] = ch;
+        if ((st = rebuild(c, tu, tp)) != STP_OK) {
+          c->sched.tpath[N] = best;
+          if (st == STP_EUNSUPPORTED) continue;
+          return st;
+        }
+        double t = 0;
+        if ((st = time_ms(c, reps, [&]() { return c->impl->launch_transform(int(g)); }, t)) != STP_OK) return st;
+        ++r.candidates;
+        if (t < 0.98 * best_t) {
+          best_t = t;
+          best = ch;
+        }
+      }
+      c->sched.tpath[N] = best;
+      if ((st = rebuild(c, tu, tp)) != STP_OK) return st;
+    }
+    return time_ms(c, reps, iter, r.iter_ms_after);
+  };
+  s = body();
+  c->opt = saved;
+  c->kt.on = kt_saved;
+  const stp_status s2 = rebuild(c, nul, nul);   // tables as after stp_create: u, p bound at the next solve
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(tmp);
+  if (s != STP_OK) return s;
+  if (s2 != STP_OK) return s2;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = c->sched;
+  }
+  if (rep) *rep = r;
+  return STP_OK;
 }
 
 stp_status stp_timing_enable(stp_ctx* c, int enable) {

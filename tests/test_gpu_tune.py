@@ -1,0 +1,89 @@
+"""GPU tests of the autotuner: a tuned schedule changes only how work is split
+among blocks (and which exact transform algorithm runs), never the result
+beyond rounding; the cache reproduces the schedule; graphs are re-captured."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import uzawa
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test collected without a GPU")
+    import paper_1802_08126_amd as stp
+    stp.load()
+    yield
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("d,n,N,prec", [(2, 63, 64, "f64"), (3, 15, 32, "f64"), (2, 31, 16, "f32"), (1, 63, 64, "f64")])
+def test_tuned_schedule_same_iterates(d, n, N, prec):
+    import paper_1802_08126_amd as stp
+    prob = synth.heat1d_random(n=n, N=N) if d == 1 else synth.small_problem(d, n, N, seed=31)
+    kw = dict(precision=prec, omega=0.7, tol=0.0, max_iter=4, check_every=2)
+    s = stp.from_problem(prob, **kw)
+    u0, p0, i0 = s.solve()
+    u0, p0 = host(u0), host(p0)
+    before = s.schedule()
+    rep = s.autotune(reps=3, use_cache=False)
+    assert rep["knobs_tuned"] >= 3 and rep["candidates"] >= rep["knobs_tuned"]
+    assert rep["iter_ms_before"] > 0 and rep["iter_ms_after"] > 0
+    assert isinstance(s.schedule(), str) and s.schedule() != "" and before != ""
+    for _ in range(2):   # graph captured again after tuning, replayed twice
+        u1, p1, i1 = s.solve()
+        assert i1["iters"] == i0["iters"] == 4
+        tol = 1e-12 if prec == "f64" else 1e-5
+        assert relmax(host(u1), u0) < tol and relmax(host(p1), p0) < tol
+    if prec == "f64":
+        ref = uzawa.uzawa_fixed(prob, 4, omega=0.7, spatial="exact" if d == 1 else "mg")
+        assert relmax(host(u1), ref["u"]) < 1e-11
+    # eager launches with the tuned schedule equal the graph replays bitwise
+    e = stp.from_problem(prob, use_graph=False, **kw)
+    e.autotune(reps=3, use_cache=True)
+    assert e.schedule() == s.schedule()
+    ue, pe, _ = e.solve()
+    assert np.array_equal(host(ue), host(u1)) and np.array_equal(host(pe), host(p1))
+    s.close()
+    e.close()
+
+
+def test_cache_reuses_schedule():
+    import paper_1802_08126_amd as stp
+    prob = synth.small_problem(2, 31, 32, seed=5)
+    a = stp.from_problem(prob, omega=0.7)
+    ra = a.autotune(reps=2, use_cache=False)
+    assert not ra["from_cache"]
+    b = stp.from_problem(prob, omega=0.7)
+    rb = b.autotune(reps=2, use_cache=True)
+    assert rb["from_cache"] and b.schedule() == a.schedule()
+    a.close()
+    b.close()
+
+
+def test_tuned_batch_matches_oracle():
+    import paper_1802_08126_amd as stp
+    probs = [synth.small_problem(2, 31, 16, seed=41), synth.small_problem(2, 7, 12, seed=42),
+             synth.small_problem(2, 15, 64, seed=43), synth.small_problem(2, 63, 8, seed=44)]
+    kw = dict(omega=0.7, tol=0.0, max_iter=3, check_every=2)
+    b = stp.BatchSolver([stp.problem_dict(q) for q in probs], **kw)
+    b.autotune(reps=2, use_cache=False)
+    us, ps, infos, _ = b.solve()
+    for i, q in enumerate(probs):
+        ref = uzawa.uzawa_fixed(q, 3, omega=0.7, spatial="mg")
+        assert relmax(host(us[i]), ref["u"]) < 1e-11, i
+        assert relmax(host(ps[i]), ref["p"]) < 1e-11, i
+    b.close()
