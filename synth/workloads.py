@@ -191,7 +191,10 @@ def heat3d_lognormal(n: int = 127, N: int = 128, T: float = 1.0, seed: int = 100
     """3-D heat, kappa = kappa_s(x) (1 + 0.3 t) with kappa_s lognormal.
 
     ``source="gaussians"``: F = 8 space-time Gaussians, u0 = sin(pi x)sin(pi y)sin(pi z).
-    ``source="none"``: F = 0 placeholder (callers build a manufactured source).
+    ``source="none"``: F is None; callers build the manufactured source for
+    u*(t,x) = exp(-3 pi^2 t) sin(pi x) sin(pi y) sin(pi z) (whose u0 this is),
+    F_n = (u*_n - u*_{n-1}) / tau + A_n u*_n, which needs the spatial operator
+    and so is not built here.
     """
     rng = np.random.default_rng(seed)
     t = _times(N, T)
@@ -201,7 +204,7 @@ def heat3d_lognormal(n: int = 127, N: int = 128, T: float = 1.0, seed: int = 100
     if source == "gaussians":
         F = gaussian_source(n, 3, N, T, rng)
     else:
-        F = np.zeros((N,) + (n,) * 3)
+        F = None
     return Problem(3, n, N, T, ks, tc, F, u0, name="heat3d_lognormal", seed=seed)
 
 

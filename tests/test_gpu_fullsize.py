@@ -1,0 +1,191 @@
+"""GPU parity at the full sizes of the five workloads (the launch
+configuration bench.py times), through the C ABI.
+
+Checks that hold at any size stand in where the oracle cannot run the whole
+solve in seconds:
+  * 1-D 63 x 64: the converged solution against the oracle's sequential
+    implicit Euler, and the iteration count against the oracle's Uzawa.
+  * 2-D 255^2 x 256: two full iterations element by element against the
+    oracle's Uzawa; the converged solution's residual ||f - B u|| / ||f||
+    recomputed with the oracle's operator.
+  * 3-D lognormal 127^3 x 128 and 255^3 x 64: a manufactured source whose
+    exact discrete solution is u*_n = exp(-3 pi^2 t_n) sin(pi x) sin(pi y)
+    sin(pi z) (the source is built from the oracle's spatial operator), so
+    the GPU solution is compared with a closed form.
+  * 64-problem batch: every problem's residual recomputed with the oracle.
+The accuracy target is 1e-8 relative to the exact solution (L2 and max norm);
+a residual of 1e-9 (1e-10 on the 127^3 workload) reaches it.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import euler, fd, spacetime as st, uzawa
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[fullsize]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test collected without a GPU")
+    import paper_1802_08126_amd as stp
+    stp.load()
+    yield
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_heat1d_63_N64_full():
+    import paper_1802_08126_amd as stp
+    prob = synth.CONFIG_BUILDERS["heat1d_63_N64"]()
+    s = stp.from_problem(prob, tol=1e-9, max_iter=500)
+    u, _, info = s.solve()
+    assert info["status"] == 0, info
+    ue = euler.seq_euler(prob)
+    uh = host(u)
+    say("1d", info["iters"], np.linalg.norm(uh - ue) / np.linalg.norm(ue), relmax(uh, ue))
+    assert np.linalg.norm(uh - ue) / np.linalg.norm(ue) < 1e-8
+    assert relmax(uh, ue) < 1e-8
+    s.close()
+    s = stp.from_problem(prob, tol=1e-8, max_iter=500)
+    _, _, info = s.solve()
+    ref = uzawa.uzawa(prob, omega=0.8, tol=1e-8, max_iter=500, spatial="exact")
+    assert abs(info["iters"] - ref["iters"]) <= 1, (info, ref["iters"])
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def heat2d():
+    t0 = time.time()
+    prob = synth.CONFIG_BUILDERS["heat2d_255_N256"]()
+    say("2d inputs", f"{time.time() - t0:.1f}s")
+    return prob
+
+
+def test_heat2d_255_N256_two_iterations_full(heat2d):
+    """Two iterations at the full size and in the bench's launch configuration
+    (autotuned schedule, graph replay), element by element against the oracle."""
+    import paper_1802_08126_amd as stp
+    prob = heat2d
+    s = stp.from_problem(prob, omega=0.8, tol=0.0, max_iter=2, check_every=8)
+    s.autotune(reps=3)
+    u, p, info = s.solve()
+    t0 = time.time()
+    ref = uzawa.uzawa_fixed(prob, 2, omega=0.8, spatial="mg")
+    say("2d oracle 2 iterations", f"{time.time() - t0:.1f}s")
+    ru, rp = relmax(host(u), ref["u"]), relmax(host(p), ref["p"])
+    say("2d trajectory", ru, rp, info["rel_res"], ref["history"][-1])
+    assert ru < 1e-11 and rp < 1e-11
+    assert abs(info["rel_res"] - ref["history"][-1]) <= 1e-9 * ref["history"][-1]
+    s.close()
+
+
+def test_heat2d_255_N256_converged_residual_full(heat2d):
+    import paper_1802_08126_amd as stp
+    prob = heat2d
+    s = stp.from_problem(prob, omega=0.8, tol=1e-9, max_iter=400)
+    s.autotune(reps=3)
+    u, p, info = s.solve()
+    assert info["status"] == 0, info
+    uh = host(u)
+    f = st.rhs(prob)
+    res = np.linalg.norm(f - st.apply_B(prob, uh)) / np.linalg.norm(f)
+    say("2d converged", info["iters"], info["rel_res"], res)
+    assert res <= 1.0e-9 * (1 + 1e-6)
+    assert abs(res - info["rel_res"]) <= 1e-6 * res
+    s.close()
+
+
+def manufactured_3d(n, N, seed, contrast):
+    """Lognormal workload with the manufactured source of the closed-form u*."""
+    t0 = time.time()
+    prob = synth.heat3d_lognormal(n=n, N=N, seed=seed, contrast=contrast, source="none")
+    S = prob.u0                                   # sin(pi x) sin(pi y) sin(pi z), shape (n, n, n)
+    AS = fd.apply(prob.kfields[0], S, prob.h, 3)  # A(kappa_s) S, by the oracle's operator
+    tau = prob.tau
+    e = np.exp(-3 * np.pi ** 2 * tau * np.arange(N + 1))
+    tc = prob.tcoef[0]
+    F = np.multiply.outer((e[1:] - e[:-1]) / tau, S)
+    F += np.multiply.outer(tc * e[1:], AS)
+    say(f"3d {n}^3 x {N} inputs", f"{time.time() - t0:.1f}s")
+    return prob, F, S, e
+
+
+def check_manufactured(u_dev, S, e):
+    """Relative L2 and max-norm error of u against e_n S, slab by slab on the host."""
+    num = den = 0.0
+    emax = umax = 0.0
+    for k in range(u_dev.shape[0]):
+        uk = u_dev[k].cpu().numpy()
+        ex = e[k + 1] * S
+        d = uk - ex
+        num += float(np.vdot(d, d))
+        den += float(np.vdot(ex, ex))
+        emax = max(emax, float(np.abs(d).max()))
+        umax = max(umax, float(np.abs(ex).max()))
+    return np.sqrt(num / den), emax / umax
+
+
+@pytest.fixture(scope="module")
+def heat3d_127():
+    return manufactured_3d(127, 128, 1003, 1e2)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_heat3d_127_N128_manufactured_full(heat3d_127, prec):
+    import paper_1802_08126_amd as stp
+    prob, F, S, e = heat3d_127
+    Fd = dev(F)
+    s = stp.SpaceTimeSolver(3, prob.n, prob.N, prob.tau, dev(prob.kfields), prob.tcoef, Fd, dev(S),
+                            precision=prec, omega=0.8, tol=1e-10, max_iter=600)
+    s.autotune(reps=2)
+    u, p, info = s.solve()
+    l2, mx = check_manufactured(u, S, e)
+    say("3d 127", prec, info["iters"], info["rel_res"], l2, mx)
+    assert info["status"] == 0, info
+    assert l2 < 1e-8 and mx < 1e-8
+    s.close()
+    del Fd, u, p
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_heat3d_255_N64_manufactured_full(prec):
+    import paper_1802_08126_amd as stp
+    prob, F, S, e = manufactured_3d(255, 64, 1005, 1e3)
+    Fd = dev(F)
+    del F
+    s = stp.SpaceTimeSolver(3, prob.n, prob.N, prob.tau, dev(prob.kfields), prob.tcoef, Fd, dev(S),
+                            precision=prec, omega=0.8, tol=1e-9, max_iter=800)
+    s.autotune(reps=2)
+    u, p, info = s.solve()
+    l2, mx = check_manufactured(u, S, e)
+    say("3d 255", prec, info["iters"], info["rel_res"], info["ms"], l2, mx)
+    assert info["status"] == 0, info
+    assert l2 < 1e-8 and mx < 1e-8
+    s.close()
+    del Fd, u, p
+    torch.cuda.empty_cache()
