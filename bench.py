@@ -160,6 +160,135 @@ def gpu_run(args):
     return prob, dims, results
 
 
+def progress(*a):
+    """Progress lines go to stderr; stdout carries only the JSON result."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def batch_inputs(count, seed, device):
+    """The mixed-size batch workload on the device.  Coefficients, initial data
+    and the source's separable Gaussian factors come from the seeded generator;
+    the source is assembled on the device from those factors in the
+    generator's own operation order (identical values)."""
+    import torch
+
+    import synth
+
+    specs = synth.batch2d(count=count, seed=seed)
+    probs = []
+    for sp in specs:
+        kf, tc, factors, u0 = synth.batch2d_parts(sp)
+        n, N = sp["side"], sp["N"]
+        F = torch.zeros((N, n, n), dtype=torch.float64, device=device)
+        for gt, (gx, gy) in factors:
+            G = torch.as_tensor(gy, device=device)[:, None] * torch.as_tensor(gx, device=device)[None, :]
+            F += torch.as_tensor(gt, device=device)[:, None, None] * G[None]
+        probs.append(dict(dim=2, n=n, N=N, tau=1.0 / N, tcoef=tc, F=F,
+                          kfields=torch.as_tensor(kf, dtype=torch.float64, device=device),
+                          u0=torch.as_tensor(u0, dtype=torch.float64, device=device)))
+    return specs, probs
+
+
+def batch_run(args):
+    """64 independent 2-D problems: one batched context (merged launches, one
+    graph per iteration) against a loop of 64 single-problem contexts."""
+    import torch
+
+    import paper_1802_08126_amd as stp
+
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    specs, probs = batch_inputs(64, 1004, dev)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    dofs = sum(q["N"] * q["n"] ** 2 for q in probs)
+    shapes = [(q["N"], q["n"], q["n"]) for q in probs]
+    us = [torch.zeros(sh, dtype=torch.float64, device=dev) for sh in shapes]
+    ps = [torch.zeros(sh, dtype=torch.float64, device=dev) for sh in shapes]
+    K = args.batch_steps
+    out = dict(problems=len(probs), dofs=dofs, sides=sorted({q["n"] for q in probs}),
+               N_range=[min(q["N"] for q in probs), max(q["N"] for q in probs)], steps=K,
+               input_setup_s=setup_s)
+
+    def zero():
+        for t in us + ps:
+            t.zero_()
+        torch.cuda.synchronize()
+
+    def timed_batch(b):
+        zero()
+        b.solve(us, ps)                        # captures the graph
+        zero()
+        t0 = time.perf_counter()
+        _, _, infos, _ = b.solve(us, ps)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, infos
+
+    for prec in ("f32", "f64"):
+        b = stp.BatchSolver(probs, precision=prec, omega=args.omega, tol=0.0, max_iter=K, check_every=K + 1)
+        sec, infos = timed_batch(b)
+        assert all(i["iters"] == K for i in infos)
+        r = dict(batch_heuristic=dict(sec=sec, value=dofs * K / sec))
+        t0 = time.perf_counter()
+        tune = b.autotune(reps=2, use_cache=False)
+        tune["sec"] = time.perf_counter() - t0
+        sec, _ = timed_batch(b)
+        r["batch_tuned"] = dict(sec=sec, value=dofs * K / sec, autotune=tune)
+        b.close()
+        # loop of single-problem contexts, built-in schedule, graph replay each
+        ss = [stp.SpaceTimeSolver(2, q["n"], q["N"], q["tau"], q["kfields"], q["tcoef"], q["F"], q["u0"],
+                                  precision=prec, omega=args.omega, tol=0.0, max_iter=K, check_every=K + 1)
+              for q in probs]
+        zero()
+        for i, sv in enumerate(ss):
+            sv.solve(us[i], ps[i])
+        zero()
+        t0 = time.perf_counter()
+        for i, sv in enumerate(ss):
+            sv.solve(us[i], ps[i])
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        r["loop_heuristic"] = dict(sec=sec, value=dofs * K / sec)
+        for sv in ss:
+            sv.close()
+        r["batching_speedup"] = r["batch_heuristic"]["value"] / r["loop_heuristic"]["value"]
+        out[prec] = r
+        progress("batch:", prec, {k: round(v["value"] / 1e9, 3) for k, v in r.items() if isinstance(v, dict)})
+    if not args.skip_tol:
+        # time to a 1e-8 residual for every problem: mixed-precision batch (tuned)
+        # against a loop of plain float64 single-problem solves
+        b = stp.BatchSolver(probs, precision="f32", omega=args.omega, tol=args.tol, max_iter=2000,
+                            check_every=args.check_every)
+        b.autotune(reps=2, use_cache=True)
+        zero()
+        t0 = time.perf_counter()
+        _, _, infos, status = b.solve(us, ps)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        b.close()
+        its = [i["iters"] for i in infos]
+        progress("batch: f32 batch to tol", f"{tb:.2f}s")
+        ss = [stp.SpaceTimeSolver(2, q["n"], q["N"], q["tau"], q["kfields"], q["tcoef"], q["F"], q["u0"],
+                                  precision="f64", omega=args.omega, tol=args.tol, max_iter=2000,
+                                  check_every=args.check_every) for q in probs]
+        zero()
+        t0 = time.perf_counter()
+        its64 = []
+        for i, sv in enumerate(ss):
+            _, _, info = sv.solve(us[i], ps[i])
+            its64.append(info["iters"])
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t0
+        for sv in ss:
+            sv.close()
+        progress("batch: f64 loop to tol", f"{tl:.2f}s")
+        out["time_to_tol"] = dict(tol=args.tol, batch_f32_sec=tb, batch_status=status,
+                                  batch_iters=[min(its), max(its)], loop_f64_sec=tl,
+                                  loop_f64_iters=[min(its64), max(its64)],
+                                  speedup_vs_loop_f64=tl / tb)
+    return out
+
+
 def roofline(rep, dims, ts, steps):
     """Dominant kernel (largest summed device time) and its achieved HBM rate."""
     if not rep:
@@ -212,12 +341,15 @@ def main():
     ap.add_argument("--skip-tol", action="store_true")
     ap.add_argument("--only-f64", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in schedule heuristic")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch workload")
+    ap.add_argument("--batch-steps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU time sharding is a design "
               "(see DESIGN.md), not an implementation.  Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     prob, dims, res = gpu_run(args)
+    progress("workload done:", args.workload)
     r64 = res["f64"]
     roof, table = roofline(r64.get("kernels"), dims, 8, args.steps)
     out = {
@@ -252,6 +384,8 @@ def main():
             out["mixed_f32_precond"]["time_to_tol"] = r32["tol"]
             if "tol" in r64:
                 out["mixed_f32_precond"]["time_to_tol_speedup"] = r64["tol"]["sec"] / r32["tol"]["sec"]
+    if not args.no_batch:
+        out["batch64"] = batch_run(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

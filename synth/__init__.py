@@ -16,5 +16,9 @@ from .workloads import (  # noqa: F401
     manufactured_u,
     small_problem,
     batch2d_problem,
+    batch2d_parts,
+    heat2d_parts,
+    gaussian_factors,
+    source_from_factors,
     CONFIG_BUILDERS,
 )

@@ -88,9 +88,11 @@ def sine_modes(n: int, dim: int, kmax: int, rng: np.random.Generator) -> np.ndar
     return np.einsum("abc,ai,bj,ck->ijk", c, S, S, S, optimize=True)
 
 
-def gaussian_source(n: int, dim: int, N: int, T: float, rng: np.random.Generator,
-                    count: int = 8) -> np.ndarray:
-    """Sum of ``count`` space-time Gaussians a_i exp(-|x-x_i|^2/2s_i^2 - (t-t_i)^2/2sig_i^2).
+def gaussian_factors(n: int, dim: int, N: int, T: float, rng: np.random.Generator,
+                     count: int = 8):
+    """Separable factors of ``count`` space-time Gaussians
+    a_i exp(-|x-x_i|^2/2s_i^2 - (t-t_i)^2/2sig_i^2): a list of (g_t, [g_x, g_y, ...])
+    with g_t of length N (amplitude included) and each g of length n.
 
     Draw order per Gaussian block: centres (dim space coords then t) ~ U[0,1]
     (t scaled by T), widths s ~ U[0.05,0.15], sig ~ U[0.1,0.3], amplitudes a ~ N(0,1).
@@ -101,12 +103,26 @@ def gaussian_source(n: int, dim: int, N: int, T: float, rng: np.random.Generator
     a = rng.standard_normal(count)
     x = _interior(n)
     t = _times(N, T)
-    F = np.zeros((N,) + (n,) * dim)
+    out = []
     for i in range(count):
         gx = [np.exp(-((x - centres[i, ax]) ** 2) / (2 * s[i] ** 2)) for ax in range(dim)]
         gt = a[i] * np.exp(-((t - T * centres[i, dim]) ** 2) / (2 * sig[i] ** 2))
+        out.append((gt, gx))
+    return out
+
+
+def source_from_factors(factors, n: int, dim: int, N: int) -> np.ndarray:
+    """F = sum_i g_t,i (x) (... (x) g_y,i (x) g_x,i), accumulated in factor order."""
+    F = np.zeros((N,) + (n,) * dim)
+    for gt, gx in factors:
         F += np.multiply.outer(gt, _outer(gx))
     return F
+
+
+def gaussian_source(n: int, dim: int, N: int, T: float, rng: np.random.Generator,
+                    count: int = 8) -> np.ndarray:
+    """Sum of ``count`` space-time Gaussians (see ``gaussian_factors``)."""
+    return source_from_factors(gaussian_factors(n, dim, N, T, rng, count), n, dim, N)
 
 
 def lognormal_field(n: int, dim: int, ell: float, contrast: float,
@@ -167,11 +183,10 @@ def heat1d_random(n: int = 63, N: int = 64, T: float = 1.0, seed: int = 1001) ->
     return Problem(1, n, N, T, kf, tc, F, u0, name="heat1d_random", seed=seed)
 
 
-def heat2d_gaussians(n: int = 255, N: int = 256, T: float = 1.0, seed: int = 1002,
-                     phase: float | None = None, kmax: int = 16) -> Problem:
-    """2-D heat.  Default coefficient kappa = 1 + 0.5 sin(2 pi t) cos(pi x)
-    (two separable terms); with ``phase`` given, kappa = 1 + 0.5 sin(2 pi t + phase)
-    (one term).  F = 8 space-time Gaussians; u0 = random sine modes k <= kmax."""
+def heat2d_parts(n: int = 255, N: int = 256, T: float = 1.0, seed: int = 1002,
+                 phase: float | None = None, kmax: int = 16):
+    """Everything of ``heat2d_gaussians`` except the assembled source: returns
+    (kfields, tcoef, source factors, u0); ``source_from_factors`` gives F."""
     rng = np.random.default_rng(seed)
     t = _times(N, T)
     if phase is None:
@@ -181,9 +196,19 @@ def heat2d_gaussians(n: int = 255, N: int = 256, T: float = 1.0, seed: int = 100
     else:
         kf = np.ones((1, n + 2, n + 2))
         tc = (1.0 + 0.5 * np.sin(2 * np.pi * t + phase))[None, :]
-    F = gaussian_source(n, 2, N, T, rng)
+    factors = gaussian_factors(n, 2, N, T, rng)
     u0 = sine_modes(n, 2, min(kmax, n), rng)
-    return Problem(2, n, N, T, np.ascontiguousarray(kf), tc, F, u0, name="heat2d_gaussians", seed=seed)
+    return np.ascontiguousarray(kf), tc, factors, u0
+
+
+def heat2d_gaussians(n: int = 255, N: int = 256, T: float = 1.0, seed: int = 1002,
+                     phase: float | None = None, kmax: int = 16) -> Problem:
+    """2-D heat.  Default coefficient kappa = 1 + 0.5 sin(2 pi t) cos(pi x)
+    (two separable terms); with ``phase`` given, kappa = 1 + 0.5 sin(2 pi t + phase)
+    (one term).  F = 8 space-time Gaussians; u0 = random sine modes k <= kmax."""
+    kf, tc, factors, u0 = heat2d_parts(n, N, T, seed, phase, kmax)
+    F = source_from_factors(factors, n, 2, N)
+    return Problem(2, n, N, T, kf, tc, F, u0, name="heat2d_gaussians", seed=seed)
 
 
 def heat3d_lognormal(n: int = 127, N: int = 128, T: float = 1.0, seed: int = 1003,
@@ -230,6 +255,11 @@ def batch2d(count: int = 64, seed: int = 1004, sides=(63, 127, 255, 511), nt_ran
 
 def batch2d_problem(spec) -> Problem:
     return heat2d_gaussians(n=spec["side"], N=spec["N"], seed=spec["seed"], phase=spec["phase"])
+
+
+def batch2d_parts(spec):
+    """``heat2d_parts`` of one batch problem (source left as factors)."""
+    return heat2d_parts(n=spec["side"], N=spec["N"], seed=spec["seed"], phase=spec["phase"])
 
 
 def small_problem(dim: int, n: int, N: int, seed: int = 7, T: float = 1.0, R: int = 2,
