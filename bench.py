@@ -124,7 +124,7 @@ def gpu_run(args):
         assert info["iters"] == args.steps, info
         sec = t1 - t0
         results[prec] = dict(sec=sec, ms_per_step=1e3 * sec / args.steps, value=dofs * args.steps / sec,
-                             device_ms=info["ms"], autotune=tune)
+                             device_ms=info["ms"], autotune=tune, omega=info["omega"])
         if prec == "f64":
             # per-kernel device times: a second timed region of the same --steps
             # iterations, launched eagerly with a HIP event pair around every launch
@@ -224,8 +224,16 @@ def batch_run(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, infos
 
+    omegas = None
     for prec in ("f32", "f64"):
-        b = stp.BatchSolver(probs, precision=prec, omega=args.omega, tol=0.0, max_iter=K, check_every=K + 1)
+        # the damping is estimated once per problem (first context) and set on the others
+        b = stp.BatchSolver(probs, precision=prec, omega=args.omega if omegas is None else 1.0, tol=0.0,
+                            max_iter=K, check_every=K + 1)
+        if omegas is None:
+            omegas = b.omegas()
+            out["omega"] = dict(min=min(omegas), max=max(omegas), source="estimated" if args.omega <= 0 else "given")
+        else:
+            b.set_omegas(omegas)
         sec, infos = timed_batch(b)
         assert all(i["iters"] == K for i in infos)
         r = dict(batch_heuristic=dict(sec=sec, value=dofs * K / sec))
@@ -237,8 +245,8 @@ def batch_run(args):
         b.close()
         # loop of single-problem contexts, built-in schedule, graph replay each
         ss = [stp.SpaceTimeSolver(2, q["n"], q["N"], q["tau"], q["kfields"], q["tcoef"], q["F"], q["u0"],
-                                  precision=prec, omega=args.omega, tol=0.0, max_iter=K, check_every=K + 1)
-              for q in probs]
+                                  precision=prec, omega=omegas[i], tol=0.0, max_iter=K, check_every=K + 1)
+              for i, q in enumerate(probs)]
         zero()
         for i, sv in enumerate(ss):
             sv.solve(us[i], ps[i])
@@ -257,8 +265,9 @@ def batch_run(args):
     if not args.skip_tol:
         # time to a 1e-8 residual for every problem: mixed-precision batch (tuned)
         # against a loop of plain float64 single-problem solves
-        b = stp.BatchSolver(probs, precision="f32", omega=args.omega, tol=args.tol, max_iter=2000,
+        b = stp.BatchSolver(probs, precision="f32", omega=1.0, tol=args.tol, max_iter=2000,
                             check_every=args.check_every)
+        b.set_omegas(omegas)
         b.autotune(reps=2, use_cache=True)
         zero()
         t0 = time.perf_counter()
@@ -269,8 +278,8 @@ def batch_run(args):
         its = [i["iters"] for i in infos]
         progress("batch: f32 batch to tol", f"{tb:.2f}s")
         ss = [stp.SpaceTimeSolver(2, q["n"], q["N"], q["tau"], q["kfields"], q["tcoef"], q["F"], q["u0"],
-                                  precision="f64", omega=args.omega, tol=args.tol, max_iter=2000,
-                                  check_every=args.check_every) for q in probs]
+                                  precision="f64", omega=omegas[i], tol=args.tol, max_iter=2000,
+                                  check_every=args.check_every) for i, q in enumerate(probs)]
         zero()
         t0 = time.perf_counter()
         its64 = []
@@ -334,7 +343,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="heat2d_255_N256")
-    ap.add_argument("--omega", type=float, default=0.8)
+    ap.add_argument("--omega", type=float, default=0.0, help="Uzawa damping; <= 0: estimated by the library")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -366,7 +375,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "dim": prob.dim, "n_interior": prob.n, "N_t": prob.N,
-                   "dofs": prob.N * prob.npts, "omega": args.omega, "spatial": "mg V(1,1) Jacobi",
+                   "dofs": prob.N * prob.npts, "omega": r64["omega"],
+                   "omega_source": "estimated" if args.omega <= 0 else "given", "spatial": "mg V(1,1) Jacobi",
                    "parallelism": "all time slabs batched in every launch"},
         "roofline": roof,
         "kernels_f64": table,

@@ -90,7 +90,8 @@ typedef struct {
   int precision;        /* STP_PREC_*                                                */
   int spatial;          /* STP_SPATIAL_*                                             */
   int nu_A, nu_H;       /* V-cycles per spatial preconditioner application (>= 1)    */
-  double omega;         /* Uzawa damping (eq. (3.1)); <= 0 selects the default 0.8   */
+  double omega;         /* Uzawa damping (eq. (3.1)); <= 0: estimated per problem at
+                           stp_create (see stp_omega_info)                            */
   double tol;           /* stop at ||f - B u||_2 <= tol ||f||_2                      */
   int max_iter;         /* maximum number of u-updates                               */
   const double* kref_coef; /* host, rank values: kappa_ref = sum_r kref_coef[r] fields[r]
@@ -177,6 +178,21 @@ stp_status stp_apply_precond(stp_ctx* ctx, int which, const double* r, double* z
 stp_status stp_uzawa_solve(stp_ctx* ctx, double* u, double* p, stp_stats* st);
 
 void stp_destroy(stp_ctx* ctx);
+
+/* Damping parameter.  With opt->omega <= 0, stp_create estimates omega for
+ * every problem (Theorem 3.1, eq. (3.7); Theorem 4.1): the extreme
+ * eigenvalues of H~^{-1} S~, S~ = K^T A~^{-1} K + K + K^T + A, as the extreme
+ * Ritz values of 12 conjugate-gradient steps on S~ preconditioned by H~^{-1},
+ * and rho_A by 8 power steps on I - A~^{-1} A, with start vectors from
+ * SplitMix64 at the global index (seeds 0x5EED and 0xA5EED).  omega =
+ * min(0.95 * 2/(lmin + lmax), 0.9 * 2/lmax).  The estimate runs the
+ * iteration's own kernels (about 25 iterations' worth of work) and allocates
+ * five float64 vectors per problem for its duration.
+ * stp_omega_info: out4 = {omega, lambda_min, lambda_max, rho_A} of problem i
+ * (the last three are 0 when omega was given).  stp_set_omega: host array of
+ * P values > 0, used from the next solve on.  Errors: EINVAL. */
+stp_status stp_omega_info(stp_ctx* ctx, int i, double* out4);
+stp_status stp_set_omega(stp_ctx* ctx, const double* omega);
 
 /* Autotuner (project-written).  Times, on the context's own buffers and
  * stream, the candidate schedules of every merged launch of an iteration and

@@ -97,6 +97,10 @@ def load() -> C.CDLL:
     lib.stp_uzawa_solve_batch.restype = C.c_int
     lib.stp_batch_size.argtypes = [C.c_void_p]
     lib.stp_batch_size.restype = C.c_int
+    lib.stp_omega_info.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double)]
+    lib.stp_omega_info.restype = C.c_int
+    lib.stp_set_omega.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+    lib.stp_set_omega.restype = C.c_int
     lib.stp_autotune.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(stp_tune_report)]
     lib.stp_autotune.restype = C.c_int
     lib.stp_schedule_string.argtypes = [C.c_void_p]
@@ -281,6 +285,17 @@ def stp_autotune(ctx, reps=5, use_cache=True):
                 iter_ms_before=r.iter_ms_before, iter_ms_after=r.iter_ms_after)
 
 
+def stp_omega_info(ctx, i=0):
+    out = (C.c_double * 4)()
+    _check(load().stp_omega_info(ctx, int(i), out), "stp_omega_info")
+    return dict(omega=out[0], lmin=out[1], lmax=out[2], rho_A=out[3])
+
+
+def stp_set_omega(ctx, omegas):
+    arr = (C.c_double * len(omegas))(*[float(w) for w in omegas])
+    _check(load().stp_set_omega(ctx, arr), "stp_set_omega")
+
+
 def stp_schedule_string(ctx) -> str:
     return load().stp_schedule_string(ctx).decode()
 
@@ -370,6 +385,9 @@ class SpaceTimeSolver:
     def schedule(self):
         return stp_schedule_string(self.ctx)
 
+    def omega_info(self, i=0):
+        return stp_omega_info(self.ctx, i)
+
     def close(self):
         if self.ctx:
             stp_destroy(self.ctx)
@@ -395,6 +413,12 @@ class BatchSolver:
 
     def __len__(self):
         return len(self.shapes)
+
+    def omegas(self):
+        return [stp_omega_info(self.ctx, i)["omega"] for i in range(len(self.shapes))]
+
+    def set_omegas(self, omegas):
+        stp_set_omega(self.ctx, omegas)
 
     def solve(self, us=None, ps=None):
         """Solve every problem from (us[i], ps[i]) (zeros if None).  Returns (us, ps, infos, status)."""
@@ -423,6 +447,9 @@ class BatchSolver:
 
     def schedule(self):
         return stp_schedule_string(self.ctx)
+
+    def omega_info(self, i=0):
+        return stp_omega_info(self.ctx, i)
 
     def close(self):
         if self.ctx:

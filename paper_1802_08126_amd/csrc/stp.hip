@@ -169,6 +169,9 @@ struct Problem {
   int tpath = TP_DENSE;         // default transform path (the tuner may choose another)
   long resid_tiles = 0;
   long npart = 0;               // residual partials (one per block of the a3 residual launch)
+  double omega = 0.8;           // damping of the u-update (eq. (3.1))
+  bool omega_auto = false;      // omega estimated at setup
+  double est_lmin = 0, est_lmax = 0, est_rho = 0;   // estimates behind an automatic omega
   long nfnorm = 0;              // partials of the setup reduction of ||f||
   // device memory
   DevState* state = nullptr;
@@ -261,7 +264,6 @@ struct SolverBase;
 struct stp_ctx {
   int P = 0, dim = 0, prec = 0, spatial = STP_SPATIAL_MG, rm = 1;
   stp_options opt{};
-  double omega = 0.8;
   hipStream_t stream = nullptr;
   std::vector<Problem> pr;
   void* ws = nullptr;
@@ -518,7 +520,8 @@ void site_path(stp_ctx* c, Site<TimeJob>& s) {
 }
 
 void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, const std::vector<const void*>& in,
-                      const std::vector<void*>& out, const std::vector<double*>& acc64, double alpha) {
+                      const std::vector<void*>& out, const std::vector<double*>& acc64,
+                      const std::vector<double>& alpha) {
   sites.clear();
   for (size_t i = 0; i < c->pr.size(); ++i) {
     Problem& q = c->pr[i];
@@ -543,7 +546,7 @@ void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, c
     j.in = in[i];
     j.out = out[i];
     j.acc64 = acc64[i];
-    j.alpha = alpha;
+    j.alpha = alpha[i];
     j.state = &q.state->done;
     long nb;
     if (s->path == TP_FFT2) {
@@ -613,8 +616,10 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
     j.sb = sched_sb(j.tiles, q.N, c->sched.e[KN_MID]);
     S.mid.add(j, long(j.tiles) * ((q.N + j.sb - 1) / j.sb));
   }
-  build_transforms(c, S.a4, 0, in4, out4, acc4, 1.0);
-  build_transforms(c, S.a6, 1, in6, out6, acc6, c->omega);
+  std::vector<double> one(P, 1.0), om(P);
+  for (size_t i = 0; i < P; ++i) om[i] = c->pr[i].omega;
+  build_transforms(c, S.a4, 0, in4, out4, acc4, one);
+  build_transforms(c, S.a6, 1, in6, out6, acc6, om);
   S.fin.clear();
   for (size_t i = 0; i < P; ++i) {
     Problem& q = c->pr[i];
@@ -686,11 +691,15 @@ stp_status upload_all(stp_ctx* c) {
   return STP_OK;
 }
 
-// Point the per-solve jobs at the caller's u and p (and the transform of
-// Phi^{-1} at accumulation target acc with factor alpha); tables are
-// uploaded on the context's stream.
-stp_status bind_solution(stp_ctx* c, const std::vector<double*>& u, const std::vector<double*>& p,
-                         const std::vector<double*>& acc, double alpha) {
+// Point the per-solve jobs at device vectors: the residual launches read u,
+// p (and f built from F, u0; Fz, when given, replaces both by another
+// vector of the problem's size), the A-tilde cycle accumulates into acc_p,
+// and the inverse transform accumulates alpha * Phi^{-1} yhat into acc_u
+// (alpha < 0: each problem's omega).  Tables are uploaded on the context's
+// stream.
+stp_status bind_jobs(stp_ctx* c, const std::vector<double*>& u, const std::vector<double*>& p,
+                     const std::vector<double*>* Fz, const std::vector<double*>& acc_p,
+                     const std::vector<double*>& acc_u, double alpha) {
   Sites& S = c->sites;
   const size_t P = c->pr.size();
   auto owner = [&](const int* st) -> size_t {
@@ -703,17 +712,20 @@ stp_status bind_solution(stp_ctx* c, const std::vector<double*>& u, const std::v
       const size_t i = owner(j.state);
       j.u = u[i];
       j.p = p[i];
+      j.F = Fz ? (*Fz)[i] : c->pr[i].F;
+      j.u0 = Fz ? (*Fz)[i] : c->pr[i].u0;
     }
   VCycle& A = S.vc[VC_A];
   if (!A.up.empty())
-    for (auto& j : A.up[0].jobs) j.acc64 = p[owner(j.state)];
+    for (auto& j : A.up[0].jobs) j.acc64 = acc_p[owner(j.state)];
   if (!A.coarse.empty())
-    for (auto& j : A.coarse[0].jobs) j.acc64 = p[owner(j.state)];
-  for (auto& j : A.tri.jobs) j.acc64 = p[owner(j.state)];
+    for (auto& j : A.coarse[0].jobs) j.acc64 = acc_p[owner(j.state)];
+  for (auto& j : A.tri.jobs) j.acc64 = acc_p[owner(j.state)];
   for (auto& s : S.a6)
     for (auto& j : s.jobs) {
-      j.acc64 = acc[owner(j.state)];
-      j.alpha = alpha;
+      const size_t i = owner(j.state);
+      j.acc64 = acc_u[i];
+      j.alpha = alpha < 0 ? c->pr[i].omega : alpha;
     }
   stp_status st;
   if ((st = upload_site(c, S.resid[0])) != STP_OK) return st;
@@ -724,6 +736,11 @@ stp_status bind_solution(stp_ctx* c, const std::vector<double*>& u, const std::v
   for (auto& s : S.a6)
     if ((st = upload_site(c, s)) != STP_OK) return st;
   return STP_OK;
+}
+
+stp_status bind_solution(stp_ctx* c, const std::vector<double*>& u, const std::vector<double*>& p,
+                         const std::vector<double*>& acc, double alpha) {
+  return bind_jobs(c, u, p, nullptr, p, acc, alpha);
 }
 
 // ---------------------------------------------------------------------------
@@ -739,6 +756,8 @@ struct SolverBase {
   virtual stp_status run_vcycle(int which) = 0;
   virtual stp_status run_precH() = 0;
   virtual stp_status cast_in(const double* a, void* b, long n) = 0;
+  virtual stp_status cast_out(const void* a, double scale, double* b, long n) = 0;
+  virtual stp_status resid(int which) = 0;
 };
 
 template <typename TS, typename TC>
@@ -1000,6 +1019,15 @@ struct Solver : SolverBase {
     return run_precH();                                  // u += omega H~^{-1} r_u
   }
 
+  stp_status cast_out(const void* a, double scale, double* b, long n) override {
+    KLAUNCH((k_cast_scale64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n,
+            (const TS*)a, scale, b);
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
+  stp_status resid(int which) override { return which == 0 ? run_resid<0>() : run_resid<1>(); }
+
   stp_status cast_in(const double* a, void* b, long n) override {
     KLAUNCH((k_cast_from64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n, a, (TS*)b);
     LAUNCH_CHECK();
@@ -1117,6 +1145,231 @@ stp_status validate_opts(const stp_options* opt) {
   return STP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// automatic damping parameter
+//
+// Theorem 3.1 gives convergence for omega lambda_max < 2 (1 - rho_A)/(1 + rho_A)
+// (eq. (3.7)), with lambda_max the largest eigenvalue of H~^{-1} S and rho_A
+// the contraction of A~^{-1}; Theorem 4.1 bounds the eigenvalues through the
+// constant alpha of eq. (2.2), too loosely to choose omega from.  The library
+// estimates instead, with the iteration's own launches and for every problem
+// of the batch at once:
+//   * lambda_min, lambda_max of H~^{-1} S~, S~ = K^T A~^{-1} K + K + K^T + A
+//     (what one sweep of eq. (3.1) applies to u with p restarted from zero and
+//     f = 0), as the extreme Ritz values of kLanczosSteps steps of conjugate
+//     gradients on S~ preconditioned by H~^{-1} (the Lanczos matrix of the CG
+//     coefficients);
+//   * rho_A by kPowerSteps power steps on I - A~^{-1} A.
+// omega = min(0.95 * 2/(lambda_min + lambda_max), 0.9 * 2/lambda_max): the
+// damping that balances the two spectral ends of the preconditioned
+// Richardson limit (rho_A -> 0), kept clear of the limit 2/lambda_max that
+// (3.7) tends to.  (3.7) itself is much tighter than needed with the rho_A of
+// one V-cycle and is not imposed.  Start vectors: SplitMix64 at the index.
+// ---------------------------------------------------------------------------
+constexpr int kLanczosSteps = 12;
+constexpr int kPowerSteps = 8;
+constexpr int kDotBlocks = 512;
+constexpr unsigned long long kSeedLanczos = 0x5EEDull;
+constexpr unsigned long long kSeedPower = 0xA5EEDull;
+
+// eigenvalue k (0-based, ascending) of the symmetric tridiagonal (d, e), by
+// bisection on Sturm counts (Givens' method)
+double tridiag_eig(const std::vector<double>& d, const std::vector<double>& e, int k) {
+  const int m = int(d.size());
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {   // Gershgorin interval
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < m; ++i) {
+      q = d[i] - x - (i > 0 ? e[i - 1] * e[i - 1] / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0.0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) > k) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+stp_status estimate_omega(stp_ctx* c) {
+  const size_t P = c->pr.size();
+  bool any = false;
+  for (auto& q : c->pr) any = any || q.omega_auto;
+  if (!any) return STP_OK;
+  std::vector<long> nv(P);
+  size_t total = 0;
+  for (size_t i = 0; i < P; ++i) {
+    nv[i] = long(c->pr[i].N) * c->pr[i].g0.npts;
+    total += size_t(5) * nv[i];
+  }
+  const size_t scal = P * (kDotBlocks + 1);
+  double* mem = nullptr;
+  if (hipMalloc((void**)&mem, (total + scal) * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(STP_ENOMEM, "omega estimate: hipMalloc of %zu bytes failed", (total + scal) * 8);
+  }
+  std::vector<double*> r(P), z(P), d(P), q(P), pb(P);
+  {
+    size_t off = 0;
+    for (size_t i = 0; i < P; ++i) {
+      r[i] = mem + off;
+      z[i] = r[i] + nv[i];
+      d[i] = z[i] + nv[i];
+      q[i] = d[i] + nv[i];
+      pb[i] = q[i] + nv[i];
+      off += size_t(5) * nv[i];
+    }
+  }
+  double* part = mem + total;
+  double* slots = part + P * kDotBlocks;
+  std::vector<double> hslots(P);
+  auto grid = [](long n) { return dim3(unsigned((n + kBlock - 1) / kBlock)); };
+  auto body = [&]() -> stp_status {
+    for (size_t i = 0; i < P; ++i) {   // every launch runs: stop flags cleared
+      c->state_host[i] = DevState{};
+      c->state_host[i].fnorm = c->pr[i].fnorm;
+      HIP_TRY(hipMemcpyAsync(c->pr[i].state, &c->state_host[i], sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+    }
+    // per-problem dots a_i . b_i, returned on the host
+    auto dots = [&](const std::vector<double*>& a, const std::vector<double*>& b) -> stp_status {
+      for (size_t i = 0; i < P; ++i) {
+        KLAUNCH(k_dot_partial, dim3(kDotBlocks), dim3(kBlock), 0, c->stream, nv[i], (const double*)a[i],
+                (const double*)b[i], part + i * kDotBlocks);
+        LAUNCH_CHECK();
+        KLAUNCH(k_sum_to, dim3(1), dim3(kBlock), 0, c->stream, (const double*)(part + i * kDotBlocks),
+                long(kDotBlocks), slots + i);
+        LAUNCH_CHECK();
+      }
+      HIP_TRY(hipMemcpyAsync(hslots.data(), slots, P * 8, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      return STP_OK;
+    };
+    auto axpby = [&](size_t i, double a, const double* x, double b, double* y) -> stp_status {
+      KLAUNCH(k_axpby, grid(nv[i]), dim3(kBlock), 0, c->stream, nv[i], a, x, b, y);
+      LAUNCH_CHECK();
+      return STP_OK;
+    };
+    // z_i = H~^{-1} x_i
+    auto precH = [&](const std::vector<double*>& x, const std::vector<double*>& zz) -> stp_status {
+      stp_status st;
+      for (size_t i = 0; i < P; ++i) {
+        if ((st = c->impl->cast_in(x[i], c->pr[i].W1, nv[i])) != STP_OK) return st;
+        HIP_TRY(hipMemsetAsync(zz[i], 0, size_t(nv[i]) * 8, c->stream));
+      }
+      if ((st = bind_jobs(c, zz, zz, nullptr, zz, zz, 1.0)) != STP_OK) return st;
+      return c->impl->run_precH();
+    };
+    // q_i = S~ x_i (pb, q: scratch; q doubles as the zero source while the residuals run)
+    auto stilde = [&](const std::vector<double*>& x) -> stp_status {
+      stp_status st;
+      for (size_t i = 0; i < P; ++i) {
+        HIP_TRY(hipMemsetAsync(q[i], 0, size_t(nv[i]) * 8, c->stream));
+        HIP_TRY(hipMemsetAsync(pb[i], 0, size_t(nv[i]) * 8, c->stream));
+      }
+      if ((st = bind_jobs(c, x, pb, &q, pb, q, 1.0)) != STP_OK) return st;
+      if ((st = c->impl->resid(0)) != STP_OK) return st;         // W1 = K x
+      if ((st = c->impl->run_vcycle(VC_A)) != STP_OK) return st;  // pb = A~^{-1} K x
+      if ((st = c->impl->resid(1)) != STP_OK) return st;         // W1 = -K^T pb - (K + K^T + A) x
+      for (size_t i = 0; i < P; ++i)
+        if ((st = c->impl->cast_out(c->pr[i].W1, -1.0, q[i], nv[i])) != STP_OK) return st;
+      return STP_OK;
+    };
+    stp_status st;
+    // conjugate gradients on S~ with preconditioner H~^{-1}
+    for (size_t i = 0; i < P; ++i) {
+      KLAUNCH(k_fill_pm1, grid(nv[i]), dim3(kBlock), 0, c->stream, nv[i], kSeedLanczos, r[i]);
+      LAUNCH_CHECK();
+    }
+    if ((st = precH(r, z)) != STP_OK) return st;
+    for (size_t i = 0; i < P; ++i) HIP_TRY(hipMemcpyAsync(d[i], z[i], size_t(nv[i]) * 8, hipMemcpyDeviceToDevice, c->stream));
+    if ((st = dots(r, z)) != STP_OK) return st;
+    std::vector<double> rz = hslots, rz0 = hslots;
+    std::vector<std::vector<double>> al(P), be(P);
+    std::vector<char> live(P, 1);
+    for (int k = 0; k < kLanczosSteps; ++k) {
+      if ((st = stilde(d)) != STP_OK) return st;
+      if ((st = dots(d, q)) != STP_OK) return st;
+      std::vector<double> a(P, 0.0);
+      for (size_t i = 0; i < P; ++i) {
+        if (live[i] && !(hslots[i] > 0 && std::isfinite(hslots[i]))) live[i] = 0;   // breakdown
+        a[i] = live[i] ? rz[i] / hslots[i] : 0.0;
+        if ((st = axpby(i, -a[i], q[i], 1.0, r[i])) != STP_OK) return st;
+      }
+      if ((st = precH(r, z)) != STP_OK) return st;
+      if ((st = dots(r, z)) != STP_OK) return st;
+      for (size_t i = 0; i < P; ++i) {
+        if (!live[i]) continue;
+        const double b = hslots[i] / rz[i];
+        al[i].push_back(a[i]);
+        be[i].push_back(b);
+        rz[i] = hslots[i];
+        // an exhausted Krylov space (tiny problems) ends that problem's steps
+        if (!(hslots[i] > 1e-28 * rz0[i]) || !std::isfinite(b)) live[i] = 0;
+        if ((st = axpby(i, 1.0, z[i], b, d[i])) != STP_OK) return st;
+      }
+    }
+    // power steps e <- e - A~^{-1} A e (r reused as e; q is the zero u and f)
+    for (size_t i = 0; i < P; ++i) {
+      KLAUNCH(k_fill_pm1, grid(nv[i]), dim3(kBlock), 0, c->stream, nv[i], kSeedPower, r[i]);
+      LAUNCH_CHECK();
+    }
+    if ((st = dots(r, r)) != STP_OK) return st;
+    for (size_t i = 0; i < P; ++i)
+      if ((st = axpby(i, 1.0 / std::sqrt(hslots[i]), r[i], 0.0, r[i])) != STP_OK) return st;
+    std::vector<double> ratio(P, 0.0);
+    std::vector<char> plive(P, 1);
+    for (int k = 0; k < kPowerSteps; ++k) {
+      for (size_t i = 0; i < P; ++i) HIP_TRY(hipMemsetAsync(q[i], 0, size_t(nv[i]) * 8, c->stream));
+      if ((st = bind_jobs(c, q, r, &q, r, q, 1.0)) != STP_OK) return st;
+      if ((st = c->impl->resid(0)) != STP_OK) return st;         // W1 = -A e
+      if ((st = c->impl->run_vcycle(VC_A)) != STP_OK) return st;  // e += A~^{-1} W1
+      if ((st = dots(r, r)) != STP_OK) return st;
+      for (size_t i = 0; i < P; ++i) {
+        if (!plive[i]) continue;
+        ratio[i] = std::sqrt(hslots[i]);
+        if (!(ratio[i] > 1e-300)) {
+          ratio[i] = 0.0;
+          plive[i] = 0;
+          continue;
+        }
+        if ((st = axpby(i, 1.0 / ratio[i], r[i], 0.0, r[i])) != STP_OK) return st;
+      }
+    }
+    for (size_t i = 0; i < P; ++i) {
+      Problem& pq = c->pr[i];
+      if (!pq.omega_auto) continue;
+      const int m = int(al[i].size());
+      if (m == 0) return fail(STP_EDEVICE, "omega estimate: no conjugate-gradient step for problem %zu", i);
+      std::vector<double> dg(m), off(std::max(0, m - 1));
+      for (int k = 0; k < m; ++k) {
+        dg[k] = 1.0 / al[i][k] + (k > 0 ? be[i][k - 1] / al[i][k - 1] : 0.0);
+        if (k + 1 < m) off[k] = std::sqrt(be[i][k]) / al[i][k];
+      }
+      const double lmin = tridiag_eig(dg, off, 0), lmax = tridiag_eig(dg, off, m - 1);
+      if (!(lmin > 0 && lmax >= lmin && std::isfinite(lmax)))
+        return fail(STP_EDEVICE, "omega estimate failed for problem %zu (lambda %.3e..%.3e)", i, lmin, lmax);
+      pq.est_lmin = lmin;
+      pq.est_lmax = lmax;
+      pq.est_rho = ratio[i];
+      pq.omega = std::min(0.95 * 2.0 / (lmin + lmax), 0.9 * 2.0 / lmax);
+    }
+    return STP_OK;
+  };
+  const stp_status s = body();
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(mem);
+  return s;
+}
+
 int resolve_spatial(int dim, int spatial) {
   if (spatial == STP_SPATIAL_AUTO) return dim == 1 ? STP_SPATIAL_EXACT : STP_SPATIAL_MG;
   return spatial;
@@ -1206,7 +1459,6 @@ size_t stp_workspace_bytes_batch(int P, const stp_grid* grids, const int* N, con
   stp_ctx c;
   c.opt = *opt;
   c.prec = opt->precision;
-  c.omega = opt->omega > 0 ? opt->omega : 0.8;
   std::vector<stp_kappa> kap(P);
   for (int i = 0; i < P; ++i) kap[i].rank = rank[i];
   if (describe(&c, P, grids, N, nullptr, kap.data(), nullptr, nullptr) != STP_OK) return 0;
@@ -1235,11 +1487,12 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
   std::unique_ptr<stp_ctx> c(new stp_ctx());
   c->opt = opt;
   c->prec = opt.precision;
-  c->omega = opt.omega > 0 ? opt.omega : 0.8;
   c->stream = (hipStream_t)hip_stream;
   if ((s = describe(c.get(), P, grids, N, tau, kappa, F, u0)) != STP_OK) return s;
   for (int i = 0; i < P; ++i) {
     Problem& q = c->pr[i];
+    q.omega_auto = !(opt.omega > 0);
+    q.omega = q.omega_auto ? 0.8 : opt.omega;   // replaced by the estimate below when automatic
     q.tcoef.assign(kappa[i].tcoef, kappa[i].tcoef + size_t(q.R) * q.N);
     q.abar.assign(q.R, 0.0);
     if (opt.kref_coef) {
@@ -1330,6 +1583,12 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
   if (!sites_fit(c.get())) return fail(STP_EUNSUPPORTED, "a launch exceeds the dispatch size limit");
   carve_tables(c->sites, (char*)c->ws + c->tables_off);
   if ((s = upload_all(c.get())) != STP_OK) return s;
+  if (c->spatial != STP_SPATIAL_NONE) {
+    if ((s = estimate_omega(c.get())) != STP_OK) return s;
+    build_sites(c.get(), nul, nul);   // f from F and u0 again; omega into the transform jobs
+    carve_tables(c->sites, (char*)c->ws + c->tables_off);
+    if ((s = upload_all(c.get())) != STP_OK) return s;
+  }
   HIP_TRY(hipStreamSynchronize(c->stream));
   *out = c.release();
   return STP_OK;
@@ -1346,6 +1605,24 @@ stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau, const
 }
 
 int stp_batch_size(stp_ctx* c) { return c ? c->P : 0; }
+
+stp_status stp_omega_info(stp_ctx* c, int i, double* out4) {
+  if (!c || !out4 || i < 0 || i >= c->P) return fail(STP_EINVAL, "bad context, problem index or output");
+  const Problem& q = c->pr[i];
+  out4[0] = q.omega;
+  out4[1] = q.est_lmin;
+  out4[2] = q.est_lmax;
+  out4[3] = q.est_rho;
+  return STP_OK;
+}
+
+stp_status stp_set_omega(stp_ctx* c, const double* omega) {
+  if (!c || !omega) return fail(STP_EINVAL, "NULL argument");
+  for (int i = 0; i < c->P; ++i)
+    if (!(omega[i] > 0) || !std::isfinite(omega[i])) return fail(STP_EINVAL, "omega[%d] must be finite and > 0", i);
+  for (int i = 0; i < c->P; ++i) c->pr[i].omega = omega[i];
+  return STP_OK;   // taken into the launch tables when the next solve binds its vectors
+}
 
 void stp_destroy(stp_ctx* c) {
   if (!c) return;
@@ -1456,7 +1733,7 @@ stp_status stp_uzawa_solve_batch(stp_ctx* c, double* const* u, double* const* p,
     c->state_host[i].fnorm = c->pr[i].fnorm;
     HIP_TRY(hipMemcpyAsync(c->pr[i].state, &c->state_host[i], sizeof(DevState), hipMemcpyHostToDevice, c->stream));
   }
-  if ((s = bind_solution(c, uv, pv, uv, c->omega)) != STP_OK) return s;
+  if ((s = bind_solution(c, uv, pv, uv, -1.0)) != STP_OK) return s;
   const bool graph = c->opt.use_graph && !c->kt.on;
   if (graph && (s = capture_iteration(c)) != STP_OK) return s;
   HIP_TRY(hipEventRecord(c->ev0, c->stream));
@@ -1489,7 +1766,7 @@ stp_status stp_uzawa_solve_batch(stp_ctx* c, double* const* u, double* const* p,
     if (stats) {
       stats[i].iters = hs.iter;
       stats[i].rel_res = hs.rel;
-      stats[i].omega_used = c->omega;
+      stats[i].omega_used = c->pr[i].omega;
       stats[i].t_solve_ms = ms;
       stats[i].status = r;
     }

@@ -901,6 +901,48 @@ __global__ void k_scale_copy(long n, const double* __restrict__ a, double s, TC*
   if (i < n) b[i] = TC(a[i] * s);
 }
 
+// ---------------------------------------------------------------------------
+// vector helpers of the damping estimate (setup only)
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea and Flood, 2014) as a counter-based generator:
+// state = seed + (i + 1) * golden gamma, then the output mix; the top 53 bits
+// give a value in [-1, 1).
+__device__ __forceinline__ double splitmix_pm1(unsigned long long i, unsigned long long seed) {
+  unsigned long long z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return double(z >> 11) * 0x1.0p-52 - 1.0;
+}
+
+__global__ void k_fill_pm1(long n, unsigned long long seed, double* __restrict__ out) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) out[i] = splitmix_pm1((unsigned long long)i, seed);
+}
+
+// block partials of a . b over a fixed grid (grid-stride), summed by k_sum_to
+__global__ void __launch_bounds__(kBlock) k_dot_partial(long n, const double* __restrict__ a,
+                                                        const double* __restrict__ b, double* __restrict__ partial) {
+  double v = 0.0;
+  for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < n; i += long(gridDim.x) * kBlock) v += a[i] * b[i];
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// y = a x + b y  (y is not read when b == 0)
+__global__ void k_axpby(long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
+}
+
+// b = s * a, widened to float64
+template <typename TS>
+__global__ void k_cast_scale64(long n, const TS* __restrict__ a, double s, double* __restrict__ b) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) b[i] = s * ld<double>(a, i);
+}
+
 // min over slabs s < S and nodes of sum_r coef[s][r] * fields[r][node]  (block partials)
 __global__ void k_kappa_min(long nnodes, int R, int S, const double* __restrict__ fields,
                             const double* __restrict__ coef, double* __restrict__ partial) {
