@@ -103,10 +103,28 @@ dim3 grid_pts(long npts, int S) {
   return dim3(unsigned(bx), unsigned(gy), unsigned(gz));
 }
 
-enum { TP_FFT2 = 0, TP_STOCKHAM = 1, TP_DENSE = 2 };
+enum { TP_FFT2 = 0, TP_STOCKHAM = 1, TP_DENSE = 2, TP_BLUESTEIN = 3 };
 
-// Transform path for N: two-step register FFT (4 <= N <= 256, power of two),
-// Stockham LDS FFT (other powers of two up to 4096), dense otherwise.
+constexpr int kBlueKey = 1 << 20;        // site key of a Bluestein group: kBlueKey + M
+constexpr int kBlueMaxN = 2048;          // Bluestein for step counts up to this (M <= 4096)
+constexpr size_t kMaxLds = 160 * 1024;   // LDS of one compute unit
+
+// Bluestein FFT length: the smallest power of two >= 2N - 1
+int bluestein_M(int N) {
+  int M = 1;
+  while (M < 2 * N - 1) M *= 2;
+  return M;
+}
+size_t bluestein_lds(int M, int C, size_t tcb) { return (size_t(2) * M * C + size_t(2) * M) * tcb; }
+int bluestein_cols(int M, size_t tcb) {
+  int C = 16;
+  while (C > 1 && (M * C > 4096 || bluestein_lds(M, C, tcb) > kMaxLds)) C /= 2;
+  return C;
+}
+
+// Default transform path for N: two-step register FFT (4 <= N <= 256, power
+// of two), Stockham LDS FFT (other powers of two up to 4096), Bluestein
+// (other N from 17 to 2048), dense otherwise.
 void transform_path(int N, size_t tcb, int& path, int& C, size_t& lds) {
   C = 0;
   lds = 0;
@@ -118,14 +136,29 @@ void transform_path(int N, size_t tcb, int& path, int& C, size_t& lds) {
   if (pow2 && N <= 4096) {
     C = std::max(1, std::min(16, 4096 / N));
     lds = (size_t(2) * N * C + size_t(4) * N) * tcb;
-    if (lds <= 160 * 1024) {
+    if (lds <= kMaxLds) {
       path = TP_STOCKHAM;
       return;
     }
   }
+  if (!pow2 && N > 16 && N <= kBlueMaxN) {
+    const int M = bluestein_M(N);
+    C = bluestein_cols(M, tcb);
+    lds = bluestein_lds(M, C, tcb);
+    path = TP_BLUESTEIN;
+    return;
+  }
   C = 0;
   lds = 0;
   path = TP_DENSE;
+}
+
+// site key of a step count: N (powers of two up to 4096), the Bluestein group
+// kBlueKey + M (other N up to kBlueMaxN), or -1 (the dense group)
+int transform_key(int N) {
+  if (N >= 1 && (N & (N - 1)) == 0 && N <= 4096) return N;
+  if (N <= kBlueMaxN) return kBlueKey + bluestein_M(N);
+  return -1;
 }
 
 bool is_pow2(int N) { return N >= 1 && (N & (N - 1)) == 0; }
@@ -184,8 +217,11 @@ struct Problem {
   void* cMid = nullptr;         // TC, kMaxRank: (2/N) tau abar
   void* sinT = nullptr;         // TC, N x N (dense path)
   void* sinM = nullptr;
-  void* tw = nullptr;           // TC, 2N
+  void* tw = nullptr;           // TC, 2N (Bluestein problems: w_M, 2M)
   void* tw4 = nullptr;          // TC, 2N
+  int blM = 0;                  // Bluestein FFT length (0: not a Bluestein step count)
+  void* chirp = nullptr;        // TC, 2N
+  void* bhat = nullptr;         // TC, 2M
   void* W1 = nullptr;           // TS, N x n^d
   void* W2 = nullptr;
   void* tri = nullptr;          // TC scratch of exact 1-D solves, 2 x N x n
@@ -377,6 +413,8 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp) {
   q.tw = q.tw4 = q.sinT = q.sinM = nullptr;
   // tables of every path the step count can take: dense (default path, or
   // a candidate for N <= 64) and the FFT twiddles (powers of two <= 4096)
+  q.chirp = q.bhat = nullptr;
+  q.blM = 0;
   if (q.tpath == TP_DENSE || q.N <= 64) {
     q.sinT = bp.take(size_t(N) * N * tcb);
     q.sinM = bp.take(size_t(N) * N * tcb);
@@ -384,6 +422,12 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp) {
   if (is_pow2(q.N) && q.N <= 4096) {
     q.tw = bp.take(size_t(2) * N * tcb);
     q.tw4 = bp.take(size_t(2) * N * tcb);
+  } else if (q.N <= kBlueMaxN) {
+    q.blM = bluestein_M(q.N);
+    q.tw = bp.take(size_t(2) * q.blM * tcb);
+    q.tw4 = bp.take(size_t(2) * N * tcb);
+    q.chirp = bp.take(size_t(2) * N * tcb);
+    q.bhat = bp.take(size_t(2) * q.blM * tcb);
   }
   q.W1 = bp.take(size_t(N) * q.g0.npts * tsb);
   q.W2 = bp.take(size_t(N) * q.g0.npts * tsb);
@@ -502,21 +546,26 @@ int fft2_l1(int N) {
 // transform path of a site: the dense group, a tuned choice, or the default
 void site_path(stp_ctx* c, Site<TimeJob>& s) {
   const size_t tcb = tc_bytes(c->prec);
+  s.C = 0;
+  s.lds = 0;
   if (s.key < 0) {
     s.path = TP_DENSE;
-    s.C = 0;
-    s.lds = 0;
     return;
   }
   auto it = c->sched.tpath.find(s.key);
   if (it != c->sched.tpath.end()) {
     s.path = it->second.path;
     s.C = it->second.C;
+  } else if (s.key >= kBlueKey) {
+    const int M = s.key - kBlueKey;
+    s.path = M <= 32 ? TP_DENSE : TP_BLUESTEIN;   // N <= 16: the dense sum is cheaper
+    s.C = s.path == TP_BLUESTEIN ? bluestein_cols(M, tcb) : 0;
   } else {
     size_t lds;
     transform_path(s.key, tcb, s.path, s.C, lds);
   }
-  s.lds = s.path == TP_STOCKHAM ? stockham_lds(s.key, s.C, tcb) : 0;
+  if (s.path == TP_STOCKHAM) s.lds = stockham_lds(s.key, s.C, tcb);
+  if (s.path == TP_BLUESTEIN) s.lds = bluestein_lds(s.key - kBlueKey, s.C, tcb);
 }
 
 void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, const std::vector<const void*>& in,
@@ -525,8 +574,9 @@ void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, c
   sites.clear();
   for (size_t i = 0; i < c->pr.size(); ++i) {
     Problem& q = c->pr[i];
-    // one site per power-of-two step count up to 4096; one dense site for the rest
-    const int key = (is_pow2(q.N) && q.N <= 4096) ? q.N : -1;
+    // one site per power-of-two step count up to 4096, one per Bluestein
+    // length M, and one dense site for the rest
+    const int key = transform_key(q.N);
     Site<TimeJob>* s = nullptr;
     for (auto& t : sites)
       if (t.key == key) s = &t;
@@ -542,6 +592,9 @@ void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, c
     j.N = q.N;
     j.tw = q.tw;
     j.tw4 = q.tw4;
+    j.M = q.blM;
+    j.chirp = q.chirp;
+    j.bhat = q.bhat;
     j.T = mode == 0 ? q.sinT : q.sinM;
     j.in = in[i];
     j.out = out[i];
@@ -552,7 +605,7 @@ void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, c
     if (s->path == TP_FFT2) {
       const int Cc = kBlock >> fft2_l1(q.N);
       nb = (j.npts + Cc - 1) / Cc;
-    } else if (s->path == TP_STOCKHAM) {
+    } else if (s->path == TP_STOCKHAM || s->path == TP_BLUESTEIN) {
       nb = (j.npts + s->C - 1) / s->C;
     } else {
       j.bx = int((j.npts + 63) / 64);
@@ -956,9 +1009,22 @@ struct Solver : SolverBase {
         if (st != STP_OK) return st;
         continue;
       }
-      // Stockham: every job of the site has the same N, hence the same layout
       const int C = s.C;
       const size_t lds = s.lds;
+      if (s.path == TP_BLUESTEIN) {   // every job of the site has the same M
+        if (mode == 0)
+          KLAUNCH_NAMED("k_time_bluestein<a4>", (k_time_bluestein<TS, TC, MODE_A4, 0>), dim3(unsigned(s.blocks)),
+                        dim3(kBlock), lds, c->stream, s.dev, int(s.jobs.size()), C);
+        else if (acc)
+          KLAUNCH_NAMED("k_time_bluestein<a6,add64>", (k_time_bluestein<TS, TC, MODE_A6, 1>), dim3(unsigned(s.blocks)),
+                        dim3(kBlock), lds, c->stream, s.dev, int(s.jobs.size()), C);
+        else
+          KLAUNCH_NAMED("k_time_bluestein<a6>", (k_time_bluestein<TS, TC, MODE_A6, 0>), dim3(unsigned(s.blocks)),
+                        dim3(kBlock), lds, c->stream, s.dev, int(s.jobs.size()), C);
+        LAUNCH_CHECK();
+        continue;
+      }
+      // Stockham: every job of the site has the same N, hence the same layout
       if (mode == 0)
         KLAUNCH_NAMED("k_time_fft<a4>", (k_time_fft<TS, TC, MODE_A4, 0>), dim3(unsigned(s.blocks)), dim3(kBlock), lds,
                       c->stream, s.dev, int(s.jobs.size()), C);
@@ -1043,6 +1109,12 @@ struct Solver : SolverBase {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 1>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    HIP_TRY(hipFuncSetAttribute((const void*)k_time_bluestein<TS, TC, MODE_A4, 0>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    HIP_TRY(hipFuncSetAttribute((const void*)k_time_bluestein<TS, TC, MODE_A6, 0>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    HIP_TRY(hipFuncSetAttribute((const void*)k_time_bluestein<TS, TC, MODE_A6, 1>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     return STP_OK;
   }
 
@@ -1077,7 +1149,44 @@ struct Solver : SolverBase {
       HIP_TRY(hipMemcpyAsync(q.sinM, sM.data(), sM.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
       HIP_TRY(hipStreamSynchronize(c->stream));
     }
-    if (q.tw) {
+    if (q.blM) {
+      // Bluestein tables: w_M^m, w_{4N}^m, chirp c_n = exp(-i pi (n^2 mod 2N) / N),
+      // and Bhat = DFT_M(b) / M with b_m = b_{M-m} = conj(c_m) (|m| < N), by
+      // direct sums with exactly reduced angles
+      const int M = q.blM;
+      std::vector<TC> twm(2 * size_t(M)), tw4(2 * size_t(N)), ch(2 * size_t(N)), bh(2 * size_t(M));
+      std::vector<double> cr(N), ci(N);
+      for (int m = 0; m < M; ++m) {
+        twm[m] = TC(std::cos(2.0 * M_PI * m / M));
+        twm[M + m] = TC(-std::sin(2.0 * M_PI * m / M));
+      }
+      for (int m = 0; m < N; ++m) {
+        tw4[m] = TC(std::cos(M_PI * m / (2.0 * N)));
+        tw4[N + m] = TC(-std::sin(M_PI * m / (2.0 * N)));
+        const long sq = (long(m) * long(m)) % (2L * N);
+        cr[m] = std::cos(M_PI * double(sq) / N);
+        ci[m] = -std::sin(M_PI * double(sq) / N);
+        ch[m] = TC(cr[m]);
+        ch[N + m] = TC(ci[m]);
+      }
+      for (int k = 0; k < M; ++k) {
+        double sr = cr[0], si = -ci[0];   // m = 0
+        for (int m = 1; m < N; ++m) {
+          // b_m = b_{M-m} = conj(c_m): b_m w^{mk} + b_m w^{-mk} = 2 conj(c_m) cos(2 pi m k / M)
+          const long r = (long(m) * long(k)) % M;
+          const double cs = std::cos(2.0 * M_PI * double(r) / M);
+          sr += 2.0 * cr[m] * cs;
+          si -= 2.0 * ci[m] * cs;
+        }
+        bh[k] = TC(sr / M);
+        bh[M + k] = TC(si / M);
+      }
+      HIP_TRY(hipMemcpyAsync(q.tw, twm.data(), twm.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(q.tw4, tw4.data(), tw4.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(q.chirp, ch.data(), ch.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(q.bhat, bh.data(), bh.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+    } else if (q.tw) {
       std::vector<TC> tw(2 * size_t(N)), tw4(2 * size_t(N));
       for (int m = 0; m < N; ++m) {
         tw[m] = TC(std::cos(2.0 * M_PI * m / N));
@@ -1874,11 +1983,14 @@ void describe_schedule(stp_ctx* c) {
     if (v.size() > 1) t += "..";
   }
   for (auto& s : c->sites.a4) {
-    const char* nm = s.path == TP_FFT2 ? "fft2" : (s.path == TP_STOCKHAM ? "stockham" : "dense");
-    if (s.key > 0) snprintf(b, sizeof(b), " dst_N%d:%s", s.key, nm);
+    const char* nm = s.path == TP_FFT2 ? "fft2"
+                     : s.path == TP_STOCKHAM ? "stockham"
+                     : s.path == TP_BLUESTEIN ? "bluestein" : "dense";
+    if (s.key >= kBlueKey) snprintf(b, sizeof(b), " dst_M%d:%s", s.key - kBlueKey, nm);
+    else if (s.key > 0) snprintf(b, sizeof(b), " dst_N%d:%s", s.key, nm);
     else snprintf(b, sizeof(b), " dst_other:%s", nm);
     t += b;
-    if (s.path == TP_STOCKHAM) {
+    if (s.path == TP_STOCKHAM || s.path == TP_BLUESTEIN) {
       snprintf(b, sizeof(b), ",C=%d", s.C);
       t += b;
     }
@@ -1993,13 +2105,21 @@ stp_status stp_autotune(stp_ctx* c, int reps, int use_cache, stp_tune_report* re
     // time transforms: path and Stockham columns per power-of-two step count
     const size_t tcb = tc_bytes(c->prec);
     for (size_t g = 0; g < c->sites.a4.size(); ++g) {
-      const int N = c->sites.a4[g].key;
-      if (N <= 0) continue;
+      const int key = c->sites.a4[g].key;
+      if (key <= 0) continue;
       std::vector<TransformChoice> cand;
-      if (N >= 4 && N <= 256) cand.push_back({TP_FFT2, 0});
-      for (int C = 1; C <= 16; C *= 2)
-        if (stockham_lds(N, C, tcb) <= 160 * 1024) cand.push_back({TP_STOCKHAM, C});
-      if (N <= 64) cand.push_back({TP_DENSE, 0});
+      if (key >= kBlueKey) {   // Bluestein group of FFT length M (every N of the group <= M / 2)
+        const int M = key - kBlueKey;
+        for (int C = 1; C <= 16; C *= 2)
+          if (M * C <= 4096 && bluestein_lds(M, C, tcb) <= kMaxLds) cand.push_back({TP_BLUESTEIN, C});
+        if (M <= 128) cand.push_back({TP_DENSE, 0});
+      } else {
+        const int N = key;
+        if (N >= 4 && N <= 256) cand.push_back({TP_FFT2, 0});
+        for (int C = 1; C <= 16; C *= 2)
+          if (N * C <= 4096 && stockham_lds(N, C, tcb) <= kMaxLds) cand.push_back({TP_STOCKHAM, C});
+        if (N <= 64) cand.push_back({TP_DENSE, 0});
+      }
       const Site<TimeJob> cur = c->sites.a4[g];
       TransformChoice best{cur.path, cur.C};
       double best_t = 0;
@@ -2008,9 +2128,9 @@ stp_status stp_autotune(stp_ctx* c, int reps, int use_cache, stp_tune_report* re
       ++r.candidates;
       for (const auto& ch : cand) {
         if (ch.path == best.path && ch.C == best.C) continue;
-        c->sched.tpath[N] = ch;
+        c->sched.tpath[key] = ch;
         if ((st = rebuild(c, tu, tp)) != STP_OK) {
-          c->sched.tpath[N] = best;
+          c->sched.tpath[key] = best;
           if (st == STP_EUNSUPPORTED) continue;
           return st;
         }
@@ -2022,7 +2142,7 @@ stp_status stp_autotune(stp_ctx* c, int reps, int use_cache, stp_tune_report* re
           best = ch;
         }
       }
-      c->sched.tpath[N] = best;
+      c->sched.tpath[key] = best;
       if ((st = rebuild(c, tu, tp)) != STP_OK) return st;
     }
     return time_ms(c, reps, iter, r.iter_ms_after);

@@ -371,8 +371,11 @@ struct TimeJob {        // transforms along the time axis
   long npts;
   int N;
   int bx;               // column blocks (dense transform)
-  const void* tw;       // FFT twiddles (2N)
+  const void* tw;       // FFT twiddles (2N; Bluestein: 2M)
   const void* tw4;      // quarter-wave twiddles (2N)
+  int M;                // Bluestein FFT length (power of two >= 2N - 1)
+  const void* chirp;    // Bluestein chirp w^{n^2/2} (2N)
+  const void* bhat;     // Bluestein kernel spectrum / M (2M)
   const void* T;        // dense matrix (N x N)
   const void* in;
   void* out;
@@ -408,6 +411,8 @@ __device__ __forceinline__ PointJob to_global(PointJob j) {
 __device__ __forceinline__ TimeJob to_global(TimeJob j) {
   j.tw = gmem(j.tw);
   j.tw4 = gmem(j.tw4);
+  j.chirp = gmem(j.chirp);
+  j.bhat = gmem(j.bhat);
   j.T = gmem(j.T);
   j.in = gmem(j.in);
   j.out = gmem(j.out);
@@ -673,6 +678,121 @@ __global__ void __launch_bounds__(kBlock) k_time_fft(const TimeJob* __restrict__
   const TimeJob J = to_global(jobs[find_job(jobs, njobs)]);
   if (J.state && done_flag(J.state)) return;
   time_fft_body<TS, TC, MODE, ACC64>(J, C, (const TC*)J.tw, (const TC*)J.tw4, (const TS*)J.in, (TS*)J.out, J.acc64);
+}
+
+// ---------------------------------------------------------------------------
+// any N (Bluestein): the length-N DFT of the MODE_A4 / MODE_A6 mappings above
+// (valid for every N, with the even/odd split of A6 at ceil(N/2)) as a chirp
+// convolution,  X_k = c_k sum_n (x_n c_n) conj(c_{k-n}),  c_n = w_N^{n^2/2} =
+// exp(-i pi (n^2 mod 2N) / N),  evaluated with two length-M Stockham FFTs in
+// LDS (M = 2^m >= 2N - 1): A = FFT(x c, zero padded), R = FFT(conj(A Bhat)),
+// X_k = c_k conj(R_k), where Bhat = FFT(b) / M and b holds conj(c) wrapped
+// around (b_m = b_{M-m} = conj(c_m), |m| < N).  Tables: tw = w_M^m (2M),
+// chirp (2N), bhat (2M), tw4 as above.
+// ---------------------------------------------------------------------------
+template <typename TS, typename TC, int MODE, int ACC64>
+__device__ __forceinline__ void time_bluestein_body(const TimeJob& J, int C, const TC* __restrict__ twM,
+                                                    const TC* __restrict__ tw4, const TC* __restrict__ chirp,
+                                                    const TC* __restrict__ bhat, const TS* __restrict__ in,
+                                                    TS* __restrict__ out, double* __restrict__ out64) {
+  const long npts = J.npts;
+  const int N = J.N, M = J.M;
+  const double alpha = J.alpha;
+  const long lb = long(blockIdx.x) - J.block0;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TC* re = reinterpret_cast<TC*>(smem_raw);
+  TC* im = re + M * C;
+  TC* twr = im + M * C;
+  TC* twi = twr + M;
+  const int t = threadIdx.x;
+  for (int q = t; q < M; q += kBlock) {
+    twr[q] = twM[q];
+    twi[q] = twM[M + q];
+  }
+  const int col = t % C, jg = t / C, G = kBlock / C;
+  const long i = lb * C + col;
+  const bool valid = (jg < G) && (i < npts);
+  const int half = (N + 1) / 2;
+  // a_n = s_n c_n for n < N, zero up to M
+  for (int n = jg; n < M; n += G) {
+    TC ar = TC(0), ai = TC(0);
+    if (valid && n < N) {
+      TC sr, si;
+      if (MODE == MODE_A4) {
+        const TC v = ld<TC>(in, long(N - 1 - n) * npts + i);
+        sr = v * tw4[n];
+        si = v * tw4[N + n];
+      } else {
+        const bool even = n < half;
+        const int row = even ? 2 * n : 2 * (N - 1 - n) + 1;
+        const TC v = ld<TC>(in, long(row) * npts + i);
+        sr = even ? v : -v;
+        si = TC(0);
+      }
+      const TC cr = chirp[n], ci = chirp[N + n];
+      ar = sr * cr - si * ci;
+      ai = sr * ci + si * cr;
+    }
+    re[n * C + col] = ar;
+    im[n * C + col] = ai;
+  }
+  __syncthreads();
+  auto fft = [&]() {
+    int Ns = 1;
+    while (Ns < M) {
+      if ((M / Ns) % 4 == 0) {
+        fft_stage<TC, 4, 4>(re, im, twr, twi, M, Ns, C, col, jg, G);
+        Ns *= 4;
+      } else {
+        fft_stage<TC, 2, 8>(re, im, twr, twi, M, Ns, C, col, jg, G);
+        Ns *= 2;
+      }
+    }
+  };
+  fft();
+  // conj(A_m Bhat_m): the second forward FFT then yields M conj(ifft(A Bhat))
+  for (int m = jg; m < M; m += G) {
+    if (jg < G) {
+      const TC xr = re[m * C + col], xi = im[m * C + col];
+      const TC br = bhat[m], bi = bhat[M + m];
+      re[m * C + col] = xr * br - xi * bi;
+      im[m * C + col] = -(xr * bi + xi * br);
+    }
+  }
+  __syncthreads();
+  fft();
+  // X_k = c_k conj(R_k), k < N
+  for (int k = jg; k < N; k += G) {
+    if (jg < G) {
+      const TC rr = re[k * C + col], ri = -im[k * C + col];
+      const TC cr = chirp[k], ci = chirp[N + k];
+      re[k * C + col] = rr * cr - ri * ci;
+      im[k * C + col] = rr * ci + ri * cr;
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+  for (int n = jg; n < N; n += G) {
+    TC v;
+    if (MODE == MODE_A4) {
+      const int m = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
+      v = (n & 1) ? -re[m * C + col] : re[m * C + col];
+    } else {
+      const int m = N - 1 - n;
+      v = tw4[m] * re[m * C + col] - tw4[N + m] * im[m * C + col];
+    }
+    const long o = long(n) * npts + i;
+    if (ACC64) out64[o] += alpha * double(v);
+    else st<TS, TC>(out, o, TC(alpha) * v);
+  }
+}
+
+template <typename TS, typename TC, int MODE, int ACC64>
+__global__ void __launch_bounds__(kBlock) k_time_bluestein(const TimeJob* __restrict__ jobs, int njobs, int C) {
+  const TimeJob J = to_global(jobs[find_job(jobs, njobs)]);
+  if (J.state && done_flag(J.state)) return;
+  time_bluestein_body<TS, TC, MODE, ACC64>(J, C, (const TC*)J.tw, (const TC*)J.tw4, (const TC*)J.chirp,
+                                           (const TC*)J.bhat, (const TS*)J.in, (TS*)J.out, J.acc64);
 }
 
 // ---------------------------------------------------------------------------

@@ -191,3 +191,22 @@ def test_graph_replay_matches_eager():
     assert np.array_equal(host(u2), ue) and np.array_equal(host(p2), pe)
     eager.close()
     g.close()
+
+
+@pytest.mark.parametrize("N", [3, 7, 17, 33, 63, 100, 127, 255, 500, 1000, 1019, 2047])
+@pytest.mark.parametrize("d,n", [(1, 7), (2, 3)])
+def test_apply_precond_H_any_N(d, n, N):
+    """H~^{-1} at step counts that are not powers of two: the time transforms
+    run as Bluestein convolutions (N > 16) or dense sums (N <= 16)."""
+    import paper_1802_08126_amd as stp
+    prob = synth.small_problem(d, n, N, seed=N)
+    s = solver(prob, spatial="mg")
+    pc = Preconditioners(prob, spatial="mg")
+    r = np.random.default_rng(N).standard_normal((N,) + (n,) * d)
+    got = host(s.apply_precond(stp.STP_PC_H, dev(r)))
+    assert relmax(got, pc.Hinv(r)) < 1e-11
+    s.close()
+    s = solver(prob, spatial="mg", precision="f32")
+    got = host(s.apply_precond(stp.STP_PC_H, dev(r)))
+    assert relmax(got, pc.Hinv(r)) < 2e-5
+    s.close()

@@ -77,7 +77,9 @@ def test_cache_reuses_schedule():
 def test_tuned_batch_matches_oracle():
     import paper_1802_08126_amd as stp
     probs = [synth.small_problem(2, 31, 16, seed=41), synth.small_problem(2, 7, 12, seed=42),
-             synth.small_problem(2, 15, 64, seed=43), synth.small_problem(2, 63, 8, seed=44)]
+             synth.small_problem(2, 15, 64, seed=43), synth.small_problem(2, 63, 8, seed=44),
+             synth.small_problem(2, 7, 40, seed=45), synth.small_problem(2, 15, 100, seed=46),
+             synth.small_problem(2, 3, 33, seed=47)]
     kw = dict(omega=0.7, tol=0.0, max_iter=3, check_every=2)
     b = stp.BatchSolver([stp.problem_dict(q) for q in probs], **kw)
     b.autotune(reps=2, use_cache=False)
