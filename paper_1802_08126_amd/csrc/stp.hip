@@ -201,6 +201,7 @@ struct Problem {
   Geom g0{};
   int tpath = TP_DENSE;         // default transform path (the tuner may choose another)
   long resid_tiles = 0;
+  int fuse_top = 0;             // first multigrid level solved by the fused coarse kernel
   long npart = 0;               // residual partials (one per block of the a3 residual launch)
   double omega = 0.8;           // damping of the u-update (eq. (3.1))
   bool omega_auto = false;      // omega estimated at setup
@@ -234,6 +235,7 @@ struct Site {
   J* dev = nullptr;
   long blocks = 0;
   int key = 0;     // transform sites: N (-1: the dense group of other step counts)
+  size_t shmem = 0;               // fused multigrid sites: dynamic LDS of the launch
   int epi = 0;
   int path = TP_DENSE, C = 0;   // transform sites: path and Stockham columns
   size_t lds = 0;
@@ -246,7 +248,7 @@ struct Site {
 
 struct VCycle {
   std::vector<Site<TileJob>> down, up;   // by level l = 0 .. Lmax-2
-  std::vector<Site<PointJob>> coarse;    // by coarsest level index 0 .. Lmax-1
+  std::vector<Site<FuseJob>> fused;      // by fused top level index 0 .. Lmax-1
   Site<PointJob> tri;                    // exact 1-D solves
 };
 
@@ -442,6 +444,19 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp) {
   }
 }
 
+// largest level (interior nodes per axis) of the fused coarse kernel: four
+// node arrays per level stay within 64 KB of LDS in float64
+int fuse_side(int dim) { return dim == 1 ? 255 : (dim == 2 ? 31 : 7); }
+
+size_t fuse_lds(int dim, const FuseJob& j, size_t tcb) {
+  size_t t = 0;
+  for (int l = 0; l < j.nlev; ++l) {
+    const size_t m = size_t(j.n[l]) + 2;
+    t += 4 * (dim == 1 ? m : (dim == 2 ? m * m : m * m * m)) * tcb;
+  }
+  return t;
+}
+
 stp_status build_levels(int spatial, Problem& q) {
   q.lv.clear();
   int n = q.n;
@@ -459,6 +474,9 @@ stp_status build_levels(int spatial, Problem& q) {
     if (int(q.lv.size()) >= STP_MAX_LEVELS) return fail(STP_EUNSUPPORTED, "too many multigrid levels");
   }
   q.g0 = q.lv[0].g;
+  // levels with at most fuse_side(dim) nodes per axis run inside one fused kernel
+  q.fuse_top = int(q.lv.size()) - 1;
+  while (q.fuse_top > 0 && q.lv[q.fuse_top - 1].n <= fuse_side(q.dim)) --q.fuse_top;
   return STP_OK;
 }
 
@@ -477,7 +495,7 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top)
   for (auto& q : c->pr) Lmax = std::max(Lmax, int(q.lv.size()));
   vc.down.assign(std::max(0, Lmax - 1), Site<TileJob>());
   vc.up.assign(std::max(0, Lmax - 1), Site<TileJob>());
-  vc.coarse.assign(Lmax, Site<PointJob>());
+  vc.fused.assign(Lmax, Site<FuseJob>());
   vc.tri = Site<PointJob>();
   for (size_t i = 0; i < c->pr.size(); ++i) {
     Problem& q = c->pr[i];
@@ -497,8 +515,10 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top)
       vc.tri.epi = acc ? EPI_ADD64 : EPI_STORE;
       continue;
     }
+    if (c->spatial != STP_SPATIAL_MG) continue;   // operators only: no V-cycle launches
     const int Lq = int(q.lv.size());
-    for (int l = 0; l + 1 < Lq; ++l) {
+    const int ft = q.fuse_top;
+    for (int l = 0; l < ft; ++l) {
       TileJob d{};
       d.gf = q.lv[l].g;
       d.gc = q.lv[l + 1].g;
@@ -523,17 +543,22 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top)
       vc.up[l].add(u, long(u.tiles) * ((q.N + u.sb - 1) / u.sb));
       vc.up[l].epi = (l == 0 && acc) ? EPI_ADD64 : EPI_STORE;
     }
-    const int cl = Lq - 1;
-    PointJob pj{};
-    pj.g = q.lv[cl].g;
-    pj.total = long(q.N) * pj.g.npts;
-    pj.op = family_op(q, cl, fam);
-    pj.b = (cl == 0) ? T.in : q.lv[cl].b;
-    pj.out = (cl == 0) ? T.out : q.lv[cl].e;
-    pj.acc64 = (cl == 0) ? T.acc64 : nullptr;
-    pj.state = &q.state->done;
-    vc.coarse[cl].add(pj, (pj.total + kBlock - 1) / kBlock);
-    vc.coarse[cl].epi = (cl == 0 && acc) ? EPI_ADD64 : EPI_STORE;
+    FuseJob fj{};
+    fj.S = q.N;
+    fj.nlev = Lq - ft;
+    for (int k = 0; k < fj.nlev; ++k) {
+      fj.n[k] = q.lv[ft + k].n;
+      fj.kap[k] = q.lv[ft + k].kscaled;
+    }
+    fj.op = family_op(q, ft, fam);
+    fj.b = (ft == 0) ? T.in : q.lv[ft].b;
+    fj.out = (ft == 0) ? T.out : q.lv[ft].e;
+    fj.acc64 = (ft == 0) ? T.acc64 : nullptr;
+    fj.state = &q.state->done;
+    Site<FuseJob>& fs = vc.fused[ft];
+    fs.add(fj, q.N);
+    fs.epi = (ft == 0 && acc) ? EPI_ADD64 : EPI_STORE;
+    fs.shmem = std::max(fs.shmem, fuse_lds(q.dim, fj, tc_bytes(c->prec)));
   }
 }
 
@@ -692,7 +717,7 @@ void for_each_site(Sites& S, F&& f) {
   for (auto& v : S.vc) {
     for (auto& x : v.down) f(x);
     for (auto& x : v.up) f(x);
-    for (auto& x : v.coarse) f(x);
+    for (auto& x : v.fused) f(x);
     f(v.tri);
   }
   f(S.mid);
@@ -712,6 +737,7 @@ bool sites_fit(stp_ctx* c) {
   bool ok = true;
   for_each_site(c->sites, [&](auto& s) {
     if (double(s.blocks) * kBlock > 4294967295.0) ok = false;
+    if (s.shmem > 65536) ok = false;   // fused multigrid launches stay within the default LDS limit
   });
   return ok;
 }
@@ -771,8 +797,8 @@ stp_status bind_jobs(stp_ctx* c, const std::vector<double*>& u, const std::vecto
   VCycle& A = S.vc[VC_A];
   if (!A.up.empty())
     for (auto& j : A.up[0].jobs) j.acc64 = acc_p[owner(j.state)];
-  if (!A.coarse.empty())
-    for (auto& j : A.coarse[0].jobs) j.acc64 = acc_p[owner(j.state)];
+  if (!A.fused.empty())
+    for (auto& j : A.fused[0].jobs) j.acc64 = acc_p[owner(j.state)];
   for (auto& j : A.tri.jobs) j.acc64 = acc_p[owner(j.state)];
   for (auto& s : S.a6)
     for (auto& j : s.jobs) {
@@ -784,7 +810,7 @@ stp_status bind_jobs(stp_ctx* c, const std::vector<double*>& u, const std::vecto
   if ((st = upload_site(c, S.resid[0])) != STP_OK) return st;
   if ((st = upload_site(c, S.resid[1])) != STP_OK) return st;
   if (!A.up.empty() && (st = upload_site(c, A.up[0])) != STP_OK) return st;
-  if (!A.coarse.empty() && (st = upload_site(c, A.coarse[0])) != STP_OK) return st;
+  if (!A.fused.empty() && (st = upload_site(c, A.fused[0])) != STP_OK) return st;
   if ((st = upload_site(c, A.tri)) != STP_OK) return st;
   for (auto& s : S.a6)
     if ((st = upload_site(c, s)) != STP_OK) return st;
@@ -820,15 +846,16 @@ struct Solver : SolverBase {
 
   TC omegaJ() const { return c->dim == 1 ? TC(2.0 / 3.0) : (c->dim == 2 ? TC(4.0 / 5.0) : TC(6.0 / 7.0)); }
 
-  template <int D>
-  stp_status coarse_site(Site<PointJob>& s, int level) {
+  template <int D, int RM>
+  stp_status fused_site(Site<FuseJob>& s, int level) {
+    if (s.jobs.empty()) return STP_OK;
     c->kt.level = level;
     if (s.epi == EPI_ADD64)
-      KLAUNCH_NAMED("k_coarsest<add64>", (k_coarsest<D, TS, TC, EPI_ADD64>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
-                    c->stream, s.dev, int(s.jobs.size()));
+      KLAUNCH_NAMED("k_mg_fused<add64>", (k_mg_fused<D, TS, TC, RM, EPI_ADD64>), dim3(unsigned(s.blocks)),
+                    dim3(kBlock), s.shmem, c->stream, s.dev, int(s.jobs.size()), omegaJ());
     else
-      KLAUNCH_NAMED("k_coarsest<store>", (k_coarsest<D, TS, TC, EPI_STORE>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
-                    c->stream, s.dev, int(s.jobs.size()));
+      KLAUNCH_NAMED("k_mg_fused<store>", (k_mg_fused<D, TS, TC, RM, EPI_STORE>), dim3(unsigned(s.blocks)),
+                    dim3(kBlock), s.shmem, c->stream, s.dev, int(s.jobs.size()), omegaJ());
     LAUNCH_CHECK();
     return STP_OK;
   }
@@ -837,12 +864,11 @@ struct Solver : SolverBase {
   stp_status vcycle_dr(VCycle& vc) {
     const int nl = int(vc.down.size());
     stp_status st;
-    if (!vc.coarse.empty() && !vc.coarse[0].jobs.empty())   // single-node problems
-      if ((st = coarse_site<D>(vc.coarse[0], 0)) != STP_OK) return st;
+    if (!vc.fused.empty())   // problems solved entirely by the fused kernel
+      if ((st = fused_site<D, RM>(vc.fused[0], 0)) != STP_OK) return st;
     for (int l = 0; l < nl; ++l) {
       if ((st = down_site<D, RM>(vc.down[l], l)) != STP_OK) return st;
-      if (!vc.coarse[l + 1].jobs.empty())
-        if ((st = coarse_site<D>(vc.coarse[l + 1], l + 1)) != STP_OK) return st;
+      if ((st = fused_site<D, RM>(vc.fused[l + 1], l + 1)) != STP_OK) return st;
     }
     for (int l = nl - 1; l >= 0; --l)
       if ((st = up_site<D, RM>(vc.up[l], l)) != STP_OK) return st;
@@ -1921,18 +1947,17 @@ std::string tune_key(stp_ctx* c) {
 std::vector<int> knob_sbs(stp_ctx* c, int k, int e) {
   std::vector<int> v;
   for (auto& q : c->pr) {
-    const int Lq = int(q.lv.size());
     const bool mg = c->spatial == STP_SPATIAL_MG;
     long tiles = -1;
     if (k == KN_R0 || k == KN_R1) tiles = q.resid_tiles;
     else if (k == KN_MID) tiles = tiles_up_d(q.dim, q.n);
-    else if (k == KN_UPA0) tiles = (mg && Lq > 1) ? tiles_up_d(q.dim, q.n) : -1;
+    else if (k == KN_UPA0) tiles = (mg && q.fuse_top > 0) ? tiles_up_d(q.dim, q.n) : -1;
     else if (k < KN_UP0) {
       const int l = k - KN_DOWN0;
-      tiles = (mg && Lq > l + 1) ? tiles_down_d(q.dim, q.lv[l + 1].n) : -1;
+      tiles = (mg && l < q.fuse_top) ? tiles_down_d(q.dim, q.lv[l + 1].n) : -1;
     } else {
       const int l = k - KN_UP0;
-      tiles = (mg && Lq > l + 1) ? tiles_up_d(q.dim, q.lv[l].n) : -1;
+      tiles = (mg && l < q.fuse_top) ? tiles_up_d(q.dim, q.lv[l].n) : -1;
     }
     if (tiles > 0) v.push_back(sched_sb(tiles, q.N, e));
   }

@@ -354,7 +354,7 @@ struct TileJob {        // multigrid level kernels and the tile operator
   const int* state;     // the problem's stop flag
 };
 
-struct PointJob {       // single-node coarsest levels and exact 1-D solves
+struct PointJob {       // exact 1-D solves
   long block0;
   long total;           // slabs * points (coarsest) or slabs (1-D solve)
   Geom g;
@@ -430,25 +430,6 @@ __device__ __forceinline__ int find_job(const J* __restrict__ jobs, int njobs) {
     else hi = mid - 1;
   }
   return lo;
-}
-
-// Coarsest level (one node): x = b / D, stored or added into a float64 vector
-template <int D, typename TS, typename TC, int EPI>
-__global__ void __launch_bounds__(kBlock) k_coarsest(const PointJob* __restrict__ jobs, int njobs) {
-  const PointJob J = to_global(jobs[find_job(jobs, njobs)]);
-  if (J.state && done_flag(J.state)) return;
-  const long q = (long(blockIdx.x) - J.block0) * kBlock + threadIdx.x;  // slab * npts + i
-  if (q >= J.total) return;
-  const Geom g = J.g;
-  const int s = int(q / g.npts);
-  const long i = q - long(s) * g.npts;
-  int px, py, pz;
-  decode<D>(i, g.n, px, py, pz);
-  const SlabOp<TC> op = level_op<TC>(J.op, s);
-  const TC dg = diag_at<D, TC>(px, py, pz, g, (const TC*)J.op.kap, op, J.op.R);
-  const TC v = ld<TC>((const TS*)J.b, q) / dg;
-  if (EPI == EPI_STORE) st<TS, TC>((TS*)J.out, q, v);
-  else J.acc64[q] += double(v);
 }
 
 // Exact 1-D solve per slab (Thomas algorithm), one thread per slab, 64 per block.

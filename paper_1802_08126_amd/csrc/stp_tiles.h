@@ -533,6 +533,227 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RM 
 }
 
 // ---------------------------------------------------------------------------
+// fused coarse levels: one block per slab runs the whole V-cycle below (and
+// including) the fused top level in LDS -- Jacobi from zero, residual and
+// full-weighting restriction on the way down, the exact solve on the
+// one-node level, multilinear prolongation and the post-sweep on the way up,
+// with the formulas of k_mg_down / k_mg_up / k_coarsest.  Every level keeps
+// four node-layout arrays ((n+2)^d, boundary nodes zero): the slab-combined
+// scaled coefficient, b, the pre-smoothed iterate x, and y (the residual on the
+// way down, the level's result on the way up).
+// ---------------------------------------------------------------------------
+constexpr int kMaxFuse = 9;
+
+struct FuseJob {
+  long block0;
+  int S;                        // slabs; one block each
+  int nlev;                     // fused levels, top first; the last has one node
+  int n[kMaxFuse];              // interior nodes per axis
+  const void* kap[kMaxFuse];    // scaled fields of each level (TC, R x (n+2)^d)
+  LevelOp op;                   // slab rows (op.kap unused)
+  const void* b;                // top-level right-hand side (TS)
+  void* out;                    // top-level result (TS), or
+  double* acc64;                // float64 accumulation target
+  const int* state;
+};
+
+__device__ __forceinline__ FuseJob to_global(FuseJob j) {
+  for (int l = 0; l < kMaxFuse; ++l) j.kap[l] = gmem(j.kap[l]);
+  j.op = to_global(j.op);
+  j.b = gmem(j.b);
+  j.out = gmem(j.out);
+  j.acc64 = gmem(j.acc64);
+  j.state = gmem(j.state);
+  return j;
+}
+
+template <int D>
+__host__ __device__ __forceinline__ long fuse_nodes(int n) {
+  const long m = n + 2;
+  return D == 1 ? m : (D == 2 ? m * m : m * m * m);
+}
+
+// node index of interior point q (0 <= q < n^d), coordinates 1..n
+template <int D>
+__device__ __forceinline__ int fuse_node_of(int q, int n, int& x, int& y, int& z) {
+  const int m = n + 2;
+  x = q % n + 1;
+  y = D >= 2 ? (q / n) % n + 1 : 0;
+  z = D >= 3 ? q / (n * n) + 1 : 0;
+  return D == 1 ? x : (D == 2 ? y * m + x : (z * m + y) * m + x);
+}
+
+template <int D, typename TS, typename TC, int RM, int EPI>
+__device__ __forceinline__ void mg_fused_body(const FuseJob& J, int s, TC omega, const TS* __restrict__ bin,
+                                              TS* __restrict__ out, double* __restrict__ acc64) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TC* base = reinterpret_cast<TC*>(smem_raw);
+  TC* kap[kMaxFuse];
+  TC* bb[kMaxFuse];
+  TC* xx[kMaxFuse];
+  TC* yy[kMaxFuse];
+  const int L = J.nlev;
+  {
+    long off = 0;
+    for (int l = 0; l < L; ++l) {
+      const long nn = fuse_nodes<D>(J.n[l]);
+      kap[l] = base + off;
+      bb[l] = kap[l] + nn;
+      xx[l] = bb[l] + nn;
+      yy[l] = xx[l] + nn;
+      off += 4 * nn;
+    }
+  }
+  const SlabOp<TC> op = level_op<TC>(J.op, s);
+  const int t = threadIdx.x;
+  // coefficients of this slab on every level; zero iterates (boundary nodes stay zero)
+  for (int l = 0; l < L; ++l) {
+    const long nn = fuse_nodes<D>(J.n[l]);
+    const TC* kl = (const TC*)J.kap[l];
+    for (long q = t; q < nn; q += kBlock) {
+      TC v = op.c[0] * kl[q];
+#pragma unroll
+      for (int r = 1; r < RM; ++r)
+        if (r < J.op.R) v += op.c[r] * kl[r * nn + q];
+      kap[l][q] = v;
+      bb[l][q] = TC(0);
+      xx[l][q] = TC(0);
+      yy[l][q] = TC(0);
+    }
+  }
+  __syncthreads();
+  {
+    const int n = J.n[0];
+    const long np = fuse_nodes<D>(n) - 0;
+    const int cnt = D == 1 ? n : (D == 2 ? n * n : n * n * n);
+    const TS* bs = bin + long(s) * cnt;
+    (void)np;
+    for (int q = t; q < cnt; q += kBlock) {
+      int x, y, z;
+      bb[0][fuse_node_of<D>(q, n, x, y, z)] = ld<TC>(bs, q);
+    }
+  }
+  __syncthreads();
+  auto diag = [&](const TC* k, int i, int sy, int sz) -> TC {
+    const TC kc = k[i];
+    TC d = op.sigma + TC(2 * D) * kc + k[i - 1] + k[i + 1];
+    if (D >= 2) d += k[i - sy] + k[i + sy];
+    if (D >= 3) d += k[i - sz] + k[i + sz];
+    return d;
+  };
+  auto offsum = [&](const TC* k, const TC* v, int i, int sy, int sz) -> TC {
+    const TC kc = k[i];
+    TC o = (kc + k[i - 1]) * v[i - 1] + (kc + k[i + 1]) * v[i + 1];
+    if (D >= 2) o += (kc + k[i - sy]) * v[i - sy] + (kc + k[i + sy]) * v[i + sy];
+    if (D >= 3) o += (kc + k[i - sz]) * v[i - sz] + (kc + k[i + sz]) * v[i + sz];
+    return o;
+  };
+  const TC one_m_omega = TC(1) - omega;
+  // down: x = omega D^-1 b, y = b - L x, b_{l+1} = R y
+  for (int l = 0; l + 1 < L; ++l) {
+    const int n = J.n[l], m = n + 2, sy = m, sz = m * m;
+    const int cnt = D == 1 ? n : (D == 2 ? n * n : n * n * n);
+    for (int q = t; q < cnt; q += kBlock) {
+      int x, y, z;
+      const int i = fuse_node_of<D>(q, n, x, y, z);
+      xx[l][i] = omega * bb[l][i] * rcp_fast(diag(kap[l], i, sy, sz));
+    }
+    __syncthreads();
+    for (int q = t; q < cnt; q += kBlock) {
+      int x, y, z;
+      const int i = fuse_node_of<D>(q, n, x, y, z);
+      yy[l][i] = one_m_omega * bb[l][i] + offsum(kap[l], xx[l], i, sy, sz);
+    }
+    __syncthreads();
+    const int nc = J.n[l + 1], mc = nc + 2;
+    const int cntc = D == 1 ? nc : (D == 2 ? nc * nc : nc * nc * nc);
+    for (int q = t; q < cntc; q += kBlock) {
+      int X, Y, Z;
+      const int ic = fuse_node_of<D>(q, nc, X, Y, Z);
+      const int c = D == 1 ? 2 * X : (D == 2 ? (2 * Y) * m + 2 * X : ((2 * Z) * m + 2 * Y) * m + 2 * X);
+      TC acc = 0;
+#pragma unroll
+      for (int dz = (D >= 3 ? -1 : 0); dz <= (D >= 3 ? 1 : 0); ++dz)
+#pragma unroll
+        for (int dy = (D >= 2 ? -1 : 0); dy <= (D >= 2 ? 1 : 0); ++dy) {
+          TC w = 1;
+          if (D >= 2) w *= (dy == 0 ? TC(0.5) : TC(0.25));
+          if (D >= 3) w *= (dz == 0 ? TC(0.5) : TC(0.25));
+          const int row = c + dz * sz + dy * sy;
+          acc += w * (TC(0.25) * yy[l][row - 1] + TC(0.5) * yy[l][row] + TC(0.25) * yy[l][row + 1]);
+        }
+      bb[l + 1][ic] = acc;
+      (void)mc;
+    }
+    __syncthreads();
+  }
+  // the one-node level: exact solve
+  {
+    const int l = L - 1, n = J.n[l], m = n + 2;
+    const int cnt = D == 1 ? n : (D == 2 ? n * n : n * n * n);
+    for (int q = t; q < cnt; q += kBlock) {
+      int x, y, z;
+      const int i = fuse_node_of<D>(q, n, x, y, z);
+      yy[l][i] = bb[l][i] / diag(kap[l], i, m, m * m);
+    }
+    __syncthreads();
+  }
+  // up: x += P y_{l+1}; y = (1 - omega) x + omega D^-1 (b + offsum(x))
+  for (int l = L - 2; l >= 0; --l) {
+    const int n = J.n[l], m = n + 2, sy = m, sz = m * m;
+    const int mc = J.n[l + 1] + 2;
+    const TC* e = yy[l + 1];
+    const int cnt = D == 1 ? n : (D == 2 ? n * n : n * n * n);
+    for (int q = t; q < cnt; q += kBlock) {
+      int x, y, z;
+      const int i = fuse_node_of<D>(q, n, x, y, z);
+      const int e0 = D == 1 ? (x >> 1) : (D == 2 ? (y >> 1) * mc + (x >> 1) : ((z >> 1) * mc + (y >> 1)) * mc + (x >> 1));
+      const int ox = x & 1, oy = D >= 2 ? (y & 1) : 0, oz = D >= 3 ? (z & 1) : 0;
+      auto px = [&](int bq) -> TC { return ox ? TC(0.5) * (e[bq] + e[bq + 1]) : e[bq]; };
+      TC pe;
+      if (D == 1) {
+        pe = px(e0);
+      } else if (D == 2) {
+        pe = oy ? TC(0.5) * (px(e0) + px(e0 + mc)) : px(e0);
+      } else {
+        auto pxy = [&](int bq) -> TC { return oy ? TC(0.5) * (px(bq) + px(bq + mc)) : px(bq); };
+        pe = oz ? TC(0.5) * (pxy(e0) + pxy(e0 + mc * mc)) : pxy(e0);
+      }
+      xx[l][i] += pe;
+    }
+    __syncthreads();
+    for (int q = t; q < cnt; q += kBlock) {
+      int x, y, z;
+      const int i = fuse_node_of<D>(q, n, x, y, z);
+      const TC wd = omega * rcp_fast(diag(kap[l], i, sy, sz));
+      yy[l][i] = one_m_omega * xx[l][i] + wd * (bb[l][i] + offsum(kap[l], xx[l], i, sy, sz));
+    }
+    __syncthreads();
+  }
+  // top-level result
+  {
+    const int n = J.n[0];
+    const int cnt = D == 1 ? n : (D == 2 ? n * n : n * n * n);
+    const long o = long(s) * cnt;
+    for (int q = t; q < cnt; q += kBlock) {
+      int x, y, z;
+      const TC v = yy[0][fuse_node_of<D>(q, n, x, y, z)];
+      if (EPI == EPI_STORE) st<TS, TC>(out, o + q, v);
+      else acc64[o + q] += double(v);
+    }
+  }
+}
+
+template <int D, typename TS, typename TC, int RM, int EPI>
+__global__ void __launch_bounds__(kBlock) k_mg_fused(const FuseJob* __restrict__ jobs, int njobs, TC omega) {
+  const FuseJob J = to_global(jobs[find_job(jobs, njobs)]);
+  if (J.state && done_flag(J.state)) return;
+  const int s = int(long(blockIdx.x) - J.block0);
+  if (s >= J.S) return;
+  mg_fused_body<D, TS, TC, RM, EPI>(J, s, omega, (const TS*)J.b, (TS*)J.out, J.acc64);
+}
+
+// ---------------------------------------------------------------------------
 // y = L x (tile version; the middle reference operator of the H-blocks,
 // whose coefficients are the same for every slab)
 // ---------------------------------------------------------------------------
