@@ -420,10 +420,22 @@ __device__ __forceinline__ TimeJob to_global(TimeJob j) {
   j.state = gmem(j.state);
   return j;
 }
+// Logical block index of a merged launch.  The hardware hands workgroups to the
+// eight XCDs round-robin, and each XCD has its own L2; remapping so that XCD x
+// runs the contiguous range [x q, (x + 1) q) of logical blocks (q = grid / 8,
+// the tail unchanged) keeps neighbouring tiles and column chunks, which share
+// halo and straddled cache lines, on one L2.
+__device__ __forceinline__ long block_id() {
+  const long nb = gridDim.x, b = blockIdx.x;
+  const long q = nb >> 3;
+  if (b >= (q << 3)) return b;
+  return (b & 7) * q + (b >> 3);
+}
+
 template <typename J>
 __device__ __forceinline__ int find_job(const J* __restrict__ jobs, int njobs) {
   int lo = 0, hi = njobs - 1;
-  const long b = blockIdx.x;
+  const long b = block_id();
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (jobs[mid].block0 <= b) lo = mid;
@@ -437,7 +449,7 @@ template <typename TS, typename TC, int EPI>
 __global__ void __launch_bounds__(64) k_tridiag(const PointJob* __restrict__ jobs, int njobs) {
   const PointJob J = to_global(jobs[find_job(jobs, njobs)]);
   if (J.state && done_flag(J.state)) return;
-  const int s = int((long(blockIdx.x) - J.block0) * 64 + threadIdx.x);
+  const int s = int((block_id() - J.block0) * 64 + threadIdx.x);
   const LevelOp L = J.op;
   if (s >= L.S) return;
   const Geom g = J.g;
@@ -487,7 +499,7 @@ template <typename TS, typename TC, int ACC64>
 __global__ void __launch_bounds__(kBlock) k_time_dense(const TimeJob* __restrict__ jobs, int njobs) {
   const TimeJob J = to_global(jobs[find_job(jobs, njobs)]);
   if (J.state && done_flag(J.state)) return;
-  const long lb = long(blockIdx.x) - J.block0;
+  const long lb = block_id() - J.block0;
   const int bxi = int(lb % J.bx), byi = int(lb / J.bx);
   const long npts = J.npts;
   const int N = J.N;
@@ -598,7 +610,7 @@ __device__ __forceinline__ void time_fft_body(const TimeJob& J, int C, const TC*
   const long npts = J.npts;
   const int N = J.N;
   const double alpha = J.alpha;
-  const long lb = long(blockIdx.x) - J.block0;
+  const long lb = block_id() - J.block0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TC* re = reinterpret_cast<TC*>(smem_raw);
   TC* im = re + N * C;
@@ -679,7 +691,7 @@ __device__ __forceinline__ void time_bluestein_body(const TimeJob& J, int C, con
   const long npts = J.npts;
   const int N = J.N, M = J.M;
   const double alpha = J.alpha;
-  const long lb = long(blockIdx.x) - J.block0;
+  const long lb = block_id() - J.block0;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TC* re = reinterpret_cast<TC*>(smem_raw);
   TC* im = re + M * C;
@@ -847,7 +859,7 @@ __device__ __forceinline__ void time_fft2_body(const TimeJob& J, const TC* __res
                                                TS* __restrict__ out, double* __restrict__ out64) {
   const long npts = J.npts;
   const double alpha = J.alpha;
-  const long lb = long(blockIdx.x) - J.block0;
+  const long lb = block_id() - J.block0;
   constexpr int N1 = 1 << L1, N2 = 1 << L2, N = N1 * N2;
   constexpr int C = kBlock / N1;             // columns per block
   extern __shared__ __align__(16) unsigned char smem_raw[];

@@ -293,7 +293,7 @@ struct Regs {
 template <typename J>
 __device__ __forceinline__ J job_tile_run(const J* __restrict__ jobs, int njobs, int S, int& tile, int& s0, int& s1) {
   const J job = to_global(jobs[find_job(jobs, njobs)]);
-  const int lb = int(long(blockIdx.x) - job.block0);
+  const int lb = int(block_id() - job.block0);
   tile = lb % job.tiles;
   s0 = (lb / job.tiles) * job.sb;
   s1 = min(S, s0 + job.sb);
@@ -748,7 +748,7 @@ template <int D, typename TS, typename TC, int RM, int EPI>
 __global__ void __launch_bounds__(kBlock) k_mg_fused(const FuseJob* __restrict__ jobs, int njobs, TC omega) {
   const FuseJob J = to_global(jobs[find_job(jobs, njobs)]);
   if (J.state && done_flag(J.state)) return;
-  const int s = int(long(blockIdx.x) - J.block0);
+  const int s = int(block_id() - J.block0);
   if (s >= J.S) return;
   mg_fused_body<D, TS, TC, RM, EPI>(J, s, omega, (const TS*)J.b, (TS*)J.out, J.acc64);
 }
@@ -930,7 +930,7 @@ __device__ __forceinline__ void resid_tile_body(const ResidJob& J, int tile, int
   }
   if (WHICH == 1) {
     const double bs = block_sum(e2);
-    if (threadIdx.x == 0) partial[long(blockIdx.x) - J.block0] = bs;
+    if (threadIdx.x == 0) partial[block_id() - J.block0] = bs;
   }
 }
 
