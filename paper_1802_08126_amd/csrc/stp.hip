@@ -175,7 +175,8 @@ enum Knob {
   KN_UPA0,              // finest up-sweep of the A-tilde cycle (float64 accumulation)
   KN_DOWN0,             // down-sweep into level l + 1 (all three cycles)
   KN_UP0 = KN_DOWN0 + STP_MAX_LEVELS,   // up-sweep on level l, stored output
-  KN_COUNT = KN_UP0 + STP_MAX_LEVELS
+  KN_FUSE = KN_UP0 + STP_MAX_LEVELS,    // threads per block of the fused coarse levels: 256 << e
+  KN_COUNT
 };
 
 struct TransformChoice {
@@ -186,7 +187,10 @@ struct TransformChoice {
 struct Schedule {
   int e[KN_COUNT];
   std::map<int, TransformChoice> tpath;   // per power-of-two step count
-  Schedule() { std::fill(e, e + KN_COUNT, 0); }
+  Schedule() {
+    std::fill(e, e + KN_COUNT, 0);
+    e[KN_FUSE] = 2;   // 1024 threads: the fused kernel has one block per slab
+  }
 };
 
 struct Problem {
@@ -236,6 +240,7 @@ struct Site {
   long blocks = 0;
   int key = 0;     // transform sites: N (-1: the dense group of other step counts)
   size_t shmem = 0;               // fused multigrid sites: dynamic LDS of the launch
+  int threads = 256;              // fused multigrid sites: threads per block
   int epi = 0;
   int path = TP_DENSE, C = 0;   // transform sites: path and Stockham columns
   size_t lds = 0;
@@ -448,6 +453,8 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp) {
 // node arrays per level stay within 64 KB of LDS in float64
 int fuse_side(int dim) { return dim == 1 ? 255 : (dim == 2 ? 31 : 7); }
 
+int fuse_threads(int e) { return 256 << std::max(0, std::min(2, e)); }
+
 size_t fuse_lds(int dim, const FuseJob& j, size_t tcb) {
   size_t t = 0;
   for (int l = 0; l < j.nlev; ++l) {
@@ -559,6 +566,7 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top)
     fs.add(fj, q.N);
     fs.epi = (ft == 0 && acc) ? EPI_ADD64 : EPI_STORE;
     fs.shmem = std::max(fs.shmem, fuse_lds(q.dim, fj, tc_bytes(c->prec)));
+    fs.threads = fuse_threads(c->sched.e[KN_FUSE]);
   }
 }
 
@@ -852,10 +860,10 @@ struct Solver : SolverBase {
     c->kt.level = level;
     if (s.epi == EPI_ADD64)
       KLAUNCH_NAMED("k_mg_fused<add64>", (k_mg_fused<D, TS, TC, RM, EPI_ADD64>), dim3(unsigned(s.blocks)),
-                    dim3(kBlock), s.shmem, c->stream, s.dev, int(s.jobs.size()), omegaJ());
+                    dim3(unsigned(s.threads)), s.shmem, c->stream, s.dev, int(s.jobs.size()), omegaJ());
     else
       KLAUNCH_NAMED("k_mg_fused<store>", (k_mg_fused<D, TS, TC, RM, EPI_STORE>), dim3(unsigned(s.blocks)),
-                    dim3(kBlock), s.shmem, c->stream, s.dev, int(s.jobs.size()), omegaJ());
+                    dim3(unsigned(s.threads)), s.shmem, c->stream, s.dev, int(s.jobs.size()), omegaJ());
     LAUNCH_CHECK();
     return STP_OK;
   }
@@ -907,6 +915,14 @@ struct Solver : SolverBase {
       case KN_R1: return resid_dr<D, 1, RM>();
       case KN_MID: return mid_dr<D, RM>();
       case KN_UPA0: return up_site<D, RM>(c->sites.vc[VC_A].up[0], 0);
+      case KN_FUSE: {
+        VCycle& v = c->sites.vc[VC_H1];
+        for (size_t l = 0; l < v.fused.size(); ++l) {
+          const stp_status st = fused_site<D, RM>(v.fused[l], int(l));
+          if (st != STP_OK) return st;
+        }
+        return STP_OK;
+      }
       default:
         if (knob < KN_UP0) return down_site<D, RM>(c->sites.vc[VC_H1].down[knob - KN_DOWN0], knob - KN_DOWN0);
         return up_site<D, RM>(c->sites.vc[VC_H1].up[knob - KN_UP0], knob - KN_UP0);
@@ -1949,6 +1965,10 @@ std::vector<int> knob_sbs(stp_ctx* c, int k, int e) {
   for (auto& q : c->pr) {
     const bool mg = c->spatial == STP_SPATIAL_MG;
     long tiles = -1;
+    if (k == KN_FUSE) {
+      if (c->spatial == STP_SPATIAL_MG) v.push_back(fuse_threads(e));
+      continue;
+    }
     if (k == KN_R0 || k == KN_R1) tiles = q.resid_tiles;
     else if (k == KN_MID) tiles = tiles_up_d(q.dim, q.n);
     else if (k == KN_UPA0) tiles = (mg && q.fuse_top > 0) ? tiles_up_d(q.dim, q.n) : -1;
@@ -1996,6 +2016,7 @@ void describe_schedule(stp_ctx* c) {
     if (k == KN_R1) return "resid_a3";
     if (k == KN_MID) return "apply_mid";
     if (k == KN_UPA0) return "up_add64_L0";
+    if (k == KN_FUSE) return "fused_threads";
     if (k < KN_UP0) snprintf(nb, sizeof(nb), "down_L%d", k - KN_DOWN0);
     else snprintf(nb, sizeof(nb), "up_L%d", k - KN_UP0);
     return nb;
@@ -2003,7 +2024,8 @@ void describe_schedule(stp_ctx* c) {
   for (int k = 0; k < KN_COUNT; ++k) {
     std::vector<int> v = knob_sbs(c, k, c->sched.e[k]);
     if (v.empty()) continue;
-    snprintf(b, sizeof(b), "%s%s:e=%d,sb=%d", t.empty() ? "" : " ", knob_name(k).c_str(), c->sched.e[k], v[0]);
+    snprintf(b, sizeof(b), "%s%s:e=%d,%s=%d", t.empty() ? "" : " ", knob_name(k).c_str(), c->sched.e[k],
+             k == KN_FUSE ? "threads" : "sb", v[0]);
     t += b;
     if (v.size() > 1) t += "..";
   }

@@ -583,91 +583,96 @@ __device__ __forceinline__ int fuse_node_of(int q, int n, int& x, int& y, int& z
   return D == 1 ? x : (D == 2 ? y * m + x : (z * m + y) * m + x);
 }
 
+template <int D>
+__device__ __forceinline__ int fuse_count(int n) { return D == 1 ? n : (D == 2 ? n * n : n * n * n); }
+
+// Level arrays live at integer offsets of one LDS array (level l: coefficient,
+// b, x, y at off(l) + {0, 1, 2, 3} (n_l+2)^d); per-level sizes and fields are
+// read from the job table (uniform scalar loads), so nothing is indexed
+// dynamically in registers.
 template <int D, typename TS, typename TC, int RM, int EPI>
-__device__ __forceinline__ void mg_fused_body(const FuseJob& J, int s, TC omega, const TS* __restrict__ bin,
-                                              TS* __restrict__ out, double* __restrict__ acc64) {
+__device__ __forceinline__ void mg_fused_body(const FuseJob* __restrict__ jp, const FuseJob& J, int s, TC omega,
+                                              const TS* __restrict__ bin, TS* __restrict__ out,
+                                              double* __restrict__ acc64) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  TC* base = reinterpret_cast<TC*>(smem_raw);
-  TC* kap[kMaxFuse];
-  TC* bb[kMaxFuse];
-  TC* xx[kMaxFuse];
-  TC* yy[kMaxFuse];
+  TC* const lds = reinterpret_cast<TC*>(smem_raw);
   const int L = J.nlev;
-  {
-    long off = 0;
-    for (int l = 0; l < L; ++l) {
-      const long nn = fuse_nodes<D>(J.n[l]);
-      kap[l] = base + off;
-      bb[l] = kap[l] + nn;
-      xx[l] = bb[l] + nn;
-      yy[l] = xx[l] + nn;
-      off += 4 * nn;
-    }
-  }
+  auto nodes = [](int n) -> int { const int m = n + 2; return D == 1 ? m : (D == 2 ? m * m : m * m * m); };
+  auto loff = [&](int l) -> int {
+    int o = 0;
+    for (int k = 0; k < l; ++k) o += 4 * nodes(jp->n[k]);
+    return o;
+  };
   const SlabOp<TC> op = level_op<TC>(J.op, s);
   const int t = threadIdx.x;
-  // coefficients of this slab on every level; zero iterates (boundary nodes stay zero)
-  for (int l = 0; l < L; ++l) {
-    const long nn = fuse_nodes<D>(J.n[l]);
-    const TC* kl = (const TC*)J.kap[l];
-    for (long q = t; q < nn; q += kBlock) {
-      TC v = op.c[0] * kl[q];
+  const int nt = blockDim.x;   // 256, 512 or 1024 threads (a schedule choice)
+  // coefficients of this slab on every level; zero b, x, y (boundary nodes stay zero)
+  {
+    int o = 0;
+    for (int l = 0; l < L; ++l) {
+      const int nn = nodes(jp->n[l]);
+      const TC* kl = gmem((const TC*)jp->kap[l]);
+      for (int q = t; q < nn; q += nt) {
+        TC v = op.c[0] * kl[q];
 #pragma unroll
-      for (int r = 1; r < RM; ++r)
-        if (r < J.op.R) v += op.c[r] * kl[r * nn + q];
-      kap[l][q] = v;
-      bb[l][q] = TC(0);
-      xx[l][q] = TC(0);
-      yy[l][q] = TC(0);
+        for (int r = 1; r < RM; ++r)
+          if (r < J.op.R) v += op.c[r] * kl[long(r) * nn + q];
+        lds[o + q] = v;
+      }
+      for (int q = t; q < 3 * nn; q += nt) lds[o + nn + q] = TC(0);
+      o += 4 * nn;
     }
   }
   __syncthreads();
   {
     const int n = J.n[0];
-    const long np = fuse_nodes<D>(n) - 0;
-    const int cnt = D == 1 ? n : (D == 2 ? n * n : n * n * n);
+    const int cnt = fuse_count<D>(n);
+    const int ob = nodes(n);   // b of level 0
     const TS* bs = bin + long(s) * cnt;
-    (void)np;
-    for (int q = t; q < cnt; q += kBlock) {
+    for (int q = t; q < cnt; q += nt) {
       int x, y, z;
-      bb[0][fuse_node_of<D>(q, n, x, y, z)] = ld<TC>(bs, q);
+      lds[ob + fuse_node_of<D>(q, n, x, y, z)] = ld<TC>(bs, q);
     }
   }
   __syncthreads();
-  auto diag = [&](const TC* k, int i, int sy, int sz) -> TC {
-    const TC kc = k[i];
-    TC d = op.sigma + TC(2 * D) * kc + k[i - 1] + k[i + 1];
-    if (D >= 2) d += k[i - sy] + k[i + sy];
-    if (D >= 3) d += k[i - sz] + k[i + sz];
+  // stencil pieces at node i of the level whose coefficient starts at ok
+  auto diag = [&](int ok, int i, int sy, int sz) -> TC {
+    const TC kc = lds[ok + i];
+    TC d = op.sigma + TC(2 * D) * kc + lds[ok + i - 1] + lds[ok + i + 1];
+    if (D >= 2) d += lds[ok + i - sy] + lds[ok + i + sy];
+    if (D >= 3) d += lds[ok + i - sz] + lds[ok + i + sz];
     return d;
   };
-  auto offsum = [&](const TC* k, const TC* v, int i, int sy, int sz) -> TC {
-    const TC kc = k[i];
-    TC o = (kc + k[i - 1]) * v[i - 1] + (kc + k[i + 1]) * v[i + 1];
-    if (D >= 2) o += (kc + k[i - sy]) * v[i - sy] + (kc + k[i + sy]) * v[i + sy];
-    if (D >= 3) o += (kc + k[i - sz]) * v[i - sz] + (kc + k[i + sz]) * v[i + sz];
+  auto offsum = [&](int ok, int ov, int i, int sy, int sz) -> TC {
+    const TC kc = lds[ok + i];
+    TC o = (kc + lds[ok + i - 1]) * lds[ov + i - 1] + (kc + lds[ok + i + 1]) * lds[ov + i + 1];
+    if (D >= 2) o += (kc + lds[ok + i - sy]) * lds[ov + i - sy] + (kc + lds[ok + i + sy]) * lds[ov + i + sy];
+    if (D >= 3) o += (kc + lds[ok + i - sz]) * lds[ov + i - sz] + (kc + lds[ok + i + sz]) * lds[ov + i + sz];
     return o;
   };
   const TC one_m_omega = TC(1) - omega;
   // down: x = omega D^-1 b, y = b - L x, b_{l+1} = R y
+  int o = 0;
   for (int l = 0; l + 1 < L; ++l) {
-    const int n = J.n[l], m = n + 2, sy = m, sz = m * m;
-    const int cnt = D == 1 ? n : (D == 2 ? n * n : n * n * n);
-    for (int q = t; q < cnt; q += kBlock) {
+    const int n = jp->n[l], m = n + 2, sy = m, sz = m * m, nn = nodes(n);
+    const int ok = o, obl = o + nn, ox = o + 2 * nn, oy = o + 3 * nn;
+    const int cnt = fuse_count<D>(n);
+    for (int q = t; q < cnt; q += nt) {
       int x, y, z;
       const int i = fuse_node_of<D>(q, n, x, y, z);
-      xx[l][i] = omega * bb[l][i] * rcp_fast(diag(kap[l], i, sy, sz));
+      lds[ox + i] = omega * lds[obl + i] * rcp_fast(diag(ok, i, sy, sz));
     }
     __syncthreads();
-    for (int q = t; q < cnt; q += kBlock) {
+    for (int q = t; q < cnt; q += nt) {
       int x, y, z;
       const int i = fuse_node_of<D>(q, n, x, y, z);
-      yy[l][i] = one_m_omega * bb[l][i] + offsum(kap[l], xx[l], i, sy, sz);
+      lds[oy + i] = one_m_omega * lds[obl + i] + offsum(ok, ox, i, sy, sz);
     }
     __syncthreads();
-    const int nc = J.n[l + 1], mc = nc + 2;
-    const int cntc = D == 1 ? nc : (D == 2 ? nc * nc : nc * nc * nc);
-    for (int q = t; q < cntc; q += kBlock) {
+    const int nc = jp->n[l + 1];
+    const int obc = o + 4 * nn + nodes(nc);   // b of level l + 1
+    const int cntc = fuse_count<D>(nc);
+    for (int q = t; q < cntc; q += nt) {
       int X, Y, Z;
       const int ic = fuse_node_of<D>(q, nc, X, Y, Z);
       const int c = D == 1 ? 2 * X : (D == 2 ? (2 * Y) * m + 2 * X : ((2 * Z) * m + 2 * Y) * m + 2 * X);
@@ -679,78 +684,85 @@ __device__ __forceinline__ void mg_fused_body(const FuseJob& J, int s, TC omega,
           TC w = 1;
           if (D >= 2) w *= (dy == 0 ? TC(0.5) : TC(0.25));
           if (D >= 3) w *= (dz == 0 ? TC(0.5) : TC(0.25));
-          const int row = c + dz * sz + dy * sy;
-          acc += w * (TC(0.25) * yy[l][row - 1] + TC(0.5) * yy[l][row] + TC(0.25) * yy[l][row + 1]);
+          const int row = oy + c + dz * sz + dy * sy;
+          acc += w * (TC(0.25) * lds[row - 1] + TC(0.5) * lds[row] + TC(0.25) * lds[row + 1]);
         }
-      bb[l + 1][ic] = acc;
-      (void)mc;
+      lds[obc + ic] = acc;
     }
     __syncthreads();
+    o += 4 * nn;
   }
-  // the one-node level: exact solve
+  // the one-node level: exact solve into y
   {
-    const int l = L - 1, n = J.n[l], m = n + 2;
-    const int cnt = D == 1 ? n : (D == 2 ? n * n : n * n * n);
-    for (int q = t; q < cnt; q += kBlock) {
+    const int n = jp->n[L - 1], m = n + 2, nn = nodes(n);
+    const int cnt = fuse_count<D>(n);
+    for (int q = t; q < cnt; q += nt) {
       int x, y, z;
       const int i = fuse_node_of<D>(q, n, x, y, z);
-      yy[l][i] = bb[l][i] / diag(kap[l], i, m, m * m);
+      lds[o + 3 * nn + i] = lds[o + nn + i] / diag(o, i, m, m * m);
     }
     __syncthreads();
   }
   // up: x += P y_{l+1}; y = (1 - omega) x + omega D^-1 (b + offsum(x))
   for (int l = L - 2; l >= 0; --l) {
-    const int n = J.n[l], m = n + 2, sy = m, sz = m * m;
-    const int mc = J.n[l + 1] + 2;
-    const TC* e = yy[l + 1];
-    const int cnt = D == 1 ? n : (D == 2 ? n * n : n * n * n);
-    for (int q = t; q < cnt; q += kBlock) {
+    const int n = jp->n[l], m = n + 2, sy = m, sz = m * m, nn = nodes(n);
+    const int ol = loff(l);
+    const int ok = ol, obl = ol + nn, ox = ol + 2 * nn, oy = ol + 3 * nn;
+    const int nc = jp->n[l + 1], mc = nc + 2;
+    const int oe = ol + 4 * nn + 3 * nodes(nc);   // y of level l + 1
+    const int cnt = fuse_count<D>(n);
+    for (int q = t; q < cnt; q += nt) {
       int x, y, z;
       const int i = fuse_node_of<D>(q, n, x, y, z);
-      const int e0 = D == 1 ? (x >> 1) : (D == 2 ? (y >> 1) * mc + (x >> 1) : ((z >> 1) * mc + (y >> 1)) * mc + (x >> 1));
-      const int ox = x & 1, oy = D >= 2 ? (y & 1) : 0, oz = D >= 3 ? (z & 1) : 0;
-      auto px = [&](int bq) -> TC { return ox ? TC(0.5) * (e[bq] + e[bq + 1]) : e[bq]; };
+      const int e0 = oe + (D == 1 ? (x >> 1)
+                           : (D == 2 ? (y >> 1) * mc + (x >> 1) : ((z >> 1) * mc + (y >> 1)) * mc + (x >> 1)));
+      const int ox1 = x & 1, oy1 = D >= 2 ? (y & 1) : 0, oz1 = D >= 3 ? (z & 1) : 0;
+      auto px = [&](int bq) -> TC { return ox1 ? TC(0.5) * (lds[bq] + lds[bq + 1]) : lds[bq]; };
       TC pe;
       if (D == 1) {
         pe = px(e0);
       } else if (D == 2) {
-        pe = oy ? TC(0.5) * (px(e0) + px(e0 + mc)) : px(e0);
+        pe = oy1 ? TC(0.5) * (px(e0) + px(e0 + mc)) : px(e0);
       } else {
-        auto pxy = [&](int bq) -> TC { return oy ? TC(0.5) * (px(bq) + px(bq + mc)) : px(bq); };
-        pe = oz ? TC(0.5) * (pxy(e0) + pxy(e0 + mc * mc)) : pxy(e0);
+        auto pxy = [&](int bq) -> TC { return oy1 ? TC(0.5) * (px(bq) + px(bq + mc)) : px(bq); };
+        pe = oz1 ? TC(0.5) * (pxy(e0) + pxy(e0 + mc * mc)) : pxy(e0);
       }
-      xx[l][i] += pe;
+      lds[ox + i] += pe;
     }
     __syncthreads();
-    for (int q = t; q < cnt; q += kBlock) {
+    for (int q = t; q < cnt; q += nt) {
       int x, y, z;
       const int i = fuse_node_of<D>(q, n, x, y, z);
-      const TC wd = omega * rcp_fast(diag(kap[l], i, sy, sz));
-      yy[l][i] = one_m_omega * xx[l][i] + wd * (bb[l][i] + offsum(kap[l], xx[l], i, sy, sz));
+      const TC wd = omega * rcp_fast(diag(ok, i, sy, sz));
+      lds[oy + i] = one_m_omega * lds[ox + i] + wd * (lds[obl + i] + offsum(ok, ox, i, sy, sz));
     }
     __syncthreads();
   }
-  // top-level result
+  // top-level result (y of level 0)
   {
     const int n = J.n[0];
-    const int cnt = D == 1 ? n : (D == 2 ? n * n : n * n * n);
-    const long o = long(s) * cnt;
-    for (int q = t; q < cnt; q += kBlock) {
+    const int cnt = fuse_count<D>(n);
+    const int oy = 3 * nodes(n);
+    const long ob = long(s) * cnt;
+    for (int q = t; q < cnt; q += nt) {
       int x, y, z;
-      const TC v = yy[0][fuse_node_of<D>(q, n, x, y, z)];
-      if (EPI == EPI_STORE) st<TS, TC>(out, o + q, v);
-      else acc64[o + q] += double(v);
+      const TC v = lds[oy + fuse_node_of<D>(q, n, x, y, z)];
+      if (EPI == EPI_STORE) st<TS, TC>(out, ob + q, v);
+      else acc64[ob + q] += double(v);
     }
   }
 }
 
+constexpr int kFuseMaxBlock = 1024;
+
 template <int D, typename TS, typename TC, int RM, int EPI>
-__global__ void __launch_bounds__(kBlock) k_mg_fused(const FuseJob* __restrict__ jobs, int njobs, TC omega) {
-  const FuseJob J = to_global(jobs[find_job(jobs, njobs)]);
+__global__ void __launch_bounds__(kFuseMaxBlock) k_mg_fused(const FuseJob* __restrict__ jobs, int njobs, TC omega) {
+  const int jx = find_job(jobs, njobs);
+  const FuseJob J = to_global(jobs[jx]);
   if (J.state && done_flag(J.state)) return;
   const int s = int(block_id() - J.block0);
   if (s >= J.S) return;
-  mg_fused_body<D, TS, TC, RM, EPI>(J, s, omega, (const TS*)J.b, (TS*)J.out, J.acc64);
+  mg_fused_body<D, TS, TC, RM, EPI>(jobs + jx, J, s, omega, (const TS*)J.b, (TS*)J.out, J.acc64);
 }
 
 // ---------------------------------------------------------------------------
