@@ -30,6 +30,24 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
+# HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (calibrated
+# against a plain copy) for (workload, dtype, kernel, level); valid only while the
+# kernel sources hash to the recorded value (see the named profile).
+MEASURED_TRAFFIC = {
+    ("heat2d_255_N256", "f64", "k_mg_down", 0): dict(
+        bytes=174384666, sources_sha256="ce2c2063783c9beb531ffac9a7f0b7433bde344523b8f17a40d9ecedf85a1fe2",
+        profile="profiles/heat2d_255_N256_f64_mg_down_L0_traffic.md"),
+}
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("stp_kernels.h", "stp_tiles.h", "stp.hip"):
+        with open(os.path.join(ROOT, "paper_1802_08126_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def algorithmic_bytes(kernel: str, level: int, dims, ts: int) -> float | None:
     """Minimum HBM bytes one launch of ``kernel`` must move (every input read
@@ -298,7 +316,7 @@ def batch_run(args):
     return out
 
 
-def roofline(rep, dims, ts, steps):
+def roofline(rep, dims, ts, steps, workload="heat2d_255_N256", dtype="f64"):
     """Dominant kernel (largest summed device time) and its achieved HBM rate."""
     if not rep:
         return None, []
@@ -311,9 +329,13 @@ def roofline(rep, dims, ts, steps):
     if b is None:
         return None, table
     achieved = b / (top["avg_ms"] * 1e-3) / 1e9
+    traffic, src = None, None
+    m = MEASURED_TRAFFIC.get((workload, dtype, top["kernel"], top["level"]))
+    if m is not None and m["sources_sha256"] == kernel_sources_sha256():
+        traffic, src = m["bytes"], m["profile"]
     return dict(bound="hbm", kernel=top["kernel"], level=top["level"], achieved=achieved, peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
-                bytes_per_launch=b, avg_launch_us=1e3 * top["avg_ms"]), table
+                unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic, traffic_unit="bytes per launch",
+                traffic_source=src, bytes_per_launch=b, avg_launch_us=1e3 * top["avg_ms"]), table
 
 
 def cpu_baseline(workload):
@@ -360,7 +382,7 @@ def main():
     prob, dims, res = gpu_run(args)
     progress("workload done:", args.workload)
     r64 = res["f64"]
-    roof, table = roofline(r64.get("kernels"), dims, 8, args.steps)
+    roof, table = roofline(r64.get("kernels"), dims, 8, args.steps, args.workload, "f64")
     out = {
         "metric": "space-time DoF-iterations/sec (u DoFs x Uzawa iterations / s), 1 GPU",
         "value": r64["value"],
