@@ -344,7 +344,6 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
   using CB = Box<D, T::X, T::Y, T::Z>;
   __shared__ TC sk[KB::size];
   __shared__ TC sx[XB::size];
-  __shared__ TC sb_[XB::size];
   __shared__ TC sr[RB::size];
   const LevelOp L = J.op;
   s1 = min(s1, L.S);
@@ -380,18 +379,29 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
           if (interior<D>(jx, jy, jz, nf))
             v = omega * bcur[k] * rcp_fast(diag_at_k<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma));
           sx[it.q] = v;
-          sb_[it.q] = bcur[k];
         }
         it.next();
       }
     }
     __syncthreads();
-    STP_BOX_FOR(RB, it) {
-      // r-box position (x, y, z) is x1-box position (x+1, y+1, z+1); nodes outside
-      // the domain have b = x1 = 0 (their r is never restricted)
-      const int ax = it.x + 1, ay = D >= 2 ? it.y + 1 : 0, az = D >= 3 ? it.z + 1 : 0;
-      const int xq = XB::idx(ax, ay, az);
-      sr[it.q] = one_m_omega * sb_[xq] + offsum_at<D, XB, KB, TC>(sk, sx, kpos<D, KB>(ax, ay, az), xq);
+    {
+      // the r-box is the interior of the x1-box (r-box position = x1-box position - 1);
+      // walking the x1-box with the same thread mapping keeps b in registers.  Nodes
+      // outside the domain have b = x1 = 0 (their r is never restricted).
+      BoxIter<XB> it;
+#pragma unroll
+      for (int k = 0; k < nit<XB>(); ++k) {
+        if (it.ok()) {
+          bool inr = in_range(it.x, 1, XB::X - 2);
+          if (D >= 2) inr = inr && in_range(it.y, 1, XB::Y - 2);
+          if (D >= 3) inr = inr && in_range(it.z, 1, XB::Z - 2);
+          if (inr) {
+            const int rq = RB::idx(it.x - 1, D >= 2 ? it.y - 1 : 0, D >= 3 ? it.z - 1 : 0);
+            sr[rq] = one_m_omega * bcur[k] + offsum_at<D, XB, KB, TC>(sk, sx, kpos<D, KB>(it.x, it.y, it.z), it.q);
+          }
+        }
+        it.next();
+      }
     }
     __syncthreads();
     TS* bcs = bc + long(s) * gc.npts;
