@@ -241,10 +241,16 @@ struct Site {
   int key = 0;     // transform sites: N (-1: the dense group of other step counts)
   size_t shmem = 0;               // fused multigrid sites: dynamic LDS of the launch
   int threads = 256;              // fused multigrid sites: threads per block
+  bool fixed = true;              // tile sites: every job's coefficient is a fixed field times a slab scalar
+  bool anyfix = false;            // tile sites: at least one job's coefficient is a fixed field
   int epi = 0;
   int path = TP_DENSE, C = 0;   // transform sites: path and Stockham columns
   size_t lds = 0;
-  void add(J j, long nb) {
+  // launch variant of the tile kernels: 0 per-slab only, 1 fixed only, 2 mixed
+  int variant() const { return fixed ? 1 : anyfix ? 2 : 0; }
+  void add(J j, long nb, bool fix = false) {
+    fixed = fixed && fix;
+    anyfix = anyfix || fix;
     j.block0 = blocks;
     blocks += nb;
     jobs.push_back(j);
@@ -381,17 +387,18 @@ LevelOp family_op(const Problem& q, int l, int fam) {
   L.kap = q.lv[l].kscaled;
   L.R = q.R;
   L.S = q.N;
-  L.uniform = 0;
-  if (fam == 0) {          // A family: tau_n A_n
+  if (fam == 0) {          // A family: tau_n A_n (rank 1: the field times tau a_0[n])
     L.sig = nullptr;
     L.c = q.cA;
-  } else if (fam == 1) {   // H family: mu_k I + tau A_ref
+    L.cmode = q.R == 1 ? CM_SCALE : CM_SLAB;
+  } else if (fam == 1) {   // H family: mu_k I + tau A_ref (the same coefficient for every k)
     L.sig = q.sigH;
     L.c = q.cH;
+    L.cmode = CM_UNIFORM;
   } else {                 // middle: (2/N) tau A_ref
     L.sig = nullptr;
     L.c = q.cMid;
-    L.uniform = 1;
+    L.cmode = CM_UNIFORM;
   }
   return L;
 }
@@ -535,7 +542,7 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top)
       d.state = &q.state->done;
       d.tiles = int(tiles_down_d(q.dim, q.lv[l + 1].n));
       d.sb = sched_sb(d.tiles, q.N, c->sched.e[KN_DOWN0 + l]);
-      vc.down[l].add(d, long(d.tiles) * ((q.N + d.sb - 1) / d.sb));
+      vc.down[l].add(d, long(d.tiles) * ((q.N + d.sb - 1) / d.sb), d.op.cmode != CM_SLAB);
       TileJob u{};
       u.gf = q.lv[l].g;
       u.gc = q.lv[l + 1].g;
@@ -547,7 +554,7 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top)
       u.state = d.state;
       u.tiles = int(tiles_up_d(q.dim, q.lv[l].n));
       u.sb = sched_sb(u.tiles, q.N, (l == 0 && acc) ? c->sched.e[KN_UPA0] : c->sched.e[KN_UP0 + l]);
-      vc.up[l].add(u, long(u.tiles) * ((q.N + u.sb - 1) / u.sb));
+      vc.up[l].add(u, long(u.tiles) * ((q.N + u.sb - 1) / u.sb), u.op.cmode != CM_SLAB);
       vc.up[l].epi = (l == 0 && acc) ? EPI_ADD64 : EPI_STORE;
     }
     FuseJob fj{};
@@ -670,7 +677,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
       j.r = q.W1;
       j.partial = q.partial;
       j.state = &q.state->done;
-      S.resid[w].add(j, nb);
+      S.resid[w].add(j, nb, q.R == 1);
     }
   }
   std::vector<VTop> topA(P), topH(P);
@@ -700,7 +707,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
     j.state = &q.state->done;
     j.tiles = int(tiles_up_d(q.dim, q.n));
     j.sb = sched_sb(j.tiles, q.N, c->sched.e[KN_MID]);
-    S.mid.add(j, long(j.tiles) * ((q.N + j.sb - 1) / j.sb));
+    S.mid.add(j, long(j.tiles) * ((q.N + j.sb - 1) / j.sb), j.op.cmode != CM_SLAB);
   }
   std::vector<double> one(P, 1.0), om(P);
   for (size_t i = 0; i < P; ++i) om[i] = c->pr[i].omega;
@@ -887,8 +894,13 @@ struct Solver : SolverBase {
   stp_status down_site(Site<TileJob>& s, int l) {
     if (s.jobs.empty()) return STP_OK;
     c->kt.level = l;
-    KLAUNCH_NAMED("k_mg_down", (k_mg_down<D, TS, TC, RM>), dim3(unsigned(s.blocks)), dim3(kBlock), 0, c->stream, s.dev,
-                  int(s.jobs.size()), omegaJ());
+    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
+    const int nj = int(s.jobs.size());
+    switch (s.variant()) {   // a fixed field needs no register copy of the fields: one instantiation
+      case 1: KLAUNCH_NAMED("k_mg_down", (k_mg_down<D, TS, TC, 1, 1>), gr, bl, 0, c->stream, s.dev, nj, omegaJ()); break;
+      case 2: KLAUNCH_NAMED("k_mg_down", (k_mg_down<D, TS, TC, RM, 2>), gr, bl, 0, c->stream, s.dev, nj, omegaJ()); break;
+      default: KLAUNCH_NAMED("k_mg_down", (k_mg_down<D, TS, TC, RM, 0>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
+    }
     LAUNCH_CHECK();
     return STP_OK;
   }
@@ -897,12 +909,20 @@ struct Solver : SolverBase {
   stp_status up_site(Site<TileJob>& s, int l) {
     if (s.jobs.empty()) return STP_OK;
     c->kt.level = l;
-    if (s.epi == EPI_ADD64)
-      KLAUNCH_NAMED("k_mg_up<add64>", (k_mg_up<D, TS, TC, RM, EPI_ADD64>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
-                    c->stream, s.dev, int(s.jobs.size()), omegaJ());
-    else
-      KLAUNCH_NAMED("k_mg_up<store>", (k_mg_up<D, TS, TC, RM, EPI_STORE>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
-                    c->stream, s.dev, int(s.jobs.size()), omegaJ());
+    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
+    const int nj = int(s.jobs.size());
+    const int v = s.variant();
+    if (s.epi == EPI_ADD64) {
+      const char* nm = "k_mg_up<add64>";
+      if (v == 1) KLAUNCH_NAMED(nm, (k_mg_up<D, TS, TC, 1, EPI_ADD64, 1>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
+      else if (v == 2) KLAUNCH_NAMED(nm, (k_mg_up<D, TS, TC, RM, EPI_ADD64, 2>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
+      else KLAUNCH_NAMED(nm, (k_mg_up<D, TS, TC, RM, EPI_ADD64, 0>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
+    } else {
+      const char* nm = "k_mg_up<store>";
+      if (v == 1) KLAUNCH_NAMED(nm, (k_mg_up<D, TS, TC, 1, EPI_STORE, 1>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
+      else if (v == 2) KLAUNCH_NAMED(nm, (k_mg_up<D, TS, TC, RM, EPI_STORE, 2>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
+      else KLAUNCH_NAMED(nm, (k_mg_up<D, TS, TC, RM, EPI_STORE, 0>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
+    }
     LAUNCH_CHECK();
     return STP_OK;
   }
@@ -982,8 +1002,13 @@ struct Solver : SolverBase {
   stp_status mid_dr() {
     Site<TileJob>& s = c->sites.mid;
     c->kt.level = 0;
-    KLAUNCH_NAMED("k_apply_tile", (k_apply_tile<D, TS, TC, RM>), dim3(unsigned(s.blocks)), dim3(kBlock), 0, c->stream,
-                  s.dev, int(s.jobs.size()));
+    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
+    const int nj = int(s.jobs.size());
+    switch (s.variant()) {
+      case 1: KLAUNCH_NAMED("k_apply_tile", (k_apply_tile<D, TS, TC, 1, 1>), gr, bl, 0, c->stream, s.dev, nj); break;
+      case 2: KLAUNCH_NAMED("k_apply_tile", (k_apply_tile<D, TS, TC, RM, 2>), gr, bl, 0, c->stream, s.dev, nj); break;
+      default: KLAUNCH_NAMED("k_apply_tile", (k_apply_tile<D, TS, TC, RM, 0>), gr, bl, 0, c->stream, s.dev, nj);
+    }
     LAUNCH_CHECK();
     return STP_OK;
   }
@@ -1095,8 +1120,14 @@ struct Solver : SolverBase {
   stp_status resid_dr() {
     Site<ResidJob>& s = c->sites.resid[WHICH];
     c->kt.level = 0;
-    KLAUNCH_NAMED(WHICH == 0 ? "k_resid_tile<a1>" : "k_resid_tile<a3>", (k_resid_tile<D, TS, WHICH, RM>),
-                  dim3(unsigned(s.blocks)), dim3(kBlock), 0, c->stream, s.dev, int(s.jobs.size()));
+    const char* nm = WHICH == 0 ? "k_resid_tile<a1>" : "k_resid_tile<a3>";
+    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
+    const int nj = int(s.jobs.size());
+    switch (s.variant()) {
+      case 1: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, 1, 1>), gr, bl, 0, c->stream, s.dev, nj); break;
+      case 2: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, RM, 2>), gr, bl, 0, c->stream, s.dev, nj); break;
+      default: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, RM, 0>), gr, bl, 0, c->stream, s.dev, nj);
+    }
     LAUNCH_CHECK();
     return STP_OK;
   }

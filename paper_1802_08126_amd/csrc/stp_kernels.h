@@ -314,20 +314,44 @@ __global__ void k_sum_to(const double* __restrict__ partial, long count, double*
 // ---------------------------------------------------------------------------
 // spatial kernels on a multigrid level (storage TS, compute TC)
 // ---------------------------------------------------------------------------
+// How the slab coefficient sum_r c_{s,r} k_r varies over the slabs:
+enum CMode {
+  CM_SLAB = 0,      // a row of c per slab
+  CM_UNIFORM = 1,   // one row (row 0) for every slab; sigma (if any) still per slab
+  CM_SCALE = 2      // rank 1: the field k_0 times the per-slab scalar c_{s,0}
+};
+
 struct LevelOp {
   const void* kap;     // scaled fields, TC
   const void* sig;     // per-slab sigma (TC) or null
   const void* c;       // per-slab coefficients, S x kMaxRank (TC)
   int R;
   int S;               // number of slabs
-  int uniform;         // 1: slab 0's (sigma, c) serve all slabs
+  int cmode;           // CMode
 };
 
 template <typename TC>
 __device__ __forceinline__ SlabOp<TC> level_op(const LevelOp& L, int s) {
-  const int so = L.uniform ? 0 : s;
-  return load_op<TC>((const TC*)L.sig, (const TC*)L.c, so, L.R);
+  const TC* sig = (const TC*)L.sig;
+  const TC* c = (const TC*)L.c;
+  SlabOp<TC> op = load_op<TC>(nullptr, c, L.cmode == CM_UNIFORM ? 0 : s, L.R);
+  op.sigma = sig ? sig[s] : TC(0);
+  return op;
 }
+
+// A fixed-field launch (cmode != CM_SLAB) stages k_fix = sum_r f_r k_r once per
+// block and scales it per slab by gamma_s:  f = row 0 and gamma = 1 (uniform),
+// or f = (1, 0, ...) and gamma_s = c_{s,0} (rank 1).
+template <typename TC>
+__device__ __forceinline__ TC fixed_coef(const LevelOp& L, int r) {
+  if (L.cmode == CM_SCALE) return r == 0 ? TC(1) : TC(0);
+  return ((const TC*)L.c)[r];
+}
+template <typename TC>
+__device__ __forceinline__ TC slab_scale(const LevelOp& L, int s) {
+  return L.cmode == CM_SCALE ? ((const TC*)L.c)[s * kMaxRank] : TC(1);
+}
+
 
 // Epilogue of the last smoothing sweep: write out, or add it into a float64 vector.
 enum Epi { EPI_STORE = 0, EPI_ADD64 = 1 };
@@ -545,6 +569,60 @@ __global__ void __launch_bounds__(kBlock) k_time_dense(const TimeJob* __restrict
 // ---------------------------------------------------------------------------
 enum { MODE_A4 = 0, MODE_A6 = 1 };
 
+__constant__ double c_w16d[32];   // re[0..16), im[16..32)
+__constant__ float c_w16f[32];
+
+template <typename TC> __device__ __forceinline__ TC w16re(int k);
+template <typename TC> __device__ __forceinline__ TC w16im(int k);
+template <> __device__ __forceinline__ double w16re<double>(int k) { return c_w16d[k]; }
+template <> __device__ __forceinline__ double w16im<double>(int k) { return c_w16d[16 + k]; }
+template <> __device__ __forceinline__ float w16re<float>(int k) { return c_w16f[k]; }
+template <> __device__ __forceinline__ float w16im<float>(int k) { return c_w16f[16 + k]; }
+
+template <int P>
+__host__ __device__ constexpr int brev(int i) {
+  int r = 0;
+  for (int b = 1, rb = P >> 1; b < P; b <<= 1, rb >>= 1)
+    if (i & b) r |= rb;
+  return r;
+}
+
+// in-register radix-2 DIT DFT of size P <= 16 (forward, exp(-2 pi i/P)), natural order out
+template <int P, typename TC>
+__device__ __forceinline__ void dft_reg(TC (&xr)[P], TC (&xi)[P]) {
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int j = brev<P>(i);
+    if (j > i) {
+      TC t = xr[i]; xr[i] = xr[j]; xr[j] = t;
+      t = xi[i]; xi[i] = xi[j]; xi[j] = t;
+    }
+  }
+#pragma unroll
+  for (int half = 1; half < P; half <<= 1) {
+#pragma unroll
+    for (int base = 0; base < P; base += 2 * half) {
+#pragma unroll
+      for (int j = 0; j < half; ++j) {
+        const int a = base + j, b = a + half;
+        TC tr, ti;
+        if (j == 0) {
+          tr = xr[b]; ti = xi[b];
+        } else {
+          const int tw = j * (16 / (2 * half));
+          const TC wr = w16re<TC>(tw), wi = w16im<TC>(tw);
+          tr = xr[b] * wr - xi[b] * wi;
+          ti = xr[b] * wi + xi[b] * wr;
+        }
+        xr[b] = xr[a] - tr; xi[b] = xi[a] - ti;
+        xr[a] = xr[a] + tr; xi[a] = xi[a] + ti;
+      }
+    }
+  }
+}
+
+
+
 template <typename TC, int R, int MAXB>
 __device__ __forceinline__ void fft_stage(TC* re, TC* im, const TC* twr, const TC* twi, int N, int Ns, int C,
                                           int col, int jg, int G) {
@@ -571,6 +649,13 @@ __device__ __forceinline__ void fft_stage(TC* re, TC* im, const TC* twr, const T
       if constexpr (R == 2) {
         orr[b * R + 0] = vr[0] + vr[1]; oii[b * R + 0] = vi[0] + vi[1];
         orr[b * R + 1] = vr[0] - vr[1]; oii[b * R + 1] = vi[0] - vi[1];
+      } else if constexpr (R == 8) {
+        dft_reg<R, TC>(vr, vi);   // R-point DFT in registers, natural order
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          orr[b * R + q] = vr[q];
+          oii[b * R + q] = vi[q];
+        }
       } else {
         // radix-4 DFT with e^{-2 pi i/4} = -i
         const TC s0r = vr[0] + vr[2], s0i = vi[0] + vi[2];
@@ -600,6 +685,29 @@ __device__ __forceinline__ void fft_stage(TC* re, TC* im, const TC* twr, const T
     }
   }
   __syncthreads();
+}
+
+// A length-N (power of two, N C <= 4096) Stockham FFT of C columns in LDS, with
+// the largest radix (8, 4 or 2) that divides what is left: fewer passes through
+// LDS (four for N = 2048 instead of six with radix 4; radix 16 would need more
+// registers than it saves).
+template <typename TC>
+__device__ __forceinline__ void fft_stages(TC* re, TC* im, const TC* twr, const TC* twi, int N, int C, int col,
+                                           int jg, int G) {
+  int Ns = 1;
+  while (Ns < N) {
+    const int rem = N / Ns;
+    if (rem % 8 == 0) {
+      fft_stage<TC, 8, 2>(re, im, twr, twi, N, Ns, C, col, jg, G);
+      Ns *= 8;
+    } else if (rem % 4 == 0) {
+      fft_stage<TC, 4, 4>(re, im, twr, twi, N, Ns, C, col, jg, G);
+      Ns *= 4;
+    } else {
+      fft_stage<TC, 2, 8>(re, im, twr, twi, N, Ns, C, col, jg, G);
+      Ns *= 2;
+    }
+  }
 }
 
 // tw: 2N values (re[0..N), im[0..N)) of w_N^m; tw4: same for w_{4N}^m.
@@ -640,16 +748,7 @@ __device__ __forceinline__ void time_fft_body(const TimeJob& J, int C, const TC*
     }
   }
   __syncthreads();
-  int Ns = 1;
-  while (Ns < N) {
-    if ((N / Ns) % 4 == 0) {
-      fft_stage<TC, 4, 4>(re, im, twr, twi, N, Ns, C, col, jg, G);
-      Ns *= 4;
-    } else {
-      fft_stage<TC, 2, 8>(re, im, twr, twi, N, Ns, C, col, jg, G);
-      Ns *= 2;
-    }
-  }
+  fft_stages<TC>(re, im, twr, twi, N, C, col, jg, G);
   if (!valid) return;
   for (int n = jg; n < N; n += G) {
     TC v;
@@ -730,18 +829,7 @@ __device__ __forceinline__ void time_bluestein_body(const TimeJob& J, int C, con
     im[n * C + col] = ai;
   }
   __syncthreads();
-  auto fft = [&]() {
-    int Ns = 1;
-    while (Ns < M) {
-      if ((M / Ns) % 4 == 0) {
-        fft_stage<TC, 4, 4>(re, im, twr, twi, M, Ns, C, col, jg, G);
-        Ns *= 4;
-      } else {
-        fft_stage<TC, 2, 8>(re, im, twr, twi, M, Ns, C, col, jg, G);
-        Ns *= 2;
-      }
-    }
-  };
+  auto fft = [&]() { fft_stages<TC>(re, im, twr, twi, M, C, col, jg, G); };
   fft();
   // conj(A_m Bhat_m): the second forward FFT then yields M conj(ifft(A Bhat))
   for (int m = jg; m < M; m += G) {
@@ -799,58 +887,6 @@ __global__ void __launch_bounds__(kBlock) k_time_bluestein(const TimeJob* __rest
 // The pre/post-processing of MODE_A4 / MODE_A6 (see above) is folded into the
 // load and store addressing.  c_w16 holds w_16^k (set by the host).
 // ---------------------------------------------------------------------------
-__constant__ double c_w16d[32];   // re[0..16), im[16..32)
-__constant__ float c_w16f[32];
-
-template <typename TC> __device__ __forceinline__ TC w16re(int k);
-template <typename TC> __device__ __forceinline__ TC w16im(int k);
-template <> __device__ __forceinline__ double w16re<double>(int k) { return c_w16d[k]; }
-template <> __device__ __forceinline__ double w16im<double>(int k) { return c_w16d[16 + k]; }
-template <> __device__ __forceinline__ float w16re<float>(int k) { return c_w16f[k]; }
-template <> __device__ __forceinline__ float w16im<float>(int k) { return c_w16f[16 + k]; }
-
-template <int P>
-__host__ __device__ constexpr int brev(int i) {
-  int r = 0;
-  for (int b = 1, rb = P >> 1; b < P; b <<= 1, rb >>= 1)
-    if (i & b) r |= rb;
-  return r;
-}
-
-// in-register radix-2 DIT DFT of size P <= 16 (forward, exp(-2 pi i/P)), natural order out
-template <int P, typename TC>
-__device__ __forceinline__ void dft_reg(TC (&xr)[P], TC (&xi)[P]) {
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const int j = brev<P>(i);
-    if (j > i) {
-      TC t = xr[i]; xr[i] = xr[j]; xr[j] = t;
-      t = xi[i]; xi[i] = xi[j]; xi[j] = t;
-    }
-  }
-#pragma unroll
-  for (int half = 1; half < P; half <<= 1) {
-#pragma unroll
-    for (int base = 0; base < P; base += 2 * half) {
-#pragma unroll
-      for (int j = 0; j < half; ++j) {
-        const int a = base + j, b = a + half;
-        TC tr, ti;
-        if (j == 0) {
-          tr = xr[b]; ti = xi[b];
-        } else {
-          const int tw = j * (16 / (2 * half));
-          const TC wr = w16re<TC>(tw), wi = w16im<TC>(tw);
-          tr = xr[b] * wr - xi[b] * wi;
-          ti = xr[b] * wi + xi[b] * wr;
-        }
-        xr[b] = xr[a] - tr; xi[b] = xi[a] - ti;
-        xr[a] = xr[a] + tr; xi[a] = xi[a] + ti;
-      }
-    }
-  }
-}
-
 // tw / tw4: 2N tables as in k_time_fft.  Dynamic LDS: N * C * sizeof(TC)
 // (real and imaginary parts pass through it one after the other).
 template <typename TS, typename TC, int MODE, int ACC64, int L1, int L2>

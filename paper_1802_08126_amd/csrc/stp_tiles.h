@@ -185,6 +185,40 @@ __device__ __forceinline__ TC offsum_at(const TC* sk, const TC* sx, int kq, int 
   return o;
 }
 
+// fixed-field launches: k_fix staged once per block over box KB (origin ox, oy, oz)
+template <int D, typename KB, typename TC>
+__device__ __forceinline__ void stage_fixed(TC* sk, const LevelOp& L, long nnodes, int n, int ox, int oy, int oz) {
+  const TC* kap = (const TC*)L.kap;
+  TC f[kMaxRank];
+#pragma unroll
+  for (int r = 0; r < kMaxRank; ++r) f[r] = r < L.R ? fixed_coef<TC>(L, r) : TC(0);
+  BoxIter<KB> it;
+#pragma unroll
+  for (int k = 0; k < nit<KB>(); ++k) {
+    if (it.ok()) {
+      const int jx = ox + it.x, jy = oy + it.y, jz = oz + it.z;
+      TC v = 0;
+      if (in_nodes<D>(jx, jy, jz, n)) {
+        const int o = node_off<D>(jx, jy, jz, n);
+        v = f[0] * kap[o];
+        for (int r = 1; r < L.R; ++r) v += f[r] * kap[r * nnodes + o];
+      }
+      sk[it.q] = v;
+    }
+    it.next();
+  }
+}
+
+// diagonal sigma + gamma (2d k_c + sum_nb k_nb) of a fixed-field launch
+template <int D, typename KB, typename TC>
+__device__ __forceinline__ TC diag_fixed(const TC* sk, int kq, TC sigma, TC gamma) {
+  const TC kc = sk[kq];
+  TC d = TC(2 * D) * kc;
+#pragma unroll
+  for (int k = 0; k < 2 * D; ++k) d += sk[kq + nb_off<KB>(k)];
+  return sigma + gamma * d;
+}
+
 // kappa-box position of x-box position (x, y, z) when KB is one node larger
 template <int D, typename KB>
 __device__ __forceinline__ int kpos(int x, int y, int z) {
@@ -334,7 +368,7 @@ __device__ __forceinline__ ResidJob to_global(ResidJob j) {
 // multigrid: pre-smooth from zero, residual and full-weighting restriction
 //   x1 = omega D^{-1} b,  r = b - L x1 = (1 - omega) b + sum_nb w x1_nb,  bc = R r
 // ---------------------------------------------------------------------------
-template <int D, typename TS, typename TC, int RM>
+template <int D, typename TS, typename TC, int RM, bool FIX>
 __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0, int s1, TC omega,
                                              const TS* __restrict__ b, TS* __restrict__ bc) {
   using T = DownTile<D>;
@@ -356,9 +390,14 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
   const int Ix = tx * T::X + 1, Iy = D >= 2 ? ty * T::Y + 1 : 1, Iz = D >= 3 ? tz * T::Z + 1 : 1;
   const int rx = 2 * Ix - 1, ry = D >= 2 ? 2 * Iy - 1 : 1, rz = D >= 3 ? 2 * Iz - 1 : 1;   // r-box origin
   const int xx = rx - 1, xy = D >= 2 ? ry - 1 : 1, xz = D >= 3 ? rz - 1 : 1;                // x1-box origin
-  TC kr[nit<KB>()][RM];
-  load_kraw<D, KB, TC, RM>(kr, (const TC*)L.kap, gf.nnodes, L.R, nf, xx - 1, D >= 2 ? xy - 1 : 1,
-                           D >= 3 ? xz - 1 : 1);
+  TC kr[FIX ? 1 : nit<KB>()][FIX ? 1 : RM];
+  if constexpr (FIX) {
+    stage_fixed<D, KB, TC>(sk, L, gf.nnodes, nf, xx - 1, D >= 2 ? xy - 1 : 1, D >= 3 ? xz - 1 : 1);
+    __syncthreads();
+  } else {
+    load_kraw<D, KB, TC, RM>(kr, (const TC*)L.kap, gf.nnodes, L.R, nf, xx - 1, D >= 2 ? xy - 1 : 1,
+                             D >= 3 ? xz - 1 : 1);
+  }
   TC bn[nit<XB>()];
   prefetch_box<D, XB, TS, TC>(bn, b + long(s0) * gf.npts, nf, xx, xy, xz);
   const TC one_m_omega = TC(1) - omega;
@@ -367,8 +406,11 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
     Regs<nit<XB>()>::copy(bcur, bn);
     if (s + 1 < s1) prefetch_box<D, XB, TS, TC>(bn, b + long(s + 1) * gf.npts, nf, xx, xy, xz);
     const SlabOp<TC> op = level_op<TC>(L, s);
-    write_kappa<KB, TC, RM>(sk, kr, op);
-    __syncthreads();
+    const TC gamma = FIX ? slab_scale<TC>(L, s) : TC(1);
+    if constexpr (!FIX) {
+      write_kappa<KB, TC, RM>(sk, kr, op);
+      __syncthreads();
+    }   // FIX: the field is staged once; every phase ends in a barrier
     {
       BoxIter<XB> it;
 #pragma unroll
@@ -377,7 +419,9 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
           const int jx = xx + it.x, jy = xy + it.y, jz = xz + it.z;
           TC v = 0;
           if (interior<D>(jx, jy, jz, nf))
-            v = omega * bcur[k] * rcp_fast(diag_at_k<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma));
+            v = omega * bcur[k] *
+                rcp_fast(FIX ? diag_fixed<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma, gamma)
+                             : diag_at_k<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma));
           sx[it.q] = v;
         }
         it.next();
@@ -397,7 +441,8 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
           if (D >= 3) inr = inr && in_range(it.z, 1, XB::Z - 2);
           if (inr) {
             const int rq = RB::idx(it.x - 1, D >= 2 ? it.y - 1 : 0, D >= 3 ? it.z - 1 : 0);
-            sr[rq] = one_m_omega * bcur[k] + offsum_at<D, XB, KB, TC>(sk, sx, kpos<D, KB>(it.x, it.y, it.z), it.q);
+            const TC off = offsum_at<D, XB, KB, TC>(sk, sx, kpos<D, KB>(it.x, it.y, it.z), it.q);
+            sr[rq] = one_m_omega * bcur[k] + (FIX ? gamma * off : off);
           }
         }
         it.next();
@@ -428,12 +473,18 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
   }
 }
 
-template <int D, typename TS, typename TC, int RM>
+// Launch variants V: 0 = every job per-slab coefficients, 1 = every job a fixed
+// field, 2 = mixed (each job runs the body of its own mode, so a problem's
+// arithmetic never depends on the batch it is in)
+__device__ __forceinline__ bool job_fixed(int V, int cmode) { return V == 1 || (V == 2 && cmode != CM_SLAB); }
+
+template <int D, typename TS, typename TC, int RM, int V>
 __global__ void __launch_bounds__(kBlock) k_mg_down(const TileJob* __restrict__ jobs, int njobs, TC omega) {
   int tile, s0, s1;
   const TileJob J = job_tile_run(jobs, njobs, 1 << 30, tile, s0, s1);
   if (J.state && done_flag(J.state)) return;
-  mg_down_body<D, TS, TC, RM>(J, tile, s0, s1, omega, (const TS*)J.b, (TS*)J.out);
+  if (job_fixed(V, J.op.cmode)) mg_down_body<D, TS, TC, RM, true>(J, tile, s0, s1, omega, (const TS*)J.b, (TS*)J.out);
+  else mg_down_body<D, TS, TC, RM, false>(J, tile, s0, s1, omega, (const TS*)J.b, (TS*)J.out);
 }
 
 // ---------------------------------------------------------------------------
@@ -441,7 +492,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_down(const TileJob* __restrict__ 
 //   x2 = omega D^{-1} b + P e,   x = (1 - omega) x2 + omega D^{-1} (b + sum_nb w x2_nb)
 // epilogue: store x (TS) or add it into a float64 vector
 // ---------------------------------------------------------------------------
-template <int D, typename TS, typename TC, int RM, int EPI>
+template <int D, typename TS, typename TC, int RM, int EPI, bool FIX>
 __device__ __forceinline__ void mg_up_body(const TileJob& J, int tile, int s0, int s1, TC omega,
                                            const TS* __restrict__ b, const TS* __restrict__ e, TS* __restrict__ out,
                                            double* __restrict__ acc64) {
@@ -464,9 +515,13 @@ __device__ __forceinline__ void mg_up_body(const TileJob& J, int tile, int s0, i
   const int jx0 = tx * T::X + 1, jy0 = D >= 2 ? ty * T::Y + 1 : 1, jz0 = D >= 3 ? tz * T::Z + 1 : 1;
   const int xx = jx0 - 1, xy = D >= 2 ? jy0 - 1 : 1, xz = D >= 3 ? jz0 - 1 : 1;   // x2-box origin
   const int ex = xx / 2, ey = D >= 2 ? xy / 2 : 1, ez = D >= 3 ? xz / 2 : 1;      // first coarse node
-  TC kr[nit<KB>()][RM];
-  load_kraw<D, KB, TC, RM>(kr, (const TC*)L.kap, gf.nnodes, L.R, nf, xx - 1, D >= 2 ? xy - 1 : 1,
-                           D >= 3 ? xz - 1 : 1);
+  TC kr[FIX ? 1 : nit<KB>()][FIX ? 1 : RM];
+  if constexpr (FIX) {
+    stage_fixed<D, KB, TC>(sk, L, gf.nnodes, nf, xx - 1, D >= 2 ? xy - 1 : 1, D >= 3 ? xz - 1 : 1);
+  } else {
+    load_kraw<D, KB, TC, RM>(kr, (const TC*)L.kap, gf.nnodes, L.R, nf, xx - 1, D >= 2 ? xy - 1 : 1,
+                             D >= 3 ? xz - 1 : 1);
+  }
   TC bn[nit<XB>()];
   TC en[nit<EB>()];
   prefetch_box<D, XB, TS, TC>(bn, b + long(s0) * gf.npts, nf, xx, xy, xz);
@@ -476,7 +531,8 @@ __device__ __forceinline__ void mg_up_body(const TileJob& J, int tile, int s0, i
     TC bcur[nit<XB>()];
     Regs<nit<XB>()>::copy(bcur, bn);
     const SlabOp<TC> op = level_op<TC>(L, s);
-    write_kappa<KB, TC, RM>(sk, kr, op);
+    const TC gamma = FIX ? slab_scale<TC>(L, s) : TC(1);
+    if constexpr (!FIX) write_kappa<KB, TC, RM>(sk, kr, op);
     write_box<EB, TC>(se, en);
     if (s + 1 < s1) {
       prefetch_box<D, XB, TS, TC>(bn, b + long(s + 1) * gf.npts, nf, xx, xy, xz);
@@ -491,7 +547,9 @@ __device__ __forceinline__ void mg_up_body(const TileJob& J, int tile, int s0, i
           const int jx = xx + it.x, jy = xy + it.y, jz = xz + it.z;
           TC v = 0;
           if (interior<D>(jx, jy, jz, nf)) {
-            const TC wd = omega * rcp_fast(diag_at_k<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma));
+            const TC wd =
+                omega * rcp_fast(FIX ? diag_fixed<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma, gamma)
+                                     : diag_at_k<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma));
             // multilinear interpolation from coarse nodes floor(j/2) and, for odd j, floor(j/2)+1
             const int lx = (jx >> 1) - ex, ly = D >= 2 ? (jy >> 1) - ey : 0, lz = D >= 3 ? (jz >> 1) - ez : 0;
             const int ox = jx & 1, oy = D >= 2 ? (jy & 1) : 0, oz = D >= 3 ? (jz & 1) : 0;
@@ -523,8 +581,10 @@ __device__ __forceinline__ void mg_up_body(const TileJob& J, int tile, int s0, i
       const int ax = it.x + 1, ay = D >= 2 ? it.y + 1 : 0, az = D >= 3 ? it.z + 1 : 0;
       const int xq = XB::idx(ax, ay, az);
       const int kq = kpos<D, KB>(ax, ay, az);
-      const TC off = offsum_at<D, XB, KB, TC>(sk, sx, kq, xq);
-      const TC wd = omega * rcp_fast(diag_at_k<D, KB, TC>(sk, kq, op.sigma));
+      TC off = offsum_at<D, XB, KB, TC>(sk, sx, kq, xq);
+      if (FIX) off *= gamma;
+      const TC wd = omega * rcp_fast(FIX ? diag_fixed<D, KB, TC>(sk, kq, op.sigma, gamma)
+                                         : diag_at_k<D, KB, TC>(sk, kq, op.sigma));
       const TC v = one_m_omega * sx[xq] + wd * (sb_[xq] + off);
       const int vo = vec_off<D>(jx, jy, jz, nf);
       if (EPI == EPI_STORE) st<TS, TC>(os, vo, v);
@@ -534,12 +594,18 @@ __device__ __forceinline__ void mg_up_body(const TileJob& J, int tile, int s0, i
   }
 }
 
-template <int D, typename TS, typename TC, int RM, int EPI>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RM <= 2 ? 4 : 3))) k_mg_up(const TileJob* __restrict__ jobs, int njobs, TC omega) {
+template <int D, typename TS, typename TC, int RM, int EPI, int V>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RM <= 2 ? 4 : 3)))
+k_mg_up(const TileJob* __restrict__ jobs, int njobs, TC omega) {
   int tile, s0, s1;
   const TileJob J = job_tile_run(jobs, njobs, 1 << 30, tile, s0, s1);
   if (J.state && done_flag(J.state)) return;
-  mg_up_body<D, TS, TC, RM, EPI>(J, tile, s0, s1, omega, (const TS*)J.b, (const TS*)J.e, (TS*)J.out, J.acc64);
+  if (job_fixed(V, J.op.cmode))
+    mg_up_body<D, TS, TC, RM, EPI, true>(J, tile, s0, s1, omega, (const TS*)J.b, (const TS*)J.e, (TS*)J.out,
+                                         J.acc64);
+  else
+    mg_up_body<D, TS, TC, RM, EPI, false>(J, tile, s0, s1, omega, (const TS*)J.b, (const TS*)J.e, (TS*)J.out,
+                                          J.acc64);
 }
 
 // ---------------------------------------------------------------------------
@@ -779,7 +845,7 @@ __global__ void __launch_bounds__(kFuseMaxBlock) k_mg_fused(const FuseJob* __res
 // y = L x (tile version; the middle reference operator of the H-blocks,
 // whose coefficients are the same for every slab)
 // ---------------------------------------------------------------------------
-template <int D, typename TS, typename TC, int RM>
+template <int D, typename TS, typename TC, int RM, bool FIX>
 __device__ __forceinline__ void apply_tile_body(const TileJob& J, int tile, int s0, int s1, const TS* __restrict__ xv,
                                                 TS* __restrict__ yv) {
   using T = UpTile<D>;
@@ -798,17 +864,14 @@ __device__ __forceinline__ void apply_tile_body(const TileJob& J, int tile, int 
   const int ox = jx0 - 1, oy = D >= 2 ? jy0 - 1 : 1, oz = D >= 3 ? jz0 - 1 : 1;
   TC xn[nit<KB>()];
   prefetch_box<D, KB, TS, TC>(xn, xv + long(s0) * g.npts, n, ox, oy, oz);
-  TC kr[nit<KB>()][RM];
-  load_kraw<D, KB, TC, RM>(kr, (const TC*)L.kap, g.nnodes, L.R, n, ox, oy, oz);
-  int cur = -1;
+  TC kr[FIX ? 1 : nit<KB>()][FIX ? 1 : RM];
+  if constexpr (FIX) stage_fixed<D, KB, TC>(sk, L, g.nnodes, n, ox, oy, oz);
+  else load_kraw<D, KB, TC, RM>(kr, (const TC*)L.kap, g.nnodes, L.R, n, ox, oy, oz);
   for (int s = s0; s < s1; ++s) {
-    const int so = L.uniform ? 0 : s;
-    if (so != cur) {
-      write_kappa<KB, TC, RM>(sk, kr, level_op<TC>(L, s));
-      cur = so;
-    }
+    const TC gamma = FIX ? slab_scale<TC>(L, s) : TC(1);
+    if constexpr (!FIX) write_kappa<KB, TC, RM>(sk, kr, level_op<TC>(L, s));
     write_box<KB, TC>(sx, xn);
-    const TC sigma = level_op<TC>(L, s).sigma;
+    const TC sigma = L.sig ? ((const TC*)L.sig)[s] : TC(0);
     if (s + 1 < s1) prefetch_box<D, KB, TS, TC>(xn, xv + long(s + 1) * g.npts, n, ox, oy, oz);
     __syncthreads();
     TS* ys = yv + long(s) * g.npts;
@@ -817,25 +880,27 @@ __device__ __forceinline__ void apply_tile_body(const TileJob& J, int tile, int 
       if (!interior<D>(jx, jy, jz, n)) continue;
       const int kq = KB::idx(it.x + 1, D >= 2 ? it.y + 1 : 0, D >= 3 ? it.z + 1 : 0);
       const TC kc = sk[kq];
-      TC dg = sigma, off = 0;
+      TC dg = FIX ? TC(0) : sigma, off = 0;
 #pragma unroll
       for (int k = 0; k < 2 * D; ++k) {
         const TC w = kc + sk[kq + nb_off<KB>(k)];
         dg += w;
         off += w * sx[kq + nb_off<KB>(k)];
       }
-      st<TS, TC>(ys, vec_off<D>(jx, jy, jz, n), dg * sx[kq] - off);
+      const TC y = FIX ? sigma * sx[kq] + gamma * (dg * sx[kq] - off) : dg * sx[kq] - off;
+      st<TS, TC>(ys, vec_off<D>(jx, jy, jz, n), y);
     }
     __syncthreads();
   }
 }
 
-template <int D, typename TS, typename TC, int RM>
+template <int D, typename TS, typename TC, int RM, int V>
 __global__ void __launch_bounds__(kBlock) k_apply_tile(const TileJob* __restrict__ jobs, int njobs) {
   int tile, s0, s1;
   const TileJob J = job_tile_run(jobs, njobs, 1 << 30, tile, s0, s1);
   if (J.state && done_flag(J.state)) return;
-  apply_tile_body<D, TS, TC, RM>(J, tile, s0, s1, (const TS*)J.b, (TS*)J.out);
+  if (job_fixed(V, J.op.cmode)) apply_tile_body<D, TS, TC, RM, true>(J, tile, s0, s1, (const TS*)J.b, (TS*)J.out);
+  else apply_tile_body<D, TS, TC, RM, false>(J, tile, s0, s1, (const TS*)J.b, (TS*)J.out);
 }
 
 // ---------------------------------------------------------------------------
@@ -846,7 +911,7 @@ __global__ void __launch_bounds__(kBlock) k_apply_tile(const TileJob* __restrict
 // f_s = tau F_s (+ u0 on the first slab).  The tile values of u_s are kept
 // in registers and serve as u_{s-1} of the next slab.
 // ---------------------------------------------------------------------------
-template <int D, typename TS, int WHICH, int RM>
+template <int D, typename TS, int WHICH, int RM, bool FIX>
 __device__ __forceinline__ void resid_tile_body(const ResidJob& J, int tile, int s0, int s1,
                                                 const double* __restrict__ u, const double* __restrict__ p,
                                                 const double* __restrict__ F, const double* __restrict__ u0,
@@ -884,8 +949,18 @@ __device__ __forceinline__ void resid_tile_body(const ResidJob& J, int tile, int
 #pragma unroll
       for (int k = 0; k < NT; ++k) v[k] = vo[k] >= 0 ? base[vo[k]] : 0.0;
     };
-    double kr[nit<KB>()][RM];
-    load_kraw<D, KB, double, RM>(kr, t.kap, g.nnodes, t.R, n, ox, oy, oz);
+    double kr[FIX ? 1 : nit<KB>()][FIX ? 1 : RM];
+    if constexpr (FIX) {
+      // rank 1: the field is staged once and scaled per slab by tau a_0[s]
+      LevelOp L1{};
+      L1.kap = t.kap;
+      L1.c = t.cA;
+      L1.R = 1;
+      L1.cmode = CM_SCALE;
+      stage_fixed<D, KB, double>(sk, L1, g.nnodes, n, ox, oy, oz);
+    } else {
+      load_kraw<D, KB, double, RM>(kr, t.kap, g.nnodes, t.R, n, ox, oy, oz);
+    }
     double xn[nit<KB>()];
     prefetch_box<D, KB, double, double>(xn, X + long(s0) * g.npts, n, ox, oy, oz);
     // pointwise values of the current and the next slab
@@ -900,7 +975,8 @@ __device__ __forceinline__ void resid_tile_body(const ResidJob& J, int tile, int
     if (WHICH == 1) load_pts(pc, p + long(s0) * g.npts);
     for (int s = s0; s < s1; ++s) {
       const long o = long(s) * g.npts;
-      write_kappa<KB, double, RM>(sk, kr, load_op<double>(nullptr, t.cA, s, t.R));
+      const double gamma = FIX ? t.cA[s * kMaxRank] : 1.0;
+      if constexpr (!FIX) write_kappa<KB, double, RM>(sk, kr, load_op<double>(nullptr, t.cA, s, t.R));
       write_box<KB, double>(sx, xn);
       const bool more = s + 1 < t.N;          // slab s+1 exists
       if (more) {
@@ -925,7 +1001,7 @@ __device__ __forceinline__ void resid_tile_body(const ResidJob& J, int tile, int
             dg += w;
             off += w * sx[kq + nb_off<KB>(q)];
           }
-          const double Ax = dg * sx[kq] - off;
+          const double Ax = FIX ? gamma * (dg * sx[kq] - off) : dg * sx[kq] - off;
           double f = tau * Fc[k];
           if (s == 0) f += u0[vo[k]];
           if (WHICH == 0) {
@@ -956,12 +1032,16 @@ __device__ __forceinline__ void resid_tile_body(const ResidJob& J, int tile, int
   }
 }
 
-template <int D, typename TS, int WHICH, int RM>
+template <int D, typename TS, int WHICH, int RM, int V>
 __global__ void __launch_bounds__(kBlock) k_resid_tile(const ResidJob* __restrict__ jobs, int njobs) {
   int tile, s0, s1;
   const ResidJob J = job_tile_run(jobs, njobs, 1 << 30, tile, s0, s1);
   if (J.state && done_flag(J.state)) return;
-  resid_tile_body<D, TS, WHICH, RM>(J, tile, s0, s1, J.u, J.p, J.F, J.u0, (TS*)J.r, J.partial);
+  // the residual's operator is the A family: a fixed field when the rank is 1
+  if (job_fixed(V, J.t.R == 1 ? CM_SCALE : CM_SLAB))
+    resid_tile_body<D, TS, WHICH, RM, true>(J, tile, s0, s1, J.u, J.p, J.F, J.u0, (TS*)J.r, J.partial);
+  else
+    resid_tile_body<D, TS, WHICH, RM, false>(J, tile, s0, s1, J.u, J.p, J.F, J.u0, (TS*)J.r, J.partial);
 }
 
 }  // namespace stp
