@@ -35,7 +35,7 @@ FP64_PEAK_TFLOPS = 78.6
 # kernel sources hash to the recorded value (see the named profile).
 MEASURED_TRAFFIC = {
     ("heat2d_255_N256", "f64", "k_mg_down", 0): dict(
-        bytes=174384666, sources_sha256="ce2c2063783c9beb531ffac9a7f0b7433bde344523b8f17a40d9ecedf85a1fe2",
+        bytes=174851546, sources_sha256="96ade679484ca20cce29e8313adf31735aef7885ad7c7124586811071b9b5c24",
         profile="profiles/heat2d_255_N256_f64_mg_down_L0_traffic.md"),
 }
 
@@ -359,6 +359,90 @@ def cpu_baseline(workload):
                        f"{workload}: {sec:.1f} s")
 
 
+# ---------------------------------------------------------------------------
+# hardware-counter profiles (rocprofv3 output of this script)
+# ---------------------------------------------------------------------------
+COPY_ELEMS = 16646400   # float64 values in one slab-vector of heat2d_255_N256
+
+
+def copy_calibration():
+    """A plain device copy of a known size, profiled with the same counters as
+    the solver so that FETCH_SIZE / WRITE_SIZE can be scaled to bytes."""
+    import torch
+    a = torch.randn(COPY_ELEMS, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes=COPY_ELEMS * 8, copies=3)), flush=True)
+
+
+# launches that precede a level-0 multigrid down-sweep of the 2-D float64 solver:
+# the r_p residual, the forward transform and the middle operator
+_L0_PRED = ("k_resid_tile<2, double, 0,", "k_time_fft2<double, double, 0, 0,", "k_apply_tile<")
+
+
+def _kname(r):
+    return r["Kernel_Name"].split("(")[0].replace("void ", "").replace("stp::", "")
+
+
+def summarize_profile(d, steps):
+    """Markdown summary of rocprofv3 output of this script under d: the
+    --stats table (trace/), the level-0 down-sweep launches of the two timed
+    solves (graph replays, then eager launches; 3 steps + 1 each, picked by
+    their predecessor), and, when the counter passes are there, their HBM bytes
+    from FETCH_SIZE (p1/) and WRITE_SIZE (p2/) scaled by the copy calibration
+    passes (c1/, c2/).  Every run was made with --steps `steps`, --only-f64,
+    --skip-tol and --no-batch, so those solves are the last launches."""
+    import csv
+
+    def rows(sub, f):
+        with open(os.path.join(d, sub, f)) as fh:
+            return list(csv.DictReader(fh))
+
+    def l0(seq):
+        sel = [b for a, b in zip(seq, seq[1:]) if b[0].startswith("k_mg_down<") and a[0].startswith(_L0_PRED)]
+        return sel[-2 * (3 * steps + 1):]
+
+    avg = lambda v: sum(v) / len(v)
+    print("## rocprofv3 --stats (run_kernel_stats.csv, all dispatches of the run)\n")
+    print("| kernel | calls | avg us | min us | max us | % |\n|---|---|---|---|---|---|")
+    for r in rows("trace", "run_kernel_stats.csv")[:18]:
+        print(f"| `{r['Name'].split('(')[0].replace('void ', '')}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+              f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {r['Percentage']} |")
+    tr = sorted(rows("trace", "run_kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
+    t = [x[1] for x in l0([(_kname(r), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3) for r in tr])]
+    print("\n## Level-0 multigrid down-sweep\n")
+    print("Launches of `k_mg_down` that directly follow the r_p residual, the forward time transform or")
+    print("the middle operator (the level-0 down-sweeps of the three V-cycles of an iteration), in the")
+    print(f"two timed solves of {steps} iterations with the tuned schedule:\n")
+    print(f"| launches | avg us | min us | max us |\n|---|---|---|---|\n| {len(t)} | {avg(t):.1f} | {min(t):.1f} | "
+          f"{max(t):.1f} |")
+    if not os.path.isdir(os.path.join(d, "p1")):
+        return
+    res = {}
+    for i, cn in ((1, "FETCH_SIZE"), (2, "WRITE_SIZE")):
+        pm = sorted(rows(f"p{i}", "run_counter_collection.csv"), key=lambda r: int(r["Dispatch_Id"]))
+        v = l0([(_kname(r), float(r["Counter_Value"])) for r in pm if r["Counter_Name"] == cn])
+        cal = [float(r["Counter_Value"]) for r in rows(f"c{i}", "run_counter_collection.csv")
+               if "copy" in r["Kernel_Name"].lower() and int(r["Grid_Size"]) > 100000 and r["Counter_Name"] == cn]
+        factor = COPY_ELEMS * 8 / (avg(cal) * 1024)
+        kib = avg([x[1] for x in v])
+        res[cn] = (len(v), kib, avg(cal), factor, kib * 1024 * factor)
+    f, w = res["FETCH_SIZE"], res["WRITE_SIZE"]
+    print("\n## HBM traffic of the level-0 down-sweep\n")
+    print(f"Calibration: a copy of {COPY_ELEMS * 8:,} bytes reads FETCH_SIZE = {f[2]:,.1f} KiB and WRITE_SIZE = "
+          f"{w[2]:,.1f} KiB per dispatch, so bytes = FETCH_SIZE x 1024 x {f[3]:.3f} and WRITE_SIZE x 1024 x "
+          f"{w[3]:.3f}.\n")
+    print("| quantity | per launch |\n|---|---|")
+    print(f"| dispatches selected | {f[0]} (FETCH_SIZE run), {w[0]} (WRITE_SIZE run) |")
+    print(f"| FETCH_SIZE (KiB, raw) | {f[1]:,.1f} |\n| WRITE_SIZE (KiB, raw) | {w[1]:,.1f} |")
+    print(f"| HBM bytes read | {f[4]:,.0f} |\n| HBM bytes written | {w[4]:,.0f} |")
+    print(f"| traffic (read + written) | {f[4] + w[4]:,.0f} |")
+    print(f"\nKernel sources at measurement (sha256 of stp_kernels.h + stp_tiles.h + stp.hip):\n"
+          f"{kernel_sources_sha256()}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -374,10 +458,20 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in schedule heuristic")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch workload")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of one slab-vector (counter calibration)")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="only summarise rocprofv3 output under DIR (no GPU use)")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile, args.steps)
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU time sharding is a design "
-              "(see DESIGN.md), not an implementation.  Use --gpus 1.", file=sys.stderr)
+        print("bench.py: runs on one GPU only; sharding the time slabs over several GPUs is a design, "
+              "not an implementation.  Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     prob, dims, res = gpu_run(args)
     progress("workload done:", args.workload)

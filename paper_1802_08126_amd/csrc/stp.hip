@@ -846,7 +846,9 @@ struct SolverBase {
   virtual stp_status launch_knob(int knob) = 0;
   virtual stp_status launch_transform(int g) = 0;
   virtual stp_status setup_problem(Problem& q) = 0;
-  virtual stp_status iteration() = 0;
+  // full = false: only up to the stop test (the u-update of an iteration whose
+  // stop test must fire would find the problem done and do nothing)
+  virtual stp_status iteration(bool full = true) = 0;
   virtual stp_status run_vcycle(int which) = 0;
   virtual stp_status run_precH() = 0;
   virtual stp_status cast_in(const double* a, void* b, long n) = 0;
@@ -1147,7 +1149,7 @@ struct Solver : SolverBase {
     }
   }
 
-  stp_status iteration() override {
+  stp_status iteration(bool full = true) override {
     stp_status s;
     if ((s = run_resid<0>()) != STP_OK) return s;        // r_p = K u - A p - f   -> W1
     if ((s = run_vcycle(VC_A)) != STP_OK) return s;      // p += A~^{-1} r_p
@@ -1155,7 +1157,7 @@ struct Solver : SolverBase {
     c->kt.level = 0;
     KLAUNCH(k_finalize, dim3(unsigned(c->P)), dim3(kBlock), 0, c->stream, (const FinJob*)c->sites.fin_dev);
     LAUNCH_CHECK();
-    return run_precH();                                  // u += omega H~^{-1} r_u
+    return full ? run_precH() : STP_OK;                  // u += omega H~^{-1} r_u
   }
 
   stp_status cast_out(const void* a, double scale, double* b, long n) override {
@@ -1925,8 +1927,10 @@ stp_status stp_uzawa_solve_batch(stp_ctx* c, double* const* u, double* const* p,
   while (true) {
     const int todo = std::min(chunk, max_launch - launched);
     for (int q = 0; q < todo; ++q) {
-      if (graph) HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
-      else if ((s = c->impl->iteration()) != STP_OK) return s;
+      // iteration max_iter always stops at its test: launch only its first half
+      const bool last = launched == max_launch - 1;
+      if (graph && !last) HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
+      else if ((s = c->impl->iteration(!last)) != STP_OK) return s;
       ++launched;
     }
     for (int i = 0; i < c->P; ++i)
