@@ -194,6 +194,39 @@ void stp_destroy(stp_ctx* ctx);
 stp_status stp_omega_info(stp_ctx* ctx, int i, double* out4);
 stp_status stp_set_omega(stp_ctx* ctx, const double* omega);
 
+/* GMRES acceleration of the inexact Uzawa method (the solver of the
+ * experiments of Section 8.3).  The iteration (3.1) is the stationary method
+ * x <- x + P^{-1}(g - S x) on the saddle system S [p; u] = g = [-f; -f] of
+ * eq. (2.7), with P^{-1} r = [d; -omega H~^{-1}(r_u + K^T d)], d = A~^{-1} r_p
+ * (one Uzawa sweep from zero).  stp_gmres_solve runs flexible GMRES(restart)
+ * with P^{-1} as right preconditioner: each cycle minimises ||g - S x||_2 over
+ * x_0 + span{P^{-1} v_0, ..., P^{-1} v_{k-1}} (Arnoldi vectors v_j; classical
+ * Gram-Schmidt, repeated once when the projection removes more than 90 % of
+ * the norm; Givens rotations on the host).  It stops on the
+ * Uzawa solver's test ||f - B u||_2 <= opt.tol ||f||_2, evaluated at every
+ * restart and after each step whose least-squares estimate of ||g - S x||_2
+ * is <= tol ||g||_2 (on the candidate u; a failed check continues the
+ * cycle), or after opt.max_iter Arnoldi steps.  omega is the context's (given
+ * or estimated); the preconditioner runs in the context's precision and the
+ * Krylov vectors in float64.  Single-problem contexts only.
+ *
+ * u, p: device, N x n^d float64 each: the initial guess in, the result out.
+ * ws: device, at least stp_gmres_workspace_bytes(ctx, restart) bytes, 8-byte
+ * aligned, owned by the caller (the restart + 1 Arnoldi vectors and restart
+ * preconditioned vectors of 2 N n^d values each, one vector of N n^d values
+ * and reduction scratch).  hist: optional host array of max_iter + 1 values:
+ * ||g - S x_0|| / ||g|| and then the least-squares estimate after each
+ * Arnoldi step, relative to ||g||.  stats (optional): iters = Arnoldi steps,
+ * rel_res = ||f - B u|| / ||f|| of the returned u.
+ * Errors: EINVAL (NULL u or p, restart not in 1..64, workspace too small or
+ * misaligned), EUNSUPPORTED (batch context, no spatial solver), ENOTCONV
+ * (max_iter reached or breakdown; u, p hold the last iterate), EDIVERGED
+ * (non-finite residual), EDEVICE.  stp_gmres_workspace_bytes returns 0 for
+ * invalid arguments. */
+size_t stp_gmres_workspace_bytes(stp_ctx* ctx, int restart);
+stp_status stp_gmres_solve(stp_ctx* ctx, double* u, double* p, int restart, void* ws, size_t ws_bytes,
+                           double* hist, stp_stats* stats);
+
 /* Autotuner (project-written).  Times, on the context's own buffers and
  * stream, the candidate schedules of every merged launch of an iteration and
  * keeps the fastest:

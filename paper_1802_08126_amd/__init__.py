@@ -32,6 +32,8 @@ from .binding import (  # noqa: F401
     stp_create,
     stp_create_batch,
     stp_destroy,
+    stp_gmres_solve,
+    stp_gmres_workspace_bytes,
     stp_omega_info,
     stp_set_omega,
     stp_schedule_string,

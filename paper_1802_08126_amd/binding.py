@@ -101,6 +101,11 @@ def load() -> C.CDLL:
     lib.stp_omega_info.restype = C.c_int
     lib.stp_set_omega.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
     lib.stp_set_omega.restype = C.c_int
+    lib.stp_gmres_workspace_bytes.argtypes = [C.c_void_p, C.c_int]
+    lib.stp_gmres_workspace_bytes.restype = C.c_size_t
+    lib.stp_gmres_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t,
+                                    C.POINTER(C.c_double), C.POINTER(stp_stats)]
+    lib.stp_gmres_solve.restype = C.c_int
     lib.stp_autotune.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(stp_tune_report)]
     lib.stp_autotune.restype = C.c_int
     lib.stp_schedule_string.argtypes = [C.c_void_p]
@@ -277,6 +282,23 @@ def stp_uzawa_solve(ctx, u, p):
     return status, st
 
 
+def stp_gmres_workspace_bytes(ctx, restart) -> int:
+    return int(load().stp_gmres_workspace_bytes(ctx, int(restart)))
+
+
+def stp_gmres_solve(ctx, u, p, restart, ws, max_iter=None):
+    """GMRES(restart) around the Uzawa sweep; ws: a device tensor of at least
+    stp_gmres_workspace_bytes bytes; max_iter: the context's (sizes the
+    residual history; None: no history).  Returns (status, stats, history)."""
+    st = stp_stats()
+    hist = (C.c_double * (max_iter + 1))() if max_iter is not None else None
+    status = load().stp_gmres_solve(ctx, C.c_void_p(u.data_ptr()), C.c_void_p(p.data_ptr()), int(restart),
+                                    C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel() * ws.element_size()),
+                                    hist, C.byref(st))
+    h = None if hist is None else [hist[i] for i in range(st.iters + 1)]
+    return status, st, h
+
+
 def stp_autotune(ctx, reps=5, use_cache=True):
     """Tune the launch schedule of the context; returns the report as a dict."""
     r = stp_tune_report()
@@ -336,6 +358,7 @@ class SpaceTimeSolver:
         self.shape = (N,) + (n,) * dim
         self.device = F.device
         self.stream = stream
+        self.max_iter = int(opts.get("max_iter", 500))
         with torch.cuda.device(self.device):
             self.ctx, self._keep = stp_create(dim, n, N, tau, kfields, tcoef, F, u0,
                                               workspace=workspace, stream=stream, **opts)
@@ -371,6 +394,27 @@ class SpaceTimeSolver:
             _check(status, "stp_uzawa_solve")
         if status not in (STP_OK, STP_ENOTCONV, STP_EDIVERGED):
             _check(status, "stp_uzawa_solve")
+        return u, p, info
+
+    def gmres(self, u=None, p=None, restart=20, workspace=None, raise_on_error=False):
+        """GMRES(restart) acceleration of the Uzawa sweep from (u, p) (zeros if
+        None), with the context's tol, max_iter and omega.  Returns (u, p,
+        stats dict with the residual history)."""
+        import torch
+        u = torch.zeros(self.shape, dtype=torch.float64, device=self.device) if u is None else self._vec(u)
+        p = torch.zeros(self.shape, dtype=torch.float64, device=self.device) if p is None else self._vec(p)
+        nb = stp_gmres_workspace_bytes(self.ctx, restart)
+        if nb == 0:
+            raise StpError(STP_EINVAL, f"no GMRES workspace size for restart {restart}")
+        if workspace is None or workspace.numel() * workspace.element_size() < nb:
+            workspace = torch.empty((nb + 7) // 8, dtype=torch.float64, device=self.device)
+        status, st, hist = stp_gmres_solve(self.ctx, u, p, restart, workspace, self.max_iter)
+        info = dict(status=status, iters=st.iters, rel_res=st.rel_res, omega=st.omega_used, ms=st.t_solve_ms,
+                    history=hist)
+        if raise_on_error and status != STP_OK:
+            _check(status, "stp_gmres_solve")
+        if status not in (STP_OK, STP_ENOTCONV, STP_EDIVERGED):
+            _check(status, "stp_gmres_solve")
         return u, p, info
 
     def timing(self, enable=True):

@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -326,6 +327,7 @@ struct stp_ctx {
   KTimer kt;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexecA = nullptr, gexecH = nullptr;   // A~^{-1} cycle and H~^{-1} (GMRES preconditioner)
   Schedule sched;
   std::string sched_text;
 };
@@ -852,6 +854,8 @@ struct SolverBase {
   virtual stp_status run_vcycle(int which) = 0;
   virtual stp_status run_precH() = 0;
   virtual stp_status cast_in(const double* a, void* b, long n) = 0;
+  // W1 of problem 0 = sgn (r + K^T d) in the storage type (input of the H-tilde solve)
+  virtual stp_status kt_add_in(const double* r, const double* d, double sgn) = 0;
   virtual stp_status cast_out(const void* a, double scale, double* b, long n) = 0;
   virtual stp_status resid(int which) = 0;
 };
@@ -1168,6 +1172,15 @@ struct Solver : SolverBase {
   }
 
   stp_status resid(int which) override { return which == 0 ? run_resid<0>() : run_resid<1>(); }
+
+  stp_status kt_add_in(const double* r, const double* d, double sgn) override {
+    Problem& q = c->pr[0];
+    const long nv = long(q.N) * q.g0.npts;
+    KLAUNCH((k_kt_add_cast<TS>), dim3(unsigned((nv + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
+            q.g0.npts, q.N, r, d, sgn, (TS*)q.W1);
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
 
   stp_status cast_in(const double* a, void* b, long n) override {
     KLAUNCH((k_cast_from64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n, a, (TS*)b);
@@ -1819,6 +1832,8 @@ void stp_destroy(stp_ctx* c) {
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   for (hipEvent_t e : c->kt.pool) (void)hipEventDestroy(e);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->gexecA) (void)hipGraphExecDestroy(c->gexecA);
+  if (c->gexecH) (void)hipGraphExecDestroy(c->gexecH);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
@@ -1872,11 +1887,42 @@ stp_status stp_apply_precond(stp_ctx* c, int which, const double* r, double* z) 
   return STP_OK;
 }
 
-// Capture one iteration over the batch on a private stream (capture is not
-// possible on the null stream).  The graph reads the job tables at replay
-// time, so it stays valid when a solve rebinds u and p.
-static stp_status capture_iteration(stp_ctx* c) {
-  if (c->gexec) return STP_OK;
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// GMRES acceleration of the Uzawa sweep
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kMaxRestart = 64;
+constexpr int kGsBlocks = 2048;   // blocks of the Gram-Schmidt reductions (fixed: deterministic sums)
+
+// workspace of stp_gmres_solve, offsets in doubles, every region 256-byte aligned
+struct GmresLayout {
+  size_t v2 = 0;   // stride of the basis vectors (2 N n^d, rounded up)
+  size_t V = 0, Z = 0, ucand = 0, part = 0, slots = 0, coef = 0, total = 0;
+};
+
+GmresLayout gmres_layout(const Problem& q, int m) {
+  auto al = [](size_t x) { return (x + 31) & ~size_t(31); };
+  const long nv = long(q.N) * q.g0.npts;
+  const dim3 gp = grid_pts(q.g0.npts, q.N);
+  const size_t fparts = size_t(gp.x) * gp.y * gp.z;
+  GmresLayout L;
+  L.v2 = al(size_t(2) * nv);
+  L.V = 0;
+  L.Z = L.V + size_t(m + 1) * L.v2;
+  L.ucand = L.Z + size_t(m) * L.v2;
+  L.part = L.ucand + al(nv);
+  L.slots = L.part + al(std::max(size_t(kMaxRestart + 2) * kGsBlocks, fparts));
+  L.coef = L.slots + al(2 * (kMaxRestart + 2));
+  L.total = L.coef + al(kMaxRestart + 1);
+  return L;
+}
+
+// Capture the launches of body on a private stream (capture is not possible on
+// the null stream) and instantiate them into *out.
+stp_status capture_graph(stp_ctx* c, hipGraphExec_t* out, const std::function<stp_status()>& body) {
   if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   hipStream_t saved = c->stream;
   c->stream = c->cap_stream;
@@ -1884,7 +1930,7 @@ static stp_status capture_iteration(stp_ctx* c) {
   hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
   stp_status s = STP_OK;
   if (e == hipSuccess) {
-    s = c->impl->iteration();
+    s = body();
     e = hipStreamEndCapture(c->cap_stream, &graph);
   }
   c->stream = saved;
@@ -1893,13 +1939,269 @@ static stp_status capture_iteration(stp_ctx* c) {
     return s;
   }
   if (e != hipSuccess) return fail(STP_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
-    c->gexec = nullptr;
+    *out = nullptr;
     return fail(STP_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
   }
   return STP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t stp_gmres_workspace_bytes(stp_ctx* c, int restart) {
+  if (!c || c->P != 1 || restart < 1 || restart > kMaxRestart) return 0;
+  return gmres_layout(c->pr[0], restart).total * 8;
+}
+
+stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* ws, size_t ws_bytes, double* hist,
+                           stp_stats* stats) {
+  if (!c || !u || !p) return fail(STP_EINVAL, "NULL argument (u and p are required)");
+  if (c->P != 1) return fail(STP_EUNSUPPORTED, "stp_gmres_solve needs a single-problem context");
+  if (c->spatial == STP_SPATIAL_NONE) return fail(STP_EUNSUPPORTED, "context created without a spatial solver");
+  if (restart < 1 || restart > kMaxRestart) return fail(STP_EINVAL, "restart %d not in 1..%d", restart, kMaxRestart);
+  Problem& q = c->pr[0];
+  const GmresLayout L = gmres_layout(q, restart);
+  if (!ws || ws_bytes < L.total * 8)
+    return fail(STP_EINVAL, "GMRES workspace of %zu bytes given, %zu needed", ws_bytes, L.total * 8);
+  if (reinterpret_cast<uintptr_t>(ws) % 8) return fail(STP_EINVAL, "GMRES workspace not 8-byte aligned");
+  const long nv = long(q.N) * q.g0.npts;
+  const long v2 = long(L.v2);
+  double* base = static_cast<double*>(ws);
+  double* V = base + L.V;
+  double* Z = base + L.Z;
+  double* uc = base + L.ucand;
+  double* part = base + L.part;
+  double* slots = base + L.slots;
+  double* coef = base + L.coef;
+  const dim3 gp = grid_pts(q.g0.npts, q.N);
+  const long fparts = long(gp.x) * gp.y * gp.z;
+  const TimeOp t{q.kap64, q.cA64, q.R, q.N};
+  const double fnorm = q.fnorm, gnorm = std::sqrt(2.0) * q.fnorm;
+  const double omega = q.omega, tol = c->opt.tol;
+  const int max_iter = c->opt.max_iter;
+  auto vgrid = [](long n) { return dim3(unsigned((n + kBlock - 1) / kBlock)); };
+  std::vector<double> hs(2 * (kMaxRestart + 2));
+
+  // the tile kernels run only while the problem's stop flag reads "running"
+  c->state_host[0] = DevState{};
+  c->state_host[0].fnorm = q.fnorm;
+  HIP_TRY(hipMemcpyAsync(q.state, &c->state_host[0], sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipEventRecord(c->ev0, c->stream));
+
+  // ||f - B uu||_2 (synchronises)
+  auto fmBu = [&](const double* uu, double& out) -> stp_status {
+    switch (c->dim) {
+      case 1: KLAUNCH(k_fmBu_partial<1>, gp, dim3(kBlock), 0, c->stream, q.g0, t, q.tau, q.F, q.u0, uu, part); break;
+      case 2: KLAUNCH(k_fmBu_partial<2>, gp, dim3(kBlock), 0, c->stream, q.g0, t, q.tau, q.F, q.u0, uu, part); break;
+      default: KLAUNCH(k_fmBu_partial<3>, gp, dim3(kBlock), 0, c->stream, q.g0, t, q.tau, q.F, q.u0, uu, part);
+    }
+    LAUNCH_CHECK();
+    KLAUNCH(k_sum_rows, dim3(1), dim3(kBlock), 0, c->stream, (const double*)part, fparts, slots);
+    LAUNCH_CHECK();
+    HIP_TRY(hipMemcpyAsync(hs.data(), slots, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    out = std::sqrt(std::max(hs[0], 0.0));
+    return STP_OK;
+  };
+  // out[0..k) = <V_i, w> (V_i = V + i v2), out[k] = <w, w> when self; device only
+  auto mdot = [&](int k, const double* w, bool self, double* out) -> stp_status {
+    for (int c0 = 0; c0 < k || (c0 == 0 && k == 0); c0 += kDotRows) {
+      const int kk = std::min(kDotRows, k - c0);
+      const bool last = c0 + kk >= k;
+      KLAUNCH(k_mdot_partial, dim3(kGsBlocks), dim3(kBlock), 0, c->stream, 2 * nv, (const double*)(V + c0 * v2), v2,
+              kk, int(self && last), w, part + long(c0) * kGsBlocks);
+      LAUNCH_CHECK();
+    }
+    KLAUNCH(k_sum_rows, dim3(unsigned(k + (self ? 1 : 0))), dim3(kBlock), 0, c->stream, (const double*)part,
+            long(kGsBlocks), out);
+    LAUNCH_CHECK();
+    return STP_OK;
+  };
+  auto maxpy = [&](double* w, long n, const double* Vb, int k, const double* cf, double sgn) -> stp_status {
+    KLAUNCH(k_maxpy, vgrid(n), dim3(kBlock), 0, c->stream, n, w, Vb, v2, k, cf, sgn);
+    LAUNCH_CHECK();
+    return STP_OK;
+  };
+  // w -= sum_{i<k} cf[i] V_i over the whole saddle vector, then *out = ||w||^2 (device)
+  auto project = [&](double* w, int k, const double* cf, double* out) -> stp_status {
+    KLAUNCH(k_maxpy_norm, dim3(kGsBlocks), dim3(kBlock), 0, c->stream, 2 * nv, w, (const double*)V, v2, k, cf,
+            part);
+    LAUNCH_CHECK();
+    KLAUNCH(k_sum_rows, dim3(1), dim3(kBlock), 0, c->stream, (const double*)part, long(kGsBlocks), out);
+    LAUNCH_CHECK();
+    return STP_OK;
+  };
+  auto scale = [&](double* x, long n, double a) -> stp_status {
+    KLAUNCH(k_axpby, vgrid(n), dim3(kBlock), 0, c->stream, n, a, (const double*)x, 0.0, x);
+    LAUNCH_CHECK();
+    return STP_OK;
+  };
+  // z = P^{-1} v: one Uzawa sweep from zero, [A~^{-1} v_p; -omega H~^{-1}(v_u + K^T A~^{-1} v_p)].
+  // The two solves replay captured graphs (they read the job tables, rebound
+  // for every z, at replay time).
+  const bool graph = c->opt.use_graph && !c->kt.on;
+  if (graph && !c->gexecA) {
+    stp_status s = capture_graph(c, &c->gexecA, [c]() { return c->impl->run_vcycle(VC_A); });
+    if (s != STP_OK) return s;
+  }
+  if (graph && !c->gexecH) {
+    stp_status s = capture_graph(c, &c->gexecH, [c]() { return c->impl->run_precH(); });
+    if (s != STP_OK) return s;
+  }
+  auto precond = [&](const double* vj, double* zj) -> stp_status {
+    stp_status s;
+    HIP_TRY(hipMemsetAsync(zj, 0, size_t(2 * nv) * 8, c->stream));
+    std::vector<double*> zp(1, zj), zu(1, zj + nv);
+    if ((s = bind_jobs(c, zp, zp, nullptr, zp, zu, omega)) != STP_OK) return s;
+    if ((s = c->impl->cast_in(vj, q.W1, nv)) != STP_OK) return s;
+    if (graph) HIP_TRY(hipGraphLaunch(c->gexecA, c->stream));             // z_p += A~^{-1} v_p
+    else if ((s = c->impl->run_vcycle(VC_A)) != STP_OK) return s;
+    if ((s = c->impl->kt_add_in(vj + nv, zj, -1.0)) != STP_OK) return s;  // W1 = -(v_u + K^T z_p)
+    if (graph) HIP_TRY(hipGraphLaunch(c->gexecH, c->stream));             // z_u += omega H~^{-1} W1
+    else if ((s = c->impl->run_precH()) != STP_OK) return s;
+    return STP_OK;
+  };
+  // upper-triangular solve of the rotated Hessenberg system (host), then upload
+  auto solve_y = [&](const std::vector<double>& H, const std::vector<double>& sv, int k, int m,
+                     std::vector<double>& y) -> stp_status {
+    y.assign(k, 0.0);
+    for (int i = k - 1; i >= 0; --i) {
+      double a = sv[i];
+      for (int l = i + 1; l < k; ++l) a -= H[i * m + l] * y[l];
+      y[i] = a / H[i * m + i];
+    }
+    HIP_TRY(hipMemcpyAsync(coef, y.data(), size_t(k) * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return STP_OK;
+  };
+
+  stp_status s;
+  int iters = 0, nh = 0;
+  int outcome = 3;   // 1 converged, 2 non-finite, 3 max_iter, 4 breakdown
+  double res = 0.0;
+  std::vector<double> H, cs, sn, sv, y;
+  while (true) {
+    if ((s = fmBu(u, res)) != STP_OK) return s;
+    if (!std::isfinite(res)) { outcome = 2; break; }
+    if (res <= tol * fnorm) { outcome = 1; break; }
+    if (iters >= max_iter) break;
+    const int m = std::min(restart, max_iter - iters);
+    switch (c->dim) {   // v_0 = g - S x
+      case 1: KLAUNCH(k_saddle_resid<1>, gp, dim3(kBlock), 0, c->stream, q.g0, t, q.tau, q.F, q.u0, p, u, V, V + nv); break;
+      case 2: KLAUNCH(k_saddle_resid<2>, gp, dim3(kBlock), 0, c->stream, q.g0, t, q.tau, q.F, q.u0, p, u, V, V + nv); break;
+      default: KLAUNCH(k_saddle_resid<3>, gp, dim3(kBlock), 0, c->stream, q.g0, t, q.tau, q.F, q.u0, p, u, V, V + nv);
+    }
+    LAUNCH_CHECK();
+    if ((s = mdot(0, V, true, slots)) != STP_OK) return s;
+    HIP_TRY(hipMemcpyAsync(hs.data(), slots, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const double beta = std::sqrt(std::max(hs[0], 0.0));
+    if (hist && nh == 0) hist[nh++] = beta / gnorm;
+    if (!(beta > 0.0)) { outcome = std::isfinite(beta) ? 1 : 2; break; }
+    if ((s = scale(V, 2 * nv, 1.0 / beta)) != STP_OK) return s;
+    H.assign(size_t(m + 1) * m, 0.0);
+    cs.assign(m, 0.0);
+    sn.assign(m, 0.0);
+    sv.assign(m + 1, 0.0);
+    sv[0] = beta;
+    int k = 0;
+    bool conv = false;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + j * v2;
+      double* zj = Z + j * v2;
+      double* w = V + (j + 1) * v2;
+      if ((s = precond(vj, zj)) != STP_OK) return s;
+      switch (c->dim) {   // w = S z_j
+        case 1: KLAUNCH(k_apply_saddle<1>, gp, dim3(kBlock), 0, c->stream, q.g0, t, zj, zj + nv, w, w + nv); break;
+        case 2: KLAUNCH(k_apply_saddle<2>, gp, dim3(kBlock), 0, c->stream, q.g0, t, zj, zj + nv, w, w + nv); break;
+        default: KLAUNCH(k_apply_saddle<3>, gp, dim3(kBlock), 0, c->stream, q.g0, t, zj, zj + nv, w, w + nv);
+      }
+      LAUNCH_CHECK();
+      // classical Gram-Schmidt, repeated once when the projection removes more
+      // than 90 % of the norm (the orthogonality lost in one pass is about the
+      // unit roundoff times the ratio of the norms before and after)
+      if ((s = mdot(j + 1, w, true, slots)) != STP_OK) return s;
+      if ((s = project(w, j + 1, slots, slots + (j + 2))) != STP_OK) return s;
+      HIP_TRY(hipMemcpyAsync(hs.data(), slots, size_t(j + 3) * 8, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      for (int i = 0; i <= j; ++i) H[i * m + j] = hs[i];
+      double nn = hs[j + 2];
+      if (nn < 1e-2 * hs[j + 1]) {
+        if ((s = mdot(j + 1, w, false, slots)) != STP_OK) return s;
+        if ((s = project(w, j + 1, slots, slots + (j + 1))) != STP_OK) return s;
+        HIP_TRY(hipMemcpyAsync(hs.data(), slots, size_t(j + 2) * 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (int i = 0; i <= j; ++i) H[i * m + j] += hs[i];
+        nn = hs[j + 1];
+      }
+      const double hn = std::sqrt(std::max(nn, 0.0));
+      if (!std::isfinite(hn)) { outcome = 2; break; }
+      if (hn > 0.0 && (s = scale(w, 2 * nv, 1.0 / hn)) != STP_OK) return s;
+      for (int i = 0; i < j; ++i) {   // earlier rotations on the new column
+        const double a = H[i * m + j], b = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * b;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      }
+      const double hjj = H[j * m + j];
+      const double den = std::hypot(hjj, hn);
+      if (den == 0.0) break;   // singular least-squares problem
+      cs[j] = hjj / den;
+      sn[j] = hn / den;
+      H[j * m + j] = den;
+      sv[j + 1] = -sn[j] * sv[j];
+      sv[j] = cs[j] * sv[j];
+      k = j + 1;
+      ++iters;
+      const double est = std::fabs(sv[j + 1]);
+      if (hist) hist[nh++] = est / gnorm;
+      if (est <= tol * gnorm) {   // check the stop test on the candidate u
+        if ((s = solve_y(H, sv, k, m, y)) != STP_OK) return s;
+        HIP_TRY(hipMemcpyAsync(uc, u, size_t(nv) * 8, hipMemcpyDeviceToDevice, c->stream));
+        if ((s = maxpy(uc, nv, Z + nv, k, coef, 1.0)) != STP_OK) return s;
+        if ((s = fmBu(uc, res)) != STP_OK) return s;
+        if (res <= tol * fnorm) {
+          conv = true;
+          break;
+        }
+      }
+    }
+    if (outcome == 2) break;
+    if (k > 0) {   // x += Z y
+      if ((s = solve_y(H, sv, k, m, y)) != STP_OK) return s;
+      if ((s = maxpy(p, nv, Z, k, coef, 1.0)) != STP_OK) return s;
+      if ((s = maxpy(u, nv, Z + nv, k, coef, 1.0)) != STP_OK) return s;
+    }
+    if (conv) { outcome = 1; break; }
+    if (k == 0) { outcome = 4; break; }
+  }
+  HIP_TRY(hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(hipEventSynchronize(c->ev1));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  const stp_status r = outcome == 1 ? STP_OK : outcome == 2 ? STP_EDIVERGED : STP_ENOTCONV;
+  if (stats) {
+    stats->iters = iters;
+    stats->rel_res = res / fnorm;
+    stats->omega_used = omega;
+    stats->t_solve_ms = ms;
+    stats->status = r;
+  }
+  if (outcome == 2) return fail(r, "GMRES: non-finite residual after %d steps", iters);
+  if (outcome == 4) return fail(r, "GMRES: breakdown after %d steps (rel %.3e)", iters, res / fnorm);
+  if (outcome == 3) return fail(r, "GMRES: max_iter %d reached (rel %.3e)", max_iter, res / fnorm);
+  return STP_OK;
+}
+
+// Capture one iteration over the batch on a private stream (capture is not
+// possible on the null stream).  The graph reads the job tables at replay
+// time, so it stays valid when a solve rebinds u and p.
+static stp_status capture_iteration(stp_ctx* c) {
+  if (c->gexec) return STP_OK;
+  return capture_graph(c, &c->gexec, [c]() { return c->impl->iteration(); });
 }
 
 stp_status stp_uzawa_solve_batch(stp_ctx* c, double* const* u, double* const* p, stp_stats* stats) {
@@ -2105,10 +2407,11 @@ stp_status stp_autotune(stp_ctx* c, int reps, int use_cache, stp_tune_report* re
       r.from_cache = 1;
     }
   }
-  if (c->gexec) {   // the launch shapes change: capture again at the next solve
-    (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
-  }
+  for (hipGraphExec_t* g : {&c->gexec, &c->gexecA, &c->gexecH})
+    if (*g) {   // the launch shapes change: capture again at the next solve
+      (void)hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
   const size_t P = c->pr.size();
   std::vector<double*> nul(P, nullptr);
   if (r.from_cache) {

@@ -55,17 +55,21 @@ struct Geom {
 
 __device__ __forceinline__ int slab_index() { return blockIdx.y + gridDim.y * blockIdx.z; }
 
+// point index inside a slab (< n^d < 2^31) -> coordinates, in 32-bit arithmetic
 template <int D>
 __device__ __forceinline__ void decode(long i, int n, int& x, int& y, int& z) {
+  const unsigned q = unsigned(i), un = unsigned(n);
   if (D == 1) {
-    x = int(i); y = 0; z = 0;
+    x = int(q); y = 0; z = 0;
   } else if (D == 2) {
-    y = int(i / n); x = int(i - long(y) * n); z = 0;
+    const unsigned yy = q / un;
+    y = int(yy); x = int(q - yy * un); z = 0;
   } else {
-    long yz = i / n;
-    x = int(i - yz * n);
-    z = int(yz / n);
-    y = int(yz - long(z) * n);
+    const unsigned yz = q / un;
+    const unsigned zz = yz / un;
+    x = int(q - yz * un);
+    z = int(zz);
+    y = int(yz - zz * un);
   }
 }
 
@@ -154,6 +158,40 @@ __device__ __forceinline__ void stencil(const TV* __restrict__ xs, long i, int x
   offsum = osum;
 }
 
+// Both stencil sums of one point for two vectors with the same operator:
+// diag, sum_nb w a_nb and sum_nb w b_nb (face weights computed once).
+template <int D>
+__device__ __forceinline__ void stencil2(const double* __restrict__ a, const double* __restrict__ b, long i, int x,
+                                         int y, int z, const Geom& g, const double* __restrict__ kap,
+                                         const SlabOp<double>& op, int R, double& diag, double& oa, double& ob) {
+  const int n = g.n;
+  const long nn = n + 2;
+  const long node = node_of<D>(x, y, z, n);
+  const double kc = kmix(kap, g.nnodes, node, op, R);
+  double dsum = op.sigma, sa = 0.0, sb = 0.0;
+  auto face = [&](long dnode, long di, bool inside) {
+    const double w = kc + kmix(kap, g.nnodes, node + dnode, op, R);
+    dsum += w;
+    if (inside) {
+      sa += w * a[i + di];
+      sb += w * b[i + di];
+    }
+  };
+  face(-1, -1, x > 0);
+  face(1, 1, x < n - 1);
+  if (D >= 2) {
+    face(-nn, -n, y > 0);
+    face(nn, n, y < n - 1);
+  }
+  if (D >= 3) {
+    face(-nn * nn, -long(n) * n, z > 0);
+    face(nn * nn, long(n) * n, z < n - 1);
+  }
+  diag = dsum;
+  oa = sa;
+  ob = sb;
+}
+
 // Diagonal only.
 template <int D, typename TC>
 __device__ __forceinline__ TC diag_at(int x, int y, int z, const Geom& g, const TC* __restrict__ kap,
@@ -226,15 +264,14 @@ __global__ void __launch_bounds__(kBlock) k_apply_saddle(Geom g, TimeOp t, const
   decode<D>(i, g.n, px, py, pz);
   const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
   const long o = long(s) * g.npts;
-  double dg, off;
-  stencil<D, double>(p + o, i, px, py, pz, g, t.kap, op, t.R, dg, off);
-  const double Ap = dg * p[o + i] - off;
-  stencil<D, double>(u + o, i, px, py, pz, g, t.kap, op, t.R, dg, off);
-  const double Au = dg * u[o + i] - off;
+  double dg, offp, offu;
+  stencil2<D>(p + o, u + o, i, px, py, pz, g, t.kap, op, t.R, dg, offp, offu);
+  const double pc = p[o + i];
   const double uc = u[o + i];
+  const double Ap = dg * pc - offp;
+  const double Au = dg * uc - offu;
   const double um = s > 0 ? u[o - g.npts + i] : 0.0;
   const double up = s + 1 < t.N ? u[o + g.npts + i] : 0.0;
-  const double pc = p[o + i];
   const double pp = s + 1 < t.N ? p[o + g.npts + i] : 0.0;
   yp[o + i] = Ap - (uc - um);
   yu[o + i] = -(pc - pp) - (2.0 * uc - um - up) - Au;
@@ -1114,6 +1151,162 @@ __global__ void k_kappa_min(long nnodes, int R, int S, const double* __restrict_
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Krylov acceleration (GMRES around the Uzawa sweep), float64 vectors
+// ---------------------------------------------------------------------------
+// r = g - saddle [p; u] with g = [-f; -f], f_s = tau F_s (+ u0 on the first slab)
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_saddle_resid(Geom g, TimeOp t, double tau, const double* __restrict__ F,
+                                                         const double* __restrict__ u0, const double* __restrict__ p,
+                                                         const double* __restrict__ u, double* __restrict__ rp,
+                                                         double* __restrict__ ru) {
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (s >= t.N || i >= g.npts) return;
+  int px, py, pz;
+  decode<D>(i, g.n, px, py, pz);
+  const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
+  const long o = long(s) * g.npts;
+  double dg, offp, offu;
+  stencil2<D>(p + o, u + o, i, px, py, pz, g, t.kap, op, t.R, dg, offp, offu);
+  const double pc = p[o + i];
+  const double uc = u[o + i];
+  const double Ap = dg * pc - offp;
+  const double Au = dg * uc - offu;
+  const double um = s > 0 ? u[o - g.npts + i] : 0.0;
+  const double up = s + 1 < t.N ? u[o + g.npts + i] : 0.0;
+  const double pp = s + 1 < t.N ? p[o + g.npts + i] : 0.0;
+  double f = tau * F[o + i];
+  if (s == 0) f += u0[i];
+  rp[o + i] = -f - (Ap - (uc - um));
+  ru[o + i] = -f + (pc - pp) + (2.0 * uc - um - up) + Au;
+}
+
+// block partials of ||f - B u||^2 over a (points, slabs) grid
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_fmBu_partial(Geom g, TimeOp t, double tau, const double* __restrict__ F,
+                                                         const double* __restrict__ u0, const double* __restrict__ u,
+                                                         double* __restrict__ partial) {
+  const int s = slab_index();
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (s < t.N && i < g.npts) {
+    int px, py, pz;
+    decode<D>(i, g.n, px, py, pz);
+    const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
+    const long o = long(s) * g.npts;
+    double dg, off;
+    stencil<D, double>(u + o, i, px, py, pz, g, t.kap, op, t.R, dg, off);
+    const double uc = u[o + i];
+    const double um = s > 0 ? u[o - g.npts + i] : 0.0;
+    double f = tau * F[o + i];
+    if (s == 0) f += u0[i];
+    const double e = f - ((uc - um) + (dg * uc - off));
+    v = e * e;
+  }
+  const double bs = block_sum(v);
+  if (threadIdx.x == 0) partial[long(slab_index()) * gridDim.x + blockIdx.x] = bs;
+}
+
+// out_s = sgn (r_s + d_s - d_{s+1})  (sgn (r + K^T d), d_N := 0), in the storage
+// type of the preconditioner's input
+template <typename TS>
+__global__ void k_kt_add_cast(long npts, int N, const double* __restrict__ r, const double* __restrict__ d,
+                              double sgn, TS* __restrict__ out) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  const long n = long(N) * npts;
+  if (i >= n) return;
+  const double dn = i + npts < n ? d[i + npts] : 0.0;
+  st<TS, double>(out, i, sgn * (r[i] + d[i] - dn));
+}
+
+constexpr int kDotRows = 8;   // basis vectors per multi-dot launch
+
+// partial[q * gridDim.x + block] = block part of <V_q, w> for q < k (V_q = V + q ld),
+// and, when self != 0, row k = block part of <w, w>
+__global__ void __launch_bounds__(kBlock) k_mdot_partial(long n, const double* __restrict__ V, long ld, int k,
+                                                         int self, const double* __restrict__ w,
+                                                         double* __restrict__ partial) {
+  __shared__ double red[kDotRows + 1][kBlock / 64];
+  double acc[kDotRows + 1];
+#pragma unroll
+  for (int q = 0; q <= kDotRows; ++q) acc[q] = 0.0;
+  for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < n; i += long(gridDim.x) * kBlock) {
+    const double wi = w[i];
+#pragma unroll
+    for (int q = 0; q < kDotRows; ++q)
+      if (q < k) acc[q] += V[q * ld + i] * wi;
+    acc[kDotRows] += wi * wi;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q <= kDotRows; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[q][wid] = v;
+  }
+  __syncthreads();
+  const int rows = k + (self ? 1 : 0);
+  if (int(threadIdx.x) < rows) {
+    const int q = int(threadIdx.x) < k ? int(threadIdx.x) : kDotRows;
+    double sum = 0.0;
+    for (int w2 = 0; w2 < kBlock / 64; ++w2) sum += red[q][w2];
+    partial[long(threadIdx.x) * gridDim.x + blockIdx.x] = sum;
+  }
+}
+
+// out[row] = sum of partial[row * count .. row * count + count), one block per row
+__global__ void __launch_bounds__(kBlock) k_sum_rows(const double* __restrict__ partial, long count,
+                                                     double* __restrict__ out) {
+  const double* pr = partial + long(blockIdx.x) * count;
+  double v = 0.0;
+  for (long q = threadIdx.x; q < count; q += kBlock) v += pr[q];
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// w -= sum_{q<k} coef[q] V_q over a fixed grid (grid-stride), with block
+// partials of the updated ||w||^2 (summed by k_sum_rows)
+__global__ void __launch_bounds__(kBlock) k_maxpy_norm(long n, double* __restrict__ w, const double* __restrict__ V,
+                                                       long ld, int k, const double* __restrict__ coef,
+                                                       double* __restrict__ partial) {
+  double v = 0.0;
+  for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < n; i += long(gridDim.x) * kBlock) {
+    double acc = 0.0;
+    for (int q0 = 0; q0 < k; q0 += 8) {   // eight independent loads in flight
+      double vv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) vv[t] = q0 + t < k ? V[(q0 + t) * ld + i] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (q0 + t < k) acc += coef[q0 + t] * vv[t];
+    }
+    const double wi = w[i] - acc;
+    w[i] = wi;
+    v += wi * wi;
+  }
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// w += sgn * sum_{q<k} coef[q] V_q  (coefficients read from device memory)
+__global__ void k_maxpy(long n, double* __restrict__ w, const double* __restrict__ V, long ld, int k,
+                        const double* __restrict__ coef, double sgn) {
+  const long i = long(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int q0 = 0; q0 < k; q0 += 8) {
+    double vv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) vv[t] = q0 + t < k ? V[(q0 + t) * ld + i] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (q0 + t < k) acc += coef[q0 + t] * vv[t];
+  }
+  w[i] += sgn * acc;
 }
 
 }  // namespace stp
