@@ -36,8 +36,8 @@ def seq_euler(prob, nsteps: int | None = None, method: str = "lu", rtol: float =
     Id = sp.identity(prob.npts, format="csr")
     u = (prob.u0 if u_start is None else u_start).ravel().astype(np.float64)
     out = np.empty((N - n_start + 1,) + shape)
-    tau = prob.tau
     for m in range(n_start, N + 1):
+        tau = prob.taus[m - 1]
         An = sum(prob.tcoef[r, m - 1] * Ar[r] for r in range(prob.R))
         L = (Id + tau * An).tocsc()
         rhs = u + tau * prob.F[m - 1].ravel()
@@ -55,7 +55,7 @@ def _pcg_mg(prob, m, L, rhs, x0, rtol):
     """CG on (I + tau A_m) x = rhs preconditioned by one V-cycle of the same operator."""
     from . import mg
     hier = mg.Hierarchy(prob.kfields, prob.n, prob.dim)
-    c = (prob.tau * prob.tcoef[:, m - 1])[None, :]
+    c = (prob.taus[m - 1] * prob.tcoef[:, m - 1])[None, :]
     sigma = np.array([1.0])
     shape = (1,) + (prob.n,) * prob.dim
 

@@ -11,7 +11,8 @@
   middle A is the exact reference operator A = A(kappa_ref).
 
 Reference pair (tau, A) of eq. (2.2): tau = T/N and kappa_ref = the time mean
-of kappa(t_n, .) (the paper allows "an average").
+of kappa(t_n, .), weighted by the step lengths when they differ (the paper
+allows "an average"); A-tilde uses each step's own tau_n.
 """
 from __future__ import annotations
 
@@ -30,7 +31,7 @@ class Preconditioners:
         self.nu_A, self.nu_H = nu_A, nu_H
         self.abar = spacetime.kref_coef(prob) if kref_coef is None else np.asarray(kref_coef, dtype=np.float64)
         self.sigA = np.zeros(N)
-        self.cA = (tau * prob.tcoef).T.copy()                     # (N, R)
+        self.cA = (prob.taus[None, :] * prob.tcoef).T.copy()      # (N, R): tau_n A_n
         self.sigH = dst.mu(N)
         self.cH = np.tile(tau * self.abar, (N, 1))               # (N, R)
         self.cmid = np.tile((2.0 / N) * tau * self.abar, (N, 1))  # (2/N) tau A

@@ -42,15 +42,15 @@ def apply_KT(x: np.ndarray) -> np.ndarray:
 
 
 def apply_Ablk(prob, x: np.ndarray) -> np.ndarray:
-    """(A x)_n = tau A(kappa(t_n)) x_n, using linearity of A in kappa."""
+    """(A x)_n = tau_n A(kappa(t_n)) x_n, using linearity of A in kappa."""
     out = np.zeros_like(x)
     for r in range(prob.R):
-        out += _bcast(prob.tau * prob.tcoef[r], x) * fd.apply(prob.kfields[r], x, prob.h, prob.dim)
+        out += _bcast(prob.taus * prob.tcoef[r], x) * fd.apply(prob.kfields[r], x, prob.h, prob.dim)
     return out
 
 
 def rhs(prob) -> np.ndarray:
-    f = prob.tau * prob.F.astype(np.float64)
+    f = _bcast(prob.taus, prob.F) * prob.F.astype(np.float64)
     f[0] += prob.u0
     return f
 
@@ -70,8 +70,12 @@ def apply_saddle(prob, p, u):
 
 def kref_coef(prob) -> np.ndarray:
     """Coefficients of the reference operator A = A(kappa_ref) used in H_k:
-    kappa_ref = time mean of kappa(t_n, .), i.e. abar_r = mean_n tcoef[r, n]."""
-    return prob.tcoef.mean(axis=1)
+    kappa_ref = time mean of kappa(t_n, .), i.e. abar_r = mean_n tcoef[r, n];
+    with non-uniform steps the step-weighted mean sum_n tau_n tcoef[r, n] / T
+    (the reference tau is T/N, so tau A_ref = sum_n tau_n A_n / N)."""
+    if prob.steps is None:
+        return prob.tcoef.mean(axis=1)
+    return (prob.tcoef * prob.taus[None, :]).sum(axis=1) / prob.taus.sum()
 
 
 # ---------------------------------------------------------------------------
@@ -127,4 +131,4 @@ def fd_dense_pieces(prob):
         kap = fd.kappa_at(prob.kfields, prob.tcoef[:, i])
         A_list.append(fd.assemble(kap, prob.n, prob.dim, prob.h).toarray())
     Aref = fd.assemble(fd.kappa_at(prob.kfields, kref_coef(prob)), prob.n, prob.dim, prob.h).toarray()
-    return np.eye(m), A_list, [prob.tau] * prob.N, Aref
+    return np.eye(m), A_list, list(prob.taus), Aref

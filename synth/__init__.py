@@ -21,4 +21,5 @@ from .workloads import (  # noqa: F401
     gaussian_factors,
     source_from_factors,
     CONFIG_BUILDERS,
+    graded_steps,
 )

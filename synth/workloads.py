@@ -6,8 +6,10 @@ Conventions shared by every consumer of these arrays
   spacing ``h = 1/(n+1)``; node ``i`` (0..n+1) sits at ``x = i*h``.  Nodes 0 and
   n+1 are on the Dirichlet boundary.  Array axes are ordered (z, y, x): the
   last axis is x and is the fastest-varying one in memory.
-* Time: ``N`` uniform steps of length ``tau = T/N``; step ``n`` (1..N) ends at
-  ``t_n = n*tau``.  Index ``n-1`` of every time axis below refers to ``t_n``.
+* Time: ``N`` steps; uniform (length ``tau = T/N``, step ``n`` (1..N) ends at
+  ``t_n = n*tau``) unless ``steps`` holds the lengths tau_n (summing to T), when
+  ``t_n = tau_1 + ... + tau_n``.  Index ``n-1`` of every time axis below refers
+  to ``t_n``.  ``tau`` is always T/N (the mean step).
 * Coefficient: ``kappa(t_n, x) = sum_r tcoef[r, n-1] * kfields[r](x)``, the
   fields sampled on all ``(n+2)^d`` nodes including the boundary.
 * Source ``F[n-1]`` is the source at ``t_n`` on the interior nodes; ``u0`` is
@@ -33,10 +35,15 @@ class Problem:
     u0: np.ndarray       # (n,)*dim
     name: str = ""
     seed: int = 0
+    steps: np.ndarray | None = None   # (N,) step lengths; None: uniform
 
     @property
     def tau(self) -> float:
         return self.T / self.N
+
+    @property
+    def taus(self) -> np.ndarray:
+        return np.full(self.N, self.T / self.N) if self.steps is None else self.steps
 
     @property
     def h(self) -> float:
@@ -63,8 +70,20 @@ def _interior(n: int) -> np.ndarray:
     return np.arange(1, n + 1, dtype=np.float64) / (n + 1)
 
 
-def _times(N: int, T: float) -> np.ndarray:
+def _times(N: int, T: float, steps=None) -> np.ndarray:
+    if steps is not None:
+        return np.cumsum(steps)
     return T * np.arange(1, N + 1, dtype=np.float64) / N
+
+
+def graded_steps(N: int, T: float = 1.0, ratio: float = 8.0, jitter: float = 0.0, seed: int = 0) -> np.ndarray:
+    """N step lengths growing geometrically from the first to the last by
+    ``ratio`` (small steps first, as for rough initial data), each optionally
+    scaled by a factor uniform in [1 - jitter, 1 + jitter], normalised to sum T."""
+    q = ratio ** (np.arange(N, dtype=np.float64) / max(N - 1, 1))
+    if jitter > 0:
+        q = q * np.random.default_rng(seed).uniform(1 - jitter, 1 + jitter, N)
+    return T * q / q.sum()
 
 
 def _outer(vecs):
@@ -171,16 +190,17 @@ def manufactured_u(n: int, dim: int, N: int, T: float) -> np.ndarray:
 # The five workloads
 # ---------------------------------------------------------------------------
 
-def heat1d_random(n: int = 63, N: int = 64, T: float = 1.0, seed: int = 1001) -> Problem:
+def heat1d_random(n: int = 63, N: int = 64, T: float = 1.0, seed: int = 1001, steps=None) -> Problem:
     """1-D heat: kappa = 1 + 0.5 sin(2 pi t); F ~ N(0,1) per node and step;
-    u0 = sin(pi x) + 0.1 N(0,1)."""
+    u0 = sin(pi x) + 0.1 N(0,1).  ``steps``: optional step lengths (sum T)."""
     rng = np.random.default_rng(seed)
-    t = _times(N, T)
+    t = _times(N, T, steps)
     kf = np.ones((1, n + 2))
     tc = (1.0 + 0.5 * np.sin(2 * np.pi * t))[None, :]
     F = rng.standard_normal((N, n))
     u0 = np.sin(np.pi * _interior(n)) + 0.1 * rng.standard_normal(n)
-    return Problem(1, n, N, T, kf, tc, F, u0, name="heat1d_random", seed=seed)
+    return Problem(1, n, N, T, kf, tc, F, u0, name="heat1d_random", seed=seed,
+                   steps=None if steps is None else np.asarray(steps, dtype=np.float64))
 
 
 def heat2d_parts(n: int = 255, N: int = 256, T: float = 1.0, seed: int = 1002,
@@ -263,17 +283,18 @@ def batch2d_parts(spec):
 
 
 def small_problem(dim: int, n: int, N: int, seed: int = 7, T: float = 1.0, R: int = 2,
-                  amp: float = 0.5) -> Problem:
+                  amp: float = 0.5, steps=None) -> Problem:
     """Small generic problem for unit and parity tests.
 
     kappa(t,x) = 1 + amp * sin(2 pi t + phi) * g(x) with g a rough random nodal
     field in [-1, 1] (R = 2 separable terms; R = 1 drops the second term and
     uses kappa = 1 + amp sin(2 pi t + phi); R = 3, 4 add R - 1 rough fields of
     weight 1/(R-1) with time frequencies 1 .. R-1).  kappa stays in [1-amp, 1+amp],
-    as in the paper-style workloads.  F and u0 are standard normal.
+    as in the paper-style workloads.  F and u0 are standard normal.  ``steps``:
+    optional step lengths (sum T).
     """
     rng = np.random.default_rng(seed)
-    t = _times(N, T)
+    t = _times(N, T, steps)
     shape = (n + 2,) * dim
     phi = rng.uniform(0, 2 * np.pi)
     if R == 1:
@@ -291,7 +312,8 @@ def small_problem(dim: int, n: int, N: int, seed: int = 7, T: float = 1.0, R: in
         tc = np.stack([np.ones(N)] + [amp * np.sin(2 * np.pi * (r + 1) * t + phis[r]) for r in range(R - 1)])
     F = rng.standard_normal((N,) + (n,) * dim)
     u0 = rng.standard_normal((n,) * dim)
-    return Problem(dim, n, N, T, kf, tc, F, u0, name=f"small{dim}d", seed=seed)
+    return Problem(dim, n, N, T, kf, tc, F, u0, name=f"small{dim}d", seed=seed,
+                   steps=None if steps is None else np.asarray(steps, dtype=np.float64))
 
 
 CONFIG_BUILDERS = {
