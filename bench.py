@@ -35,7 +35,7 @@ FP64_PEAK_TFLOPS = 78.6
 # kernel sources hash to the recorded value (see the named profile).
 MEASURED_TRAFFIC = {
     ("heat2d_255_N256", "f64", "k_mg_down", 0): dict(
-        bytes=174851546, sources_sha256="96ade679484ca20cce29e8313adf31735aef7885ad7c7124586811071b9b5c24",
+        bytes=183544905, sources_sha256="6707fba53ea905aec39b7f4b74797486c1d06badf743fcf1521d7b969837b386",
         profile="profiles/heat2d_255_N256_f64_mg_down_L0_traffic.md"),
 }
 
@@ -333,6 +333,65 @@ def batch_run(args):
     return out
 
 
+def heat3d_run(args):
+    """3-D heat, 127^3 interior nodes, N_t = 128, lognormal kappa (contrast 1e2)
+    times (1 + 0.3 t), Gaussian source: time to ||f - B u|| <= 1e-10 ||f|| from a
+    zero guess, Uzawa and GMRES(restart), with float64, float32 and
+    bfloat16-storage preconditioners (outer residuals and updates in float64).
+    Each solve runs twice; the second is reported."""
+    import torch
+
+    import paper_1802_08126_amd as stp
+    import synth
+
+    prob = synth.CONFIG_BUILDERS["heat3d_127_N128_lognormal"]()
+    dofs = prob.N * prob.npts
+    dev = "cuda:0"
+    kf = torch.as_tensor(prob.kfields, dtype=torch.float64, device=dev)
+    F = torch.as_tensor(prob.F, dtype=torch.float64, device=dev)
+    u0 = torch.as_tensor(prob.u0, dtype=torch.float64, device=dev)
+    shape = (prob.N,) + (prob.n,) * prob.dim
+    u = torch.zeros(shape, dtype=torch.float64, device=dev)
+    p = torch.zeros_like(u)
+    out = dict(workload="heat3d_127_N128_lognormal", dofs=dofs, tol=args.tol3d, restart=args.gmres_restart)
+    for prec in ("f64", "f32", "bf16"):
+        s = stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0, precision=prec,
+                                omega=0.0, tol=args.tol3d, max_iter=3000, check_every=args.check_every)
+        s.autotune(reps=3)
+        r = dict(omega=s.omega_info()["omega"])
+        for _ in range(2):
+            u.zero_()
+            p.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, info = s.solve(u, p)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        r["uzawa"] = dict(iters=info["iters"], sec=t1 - t0, rel_res=info["rel_res"], status=info["status"],
+                          dof_it_per_s=dofs * info["iters"] / (t1 - t0))
+        progress(f"3-D {prec}: uzawa to tol", f"{info['iters']} its {t1 - t0:.2f}s")
+        nb = stp.stp_gmres_workspace_bytes(s.ctx, args.gmres_restart)
+        ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            u.zero_()
+            p.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, gi = s.gmres(u, p, restart=args.gmres_restart, workspace=ws)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        r["gmres"] = dict(steps=gi["iters"], sec=t1 - t0, rel_res=gi["rel_res"], status=gi["status"])
+        progress(f"3-D {prec}: gmres to tol", f"{gi['iters']} steps {t1 - t0:.2f}s")
+        del ws
+        s.close()
+        out[prec] = r
+    for prec in ("f32", "bf16"):
+        out[prec]["uzawa_speedup_vs_f64"] = out["f64"]["uzawa"]["sec"] / out[prec]["uzawa"]["sec"]
+        out[prec]["best_speedup_vs_f64_uzawa"] = out["f64"]["uzawa"]["sec"] / min(out[prec]["uzawa"]["sec"],
+                                                                                   out[prec]["gmres"]["sec"])
+    return out
+
+
 def roofline(rep, dims, ts, steps, workload="heat2d_255_N256", dtype="f64"):
     """Dominant kernel (largest summed device time) and its achieved HBM rate."""
     if not rep:
@@ -410,7 +469,7 @@ def summarize_profile(d, steps):
     their predecessor), and, when the counter passes are there, their HBM bytes
     from FETCH_SIZE (p1/) and WRITE_SIZE (p2/) scaled by the copy calibration
     passes (c1/, c2/).  Every run was made with --steps `steps`, --only-f64,
-    --skip-tol and --no-batch, so those solves are the last launches."""
+    --skip-tol, --no-batch and --no-3d, so those solves are the last launches."""
     import csv
 
     def rows(sub, f):
@@ -476,6 +535,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch workload")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--gmres-restart", type=int, default=10)
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D lognormal time-to-tolerance runs")
+    ap.add_argument("--tol3d", type=float, default=1e-10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of one slab-vector (counter calibration)")
     ap.add_argument("--summarize-profile", metavar="DIR",
@@ -532,6 +593,8 @@ def main():
                 out["mixed_f32_precond"]["time_to_tol_speedup"] = r64["tol"]["sec"] / r32["tol"]["sec"]
     if not args.no_batch:
         out["batch64"] = batch_run(args)
+    if not args.no_3d:
+        out["heat3d_lognormal"] = heat3d_run(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

@@ -98,6 +98,12 @@ typedef struct {
                               for the reference operator A of eq. (2.2); NULL = time mean */
   int check_every;      /* iterations enqueued between host checks of the stop flag  */
   int use_graph;        /* 1: replay each iteration as a captured HIP graph          */
+  const double* tau_steps; /* host, N step lengths tau_n of eq. (2.1) (copied by stp_create),
+                              or NULL for N steps of length tau.  When given, tau is the
+                              reference step of eq. (2.2) used by H-tilde (<= 0: the mean
+                              of tau_n), A = diag(tau_n A_n), f_n = tau_n F_n (+ u0), and
+                              without kref_coef kappa_ref is the step-weighted time mean
+                              sum_n tau_n kappa(t_n) / sum_n tau_n.  Single problems only. */
 } stp_options;
 
 typedef struct {
@@ -109,7 +115,7 @@ typedef struct {
 } stp_stats;
 
 /* Fill *opt with defaults: F64, AUTO, nu = 1, omega 0.8, tol 1e-8, max_iter 500,
-   time-mean kappa_ref, check_every 8, graphs on. */
+   time-mean kappa_ref, check_every 8, graphs on, uniform steps. */
 void stp_default_options(stp_options* opt);
 
 /* Device bytes stp_create needs as workspace for this problem and options. */
@@ -120,9 +126,10 @@ size_t stp_workspace_bytes(const stp_grid* g, int N, int rank, const stp_options
  * u0 (device, n^d).  F, u0 and kappa->fields are borrowed until stp_destroy.
  * workspace: device buffer of >= stp_workspace_bytes (256-byte aligned), or NULL
  * to let the library allocate (and free) its own.  hip_stream: hipStream_t or NULL.
- * Errors: EINVAL (dim not 1..3, n < 1, N < 1, tau <= 0 or not finite, rank out of
- * range, NULL pointers, some kappa <= 0), EUNSUPPORTED (MG with n != 2^L - 1,
- * EXACT with dim > 1, nu != 1), ENOMEM, EDEVICE. */
+ * Errors: EINVAL (dim not 1..3, n < 1, N < 1, tau <= 0 or not finite without
+ * opt->tau_steps, a step length <= 0 or not finite, rank out of range, NULL
+ * pointers, some kappa <= 0), EUNSUPPORTED (MG with n != 2^L - 1, EXACT with
+ * dim > 1, nu != 1), ENOMEM, EDEVICE. */
 stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau,
                       const stp_kappa* kappa, const double* F, const double* u0,
                       const stp_options* opt, void* workspace, size_t ws_bytes,

@@ -39,7 +39,8 @@ class stp_kappa(C.Structure):
 class stp_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("spatial", C.c_int), ("nu_A", C.c_int), ("nu_H", C.c_int),
                 ("omega", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int),
-                ("kref_coef", C.POINTER(C.c_double)), ("check_every", C.c_int), ("use_graph", C.c_int)]
+                ("kref_coef", C.POINTER(C.c_double)), ("check_every", C.c_int), ("use_graph", C.c_int),
+                ("tau_steps", C.POINTER(C.c_double))]
 
 
 class stp_stats(C.Structure):
@@ -143,7 +144,7 @@ def _dev_f64(t, shape, name):
 
 
 def make_options(precision="f64", spatial="auto", omega=0.8, tol=1e-8, max_iter=500, kref_coef=None,
-                 check_every=8, use_graph=True, nu_A=1, nu_H=1):
+                 check_every=8, use_graph=True, nu_A=1, nu_H=1, tau_steps=None):
     o = stp_options()
     load().stp_default_options(C.byref(o))
     o.precision = STP_PREC[precision]
@@ -154,10 +155,13 @@ def make_options(precision="f64", spatial="auto", omega=0.8, tol=1e-8, max_iter=
     o.max_iter = max_iter
     o.check_every = check_every
     o.use_graph = 1 if use_graph else 0
-    keep = None
+    keep = []
     if kref_coef is not None:
-        keep = (C.c_double * len(kref_coef))(*[float(v) for v in kref_coef])
-        o.kref_coef = C.cast(keep, C.POINTER(C.c_double))
+        keep.append((C.c_double * len(kref_coef))(*[float(v) for v in kref_coef]))
+        o.kref_coef = C.cast(keep[-1], C.POINTER(C.c_double))
+    if tau_steps is not None:
+        keep.append((C.c_double * len(tau_steps))(*[float(v) for v in tau_steps]))
+        o.tau_steps = C.cast(keep[-1], C.POINTER(C.c_double))
     return o, keep
 
 
@@ -516,9 +520,12 @@ def problem_dict(prob, device="cuda"):
 
 
 def from_problem(prob, device="cuda", **opts):
-    """Build a solver from a ``synth.Problem`` (copies its arrays to the device)."""
+    """Build a solver from a ``synth.Problem`` (copies its arrays to the device;
+    its step lengths, when non-uniform, become the tau_steps option)."""
     import torch
     kf = torch.as_tensor(np.ascontiguousarray(prob.kfields), dtype=torch.float64, device=device)
     F = torch.as_tensor(np.ascontiguousarray(prob.F), dtype=torch.float64, device=device)
     u0 = torch.as_tensor(np.ascontiguousarray(prob.u0), dtype=torch.float64, device=device)
+    if getattr(prob, "steps", None) is not None and "tau_steps" not in opts:
+        opts["tau_steps"] = list(prob.steps)
     return SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0, **opts)

@@ -196,7 +196,8 @@ struct Schedule {
 
 struct Problem {
   int dim = 0, n = 0, N = 0, R = 0;
-  double tau = 0;
+  double tau = 0;               // reference step of eq. (2.2) (the step when uniform)
+  std::vector<double> taus;     // N step lengths tau_n
   const double* F = nullptr;
   const double* u0 = nullptr;
   const double* fields = nullptr;
@@ -216,7 +217,8 @@ struct Problem {
   DevState* state = nullptr;
   double* partial = nullptr;
   double* kap64 = nullptr;      // finest-level scaled fields, float64
-  double* cA64 = nullptr;       // N x kMaxRank: tau * tcoef
+  double* cA64 = nullptr;       // N x kMaxRank: tau_n * tcoef
+  double* taus64 = nullptr;     // N step lengths
   void* cA = nullptr;           // TC, N x kMaxRank
   void* sigH = nullptr;         // TC, N: mu_k
   void* cH = nullptr;           // TC, N x kMaxRank: tau * abar
@@ -422,6 +424,7 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp) {
   q.partial = (double*)bp.take(size_t(std::max(q.resid_tiles * q.N, q.nfnorm)) * 8);
   q.kap64 = (double*)bp.take(size_t(q.R) * q.g0.nnodes * 8);
   q.cA64 = (double*)bp.take(size_t(N) * kMaxRank * 8);
+  q.taus64 = (double*)bp.take(size_t(N) * 8);
   q.cA = bp.take(size_t(N) * kMaxRank * tcb);
   q.cH = bp.take(size_t(N) * kMaxRank * tcb);
   q.sigH = bp.take(size_t(N) * tcb);
@@ -671,7 +674,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
       if (w == 1) q.npart = nb;
       j.g = q.g0;
       j.t = TimeOp{q.kap64, q.cA64, q.R, q.N};
-      j.tau = q.tau;
+      j.taus = q.taus64;
       j.u = u[i];
       j.p = p[i];
       j.F = q.F;
@@ -1212,13 +1215,14 @@ struct Solver : SolverBase {
     std::vector<double> cA64(size_t(N) * kMaxRank, 0.0);
     for (int s = 0; s < N; ++s)
       for (int r = 0; r < R; ++r) {
-        cA64[size_t(s) * kMaxRank + r] = q.tau * q.tcoef[size_t(r) * N + s];
-        cA[size_t(s) * kMaxRank + r] = TC(q.tau * q.tcoef[size_t(r) * N + s]);
+        cA64[size_t(s) * kMaxRank + r] = q.taus[s] * q.tcoef[size_t(r) * N + s];
+        cA[size_t(s) * kMaxRank + r] = TC(q.taus[s] * q.tcoef[size_t(r) * N + s]);
         cH[size_t(s) * kMaxRank + r] = TC(q.tau * q.abar[r]);
       }
     for (int k = 0; k < N; ++k) sig[k] = TC(2.0 * std::sin((2.0 * k + 1.0) * M_PI / (4.0 * N)));
     for (int r = 0; r < R; ++r) mid[r] = TC((2.0 / N) * q.tau * q.abar[r]);
     HIP_TRY(hipMemcpyAsync(q.cA64, cA64.data(), cA64.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(q.taus64, q.taus.data(), size_t(N) * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(q.cA, cA.data(), cA.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(q.cH, cH.data(), cH.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(q.sigH, sig.data(), sig.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
@@ -1627,6 +1631,7 @@ void stp_default_options(stp_options* o) {
   o->kref_coef = nullptr;
   o->check_every = 8;
   o->use_graph = 1;
+  o->tau_steps = nullptr;
 }
 
 const char* stp_status_string(stp_status s) {
@@ -1679,21 +1684,43 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
   stp_status s = validate_opts(&opt);
   if (s != STP_OK) return s;
   if (opt.kref_coef && P > 1) return fail(STP_EINVAL, "kref_coef must be NULL for a batch of more than one problem");
+  if (opt.tau_steps && P > 1) return fail(STP_EINVAL, "tau_steps must be NULL for a batch of more than one problem");
+  // non-uniform steps: tau is the reference step of eq. (2.2), <= 0 for their mean
+  std::vector<double> tref(tau, tau + P);
+  if (opt.tau_steps) {
+    double sum = 0;
+    for (int n = 0; n < N[0]; ++n) {
+      const double t = opt.tau_steps[n];
+      if (!(t > 0) || !std::isfinite(t)) return fail(STP_EINVAL, "tau_steps[%d] must be finite and > 0", n);
+      sum += t;
+    }
+    if (!(tref[0] > 0)) tref[0] = sum / N[0];
+  }
   for (int i = 0; i < P; ++i)
-    if ((s = validate_one(&grids[i], N[i], tau[i], &kappa[i], F[i], u0[i], &opt)) != STP_OK) return s;
+    if ((s = validate_one(&grids[i], N[i], tref[i], &kappa[i], F[i], u0[i], &opt)) != STP_OK) return s;
   std::unique_ptr<stp_ctx> c(new stp_ctx());
   c->opt = opt;
   c->prec = opt.precision;
   c->stream = (hipStream_t)hip_stream;
-  if ((s = describe(c.get(), P, grids, N, tau, kappa, F, u0)) != STP_OK) return s;
+  if ((s = describe(c.get(), P, grids, N, tref.data(), kappa, F, u0)) != STP_OK) return s;
   for (int i = 0; i < P; ++i) {
     Problem& q = c->pr[i];
     q.omega_auto = !(opt.omega > 0);
     q.omega = q.omega_auto ? 0.8 : opt.omega;   // replaced by the estimate below when automatic
     q.tcoef.assign(kappa[i].tcoef, kappa[i].tcoef + size_t(q.R) * q.N);
+    if (opt.tau_steps) q.taus.assign(opt.tau_steps, opt.tau_steps + q.N);
+    else q.taus.assign(q.N, q.tau);
     q.abar.assign(q.R, 0.0);
     if (opt.kref_coef) {
       for (int r = 0; r < q.R; ++r) q.abar[r] = opt.kref_coef[r];
+    } else if (opt.tau_steps) {   // step-weighted time mean: tau A_ref = (1/N) sum_n tau_n A_n
+      double tsum = 0;
+      for (int n = 0; n < q.N; ++n) tsum += q.taus[n];
+      for (int r = 0; r < q.R; ++r) {
+        double sum = 0;
+        for (int n = 0; n < q.N; ++n) sum += q.taus[n] * q.tcoef[size_t(r) * q.N + n];
+        q.abar[r] = sum / tsum;
+      }
     } else {
       for (int r = 0; r < q.R; ++r) {
         double sum = 0;
@@ -1765,7 +1792,7 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
     if (!(mn > 0)) return fail(STP_EINVAL, "kappa must be > 0 at every node and step (min %.3e)", mn);
     // ||f||
     const dim3 gr = grid_pts(q.g0.npts, q.N);
-    KLAUNCH(k_fnorm, gr, dim3(kBlock), 0, c->stream, q.g0, q.N, q.tau, q.F, q.u0, q.partial);
+    KLAUNCH(k_fnorm, gr, dim3(kBlock), 0, c->stream, q.g0, q.N, (const double*)q.taus64, q.F, q.u0, q.partial);
     LAUNCH_CHECK();
     KLAUNCH(k_sum_to, dim3(1), dim3(kBlock), 0, c->stream, (const double*)q.partial, q.nfnorm, &q.state->fnorm);
     LAUNCH_CHECK();
@@ -1995,9 +2022,9 @@ stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* 
   // ||f - B uu||_2 (synchronises)
   auto fmBu = [&](const double* uu, double& out) -> stp_status {
     switch (c->dim) {
-      case 1: KLAUNCH(k_fmBu_partial<1>, gp, dim3(kBlock), 0, c->stream, q.g0, t, q.tau, q.F, q.u0, uu, part); break;
-      case 2: KLAUNCH(k_fmBu_partial<2>, gp, dim3(kBlock), 0, c->stream, q.g0, t, q.tau, q.F, q.u0, uu, part); break;
-      default: KLAUNCH(k_fmBu_partial<3>, gp, dim3(kBlock), 0, c->stream, q.g0, t, q.tau, q.F, q.u0, uu, part);
+      case 1: KLAUNCH(k_fmBu_partial<1>, gp, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, uu, part); break;
+      case 2: KLAUNCH(k_fmBu_partial<2>, gp, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, uu, part); break;
+      default: KLAUNCH(k_fmBu_partial<3>, gp, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, uu, part);
     }
     LAUNCH_CHECK();
     KLAUNCH(k_sum_rows, dim3(1), dim3(kBlock), 0, c->stream, (const double*)part, fparts, slots);
@@ -2091,9 +2118,9 @@ stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* 
     if (iters >= max_iter) break;
     const int m = std::min(restart, max_iter - iters);
     switch (c->dim) {   // v_0 = g - S x
-      case 1: KLAUNCH(k_saddle_resid<1>, gp, dim3(kBlock), 0, c->stream, q.g0, t, q.tau, q.F, q.u0, p, u, V, V + nv); break;
-      case 2: KLAUNCH(k_saddle_resid<2>, gp, dim3(kBlock), 0, c->stream, q.g0, t, q.tau, q.F, q.u0, p, u, V, V + nv); break;
-      default: KLAUNCH(k_saddle_resid<3>, gp, dim3(kBlock), 0, c->stream, q.g0, t, q.tau, q.F, q.u0, p, u, V, V + nv);
+      case 1: KLAUNCH(k_saddle_resid<1>, gp, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, V, V + nv); break;
+      case 2: KLAUNCH(k_saddle_resid<2>, gp, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, V, V + nv); break;
+      default: KLAUNCH(k_saddle_resid<3>, gp, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, V, V + nv);
     }
     LAUNCH_CHECK();
     if ((s = mdot(0, V, true, slots)) != STP_OK) return s;

@@ -278,13 +278,14 @@ __global__ void __launch_bounds__(kBlock) k_apply_saddle(Geom g, TimeOp t, const
 }
 
 // ||f||^2 partials (setup)
-__global__ void __launch_bounds__(kBlock) k_fnorm(Geom g, int N, double tau, const double* __restrict__ F,
-                                                  const double* __restrict__ u0, double* __restrict__ partial) {
+__global__ void __launch_bounds__(kBlock) k_fnorm(Geom g, int N, const double* __restrict__ taus,
+                                                  const double* __restrict__ F, const double* __restrict__ u0,
+                                                  double* __restrict__ partial) {
   const int s = slab_index();
   const long i = long(blockIdx.x) * kBlock + threadIdx.x;
   double v = 0.0;
   if (s < N && i < g.npts) {
-    double f = tau * F[long(s) * g.npts + i];
+    double f = taus[s] * F[long(s) * g.npts + i];
     if (s == 0) f += u0[i];
     v = f * f;
   }
@@ -1156,9 +1157,10 @@ __global__ void k_kappa_min(long nnodes, int R, int S, const double* __restrict_
 // ---------------------------------------------------------------------------
 // Krylov acceleration (GMRES around the Uzawa sweep), float64 vectors
 // ---------------------------------------------------------------------------
-// r = g - saddle [p; u] with g = [-f; -f], f_s = tau F_s (+ u0 on the first slab)
+// r = g - saddle [p; u] with g = [-f; -f], f_s = tau_s F_s (+ u0 on the first slab)
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_saddle_resid(Geom g, TimeOp t, double tau, const double* __restrict__ F,
+__global__ void __launch_bounds__(kBlock) k_saddle_resid(Geom g, TimeOp t, const double* __restrict__ taus,
+                                                         const double* __restrict__ F,
                                                          const double* __restrict__ u0, const double* __restrict__ p,
                                                          const double* __restrict__ u, double* __restrict__ rp,
                                                          double* __restrict__ ru) {
@@ -1178,7 +1180,7 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(Geom g, TimeOp t, doubl
   const double um = s > 0 ? u[o - g.npts + i] : 0.0;
   const double up = s + 1 < t.N ? u[o + g.npts + i] : 0.0;
   const double pp = s + 1 < t.N ? p[o + g.npts + i] : 0.0;
-  double f = tau * F[o + i];
+  double f = taus[s] * F[o + i];
   if (s == 0) f += u0[i];
   rp[o + i] = -f - (Ap - (uc - um));
   ru[o + i] = -f + (pc - pp) + (2.0 * uc - um - up) + Au;
@@ -1186,7 +1188,8 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(Geom g, TimeOp t, doubl
 
 // block partials of ||f - B u||^2 over a (points, slabs) grid
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_fmBu_partial(Geom g, TimeOp t, double tau, const double* __restrict__ F,
+__global__ void __launch_bounds__(kBlock) k_fmBu_partial(Geom g, TimeOp t, const double* __restrict__ taus,
+                                                         const double* __restrict__ F,
                                                          const double* __restrict__ u0, const double* __restrict__ u,
                                                          double* __restrict__ partial) {
   const int s = slab_index();
@@ -1201,7 +1204,7 @@ __global__ void __launch_bounds__(kBlock) k_fmBu_partial(Geom g, TimeOp t, doubl
     stencil<D, double>(u + o, i, px, py, pz, g, t.kap, op, t.R, dg, off);
     const double uc = u[o + i];
     const double um = s > 0 ? u[o - g.npts + i] : 0.0;
-    double f = tau * F[o + i];
+    double f = taus[s] * F[o + i];
     if (s == 0) f += u0[i];
     const double e = f - ((uc - um) + (dg * uc - off));
     v = e * e;

@@ -341,7 +341,7 @@ struct ResidJob {
   int sb;
   Geom g;
   TimeOp t;
-  double tau;
+  const double* taus;   // N step lengths tau_n
   const double* u;
   const double* p;
   const double* F;
@@ -354,6 +354,7 @@ struct ResidJob {
 __device__ __forceinline__ ResidJob to_global(ResidJob j) {
   j.t.kap = gmem(j.t.kap);
   j.t.cA = gmem(j.t.cA);
+  j.taus = gmem(j.taus);
   j.u = gmem(j.u);
   j.p = gmem(j.p);
   j.F = gmem(j.F);
@@ -905,10 +906,10 @@ __global__ void __launch_bounds__(kBlock) k_apply_tile(const TileJob* __restrict
 
 // ---------------------------------------------------------------------------
 // time-global residuals (float64), tile versions marching forward in time
-//   WHICH = 0 (a1):  r = (u_s - u_{s-1}) - tau A_s p_s - f_s
-//   WHICH = 1 (a3):  e = f_s - (u_s - u_{s-1}) - tau A_s u_s,
+//   WHICH = 0 (a1):  r = (u_s - u_{s-1}) - tau_s A_s p_s - f_s
+//   WHICH = 1 (a3):  e = f_s - (u_s - u_{s-1}) - tau_s A_s u_s,
 //                    r = e - ((u+p)_s - (u+p)_{s+1}),  block partial of e^2
-// f_s = tau F_s (+ u0 on the first slab).  The tile values of u_s are kept
+// f_s = tau_s F_s (+ u0 on the first slab).  The tile values of u_s are kept
 // in registers and serve as u_{s-1} of the next slab.
 // ---------------------------------------------------------------------------
 template <int D, typename TS, int WHICH, int RM, bool FIX>
@@ -925,7 +926,6 @@ __device__ __forceinline__ void resid_tile_body(const ResidJob& J, int tile, int
   const TimeOp t = J.t;
   s1 = min(s1, t.N);
   const Geom g = J.g;
-  const double tau = J.tau;
   double e2 = 0.0;
   if (s0 < s1) {
     const int n = g.n;
@@ -975,6 +975,7 @@ __device__ __forceinline__ void resid_tile_body(const ResidJob& J, int tile, int
     if (WHICH == 1) load_pts(pc, p + long(s0) * g.npts);
     for (int s = s0; s < s1; ++s) {
       const long o = long(s) * g.npts;
+      const double tau = J.taus[s];
       const double gamma = FIX ? t.cA[s * kMaxRank] : 1.0;
       if constexpr (!FIX) write_kappa<KB, double, RM>(sk, kr, load_op<double>(nullptr, t.cA, s, t.R));
       write_box<KB, double>(sx, xn);
