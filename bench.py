@@ -35,7 +35,7 @@ FP64_PEAK_TFLOPS = 78.6
 # kernel sources hash to the recorded value (see the named profile).
 MEASURED_TRAFFIC = {
     ("heat2d_255_N256", "f64", "k_mg_down", 0): dict(
-        bytes=183544905, sources_sha256="6707fba53ea905aec39b7f4b74797486c1d06badf743fcf1521d7b969837b386",
+        bytes=195069799, sources_sha256="4565464c0be387e8be16a10c5f78e580581be8d228cf027f57e6fbd8bac01cd6",
         profile="profiles/heat2d_255_N256_f64_mg_down_L0_traffic.md"),
 }
 
@@ -392,6 +392,67 @@ def heat3d_run(args):
     return out
 
 
+def paper83_run(args):
+    """The 3-D problem of the paper's time-parallel experiments (Section 8.3,
+    Tables 3 and 4) in finite-difference form on one GPU: 15^3 interior nodes
+    (the paper's 16^3-cell mesh), T = 0.1, kappa = 1, F = 0, u0 = sin sin sin
+    (exact solution exp(-3 pi^2 t) sin sin sin); time to ||f - B u|| <= 1e-8 ||f||
+    from zero with Uzawa and GMRES(restart) for growing N (the weak-scaling
+    direction of Table 3), float64, and float32 preconditioners at the largest
+    N.  The paper's numbers (Q1 elements, hypre AMG, GMRES-accelerated Uzawa,
+    Vulcan BlueGene/Q) are context only."""
+    import torch
+
+    import paper_1802_08126_amd as stp
+    import synth
+
+    out = dict(workload="heat3d_sine_15", tol=1e-8, restart=args.gmres_restart,
+               paper_context=dict(source="Tables 3-4", machine="Vulcan BlueGene/Q", procs=4096, N=65536,
+                                  iters=22, sec_per_iter=1.87, total_sec=41.09,
+                                  method="GMRES-accelerated inexact Uzawa, Q1 FEM, hypre AMG, FFTW3"),
+               runs=[])
+    for N, prec in ((1024, "f64"), (16384, "f64"), (65536, "f64"), (65536, "f32")):
+        prob = synth.heat3d_sine(N=N)
+        dev = "cuda:0"
+        kf = torch.as_tensor(prob.kfields, dtype=torch.float64, device=dev)
+        F = torch.zeros((N,) + (prob.n,) * 3, dtype=torch.float64, device=dev)
+        u0 = torch.as_tensor(prob.u0, dtype=torch.float64, device=dev)
+        s = stp.SpaceTimeSolver(3, prob.n, N, prob.tau, kf, prob.tcoef, F, u0, precision=prec, omega=0.0,
+                                tol=1e-8, max_iter=2000, check_every=args.check_every)
+        s.autotune(reps=3)
+        r = dict(N=N, precision=prec, dofs=N * prob.npts, omega=s.omega_info()["omega"])
+        u = torch.zeros((N,) + (prob.n,) * 3, dtype=torch.float64, device=dev)
+        p = torch.zeros_like(u)
+        for _ in range(2):
+            u.zero_()
+            p.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, info = s.solve(u, p)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        r["uzawa"] = dict(iters=info["iters"], sec=t1 - t0, sec_per_iter=(t1 - t0) / max(info["iters"], 1),
+                          rel_res=info["rel_res"], status=info["status"])
+        nb = stp.stp_gmres_workspace_bytes(s.ctx, args.gmres_restart)
+        ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            u.zero_()
+            p.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, gi = s.gmres(u, p, restart=args.gmres_restart, workspace=ws)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        r["gmres"] = dict(steps=gi["iters"], sec=t1 - t0, sec_per_step=(t1 - t0) / max(gi["iters"], 1),
+                          rel_res=gi["rel_res"], status=gi["status"])
+        progress(f"sec8.3 N={N} {prec}", f"uzawa {r['uzawa']['iters']} its {r['uzawa']['sec']:.2f}s, "
+                 f"gmres {gi['iters']} steps {t1 - t0:.2f}s")
+        del ws, u, p, F
+        s.close()
+        out["runs"].append(r)
+    return out
+
+
 def roofline(rep, dims, ts, steps, workload="heat2d_255_N256", dtype="f64"):
     """Dominant kernel (largest summed device time) and its achieved HBM rate."""
     if not rep:
@@ -595,6 +656,7 @@ def main():
         out["batch64"] = batch_run(args)
     if not args.no_3d:
         out["heat3d_lognormal"] = heat3d_run(args)
+        out["paper_sec8_3"] = paper83_run(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

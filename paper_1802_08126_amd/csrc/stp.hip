@@ -104,11 +104,26 @@ dim3 grid_pts(long npts, int S) {
   return dim3(unsigned(bx), unsigned(gy), unsigned(gz));
 }
 
-enum { TP_FFT2 = 0, TP_STOCKHAM = 1, TP_DENSE = 2, TP_BLUESTEIN = 3 };
+enum { TP_FFT2 = 0, TP_STOCKHAM = 1, TP_DENSE = 2, TP_BLUESTEIN = 3, TP_FOUR = 4 };
 
 constexpr int kBlueKey = 1 << 20;        // site key of a Bluestein group: kBlueKey + M
 constexpr int kBlueMaxN = 2048;          // Bluestein for step counts up to this (M <= 4096)
 constexpr size_t kMaxLds = 160 * 1024;   // LDS of one compute unit
+constexpr int kFourMaxN = 1 << 20;       // four-step FFT for powers of two above 4096 up to this
+
+// four-step FFT: LDS of a pass (FFT length N1 >= N2, C columns) and default columns
+size_t four_lds(int N, int C, size_t tcb) {
+  const int N1 = four_n1(N);
+  return (size_t(2) * N1 * C + size_t(2) * N1) * tcb;
+}
+int four_cols(int N) { return std::max(1, std::min(16, 4096 / four_n1(N))); }
+size_t stockham_lds(int N, int C, size_t tcb);
+// powers of two the in-LDS Stockham FFT cannot take (N > 4096, or one column
+// too large for the LDS) run as four-step FFTs
+bool four_step_n(int N, size_t tcb) {
+  const bool pow2 = N >= 1 && (N & (N - 1)) == 0;
+  return pow2 && N >= 512 && N <= kFourMaxN && (N > 4096 || stockham_lds(N, 1, tcb) > kMaxLds);
+}
 
 // Bluestein FFT length: the smallest power of two >= 2N - 1
 int bluestein_M(int N) {
@@ -142,6 +157,12 @@ void transform_path(int N, size_t tcb, int& path, int& C, size_t& lds) {
       return;
     }
   }
+  if (four_step_n(N, tcb)) {
+    C = four_cols(N);
+    lds = four_lds(N, C, tcb);
+    path = TP_FOUR;
+    return;
+  }
   if (!pow2 && N > 16 && N <= kBlueMaxN) {
     const int M = bluestein_M(N);
     C = bluestein_cols(M, tcb);
@@ -157,7 +178,7 @@ void transform_path(int N, size_t tcb, int& path, int& C, size_t& lds) {
 // site key of a step count: N (powers of two up to 4096), the Bluestein group
 // kBlueKey + M (other N up to kBlueMaxN), or -1 (the dense group)
 int transform_key(int N) {
-  if (N >= 1 && (N & (N - 1)) == 0 && N <= 4096) return N;
+  if (N >= 1 && (N & (N - 1)) == 0 && N <= kFourMaxN) return N;
   if (N <= kBlueMaxN) return kBlueKey + bluestein_M(N);
   return -1;
 }
@@ -230,6 +251,7 @@ struct Problem {
   int blM = 0;                  // Bluestein FFT length (0: not a Bluestein step count)
   void* chirp = nullptr;        // TC, 2N
   void* bhat = nullptr;         // TC, 2M
+  void* fs = nullptr;           // TC, 2 x N x n^d: four-step FFT scratch (powers of two > 4096)
   void* W1 = nullptr;           // TS, N x n^d
   void* W2 = nullptr;
   void* tri = nullptr;          // TC scratch of exact 1-D solves, 2 x N x n
@@ -438,9 +460,11 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp) {
     q.sinT = bp.take(size_t(N) * N * tcb);
     q.sinM = bp.take(size_t(N) * N * tcb);
   }
-  if (is_pow2(q.N) && q.N <= 4096) {
+  q.fs = nullptr;
+  if (is_pow2(q.N) && q.N <= kFourMaxN) {
     q.tw = bp.take(size_t(2) * N * tcb);
     q.tw4 = bp.take(size_t(2) * N * tcb);
+    if (four_step_n(q.N, tcb)) q.fs = bp.take(size_t(2) * N * q.g0.npts * tcb);   // four-step scratch
   } else if (q.N <= kBlueMaxN) {
     q.blM = bluestein_M(q.N);
     q.tw = bp.take(size_t(2) * q.blM * tcb);
@@ -611,6 +635,7 @@ void site_path(stp_ctx* c, Site<TimeJob>& s) {
   }
   if (s.path == TP_STOCKHAM) s.lds = stockham_lds(s.key, s.C, tcb);
   if (s.path == TP_BLUESTEIN) s.lds = bluestein_lds(s.key - kBlueKey, s.C, tcb);
+  if (s.path == TP_FOUR) s.lds = four_lds(s.key, s.C, tcb);
 }
 
 void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, const std::vector<const void*>& in,
@@ -641,6 +666,7 @@ void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, c
     j.chirp = q.chirp;
     j.bhat = q.bhat;
     j.T = mode == 0 ? q.sinT : q.sinM;
+    j.fs = q.fs;
     j.in = in[i];
     j.out = out[i];
     j.acc64 = acc64[i];
@@ -652,6 +678,8 @@ void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, c
       nb = (j.npts + Cc - 1) / Cc;
     } else if (s->path == TP_STOCKHAM || s->path == TP_BLUESTEIN) {
       nb = (j.npts + s->C - 1) / s->C;
+    } else if (s->path == TP_FOUR) {
+      nb = ((j.npts + s->C - 1) / s->C) * four_n1(q.N);
     } else {
       j.bx = int((j.npts + 63) / 64);
       nb = long(j.bx) * ((q.N + 4 * kDstKpt - 1) / (4 * kDstKpt));
@@ -1100,6 +1128,26 @@ struct Solver : SolverBase {
         LAUNCH_CHECK();
         continue;
       }
+      if (s.path == TP_FOUR) {   // two passes over the scratch
+        const dim3 gr(unsigned(s.blocks)), bl(kBlock);
+        const int nj = int(s.jobs.size());
+        if (mode == 0) {
+          KLAUNCH_NAMED("k_time_fft4<a4,p0>", (k_time_fft4<TS, TC, MODE_A4, 0, 0>), gr, bl, lds, c->stream, s.dev, nj, C);
+          LAUNCH_CHECK();
+          KLAUNCH_NAMED("k_time_fft4<a4,p1>", (k_time_fft4<TS, TC, MODE_A4, 1, 0>), gr, bl, lds, c->stream, s.dev, nj, C);
+        } else {
+          KLAUNCH_NAMED("k_time_fft4<a6,p0>", (k_time_fft4<TS, TC, MODE_A6, 0, 0>), gr, bl, lds, c->stream, s.dev, nj, C);
+          LAUNCH_CHECK();
+          if (acc)
+            KLAUNCH_NAMED("k_time_fft4<a6,p1,add64>", (k_time_fft4<TS, TC, MODE_A6, 1, 1>), gr, bl, lds, c->stream,
+                          s.dev, nj, C);
+          else
+            KLAUNCH_NAMED("k_time_fft4<a6,p1>", (k_time_fft4<TS, TC, MODE_A6, 1, 0>), gr, bl, lds, c->stream, s.dev,
+                          nj, C);
+        }
+        LAUNCH_CHECK();
+        continue;
+      }
       // Stockham: every job of the site has the same N, hence the same layout
       if (mode == 0)
         KLAUNCH_NAMED("k_time_fft<a4>", (k_time_fft<TS, TC, MODE_A4, 0>), dim3(unsigned(s.blocks)), dim3(kBlock), lds,
@@ -1206,6 +1254,10 @@ struct Solver : SolverBase {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     HIP_TRY(hipFuncSetAttribute((const void*)k_time_bluestein<TS, TC, MODE_A6, 1>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    for (const void* f : {(const void*)k_time_fft4<TS, TC, MODE_A4, 0, 0>, (const void*)k_time_fft4<TS, TC, MODE_A4, 1, 0>,
+                          (const void*)k_time_fft4<TS, TC, MODE_A6, 0, 0>, (const void*)k_time_fft4<TS, TC, MODE_A6, 1, 0>,
+                          (const void*)k_time_fft4<TS, TC, MODE_A6, 1, 1>})
+      HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     return STP_OK;
   }
 
@@ -2396,12 +2448,13 @@ void describe_schedule(stp_ctx* c) {
   for (auto& s : c->sites.a4) {
     const char* nm = s.path == TP_FFT2 ? "fft2"
                      : s.path == TP_STOCKHAM ? "stockham"
-                     : s.path == TP_BLUESTEIN ? "bluestein" : "dense";
+                     : s.path == TP_BLUESTEIN ? "bluestein"
+                     : s.path == TP_FOUR ? "fourstep" : "dense";
     if (s.key >= kBlueKey) snprintf(b, sizeof(b), " dst_M%d:%s", s.key - kBlueKey, nm);
     else if (s.key > 0) snprintf(b, sizeof(b), " dst_N%d:%s", s.key, nm);
     else snprintf(b, sizeof(b), " dst_other:%s", nm);
     t += b;
-    if (s.path == TP_STOCKHAM || s.path == TP_BLUESTEIN) {
+    if (s.path == TP_STOCKHAM || s.path == TP_BLUESTEIN || s.path == TP_FOUR) {
       snprintf(b, sizeof(b), ",C=%d", s.C);
       t += b;
     }
@@ -2530,6 +2583,9 @@ stp_status stp_autotune(stp_ctx* c, int reps, int use_cache, stp_tune_report* re
         if (N >= 4 && N <= 256) cand.push_back({TP_FFT2, 0});
         for (int C = 1; C <= 16; C *= 2)
           if (N * C <= 4096 && stockham_lds(N, C, tcb) <= kMaxLds) cand.push_back({TP_STOCKHAM, C});
+        if (four_step_n(N, tcb))
+          for (int C = 1; C <= 16; C *= 2)
+            if (four_n1(N) * C <= 4096 && four_lds(N, C, tcb) <= kMaxLds) cand.push_back({TP_FOUR, C});
         if (N <= 64) cand.push_back({TP_DENSE, 0});
       }
       const Site<TimeJob> cur = c->sites.a4[g];

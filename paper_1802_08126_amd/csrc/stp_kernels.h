@@ -439,6 +439,7 @@ struct TimeJob {        // transforms along the time axis
   const void* chirp;    // Bluestein chirp w^{n^2/2} (2N)
   const void* bhat;     // Bluestein kernel spectrum / M (2M)
   const void* T;        // dense matrix (N x N)
+  void* fs;             // four-step scratch: 2 x N x npts TC (re, im)
   const void* in;
   void* out;
   double* acc64;
@@ -476,6 +477,7 @@ __device__ __forceinline__ TimeJob to_global(TimeJob j) {
   j.chirp = gmem(j.chirp);
   j.bhat = gmem(j.bhat);
   j.T = gmem(j.T);
+  j.fs = gmem(j.fs);
   j.in = gmem(j.in);
   j.out = gmem(j.out);
   j.acc64 = gmem(j.acc64);
@@ -811,6 +813,109 @@ __global__ void __launch_bounds__(kBlock) k_time_fft(const TimeJob* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// large powers of two (N > 4096): the same mappings with the length-N FFT split
+// as N = N1 N2 (four-step; N1 = 2^ceil(log2(N)/2), both <= 1024).  With
+// n = N2 n1 + n2 and k = k1 + N1 k2,
+//   W_k = sum_n2 w_N2^{n2 k2} [ w_N^{n2 k1} sum_n1 w_N1^{n1 k1} s_{N2 n1 + n2} ].
+// Pass 0: gather s for one n2 and C columns (pre-map), length-N1 FFT in LDS,
+//         twiddle w_N^{n2 k1}, store to the scratch at row k1 N2 + n2.
+// Pass 1: load row block k1, length-N2 FFT in LDS, post-map W_k to its output
+//         (each FFT value feeds exactly one output).
+// Blocks of a job: ceil(npts / C) column blocks times N1 rows (pass 0 skips
+// rows >= N2 when N1 = 2 N2).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int four_n1(int N) {
+  int m = 0;
+  while ((1 << m) < N) ++m;
+  return 1 << ((m + 1) / 2);
+}
+
+template <typename TS, typename TC, int MODE, int PASS, int ACC64>
+__device__ __forceinline__ void time_fft4_body(const TimeJob& J, int C) {
+  const long npts = J.npts;
+  const int N = J.N, N1 = four_n1(N), N2 = N / N1;
+  const int L = PASS == 0 ? N1 : N2;        // length of this pass's FFTs
+  const int stride = PASS == 0 ? N2 : N1;   // w_L^j = w_N^{j stride}
+  const long ncb = (npts + C - 1) / C;
+  const long lb = block_id() - J.block0;
+  const int row = int(lb / ncb);            // pass 0: n2; pass 1: k1
+  if (PASS == 0 && row >= N2) return;
+  const long cb = lb - long(row) * ncb;
+  const TC* tw = (const TC*)J.tw;
+  const TC* tw4 = (const TC*)J.tw4;
+  TC* fre = (TC*)J.fs;
+  TC* fim = fre + long(N) * npts;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TC* re = reinterpret_cast<TC*>(smem_raw);
+  TC* im = re + L * C;
+  TC* twr = im + L * C;
+  TC* twi = twr + L;
+  const int t = threadIdx.x;
+  for (int q = t; q < L; q += kBlock) {
+    twr[q] = tw[long(q) * stride];
+    twi[q] = tw[N + long(q) * stride];
+  }
+  const int col = t % C, jg = t / C, G = kBlock / C;
+  const long i = cb * C + col;
+  const bool valid = (jg < G) && (i < npts);
+  for (int a = jg; a < L; a += G) {
+    TC vr = 0, vi = 0;
+    if (PASS == 0) {
+      const int m = a * N2 + row;
+      if (MODE == MODE_A4) {   // s_m = in[N-1-m] w4^m
+        const TC v = valid ? ld<TC>((const TS*)J.in, long(N - 1 - m) * npts + i) : TC(0);
+        vr = v * tw4[m];
+        vi = v * tw4[N + m];
+      } else {                 // v_m = in[2m] (m < N/2), -in[2(N-1-m)+1] (m >= N/2)
+        const int n = m < N / 2 ? 2 * m : 2 * (N - 1 - m) + 1;
+        const TC v = valid ? ld<TC>((const TS*)J.in, long(n) * npts + i) : TC(0);
+        vr = m < N / 2 ? v : -v;
+      }
+    } else if (valid) {
+      const long o = (long(row) * N2 + a) * npts + i;
+      vr = fre[o];
+      vi = fim[o];
+    }
+    re[a * C + col] = vr;
+    im[a * C + col] = vi;
+  }
+  __syncthreads();
+  fft_stages<TC>(re, im, twr, twi, L, C, col, jg, G);
+  if (!valid) return;
+  for (int a = jg; a < L; a += G) {
+    const TC xr = re[a * C + col], xi = im[a * C + col];
+    if (PASS == 0) {   // a = k1: twiddle w_N^{n2 k1}, scratch row k1 N2 + n2
+      const int e = int((long(row) * a) & (N - 1));
+      const TC wr = tw[e], wi = tw[N + e];
+      const long o = (long(a) * N2 + row) * npts + i;
+      fre[o] = xr * wr - xi * wi;
+      fim[o] = xr * wi + xi * wr;
+    } else {           // a = k2: W_m, m = k1 + N1 k2
+      const int m = row + N1 * a;
+      int n;
+      TC v;
+      if (MODE == MODE_A4) {
+        n = m < N / 2 ? 2 * m : 2 * (N - 1 - m) + 1;
+        v = m < N / 2 ? xr : -xr;
+      } else {
+        n = N - 1 - m;
+        v = tw4[m] * xr - tw4[N + m] * xi;
+      }
+      const long o = long(n) * npts + i;
+      if (ACC64) J.acc64[o] += J.alpha * double(v);
+      else st<TS, TC>((TS*)J.out, o, TC(J.alpha) * v);
+    }
+  }
+}
+
+template <typename TS, typename TC, int MODE, int PASS, int ACC64>
+__global__ void __launch_bounds__(kBlock) k_time_fft4(const TimeJob* __restrict__ jobs, int njobs, int C) {
+  const TimeJob J = to_global(jobs[find_job(jobs, njobs)]);
+  if (J.state && done_flag(J.state)) return;
+  time_fft4_body<TS, TC, MODE, PASS, ACC64>(J, C);
+}
+
 // any N (Bluestein): the length-N DFT of the MODE_A4 / MODE_A6 mappings above
 // (valid for every N, with the even/odd split of A6 at ceil(N/2)) as a chirp
 // convolution,  X_k = c_k sum_n (x_n c_n) conj(c_{k-n}),  c_n = w_N^{n^2/2} =

@@ -11,6 +11,7 @@ from .workloads import (  # noqa: F401
     heat1d_random,
     heat2d_gaussians,
     heat3d_lognormal,
+    heat3d_sine,
     batch2d,
     lognormal_field,
     manufactured_u,

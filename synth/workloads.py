@@ -316,6 +316,21 @@ def small_problem(dim: int, n: int, N: int, seed: int = 7, T: float = 1.0, R: in
                    steps=None if steps is None else np.asarray(steps, dtype=np.float64))
 
 
+def heat3d_sine(n: int = 15, N: int = 16, T: float = 0.1) -> Problem:
+    """The 3-D test problem of the paper's time-parallel experiments (Section
+    8.3) in finite-difference form: kappa = 1, T = 0.1, exact solution
+    exp(-3 pi^2 t) sin(pi x) sin(pi y) sin(pi z), which solves the heat equation
+    with F = 0 and u0 = sin(pi x) sin(pi y) sin(pi z).  n = 15 interior nodes
+    per axis is the paper's mesh of 16^3 cells (h = 1/16)."""
+    x = _interior(n)
+    s = np.sin(np.pi * x)
+    u0 = _outer([s, s, s])
+    kf = np.ones((1, n + 2, n + 2, n + 2))
+    tc = np.ones((1, N))
+    F = np.zeros((N, n, n, n))
+    return Problem(3, n, N, T, kf, tc, F, u0, name="heat3d_sine", seed=0)
+
+
 CONFIG_BUILDERS = {
     "heat1d_63_N64": lambda: heat1d_random(),
     "heat2d_255_N256": lambda: heat2d_gaussians(),

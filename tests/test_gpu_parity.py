@@ -210,3 +210,37 @@ def test_apply_precond_H_any_N(d, n, N):
     got = host(s.apply_precond(stp.STP_PC_H, dev(r)))
     assert relmax(got, pc.Hinv(r)) < 2e-5
     s.close()
+
+
+@pytest.mark.parametrize("N", [4096, 8192, 16384, 65536, 131072])
+@pytest.mark.parametrize("d,n", [(1, 7), (2, 3)])
+def test_apply_precond_H_large_N(d, n, N):
+    """H~^{-1} at large power-of-two step counts: the time transforms run as
+    four-step FFTs (N = N1 N2 with a complex scratch pass; N = 2^17 has
+    N1 = 2 N2; in float64 also N = 4096, whose single-pass LDS FFT does not fit)."""
+    import paper_1802_08126_amd as stp
+    prob = synth.small_problem(d, n, N, seed=N % 1000)
+    print(f"case d={d} n={n} N={N}", flush=True)
+    s = solver(prob, spatial="mg")
+    assert "fourstep" in s.schedule()
+    pc = Preconditioners(prob, spatial="mg")
+    r = np.random.default_rng(N).standard_normal((N,) + (n,) * d)
+    want = pc.Hinv(r)
+    got = host(s.apply_precond(stp.STP_PC_H, dev(r)))
+    assert relmax(got, want) < 1e-11
+    s.close()
+    s = solver(prob, spatial="mg", precision="f32")
+    got = host(s.apply_precond(stp.STP_PC_H, dev(r)))
+    assert relmax(got, want) < 5e-5
+    s.close()
+
+
+def test_uzawa_iterations_large_N():
+    """Three Uzawa iterations at N = 16384 (four-step transforms inside the
+    captured iteration) against the oracle."""
+    prob = synth.small_problem(2, 3, 16384, seed=5)
+    s = solver(prob, omega=0.7, tol=0.0, max_iter=3)
+    u, p, info = s.solve()
+    ref = uzawa.uzawa_fixed(prob, 3, omega=0.7, spatial="mg")
+    assert relmax(host(u), ref["u"]) < 1e-11 and relmax(host(p), ref["p"]) < 1e-11
+    s.close()

@@ -41,6 +41,20 @@ def test_library_dst_mapping(N):
     assert np.allclose(dst.forward(r), sfft.dst(r, type=3) / N, atol=tol)
 
 
+@pytest.mark.parametrize("N", [4097, 8192])
+def test_large_N_route_equals_definition(N):
+    """Above DENSE_MAX_N the oracle evaluates the maps through the library DST;
+    compare with the dense sums (sine matrix built here) on a few columns."""
+    assert N > dst.DENSE_MAX_N
+    rng = np.random.default_rng(N)
+    r = rng.standard_normal((N, 2))
+    S = dst.sine_matrix(N)
+    tol = 1e-13 * N
+    assert np.allclose(dst.inverse(r), S @ r, atol=tol)
+    assert np.allclose(dst.inverse_transpose(r), S.T @ r, atol=tol)
+    assert np.allclose(dst.forward(r), (2.0 / N) * S.T @ (dst.weights(N)[:, None] * r), atol=tol)
+
+
 def test_mu_positive_and_bounded():
     for N in [1, 4, 1000]:
         m = dst.mu(N)
