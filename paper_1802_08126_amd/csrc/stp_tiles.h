@@ -377,9 +377,15 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
   using XB = Box<D, 2 * T::X + 3, 2 * T::Y + 3, 2 * T::Z + 3>;
   using RB = Box<D, 2 * T::X + 1, 2 * T::Y + 1, 2 * T::Z + 1>;
   using CB = Box<D, T::X, T::Y, T::Z>;
+  // the residual tile is stored split by the parity of x (rows of RE even and
+  // RO odd positions), so the restriction's three x-taps of consecutive coarse
+  // nodes are unit-stride LDS reads instead of stride 2 (bank conflicts)
+  constexpr int RE = T::X + 1, RO = T::X;
+  constexpr int RROWS = RB::Y * RB::Z;
   __shared__ TC sk[KB::size];
   __shared__ TC sx[XB::size];
-  __shared__ TC sr[RB::size];
+  __shared__ TC sre[RROWS * RE];
+  __shared__ TC sro[RROWS * RO];
   const LevelOp L = J.op;
   s1 = min(s1, L.S);
   if (s0 >= s1) return;
@@ -441,9 +447,12 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
           if (D >= 2) inr = inr && in_range(it.y, 1, XB::Y - 2);
           if (D >= 3) inr = inr && in_range(it.z, 1, XB::Z - 2);
           if (inr) {
-            const int rq = RB::idx(it.x - 1, D >= 2 ? it.y - 1 : 0, D >= 3 ? it.z - 1 : 0);
+            const int px = it.x - 1;
+            const int row = (D >= 2 ? it.y - 1 : 0) + (D >= 3 ? (it.z - 1) * RB::Y : 0);
             const TC off = offsum_at<D, XB, KB, TC>(sk, sx, kpos<D, KB>(it.x, it.y, it.z), it.q);
-            sr[rq] = one_m_omega * bcur[k] + (FIX ? gamma * off : off);
+            const TC rv = one_m_omega * bcur[k] + (FIX ? gamma * off : off);
+            if (px & 1) sro[row * RO + (px >> 1)] = rv;
+            else sre[row * RE + (px >> 1)] = rv;
           }
         }
         it.next();
@@ -454,8 +463,9 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
     STP_BOX_FOR(CB, it) {
       const int Jx = Ix + it.x, Jy = Iy + it.y, Jz = Iz + it.z;
       if (!interior<D>(Jx, Jy, Jz, nc)) continue;
-      // fine node 2J sits at r-box position 2x+1 per axis
-      const int c = RB::idx(2 * it.x + 1, D >= 2 ? 2 * it.y + 1 : 0, D >= 3 ? 2 * it.z + 1 : 0);
+      // fine node 2J sits at r-box position 2x+1 per axis: x-taps 2x (even row
+      // entry x), 2x+1 (odd entry x) and 2x+2 (even entry x+1)
+      const int r0 = (D >= 2 ? 2 * it.y + 1 : 0) + (D >= 3 ? (2 * it.z + 1) * RB::Y : 0);
       TC acc = 0;
 #pragma unroll
       for (int dz = (D >= 3 ? -1 : 0); dz <= (D >= 3 ? 1 : 0); ++dz)
@@ -464,8 +474,9 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
           TC w = 1;
           if (D >= 2) w *= (dy == 0 ? TC(0.5) : TC(0.25));
           if (D >= 3) w *= (dz == 0 ? TC(0.5) : TC(0.25));
-          const int row = c + dz * RB::X * RB::Y + dy * RB::X;
-          acc += w * (TC(0.25) * sr[row - 1] + TC(0.5) * sr[row] + TC(0.25) * sr[row + 1]);
+          const int row = r0 + dz * RB::Y + dy;
+          acc += w * (TC(0.25) * sre[row * RE + it.x] + TC(0.5) * sro[row * RO + it.x] +
+                      TC(0.25) * sre[row * RE + it.x + 1]);
         }
       st<TS, TC>(bcs, vec_off<D>(Jx, Jy, Jz, nc), acc);
     }
