@@ -28,9 +28,15 @@ method with GMRES and give no further detail.  The reading taken here:
   restart; a failed check lets the cycle go on.  At most max_iter Arnoldi
   steps in total.
 
-Remark 3.4 names MINRES with a block-diagonal preconditioner as an
-alternative; it needs a symmetric positive definite preconditioner and no
-omega, and is not what the experiments used.
+MINRES (Remark 3.4) is the alternative the paper names: the saddle matrix is
+symmetric, and with the symmetric positive definite block-diagonal
+preconditioner P = diag(A~, H~) (P^{-1} = diag(A~^{-1}, H~^{-1})) no damping
+parameter is needed.  ``minres`` below is the preconditioned MINRES of Paige and
+Saunders (1975): a Lanczos process on P^{-1} S in the P inner product, the
+tridiagonal least-squares problem solved by Givens rotations, three-term
+updates of the iterate.  Its residual estimate is ||g - S x||_{P^{-1}}; the stop
+test is again ||f - B u|| <= tol ||f||, checked once that estimate is <= tol times
+its initial value and then every ``check_every`` steps.
 """
 from __future__ import annotations
 
@@ -171,3 +177,91 @@ def gmres(prob, omega: float = 0.8, tol: float = 1e-8, restart: int = 20, max_it
     rel_b = float(np.linalg.norm(f - st.apply_B(prob, u)) / np.linalg.norm(f))
     return dict(u=u, p=p, iters=iters, history=np.array(hist), checks=checks, rel=true_rel, rel_res=rel_b,
                 status=status)
+
+
+def block_precond(prob, pc: Preconditioners, r1, r2):
+    """P^{-1} r = [A~^{-1} r_1; H~^{-1} r_2] (Remark 3.4)."""
+    return pc.Ainv(r1), pc.Hinv(r2)
+
+
+def minres(prob, tol: float = 1e-8, max_iter: int = 500, spatial: str = "mg", pc: Preconditioners | None = None,
+           p_init=None, u_init=None, check_every: int = 8):
+    """Preconditioned MINRES on the saddle system with P^{-1} = diag(A~^{-1}, H~^{-1}).
+    Returns u, p, iters, the history of the residual estimate ||g - S x||_{P^{-1}}
+    relative to its initial value (initial entry first), ||f - B u|| / ||f||."""
+    pc = pc or Preconditioners(prob, spatial=spatial)
+    g1, g2 = saddle_rhs(prob)
+    shape = g1.shape
+    n = g1.size
+    g = np.concatenate([g1.ravel(), g2.ravel()])
+    f = st.rhs(prob)
+    fnorm = np.linalg.norm(f)
+    x = np.zeros(2 * n)
+    if p_init is not None:
+        x[:n] = np.asarray(p_init, dtype=np.float64).ravel()
+    if u_init is not None:
+        x[n:] = np.asarray(u_init, dtype=np.float64).ravel()
+
+    def S(v):
+        a, b = saddle_apply(prob, v[:n].reshape(shape), v[n:].reshape(shape))
+        return np.concatenate([a.ravel(), b.ravel()])
+
+    def Pinv(v):
+        a, b = block_precond(prob, pc, v[:n].reshape(shape), v[n:].reshape(shape))
+        return np.concatenate([a.ravel(), b.ravel()])
+
+    def stop_ok(xc):
+        return np.linalg.norm(f - st.apply_B(prob, xc[n:].reshape(shape))) <= tol * fnorm
+
+    r1 = g - S(x)
+    y = Pinv(r1)
+    beta1 = float(np.sqrt(np.dot(r1, y)))
+    hist = [1.0]
+    status = "maxiter"
+    iters = 0
+    if stop_ok(x):
+        status = "converged"
+    elif beta1 > 0:
+        oldb, beta, dbar, epsln, phibar = 0.0, beta1, 0.0, 0.0, beta1
+        cs, sn = -1.0, 0.0
+        w = np.zeros(2 * n)
+        w2 = np.zeros(2 * n)
+        r2 = r1.copy()
+        checking = False
+        while iters < max_iter:
+            v = y / beta                      # Lanczos vector (P^{-1} space)
+            y = S(v)
+            if iters > 0:
+                y = y - (beta / oldb) * r1
+            alfa = float(np.dot(v, y))
+            y = y - (alfa / beta) * r2
+            r1, r2 = r2, y
+            y = Pinv(r2)
+            oldb, beta = beta, float(np.sqrt(max(np.dot(r2, y), 0.0)))
+            # apply the previous rotation, then the new one annihilating beta
+            oldeps = epsln
+            delta = cs * dbar + sn * alfa
+            gbar = sn * dbar - cs * alfa
+            epsln = sn * beta
+            dbar = -cs * beta
+            gamma = max(float(np.hypot(gbar, beta)), 1e-300)
+            cs, sn = gbar / gamma, beta / gamma
+            phi = cs * phibar
+            phibar = sn * phibar
+            w1, w2 = w2, w
+            w = (v - oldeps * w1 - delta * w2) / gamma
+            x = x + phi * w
+            iters += 1
+            hist.append(abs(phibar) / beta1)
+            if abs(phibar) <= tol * beta1:
+                checking = True
+            if (checking and (iters % check_every == 0 or abs(phibar) <= tol * beta1)) and stop_ok(x):
+                status = "converged"
+                break
+            if beta == 0.0:
+                status = "converged" if stop_ok(x) else "breakdown"
+                break
+    u = x[n:].reshape(shape)
+    p = x[:n].reshape(shape)
+    rel_b = float(np.linalg.norm(f - st.apply_B(prob, u)) / fnorm)
+    return dict(u=u, p=p, iters=iters, history=np.array(hist), rel_res=rel_b, status=status)

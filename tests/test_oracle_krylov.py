@@ -123,3 +123,38 @@ def test_gmres_restarted_reaches_tolerance_with_paper_stop_test():
     for c in range(0, len(h) - 1, 5):                  # cycles of 5 steps
         seg = h[c + 1:c + 6]
         assert np.all(np.diff(seg) <= 1e-12 * h[0])
+
+
+def test_minres_matches_library_minres():
+    """The oracle's preconditioned MINRES (Remark 3.4, P = diag(A~, H~)) gives
+    the iterates of scipy's MINRES with the same operator and preconditioner."""
+    import scipy.sparse.linalg as spla
+    prob = small(2, 3, 4, seed=21)
+    pc = Preconditioners(prob, spatial="mg")
+    g = flat(krylov.saddle_rhs(prob))
+    n = g.size // 2
+    shape = (prob.N,) + (prob.n,) * prob.dim
+    S = spla.LinearOperator((2 * n, 2 * n), dtype=np.float64,
+                            matvec=lambda v: flat(krylov.saddle_apply(prob, v[:n].reshape(shape), v[n:].reshape(shape))))
+    M = spla.LinearOperator((2 * n, 2 * n), dtype=np.float64,
+                            matvec=lambda v: flat(krylov.block_precond(prob, pc, v[:n].reshape(shape), v[n:].reshape(shape))))
+    for k in (1, 4, 9):
+        x_lib, _ = spla.minres(S, g, M=M, maxiter=k, rtol=0.0)
+        out = krylov.minres(prob, tol=0.0, max_iter=k, pc=pc)
+        x = np.concatenate([out["p"].ravel(), out["u"].ravel()])
+        assert out["iters"] == k
+        assert np.abs(x - x_lib).max() < 1e-10 * np.abs(x_lib).max(), k
+
+
+def test_minres_needs_no_damping_and_reaches_euler():
+    """MINRES has no omega; it reaches the sequential solution on a problem
+    where Uzawa with omega = 1.2 diverges, and its residual estimate never
+    rises."""
+    prob = small(2, 7, 8, seed=3)
+    pc = Preconditioners(prob, spatial="mg")
+    assert uzawa.uzawa(prob, omega=1.2, tol=1e-10, max_iter=300, pc=pc)["status"] != "converged"
+    out = krylov.minres(prob, tol=1e-12, max_iter=600, pc=pc)
+    assert out["status"] == "converged"
+    ref = euler.seq_euler(prob)
+    assert np.abs(out["u"] - ref).max() < 1e-9 * np.abs(ref).max()
+    assert np.all(np.diff(out["history"]) <= 1e-12)
