@@ -89,7 +89,12 @@ typedef struct {
 typedef struct {
   int precision;        /* STP_PREC_*                                                */
   int spatial;          /* STP_SPATIAL_*                                             */
-  int nu_A, nu_H;       /* V-cycles per spatial preconditioner application (>= 1)    */
+  int nu_A, nu_H;       /* V-cycles per application of A~_n^{-1} (nu_A) and of each
+                           H~_k^{-1} (nu_H), 1..8 (Section 8.2 uses one or two); every
+                           cycle after the first acts on the residual the earlier ones
+                           leave.  Multigrid only (exact solves need one; ignored
+                           there).  Above 1 the workspace holds one more N x n^dim
+                           vector of the storage type.  Out of range: STP_EINVAL.    */
   double omega;         /* Uzawa damping (eq. (3.1)); <= 0: estimated per problem at
                            stp_create (see stp_omega_info)                            */
   double tol;           /* stop at ||f - B u||_2 <= tol ||f||_2                      */

@@ -59,6 +59,29 @@ def apply_B(prob, x):
     return apply_K(x) + apply_Ablk(prob, x)
 
 
+def s_norm(prob, v: np.ndarray) -> float:
+    """||v||_S by the identity of Theorem 6.2 (eqs. (6.11)-(6.14)) with M = I:
+    v^T S v = sum_n [ (1/tau_n)|dv_n|^2_{A_n^{-1}} + tau_n |v_n|^2_{A_n} + |dv_n|^2 ] + |v_N|^2,
+    dv_n = v_n - v_{n-1}, v_0 = 0; A_n^{-1} by a sparse LU per distinct step operator."""
+    import scipy.sparse.linalg as spla
+    Ar = [fd.assemble(prob.kfields[r], prob.n, prob.dim, prob.h) for r in range(prob.R)]
+    lus = {}
+    total = 0.0
+    prev = np.zeros(prob.npts)
+    for i in range(prob.N):
+        key = tuple(prob.tcoef[:, i])
+        An = sum(prob.tcoef[r, i] * Ar[r] for r in range(prob.R)).tocsc()
+        if key not in lus:
+            lus[key] = spla.splu(An)
+        vi = v[i].ravel()
+        dv = vi - prev
+        t = prob.taus[i]
+        total += dv @ lus[key].solve(dv) / t + t * (vi @ (An @ vi)) + dv @ dv
+        prev = vi
+    total += prev @ prev
+    return float(np.sqrt(total))
+
+
 def apply_saddle(prob, p, u):
     """saddle [p; u] = [A p - K u;  -K^T p - (K + K^T + A) u]."""
     Ap = apply_Ablk(prob, p)

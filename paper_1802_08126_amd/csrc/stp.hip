@@ -254,6 +254,7 @@ struct Problem {
   void* fs = nullptr;           // TC, 2 x N x n^d: four-step FFT scratch (powers of two > 4096)
   void* W1 = nullptr;           // TS, N x n^d
   void* W2 = nullptr;
+  void* Xnu = nullptr;          // TS, N x n^d: correction of one cycle when nu_A or nu_H > 1
   void* tri = nullptr;          // TC scratch of exact 1-D solves, 2 x N x n
   double fnorm = 0;
 };
@@ -288,11 +289,13 @@ struct VCycle {
   Site<PointJob> tri;                    // exact 1-D solves
 };
 
-enum { VC_A = 0, VC_H1 = 1, VC_H2 = 2 };
+// VC_AX, VC_HX: the A and H cycles with their output stored to Xnu (nu > 1)
+enum { VC_A = 0, VC_H1 = 1, VC_H2 = 2, VC_AX = 3, VC_HX = 4 };
 
 struct Sites {
   Site<ResidJob> resid[2];
-  VCycle vc[3];
+  VCycle vc[5];
+  Site<NuJob> nu[2];     // steps between the cycles of an application with nu > 1 (A, H)
   Site<TileJob> mid;
   std::vector<Site<TimeJob>> a4, a6;
   std::vector<FinJob> fin;
@@ -355,6 +358,14 @@ struct stp_ctx {
   Schedule sched;
   std::string sched_text;
 };
+
+namespace {
+constexpr int kMaxNu = 8;   // V-cycles per spatial preconditioner application
+// nu_A or nu_H > 1 with multigrid: the cycles of one application run through Xnu
+bool multi_cycle(const stp_ctx* c) {
+  return c->spatial == STP_SPATIAL_MG && (c->opt.nu_A > 1 || c->opt.nu_H > 1);
+}
+}  // namespace
 
 static inline void kt_begin(stp_ctx* c, const char* name) {
   if (!c->kt.on) return;
@@ -430,7 +441,7 @@ LevelOp family_op(const Problem& q, int l, int fam) {
 }
 
 // Plan (dry run) or carve (real run) one problem's buffers.
-void plan_problem(int prec, int spatial, Problem& q, Bump& bp) {
+void plan_problem(int prec, int spatial, Problem& q, Bump& bp, bool nux) {
   const size_t tsb = ts_bytes(prec), tcb = tc_bytes(prec);
   const long N = q.N;
   {
@@ -474,6 +485,7 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp) {
   }
   q.W1 = bp.take(size_t(N) * q.g0.npts * tsb);
   q.W2 = bp.take(size_t(N) * q.g0.npts * tsb);
+  q.Xnu = nux ? bp.take(size_t(N) * q.g0.npts * tsb) : nullptr;
   q.tri = (spatial == STP_SPATIAL_EXACT) ? bp.take(size_t(2) * N * q.n * tcb) : nullptr;
   for (size_t l = 0; l < q.lv.size(); ++l) {
     Level& L = q.lv[l];
@@ -533,7 +545,8 @@ struct VTop {
   double* acc64;   // float64 accumulation target (or null)
 };
 
-void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top) {
+// acc: the finest up-sweep adds into the float64 targets (else stores)
+void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top, bool acc) {
   int Lmax = 0;
   for (auto& q : c->pr) Lmax = std::max(Lmax, int(q.lv.size()));
   vc.down.assign(std::max(0, Lmax - 1), Site<TileJob>());
@@ -543,7 +556,6 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top)
   for (size_t i = 0; i < c->pr.size(); ++i) {
     Problem& q = c->pr[i];
     const VTop& T = top[i];
-    const bool acc = fam == 0;   // the A-tilde cycle adds into p; the H cycles store
     if (c->spatial == STP_SPATIAL_EXACT) {
       PointJob j{};
       j.total = q.N;
@@ -726,9 +738,27 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
     in6[i] = q.W1;                             // u += omega Phi^{-1} yhat
     acc6[i] = u[i];
   }
-  build_vcycle(c, S.vc[VC_A], 0, topA);
-  build_vcycle(c, S.vc[VC_H1], 1, topH);
-  build_vcycle(c, S.vc[VC_H2], 1, topH);
+  build_vcycle(c, S.vc[VC_A], 0, topA, true);    // the A-tilde cycle adds into p
+  build_vcycle(c, S.vc[VC_H1], 1, topH, false);  // the H cycles store
+  build_vcycle(c, S.vc[VC_H2], 1, topH, false);
+  S.vc[VC_AX] = VCycle();
+  S.vc[VC_HX] = VCycle();
+  S.nu[0] = Site<NuJob>();
+  S.nu[1] = Site<NuJob>();
+  if (multi_cycle(c)) {
+    std::vector<VTop> topAX(P), topHX(P);
+    for (size_t i = 0; i < P; ++i) {
+      Problem& q = c->pr[i];
+      topAX[i] = VTop{q.W1, q.Xnu, nullptr};
+      topHX[i] = VTop{q.W2, q.Xnu, nullptr};
+      const long total = long(q.N) * q.g0.npts;
+      const long nb = (total + kBlock - 1) / kBlock;
+      S.nu[0].add(NuJob{0, q.g0, family_op(q, 0, 0), total, q.W1, q.Xnu, nullptr, p[i], &q.state->done}, nb);
+      S.nu[1].add(NuJob{0, q.g0, family_op(q, 0, 1), total, q.W2, q.Xnu, q.W1, nullptr, &q.state->done}, nb);
+    }
+    build_vcycle(c, S.vc[VC_AX], 0, topAX, false);
+    build_vcycle(c, S.vc[VC_HX], 1, topHX, false);
+  }
   S.mid = Site<TileJob>();
   for (size_t i = 0; i < P; ++i) {
     Problem& q = c->pr[i];
@@ -769,6 +799,8 @@ void for_each_site(Sites& S, F&& f) {
     f(v.tri);
   }
   f(S.mid);
+  f(S.nu[0]);
+  f(S.nu[1]);
   for (auto& x : S.a4) f(x);
   for (auto& x : S.a6) f(x);
 }
@@ -848,6 +880,7 @@ stp_status bind_jobs(stp_ctx* c, const std::vector<double*>& u, const std::vecto
   if (!A.fused.empty())
     for (auto& j : A.fused[0].jobs) j.acc64 = acc_p[owner(j.state)];
   for (auto& j : A.tri.jobs) j.acc64 = acc_p[owner(j.state)];
+  for (auto& j : S.nu[0].jobs) j.t = acc_p[owner(j.state)];
   for (auto& s : S.a6)
     for (auto& j : s.jobs) {
       const size_t i = owner(j.state);
@@ -860,6 +893,7 @@ stp_status bind_jobs(stp_ctx* c, const std::vector<double*>& u, const std::vecto
   if (!A.up.empty() && (st = upload_site(c, A.up[0])) != STP_OK) return st;
   if (!A.fused.empty() && (st = upload_site(c, A.fused[0])) != STP_OK) return st;
   if ((st = upload_site(c, A.tri)) != STP_OK) return st;
+  if ((st = upload_site(c, S.nu[0])) != STP_OK) return st;
   for (auto& s : S.a6)
     if ((st = upload_site(c, s)) != STP_OK) return st;
   return STP_OK;
@@ -1008,8 +1042,49 @@ struct Solver : SolverBase {
     return transform_sites(one6, 1);
   }
 
+  // nu_A (A) or nu_H (H1, H2) cycles, each on the residual the ones before
+  // it leave (multigrid only; exact solves need one).  A: cycles 1..nu-1 store
+  // to Xnu, then b -= L Xnu and p += Xnu, and the last cycle adds into p.
+  // H: the first cycle stores the output o, b -= L o, then each further cycle
+  // stores to Xnu and o += Xnu (b -= L Xnu if another follows).  The steps
+  // read their operands from job tables, so captured graphs follow a rebinding
+  // of the A target as the cycles do.
   stp_status run_vcycle(int which) override {
-    VCycle& vc = c->sites.vc[which];
+    const int nu = which == VC_A ? c->opt.nu_A : c->opt.nu_H;
+    if (nu <= 1 || !multi_cycle(c)) return run_cycle(c->sites.vc[which]);
+    const int fam = which == VC_A ? 0 : 1;
+    VCycle& vx = c->sites.vc[fam == 0 ? VC_AX : VC_HX];
+    stp_status st;
+    if (fam == 0) {
+      for (int k = 1; k < nu; ++k) {
+        if ((st = run_cycle(vx)) != STP_OK) return st;
+        if ((st = nu_step(fam, NU_RES_X | NU_ADD)) != STP_OK) return st;
+      }
+      return run_cycle(c->sites.vc[which]);
+    }
+    if ((st = run_cycle(c->sites.vc[which])) != STP_OK) return st;
+    if ((st = nu_step(fam, NU_RES_O)) != STP_OK) return st;
+    for (int k = 1; k < nu; ++k) {
+      if ((st = run_cycle(vx)) != STP_OK) return st;
+      if ((st = nu_step(fam, NU_ADD | (k + 1 < nu ? NU_RES_X : 0))) != STP_OK) return st;
+    }
+    return STP_OK;
+  }
+
+  stp_status nu_step(int fam, int mode) {
+    Site<NuJob>& s = c->sites.nu[fam];
+    if (s.jobs.empty()) return STP_OK;
+    c->kt.level = 0;
+    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
+    const int nj = int(s.jobs.size());
+    if (c->dim == 1) KLAUNCH_NAMED("k_nu_step", (k_nu_step<1, TS, TC>), gr, bl, 0, c->stream, s.dev, nj, mode);
+    else if (c->dim == 2) KLAUNCH_NAMED("k_nu_step", (k_nu_step<2, TS, TC>), gr, bl, 0, c->stream, s.dev, nj, mode);
+    else KLAUNCH_NAMED("k_nu_step", (k_nu_step<3, TS, TC>), gr, bl, 0, c->stream, s.dev, nj, mode);
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
+  stp_status run_cycle(VCycle& vc) {
     if (c->spatial == STP_SPATIAL_EXACT) {
       Site<PointJob>& s = vc.tri;
       c->kt.level = 0;
@@ -1392,7 +1467,8 @@ stp_status validate_one(const stp_grid* g, int N, double tau, const stp_kappa* k
 stp_status validate_opts(const stp_options* opt) {
   if (opt->precision < STP_PREC_F64 || opt->precision > STP_PREC_BF16) return fail(STP_EINVAL, "bad precision");
   if (opt->spatial < STP_SPATIAL_AUTO || opt->spatial > STP_SPATIAL_NONE) return fail(STP_EINVAL, "bad spatial mode");
-  if (opt->nu_A != 1 || opt->nu_H != 1) return fail(STP_EUNSUPPORTED, "only nu_A = nu_H = 1 is implemented");
+  if (opt->nu_A < 1 || opt->nu_A > kMaxNu || opt->nu_H < 1 || opt->nu_H > kMaxNu)
+    return fail(STP_EINVAL, "nu_A and nu_H must lie in 1..%d", kMaxNu);
   if (!(opt->tol >= 0)) return fail(STP_EINVAL, "tol must be >= 0");
   if (opt->max_iter < 0) return fail(STP_EINVAL, "max_iter must be >= 0");
   return STP_OK;
@@ -1656,7 +1732,7 @@ stp_status describe(stp_ctx* c, int P, const stp_grid* grids, const int* N, cons
 }
 
 size_t plan_all(stp_ctx* c, Bump& bp) {
-  for (auto& q : c->pr) plan_problem(c->prec, c->spatial, q, bp);
+  for (auto& q : c->pr) plan_problem(c->prec, c->spatial, q, bp, multi_cycle(c));
   std::vector<double*> nul(c->P, nullptr);
   build_sites(c, nul, nul);
   c->tables_off = (bp.off + 255) & ~size_t(255);
@@ -1797,7 +1873,7 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
   Bump real;
   real.dry = false;
   real.base = (char*)c->ws;
-  for (auto& q : c->pr) plan_problem(c->prec, c->spatial, q, real);
+  for (auto& q : c->pr) plan_problem(c->prec, c->spatial, q, real, multi_cycle(c.get()));
   HIP_TRY(hipHostMalloc((void**)&c->state_host, sizeof(DevState) * P, hipHostMallocDefault));
   HIP_TRY(hipEventCreate(&c->ev0));
   HIP_TRY(hipEventCreate(&c->ev1));

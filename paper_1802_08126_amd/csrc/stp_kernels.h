@@ -428,6 +428,19 @@ struct PointJob {       // exact 1-D solves
   const int* state;
 };
 
+struct NuJob {          // steps between the cycles of one application (nu > 1)
+  long block0;
+  Geom g;
+  LevelOp op;           // level-0 operator of the cycles' family
+  long total;           // slabs x points
+  void* b;              // cycle input, turned into the remaining residual in place (TS)
+  void* x;              // the correction of the last cycle (TS)
+  void* o;              // H family: the stored output (TS), else null
+  double* t;            // A family: the float64 accumulation target, else null
+  const int* state;
+};
+enum NuMode { NU_RES_X = 1, NU_RES_O = 2, NU_ADD = 4 };
+
 struct TimeJob {        // transforms along the time axis
   long block0;
   long npts;
@@ -468,6 +481,15 @@ __device__ __forceinline__ PointJob to_global(PointJob j) {
   j.out = gmem(j.out);
   j.acc64 = gmem(j.acc64);
   j.scratch = gmem(j.scratch);
+  j.state = gmem(j.state);
+  return j;
+}
+__device__ __forceinline__ NuJob to_global(NuJob j) {
+  j.op = to_global(j.op);
+  j.b = gmem(j.b);
+  j.x = gmem(j.x);
+  j.o = gmem(j.o);
+  j.t = gmem(j.t);
   j.state = gmem(j.state);
   return j;
 }
@@ -1142,6 +1164,39 @@ __global__ void k_cast_add64(long n, const TS* __restrict__ a, double* __restric
   if (state && done_flag(state)) return;
   const long i = long(blockIdx.x) * kBlock + threadIdx.x;
   if (i < n) b[i] += ld<double>(a, i);
+}
+
+// Between two V-cycles of one application (nu > 1 cycles, each on the residual
+// the cycles before it leave) for the slab operators L_s of the job's family:
+//   b_s <- b_s - L_s y_s   (y = x with NU_RES_X, y = o with NU_RES_O)
+//   o_s <- o_s + x_s  or  t_s <- t_s + x_s (float64)   (NU_ADD)
+// b is read and written at the point only; y and x are only read.
+template <int D, typename TS, typename TC>
+__global__ void __launch_bounds__(kBlock) k_nu_step(const NuJob* __restrict__ jobs, int njobs, int mode) {
+  const int jx = find_job(jobs, njobs);
+  const NuJob J = to_global(jobs[jx]);
+  if (J.state && done_flag(J.state)) return;
+  const long k = (block_id() - J.block0) * kBlock + threadIdx.x;
+  if (k >= J.total) return;
+  const Geom g = J.g;
+  const int s = int(k / g.npts);
+  const long i = k - long(s) * g.npts;
+  TS* b = (TS*)J.b;
+  const TS* x = (const TS*)J.x;
+  TS* o = (TS*)J.o;
+  if (mode & (NU_RES_X | NU_RES_O)) {
+    int px, py, pz;
+    decode<D>(i, g.n, px, py, pz);
+    const SlabOp<TC> op = level_op<TC>(J.op, s);
+    const TS* ys = ((mode & NU_RES_X) ? x : o) + long(s) * g.npts;
+    TC dg, off;
+    stencil<D, TC>(ys, i, px, py, pz, g, (const TC*)J.op.kap, op, J.op.R, dg, off);
+    st<TS, TC>(b, k, ld<TC>(b, k) - (dg * ld<TC>(ys, i) - off));
+  }
+  if (mode & NU_ADD) {
+    if (o) st<TS, TC>(o, k, ld<TC>(o, k) + ld<TC>(x, k));
+    if (J.t) J.t[k] += ld<double>(x, k);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -12,6 +12,7 @@ from .workloads import (  # noqa: F401
     heat2d_gaussians,
     heat3d_lognormal,
     heat3d_sine,
+    heat2d_sine,
     batch2d,
     lognormal_field,
     manufactured_u,

@@ -316,6 +316,16 @@ def small_problem(dim: int, n: int, N: int, seed: int = 7, T: float = 1.0, R: in
                    steps=None if steps is None else np.asarray(steps, dtype=np.float64))
 
 
+def heat2d_sine(n: int = 63, N: int = 512, T: float = 1.0) -> Problem:
+    """The 2-D problem of the paper's robustness study (Section 8.2) in
+    finite-difference form: kappa = 1, T = 1, F = 0, u0 = sin(pi x) sin(pi y);
+    n = 2^k - 1 interior nodes per axis is the mesh h = 2^-k."""
+    s = np.sin(np.pi * _interior(n))
+    u0 = _outer([s, s])
+    return Problem(2, n, N, T, np.ones((1, n + 2, n + 2)), np.ones((1, N)), np.zeros((N, n, n)), u0,
+                   name="heat2d_sine", seed=0)
+
+
 def heat3d_sine(n: int = 15, N: int = 16, T: float = 0.1) -> Problem:
     """The 3-D test problem of the paper's time-parallel experiments (Section
     8.3) in finite-difference form: kappa = 1, T = 0.1, exact solution

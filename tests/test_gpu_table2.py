@@ -1,0 +1,77 @@
+"""The robustness study of Section 8.2 (Table 2) on the GPU, in
+finite-difference form: 2-D heat equation, T = 1, u(0) = sin(pi x) sin(pi y),
+F = 0, omega = 0.9, h = 2^-k.  For each (h, N) the count is the first Uzawa
+iteration j whose GPU iterate u_j has ||u - u_j||_S < 1e-6 ||u||_S, with u the
+sequential implicit Euler solution and the S-norm of Theorem 6.2 (both from
+the oracle).  The counts must not grow with 1/h or N.  The default run covers
+h = 1/8, 1/32 and N = 128, 512; STP_SLOW=1 runs h = 1/8 .. 1/64 and
+N = 128 .. 1024."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import euler, spacetime as st
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SLOW = os.environ.get("STP_SLOW", "0") == "1"
+NS = (7, 15, 31, 63) if SLOW else (7, 31)
+STEPS = (128, 256, 512, 1024) if SLOW else (128, 512)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test collected without a GPU")
+    import paper_1802_08126_amd as stp
+    stp.load()
+    yield
+
+
+def gpu_count(prob, ue, scale, nu, guess):
+    """First j with the relative S-norm error of the GPU iterate below 1e-6,
+    searched from ``guess`` (each iterate from a fresh solve of j iterations)."""
+    import paper_1802_08126_amd as stp
+    cache = {}
+
+    def err(j):
+        if j not in cache:
+            s = stp.from_problem(prob, spatial="mg", omega=0.9, tol=0.0, max_iter=j, nu_A=nu, nu_H=nu)
+            u, _, info = s.solve()
+            assert info["iters"] == j
+            torch.cuda.synchronize()
+            cache[j] = st.s_norm(prob, ue - u.cpu().numpy()) / scale
+            s.close()
+        return cache[j]
+
+    j = guess
+    while err(j) >= 1e-6:
+        j += 1
+        assert j < 3 * guess, "no convergence"
+    while j > 1 and err(j - 1) < 1e-6:
+        j -= 1
+    return j, cache
+
+
+# two cycles of this multigrid (contraction about 0.1 on tau A) stay inside
+# the range the paper prints (20-22); one cycle (about 0.3) needs more
+# iterations, equally many for every h and N within a spread of three
+@pytest.mark.parametrize("nu,lo,hi,spread", [(2, 20, 22, 2), (1, 30, 40, 3)])
+def test_table2_counts_flat_in_h_and_N(nu, lo, hi, spread):
+    counts = {}
+    for n in NS:
+        for N in STEPS:
+            prob = synth.heat2d_sine(n, N)
+            ue = euler.seq_euler(prob)
+            scale = st.s_norm(prob, ue)
+            j, errs = gpu_count(prob, ue, scale, nu, guess=lo + 2)
+            counts[(n, N)] = j
+            print(f"table2 nu={nu} h=1/{n + 1} N={N}: {j} iterations "
+                  f"(err {errs[j - 1]:.2e} -> {errs[j]:.2e})", flush=True)
+    vals = np.array(list(counts.values()))
+    assert vals.min() >= lo and vals.max() <= hi, counts
+    assert vals.max() - vals.min() <= spread, counts

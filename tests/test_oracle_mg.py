@@ -108,3 +108,19 @@ def test_vcycle_contraction_mesh_independent(d):
 def test_hierarchy_requires_odd_levels():
     with pytest.raises(ValueError):
         mg.Hierarchy(np.ones((1, 12, 12)), 10, 2)
+
+
+@pytest.mark.parametrize("nu", [2, 3])
+def test_nu_cycles_iterate_the_error_propagator(nu):
+    """nu cycles, each on the residual the earlier ones leave, give
+    x = (I - (I - V L)^nu) L^{-1} b with V the dense single cycle."""
+    d, n, sigma = 2, 7, 0.4
+    prob = synth.small_problem(d, n, 2, seed=13)
+    hier = mg.Hierarchy(prob.kfields, n, d)
+    c = np.array([0.05, 0.02])
+    V, L = _dense_vcycle(hier, sigma, c)
+    E = np.eye(L.shape[0]) - V @ L
+    b = np.random.default_rng(nu).standard_normal((1,) + (n,) * d)
+    want = (np.eye(L.shape[0]) - np.linalg.matrix_power(E, nu)) @ np.linalg.solve(L, b.ravel())
+    got = hier.vcycles(np.array([sigma]), c[None, :], b, nu)
+    assert np.allclose(got.ravel(), want, rtol=1e-10, atol=1e-12 * np.abs(want).max())

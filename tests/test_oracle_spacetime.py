@@ -168,3 +168,18 @@ def test_manufactured_source_has_closed_form_solution():
     ue = euler.seq_euler(prob)
     us = np.multiply.outer(e[1:], S)
     assert np.abs(ue - us).max() < 1e-13 * np.abs(us).max()
+
+
+@pytest.mark.parametrize("d,n,N", [(1, 5, 7), (2, 3, 4)])
+def test_s_norm_matches_dense_S(d, n, N):
+    """The matrix-free ||v||_S equals sqrt(v^T S v) with S assembled densely
+    (eq. (2.5)), also with non-uniform steps."""
+    steps = synth.graded_steps(N, 1.0, ratio=5.0, jitter=0.2, seed=n)
+    for st_ in (None, steps):
+        prob = synth.heat1d_random(n=n, N=N, seed=4, steps=st_) if d == 1 else \
+            synth.small_problem(d, n, N, seed=4, steps=st_)
+        M, Al, taus, Aref = st.fd_dense_pieces(prob)
+        S = st.dense_system(M, Al, taus)["S"]
+        v = np.random.default_rng(2).standard_normal((N,) + (n,) * d)
+        want = np.sqrt(v.ravel() @ S @ v.ravel())
+        assert abs(st.s_norm(prob, v) - want) <= 1e-11 * want
