@@ -123,3 +123,32 @@ def test_nu_out_of_range():
         with pytest.raises(stp.StpError) as ex:
             stp.from_problem(prob, nu_A=bad[0], nu_H=bad[1])
         assert ex.value.status == stp.STP_EINVAL
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_mixed_precision_nu2_reaches_euler(prec):
+    """Two cycles per application with float32 / bfloat16 storage: the
+    float64 outer iteration still reaches the sequential implicit Euler
+    solution to 1e-8 relative."""
+    import paper_1802_08126_amd as stp
+    from oracle import euler
+    prob = make(3, 15, 16, 2, seed=37)
+    s = stp.from_problem(prob, precision=prec, omega=0.0, tol=1e-10, max_iter=600, nu_A=2, nu_H=2)
+    u, _, info = s.solve()
+    assert info["status"] == stp.STP_OK, info
+    ue = euler.seq_euler(prob)
+    assert relmax(host(u), ue) < 1e-8
+    s.close()
+
+
+def test_nu2_with_graded_steps():
+    """Non-uniform steps (per-slab tau_n in the A~ cycles and in the steps
+    between them): Uzawa iterates against the oracle."""
+    import paper_1802_08126_amd as stp
+    steps = synth.graded_steps(12, 1.0, ratio=4.0, jitter=0.3, seed=38)
+    prob = synth.small_problem(2, 31, 12, seed=38, R=2, steps=steps)
+    s = stp.from_problem(prob, omega=0.6, tol=0.0, max_iter=4, nu_A=2, nu_H=3)
+    u, p, _ = s.solve()
+    ref = uzawa.uzawa_fixed(prob, 4, omega=0.6, spatial="mg", nu_A=2, nu_H=3)
+    assert relmax(host(u), ref["u"]) < 1e-11 and relmax(host(p), ref["p"]) < 1e-11
+    s.close()
