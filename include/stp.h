@@ -108,7 +108,11 @@ typedef struct {
                               reference step of eq. (2.2) used by H-tilde (<= 0: the mean
                               of tau_n), A = diag(tau_n A_n), f_n = tau_n F_n (+ u0), and
                               without kref_coef kappa_ref is the step-weighted time mean
-                              sum_n tau_n kappa(t_n) / sum_n tau_n.  Single problems only. */
+                              sum_n tau_n kappa(t_n) / sum_n tau_n.  For stp_create_batch:
+                              the steps of every problem, one problem after the other
+                              (N[0] + ... + N[P-1] values; a problem with uniform steps
+                              lists N[i] copies of its tau), and each tau[i] <= 0 selects
+                              the mean of problem i's own steps.                         */
 } stp_options;
 
 typedef struct {

@@ -187,6 +187,8 @@ def stp_create(dim, n, N, tau, kfields, tcoef, F, u0, workspace=None, stream=Non
     up = _dev_f64(u0, (n,) * dim, "u0")
     if kfields.numel() != R * (n + 2) ** dim or F.numel() != N * npts or u0.numel() != npts:
         raise ValueError("kfields/F/u0 sizes do not match (dim, n, N, rank)")
+    if opts.get("tau_steps") is not None and len(opts["tau_steps"]) != N:
+        raise ValueError(f"tau_steps must hold N = {N} step lengths, got {len(opts['tau_steps'])}")
     o, keep = make_options(**opts)
     g = stp_grid(dim, n)
     tc = tcoef.ctypes.data_as(C.POINTER(C.c_double))
@@ -213,7 +215,9 @@ def stp_workspace_bytes_batch(specs, **opts) -> int:
 
 def stp_create_batch(problems, workspace=None, stream=None, **opts):
     """problems: list of dicts with keys dim, n, N, tau, kfields, tcoef, F, u0 (as in
-    stp_create).  Returns (ctx handle, keepalive tuple)."""
+    stp_create) and optionally steps (N step lengths; tau is then the reference
+    step).  Without a tau_steps option the steps of the problems that give them
+    (N copies of tau for the others) form it.  Returns (ctx handle, keepalive tuple)."""
     lib = load()
     P = len(problems)
     if P < 1:
@@ -243,6 +247,12 @@ def stp_create_batch(problems, workspace=None, stream=None, **opts):
         Fs[i] = _dev_f64(F, (N,) + (n,) * dim, "F").value
         u0s[i] = _dev_f64(u0, (n,) * dim, "u0").value
         keep.append((kf, F, u0, tcoef))
+    total = sum(q["N"] for q in problems)
+    if opts.get("tau_steps") is None and any(q.get("steps") is not None for q in problems):
+        opts["tau_steps"] = [float(v) for q in problems
+                             for v in (q["steps"] if q.get("steps") is not None else [q["tau"]] * q["N"])]
+    if opts.get("tau_steps") is not None and len(opts["tau_steps"]) != total:
+        raise ValueError(f"tau_steps must hold sum(N) = {total} step lengths, got {len(opts['tau_steps'])}")
     o, okeep = make_options(**opts)
     ctx = C.c_void_p()
     ws_ptr, ws_bytes = None, 0
@@ -515,8 +525,11 @@ def problem_dict(prob, device="cuda"):
     """Device copy of a ``synth.Problem`` in the form stp_create_batch takes."""
     import torch
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)  # noqa: E731
-    return dict(dim=prob.dim, n=prob.n, N=prob.N, tau=prob.tau, kfields=t(prob.kfields), tcoef=prob.tcoef,
-                F=t(prob.F), u0=t(prob.u0))
+    d = dict(dim=prob.dim, n=prob.n, N=prob.N, tau=prob.tau, kfields=t(prob.kfields), tcoef=prob.tcoef,
+             F=t(prob.F), u0=t(prob.u0))
+    if getattr(prob, "steps", None) is not None:
+        d["steps"] = list(prob.steps)
+    return d
 
 
 def from_problem(prob, device="cuda", **opts):

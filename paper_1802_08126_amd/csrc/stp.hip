@@ -1812,17 +1812,25 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
   stp_status s = validate_opts(&opt);
   if (s != STP_OK) return s;
   if (opt.kref_coef && P > 1) return fail(STP_EINVAL, "kref_coef must be NULL for a batch of more than one problem");
-  if (opt.tau_steps && P > 1) return fail(STP_EINVAL, "tau_steps must be NULL for a batch of more than one problem");
-  // non-uniform steps: tau is the reference step of eq. (2.2), <= 0 for their mean
+  // non-uniform steps (every problem's, one after the other): tau[i] is the
+  // reference step of eq. (2.2), <= 0 for the mean of problem i's steps
   std::vector<double> tref(tau, tau + P);
+  std::vector<long> toff(P, 0);
   if (opt.tau_steps) {
-    double sum = 0;
-    for (int n = 0; n < N[0]; ++n) {
-      const double t = opt.tau_steps[n];
-      if (!(t > 0) || !std::isfinite(t)) return fail(STP_EINVAL, "tau_steps[%d] must be finite and > 0", n);
-      sum += t;
+    long off = 0;
+    for (int i = 0; i < P; ++i) {
+      if (N[i] < 1) return fail(STP_EINVAL, "problem %d: N must be >= 1", i);
+      toff[i] = off;
+      double sum = 0;
+      for (int n = 0; n < N[i]; ++n) {
+        const double t = opt.tau_steps[off + n];
+        if (!(t > 0) || !std::isfinite(t))
+          return fail(STP_EINVAL, "tau_steps[%ld] (problem %d, step %d) must be finite and > 0", off + n, i, n);
+        sum += t;
+      }
+      if (!(tref[i] > 0)) tref[i] = sum / N[i];
+      off += N[i];
     }
-    if (!(tref[0] > 0)) tref[0] = sum / N[0];
   }
   for (int i = 0; i < P; ++i)
     if ((s = validate_one(&grids[i], N[i], tref[i], &kappa[i], F[i], u0[i], &opt)) != STP_OK) return s;
@@ -1836,7 +1844,7 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
     q.omega_auto = !(opt.omega > 0);
     q.omega = q.omega_auto ? 0.8 : opt.omega;   // replaced by the estimate below when automatic
     q.tcoef.assign(kappa[i].tcoef, kappa[i].tcoef + size_t(q.R) * q.N);
-    if (opt.tau_steps) q.taus.assign(opt.tau_steps, opt.tau_steps + q.N);
+    if (opt.tau_steps) q.taus.assign(opt.tau_steps + toff[i], opt.tau_steps + toff[i] + q.N);
     else q.taus.assign(q.N, q.tau);
     q.abar.assign(q.R, 0.0);
     if (opt.kref_coef) {

@@ -1,6 +1,7 @@
 """GPU parity with non-uniform time steps tau_n (Section 2; the tau_steps
 option): Uzawa and GMRES iterates against the oracle, convergence to the
-sequential implicit Euler solution, and argument checks."""
+sequential implicit Euler solution, batches of problems with their own
+steps, and argument checks."""
 import numpy as np
 import pytest
 
@@ -106,5 +107,30 @@ def test_reference_step_defaults_to_mean_and_checks():
     bad[3] = 0.0
     with pytest.raises(stp.StpError):
         stp.SpaceTimeSolver(2, 15, 8, 0.0, kf, prob.tcoef, F, u0, tau_steps=bad)
-    with pytest.raises(stp.StpError):
+    with pytest.raises(ValueError):      # a batch takes the steps of every problem
         stp.BatchSolver([stp.problem_dict(prob), stp.problem_dict(prob)], tau_steps=list(prob.steps))
+
+
+def test_batch_with_per_problem_steps():
+    """A batch whose problems have their own step lengths (one of them
+    uniform): each problem's iterates equal its single-problem context's
+    bitwise and the oracle's; a bad step of a later problem is rejected."""
+    import paper_1802_08126_amd as stp
+    probs = [graded(2, 15, 16, 2, seed=85), synth.small_problem(2, 31, 8, seed=86, R=1),
+             graded(2, 31, 12, 3, ratio=4.0, seed=87)]
+    b = stp.BatchSolver([stp.problem_dict(q) for q in probs], omega=0.6, tol=0.0, max_iter=4)
+    us, ps, infos, _ = b.solve()
+    for k, (q, u, p) in enumerate(zip(probs, us, ps)):
+        print(f"case batch problem {k}", flush=True)
+        s = stp.from_problem(q, omega=0.6, tol=0.0, max_iter=4)
+        u1, p1, _ = s.solve()
+        assert np.array_equal(host(u), host(u1)) and np.array_equal(host(p), host(p1))
+        s.close()
+        ref = uzawa.uzawa_fixed(q, 4, omega=0.6, spatial="mg")
+        assert relmax(host(u), ref["u"]) < 1e-11 and relmax(host(p), ref["p"]) < 1e-11
+    b.close()
+    bad = [stp.problem_dict(q) for q in probs]
+    bad[2]["steps"][5] = -1.0
+    with pytest.raises(stp.StpError) as e:
+        stp.BatchSolver(bad)
+    assert e.value.status == stp.STP_EINVAL
