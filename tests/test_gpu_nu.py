@@ -152,3 +152,16 @@ def test_nu2_with_graded_steps():
     ref = uzawa.uzawa_fixed(prob, 4, omega=0.6, spatial="mg", nu_A=2, nu_H=3)
     assert relmax(host(u), ref["u"]) < 1e-11 and relmax(host(p), ref["p"]) < 1e-11
     s.close()
+
+
+def test_autotuned_schedule_with_nu2():
+    """The autotuner rebuilds every launch table, the steps between cycles
+    included: the tuned context still gives the oracle's iterates."""
+    import paper_1802_08126_amd as stp
+    prob = make(2, 63, 16, 2, seed=39)
+    s = stp.from_problem(prob, omega=0.7, tol=0.0, max_iter=4, nu_A=2, nu_H=2)
+    s.autotune(reps=1, use_cache=False)
+    u, p, _ = s.solve()
+    ref = uzawa.uzawa_fixed(prob, 4, omega=0.7, spatial="mg", nu_A=2, nu_H=2)
+    assert relmax(host(u), ref["u"]) < 1e-11 and relmax(host(p), ref["p"]) < 1e-11
+    s.close()
