@@ -165,3 +165,17 @@ def test_autotuned_schedule_with_nu2():
     ref = uzawa.uzawa_fixed(prob, 4, omega=0.7, spatial="mg", nu_A=2, nu_H=2)
     assert relmax(host(u), ref["u"]) < 1e-11 and relmax(host(p), ref["p"]) < 1e-11
     s.close()
+
+
+def test_exact_solves_ignore_nu():
+    """Exact 1-D spatial solves need one application: nu > 1 gives bitwise the
+    iterates of nu = 1 (no extra buffer, no extra launches)."""
+    import paper_1802_08126_amd as stp
+    prob = synth.heat1d_random(n=63, N=32, seed=40)
+    a = stp.from_problem(prob, spatial="exact", omega=0.7, tol=0.0, max_iter=3)
+    b = stp.from_problem(prob, spatial="exact", omega=0.7, tol=0.0, max_iter=3, nu_A=3, nu_H=2)
+    ua, pa, _ = a.solve()
+    ub, pb, _ = b.solve()
+    assert np.array_equal(host(ua), host(ub)) and np.array_equal(host(pa), host(pb))
+    a.close()
+    b.close()
