@@ -289,12 +289,13 @@ struct VCycle {
   Site<PointJob> tri;                    // exact 1-D solves
 };
 
-// VC_AX, VC_HX: the A and H cycles with their output stored to Xnu (nu > 1)
-enum { VC_A = 0, VC_H1 = 1, VC_H2 = 2, VC_AX = 3, VC_HX = 4 };
+// VC_AX, VC_HX: the A and H cycles with their output stored to Xnu; VC_HA: the
+// H cycle adding its result into its output (the last of nu > 1 H cycles)
+enum { VC_A = 0, VC_H1 = 1, VC_H2 = 2, VC_AX = 3, VC_HX = 4, VC_HA = 5 };
 
 struct Sites {
   Site<ResidJob> resid[2];
-  VCycle vc[5];
+  VCycle vc[6];
   Site<NuJob> nu[2];     // steps between the cycles of an application with nu > 1 (A, H)
   Site<TileJob> mid;
   std::vector<Site<TimeJob>> a4, a6;
@@ -545,8 +546,9 @@ struct VTop {
   double* acc64;   // float64 accumulation target (or null)
 };
 
-// acc: the finest up-sweep adds into the float64 targets (else stores)
-void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top, bool acc) {
+// acc: the finest up-sweep adds into the float64 targets (else stores);
+// addout: the stored result is added into the output instead
+void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top, bool acc, bool addout = false) {
   int Lmax = 0;
   for (auto& q : c->pr) Lmax = std::max(Lmax, int(q.lv.size()));
   vc.down.assign(std::max(0, Lmax - 1), Site<TileJob>());
@@ -592,6 +594,7 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top,
       u.e = q.lv[l + 1].e;
       u.out = (l == 0) ? T.out : q.lv[l].e;
       u.acc64 = (l == 0) ? T.acc64 : nullptr;
+      u.addout = (l == 0 && addout) ? 1 : 0;
       u.state = d.state;
       u.tiles = int(tiles_up_d(q.dim, q.lv[l].n));
       u.sb = sched_sb(u.tiles, q.N, (l == 0 && acc) ? c->sched.e[KN_UPA0] : c->sched.e[KN_UP0 + l]);
@@ -609,6 +612,7 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top,
     fj.b = (ft == 0) ? T.in : q.lv[ft].b;
     fj.out = (ft == 0) ? T.out : q.lv[ft].e;
     fj.acc64 = (ft == 0) ? T.acc64 : nullptr;
+    fj.addout = (ft == 0 && addout) ? 1 : 0;
     fj.state = &q.state->done;
     Site<FuseJob>& fs = vc.fused[ft];
     fs.add(fj, q.N);
@@ -743,6 +747,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
   build_vcycle(c, S.vc[VC_H2], 1, topH, false);
   S.vc[VC_AX] = VCycle();
   S.vc[VC_HX] = VCycle();
+  S.vc[VC_HA] = VCycle();
   S.nu[0] = Site<NuJob>();
   S.nu[1] = Site<NuJob>();
   if (multi_cycle(c)) {
@@ -751,13 +756,15 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
       Problem& q = c->pr[i];
       topAX[i] = VTop{q.W1, q.Xnu, nullptr};
       topHX[i] = VTop{q.W2, q.Xnu, nullptr};
-      const long total = long(q.N) * q.g0.npts;
-      const long nb = (total + kBlock - 1) / kBlock;
-      S.nu[0].add(NuJob{0, q.g0, family_op(q, 0, 0), total, q.W1, q.Xnu, nullptr, p[i], &q.state->done}, nb);
-      S.nu[1].add(NuJob{0, q.g0, family_op(q, 0, 1), total, q.W2, q.Xnu, q.W1, nullptr, &q.state->done}, nb);
+      const int pb = int((q.g0.npts + kBlock - 1) / kBlock);
+      const int sb = pick_sb(pb, q.N);
+      const long nb = long(pb) * ((q.N + sb - 1) / sb);
+      S.nu[0].add(NuJob{0, q.g0, family_op(q, 0, 0), pb, sb, q.W1, q.Xnu, nullptr, p[i], &q.state->done}, nb);
+      S.nu[1].add(NuJob{0, q.g0, family_op(q, 0, 1), pb, sb, q.W2, q.Xnu, q.W1, nullptr, &q.state->done}, nb);
     }
     build_vcycle(c, S.vc[VC_AX], 0, topAX, false);
     build_vcycle(c, S.vc[VC_HX], 1, topHX, false);
+    build_vcycle(c, S.vc[VC_HA], 1, topH, false, true);
   }
   S.mid = Site<TileJob>();
   for (size_t i = 0; i < P; ++i) {
@@ -1045,8 +1052,8 @@ struct Solver : SolverBase {
   // nu_A (A) or nu_H (H1, H2) cycles, each on the residual the ones before
   // it leave (multigrid only; exact solves need one).  A: cycles 1..nu-1 store
   // to Xnu, then b -= L Xnu and p += Xnu, and the last cycle adds into p.
-  // H: the first cycle stores the output o, b -= L o, then each further cycle
-  // stores to Xnu and o += Xnu (b -= L Xnu if another follows).  The steps
+  // H: the first cycle stores the output o, b -= L o, each middle cycle stores
+  // to Xnu, then o += Xnu and b -= L Xnu, and the last cycle adds into o.  The steps
   // read their operands from job tables, so captured graphs follow a rebinding
   // of the A target as the cycles do.
   stp_status run_vcycle(int which) override {
@@ -1064,11 +1071,11 @@ struct Solver : SolverBase {
     }
     if ((st = run_cycle(c->sites.vc[which])) != STP_OK) return st;
     if ((st = nu_step(fam, NU_RES_O)) != STP_OK) return st;
-    for (int k = 1; k < nu; ++k) {
+    for (int k = 1; k + 1 < nu; ++k) {
       if ((st = run_cycle(vx)) != STP_OK) return st;
-      if ((st = nu_step(fam, NU_ADD | (k + 1 < nu ? NU_RES_X : 0))) != STP_OK) return st;
+      if ((st = nu_step(fam, NU_ADD | NU_RES_X)) != STP_OK) return st;
     }
-    return STP_OK;
+    return run_cycle(c->sites.vc[VC_HA]);
   }
 
   stp_status nu_step(int fam, int mode) {
@@ -1077,9 +1084,19 @@ struct Solver : SolverBase {
     c->kt.level = 0;
     const dim3 gr(unsigned(s.blocks)), bl(kBlock);
     const int nj = int(s.jobs.size());
-    if (c->dim == 1) KLAUNCH_NAMED("k_nu_step", (k_nu_step<1, TS, TC>), gr, bl, 0, c->stream, s.dev, nj, mode);
-    else if (c->dim == 2) KLAUNCH_NAMED("k_nu_step", (k_nu_step<2, TS, TC>), gr, bl, 0, c->stream, s.dev, nj, mode);
-    else KLAUNCH_NAMED("k_nu_step", (k_nu_step<3, TS, TC>), gr, bl, 0, c->stream, s.dev, nj, mode);
+#define STP_NU(D_, RM_) KLAUNCH_NAMED("k_nu_step", (k_nu_step<D_, TS, TC, RM_>), gr, bl, 0, c->stream, s.dev, nj, mode)
+    switch (c->dim * 10 + c->rm) {
+      case 11: STP_NU(1, 1); break;
+      case 12: STP_NU(1, 2); break;
+      case 14: STP_NU(1, 4); break;
+      case 21: STP_NU(2, 1); break;
+      case 22: STP_NU(2, 2); break;
+      case 24: STP_NU(2, 4); break;
+      case 31: STP_NU(3, 1); break;
+      case 32: STP_NU(3, 2); break;
+      default: STP_NU(3, 4);
+    }
+#undef STP_NU
     LAUNCH_CHECK();
     return STP_OK;
   }

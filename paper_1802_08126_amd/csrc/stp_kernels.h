@@ -414,6 +414,7 @@ struct TileJob {        // multigrid level kernels and the tile operator
   void* out;            // output (TS)
   double* acc64;        // float64 target of EPI_ADD64
   const int* state;     // the problem's stop flag
+  int addout;           // EPI_STORE at the top level: 1 adds the result into out
 };
 
 struct PointJob {       // exact 1-D solves
@@ -432,7 +433,8 @@ struct NuJob {          // steps between the cycles of one application (nu > 1)
   long block0;
   Geom g;
   LevelOp op;           // level-0 operator of the cycles' family
-  long total;           // slabs x points
+  int pblocks;          // blocks per slab run: ceil(points / kBlock)
+  int sb;               // slabs per block
   void* b;              // cycle input, turned into the remaining residual in place (TS)
   void* x;              // the correction of the last cycle (TS)
   void* o;              // H family: the stored output (TS), else null
@@ -1170,32 +1172,67 @@ __global__ void k_cast_add64(long n, const TS* __restrict__ a, double* __restric
 // the cycles before it leave) for the slab operators L_s of the job's family:
 //   b_s <- b_s - L_s y_s   (y = x with NU_RES_X, y = o with NU_RES_O)
 //   o_s <- o_s + x_s  or  t_s <- t_s + x_s (float64)   (NU_ADD)
-// b is read and written at the point only; y and x are only read.
-template <int D, typename TS, typename TC>
+// A thread owns one spatial point for a run of sb slabs: the raw nodal fields
+// of its stencil are loaded once into registers and mixed per slab with the
+// slab's coefficient row.  b is read and written at the point only; y and x
+// are only read.
+template <int D, typename TS, typename TC, int RM>
 __global__ void __launch_bounds__(kBlock) k_nu_step(const NuJob* __restrict__ jobs, int njobs, int mode) {
-  const int jx = find_job(jobs, njobs);
-  const NuJob J = to_global(jobs[jx]);
+  const NuJob J = to_global(jobs[find_job(jobs, njobs)]);
   if (J.state && done_flag(J.state)) return;
-  const long k = (block_id() - J.block0) * kBlock + threadIdx.x;
-  if (k >= J.total) return;
+  const int lb = int(block_id() - J.block0);
+  const int run = lb / J.pblocks;
   const Geom g = J.g;
-  const int s = int(k / g.npts);
-  const long i = k - long(s) * g.npts;
+  const long i = long(lb - run * J.pblocks) * kBlock + threadIdx.x;
+  if (i >= g.npts) return;
+  const LevelOp L = J.op;
+  const int s0 = run * J.sb, s1 = min(L.S, s0 + J.sb);
   TS* b = (TS*)J.b;
   const TS* x = (const TS*)J.x;
   TS* o = (TS*)J.o;
-  if (mode & (NU_RES_X | NU_RES_O)) {
-    int px, py, pz;
-    decode<D>(i, g.n, px, py, pz);
-    const SlabOp<TC> op = level_op<TC>(J.op, s);
-    const TS* ys = ((mode & NU_RES_X) ? x : o) + long(s) * g.npts;
-    TC dg, off;
-    stencil<D, TC>(ys, i, px, py, pz, g, (const TC*)J.op.kap, op, J.op.R, dg, off);
-    st<TS, TC>(b, k, ld<TC>(b, k) - (dg * ld<TC>(ys, i) - off));
+  const bool res = (mode & (NU_RES_X | NU_RES_O)) != 0;
+  const TS* y = (mode & NU_RES_X) ? x : o;
+  // stencil geometry and raw fields: centre node, then the 2d faces (x-, x+, y-, y+, z-, z+)
+  int px = 0, py = 0, pz = 0;
+  decode<D>(i, g.n, px, py, pz);
+  const int n = g.n;
+  const long nn = n + 2;
+  const long node = node_of<D>(px, py, pz, n);
+  const long dnode[6] = {-1, 1, -nn, nn, -nn * nn, nn * nn};
+  const long di[6] = {-1, 1, -long(n), long(n), -long(n) * n, long(n) * n};
+  bool inside[6] = {px > 0, px < n - 1, py > 0, py < n - 1, pz > 0, pz < n - 1};
+  const TC* kap = (const TC*)L.kap;
+  TC kc[RM], kf[2 * D][RM];
+#pragma unroll
+  for (int r = 0; r < RM; ++r) {
+    const bool ok = res && r < L.R;
+    kc[r] = ok ? kap[r * g.nnodes + node] : TC(0);
+#pragma unroll
+    for (int f = 0; f < 2 * D; ++f) kf[f][r] = ok ? kap[r * g.nnodes + node + dnode[f]] : TC(0);
   }
-  if (mode & NU_ADD) {
-    if (o) st<TS, TC>(o, k, ld<TC>(o, k) + ld<TC>(x, k));
-    if (J.t) J.t[k] += ld<double>(x, k);
+  for (int s = s0; s < s1; ++s) {
+    const long k = long(s) * g.npts + i;
+    if (res) {
+      const SlabOp<TC> op = level_op<TC>(L, s);
+      TC kcs = op.c[0] * kc[0];
+#pragma unroll
+      for (int r = 1; r < RM; ++r) kcs += op.c[r] * kc[r];
+      const TS* ys = y + long(s) * g.npts;
+      TC dg = op.sigma, off = 0;
+#pragma unroll
+      for (int f = 0; f < 2 * D; ++f) {
+        TC w = kcs;
+#pragma unroll
+        for (int r = 0; r < RM; ++r) w += op.c[r] * kf[f][r];
+        dg += w;
+        if (inside[f]) off += w * ld<TC>(ys, i + di[f]);
+      }
+      st<TS, TC>(b, k, ld<TC>(b, k) - (dg * ld<TC>(ys, i) - off));
+    }
+    if (mode & NU_ADD) {
+      if (o) st<TS, TC>(o, k, ld<TC>(o, k) + ld<TC>(x, k));
+      if (J.t) J.t[k] += ld<double>(x, k);
+    }
   }
 }
 

@@ -599,7 +599,7 @@ __device__ __forceinline__ void mg_up_body(const TileJob& J, int tile, int s0, i
                                          : diag_at_k<D, KB, TC>(sk, kq, op.sigma));
       const TC v = one_m_omega * sx[xq] + wd * (sb_[xq] + off);
       const int vo = vec_off<D>(jx, jy, jz, nf);
-      if (EPI == EPI_STORE) st<TS, TC>(os, vo, v);
+      if (EPI == EPI_STORE) st<TS, TC>(os, vo, J.addout ? ld<TC>(os, vo) + v : v);
       else as[vo] += double(v);
     }
     __syncthreads();   // sk and se are rewritten for the next slab
@@ -643,6 +643,7 @@ struct FuseJob {
   void* out;                    // top-level result (TS), or
   double* acc64;                // float64 accumulation target
   const int* state;
+  int addout;                   // EPI_STORE: 1 adds the result into out
 };
 
 __device__ __forceinline__ FuseJob to_global(FuseJob j) {
@@ -835,7 +836,7 @@ __device__ __forceinline__ void mg_fused_body(const FuseJob* __restrict__ jp, co
     for (int q = t; q < cnt; q += nt) {
       int x, y, z;
       const TC v = lds[oy + fuse_node_of<D>(q, n, x, y, z)];
-      if (EPI == EPI_STORE) st<TS, TC>(out, ob + q, v);
+      if (EPI == EPI_STORE) st<TS, TC>(out, ob + q, J.addout ? ld<TC>(out, ob + q) + v : v);
       else acc64[ob + q] += double(v);
     }
   }
