@@ -192,6 +192,24 @@ def gpu_run(args):
             progress(f"{prec}: gmres to tol", f"{gi['iters']} steps {t1 - t0:.3f}s")
             del ws
             s.close()
+            # the same stop test with two V-cycles per H~_k^{-1} (nu_H = 2; second of two runs)
+            s = stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0,
+                                    precision=prec, omega=args.omega, tol=args.tol, max_iter=2000,
+                                    check_every=args.check_every, nu_H=2)
+            if tune is not None:
+                s.autotune(use_cache=True)
+            for _ in range(2):
+                u.zero_()
+                p.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, info = s.solve(u, p)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+            results[prec]["tol_nuH2"] = dict(tol=args.tol, nu_H=2, iters=info["iters"], sec=t1 - t0,
+                                             rel_res=info["rel_res"], status=info["status"], omega=info["omega"])
+            progress(f"{prec}: uzawa nu_H=2 to tol", f"{info['iters']} its {t1 - t0:.3f}s")
+            s.close()
     return prob, dims, results
 
 
@@ -624,7 +642,8 @@ def main():
     out = {
         "metric": "space-time DoF-iterations/sec + time to 1e-8 residual, mixed vs FP64, 1 GPU",
         "metric_note": "value: u DoFs x Uzawa iterations / s, float64; time to 1e-8: time_to_tol_f64 "
-                       "and mixed_f32_precond.time_to_tol",
+                       "and mixed_f32_precond.time_to_tol (one V-cycle per spatial solve, the default); "
+                       "nuH2_time_to_tol_f64 and mixed_f32_precond.nuH2_time_to_tol with two per H-block",
         "value": r64["value"],
         "unit": "DoF-it/s",
         "n_gpus": 1,
@@ -648,6 +667,7 @@ def main():
     if "tol" in r64:
         out["time_to_tol_f64"] = r64["tol"]
         out["gmres_time_to_tol_f64"] = r64["gmres"]
+        out["nuH2_time_to_tol_f64"] = r64["tol_nuH2"]
     if "f32" in res:
         r32 = res["f32"]
         out["mixed_f32_precond"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
@@ -656,6 +676,7 @@ def main():
         if "tol" in r32:
             out["mixed_f32_precond"]["time_to_tol"] = r32["tol"]
             out["mixed_f32_precond"]["gmres_time_to_tol"] = r32["gmres"]
+            out["mixed_f32_precond"]["nuH2_time_to_tol"] = r32["tol_nuH2"]
             if "tol" in r64:
                 out["mixed_f32_precond"]["time_to_tol_speedup"] = r64["tol"]["sec"] / r32["tol"]["sec"]
     if not args.no_batch:

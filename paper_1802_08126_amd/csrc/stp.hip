@@ -297,6 +297,7 @@ struct Sites {
   Site<ResidJob> resid[2];
   VCycle vc[6];
   Site<NuJob> nu[2];     // steps between the cycles of an application with nu > 1 (A, H)
+  Site<TileJob> nures;   // b -= L o after the first of nu_H > 1 H cycles (tiled operator)
   Site<TileJob> mid;
   std::vector<Site<TimeJob>> a4, a6;
   std::vector<FinJob> fin;
@@ -748,6 +749,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
   S.vc[VC_AX] = VCycle();
   S.vc[VC_HX] = VCycle();
   S.vc[VC_HA] = VCycle();
+  S.nures = Site<TileJob>();
   S.nu[0] = Site<NuJob>();
   S.nu[1] = Site<NuJob>();
   if (multi_cycle(c)) {
@@ -765,6 +767,19 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
     build_vcycle(c, S.vc[VC_AX], 0, topAX, false);
     build_vcycle(c, S.vc[VC_HX], 1, topHX, false);
     build_vcycle(c, S.vc[VC_HA], 1, topH, false, true);
+    for (size_t i = 0; i < P; ++i) {
+      Problem& q = c->pr[i];
+      TileJob j{};
+      j.gf = q.g0;
+      j.op = family_op(q, 0, 1);
+      j.b = q.W1;                                // o, the first cycle's result
+      j.out = q.W2;                              // the cycles' right-hand side, reduced in place
+      j.addout = -1;
+      j.state = &q.state->done;
+      j.tiles = int(tiles_up_d(q.dim, q.n));
+      j.sb = sched_sb(j.tiles, q.N, c->sched.e[KN_MID]);
+      S.nures.add(j, long(j.tiles) * ((q.N + j.sb - 1) / j.sb), j.op.cmode != CM_SLAB);
+    }
   }
   S.mid = Site<TileJob>();
   for (size_t i = 0; i < P; ++i) {
@@ -808,6 +823,7 @@ void for_each_site(Sites& S, F&& f) {
   f(S.mid);
   f(S.nu[0]);
   f(S.nu[1]);
+  f(S.nures);
   for (auto& x : S.a4) f(x);
   for (auto& x : S.a6) f(x);
 }
@@ -1011,7 +1027,7 @@ struct Solver : SolverBase {
     switch (knob) {
       case KN_R0: return resid_dr<D, 0, RM>();
       case KN_R1: return resid_dr<D, 1, RM>();
-      case KN_MID: return mid_dr<D, RM>();
+      case KN_MID: return apply_dr<D, RM>(c->sites.mid);
       case KN_UPA0: return up_site<D, RM>(c->sites.vc[VC_A].up[0], 0);
       case KN_FUSE: {
         VCycle& v = c->sites.vc[VC_H1];
@@ -1052,8 +1068,9 @@ struct Solver : SolverBase {
   // nu_A (A) or nu_H (H1, H2) cycles, each on the residual the ones before
   // it leave (multigrid only; exact solves need one).  A: cycles 1..nu-1 store
   // to Xnu, then b -= L Xnu and p += Xnu, and the last cycle adds into p.
-  // H: the first cycle stores the output o, b -= L o, each middle cycle stores
-  // to Xnu, then o += Xnu and b -= L Xnu, and the last cycle adds into o.  The steps
+  // H: the first cycle stores the output o, b -= L o (the tiled operator),
+  // each middle cycle stores to Xnu, then o += Xnu and b -= L Xnu, and the last
+  // cycle adds into o.  The steps
   // read their operands from job tables, so captured graphs follow a rebinding
   // of the A target as the cycles do.
   stp_status run_vcycle(int which) override {
@@ -1070,7 +1087,7 @@ struct Solver : SolverBase {
       return run_cycle(c->sites.vc[which]);
     }
     if ((st = run_cycle(c->sites.vc[which])) != STP_OK) return st;
-    if ((st = nu_step(fam, NU_RES_O)) != STP_OK) return st;
+    if ((st = run_apply(c->sites.nures)) != STP_OK) return st;   // b -= L o
     for (int k = 1; k + 1 < nu; ++k) {
       if ((st = run_cycle(vx)) != STP_OK) return st;
       if ((st = nu_step(fam, NU_ADD | NU_RES_X)) != STP_OK) return st;
@@ -1128,8 +1145,8 @@ struct Solver : SolverBase {
   }
 
   template <int D, int RM>
-  stp_status mid_dr() {
-    Site<TileJob>& s = c->sites.mid;
+  stp_status apply_dr(Site<TileJob>& s) {
+    if (s.jobs.empty()) return STP_OK;
     c->kt.level = 0;
     const dim3 gr(unsigned(s.blocks)), bl(kBlock);
     const int nj = int(s.jobs.size());
@@ -1142,19 +1159,21 @@ struct Solver : SolverBase {
     return STP_OK;
   }
 
-  stp_status run_mid() {
+  stp_status run_apply(Site<TileJob>& s) {
     switch (c->dim * 10 + c->rm) {
-      case 11: return mid_dr<1, 1>();
-      case 12: return mid_dr<1, 2>();
-      case 14: return mid_dr<1, 4>();
-      case 21: return mid_dr<2, 1>();
-      case 22: return mid_dr<2, 2>();
-      case 24: return mid_dr<2, 4>();
-      case 31: return mid_dr<3, 1>();
-      case 32: return mid_dr<3, 2>();
-      default: return mid_dr<3, 4>();
+      case 11: return apply_dr<1, 1>(s);
+      case 12: return apply_dr<1, 2>(s);
+      case 14: return apply_dr<1, 4>(s);
+      case 21: return apply_dr<2, 1>(s);
+      case 22: return apply_dr<2, 2>(s);
+      case 24: return apply_dr<2, 4>(s);
+      case 31: return apply_dr<3, 1>(s);
+      case 32: return apply_dr<3, 2>(s);
+      default: return apply_dr<3, 4>(s);
     }
   }
+
+  stp_status run_mid() { return run_apply(c->sites.mid); }
 
   template <int L1, int L2, int MODE, int ACC>
   stp_status fft2_site(Site<TimeJob>& s) {

@@ -414,7 +414,7 @@ struct TileJob {        // multigrid level kernels and the tile operator
   void* out;            // output (TS)
   double* acc64;        // float64 target of EPI_ADD64
   const int* state;     // the problem's stop flag
-  int addout;           // EPI_STORE at the top level: 1 adds the result into out
+  int addout;           // top-level output: 0 store, 1 add into out (up-sweep), -1 subtract from out (operator)
 };
 
 struct PointJob {       // exact 1-D solves
@@ -441,7 +441,7 @@ struct NuJob {          // steps between the cycles of one application (nu > 1)
   double* t;            // A family: the float64 accumulation target, else null
   const int* state;
 };
-enum NuMode { NU_RES_X = 1, NU_RES_O = 2, NU_ADD = 4 };
+enum NuMode { NU_RES_X = 1, NU_ADD = 2 };
 
 struct TimeJob {        // transforms along the time axis
   long block0;
@@ -1170,12 +1170,12 @@ __global__ void k_cast_add64(long n, const TS* __restrict__ a, double* __restric
 
 // Between two V-cycles of one application (nu > 1 cycles, each on the residual
 // the cycles before it leave) for the slab operators L_s of the job's family:
-//   b_s <- b_s - L_s y_s   (y = x with NU_RES_X, y = o with NU_RES_O)
+//   b_s <- b_s - L_s x_s   (NU_RES_X)
 //   o_s <- o_s + x_s  or  t_s <- t_s + x_s (float64)   (NU_ADD)
 // A thread owns one spatial point for a run of sb slabs: the raw nodal fields
 // of its stencil are loaded once into registers and mixed per slab with the
-// slab's coefficient row.  b is read and written at the point only; y and x
-// are only read.
+// slab's coefficient row.  b is read and written at the point only; x is
+// only read.
 template <int D, typename TS, typename TC, int RM>
 __global__ void __launch_bounds__(kBlock) k_nu_step(const NuJob* __restrict__ jobs, int njobs, int mode) {
   const NuJob J = to_global(jobs[find_job(jobs, njobs)]);
@@ -1190,8 +1190,7 @@ __global__ void __launch_bounds__(kBlock) k_nu_step(const NuJob* __restrict__ jo
   TS* b = (TS*)J.b;
   const TS* x = (const TS*)J.x;
   TS* o = (TS*)J.o;
-  const bool res = (mode & (NU_RES_X | NU_RES_O)) != 0;
-  const TS* y = (mode & NU_RES_X) ? x : o;
+  const bool res = (mode & NU_RES_X) != 0;
   // stencil geometry and raw fields: centre node, then the 2d faces (x-, x+, y-, y+, z-, z+)
   int px = 0, py = 0, pz = 0;
   decode<D>(i, g.n, px, py, pz);
@@ -1217,7 +1216,7 @@ __global__ void __launch_bounds__(kBlock) k_nu_step(const NuJob* __restrict__ jo
       TC kcs = op.c[0] * kc[0];
 #pragma unroll
       for (int r = 1; r < RM; ++r) kcs += op.c[r] * kc[r];
-      const TS* ys = y + long(s) * g.npts;
+      const TS* ys = x + long(s) * g.npts;
       TC dg = op.sigma, off = 0;
 #pragma unroll
       for (int f = 0; f < 2 * D; ++f) {

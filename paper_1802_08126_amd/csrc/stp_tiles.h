@@ -901,7 +901,8 @@ __device__ __forceinline__ void apply_tile_body(const TileJob& J, int tile, int 
         off += w * sx[kq + nb_off<KB>(k)];
       }
       const TC y = FIX ? sigma * sx[kq] + gamma * (dg * sx[kq] - off) : dg * sx[kq] - off;
-      st<TS, TC>(ys, vec_off<D>(jx, jy, jz, n), y);
+      const int vo = vec_off<D>(jx, jy, jz, n);
+      st<TS, TC>(ys, vo, J.addout < 0 ? ld<TC>(ys, vo) - y : y);
     }
     __syncthreads();
   }
