@@ -348,6 +348,21 @@ def batch_run(args):
                                   batch_iters=[min(its), max(its)], loop_f64_sec=tl,
                                   loop_f64_iters=[min(its64), max(its64)],
                                   speedup_vs_loop_f64=tl / tb)
+        # the mixed-precision batch with two V-cycles per H~_k^{-1} (each problem's
+        # damping estimated for that preconditioner at setup)
+        b = stp.BatchSolver(probs, precision="f32", omega=0.0, tol=args.tol, max_iter=2000,
+                            check_every=args.check_every, nu_H=2)
+        b.autotune(reps=2, use_cache=True)
+        zero()
+        t0 = time.perf_counter()
+        _, _, infos, status = b.solve(us, ps)
+        torch.cuda.synchronize()
+        tb2 = time.perf_counter() - t0
+        b.close()
+        its = [i["iters"] for i in infos]
+        progress("batch: f32 nu_H=2 batch to tol", f"{tb2:.2f}s")
+        out["time_to_tol"].update(batch_f32_nuH2_sec=tb2, batch_nuH2_status=status,
+                                  batch_nuH2_iters=[min(its), max(its)], speedup_nuH2_vs_loop_f64=tl / tb2)
     return out
 
 
