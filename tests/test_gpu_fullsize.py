@@ -102,6 +102,22 @@ def test_heat2d_255_N256_two_iterations_full(heat2d):
     s.close()
 
 
+def test_heat2d_255_N256_two_iterations_nuH2_full(heat2d):
+    """The same with two V-cycles per H~_k^{-1} and a float32 preconditioner
+    (the bench's time-to-tolerance variant) against the float64 oracle."""
+    import paper_1802_08126_amd as stp
+    prob = heat2d
+    ref = uzawa.uzawa_fixed(prob, 2, omega=0.8, spatial="mg", nu_H=2)
+    for prec, tol in (("f64", 1e-11), ("f32", 2e-5)):
+        s = stp.from_problem(prob, precision=prec, omega=0.8, tol=0.0, max_iter=2, check_every=8, nu_H=2)
+        s.autotune(reps=3)
+        u, p, info = s.solve()
+        ru, rp = relmax(host(u), ref["u"]), relmax(host(p), ref["p"])
+        say("2d nu_H=2 trajectory", prec, ru, rp)
+        assert ru < tol and rp < tol
+        s.close()
+
+
 def test_heat2d_255_N256_converged_residual_full(heat2d):
     import paper_1802_08126_amd as stp
     prob = heat2d
