@@ -6,35 +6,17 @@
 // dimension.  Every step of an Uzawa iteration is one merged launch per
 // kernel instantiation ("site") that serves all problems at once; a site is a
 // table of jobs, one per problem, that the kernels search by block index.
-#include <hip/hip_runtime.h>
+#include "stp_internal.h"
 
-#include <algorithm>
-#include <cmath>
 #include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <functional>
-#include <map>
-#include <memory>
-#include <mutex>
-#include <string>
-#include <type_traits>
-#include <vector>
-
-#include "stp.h"
-#include "stp_kernels.h"
-#include "stp_tiles.h"
-
-using namespace stp;
 
 // ---------------------------------------------------------------------------
 // error reporting
 // ---------------------------------------------------------------------------
 static thread_local std::string g_last_error;
-struct stp_ctx;
-static inline void kt_end(stp_ctx* c);
 
-static stp_status fail(stp_status s, const char* fmt, ...) {
+namespace stpx {
+stp_status fail(stp_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -43,359 +25,16 @@ static stp_status fail(stp_status s, const char* fmt, ...) {
   g_last_error = buf;
   return s;
 }
+}  // namespace stpx
 
-#define HIP_TRY(expr)                                                                     \
-  do {                                                                                    \
-    hipError_t _e = (expr);                                                               \
-    if (_e != hipSuccess)                                                                 \
-      return fail(STP_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),     \
-                  __FILE__, __LINE__);                                                    \
-  } while (0)
-
-#define LAUNCH_CHECK()                                                                    \
-  do {                                                                                    \
-    kt_end(&*c);                                                                          \
-    hipError_t _e = hipGetLastError();                                                    \
-    if (_e != hipSuccess)                                                                 \
-      return fail(STP_EDEVICE, "kernel launch failed: %s (%s:%d)", hipGetErrorString(_e), \
-                  __FILE__, __LINE__);                                                    \
-  } while (0)
-
-// ---------------------------------------------------------------------------
-// problem, sites, context
-// ---------------------------------------------------------------------------
-namespace {
-
-struct Level {
-  int n;
-  double h;
-  Geom g;
-  double* kraw;    // unscaled nodal fields (float64), R x nnodes (level 0: the caller's)
-  void* kscaled;   // TC fields scaled by 0.5/h^2
-  void* b;         // TS right-hand side of the level (levels >= 1)
-  void* e;         // TS correction produced on the level (levels >= 1)
-};
-
-struct Bump {
-  char* base = nullptr;
-  size_t off = 0;
-  bool dry = true;
-  void* take(size_t bytes) {
-    off = (off + 255) & ~size_t(255);
-    void* p = dry ? nullptr : base + off;
-    off += bytes;
-    return p;
-  }
-};
-
-size_t ts_bytes(int prec) { return prec == STP_PREC_F64 ? 8 : (prec == STP_PREC_F32 ? 4 : 2); }
-size_t tc_bytes(int prec) { return prec == STP_PREC_F64 ? 8 : 4; }
-
-long ipow(long a, int d) {
-  long r = 1;
-  for (int i = 0; i < d; ++i) r *= a;
-  return r;
+namespace stpx {
+stp_status launch_finalize(stp_ctx* c) {
+  c->kt.level = 0;
+  KLAUNCH(k_finalize, dim3(unsigned(c->P)), dim3(kBlock), 0, c->stream, (const FinJob*)c->sites.fin_dev);
+  LAUNCH_CHECK();
+  return STP_OK;
 }
-
-dim3 grid_pts(long npts, int S) {
-  const long bx = (npts + kBlock - 1) / kBlock;
-  const int gy = std::min(S, 65535);
-  const int gz = (S + 65534) / 65535;
-  return dim3(unsigned(bx), unsigned(gy), unsigned(gz));
-}
-
-enum { TP_FFT2 = 0, TP_STOCKHAM = 1, TP_DENSE = 2, TP_BLUESTEIN = 3, TP_FOUR = 4 };
-
-constexpr int kBlueKey = 1 << 20;        // site key of a Bluestein group: kBlueKey + M
-constexpr int kBlueMaxN = 2048;          // Bluestein for step counts up to this (M <= 4096)
-constexpr size_t kMaxLds = 160 * 1024;   // LDS of one compute unit
-constexpr int kFourMaxN = 1 << 20;       // four-step FFT for powers of two above 4096 up to this
-
-// four-step FFT: LDS of a pass (FFT length N1 >= N2, C columns) and default columns
-size_t four_lds(int N, int C, size_t tcb) {
-  const int N1 = four_n1(N);
-  return (size_t(2) * N1 * C + size_t(2) * N1) * tcb;
-}
-int four_cols(int N) { return std::max(1, std::min(16, 4096 / four_n1(N))); }
-size_t stockham_lds(int N, int C, size_t tcb);
-// powers of two the in-LDS Stockham FFT cannot take (N > 4096, or one column
-// too large for the LDS) run as four-step FFTs
-bool four_step_n(int N, size_t tcb) {
-  const bool pow2 = N >= 1 && (N & (N - 1)) == 0;
-  return pow2 && N >= 512 && N <= kFourMaxN && (N > 4096 || stockham_lds(N, 1, tcb) > kMaxLds);
-}
-
-// Bluestein FFT length: the smallest power of two >= 2N - 1
-int bluestein_M(int N) {
-  int M = 1;
-  while (M < 2 * N - 1) M *= 2;
-  return M;
-}
-size_t bluestein_lds(int M, int C, size_t tcb) { return (size_t(2) * M * C + size_t(2) * M) * tcb; }
-int bluestein_cols(int M, size_t tcb) {
-  int C = 16;
-  while (C > 1 && (M * C > 4096 || bluestein_lds(M, C, tcb) > kMaxLds)) C /= 2;
-  return C;
-}
-
-// Default transform path for N: two-step register FFT (4 <= N <= 256, power
-// of two), Stockham LDS FFT (other powers of two up to 4096), Bluestein
-// (other N from 17 to 2048), dense otherwise.
-void transform_path(int N, size_t tcb, int& path, int& C, size_t& lds) {
-  C = 0;
-  lds = 0;
-  const bool pow2 = N >= 1 && (N & (N - 1)) == 0;
-  if (pow2 && N >= 4 && N <= 256) {
-    path = TP_FFT2;
-    return;
-  }
-  if (pow2 && N <= 4096) {
-    C = std::max(1, std::min(16, 4096 / N));
-    lds = (size_t(2) * N * C + size_t(4) * N) * tcb;
-    if (lds <= kMaxLds) {
-      path = TP_STOCKHAM;
-      return;
-    }
-  }
-  if (four_step_n(N, tcb)) {
-    C = four_cols(N);
-    lds = four_lds(N, C, tcb);
-    path = TP_FOUR;
-    return;
-  }
-  if (!pow2 && N > 16 && N <= kBlueMaxN) {
-    const int M = bluestein_M(N);
-    C = bluestein_cols(M, tcb);
-    lds = bluestein_lds(M, C, tcb);
-    path = TP_BLUESTEIN;
-    return;
-  }
-  C = 0;
-  lds = 0;
-  path = TP_DENSE;
-}
-
-// site key of a step count: N (powers of two up to 4096), the Bluestein group
-// kBlueKey + M (other N up to kBlueMaxN), or -1 (the dense group)
-int transform_key(int N) {
-  if (N >= 1 && (N & (N - 1)) == 0 && N <= kFourMaxN) return N;
-  if (N <= kBlueMaxN) return kBlueKey + bluestein_M(N);
-  return -1;
-}
-
-bool is_pow2(int N) { return N >= 1 && (N & (N - 1)) == 0; }
-
-// Stockham LDS bytes for N points and C columns per block
-size_t stockham_lds(int N, int C, size_t tcb) { return (size_t(2) * N * C + size_t(4) * N) * tcb; }
-
-// Schedule knobs of the tile launches.  Each knob scales the slabs per
-// block of every job of its launch sites by 2^e relative to the heuristic.
-enum Knob {
-  KN_R0 = 0,            // residual r_p
-  KN_R1,                // residual r_u (and the stop-test partials)
-  KN_MID,               // middle reference operator of the H-blocks
-  KN_UPA0,              // finest up-sweep of the A-tilde cycle (float64 accumulation)
-  KN_DOWN0,             // down-sweep into level l + 1 (all three cycles)
-  KN_UP0 = KN_DOWN0 + STP_MAX_LEVELS,   // up-sweep on level l, stored output
-  KN_FUSE = KN_UP0 + STP_MAX_LEVELS,    // threads per block of the fused coarse levels: 256 << e
-  KN_COUNT
-};
-
-struct TransformChoice {
-  int path;
-  int C;      // Stockham columns per block
-};
-
-struct Schedule {
-  int e[KN_COUNT];
-  std::map<int, TransformChoice> tpath;   // per power-of-two step count
-  Schedule() {
-    std::fill(e, e + KN_COUNT, 0);
-    e[KN_FUSE] = 2;   // 1024 threads: the fused kernel has one block per slab
-  }
-};
-
-struct Problem {
-  int dim = 0, n = 0, N = 0, R = 0;
-  double tau = 0;               // reference step of eq. (2.2) (the step when uniform)
-  std::vector<double> taus;     // N step lengths tau_n
-  const double* F = nullptr;
-  const double* u0 = nullptr;
-  const double* fields = nullptr;
-  std::vector<double> tcoef;   // R x N
-  std::vector<double> abar;    // R
-  std::vector<Level> lv;
-  Geom g0{};
-  int tpath = TP_DENSE;         // default transform path (the tuner may choose another)
-  long resid_tiles = 0;
-  int fuse_top = 0;             // first multigrid level solved by the fused coarse kernel
-  long npart = 0;               // residual partials (one per block of the a3 residual launch)
-  double omega = 0.8;           // damping of the u-update (eq. (3.1))
-  bool omega_auto = false;      // omega estimated at setup
-  double est_lmin = 0, est_lmax = 0, est_rho = 0;   // estimates behind an automatic omega
-  long nfnorm = 0;              // partials of the setup reduction of ||f||
-  // device memory
-  DevState* state = nullptr;
-  double* partial = nullptr;
-  double* kap64 = nullptr;      // finest-level scaled fields, float64
-  double* cA64 = nullptr;       // N x kMaxRank: tau_n * tcoef
-  double* taus64 = nullptr;     // N step lengths
-  void* cA = nullptr;           // TC, N x kMaxRank
-  void* sigH = nullptr;         // TC, N: mu_k
-  void* cH = nullptr;           // TC, N x kMaxRank: tau * abar
-  void* cMid = nullptr;         // TC, kMaxRank: (2/N) tau abar
-  void* sinT = nullptr;         // TC, N x N (dense path)
-  void* sinM = nullptr;
-  void* tw = nullptr;           // TC, 2N (Bluestein problems: w_M, 2M)
-  void* tw4 = nullptr;          // TC, 2N
-  int blM = 0;                  // Bluestein FFT length (0: not a Bluestein step count)
-  void* chirp = nullptr;        // TC, 2N
-  void* bhat = nullptr;         // TC, 2M
-  void* fs = nullptr;           // TC, 2 x N x n^d: four-step FFT scratch (powers of two > 4096)
-  void* W1 = nullptr;           // TS, N x n^d
-  void* W2 = nullptr;
-  void* Xnu = nullptr;          // TS, N x n^d: correction of one cycle when nu_A or nu_H > 1
-  void* tri = nullptr;          // TC scratch of exact 1-D solves, 2 x N x n
-  double fnorm = 0;
-};
-
-template <typename J>
-struct Site {
-  std::vector<J> jobs;
-  J* dev = nullptr;
-  long blocks = 0;
-  int key = 0;     // transform sites: N (-1: the dense group of other step counts)
-  size_t shmem = 0;               // fused multigrid sites: dynamic LDS of the launch
-  int threads = 256;              // fused multigrid sites: threads per block
-  bool fixed = true;              // tile sites: every job's coefficient is a fixed field times a slab scalar
-  bool anyfix = false;            // tile sites: at least one job's coefficient is a fixed field
-  int epi = 0;
-  int path = TP_DENSE, C = 0;   // transform sites: path and Stockham columns
-  size_t lds = 0;
-  // launch variant of the tile kernels: 0 per-slab only, 1 fixed only, 2 mixed
-  int variant() const { return fixed ? 1 : anyfix ? 2 : 0; }
-  void add(J j, long nb, bool fix = false) {
-    fixed = fixed && fix;
-    anyfix = anyfix || fix;
-    j.block0 = blocks;
-    blocks += nb;
-    jobs.push_back(j);
-  }
-};
-
-struct VCycle {
-  std::vector<Site<TileJob>> down, up;   // by level l = 0 .. Lmax-2
-  std::vector<Site<FuseJob>> fused;      // by fused top level index 0 .. Lmax-1
-  Site<PointJob> tri;                    // exact 1-D solves
-};
-
-// VC_AX, VC_HX: the A and H cycles with their output stored to Xnu; VC_HA: the
-// H cycle adding its result into its output (the last of nu > 1 H cycles)
-enum { VC_A = 0, VC_H1 = 1, VC_H2 = 2, VC_AX = 3, VC_HX = 4, VC_HA = 5 };
-
-struct Sites {
-  Site<ResidJob> resid[2];
-  VCycle vc[6];
-  Site<NuJob> nu[2];     // steps between the cycles of an application with nu > 1 (A, H)
-  Site<TileJob> nures;   // b -= L o after the first of nu_H > 1 H cycles (tiled operator)
-  Site<TileJob> mid;
-  std::vector<Site<TimeJob>> a4, a6;
-  std::vector<FinJob> fin;
-  FinJob* fin_dev = nullptr;
-};
-
-// Optional per-launch device timing (HIP events on the context's stream).
-struct KTimer {
-  bool on = false;
-  int level = 0;
-  std::vector<hipEvent_t> pool;
-  size_t used = 0;
-  struct Rec {
-    const char* name;
-    int level;
-    hipEvent_t a, b;
-  };
-  std::vector<Rec> recs;
-  const char* pend_name = nullptr;
-  int pend_level = 0;
-  hipEvent_t pend_a = nullptr;
-  struct Agg {
-    std::string name;
-    int level;
-    long count;
-    double ms;
-  };
-  std::vector<Agg> agg;
-  hipEvent_t get() {
-    if (used == pool.size()) {
-      hipEvent_t e = nullptr;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
-      pool.push_back(e);
-    }
-    return pool[used++];
-  }
-};
-
-struct SolverBase;
-
-}  // namespace
-
-struct stp_ctx {
-  int P = 0, dim = 0, prec = 0, spatial = STP_SPATIAL_MG, rm = 1;
-  stp_options opt{};
-  hipStream_t stream = nullptr;
-  std::vector<Problem> pr;
-  void* ws = nullptr;
-  bool own_ws = false;
-  size_t tables_off = 0;
-  size_t tables_bytes = 0;
-  DevState* state_host = nullptr;   // pinned, P entries
-  Sites sites;
-  SolverBase* impl = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  KTimer kt;
-  hipStream_t cap_stream = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  hipGraphExec_t gexecA = nullptr, gexecH = nullptr;   // A~^{-1} cycle and H~^{-1} (GMRES preconditioner)
-  Schedule sched;
-  std::string sched_text;
-};
-
-namespace {
-constexpr int kMaxNu = 8;   // V-cycles per spatial preconditioner application
-// nu_A or nu_H > 1 with multigrid: the cycles of one application run through Xnu
-bool multi_cycle(const stp_ctx* c) {
-  return c->spatial == STP_SPATIAL_MG && (c->opt.nu_A > 1 || c->opt.nu_H > 1);
-}
-}  // namespace
-
-static inline void kt_begin(stp_ctx* c, const char* name) {
-  if (!c->kt.on) return;
-  hipEvent_t a = c->kt.get();
-  if (!a) return;
-  (void)hipEventRecord(a, c->stream);
-  c->kt.pend_name = name;
-  c->kt.pend_level = c->kt.level;
-  c->kt.pend_a = a;
-}
-
-static inline void kt_end(stp_ctx* c) {
-  if (!c->kt.on || !c->kt.pend_name) return;
-  hipEvent_t b = c->kt.get();
-  if (b) {
-    (void)hipEventRecord(b, c->stream);
-    c->kt.recs.push_back({c->kt.pend_name, c->kt.pend_level, c->kt.pend_a, b});
-  }
-  c->kt.pend_name = nullptr;
-}
-
-// Every kernel launch goes through KLAUNCH (optional timing) and LAUNCH_CHECK.
-#define KLAUNCH_NAMED(name, kern, ...)     \
-  do {                                     \
-    kt_begin(&*c, name);                   \
-    hipLaunchKernelGGL(kern, __VA_ARGS__); \
-  } while (0)
-#define KLAUNCH(kern, ...) KLAUNCH_NAMED(#kern, kern, __VA_ARGS__)
+}  // namespace stpx
 
 namespace {
 
@@ -927,562 +566,6 @@ stp_status bind_solution(stp_ctx* c, const std::vector<double*>& u, const std::v
   return bind_jobs(c, u, p, nullptr, p, acc, alpha);
 }
 
-// ---------------------------------------------------------------------------
-// typed execution
-// ---------------------------------------------------------------------------
-struct SolverBase {
-  virtual ~SolverBase() {}
-  virtual stp_status init() = 0;
-  virtual stp_status launch_knob(int knob) = 0;
-  virtual stp_status launch_transform(int g) = 0;
-  virtual stp_status setup_problem(Problem& q) = 0;
-  // full = false: only up to the stop test (the u-update of an iteration whose
-  // stop test must fire would find the problem done and do nothing)
-  virtual stp_status iteration(bool full = true) = 0;
-  virtual stp_status run_vcycle(int which) = 0;
-  virtual stp_status run_precH() = 0;
-  virtual stp_status cast_in(const double* a, void* b, long n) = 0;
-  // W1 of problem 0 = sgn (r + K^T d) in the storage type (input of the H-tilde solve)
-  virtual stp_status kt_add_in(const double* r, const double* d, double sgn) = 0;
-  virtual stp_status cast_out(const void* a, double scale, double* b, long n) = 0;
-  virtual stp_status resid(int which) = 0;
-};
-
-template <typename TS, typename TC>
-struct Solver : SolverBase {
-  stp_ctx* c;
-  explicit Solver(stp_ctx* ctx) : c(ctx) {}
-
-  TC omegaJ() const { return c->dim == 1 ? TC(2.0 / 3.0) : (c->dim == 2 ? TC(4.0 / 5.0) : TC(6.0 / 7.0)); }
-
-  template <int D, int RM>
-  stp_status fused_site(Site<FuseJob>& s, int level) {
-    if (s.jobs.empty()) return STP_OK;
-    c->kt.level = level;
-    if (s.epi == EPI_ADD64)
-      KLAUNCH_NAMED("k_mg_fused<add64>", (k_mg_fused<D, TS, TC, RM, EPI_ADD64>), dim3(unsigned(s.blocks)),
-                    dim3(unsigned(s.threads)), s.shmem, c->stream, s.dev, int(s.jobs.size()), omegaJ());
-    else
-      KLAUNCH_NAMED("k_mg_fused<store>", (k_mg_fused<D, TS, TC, RM, EPI_STORE>), dim3(unsigned(s.blocks)),
-                    dim3(unsigned(s.threads)), s.shmem, c->stream, s.dev, int(s.jobs.size()), omegaJ());
-    LAUNCH_CHECK();
-    return STP_OK;
-  }
-
-  template <int D, int RM>
-  stp_status vcycle_dr(VCycle& vc) {
-    const int nl = int(vc.down.size());
-    stp_status st;
-    if (!vc.fused.empty())   // problems solved entirely by the fused kernel
-      if ((st = fused_site<D, RM>(vc.fused[0], 0)) != STP_OK) return st;
-    for (int l = 0; l < nl; ++l) {
-      if ((st = down_site<D, RM>(vc.down[l], l)) != STP_OK) return st;
-      if ((st = fused_site<D, RM>(vc.fused[l + 1], l + 1)) != STP_OK) return st;
-    }
-    for (int l = nl - 1; l >= 0; --l)
-      if ((st = up_site<D, RM>(vc.up[l], l)) != STP_OK) return st;
-    return STP_OK;
-  }
-
-  template <int D, int RM>
-  stp_status down_site(Site<TileJob>& s, int l) {
-    if (s.jobs.empty()) return STP_OK;
-    c->kt.level = l;
-    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
-    const int nj = int(s.jobs.size());
-    switch (s.variant()) {   // a fixed field needs no register copy of the fields: one instantiation
-      case 1: KLAUNCH_NAMED("k_mg_down", (k_mg_down<D, TS, TC, 1, 1>), gr, bl, 0, c->stream, s.dev, nj, omegaJ()); break;
-      case 2: KLAUNCH_NAMED("k_mg_down", (k_mg_down<D, TS, TC, RM, 2>), gr, bl, 0, c->stream, s.dev, nj, omegaJ()); break;
-      default: KLAUNCH_NAMED("k_mg_down", (k_mg_down<D, TS, TC, RM, 0>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
-    }
-    LAUNCH_CHECK();
-    return STP_OK;
-  }
-
-  template <int D, int RM>
-  stp_status up_site(Site<TileJob>& s, int l) {
-    if (s.jobs.empty()) return STP_OK;
-    c->kt.level = l;
-    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
-    const int nj = int(s.jobs.size());
-    const int v = s.variant();
-    if (s.epi == EPI_ADD64) {
-      const char* nm = "k_mg_up<add64>";
-      if (v == 1) KLAUNCH_NAMED(nm, (k_mg_up<D, TS, TC, 1, EPI_ADD64, 1>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
-      else if (v == 2) KLAUNCH_NAMED(nm, (k_mg_up<D, TS, TC, RM, EPI_ADD64, 2>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
-      else KLAUNCH_NAMED(nm, (k_mg_up<D, TS, TC, RM, EPI_ADD64, 0>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
-    } else {
-      const char* nm = "k_mg_up<store>";
-      if (v == 1) KLAUNCH_NAMED(nm, (k_mg_up<D, TS, TC, 1, EPI_STORE, 1>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
-      else if (v == 2) KLAUNCH_NAMED(nm, (k_mg_up<D, TS, TC, RM, EPI_STORE, 2>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
-      else KLAUNCH_NAMED(nm, (k_mg_up<D, TS, TC, RM, EPI_STORE, 0>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
-    }
-    LAUNCH_CHECK();
-    return STP_OK;
-  }
-
-  // one launch of the representative site of a schedule knob
-  template <int D, int RM>
-  stp_status knob_dr(int knob) {
-    switch (knob) {
-      case KN_R0: return resid_dr<D, 0, RM>();
-      case KN_R1: return resid_dr<D, 1, RM>();
-      case KN_MID: return apply_dr<D, RM>(c->sites.mid);
-      case KN_UPA0: return up_site<D, RM>(c->sites.vc[VC_A].up[0], 0);
-      case KN_FUSE: {
-        VCycle& v = c->sites.vc[VC_H1];
-        for (size_t l = 0; l < v.fused.size(); ++l) {
-          const stp_status st = fused_site<D, RM>(v.fused[l], int(l));
-          if (st != STP_OK) return st;
-        }
-        return STP_OK;
-      }
-      default:
-        if (knob < KN_UP0) return down_site<D, RM>(c->sites.vc[VC_H1].down[knob - KN_DOWN0], knob - KN_DOWN0);
-        return up_site<D, RM>(c->sites.vc[VC_H1].up[knob - KN_UP0], knob - KN_UP0);
-    }
-  }
-
-  stp_status launch_knob(int knob) override {
-    switch (c->dim * 10 + c->rm) {
-      case 11: return knob_dr<1, 1>(knob);
-      case 12: return knob_dr<1, 2>(knob);
-      case 14: return knob_dr<1, 4>(knob);
-      case 21: return knob_dr<2, 1>(knob);
-      case 22: return knob_dr<2, 2>(knob);
-      case 24: return knob_dr<2, 4>(knob);
-      case 31: return knob_dr<3, 1>(knob);
-      case 32: return knob_dr<3, 2>(knob);
-      default: return knob_dr<3, 4>(knob);
-    }
-  }
-
-  // transform group g: forward (mode 0) and inverse-accumulate (mode 1) launches
-  stp_status launch_transform(int g) override {
-    std::vector<Site<TimeJob>> one4(1, c->sites.a4[g]), one6(1, c->sites.a6[g]);
-    stp_status st = transform_sites(one4, 0);
-    if (st != STP_OK) return st;
-    return transform_sites(one6, 1);
-  }
-
-  // nu_A (A) or nu_H (H1, H2) cycles, each on the residual the ones before
-  // it leave (multigrid only; exact solves need one).  A: cycles 1..nu-1 store
-  // to Xnu, then b -= L Xnu and p += Xnu, and the last cycle adds into p.
-  // H: the first cycle stores the output o, b -= L o (the tiled operator),
-  // each middle cycle stores to Xnu, then o += Xnu and b -= L Xnu, and the last
-  // cycle adds into o.  The steps
-  // read their operands from job tables, so captured graphs follow a rebinding
-  // of the A target as the cycles do.
-  stp_status run_vcycle(int which) override {
-    const int nu = which == VC_A ? c->opt.nu_A : c->opt.nu_H;
-    if (nu <= 1 || !multi_cycle(c)) return run_cycle(c->sites.vc[which]);
-    const int fam = which == VC_A ? 0 : 1;
-    VCycle& vx = c->sites.vc[fam == 0 ? VC_AX : VC_HX];
-    stp_status st;
-    if (fam == 0) {
-      for (int k = 1; k < nu; ++k) {
-        if ((st = run_cycle(vx)) != STP_OK) return st;
-        if ((st = nu_step(fam, NU_RES_X | NU_ADD)) != STP_OK) return st;
-      }
-      return run_cycle(c->sites.vc[which]);
-    }
-    if ((st = run_cycle(c->sites.vc[which])) != STP_OK) return st;
-    if ((st = run_apply(c->sites.nures)) != STP_OK) return st;   // b -= L o
-    for (int k = 1; k + 1 < nu; ++k) {
-      if ((st = run_cycle(vx)) != STP_OK) return st;
-      if ((st = nu_step(fam, NU_ADD | NU_RES_X)) != STP_OK) return st;
-    }
-    return run_cycle(c->sites.vc[VC_HA]);
-  }
-
-  stp_status nu_step(int fam, int mode) {
-    Site<NuJob>& s = c->sites.nu[fam];
-    if (s.jobs.empty()) return STP_OK;
-    c->kt.level = 0;
-    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
-    const int nj = int(s.jobs.size());
-#define STP_NU(D_, RM_) KLAUNCH_NAMED("k_nu_step", (k_nu_step<D_, TS, TC, RM_>), gr, bl, 0, c->stream, s.dev, nj, mode)
-    switch (c->dim * 10 + c->rm) {
-      case 11: STP_NU(1, 1); break;
-      case 12: STP_NU(1, 2); break;
-      case 14: STP_NU(1, 4); break;
-      case 21: STP_NU(2, 1); break;
-      case 22: STP_NU(2, 2); break;
-      case 24: STP_NU(2, 4); break;
-      case 31: STP_NU(3, 1); break;
-      case 32: STP_NU(3, 2); break;
-      default: STP_NU(3, 4);
-    }
-#undef STP_NU
-    LAUNCH_CHECK();
-    return STP_OK;
-  }
-
-  stp_status run_cycle(VCycle& vc) {
-    if (c->spatial == STP_SPATIAL_EXACT) {
-      Site<PointJob>& s = vc.tri;
-      c->kt.level = 0;
-      if (s.epi == EPI_ADD64)
-        KLAUNCH_NAMED("k_tridiag<add64>", (k_tridiag<TS, TC, EPI_ADD64>), dim3(unsigned(s.blocks)), dim3(64), 0,
-                      c->stream, s.dev, int(s.jobs.size()));
-      else
-        KLAUNCH_NAMED("k_tridiag<store>", (k_tridiag<TS, TC, EPI_STORE>), dim3(unsigned(s.blocks)), dim3(64), 0,
-                      c->stream, s.dev, int(s.jobs.size()));
-      LAUNCH_CHECK();
-      return STP_OK;
-    }
-    switch (c->dim * 10 + c->rm) {
-      case 11: return vcycle_dr<1, 1>(vc);
-      case 12: return vcycle_dr<1, 2>(vc);
-      case 14: return vcycle_dr<1, 4>(vc);
-      case 21: return vcycle_dr<2, 1>(vc);
-      case 22: return vcycle_dr<2, 2>(vc);
-      case 24: return vcycle_dr<2, 4>(vc);
-      case 31: return vcycle_dr<3, 1>(vc);
-      case 32: return vcycle_dr<3, 2>(vc);
-      default: return vcycle_dr<3, 4>(vc);
-    }
-  }
-
-  template <int D, int RM>
-  stp_status apply_dr(Site<TileJob>& s) {
-    if (s.jobs.empty()) return STP_OK;
-    c->kt.level = 0;
-    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
-    const int nj = int(s.jobs.size());
-    switch (s.variant()) {
-      case 1: KLAUNCH_NAMED("k_apply_tile", (k_apply_tile<D, TS, TC, 1, 1>), gr, bl, 0, c->stream, s.dev, nj); break;
-      case 2: KLAUNCH_NAMED("k_apply_tile", (k_apply_tile<D, TS, TC, RM, 2>), gr, bl, 0, c->stream, s.dev, nj); break;
-      default: KLAUNCH_NAMED("k_apply_tile", (k_apply_tile<D, TS, TC, RM, 0>), gr, bl, 0, c->stream, s.dev, nj);
-    }
-    LAUNCH_CHECK();
-    return STP_OK;
-  }
-
-  stp_status run_apply(Site<TileJob>& s) {
-    switch (c->dim * 10 + c->rm) {
-      case 11: return apply_dr<1, 1>(s);
-      case 12: return apply_dr<1, 2>(s);
-      case 14: return apply_dr<1, 4>(s);
-      case 21: return apply_dr<2, 1>(s);
-      case 22: return apply_dr<2, 2>(s);
-      case 24: return apply_dr<2, 4>(s);
-      case 31: return apply_dr<3, 1>(s);
-      case 32: return apply_dr<3, 2>(s);
-      default: return apply_dr<3, 4>(s);
-    }
-  }
-
-  stp_status run_mid() { return run_apply(c->sites.mid); }
-
-  template <int L1, int L2, int MODE, int ACC>
-  stp_status fft2_site(Site<TimeJob>& s) {
-    constexpr int C = kBlock / (1 << L1);
-    const size_t lds = size_t(1 << (L1 + L2)) * C * sizeof(TC);
-    KLAUNCH_NAMED(MODE == MODE_A4 ? "k_time_fft2<a4>" : (ACC ? "k_time_fft2<a6,add64>" : "k_time_fft2<a6>"),
-                  (k_time_fft2<TS, TC, MODE, ACC, L1, L2>), dim3(unsigned(s.blocks)), dim3(kBlock), lds, c->stream,
-                  s.dev, int(s.jobs.size()));
-    LAUNCH_CHECK();
-    return STP_OK;
-  }
-
-  template <int MODE, int ACC>
-  stp_status fft2_dispatch(Site<TimeJob>& s) {
-    switch (s.key) {
-      case 4: return fft2_site<1, 1, MODE, ACC>(s);
-      case 8: return fft2_site<2, 1, MODE, ACC>(s);
-      case 16: return fft2_site<2, 2, MODE, ACC>(s);
-      case 32: return fft2_site<3, 2, MODE, ACC>(s);
-      case 64: return fft2_site<3, 3, MODE, ACC>(s);
-      case 128: return fft2_site<4, 3, MODE, ACC>(s);
-      default: return fft2_site<4, 4, MODE, ACC>(s);
-    }
-  }
-
-  // timing records of transform site g carry "level" g
-  stp_status transform_sites(std::vector<Site<TimeJob>>& sites, int mode) {
-    for (size_t g = 0; g < sites.size(); ++g) {
-      Site<TimeJob>& s = sites[g];
-      c->kt.level = int(g);
-      if (s.jobs.empty()) continue;
-      const bool acc = s.epi != 0;
-      if (s.path == TP_DENSE) {
-        if (acc)
-          KLAUNCH_NAMED("k_time_dense<a6,add64>", (k_time_dense<TS, TC, 1>), dim3(unsigned(s.blocks)), dim3(kBlock), 0,
-                        c->stream, s.dev, int(s.jobs.size()));
-        else
-          KLAUNCH_NAMED(mode == 0 ? "k_time_dense<a4>" : "k_time_dense<a6>", (k_time_dense<TS, TC, 0>),
-                        dim3(unsigned(s.blocks)), dim3(kBlock), 0, c->stream, s.dev, int(s.jobs.size()));
-        LAUNCH_CHECK();
-        continue;
-      }
-      if (s.path == TP_FFT2) {
-        stp_status st;
-        if (mode == 0) st = fft2_dispatch<MODE_A4, 0>(s);
-        else if (acc) st = fft2_dispatch<MODE_A6, 1>(s);
-        else st = fft2_dispatch<MODE_A6, 0>(s);
-        if (st != STP_OK) return st;
-        continue;
-      }
-      const int C = s.C;
-      const size_t lds = s.lds;
-      if (s.path == TP_BLUESTEIN) {   // every job of the site has the same M
-        if (mode == 0)
-          KLAUNCH_NAMED("k_time_bluestein<a4>", (k_time_bluestein<TS, TC, MODE_A4, 0>), dim3(unsigned(s.blocks)),
-                        dim3(kBlock), lds, c->stream, s.dev, int(s.jobs.size()), C);
-        else if (acc)
-          KLAUNCH_NAMED("k_time_bluestein<a6,add64>", (k_time_bluestein<TS, TC, MODE_A6, 1>), dim3(unsigned(s.blocks)),
-                        dim3(kBlock), lds, c->stream, s.dev, int(s.jobs.size()), C);
-        else
-          KLAUNCH_NAMED("k_time_bluestein<a6>", (k_time_bluestein<TS, TC, MODE_A6, 0>), dim3(unsigned(s.blocks)),
-                        dim3(kBlock), lds, c->stream, s.dev, int(s.jobs.size()), C);
-        LAUNCH_CHECK();
-        continue;
-      }
-      if (s.path == TP_FOUR) {   // two passes over the scratch
-        const dim3 gr(unsigned(s.blocks)), bl(kBlock);
-        const int nj = int(s.jobs.size());
-        if (mode == 0) {
-          KLAUNCH_NAMED("k_time_fft4<a4,p0>", (k_time_fft4<TS, TC, MODE_A4, 0, 0>), gr, bl, lds, c->stream, s.dev, nj, C);
-          LAUNCH_CHECK();
-          KLAUNCH_NAMED("k_time_fft4<a4,p1>", (k_time_fft4<TS, TC, MODE_A4, 1, 0>), gr, bl, lds, c->stream, s.dev, nj, C);
-        } else {
-          KLAUNCH_NAMED("k_time_fft4<a6,p0>", (k_time_fft4<TS, TC, MODE_A6, 0, 0>), gr, bl, lds, c->stream, s.dev, nj, C);
-          LAUNCH_CHECK();
-          if (acc)
-            KLAUNCH_NAMED("k_time_fft4<a6,p1,add64>", (k_time_fft4<TS, TC, MODE_A6, 1, 1>), gr, bl, lds, c->stream,
-                          s.dev, nj, C);
-          else
-            KLAUNCH_NAMED("k_time_fft4<a6,p1>", (k_time_fft4<TS, TC, MODE_A6, 1, 0>), gr, bl, lds, c->stream, s.dev,
-                          nj, C);
-        }
-        LAUNCH_CHECK();
-        continue;
-      }
-      // Stockham: every job of the site has the same N, hence the same layout
-      if (mode == 0)
-        KLAUNCH_NAMED("k_time_fft<a4>", (k_time_fft<TS, TC, MODE_A4, 0>), dim3(unsigned(s.blocks)), dim3(kBlock), lds,
-                      c->stream, s.dev, int(s.jobs.size()), C);
-      else if (acc)
-        KLAUNCH_NAMED("k_time_fft<a6,add64>", (k_time_fft<TS, TC, MODE_A6, 1>), dim3(unsigned(s.blocks)), dim3(kBlock),
-                      lds, c->stream, s.dev, int(s.jobs.size()), C);
-      else
-        KLAUNCH_NAMED("k_time_fft<a6>", (k_time_fft<TS, TC, MODE_A6, 0>), dim3(unsigned(s.blocks)), dim3(kBlock), lds,
-                      c->stream, s.dev, int(s.jobs.size()), C);
-      LAUNCH_CHECK();
-    }
-    return STP_OK;
-  }
-
-  // H-tilde^{-1}: W1 holds r on entry; Phi^{-1} yhat goes to the a6 targets.
-  stp_status run_precH() override {
-    stp_status s;
-    if ((s = transform_sites(c->sites.a4, 0)) != STP_OK) return s;   // rhat = Phi^{-T} r    (W1 -> W2)
-    if ((s = run_vcycle(VC_H1)) != STP_OK) return s;                  // x = H~_k^{-1} rhat   (W2 -> W1)
-    if ((s = run_mid()) != STP_OK) return s;                          // y = (2/N) tau A x    (W1 -> W2)
-    if ((s = run_vcycle(VC_H2)) != STP_OK) return s;                  // yhat = H~_k^{-1} y   (W2 -> W1)
-    return transform_sites(c->sites.a6, 1);                           // += alpha Phi^{-1} yhat
-  }
-
-  template <int D, int WHICH, int RM>
-  stp_status resid_dr() {
-    Site<ResidJob>& s = c->sites.resid[WHICH];
-    c->kt.level = 0;
-    const char* nm = WHICH == 0 ? "k_resid_tile<a1>" : "k_resid_tile<a3>";
-    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
-    const int nj = int(s.jobs.size());
-    switch (s.variant()) {
-      case 1: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, 1, 1>), gr, bl, 0, c->stream, s.dev, nj); break;
-      case 2: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, RM, 2>), gr, bl, 0, c->stream, s.dev, nj); break;
-      default: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, RM, 0>), gr, bl, 0, c->stream, s.dev, nj);
-    }
-    LAUNCH_CHECK();
-    return STP_OK;
-  }
-
-  template <int WHICH>
-  stp_status run_resid() {
-    switch (c->dim * 10 + c->rm) {
-      case 11: return resid_dr<1, WHICH, 1>();
-      case 12: return resid_dr<1, WHICH, 2>();
-      case 14: return resid_dr<1, WHICH, 4>();
-      case 21: return resid_dr<2, WHICH, 1>();
-      case 22: return resid_dr<2, WHICH, 2>();
-      case 24: return resid_dr<2, WHICH, 4>();
-      case 31: return resid_dr<3, WHICH, 1>();
-      case 32: return resid_dr<3, WHICH, 2>();
-      default: return resid_dr<3, WHICH, 4>();
-    }
-  }
-
-  stp_status iteration(bool full = true) override {
-    stp_status s;
-    if ((s = run_resid<0>()) != STP_OK) return s;        // r_p = K u - A p - f   -> W1
-    if ((s = run_vcycle(VC_A)) != STP_OK) return s;      // p += A~^{-1} r_p
-    if ((s = run_resid<1>()) != STP_OK) return s;        // r_u -> W1, partials of ||f - B u||^2
-    c->kt.level = 0;
-    KLAUNCH(k_finalize, dim3(unsigned(c->P)), dim3(kBlock), 0, c->stream, (const FinJob*)c->sites.fin_dev);
-    LAUNCH_CHECK();
-    return full ? run_precH() : STP_OK;                  // u += omega H~^{-1} r_u
-  }
-
-  stp_status cast_out(const void* a, double scale, double* b, long n) override {
-    KLAUNCH((k_cast_scale64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n,
-            (const TS*)a, scale, b);
-    LAUNCH_CHECK();
-    return STP_OK;
-  }
-
-  stp_status resid(int which) override { return which == 0 ? run_resid<0>() : run_resid<1>(); }
-
-  stp_status kt_add_in(const double* r, const double* d, double sgn) override {
-    Problem& q = c->pr[0];
-    const long nv = long(q.N) * q.g0.npts;
-    KLAUNCH((k_kt_add_cast<TS>), dim3(unsigned((nv + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
-            q.g0.npts, q.N, r, d, sgn, (TS*)q.W1);
-    LAUNCH_CHECK();
-    return STP_OK;
-  }
-
-  stp_status cast_in(const double* a, void* b, long n) override {
-    KLAUNCH((k_cast_from64<TS>), dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, n, a, (TS*)b);
-    LAUNCH_CHECK();
-    return STP_OK;
-  }
-
-  // the Stockham kernels may take up to the whole LDS of a CU
-  stp_status init() override {
-    const int lds = 160 * 1024;
-    HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A4, 0>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 0>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    HIP_TRY(hipFuncSetAttribute((const void*)k_time_fft<TS, TC, MODE_A6, 1>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    HIP_TRY(hipFuncSetAttribute((const void*)k_time_bluestein<TS, TC, MODE_A4, 0>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    HIP_TRY(hipFuncSetAttribute((const void*)k_time_bluestein<TS, TC, MODE_A6, 0>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    HIP_TRY(hipFuncSetAttribute((const void*)k_time_bluestein<TS, TC, MODE_A6, 1>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    for (const void* f : {(const void*)k_time_fft4<TS, TC, MODE_A4, 0, 0>, (const void*)k_time_fft4<TS, TC, MODE_A4, 1, 0>,
-                          (const void*)k_time_fft4<TS, TC, MODE_A6, 0, 0>, (const void*)k_time_fft4<TS, TC, MODE_A6, 1, 0>,
-                          (const void*)k_time_fft4<TS, TC, MODE_A6, 1, 1>})
-      HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    return STP_OK;
-  }
-
-  stp_status setup_problem(Problem& q) override {
-    const int N = q.N, R = q.R;
-    std::vector<TC> cA(size_t(N) * kMaxRank, TC(0)), cH(size_t(N) * kMaxRank, TC(0)), sig(N), mid(kMaxRank, TC(0));
-    std::vector<double> cA64(size_t(N) * kMaxRank, 0.0);
-    for (int s = 0; s < N; ++s)
-      for (int r = 0; r < R; ++r) {
-        cA64[size_t(s) * kMaxRank + r] = q.taus[s] * q.tcoef[size_t(r) * N + s];
-        cA[size_t(s) * kMaxRank + r] = TC(q.taus[s] * q.tcoef[size_t(r) * N + s]);
-        cH[size_t(s) * kMaxRank + r] = TC(q.tau * q.abar[r]);
-      }
-    for (int k = 0; k < N; ++k) sig[k] = TC(2.0 * std::sin((2.0 * k + 1.0) * M_PI / (4.0 * N)));
-    for (int r = 0; r < R; ++r) mid[r] = TC((2.0 / N) * q.tau * q.abar[r]);
-    HIP_TRY(hipMemcpyAsync(q.cA64, cA64.data(), cA64.size() * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(q.taus64, q.taus.data(), size_t(N) * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(q.cA, cA.data(), cA.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(q.cH, cH.data(), cH.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(q.sigH, sig.data(), sig.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(q.cMid, mid.data(), mid.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-    if (q.sinT) {
-      std::vector<TC> sT(size_t(N) * N), sM(size_t(N) * N);
-      for (int k = 0; k < N; ++k)
-        for (int m = 0; m < N; ++m) {
-          // sin((2k+1)(m+1) pi / (2N)) with the angle reduced exactly in integers
-          const long qq = (long(2 * k + 1) * long(m + 1)) % (4L * N);
-          const double v = std::sin(double(qq) * M_PI / (2.0 * N));
-          sT[size_t(k) * N + m] = TC(v);
-          sM[size_t(m) * N + k] = TC(v);
-        }
-      HIP_TRY(hipMemcpyAsync(q.sinT, sT.data(), sT.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipMemcpyAsync(q.sinM, sM.data(), sM.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipStreamSynchronize(c->stream));
-    }
-    if (q.blM) {
-      // Bluestein tables: w_M^m, w_{4N}^m, chirp c_n = exp(-i pi (n^2 mod 2N) / N),
-      // and Bhat = DFT_M(b) / M with b_m = b_{M-m} = conj(c_m) (|m| < N), by
-      // direct sums with exactly reduced angles
-      const int M = q.blM;
-      std::vector<TC> twm(2 * size_t(M)), tw4(2 * size_t(N)), ch(2 * size_t(N)), bh(2 * size_t(M));
-      std::vector<double> cr(N), ci(N);
-      for (int m = 0; m < M; ++m) {
-        twm[m] = TC(std::cos(2.0 * M_PI * m / M));
-        twm[M + m] = TC(-std::sin(2.0 * M_PI * m / M));
-      }
-      for (int m = 0; m < N; ++m) {
-        tw4[m] = TC(std::cos(M_PI * m / (2.0 * N)));
-        tw4[N + m] = TC(-std::sin(M_PI * m / (2.0 * N)));
-        const long sq = (long(m) * long(m)) % (2L * N);
-        cr[m] = std::cos(M_PI * double(sq) / N);
-        ci[m] = -std::sin(M_PI * double(sq) / N);
-        ch[m] = TC(cr[m]);
-        ch[N + m] = TC(ci[m]);
-      }
-      for (int k = 0; k < M; ++k) {
-        double sr = cr[0], si = -ci[0];   // m = 0
-        for (int m = 1; m < N; ++m) {
-          // b_m = b_{M-m} = conj(c_m): b_m w^{mk} + b_m w^{-mk} = 2 conj(c_m) cos(2 pi m k / M)
-          const long r = (long(m) * long(k)) % M;
-          const double cs = std::cos(2.0 * M_PI * double(r) / M);
-          sr += 2.0 * cr[m] * cs;
-          si -= 2.0 * ci[m] * cs;
-        }
-        bh[k] = TC(sr / M);
-        bh[M + k] = TC(si / M);
-      }
-      HIP_TRY(hipMemcpyAsync(q.tw, twm.data(), twm.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipMemcpyAsync(q.tw4, tw4.data(), tw4.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipMemcpyAsync(q.chirp, ch.data(), ch.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipMemcpyAsync(q.bhat, bh.data(), bh.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipStreamSynchronize(c->stream));
-    } else if (q.tw) {
-      std::vector<TC> tw(2 * size_t(N)), tw4(2 * size_t(N));
-      for (int m = 0; m < N; ++m) {
-        tw[m] = TC(std::cos(2.0 * M_PI * m / N));
-        tw[N + m] = TC(-std::sin(2.0 * M_PI * m / N));
-        tw4[m] = TC(std::cos(M_PI * m / (2.0 * N)));
-        tw4[N + m] = TC(-std::sin(M_PI * m / (2.0 * N)));
-      }
-      HIP_TRY(hipMemcpyAsync(q.tw, tw.data(), tw.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipMemcpyAsync(q.tw4, tw4.data(), tw4.size() * sizeof(TC), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipStreamSynchronize(c->stream));
-    }
-    // level fields: restrict unscaled float64 fields, then scale by 0.5/h^2 into TC
-    for (size_t l = 0; l < q.lv.size(); ++l) {
-      Level& L = q.lv[l];
-      const long nn = L.g.nnodes;
-      if (l > 0) {
-        Level& Fl = q.lv[l - 1];
-        for (int r = 0; r < R; ++r) {
-          const dim3 gr(unsigned((nn + kBlock - 1) / kBlock));
-          switch (q.dim) {
-            case 1: KLAUNCH(k_restrict_kappa<1>, gr, dim3(kBlock), 0, c->stream, Fl.n, L.n, Fl.kraw + r * Fl.g.nnodes, L.kraw + r * nn); break;
-            case 2: KLAUNCH(k_restrict_kappa<2>, gr, dim3(kBlock), 0, c->stream, Fl.n, L.n, Fl.kraw + r * Fl.g.nnodes, L.kraw + r * nn); break;
-            default: KLAUNCH(k_restrict_kappa<3>, gr, dim3(kBlock), 0, c->stream, Fl.n, L.n, Fl.kraw + r * Fl.g.nnodes, L.kraw + r * nn); break;
-          }
-          LAUNCH_CHECK();
-        }
-      }
-      const double sc = 0.5 / (L.h * L.h);
-      const long tot = nn * R;
-      KLAUNCH((k_scale_copy<TC>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream, tot,
-              (const double*)L.kraw, sc, (TC*)L.kscaled);
-      LAUNCH_CHECK();
-      if (l == 0) {
-        KLAUNCH((k_scale_copy<double>), dim3(unsigned((tot + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
-                tot, (const double*)L.kraw, sc, q.kap64);
-        LAUNCH_CHECK();
-      }
-    }
-    return STP_OK;
-  }
-};
 
 stp_status validate_one(const stp_grid* g, int N, double tau, const stp_kappa* kappa, const double* F,
                         const double* u0, const stp_options* opt) {
@@ -1922,21 +1005,9 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
   HIP_TRY(hipEventCreate(&c->ev0));
   HIP_TRY(hipEventCreate(&c->ev1));
   switch (opt.precision) {
-    case STP_PREC_F64: c->impl = new Solver<double, double>(c.get()); break;
-    case STP_PREC_F32: c->impl = new Solver<float, float>(c.get()); break;
-    default: c->impl = new Solver<bf16, float>(c.get()); break;
-  }
-  {
-    double wd[32];
-    float wf[32];
-    for (int k = 0; k < 16; ++k) {
-      wd[k] = std::cos(2.0 * M_PI * k / 16.0);
-      wd[16 + k] = -std::sin(2.0 * M_PI * k / 16.0);
-      wf[k] = float(wd[k]);
-      wf[16 + k] = float(wd[16 + k]);
-    }
-    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_w16d), wd, sizeof(wd)));
-    HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_w16f), wf, sizeof(wf)));
+    case STP_PREC_F64: c->impl = make_solver_f64(c.get()); break;
+    case STP_PREC_F32: c->impl = make_solver_f32(c.get()); break;
+    default: c->impl = make_solver_bf16(c.get()); break;
   }
   if ((s = c->impl->init()) != STP_OK) return s;
   for (auto& q : c->pr) {

@@ -278,6 +278,7 @@ __global__ void __launch_bounds__(kBlock) k_apply_saddle(Geom g, TimeOp t, const
 }
 
 // ||f||^2 partials (setup)
+#ifndef STP_SOLVER_TU   // used by the base translation unit only
 __global__ void __launch_bounds__(kBlock) k_fnorm(Geom g, int N, const double* __restrict__ taus,
                                                   const double* __restrict__ F, const double* __restrict__ u0,
                                                   double* __restrict__ partial) {
@@ -292,6 +293,7 @@ __global__ void __launch_bounds__(kBlock) k_fnorm(Geom g, int N, const double* _
   const double bs = block_sum(v);
   if (threadIdx.x == 0) partial[long(slab_index()) * gridDim.x + blockIdx.x] = bs;
 }
+#endif
 
 // Solver state shared by the iteration kernels and the host.
 struct DevState {
@@ -318,6 +320,7 @@ __device__ __forceinline__ FinJob to_global(FinJob j) {
   return j;
 }
 
+#ifndef STP_SOLVER_TU   // used by the base translation unit only
 __global__ void __launch_bounds__(kBlock) k_finalize(const FinJob* __restrict__ jobs) {
   const FinJob J = to_global(jobs[blockIdx.x]);
   DevState* st = J.st;
@@ -341,13 +344,16 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const FinJob* __restrict__ 
     }
   }
 }
+#endif
 
+#ifndef STP_SOLVER_TU   // used by the base translation unit only
 __global__ void k_sum_to(const double* __restrict__ partial, long count, double* out) {
   double v = 0.0;
   for (long q = threadIdx.x; q < count; q += kBlock) v += partial[q];
   const double s = block_sum(v);
   if (threadIdx.x == 0) *out = s;
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // spatial kernels on a multigrid level (storage TS, compute TC)
@@ -633,8 +639,9 @@ __global__ void __launch_bounds__(kBlock) k_time_dense(const TimeJob* __restrict
 // ---------------------------------------------------------------------------
 enum { MODE_A4 = 0, MODE_A6 = 1 };
 
-__constant__ double c_w16d[32];   // re[0..16), im[16..32)
-__constant__ float c_w16f[32];
+// one copy per translation unit (internal linkage), set by the solver's init
+static __constant__ double c_w16d[32];   // re[0..16), im[16..32)
+static __constant__ float c_w16f[32];
 
 template <typename TC> __device__ __forceinline__ TC w16re(int k);
 template <typename TC> __device__ __forceinline__ TC w16im(int k);
@@ -1298,12 +1305,15 @@ __device__ __forceinline__ double splitmix_pm1(unsigned long long i, unsigned lo
   return double(z >> 11) * 0x1.0p-52 - 1.0;
 }
 
+#ifndef STP_SOLVER_TU   // used by the base translation unit only
 __global__ void k_fill_pm1(long n, unsigned long long seed, double* __restrict__ out) {
   const long i = long(blockIdx.x) * kBlock + threadIdx.x;
   if (i < n) out[i] = splitmix_pm1((unsigned long long)i, seed);
 }
+#endif
 
 // block partials of a . b over a fixed grid (grid-stride), summed by k_sum_to
+#ifndef STP_SOLVER_TU   // used by the base translation unit only
 __global__ void __launch_bounds__(kBlock) k_dot_partial(long n, const double* __restrict__ a,
                                                         const double* __restrict__ b, double* __restrict__ partial) {
   double v = 0.0;
@@ -1311,13 +1321,16 @@ __global__ void __launch_bounds__(kBlock) k_dot_partial(long n, const double* __
   const double s = block_sum(v);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
+#endif
 
 // y = a x + b y  (y is not read when b == 0)
+#ifndef STP_SOLVER_TU   // used by the base translation unit only
 __global__ void k_axpby(long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
   const long i = long(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= n) return;
   y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
 }
+#endif
 
 // b = s * a, widened to float64
 template <typename TS>
@@ -1327,6 +1340,7 @@ __global__ void k_cast_scale64(long n, const TS* __restrict__ a, double s, doubl
 }
 
 // min over slabs s < S and nodes of sum_r coef[s][r] * fields[r][node]  (block partials)
+#ifndef STP_SOLVER_TU   // used by the base translation unit only
 __global__ void k_kappa_min(long nnodes, int R, int S, const double* __restrict__ fields,
                             const double* __restrict__ coef, double* __restrict__ partial) {
   __shared__ double red[kBlock];
@@ -1349,6 +1363,7 @@ __global__ void k_kappa_min(long nnodes, int R, int S, const double* __restrict_
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // Krylov acceleration (GMRES around the Uzawa sweep), float64 vectors
@@ -1425,6 +1440,7 @@ constexpr int kDotRows = 8;   // basis vectors per multi-dot launch
 
 // partial[q * gridDim.x + block] = block part of <V_q, w> for q < k (V_q = V + q ld),
 // and, when self != 0, row k = block part of <w, w>
+#ifndef STP_SOLVER_TU   // used by the base translation unit only
 __global__ void __launch_bounds__(kBlock) k_mdot_partial(long n, const double* __restrict__ V, long ld, int k,
                                                          int self, const double* __restrict__ w,
                                                          double* __restrict__ partial) {
@@ -1456,8 +1472,10 @@ __global__ void __launch_bounds__(kBlock) k_mdot_partial(long n, const double* _
     partial[long(threadIdx.x) * gridDim.x + blockIdx.x] = sum;
   }
 }
+#endif
 
 // out[row] = sum of partial[row * count .. row * count + count), one block per row
+#ifndef STP_SOLVER_TU   // used by the base translation unit only
 __global__ void __launch_bounds__(kBlock) k_sum_rows(const double* __restrict__ partial, long count,
                                                      double* __restrict__ out) {
   const double* pr = partial + long(blockIdx.x) * count;
@@ -1466,9 +1484,11 @@ __global__ void __launch_bounds__(kBlock) k_sum_rows(const double* __restrict__ 
   const double s = block_sum(v);
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
+#endif
 
 // w -= sum_{q<k} coef[q] V_q over a fixed grid (grid-stride), with block
 // partials of the updated ||w||^2 (summed by k_sum_rows)
+#ifndef STP_SOLVER_TU   // used by the base translation unit only
 __global__ void __launch_bounds__(kBlock) k_maxpy_norm(long n, double* __restrict__ w, const double* __restrict__ V,
                                                        long ld, int k, const double* __restrict__ coef,
                                                        double* __restrict__ partial) {
@@ -1490,8 +1510,10 @@ __global__ void __launch_bounds__(kBlock) k_maxpy_norm(long n, double* __restric
   const double s = block_sum(v);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
+#endif
 
 // w += sgn * sum_{q<k} coef[q] V_q  (coefficients read from device memory)
+#ifndef STP_SOLVER_TU   // used by the base translation unit only
 __global__ void k_maxpy(long n, double* __restrict__ w, const double* __restrict__ V, long ld, int k,
                         const double* __restrict__ coef, double sgn) {
   const long i = long(blockIdx.x) * kBlock + threadIdx.x;
@@ -1507,5 +1529,6 @@ __global__ void k_maxpy(long n, double* __restrict__ w, const double* __restrict
   }
   w[i] += sgn * acc;
 }
+#endif
 
 }  // namespace stp
