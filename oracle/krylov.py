@@ -187,6 +187,12 @@ def block_precond(prob, pc: Preconditioners, r1, r2):
 def minres(prob, tol: float = 1e-8, max_iter: int = 500, spatial: str = "mg", pc: Preconditioners | None = None,
            p_init=None, u_init=None, check_every: int = 8):
     """Preconditioned MINRES on the saddle system with P^{-1} = diag(A~^{-1}, H~^{-1}).
+
+    The recurrence is the Paige-Saunders algorithm (SIAM J. Numer. Anal. 12, 1975)
+    in the form and variable names of scipy's reference implementation
+    (scipy/sparse/linalg/_isolve/minres.py: oldb, dbar, epsln, phibar, ...),
+    with the same update order; the pin that does not rest on that code is
+    convergence to the sequential Euler solution without damping.
     Returns u, p, iters, the history of the residual estimate ||g - S x||_{P^{-1}}
     relative to its initial value (initial entry first), ||f - B u|| / ||f||."""
     pc = pc or Preconditioners(prob, spatial=spatial)

@@ -9,20 +9,7 @@ import pytest
 import synth
 from oracle import fd, mg
 
-
-def R1(n):
-    nc = (n - 1) // 2
-    R = np.zeros((nc, n))
-    for I in range(nc):
-        R[I, 2 * I:2 * I + 3] = [0.25, 0.5, 0.25]
-    return R
-
-
-def kron_d(M1, d):
-    out = M1
-    for _ in range(d - 1):
-        out = np.kron(out, M1)
-    return out
+from _dense import R1, dense_vcycle as _dense_vcycle, kron_d
 
 
 @pytest.mark.parametrize("d,n", [(1, 15), (2, 7), (3, 7)])
@@ -45,26 +32,6 @@ def test_transfer_operators(d, n):
     assert np.allclose(mg.restrict_kappa(k, d), 2.5)
     kr = rng.uniform(0.1, 3.0, size=(n + 2,) * d)
     assert mg.restrict_kappa(kr, d).min() > 0
-
-
-def _dense_vcycle(hier, sigma, c, l=0):
-    """V-cycle as a matrix: V = (I - E) L^{-1}, E = (I - W L)(I - P V_c R L)(I - W L)."""
-    lev = hier.levels[l]
-    d = hier.d
-    n = lev.n
-    m = n ** d
-    Ar = [fd.assemble(lev.kfields[r], n, d, lev.h).toarray() for r in range(lev.kfields.shape[0])]
-    L = sigma * np.eye(m) + sum(c[r] * Ar[r] for r in range(len(Ar)))
-    D = np.diag(np.diag(L))
-    if l == len(hier.levels) - 1:
-        return np.linalg.inv(D), L
-    W = mg.JACOBI_WEIGHT[d] * np.linalg.inv(D)
-    Rd = kron_d(R1(n), d)
-    Pd = (2 ** d) * Rd.T
-    Vc, _ = _dense_vcycle(hier, sigma, c, l + 1)
-    I = np.eye(m)
-    E = (I - W @ L) @ (I - Pd @ Vc @ Rd @ L) @ (I - W @ L)
-    return (I - E) @ np.linalg.inv(L), L
 
 
 @pytest.mark.parametrize("d,n", [(1, 15), (2, 7), (3, 7)])

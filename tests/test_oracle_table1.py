@@ -49,7 +49,7 @@ def test_table1(row):
     _check(*row)
 
 
-@pytest.mark.slow
 @pytest.mark.parametrize("row", [r for r in _rows() if r[1] > 256], ids=lambda r: f"h1/{r[0]}-N{r[1]}")
 def test_table1_large_N(row):
+    """N = 512, 1024: about 90 s of dense eigen-solves on 8 cores."""
     _check(*row)
