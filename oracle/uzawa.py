@@ -4,7 +4,8 @@
     u_{j+1} = u_j + omega H~^{-1} (f - K^T p_{j+1} - (K + K^T + A) u_j)
 
 Stopping rule (the paper states "residual tolerance" without a norm): stop at
-the first j with ||f - B u_j||_2 <= tol ||f||_2.  The test is evaluated in
+the first j with ||f - B u_j||_2 <= tol ||f||_2 (for f = 0, whose solution is
+zero, the absolute ||B u_j||_2 <= tol).  The test is evaluated in
 iteration j after the p-update (the same place the GPU library evaluates it),
 so on return u = u_j and p = p_{j+1}; ``iters`` = j.  Initial guess
 u_0 = p_0 = 0 unless given.
@@ -26,6 +27,7 @@ def uzawa(prob, omega: float = 0.8, tol: float = 1e-8, max_iter: int = 200,
     u = np.zeros(shape) if u_init is None else np.array(u_init, dtype=np.float64).reshape(shape)
     p = np.zeros(shape) if p_init is None else np.array(p_init, dtype=np.float64).reshape(shape)
     fnorm = np.linalg.norm(f)
+    den = fnorm if fnorm > 0 else 1.0        # f = 0: absolute residual
     hist = []
     status = "maxiter"
     j = 0
@@ -36,13 +38,13 @@ def uzawa(prob, omega: float = 0.8, tol: float = 1e-8, max_iter: int = 200,
         p = p + pc.Ainv(rp)
         e = f - Ku - Au                      # f - B u_j
         res = np.linalg.norm(e)
-        hist.append(res / fnorm)
+        hist.append(res / den)
         if callback is not None:
-            callback(j, u, p, res / fnorm)
+            callback(j, u, p, res / den)
         if not np.isfinite(res):
             status = "diverged"
             break
-        if res <= tol * fnorm:
+        if res <= tol * den:
             status = "converged"
             break
         if j >= max_iter:

@@ -1,7 +1,6 @@
 """Pins for the oracle's sequential implicit Euler (eq. (2.1))."""
 import numpy as np
 import pytest
-import scipy.fft as sfft
 
 import synth
 from oracle import euler, fd, spacetime as st
@@ -34,24 +33,31 @@ def test_sine_mode_decay_closed_form(d, n, N):
     assert np.allclose(u, exact, rtol=1e-12, atol=1e-14)
 
 
-@pytest.mark.parametrize("d,n,N", [(1, 63, 64), (2, 31, 16)])
-def test_modal_recurrence_with_source(d, n, N):
-    """kappa = kappa(t) only: a spatial DST-I diagonalises every A_n, so each mode
-    follows uh_n = (uh_{n-1} + tau Fh_n) / (1 + tau kappa(t_n) lambda_k)
-    (an independent route through scipy's DST-I)."""
-    prob = synth.heat1d_random(n=n, N=N) if d == 1 else synth.small_problem(d, n, N, R=1)
-    axes = tuple(range(-d, 0))
-    Fh = sfft.dstn(prob.F, type=1, axes=axes)
-    uh = sfft.dstn(prob.u0, type=1, axes=axes)
-    ks = np.arange(1, n + 1)
-    lam1 = 4 * (n + 1) ** 2 * np.sin(ks * np.pi / (2 * (n + 1))) ** 2
-    lam = sum(np.meshgrid(*([lam1] * d), indexing="ij"))
-    out = []
-    for m in range(N):
-        uh = (uh + prob.tau * Fh[m]) / (1 + prob.tau * prob.tcoef[0, m] * lam)
-        out.append(sfft.idstn(uh, type=1, axes=axes))
-    u = euler.seq_euler(prob)
-    assert np.allclose(u, np.array(out), rtol=1e-11, atol=1e-12)
+@pytest.mark.parametrize("d,n,N,graded", [(1, 63, 64, False), (2, 31, 16, False), (2, 15, 12, True), (3, 7, 6, False)])
+def test_modal_route_matches_lu(d, n, N, graded):
+    """kappa = kappa(t) only: the sine-transform route (``seq_euler_modal``)
+    equals the sparse-LU route step by step."""
+    steps = synth.graded_steps(N, ratio=5.0, jitter=0.2, seed=3) if graded else None
+    prob = (synth.heat1d_random(n=n, N=N, steps=steps) if d == 1
+            else synth.small_problem(d, n, N, R=1, steps=steps))
+    assert np.allclose(euler.seq_euler_modal(prob), euler.seq_euler(prob), rtol=1e-11, atol=1e-12)
+
+
+def test_modal_route_closed_form_and_factors():
+    """A single sine mode with F = 0 decays by prod (1 + tau kappa(t_m) lambda_k)^{-1};
+    a separable Gaussian source given as factors equals the assembled one."""
+    n, N = 31, 10
+    prob = synth.heat2d_gaussians(n=n, N=N, seed=9, phase=0.4)
+    kf, tc, factors, u0 = synth.heat2d_parts(n=n, N=N, seed=9, phase=0.4)
+    assert np.allclose(euler.seq_euler_modal(prob, factors=factors), euler.seq_euler(prob),
+                       rtol=1e-11, atol=1e-12)
+    mode = _sine(n, 2, [3, 2])
+    q = synth.Problem(2, n, N, 1.0, kf, tc, np.zeros((N, n, n)), mode)
+    lam = fd.laplace_eigenvalue([3, 2], q.h)
+    fac = np.cumprod(1.0 / (1.0 + q.tau * tc[0] * lam))
+    assert np.allclose(euler.seq_euler_modal(q), fac[:, None, None] * mode, rtol=1e-12, atol=1e-14)
+    with pytest.raises(ValueError):
+        euler.seq_euler_modal(synth.small_problem(2, 7, 3, R=2))
 
 
 @pytest.mark.parametrize("d,n,N", [(1, 15, 9), (2, 7, 5), (3, 3, 4)])

@@ -98,3 +98,16 @@ def test_iterations_flat_in_N():
         its.append(uzawa.uzawa(prob, omega=0.7, tol=1e-8, spatial="exact")["iters"])
     assert max(its) - min(its) <= 6, its
     assert max(its) < 60
+
+
+def test_zero_right_hand_side_stops_at_once():
+    """f = 0 (F = 0, u0 = 0): the solution is zero and the absolute residual
+    test stops at iteration 0; from a nonzero guess the iterates tend to 0."""
+    prob = synth.small_problem(2, 7, 4, seed=9)
+    prob.F = np.zeros_like(prob.F)
+    prob.u0 = np.zeros_like(prob.u0)
+    res = uzawa.uzawa(prob, omega=0.7, tol=1e-10)
+    assert res["status"] == "converged" and res["iters"] == 0 and res["history"][0] == 0.0
+    g = np.random.default_rng(1).standard_normal(res["u"].shape)
+    res = uzawa.uzawa(prob, omega=0.7, tol=1e-10, u_init=g, max_iter=400)
+    assert res["status"] == "converged" and np.abs(res["u"]).max() < 1e-8 * np.abs(g).max()
