@@ -48,7 +48,7 @@ typedef enum {
   STP_ENOMEM = -2,       /* device allocation failed / workspace too small       */
   STP_EDEVICE = -3,      /* a HIP call failed                                    */
   STP_ENOTCONV = -4,     /* max_iter reached; u, p hold the last iterate         */
-  STP_EDIVERGED = -5,    /* non-finite or exploding residual; last finite iterate is not kept */
+  STP_EDIVERGED = -5,    /* exploding or non-finite residual; see stp_uzawa_solve     */
   STP_EUNSUPPORTED = -6  /* valid request this build does not implement          */
 } stp_status;
 
@@ -64,6 +64,13 @@ enum { STP_SPATIAL_AUTO = 0,   /* exact tridiagonal solves in 1-D, multigrid in 
        STP_SPATIAL_EXACT = 2,  /* exact spatial solves (1-D only)                          */
        STP_SPATIAL_NONE = 3 }; /* operators only: stp_apply_precond / stp_uzawa_solve
                                   return STP_EUNSUPPORTED; any n allowed                   */
+
+enum { STP_DISC_FD = 0,    /* finite differences, M = I, kappa(t, x) of rank <= 4 (the default)   */
+       STP_DISC_FEM = 1 }; /* finite elements with the consistent mass matrix M of Section 2:
+                              P1 in 1-D and 2-D (squares split by their lower-left/upper-right
+                              diagonal), Q1 hexahedra in 3-D; kappa constant in space (rank 1,
+                              a constant field) times the time factor tcoef; single problems,
+                              exact solves in 1-D, one V-cycle (nu = 1) in 2-D and 3-D          */
 
 enum { STP_OP_B = 0,        /* y = B x = (K + A) x, eq. (2.3); x, y: N*n^d              */
        STP_OP_SADDLE = 1 }; /* [y_p; y_u] = saddle [x_p; x_u], eq. (2.7); 2*N*n^d each  */
@@ -113,32 +120,75 @@ typedef struct {
                               (N[0] + ... + N[P-1] values; a problem with uniform steps
                               lists N[i] copies of its tau), and each tau[i] <= 0 selects
                               the mean of problem i's own steps.                         */
+  int disc;             /* STP_DISC_*.  With STP_DISC_FEM the problem of stp_create is
+                           M (u_n - u_{n-1}) + tau_n a_n A u_n = tau_n M F_n (eq. (2.1)),
+                           u_0 = u0, with M, A the element matrices of the mesh and
+                           a_n = tcoef[n-1] * (the field's constant value); F holds the
+                           nodal values of the source, so f_n = tau_n M F_n + [n = 1] M u0.
+                           The multigrid levels are the element operators of the coarse
+                           meshes (the Galerkin operators of the element interpolation),
+                           smoothed by l1-Jacobi, x += 1.6 (b - L x) / (absolute row sum
+                           of L), which contracts for every mix of mass and stiffness.    */
+  int sweeps;           /* finite elements: l1-Jacobi sweeps before and after the
+                           coarse correction of each V-cycle, 1..4 (0 means 1); the finite-
+                           difference cycle is fixed at one.  Out of range: EINVAL.       */
 } stp_options;
+
+/* Per-phase device times of a solve (stp_stats.t_phase_ms), Tables 3-4 of
+ * Section 8.3 split the time the same way (FFT vs spatial solves). */
+enum { STP_PHASE_RESID = 0,    /* residuals r_p, r_u and the stop test (eq. (3.1))          */
+       STP_PHASE_ATILDE = 1,   /* A-tilde^{-1} solves, eq. (3.2)                             */
+       STP_PHASE_DST = 2,      /* time transforms Phi^{-T}, Phi^{-1}, eqs. (4.2)-(4.3)        */
+       STP_PHASE_HBLOCK = 3,   /* H-blocks (2 tau / N) H~_k^{-1} A H~_k^{-1}, eq. (4.6)      */
+       STP_PHASE_OTHER = 4,    /* everything else (GMRES orthogonalisation, casts)           */
+       STP_NPHASE = 5 };
 
 typedef struct {
   int iters;            /* number of u-updates performed (j of the returned u_j)     */
-  double rel_res;       /* ||f - B u_j||_2 / ||f||_2 of the returned u_j             */
+  double rel_res;       /* ||f - B u_j||_2 / ||f||_2 of the returned u_j (when f = 0:
+                           the absolute ||B u_j||_2)                                  */
   double omega_used;
   double t_solve_ms;    /* device time of the iteration loop (HIP events)            */
   int status;           /* stp_status of the solve                                   */
+  double rel_rp;        /* ||K u - A p - f||_2 / ||f||_2 and                          */
+  double rel_ru;        /* ||f - K^T p - (K + K^T + A) u||_2 / ||f||_2 of the returned
+                           pair (u_j, p_{j+1}): the two blocks of the saddle residual
+                           of eq. (2.7) (absolute when f = 0); one extra pass over
+                           u, p, F after the solve                                    */
+  double t_setup_ms;    /* wall time of stp_create[_batch] (all problems), including  */
+  double t_omega_ms;    /* the damping estimate (this part)                           */
+  double t_phase_ms[STP_NPHASE]; /* device time of the solve's kernels by phase
+                           (STP_PHASE_*), summed over launches; measured only while
+                           stp_timing_enable(ctx, 1) is in effect (the solve then runs
+                           without graph replay), else 0                             */
 } stp_stats;
 
 /* Fill *opt with defaults: F64, AUTO, nu = 1, omega 0.8, tol 1e-8, max_iter 500,
    time-mean kappa_ref, check_every 8, graphs on, uniform steps. */
 void stp_default_options(stp_options* opt);
 
-/* Device bytes stp_create needs as workspace for this problem and options. */
+/* Device bytes stp_create needs as workspace for this problem and options.
+ * Layout: [solver vectors and coefficient tables | launch tables | setup and
+ * tuning scratch]; the scratch holds max(5 float64 vectors per problem plus
+ * 8 KB of dot partials when omega is estimated (opt->omega <= 0), 2 float64
+ * vectors per problem for stp_autotune) and is only used inside stp_create
+ * and stp_autotune. */
 size_t stp_workspace_bytes(const stp_grid* g, int N, int rank, const stp_options* opt);
 
 /* Set up one problem (Section 2 problem statement): grid, N steps of length tau,
  * kappa, source F (device, N x n^d: F_n on the interior nodes) and initial datum
  * u0 (device, n^d).  F, u0 and kappa->fields are borrowed until stp_destroy.
- * workspace: device buffer of >= stp_workspace_bytes (256-byte aligned), or NULL
- * to let the library allocate (and free) its own.  hip_stream: hipStream_t or NULL.
+ * workspace: device buffer of >= stp_workspace_bytes (256-byte aligned), owned
+ * by the caller; the library then allocates no device memory for this context,
+ * neither here nor in any later call (it keeps a small pinned host array of
+ * per-problem stop flags).  NULL: the library allocates the solver part
+ * itself (freed by stp_destroy) and the setup and tuning scratch only while
+ * it is in use.  hip_stream: hipStream_t or NULL.
  * Errors: EINVAL (dim not 1..3, n < 1, N < 1, tau <= 0 or not finite without
  * opt->tau_steps, a step length <= 0 or not finite, rank out of range, NULL
- * pointers, some kappa <= 0), EUNSUPPORTED (MG with n != 2^L - 1, EXACT with
- * dim > 1, nu != 1), ENOMEM, EDEVICE. */
+ * pointers, some kappa <= 0, a non-finite value in F or u0, nu_A or nu_H not
+ * in 1..8), EUNSUPPORTED (MG with n != 2^L - 1, EXACT with dim > 1), ENOMEM
+ * (allocation failed or workspace too small), EDEVICE. */
 stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau,
                       const stp_kappa* kappa, const double* F, const double* u0,
                       const stp_options* opt, void* workspace, size_t ws_bytes,
@@ -189,9 +239,20 @@ stp_status stp_apply_precond(stp_ctx* ctx, int which, const double* r, double* z
 /* Inexact Uzawa iteration, eq. (3.1), from the initial guess held in u and p
  * (device, N x n^d float64 each, both required; zero them to start from zero).
  * On return u = u_j with j = st->iters, p = p_{j+1}.  Returns OK, ENOTCONV
- * (max_iter reached, the last iterate is returned) or EDIVERGED (the iterate
- * is not meaningful).  st may be NULL. */
+ * (max_iter reached, the last iterate is returned) or EDIVERGED: the residual
+ * ||f - B u_j|| grew above 1e8 times its initial value (and above 1e8 tol ||f||)
+ * or became non-finite.  Growth is caught long before floating-point overflow,
+ * so with finite inputs (stp_create rejects others) the returned u_j, p_{j+1}
+ * are the last iterate and finite.  A diverging solve with an estimated omega
+ * can be repeated with the damping bound of eq. (3.7) (stp_omega_info out[4],
+ * set by stp_set_omega), under which Theorem 3.1 guarantees convergence.
+ * st may be NULL. */
 stp_status stp_uzawa_solve(stp_ctx* ctx, double* u, double* p, stp_stats* st);
+
+/* Stop rule of the following solves (stp_uzawa_solve[_batch], stp_gmres_solve):
+ * tol >= 0 and max_iter >= 0 replace the values given to stp_create, for every
+ * problem of the context.  Captured iteration graphs stay valid.  Errors: EINVAL. */
+stp_status stp_set_stop(stp_ctx* ctx, double tol, int max_iter);
 
 void stp_destroy(stp_ctx* ctx);
 
@@ -201,13 +262,19 @@ void stp_destroy(stp_ctx* ctx);
  * Ritz values of 12 conjugate-gradient steps on S~ preconditioned by H~^{-1},
  * and rho_A by 8 power steps on I - A~^{-1} A, with start vectors from
  * SplitMix64 at the global index (seeds 0x5EED and 0xA5EED).  omega =
- * min(0.95 * 2/(lmin + lmax), 0.9 * 2/lmax).  The estimate runs the
- * iteration's own kernels (about 25 iterations' worth of work) and allocates
- * five float64 vectors per problem for its duration.
- * stp_omega_info: out4 = {omega, lambda_min, lambda_max, rho_A} of problem i
- * (the last three are 0 when omega was given).  stp_set_omega: host array of
- * P values > 0, used from the next solve on.  Errors: EINVAL. */
-stp_status stp_omega_info(stp_ctx* ctx, int i, double* out4);
+ * min(0.95 * 2/(lmin + lmax), 0.9 * 2/lmax).  This balances the two ends of
+ * the spectrum; the sufficient condition (3.7) of Theorem 3.1,
+ * omega lambda_max < 2 (1 - rho_A) / (1 + rho_A), is NOT imposed (with the
+ * rho_A ~ 0.3 of one V-cycle it halves the damping and the iteration count
+ * roughly doubles), so convergence with the estimated omega is observed, not
+ * guaranteed.  The estimate runs the iteration's own kernels (about 25
+ * iterations' worth of work) in the setup scratch of the workspace.
+ * stp_omega_info: out5 = {omega, lambda_min, lambda_max, rho_A, omega_37} of
+ * problem i, omega_37 = 2 (1 - rho_A) / ((1 + rho_A) lambda_max), the bound of
+ * (3.7) from the estimates (lambda_min, lambda_max, rho_A and omega_37 are 0
+ * when omega was given).  stp_set_omega: host array of P values > 0, used from
+ * the next solve on.  Errors: EINVAL. */
+stp_status stp_omega_info(stp_ctx* ctx, int i, double* out5);
 stp_status stp_set_omega(stp_ctx* ctx, const double* omega);
 
 /* GMRES acceleration of the inexact Uzawa method (the solver of the
@@ -254,8 +321,9 @@ stp_status stp_gmres_solve(stp_ctx* ctx, double* u, double* p, int restart, void
  *     columns per block (as LDS allows), or the dense transform (N <= 64).
  * Each candidate is timed over reps launches (after one warm-up) with HIP
  * events; a candidate replaces the current choice only when it is at least 2%
- * faster.  The tuner allocates (and frees) two scratch vectors per problem for
- * its launches, leaves the caller's data untouched, and invalidates the
+ * faster.  The tuner runs its launches on two scratch vectors per problem (the
+ * workspace's scratch region, or a temporary allocation when the library owns
+ * the workspace), leaves the caller's data untouched, and invalidates the
  * captured iteration graph (the next solve captures again).  The result is
  * kept in a process-wide cache keyed by precision, dimension, spatial mode,
  * coefficient rank and the (n, N, rank) of every problem; with use_cache != 0
@@ -290,6 +358,10 @@ stp_status stp_timing_get(stp_ctx* ctx, int idx, const char** name, int* level, 
                           double* total_ms);
 const char* stp_status_string(stp_status s);
 const char* stp_last_error(void);
+/* Total device bytes the library has obtained with hipMalloc in this process
+ * (never decreases).  A diagnostic for callers that pass workspaces: with a
+ * caller workspace, stp_create, stp_autotune and the solves leave it unchanged. */
+size_t stp_device_bytes_allocated(void);
 
 #ifdef __cplusplus
 }

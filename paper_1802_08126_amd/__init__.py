@@ -32,10 +32,13 @@ from .binding import (  # noqa: F401
     stp_create,
     stp_create_batch,
     stp_destroy,
+    stp_device_bytes_allocated,
     stp_gmres_solve,
     stp_gmres_workspace_bytes,
     stp_omega_info,
     stp_set_omega,
+    stp_set_stop,
+    stats_dict,
     stp_schedule_string,
     stp_timing_enable,
     stp_timing_report,

@@ -40,12 +40,27 @@ class stp_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("spatial", C.c_int), ("nu_A", C.c_int), ("nu_H", C.c_int),
                 ("omega", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("kref_coef", C.POINTER(C.c_double)), ("check_every", C.c_int), ("use_graph", C.c_int),
-                ("tau_steps", C.POINTER(C.c_double))]
+                ("tau_steps", C.POINTER(C.c_double)), ("disc", C.c_int),
+                ("sweeps", C.c_int)]
+
+
+STP_NPHASE = 5
+PHASES = ("resid", "atilde", "dst", "hblock", "other")   # STP_PHASE_* order
 
 
 class stp_stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("rel_res", C.c_double), ("omega_used", C.c_double),
-                ("t_solve_ms", C.c_double), ("status", C.c_int)]
+                ("t_solve_ms", C.c_double), ("status", C.c_int), ("rel_rp", C.c_double),
+                ("rel_ru", C.c_double), ("t_setup_ms", C.c_double), ("t_omega_ms", C.c_double),
+                ("t_phase_ms", C.c_double * STP_NPHASE)]
+
+
+def stats_dict(st, status=None):
+    """The fields of an stp_stats as a dict (status: the call's return code if given)."""
+    return dict(status=st.status if status is None else status, iters=st.iters, rel_res=st.rel_res,
+                omega=st.omega_used, ms=st.t_solve_ms, rel_rp=st.rel_rp, rel_ru=st.rel_ru,
+                setup_ms=st.t_setup_ms, omega_ms=st.t_omega_ms,
+                phase_ms=dict(zip(PHASES, list(st.t_phase_ms))))
 
 
 class stp_tune_report(C.Structure):
@@ -98,6 +113,10 @@ def load() -> C.CDLL:
     lib.stp_uzawa_solve_batch.restype = C.c_int
     lib.stp_batch_size.argtypes = [C.c_void_p]
     lib.stp_batch_size.restype = C.c_int
+    lib.stp_device_bytes_allocated.argtypes = []
+    lib.stp_device_bytes_allocated.restype = C.c_size_t
+    lib.stp_set_stop.argtypes = [C.c_void_p, C.c_double, C.c_int]
+    lib.stp_set_stop.restype = C.c_int
     lib.stp_omega_info.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double)]
     lib.stp_omega_info.restype = C.c_int
     lib.stp_set_omega.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
@@ -143,10 +162,15 @@ def _dev_f64(t, shape, name):
     return C.c_void_p(t.data_ptr())
 
 
+STP_DISC = {"fd": 0, "fem": 1}
+
+
 def make_options(precision="f64", spatial="auto", omega=0.8, tol=1e-8, max_iter=500, kref_coef=None,
-                 check_every=8, use_graph=True, nu_A=1, nu_H=1, tau_steps=None):
+                 check_every=8, use_graph=True, nu_A=1, nu_H=1, tau_steps=None, disc="fd", sweeps=1):
     o = stp_options()
     load().stp_default_options(C.byref(o))
+    o.disc = STP_DISC[disc]
+    o.sweeps = sweeps
     o.precision = STP_PREC[precision]
     o.spatial = STP_SPATIAL[spatial]
     o.nu_A, o.nu_H = nu_A, nu_H
@@ -322,9 +346,17 @@ def stp_autotune(ctx, reps=5, use_cache=True):
 
 
 def stp_omega_info(ctx, i=0):
-    out = (C.c_double * 4)()
+    out = (C.c_double * 5)()
     _check(load().stp_omega_info(ctx, int(i), out), "stp_omega_info")
-    return dict(omega=out[0], lmin=out[1], lmax=out[2], rho_A=out[3])
+    return dict(omega=out[0], lmin=out[1], lmax=out[2], rho_A=out[3], omega_37=out[4])
+
+
+def stp_device_bytes_allocated() -> int:
+    return int(load().stp_device_bytes_allocated())
+
+
+def stp_set_stop(ctx, tol, max_iter):
+    _check(load().stp_set_stop(ctx, float(tol), int(max_iter)), "stp_set_stop")
 
 
 def stp_set_omega(ctx, omegas):
@@ -403,7 +435,7 @@ class SpaceTimeSolver:
         u = torch.zeros(self.shape, dtype=torch.float64, device=self.device) if u is None else self._vec(u)
         p = torch.zeros(self.shape, dtype=torch.float64, device=self.device) if p is None else self._vec(p)
         status, st = stp_uzawa_solve(self.ctx, u, p)
-        info = dict(status=status, iters=st.iters, rel_res=st.rel_res, omega=st.omega_used, ms=st.t_solve_ms)
+        info = stats_dict(st, status)
         if raise_on_error and status != STP_OK:
             _check(status, "stp_uzawa_solve")
         if status not in (STP_OK, STP_ENOTCONV, STP_EDIVERGED):
@@ -423,8 +455,8 @@ class SpaceTimeSolver:
         if workspace is None or workspace.numel() * workspace.element_size() < nb:
             workspace = torch.empty((nb + 7) // 8, dtype=torch.float64, device=self.device)
         status, st, hist = stp_gmres_solve(self.ctx, u, p, restart, workspace, self.max_iter)
-        info = dict(status=status, iters=st.iters, rel_res=st.rel_res, omega=st.omega_used, ms=st.t_solve_ms,
-                    history=hist)
+        info = stats_dict(st, status)
+        info["history"] = hist
         if raise_on_error and status != STP_OK:
             _check(status, "stp_gmres_solve")
         if status not in (STP_OK, STP_ENOTCONV, STP_EDIVERGED):
@@ -445,6 +477,11 @@ class SpaceTimeSolver:
 
     def omega_info(self, i=0):
         return stp_omega_info(self.ctx, i)
+
+    def set_stop(self, tol, max_iter):
+        """Stop rule of the following solves (the captured iteration graph stays valid)."""
+        stp_set_stop(self.ctx, tol, max_iter)
+        self.max_iter = int(max_iter)
 
     def close(self):
         if self.ctx:
@@ -478,6 +515,10 @@ class BatchSolver:
     def set_omegas(self, omegas):
         stp_set_omega(self.ctx, omegas)
 
+    def set_stop(self, tol, max_iter):
+        """Stop rule of the following solves of every problem."""
+        stp_set_stop(self.ctx, tol, max_iter)
+
     def solve(self, us=None, ps=None):
         """Solve every problem from (us[i], ps[i]) (zeros if None).  Returns (us, ps, infos, status)."""
         import torch
@@ -490,8 +531,7 @@ class BatchSolver:
         status, sts = stp_uzawa_solve_batch(self.ctx, us, ps)
         if status not in (STP_OK, STP_ENOTCONV, STP_EDIVERGED):
             _check(status, "stp_uzawa_solve_batch")
-        infos = [dict(status=s.status, iters=s.iters, rel_res=s.rel_res, omega=s.omega_used, ms=s.t_solve_ms)
-                 for s in sts]
+        infos = [stats_dict(s) for s in sts]
         return us, ps, infos, status
 
     def timing(self, enable=True):

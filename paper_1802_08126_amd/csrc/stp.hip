@@ -8,12 +8,16 @@
 // table of jobs, one per problem, that the kernels search by block index.
 #include "stp_internal.h"
 
+#include <atomic>
+#include <chrono>
 #include <cstdarg>
 
 // ---------------------------------------------------------------------------
 // error reporting
 // ---------------------------------------------------------------------------
 static thread_local std::string g_last_error;
+// device bytes obtained with hipMalloc by the library in this process (diagnostic)
+static std::atomic<size_t> g_dev_bytes{0};
 
 namespace stpx {
 stp_status fail(stp_status s, const char* fmt, ...) {
@@ -37,6 +41,50 @@ stp_status launch_finalize(stp_ctx* c) {
 }  // namespace stpx
 
 namespace {
+
+constexpr int kDotBlocks = 512;   // partial sums of the setup dot products
+
+// Doubles of setup and tuning scratch a context needs: the omega estimate
+// (five float64 vectors per problem and the dot partials, only when omega is
+// estimated), the autotuner (two float64 vectors per problem) and the kappa
+// check (block partials of one problem's node count); the three uses never
+// overlap in time, so they share one region.
+size_t scratch_doubles(const stp_ctx* c) {
+  size_t est = 0, tune = 0, kap = 0;
+  for (const Problem& q : c->pr) {
+    const size_t nv = size_t(q.N) * size_t(q.g0.npts);
+    est += 5 * nv;
+    tune += 2 * nv;
+    kap = std::max(kap, size_t((q.g0.nnodes + kBlock - 1) / kBlock) + kMaxRank);
+  }
+  if (c->opt.omega > 0 || c->spatial == STP_SPATIAL_NONE) est = 0;
+  else est += c->pr.size() * (kDotBlocks + 1);
+  return std::max(est, std::max(tune, kap));
+}
+
+// Scratch for one use: the region of the caller's workspace, or (when the
+// library owns the workspace) an allocation held until scratch_put.
+stp_status scratch_get(stp_ctx* c, size_t n, double** out, bool* owned) {
+  *owned = false;
+  if (c->scratch_n) {
+    if (n > c->scratch_n) return fail(STP_EDEVICE, "scratch of %zu doubles exceeds its reservation", n);
+    *out = c->scratch;
+    return STP_OK;
+  }
+  if (hipMalloc((void**)out, std::max<size_t>(n, 1) * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return fail(STP_ENOMEM, "hipMalloc of %zu bytes of scratch failed", n * 8);
+  }
+  g_dev_bytes += std::max<size_t>(n, 1) * 8;
+  *owned = true;
+  return STP_OK;
+}
+
+void scratch_put(stp_ctx* c, double* p, bool owned) {
+  (void)hipStreamSynchronize(c->stream);
+  if (owned && p) (void)hipFree(p);
+}
 
 // slabs per block for a launch over `tiles` tiles and S slabs: enough blocks
 // to fill the chip several times over, otherwise runs of up to 16 slabs
@@ -82,7 +130,7 @@ LevelOp family_op(const Problem& q, int l, int fam) {
 }
 
 // Plan (dry run) or carve (real run) one problem's buffers.
-void plan_problem(int prec, int spatial, Problem& q, Bump& bp, bool nux) {
+void plan_problem(int prec, int spatial, Problem& q, Bump& bp, bool nux, bool fem) {
   const size_t tsb = ts_bytes(prec), tcb = tc_bytes(prec);
   const long N = q.N;
   {
@@ -96,6 +144,8 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp, bool nux) {
   q.state = (DevState*)bp.take(sizeof(DevState));
   // residual partials for any slabs-per-block choice (at most one slab per block)
   q.partial = (double*)bp.take(size_t(std::max(q.resid_tiles * q.N, q.nfnorm)) * 8);
+  q.nrm = (double*)bp.take(size_t(2) * kNormBlocks * 8);
+  q.fbind = fem ? (FemBind*)bp.take(sizeof(FemBind)) : nullptr;
   q.kap64 = (double*)bp.take(size_t(q.R) * q.g0.nnodes * 8);
   q.cA64 = (double*)bp.take(size_t(N) * kMaxRank * 8);
   q.taus64 = (double*)bp.take(size_t(N) * 8);
@@ -135,7 +185,60 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp, bool nux) {
     const size_t vb = size_t(N) * L.g.npts * tsb;
     L.b = (l == 0) ? nullptr : bp.take(vb);
     L.e = (l == 0) ? nullptr : bp.take(vb);
+    const bool fx = fem && spatial == STP_SPATIAL_MG && l + 1 < q.lv.size();
+    L.fr = fx ? bp.take(vb) : nullptr;
+    L.fr2 = fx ? bp.take(vb) : nullptr;
   }
+}
+
+// Finite-element stencils of M and A (coefficient kap0) on a uniform mesh with
+// n interior nodes per axis, times scale: P1 in 1-D and 2-D (squares split by
+// the lower-left/upper-right diagonal), Q1 in 3-D; index ((dz+1)*3 + (dy+1))*3
+// + (dx+1).  Element integrals: 1-D mass (h/6)(1, 4, 1), stiffness (1/h)(-1, 2,
+// -1); 2-D P1 mass (h^2/12)(6 at the node, 1 at the four edge neighbours and the
+// two diagonal neighbours along the split), stiffness (4, -1 x 4); 3-D Q1
+// tensor products of the 1-D mass and stiffness.
+FemLevelW fem_stencils(int dim, int n, double kap0, double scale) {
+  FemLevelW w{};
+  const double h = 1.0 / (n + 1);
+  auto m1 = [&](int o) { return (h / 6.0) * (o == 0 ? 4.0 : 1.0); };
+  auto k1 = [&](int o) { return (o == 0 ? 2.0 : -1.0) / h; };
+  if (dim == 1) {
+    for (int dx = -1; dx <= 1; ++dx) {
+      w.m[dx + 1] = m1(dx);
+      w.a[dx + 1] = kap0 * k1(dx);
+    }
+  } else if (dim == 2) {
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int k = (dy + 1) * 3 + (dx + 1);
+        const bool ctr = dx == 0 && dy == 0, edge = (dx == 0) != (dy == 0), diag = dx != 0 && dx == dy;
+        w.m[k] = (h * h / 12.0) * (ctr ? 6.0 : (edge || diag) ? 1.0 : 0.0);
+        w.a[k] = kap0 * (ctr ? 4.0 : edge ? -1.0 : 0.0);
+      }
+  } else {
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int k = ((dz + 1) * 3 + (dy + 1)) * 3 + (dx + 1);
+          w.m[k] = m1(dx) * m1(dy) * m1(dz);
+          w.a[k] = kap0 * (k1(dx) * m1(dy) * m1(dz) + m1(dx) * k1(dy) * m1(dz) + m1(dx) * m1(dy) * k1(dz));
+        }
+  }
+  for (int k = 0; k < 27; ++k) {
+    w.m[k] *= scale;
+    w.a[k] *= scale;
+  }
+  return w;
+}
+
+FemW<double> fem_w64(const Problem& q) {
+  FemW<double> w;
+  for (int k = 0; k < 27; ++k) {
+    w.m[k] = q.fw[0].m[k];
+    w.a[k] = q.fw[0].a[k];
+  }
+  return w;
 }
 
 // largest level (interior nodes per axis) of the fused coarse kernel: four
@@ -440,7 +543,9 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
   S.fin.clear();
   for (size_t i = 0; i < P; ++i) {
     Problem& q = c->pr[i];
-    S.fin.push_back(FinJob{q.partial, q.npart, q.state, c->opt.tol, c->opt.max_iter});
+    // finite elements: the a3 residual writes one partial per block of its (points, slabs) grid
+    const long np = c->disc == STP_DISC_FEM ? q.nfnorm : q.npart;
+    S.fin.push_back(FinJob{q.partial, np, q.state, c->opt.tol, c->opt.max_iter});
   }
 }
 
@@ -550,6 +655,12 @@ stp_status bind_jobs(stp_ctx* c, const std::vector<double*>& u, const std::vecto
       j.alpha = alpha < 0 ? c->pr[i].omega : alpha;
     }
   stp_status st;
+  if (c->disc == STP_DISC_FEM) {   // single problem: the vectors the FEM kernels read when they run
+    Problem& q = c->pr[0];
+    const FemBind fb{u[0], p[0], Fz ? (*Fz)[0] : q.F, Fz ? (*Fz)[0] : q.u0, acc_p[0]};
+    HIP_TRY(hipMemcpyAsync(q.fbind, &fb, sizeof(FemBind), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
   if ((st = upload_site(c, S.resid[0])) != STP_OK) return st;
   if ((st = upload_site(c, S.resid[1])) != STP_OK) return st;
   if (!A.up.empty() && (st = upload_site(c, A.up[0])) != STP_OK) return st;
@@ -590,6 +701,10 @@ stp_status validate_opts(const stp_options* opt) {
     return fail(STP_EINVAL, "nu_A and nu_H must lie in 1..%d", kMaxNu);
   if (!(opt->tol >= 0)) return fail(STP_EINVAL, "tol must be >= 0");
   if (opt->max_iter < 0) return fail(STP_EINVAL, "max_iter must be >= 0");
+  if (opt->disc != STP_DISC_FD && opt->disc != STP_DISC_FEM) return fail(STP_EINVAL, "bad discretisation %d", opt->disc);
+  if (opt->disc == STP_DISC_FEM && (opt->nu_A != 1 || opt->nu_H != 1))
+    return fail(STP_EUNSUPPORTED, "finite elements run one V-cycle per spatial solve (nu_A = nu_H = 1)");
+  if (opt->sweeps < 0 || opt->sweeps > 4) return fail(STP_EINVAL, "sweeps must lie in 0..4");
   return STP_OK;
 }
 
@@ -616,7 +731,6 @@ stp_status validate_opts(const stp_options* opt) {
 // ---------------------------------------------------------------------------
 constexpr int kLanczosSteps = 12;
 constexpr int kPowerSteps = 8;
-constexpr int kDotBlocks = 512;
 constexpr unsigned long long kSeedLanczos = 0x5EEDull;
 constexpr unsigned long long kSeedPower = 0xA5EEDull;
 
@@ -661,10 +775,9 @@ stp_status estimate_omega(stp_ctx* c) {
   }
   const size_t scal = P * (kDotBlocks + 1);
   double* mem = nullptr;
-  if (hipMalloc((void**)&mem, (total + scal) * 8) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(STP_ENOMEM, "omega estimate: hipMalloc of %zu bytes failed", (total + scal) * 8);
-  }
+  bool owned = false;
+  stp_status s0 = scratch_get(c, total + scal, &mem, &owned);
+  if (s0 != STP_OK) return s0;
   std::vector<double*> r(P), z(P), d(P), q(P), pb(P);
   {
     size_t off = 0;
@@ -813,8 +926,7 @@ stp_status estimate_omega(stp_ctx* c) {
     return STP_OK;
   };
   const stp_status s = body();
-  (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(mem);
+  scratch_put(c, mem, owned);
   return s;
 }
 
@@ -847,11 +959,19 @@ stp_status describe(stp_ctx* c, int P, const stp_grid* grids, const int* N, cons
     if (s != STP_OK) return s;
   }
   c->rm = rmax <= 1 ? 1 : (rmax <= 2 ? 2 : 4);
+  if (c->disc == STP_DISC_FEM) {
+    if (P != 1) return fail(STP_EUNSUPPORTED, "finite elements: single-problem contexts only");
+    if (c->pr[0].R != 1) return fail(STP_EUNSUPPORTED, "finite elements: kappa must have rank 1 (a constant field)");
+    if (c->spatial == STP_SPATIAL_MG && c->dim == 1)
+      return fail(STP_EUNSUPPORTED, "finite elements in 1-D use exact spatial solves");
+    if (c->spatial == STP_SPATIAL_MG && c->pr[0].n < 3)
+      return fail(STP_EUNSUPPORTED, "finite-element multigrid needs n = 2^L - 1 >= 3");
+  }
   return STP_OK;
 }
 
 size_t plan_all(stp_ctx* c, Bump& bp) {
-  for (auto& q : c->pr) plan_problem(c->prec, c->spatial, q, bp, multi_cycle(c));
+  for (auto& q : c->pr) plan_problem(c->prec, c->spatial, q, bp, multi_cycle(c), c->disc == STP_DISC_FEM);
   std::vector<double*> nul(c->P, nullptr);
   build_sites(c, nul, nul);
   c->tables_off = (bp.off + 255) & ~size_t(255);
@@ -896,6 +1016,8 @@ const char* stp_status_string(stp_status s) {
 
 const char* stp_last_error(void) { return g_last_error.c_str(); }
 
+size_t stp_device_bytes_allocated(void) { return g_dev_bytes.load(); }
+
 size_t stp_workspace_bytes_batch(int P, const stp_grid* grids, const int* N, const int* rank,
                                  const stp_options* opt) {
   if (P < 1 || !grids || !N || !rank || !opt) return 0;
@@ -908,11 +1030,12 @@ size_t stp_workspace_bytes_batch(int P, const stp_grid* grids, const int* N, con
   stp_ctx c;
   c.opt = *opt;
   c.prec = opt->precision;
+  c.disc = opt->disc;
   std::vector<stp_kappa> kap(P);
   for (int i = 0; i < P; ++i) kap[i].rank = rank[i];
   if (describe(&c, P, grids, N, nullptr, kap.data(), nullptr, nullptr) != STP_OK) return 0;
   Bump bp;
-  return plan_all(&c, bp);
+  return ((plan_all(&c, bp) + 255) & ~size_t(255)) + scratch_doubles(&c) * 8;
 }
 
 size_t stp_workspace_bytes(const stp_grid* g, int N, int rank, const stp_options* opt) {
@@ -922,6 +1045,7 @@ size_t stp_workspace_bytes(const stp_grid* g, int N, int rank, const stp_options
 stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const int* N, const double* tau,
                             const stp_kappa* kappa, const double* const* F, const double* const* u0,
                             const stp_options* opt_in, void* workspace, size_t ws_bytes, void* hip_stream) {
+  const auto t_start = std::chrono::steady_clock::now();
   if (!out) return fail(STP_EINVAL, "NULL output context pointer");
   *out = nullptr;
   if (P < 1 || !grids || !N || !tau || !kappa || !F || !u0) return fail(STP_EINVAL, "NULL batch argument or P < 1");
@@ -956,6 +1080,7 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
   std::unique_ptr<stp_ctx> c(new stp_ctx());
   c->opt = opt;
   c->prec = opt.precision;
+  c->disc = opt.disc;
   c->stream = (hipStream_t)hip_stream;
   if ((s = describe(c.get(), P, grids, N, tref.data(), kappa, F, u0)) != STP_OK) return s;
   for (int i = 0; i < P; ++i) {
@@ -986,21 +1111,27 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
   }
   Bump dry;
   const size_t need = plan_all(c.get(), dry);
-  if (workspace) {
-    if (ws_bytes < need) return fail(STP_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  if (workspace) {   // [solver buffers | launch tables | setup and tuning scratch]
+    const size_t soff = (need + 255) & ~size_t(255);
+    const size_t sn = scratch_doubles(c.get());
+    if (ws_bytes < soff + sn * 8)
+      return fail(STP_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, soff + sn * 8);
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(STP_EINVAL, "workspace not 256-byte aligned");
     c->ws = workspace;
-  } else {
+    c->scratch = reinterpret_cast<double*>((char*)workspace + soff);
+    c->scratch_n = sn;
+  } else {   // the scratch is then allocated for the duration of each use
     if (hipMalloc(&c->ws, need) != hipSuccess) {
       (void)hipGetLastError();
       return fail(STP_ENOMEM, "hipMalloc of %zu bytes failed", need);
     }
+    g_dev_bytes += need;
     c->own_ws = true;
   }
   Bump real;
   real.dry = false;
   real.base = (char*)c->ws;
-  for (auto& q : c->pr) plan_problem(c->prec, c->spatial, q, real, multi_cycle(c.get()));
+  for (auto& q : c->pr) plan_problem(c->prec, c->spatial, q, real, multi_cycle(c.get()), c->disc == STP_DISC_FEM);
   HIP_TRY(hipHostMalloc((void**)&c->state_host, sizeof(DevState) * P, hipHostMallocDefault));
   HIP_TRY(hipEventCreate(&c->ev0));
   HIP_TRY(hipEventCreate(&c->ev1));
@@ -1016,7 +1147,8 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
     const long nn = q.g0.nnodes;
     const long nb = (nn + kBlock - 1) / kBlock;
     double* scratch = nullptr;
-    HIP_TRY(hipMallocAsync((void**)&scratch, size_t(nb + kMaxRank) * 8, c->stream));
+    bool owned = false;
+    if ((s = scratch_get(c.get(), size_t(nb + kMaxRank), &scratch, &owned)) != STP_OK) return s;
     std::vector<double> cref(kMaxRank, 0.0);
     for (int r = 0; r < q.R; ++r) cref[r] = q.abar[r];
     double* part = scratch + kMaxRank;
@@ -1031,11 +1163,36 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
       HIP_TRY(hipStreamSynchronize(c->stream));
       mn = std::min(mn, *std::min_element(h.begin(), h.end()));
     }
-    HIP_TRY(hipFreeAsync(scratch, c->stream));
+    double spread = 0.0, kap0 = 0.0;
+    if (c->disc == STP_DISC_FEM) {   // the coefficient must be constant in space
+      const long gb = std::min(nb, 512L);
+      KLAUNCH(k_field_spread, dim3(unsigned(gb)), dim3(kBlock), 0, c->stream, nn, q.fields, part);
+      LAUNCH_CHECK();
+      HIP_TRY(hipMemcpyAsync(h.data(), part, size_t(gb) * 8, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipMemcpyAsync(&kap0, q.fields, 8, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      spread = *std::max_element(h.begin(), h.begin() + gb);
+    }
+    scratch_put(c.get(), scratch, owned);
     if (!(mn > 0)) return fail(STP_EINVAL, "kappa must be > 0 at every node and step (min %.3e)", mn);
+    if (c->disc == STP_DISC_FEM) {
+      if (!(spread == 0.0)) return fail(STP_EINVAL, "finite elements: the kappa field must be constant in space");
+      // element stencils of every level: the Galerkin operators of the coarse meshes, 2^-d per level
+      q.fw.clear();
+      for (size_t l = 0; l < q.lv.size(); ++l)
+        q.fw.push_back(fem_stencils(q.dim, q.lv[l].n, kap0, std::ldexp(1.0, -int(q.dim * l))));
+    }
     // ||f||
     const dim3 gr = grid_pts(q.g0.npts, q.N);
-    KLAUNCH(k_fnorm, gr, dim3(kBlock), 0, c->stream, q.g0, q.N, (const double*)q.taus64, q.F, q.u0, q.partial);
+    if (c->disc == STP_DISC_FEM) {
+      switch (q.dim) {
+        case 1: KLAUNCH(k_fem_fnorm<1>, gr, dim3(kBlock), 0, c->stream, q.g0, q.N, fem_w64(q), (const double*)q.taus64, q.F, q.u0, q.partial); break;
+        case 2: KLAUNCH(k_fem_fnorm<2>, gr, dim3(kBlock), 0, c->stream, q.g0, q.N, fem_w64(q), (const double*)q.taus64, q.F, q.u0, q.partial); break;
+        default: KLAUNCH(k_fem_fnorm<3>, gr, dim3(kBlock), 0, c->stream, q.g0, q.N, fem_w64(q), (const double*)q.taus64, q.F, q.u0, q.partial);
+      }
+    } else {
+      KLAUNCH(k_fnorm, gr, dim3(kBlock), 0, c->stream, q.g0, q.N, (const double*)q.taus64, q.F, q.u0, q.partial);
+    }
     LAUNCH_CHECK();
     KLAUNCH(k_sum_to, dim3(1), dim3(kBlock), 0, c->stream, (const double*)q.partial, q.nfnorm, &q.state->fnorm);
     LAUNCH_CHECK();
@@ -1043,6 +1200,7 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
     HIP_TRY(hipMemcpyAsync(&hs, q.state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     q.fnorm = std::sqrt(hs.fnorm);
+    if (!std::isfinite(q.fnorm)) return fail(STP_EINVAL, "F or u0 holds a non-finite value");
   }
   // launch tables (jobs point at null u, p until a solve binds them)
   std::vector<double*> nul(P, nullptr);
@@ -1051,12 +1209,16 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
   carve_tables(c->sites, (char*)c->ws + c->tables_off);
   if ((s = upload_all(c.get())) != STP_OK) return s;
   if (c->spatial != STP_SPATIAL_NONE) {
+    const auto te = std::chrono::steady_clock::now();
     if ((s = estimate_omega(c.get())) != STP_OK) return s;
+    if (!(opt.omega > 0))   // estimated: the time it took (a given omega costs nothing)
+      c->t_omega_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - te).count();
     build_sites(c.get(), nul, nul);   // f from F and u0 again; omega into the transform jobs
     carve_tables(c->sites, (char*)c->ws + c->tables_off);
     if ((s = upload_all(c.get())) != STP_OK) return s;
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
+  c->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   *out = c.release();
   return STP_OK;
 }
@@ -1073,13 +1235,15 @@ stp_status stp_create(stp_ctx** out, const stp_grid* g, int N, double tau, const
 
 int stp_batch_size(stp_ctx* c) { return c ? c->P : 0; }
 
-stp_status stp_omega_info(stp_ctx* c, int i, double* out4) {
-  if (!c || !out4 || i < 0 || i >= c->P) return fail(STP_EINVAL, "bad context, problem index or output");
+stp_status stp_omega_info(stp_ctx* c, int i, double* out5) {
+  if (!c || !out5 || i < 0 || i >= c->P) return fail(STP_EINVAL, "bad context, problem index or output");
   const Problem& q = c->pr[i];
-  out4[0] = q.omega;
-  out4[1] = q.est_lmin;
-  out4[2] = q.est_lmax;
-  out4[3] = q.est_rho;
+  out5[0] = q.omega;
+  out5[1] = q.est_lmin;
+  out5[2] = q.est_lmax;
+  out5[3] = q.est_rho;
+  // damping bound of eq. (3.7) from the estimates (0 when omega was given)
+  out5[4] = q.est_lmax > 0 ? 2.0 * (1.0 - q.est_rho) / ((1.0 + q.est_rho) * q.est_lmax) : 0.0;
   return STP_OK;
 }
 
@@ -1089,6 +1253,23 @@ stp_status stp_set_omega(stp_ctx* c, const double* omega) {
     if (!(omega[i] > 0) || !std::isfinite(omega[i])) return fail(STP_EINVAL, "omega[%d] must be finite and > 0", i);
   for (int i = 0; i < c->P; ++i) c->pr[i].omega = omega[i];
   return STP_OK;   // taken into the launch tables when the next solve binds its vectors
+}
+
+stp_status stp_set_stop(stp_ctx* c, double tol, int max_iter) {
+  if (!c) return fail(STP_EINVAL, "NULL context");
+  if (!(tol >= 0) || !std::isfinite(tol)) return fail(STP_EINVAL, "tol must be finite and >= 0");
+  if (max_iter < 0) return fail(STP_EINVAL, "max_iter must be >= 0");
+  c->opt.tol = tol;
+  c->opt.max_iter = max_iter;
+  for (auto& j : c->sites.fin) {
+    j.tol = tol;
+    j.max_iter = max_iter;
+  }
+  // the stop-test kernel reads these when it runs, so captured graphs stay valid
+  HIP_TRY(hipMemcpyAsync(c->sites.fin_dev, c->sites.fin.data(), c->sites.fin.size() * sizeof(FinJob),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return STP_OK;
 }
 
 void stp_destroy(stp_ctx* c) {
@@ -1115,6 +1296,28 @@ stp_status stp_apply_operator(stp_ctx* c, int op, const double* x, double* y) {
   const dim3 gr = grid_pts(q.g0.npts, q.N);
   TimeOp t{q.kap64, q.cA64, q.R, q.N};
   const long nv = long(q.N) * q.g0.npts;
+  if (c->disc == STP_DISC_FEM) {
+    const FemW<double> w = fem_w64(q);
+    const double* cA = q.cA64;
+    const double* taus = q.taus64;
+    if (op == STP_OP_B) {
+      switch (c->dim) {
+        case 1: KLAUNCH(k_fem_apply_B<1>, gr, dim3(kBlock), 0, c->stream, q.g0, q.N, w, cA, x, y); break;
+        case 2: KLAUNCH(k_fem_apply_B<2>, gr, dim3(kBlock), 0, c->stream, q.g0, q.N, w, cA, x, y); break;
+        default: KLAUNCH(k_fem_apply_B<3>, gr, dim3(kBlock), 0, c->stream, q.g0, q.N, w, cA, x, y);
+      }
+    } else if (op == STP_OP_SADDLE) {
+      switch (c->dim) {
+        case 1: KLAUNCH((k_fem_saddle<1, false>), gr, dim3(kBlock), 0, c->stream, q.g0, q.N, w, taus, cA, q.F, q.u0, x, x + nv, y, y + nv); break;
+        case 2: KLAUNCH((k_fem_saddle<2, false>), gr, dim3(kBlock), 0, c->stream, q.g0, q.N, w, taus, cA, q.F, q.u0, x, x + nv, y, y + nv); break;
+        default: KLAUNCH((k_fem_saddle<3, false>), gr, dim3(kBlock), 0, c->stream, q.g0, q.N, w, taus, cA, q.F, q.u0, x, x + nv, y, y + nv);
+      }
+    } else {
+      return fail(STP_EINVAL, "unknown operator %d", op);
+    }
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
   if (op == STP_OP_B) {
     switch (c->dim) {
       case 1: KLAUNCH(k_apply_B<1>, gr, dim3(kBlock), 0, c->stream, q.g0, t, x, y); break;
@@ -1190,6 +1393,46 @@ GmresLayout gmres_layout(const Problem& q, int m) {
   return L;
 }
 
+// ||r_p||^2 and ||r_u||^2 of the pair (u, p) of problem i into its state
+// (rp2, ru2): one pass over u, p and F after a solve.
+stp_status pair_norms(stp_ctx* c, int i, const double* u, const double* p) {
+  Problem& q = c->pr[i];
+  const TimeOp t{q.kap64, q.cA64, q.R, q.N};
+  const long nb = std::max(1L, std::min(long(kNormBlocks), (q.g0.npts + kBlock - 1) / kBlock));
+  c->kt.level = 0;
+  if (c->disc == STP_DISC_FEM) {
+    const FemW<double> w = fem_w64(q);
+    switch (c->dim) {
+      case 1: KLAUNCH(k_fem_saddle_norms<1>, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, q.g0, q.N, w, (const double*)q.taus64, (const double*)q.cA64, q.F, q.u0, p, u, q.nrm); break;
+      case 2: KLAUNCH(k_fem_saddle_norms<2>, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, q.g0, q.N, w, (const double*)q.taus64, (const double*)q.cA64, q.F, q.u0, p, u, q.nrm); break;
+      default: KLAUNCH(k_fem_saddle_norms<3>, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, q.g0, q.N, w, (const double*)q.taus64, (const double*)q.cA64, q.F, q.u0, p, u, q.nrm);
+    }
+    LAUNCH_CHECK();
+    KLAUNCH(k_sum_rows, dim3(2), dim3(kBlock), 0, c->stream, (const double*)q.nrm, nb, &q.state->rp2);
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+  switch (c->dim) {
+    case 1: KLAUNCH(k_saddle_norms<1>, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm); break;
+    case 2: KLAUNCH(k_saddle_norms<2>, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm); break;
+    default: KLAUNCH(k_saddle_norms<3>, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm);
+  }
+  LAUNCH_CHECK();
+  KLAUNCH(k_sum_rows, dim3(2), dim3(kBlock), 0, c->stream, (const double*)q.nrm, nb, &q.state->rp2);
+  LAUNCH_CHECK();
+  return STP_OK;
+}
+
+// Device time per phase of the timing records r0 .. r1-1 (0 unless timing is on).
+void phase_times(stp_ctx* c, size_t r0, size_t r1, double* out) {
+  for (int k = 0; k < PH_COUNT; ++k) out[k] = 0.0;
+  if (!c->kt.on) return;
+  for (size_t k = r0; k < r1 && k < c->kt.recs.size(); ++k) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->kt.recs[k].a, c->kt.recs[k].b) == hipSuccess) out[c->kt.recs[k].phase] += ms;
+  }
+}
+
 // Capture the launches of body on a private stream (capture is not possible on
 // the null stream) and instantiate them into *out.
 stp_status capture_graph(stp_ctx* c, hipGraphExec_t* out, const std::function<stp_status()>& body) {
@@ -1227,20 +1470,28 @@ size_t stp_gmres_workspace_bytes(stp_ctx* c, int restart) {
   return gmres_layout(c->pr[0], restart).total * 8;
 }
 
-stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* ws, size_t ws_bytes, double* hist,
-                           stp_stats* stats) {
+}  // extern "C"
+
+namespace {
+
+// Arguments common to both GMRES entry points.
+stp_status gmres_check(stp_ctx* c, double* u, double* p, int restart) {
   if (!c || !u || !p) return fail(STP_EINVAL, "NULL argument (u and p are required)");
-  if (c->P != 1) return fail(STP_EUNSUPPORTED, "stp_gmres_solve needs a single-problem context");
+  if (c->P != 1) return fail(STP_EUNSUPPORTED, "GMRES needs a single-problem context");
   if (c->spatial == STP_SPATIAL_NONE) return fail(STP_EUNSUPPORTED, "context created without a spatial solver");
   if (restart < 1 || restart > kMaxRestart) return fail(STP_EINVAL, "restart %d not in 1..%d", restart, kMaxRestart);
+  return STP_OK;
+}
+
+// Flexible GMRES(restart) around the Uzawa sweep with its vectors at base
+// (gmres_layout doubles).  graph: replay the two preconditioner solves as
+// captured HIP graphs (captured on first use); false launches them eagerly.
+stp_status gmres_run(stp_ctx* c, double* u, double* p, int restart, double* base, bool graph, double* hist,
+                     stp_stats* stats) {
   Problem& q = c->pr[0];
   const GmresLayout L = gmres_layout(q, restart);
-  if (!ws || ws_bytes < L.total * 8)
-    return fail(STP_EINVAL, "GMRES workspace of %zu bytes given, %zu needed", ws_bytes, L.total * 8);
-  if (reinterpret_cast<uintptr_t>(ws) % 8) return fail(STP_EINVAL, "GMRES workspace not 8-byte aligned");
   const long nv = long(q.N) * q.g0.npts;
   const long v2 = long(L.v2);
-  double* base = static_cast<double*>(ws);
   double* V = base + L.V;
   double* Z = base + L.Z;
   double* uc = base + L.ucand;
@@ -1250,7 +1501,8 @@ stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* 
   const dim3 gp = grid_pts(q.g0.npts, q.N);
   const long fparts = long(gp.x) * gp.y * gp.z;
   const TimeOp t{q.kap64, q.cA64, q.R, q.N};
-  const double fnorm = q.fnorm, gnorm = std::sqrt(2.0) * q.fnorm;
+  // f = 0: the stop test and the reported residuals are absolute
+  const double fnorm = q.fnorm > 0 ? q.fnorm : 1.0, gnorm = std::sqrt(2.0) * fnorm;
   const double omega = q.omega, tol = c->opt.tol;
   const int max_iter = c->opt.max_iter;
   auto vgrid = [](long n) { return dim3(unsigned((n + kBlock - 1) / kBlock)); };
@@ -1260,11 +1512,20 @@ stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* 
   c->state_host[0] = DevState{};
   c->state_host[0].fnorm = q.fnorm;
   HIP_TRY(hipMemcpyAsync(q.state, &c->state_host[0], sizeof(DevState), hipMemcpyHostToDevice, c->stream));
+  const size_t rec0 = c->kt.recs.size();
   HIP_TRY(hipEventRecord(c->ev0, c->stream));
 
   // ||f - B uu||_2 (synchronises)
+  const bool fem = c->disc == STP_DISC_FEM;
+  const FemW<double> fw64 = fem ? fem_w64(q) : FemW<double>{};
   auto fmBu = [&](const double* uu, double& out) -> stp_status {
-    switch (c->dim) {
+    if (fem) {
+      switch (c->dim) {
+        case 1: KLAUNCH(k_fem_fmBu_partial<1>, gp, dim3(kBlock), 0, c->stream, q.g0, q.N, fw64, (const double*)q.taus64, (const double*)q.cA64, q.F, q.u0, uu, part); break;
+        case 2: KLAUNCH(k_fem_fmBu_partial<2>, gp, dim3(kBlock), 0, c->stream, q.g0, q.N, fw64, (const double*)q.taus64, (const double*)q.cA64, q.F, q.u0, uu, part); break;
+        default: KLAUNCH(k_fem_fmBu_partial<3>, gp, dim3(kBlock), 0, c->stream, q.g0, q.N, fw64, (const double*)q.taus64, (const double*)q.cA64, q.F, q.u0, uu, part);
+      }
+    } else switch (c->dim) {
       case 1: KLAUNCH(k_fmBu_partial<1>, gp, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, uu, part); break;
       case 2: KLAUNCH(k_fmBu_partial<2>, gp, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, uu, part); break;
       default: KLAUNCH(k_fmBu_partial<3>, gp, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, uu, part);
@@ -1313,7 +1574,6 @@ stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* 
   // z = P^{-1} v: one Uzawa sweep from zero, [A~^{-1} v_p; -omega H~^{-1}(v_u + K^T A~^{-1} v_p)].
   // The two solves replay captured graphs (they read the job tables, rebound
   // for every z, at replay time).
-  const bool graph = c->opt.use_graph && !c->kt.on;
   if (graph && !c->gexecA) {
     stp_status s = capture_graph(c, &c->gexecA, [c]() { return c->impl->run_vcycle(VC_A); });
     if (s != STP_OK) return s;
@@ -1328,8 +1588,10 @@ stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* 
     std::vector<double*> zp(1, zj), zu(1, zj + nv);
     if ((s = bind_jobs(c, zp, zp, nullptr, zp, zu, omega)) != STP_OK) return s;
     if ((s = c->impl->cast_in(vj, q.W1, nv)) != STP_OK) return s;
+    c->kt.phase = PH_ATILDE;
     if (graph) HIP_TRY(hipGraphLaunch(c->gexecA, c->stream));             // z_p += A~^{-1} v_p
     else if ((s = c->impl->run_vcycle(VC_A)) != STP_OK) return s;
+    c->kt.phase = PH_OTHER;
     if ((s = c->impl->kt_add_in(vj + nv, zj, -1.0)) != STP_OK) return s;  // W1 = -(v_u + K^T z_p)
     if (graph) HIP_TRY(hipGraphLaunch(c->gexecH, c->stream));             // z_u += omega H~^{-1} W1
     else if ((s = c->impl->run_precH()) != STP_OK) return s;
@@ -1360,7 +1622,12 @@ stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* 
     if (res <= tol * fnorm) { outcome = 1; break; }
     if (iters >= max_iter) break;
     const int m = std::min(restart, max_iter - iters);
-    switch (c->dim) {   // v_0 = g - S x
+    if (fem) switch (c->dim) {   // v_0 = g - S x
+      case 1: KLAUNCH((k_fem_saddle<1, true>), gp, dim3(kBlock), 0, c->stream, q.g0, q.N, fw64, (const double*)q.taus64, (const double*)q.cA64, q.F, q.u0, p, u, V, V + nv); break;
+      case 2: KLAUNCH((k_fem_saddle<2, true>), gp, dim3(kBlock), 0, c->stream, q.g0, q.N, fw64, (const double*)q.taus64, (const double*)q.cA64, q.F, q.u0, p, u, V, V + nv); break;
+      default: KLAUNCH((k_fem_saddle<3, true>), gp, dim3(kBlock), 0, c->stream, q.g0, q.N, fw64, (const double*)q.taus64, (const double*)q.cA64, q.F, q.u0, p, u, V, V + nv);
+    }
+    else switch (c->dim) {   // v_0 = g - S x
       case 1: KLAUNCH(k_saddle_resid<1>, gp, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, V, V + nv); break;
       case 2: KLAUNCH(k_saddle_resid<2>, gp, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, V, V + nv); break;
       default: KLAUNCH(k_saddle_resid<3>, gp, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, V, V + nv);
@@ -1385,7 +1652,12 @@ stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* 
       double* zj = Z + j * v2;
       double* w = V + (j + 1) * v2;
       if ((s = precond(vj, zj)) != STP_OK) return s;
-      switch (c->dim) {   // w = S z_j
+      if (fem) switch (c->dim) {   // w = S z_j
+        case 1: KLAUNCH((k_fem_saddle<1, false>), gp, dim3(kBlock), 0, c->stream, q.g0, q.N, fw64, (const double*)q.taus64, (const double*)q.cA64, q.F, q.u0, zj, zj + nv, w, w + nv); break;
+        case 2: KLAUNCH((k_fem_saddle<2, false>), gp, dim3(kBlock), 0, c->stream, q.g0, q.N, fw64, (const double*)q.taus64, (const double*)q.cA64, q.F, q.u0, zj, zj + nv, w, w + nv); break;
+        default: KLAUNCH((k_fem_saddle<3, false>), gp, dim3(kBlock), 0, c->stream, q.g0, q.N, fw64, (const double*)q.taus64, (const double*)q.cA64, q.F, q.u0, zj, zj + nv, w, w + nv);
+      }
+      else switch (c->dim) {   // w = S z_j
         case 1: KLAUNCH(k_apply_saddle<1>, gp, dim3(kBlock), 0, c->stream, q.g0, t, zj, zj + nv, w, w + nv); break;
         case 2: KLAUNCH(k_apply_saddle<2>, gp, dim3(kBlock), 0, c->stream, q.g0, t, zj, zj + nv, w, w + nv); break;
         default: KLAUNCH(k_apply_saddle<3>, gp, dim3(kBlock), 0, c->stream, q.g0, t, zj, zj + nv, w, w + nv);
@@ -1449,7 +1721,11 @@ stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* 
     if (k == 0) { outcome = 4; break; }
   }
   HIP_TRY(hipEventRecord(c->ev1, c->stream));
-  HIP_TRY(hipEventSynchronize(c->ev1));
+  const size_t r1 = c->kt.recs.size();
+  c->kt.phase = PH_OTHER;
+  if ((s = pair_norms(c, 0, u, p)) != STP_OK) return s;
+  HIP_TRY(hipMemcpyAsync(&c->state_host[0], q.state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
   const stp_status r = outcome == 1 ? STP_OK : outcome == 2 ? STP_EDIVERGED : STP_ENOTCONV;
@@ -1459,11 +1735,30 @@ stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* 
     stats->omega_used = omega;
     stats->t_solve_ms = ms;
     stats->status = r;
+    stats->rel_rp = std::sqrt(std::max(c->state_host[0].rp2, 0.0)) / fnorm;
+    stats->rel_ru = std::sqrt(std::max(c->state_host[0].ru2, 0.0)) / fnorm;
+    stats->t_setup_ms = c->t_setup_ms;
+    stats->t_omega_ms = c->t_omega_ms;
+    phase_times(c, rec0, r1, stats->t_phase_ms);
   }
   if (outcome == 2) return fail(r, "GMRES: non-finite residual after %d steps", iters);
   if (outcome == 4) return fail(r, "GMRES: breakdown after %d steps (rel %.3e)", iters, res / fnorm);
   if (outcome == 3) return fail(r, "GMRES: max_iter %d reached (rel %.3e)", max_iter, res / fnorm);
   return STP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* ws, size_t ws_bytes, double* hist,
+                           stp_stats* stats) {
+  stp_status s = gmres_check(c, u, p, restart);
+  if (s != STP_OK) return s;
+  const GmresLayout L = gmres_layout(c->pr[0], restart);
+  if (!ws || ws_bytes < L.total * 8)
+    return fail(STP_EINVAL, "GMRES workspace of %zu bytes given, %zu needed", ws_bytes, L.total * 8);
+  if (reinterpret_cast<uintptr_t>(ws) % 8) return fail(STP_EINVAL, "GMRES workspace not 8-byte aligned");
+  return gmres_run(c, u, p, restart, static_cast<double*>(ws), c->opt.use_graph && !c->kt.on, hist, stats);
 }
 
 // Capture one iteration over the batch on a private stream (capture is not
@@ -1492,6 +1787,7 @@ stp_status stp_uzawa_solve_batch(stp_ctx* c, double* const* u, double* const* p,
   if ((s = bind_solution(c, uv, pv, uv, -1.0)) != STP_OK) return s;
   const bool graph = c->opt.use_graph && !c->kt.on;
   if (graph && (s = capture_iteration(c)) != STP_OK) return s;
+  const size_t rec0 = c->kt.recs.size();
   HIP_TRY(hipEventRecord(c->ev0, c->stream));
   const int chunk = std::max(1, c->opt.check_every);
   const int max_launch = c->opt.max_iter + 1;   // iterations 0..max_iter each evaluate the stop test
@@ -1514,19 +1810,33 @@ stp_status stp_uzawa_solve_batch(stp_ctx* c, double* const* u, double* const* p,
     if (launched >= max_launch) return fail(STP_EDEVICE, "iteration state did not terminate");
   }
   HIP_TRY(hipEventRecord(c->ev1, c->stream));
-  HIP_TRY(hipEventSynchronize(c->ev1));
+  const size_t r1 = c->kt.recs.size();
+  c->kt.phase = PH_OTHER;
+  for (int i = 0; i < c->P; ++i)   // residual blocks of the returned pairs (outside the timed loop)
+    if ((s = pair_norms(c, i, uv[i], pv[i])) != STP_OK) return s;
+  for (int i = 0; i < c->P; ++i)
+    HIP_TRY(hipMemcpyAsync(&c->state_host[i], c->pr[i].state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  double tph[PH_COUNT];
+  phase_times(c, rec0, r1, tph);   // the norm pass is not part of the solve's phases
   stp_status worst = STP_OK;
   for (int i = 0; i < c->P; ++i) {
     const DevState& hs = c->state_host[i];
     const stp_status r = hs.done == 1 ? STP_OK : (hs.done == 2 ? STP_EDIVERGED : STP_ENOTCONV);
     if (stats) {
+      const double den = c->pr[i].fnorm > 0 ? c->pr[i].fnorm : 1.0;
       stats[i].iters = hs.iter;
       stats[i].rel_res = hs.rel;
       stats[i].omega_used = c->pr[i].omega;
       stats[i].t_solve_ms = ms;
       stats[i].status = r;
+      stats[i].rel_rp = std::sqrt(std::max(hs.rp2, 0.0)) / den;
+      stats[i].rel_ru = std::sqrt(std::max(hs.ru2, 0.0)) / den;
+      stats[i].t_setup_ms = c->t_setup_ms;
+      stats[i].t_omega_ms = c->t_omega_ms;
+      for (int k = 0; k < PH_COUNT; ++k) stats[i].t_phase_ms[k] = tph[k];
     }
     if (r == STP_EDIVERGED) {
       worst = r;
@@ -1569,6 +1879,7 @@ std::string tune_key(stp_ctx* c) {
 // slabs per block that knob k with exponent e gives each job (empty: knob unused)
 std::vector<int> knob_sbs(stp_ctx* c, int k, int e) {
   std::vector<int> v;
+  if (c->disc == STP_DISC_FEM) return v;   // finite elements: one thread per node, no tile schedule
   for (auto& q : c->pr) {
     const bool mg = c->spatial == STP_SPATIAL_MG;
     long tiles = -1;
@@ -1695,10 +2006,8 @@ stp_status stp_autotune(stp_ctx* c, int reps, int use_cache, stp_tune_report* re
   size_t total = 0;
   for (auto& q : c->pr) total += size_t(2) * q.N * q.g0.npts;
   double* tmp = nullptr;
-  if (hipMalloc((void**)&tmp, total * 8) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(STP_ENOMEM, "autotune: hipMalloc of %zu bytes failed", total * 8);
-  }
+  bool owned = false;
+  if ((s = scratch_get(c, total, &tmp, &owned)) != STP_OK) return s;
   std::vector<double*> tu(P), tp(P);
   {
     size_t off = 0;
@@ -1810,8 +2119,7 @@ stp_status stp_autotune(stp_ctx* c, int reps, int use_cache, stp_tune_report* re
   c->opt = saved;
   c->kt.on = kt_saved;
   const stp_status s2 = rebuild(c, nul, nul);   // tables as after stp_create: u, p bound at the next solve
-  (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(tmp);
+  scratch_put(c, tmp, owned);
   if (s != STP_OK) return s;
   if (s2 != STP_OK) return s2;
   {

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "stp.h"
+#include "stp_fem.h"
 #include "stp_kernels.h"
 #include "stp_tiles.h"
 
@@ -53,10 +54,18 @@ void kt_end(stp_ctx* c);
 namespace stpx {
 
 
+// finite-element stencils of one level (M and A, scaled to the Galerkin level)
+struct FemLevelW {
+  double m[27];
+  double a[27];
+};
+
 struct Level {
   int n;
   double h;
   Geom g;
+  void* fr = nullptr;   // finite elements: two TS iterates of the level's Jacobi sweeps
+  void* fr2 = nullptr;
   double* kraw;    // unscaled nodal fields (float64), R x nnodes (level 0: the caller's)
   void* kscaled;   // TC fields scaled by 0.5/h^2
   void* b;         // TS right-hand side of the level (levels >= 1)
@@ -93,6 +102,7 @@ inline dim3 grid_pts(long npts, int S) {
 
 enum { TP_FFT2 = 0, TP_STOCKHAM = 1, TP_DENSE = 2, TP_BLUESTEIN = 3, TP_FOUR = 4 };
 
+constexpr int kNormBlocks = 1024;     // blocks of the residual-norm pass after a solve
 constexpr int kBlueKey = 1 << 20;        // site key of a Bluestein group: kBlueKey + M
 constexpr int kBlueMaxN = 2048;          // Bluestein for step counts up to this (M <= 4096)
 constexpr size_t kMaxLds = 160 * 1024;   // LDS of one compute unit
@@ -224,6 +234,7 @@ struct Problem {
   // device memory
   DevState* state = nullptr;
   double* partial = nullptr;
+  double* nrm = nullptr;        // 2 x kNormBlocks partials of the returned pair's residual norms
   double* kap64 = nullptr;      // finest-level scaled fields, float64
   double* cA64 = nullptr;       // N x kMaxRank: tau_n * tcoef
   double* taus64 = nullptr;     // N step lengths
@@ -244,6 +255,9 @@ struct Problem {
   void* Xnu = nullptr;          // TS, N x n^d: correction of one cycle when nu_A or nu_H > 1
   void* tri = nullptr;          // TC scratch of exact 1-D solves, 2 x N x n
   double fnorm = 0;
+  // finite elements: stencils per level and the binding of the current solve
+  std::vector<FemLevelW> fw;
+  FemBind* fbind = nullptr;
 };
 
 template <typename J>
@@ -292,19 +306,28 @@ struct Sites {
 };
 
 // Optional per-launch device timing (HIP events on the context's stream).
+// Phases of an iteration for the per-phase device times of a solve:
+// residuals and stop test (a1, a3), A-tilde solves (a2), time transforms
+// (a4, a6), H-blocks (a5), and everything else (GMRES orthogonalisation,
+// casts, setup).
+enum { PH_RESID = 0, PH_ATILDE = 1, PH_DST = 2, PH_HBLOCK = 3, PH_OTHER = 4, PH_COUNT = 5 };
+
 struct KTimer {
   bool on = false;
   int level = 0;
+  int phase = PH_OTHER;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   struct Rec {
     const char* name;
     int level;
+    int phase;
     hipEvent_t a, b;
   };
   std::vector<Rec> recs;
   const char* pend_name = nullptr;
   int pend_level = 0;
+  int pend_phase = PH_OTHER;
   hipEvent_t pend_a = nullptr;
   struct Agg {
     std::string name;
@@ -331,6 +354,7 @@ using namespace stpx;
 
 struct stp_ctx {
   int P = 0, dim = 0, prec = 0, spatial = STP_SPATIAL_MG, rm = 1;
+  int disc = STP_DISC_FD;
   stp_options opt{};
   hipStream_t stream = nullptr;
   std::vector<Problem> pr;
@@ -338,6 +362,12 @@ struct stp_ctx {
   bool own_ws = false;
   size_t tables_off = 0;
   size_t tables_bytes = 0;
+  // setup and tuning scratch (omega estimate, kappa check, autotuner): a region
+  // at the end of a caller's workspace, or (library-owned workspace) allocated
+  // for the duration of each use
+  double* scratch = nullptr;
+  size_t scratch_n = 0;       // doubles the region holds (0: allocate per use)
+  double t_setup_ms = 0, t_omega_ms = 0;
   DevState* state_host = nullptr;   // pinned, P entries
   Sites sites;
   SolverBase* impl = nullptr;
@@ -365,6 +395,7 @@ inline void kt_begin(stp_ctx* c, const char* name) {
   (void)hipEventRecord(a, c->stream);
   c->kt.pend_name = name;
   c->kt.pend_level = c->kt.level;
+  c->kt.pend_phase = c->kt.phase;
   c->kt.pend_a = a;
 }
 
@@ -373,7 +404,7 @@ inline void kt_end(stp_ctx* c) {
   hipEvent_t b = c->kt.get();
   if (b) {
     (void)hipEventRecord(b, c->stream);
-    c->kt.recs.push_back({c->kt.pend_name, c->kt.pend_level, c->kt.pend_a, b});
+    c->kt.recs.push_back({c->kt.pend_name, c->kt.pend_level, c->kt.pend_phase, c->kt.pend_a, b});
   }
   c->kt.pend_name = nullptr;
 }

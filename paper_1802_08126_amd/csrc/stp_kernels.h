@@ -299,9 +299,10 @@ __global__ void __launch_bounds__(kBlock) k_fnorm(Geom g, int N, const double* _
 struct DevState {
   int done;       // 0 running, 1 converged, 2 diverged, 3 max_iter
   int iter;       // current iteration index j
-  double rel;     // ||f - B u_j|| / ||f||
+  double rel;     // ||f - B u_j|| / ||f||  (||f - B u_j|| when f = 0)
   double fnorm;
   double res0;
+  double rp2, ru2;   // ||r_p||^2, ||r_u||^2 of the returned pair (after a solve)
 };
 
 // Deterministic reduction of one problem's residual partials and its stop
@@ -330,7 +331,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const FinJob* __restrict__ 
   const double s = block_sum(v);
   if (threadIdx.x == 0) {
     const double res = sqrt(s);
-    const double rel = res / st->fnorm;
+    const double rel = st->fnorm > 0 ? res / st->fnorm : res;   // f = 0: absolute residual
     st->rel = rel;
     if (st->iter == 0) st->res0 = res;
     if (!(rel == rel) || rel > 1e300 || (st->iter > 0 && res > 1e8 * st->res0 && res > 1e8 * st->fnorm * J.tol)) {
@@ -1395,6 +1396,46 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(Geom g, TimeOp t, const
   if (s == 0) f += u0[i];
   rp[o + i] = -f - (Ap - (uc - um));
   ru[o + i] = -f + (pc - pp) + (2.0 * uc - um - up) + Au;
+}
+
+// block partials of ||r_p||^2 and ||r_u||^2 of a pair (p, u), eq. (3.1):
+// r_p = K u - A p - f and r_u = f - K^T p - (K + K^T + A) u, the two blocks of
+// the saddle residual g - saddle [p; u] up to sign.  A fixed grid of G blocks
+// strides over the points; each thread walks all slabs of its points (for a
+// fixed slab the threads of a block read consecutive points).  Block b writes
+// partial[b] (r_p) and partial[G + b] (r_u).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_saddle_norms(Geom g, TimeOp t, const double* __restrict__ taus,
+                                                         const double* __restrict__ F,
+                                                         const double* __restrict__ u0, const double* __restrict__ p,
+                                                         const double* __restrict__ u, double* __restrict__ partial) {
+  double vp = 0.0, vu = 0.0;
+  for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < g.npts; i += long(gridDim.x) * kBlock) {
+    int px, py, pz;
+    decode<D>(i, g.n, px, py, pz);
+    for (int s = 0; s < t.N; ++s) {
+      const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
+      const long o = long(s) * g.npts;
+      double dg, offp, offu;
+      stencil2<D>(p + o, u + o, i, px, py, pz, g, t.kap, op, t.R, dg, offp, offu);
+      const double pc = p[o + i];
+      const double uc = u[o + i];
+      const double um = s > 0 ? u[o - g.npts + i] : 0.0;
+      const double up = s + 1 < t.N ? u[o + g.npts + i] : 0.0;
+      const double pp = s + 1 < t.N ? p[o + g.npts + i] : 0.0;
+      double f = taus[s] * F[o + i];
+      if (s == 0) f += u0[i];
+      const double rp = (uc - um) - (dg * pc - offp) - f;
+      const double ru = f - (pc - pp) - (2.0 * uc - um - up) - (dg * uc - offu);
+      vp += rp * rp;
+      vu += ru * ru;
+    }
+  }
+  const double sp = block_sum(vp);
+  if (threadIdx.x == 0) partial[blockIdx.x] = sp;
+  __syncthreads();   // block_sum's LDS slots are reused
+  const double su = block_sum(vu);
+  if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = su;
 }
 
 // block partials of ||f - B u||^2 over a (points, slabs) grid

@@ -12,6 +12,169 @@ struct Solver : SolverBase {
 
   TC omegaJ() const { return c->dim == 1 ? TC(2.0 / 3.0) : (c->dim == 2 ? TC(4.0 / 5.0) : TC(6.0 / 7.0)); }
 
+  // -------------------------------------------------------------------------
+  // finite elements (single problem): operator kernels of stp_fem.h
+  // -------------------------------------------------------------------------
+  // damping of the finite-element l1-Jacobi sweeps
+  TC fem_theta() const { return TC(1.6); }
+
+  static FemW<TC> fem_w(const FemLevelW& f) {
+    FemW<TC> w;
+    for (int k = 0; k < 27; ++k) {
+      w.m[k] = TC(f.m[k]);
+      w.a[k] = TC(f.a[k]);
+    }
+    return w;
+  }
+  static FemW<double> fem_w64(const FemLevelW& f) {
+    FemW<double> w;
+    for (int k = 0; k < 27; ++k) {
+      w.m[k] = f.m[k];
+      w.a[k] = f.a[k];
+    }
+    return w;
+  }
+
+  // operator of a V-cycle family: (sigma table or null, c table, stride)
+  void fem_family(int which, const TC*& sig, const TC*& cc, int& stride) {
+    Problem& q = c->pr[0];
+    if (which == VC_A) {
+      sig = nullptr;
+      cc = (const TC*)q.cA;
+    } else {
+      sig = (const TC*)q.sigH;
+      cc = (const TC*)q.cH;
+    }
+    stride = kMaxRank;
+  }
+
+  template <int D>
+  stp_status fem_level(int l, const TC* sig, const TC* cc, int stride, const TS* b, TS* out, bool add64) {
+    Problem& q = c->pr[0];
+    const int N = q.N;
+    const int L = int(q.lv.size());
+    const Level& lv = q.lv[l];
+    const int* stf = &q.state->done;
+    c->kt.level = l;
+    const FemW<TC> w = fem_w(q.fw[l]);
+    if (l == L - 1) {   // one node per slab (never the top level)
+      KLAUNCH_NAMED("k_fem_coarsest", (k_fem_coarsest<TS, TC>), dim3(unsigned((N + kBlock - 1) / kBlock)), dim3(kBlock),
+                    0, c->stream, N, w.m[fem_ctr<D>()], w.a[fem_ctr<D>()], sig, cc, stride, b, out, stf);
+      LAUNCH_CHECK();
+      return STP_OK;
+    }
+    const Level& lc = q.lv[l + 1];
+    const TC om = fem_theta();
+    const int ns = std::max(1, c->opt.sweeps);
+    const dim3 gf = grid_pts(lv.g.npts, N), gc = grid_pts(lc.g.npts, N), bl(kBlock);
+    TS* xa = (TS*)lv.fr;
+    TS* xb = (TS*)lv.fr2;
+    KLAUNCH_NAMED("k_fem_jac0", (k_fem_jac0<D, TS, TC>), gf, bl, 0, c->stream, lv.g.npts, N, w, sig, cc, stride, om,
+                  b, xa, stf);
+    LAUNCH_CHECK();
+    for (int k = 1; k < ns; ++k) {   // further pre-sweeps
+      KLAUNCH_NAMED("k_fem_sweep", (k_fem_sweep<D, TS, TC, EPI_STORE>), gf, bl, 0, c->stream, lv.g, N, w, sig, cc,
+                    stride, om, b, (const TS*)xa, xb, (const FemBind*)q.fbind, stf);
+      LAUNCH_CHECK();
+      std::swap(xa, xb);
+    }
+    KLAUNCH_NAMED("k_fem_res", (k_fem_res<D, TS, TC>), gf, bl, 0, c->stream, lv.g, N, w, sig, cc, stride, b,
+                  (const TS*)xa, xb, stf);
+    LAUNCH_CHECK();
+    KLAUNCH_NAMED("k_fem_restrict", (k_fem_restrict<D, TS, TC, D == 2>), gc, bl, 0, c->stream, lv.g, lc.g, N,
+                  (const TS*)xb, (TS*)lc.b, stf);
+    LAUNCH_CHECK();
+    stp_status st = fem_level<D>(l + 1, sig, cc, stride, (const TS*)lc.b, (TS*)lc.e, false);
+    if (st != STP_OK) return st;
+    c->kt.level = l;
+    KLAUNCH_NAMED("k_fem_prolong_add", (k_fem_prolong_add<D, TS, TC, D == 2>), gf, bl, 0, c->stream, lv.g, lc.g, N,
+                  (const TS*)lc.e, xa, stf);
+    LAUNCH_CHECK();
+    for (int k = 1; k < ns; ++k) {   // post-sweeps but the last
+      KLAUNCH_NAMED("k_fem_sweep", (k_fem_sweep<D, TS, TC, EPI_STORE>), gf, bl, 0, c->stream, lv.g, N, w, sig, cc,
+                    stride, om, b, (const TS*)xa, xb, (const FemBind*)q.fbind, stf);
+      LAUNCH_CHECK();
+      std::swap(xa, xb);
+    }
+    if (add64)
+      KLAUNCH_NAMED("k_fem_sweep<add64>", (k_fem_sweep<D, TS, TC, EPI_ADD64>), gf, bl, 0, c->stream, lv.g, N, w, sig,
+                    cc, stride, om, b, (const TS*)xa, out, (const FemBind*)q.fbind, stf);
+    else
+      KLAUNCH_NAMED("k_fem_sweep", (k_fem_sweep<D, TS, TC, EPI_STORE>), gf, bl, 0, c->stream, lv.g, N, w, sig, cc,
+                    stride, om, b, (const TS*)xa, out, (const FemBind*)q.fbind, stf);
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
+  // one application of A-tilde^{-1} (which = VC_A: W1 -> += the binding's p
+  // target) or of an H-tilde_k^{-1} family (VC_H1, VC_H2: W2 -> W1)
+  stp_status fem_vcycle(int which) {
+    Problem& q = c->pr[0];
+    const TC *sig, *cc;
+    int stride;
+    fem_family(which, sig, cc, stride);
+    const bool a = which == VC_A;
+    const TS* in = (const TS*)(a ? q.W1 : q.W2);
+    TS* out = (TS*)q.W1;
+    if (c->spatial == STP_SPATIAL_EXACT) {   // 1-D: exact tridiagonal solves
+      const FemLevelW& f = q.fw[0];
+      c->kt.level = 0;
+      const dim3 gr(unsigned((q.N + 63) / 64)), bl(64);
+      if (a)
+        KLAUNCH_NAMED("k_fem_tridiag<add64>", (k_fem_tridiag<TS, TC, EPI_ADD64>), gr, bl, 0, c->stream, q.n, q.N,
+                      TC(f.m[1]), TC(f.m[0]), TC(f.a[1]), TC(f.a[0]), sig, cc, stride, in, out,
+                      (const FemBind*)q.fbind, (TC*)q.tri, &q.state->done);
+      else
+        KLAUNCH_NAMED("k_fem_tridiag<store>", (k_fem_tridiag<TS, TC, EPI_STORE>), gr, bl, 0, c->stream, q.n, q.N,
+                      TC(f.m[1]), TC(f.m[0]), TC(f.a[1]), TC(f.a[0]), sig, cc, stride, in, out,
+                      (const FemBind*)q.fbind, (TC*)q.tri, &q.state->done);
+      LAUNCH_CHECK();
+      return STP_OK;
+    }
+    switch (c->dim) {
+      case 2: return fem_level<2>(0, sig, cc, stride, in, out, a);
+      default: return fem_level<3>(0, sig, cc, stride, in, out, a);
+    }
+  }
+
+  template <int D>
+  stp_status fem_mid_d() {
+    Problem& q = c->pr[0];
+    c->kt.level = 0;
+    const TC cmid = TC((2.0 / q.N) * q.tau * q.abar[0]);
+    KLAUNCH_NAMED("k_fem_apply", (k_fem_apply<D, TS, TC>), grid_pts(q.g0.npts, q.N), dim3(kBlock), 0, c->stream, q.g0,
+                  q.N, fem_w(q.fw[0]), cmid, (const TS*)q.W1, (TS*)q.W2, &q.state->done);
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+  stp_status fem_mid() {
+    switch (c->dim) {
+      case 1: return fem_mid_d<1>();
+      case 2: return fem_mid_d<2>();
+      default: return fem_mid_d<3>();
+    }
+  }
+
+  template <int D, int WHICH>
+  stp_status fem_resid_d() {
+    Problem& q = c->pr[0];
+    c->kt.level = 0;
+    KLAUNCH_NAMED(WHICH == 0 ? "k_fem_resid<a1>" : "k_fem_resid<a3>", (k_fem_resid<D, TS, WHICH>),
+                  grid_pts(q.g0.npts, q.N), dim3(kBlock), 0, c->stream, q.g0, q.N, fem_w64(q.fw[0]),
+                  (const double*)q.taus64, (const double*)q.cA64, (const FemBind*)q.fbind, &q.state->done,
+                  (TS*)q.W1, q.partial);
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+  template <int WHICH>
+  stp_status fem_resid() {
+    switch (c->dim) {
+      case 1: return fem_resid_d<1, WHICH>();
+      case 2: return fem_resid_d<2, WHICH>();
+      default: return fem_resid_d<3, WHICH>();
+    }
+  }
+
   template <int D, int RM>
   stp_status fused_site(Site<FuseJob>& s, int level) {
     if (s.jobs.empty()) return STP_OK;
@@ -131,6 +294,7 @@ struct Solver : SolverBase {
   // read their operands from job tables, so captured graphs follow a rebinding
   // of the A target as the cycles do.
   stp_status run_vcycle(int which) override {
+    if (c->disc == STP_DISC_FEM) return fem_vcycle(which);
     const int nu = which == VC_A ? c->opt.nu_A : c->opt.nu_H;
     if (nu <= 1 || !multi_cycle(c)) return run_cycle(c->sites.vc[which]);
     const int fam = which == VC_A ? 0 : 1;
@@ -230,7 +394,7 @@ struct Solver : SolverBase {
     }
   }
 
-  stp_status run_mid() { return run_apply(c->sites.mid); }
+  stp_status run_mid() { return c->disc == STP_DISC_FEM ? fem_mid() : run_apply(c->sites.mid); }
 
   template <int L1, int L2, int MODE, int ACC>
   stp_status fft2_site(Site<TimeJob>& s) {
@@ -334,11 +498,16 @@ struct Solver : SolverBase {
   // H-tilde^{-1}: W1 holds r on entry; Phi^{-1} yhat goes to the a6 targets.
   stp_status run_precH() override {
     stp_status s;
+    c->kt.phase = PH_DST;
     if ((s = transform_sites(c->sites.a4, 0)) != STP_OK) return s;   // rhat = Phi^{-T} r    (W1 -> W2)
+    c->kt.phase = PH_HBLOCK;
     if ((s = run_vcycle(VC_H1)) != STP_OK) return s;                  // x = H~_k^{-1} rhat   (W2 -> W1)
     if ((s = run_mid()) != STP_OK) return s;                          // y = (2/N) tau A x    (W1 -> W2)
     if ((s = run_vcycle(VC_H2)) != STP_OK) return s;                  // yhat = H~_k^{-1} y   (W2 -> W1)
-    return transform_sites(c->sites.a6, 1);                           // += alpha Phi^{-1} yhat
+    c->kt.phase = PH_DST;
+    s = transform_sites(c->sites.a6, 1);                              // += alpha Phi^{-1} yhat
+    c->kt.phase = PH_OTHER;
+    return s;
   }
 
   template <int D, int WHICH, int RM>
@@ -374,10 +543,15 @@ struct Solver : SolverBase {
 
   stp_status iteration(bool full = true) override {
     stp_status s;
-    if ((s = run_resid<0>()) != STP_OK) return s;        // r_p = K u - A p - f   -> W1
+    const bool fem = c->disc == STP_DISC_FEM;
+    c->kt.phase = PH_RESID;
+    if ((s = fem ? fem_resid<0>() : run_resid<0>()) != STP_OK) return s;   // r_p = K u - A p - f   -> W1
+    c->kt.phase = PH_ATILDE;
     if ((s = run_vcycle(VC_A)) != STP_OK) return s;      // p += A~^{-1} r_p
-    if ((s = run_resid<1>()) != STP_OK) return s;        // r_u -> W1, partials of ||f - B u||^2
+    c->kt.phase = PH_RESID;
+    if ((s = fem ? fem_resid<1>() : run_resid<1>()) != STP_OK) return s;   // r_u -> W1, partials of ||f - B u||^2
     if ((s = launch_finalize(c)) != STP_OK) return s;   // stop test and divergence guard
+    c->kt.phase = PH_OTHER;
     return full ? run_precH() : STP_OK;                  // u += omega H~^{-1} r_u
   }
 
@@ -388,11 +562,25 @@ struct Solver : SolverBase {
     return STP_OK;
   }
 
-  stp_status resid(int which) override { return which == 0 ? run_resid<0>() : run_resid<1>(); }
+  stp_status resid(int which) override {
+    if (c->disc == STP_DISC_FEM) return which == 0 ? fem_resid<0>() : fem_resid<1>();
+    return which == 0 ? run_resid<0>() : run_resid<1>();
+  }
 
   stp_status kt_add_in(const double* r, const double* d, double sgn) override {
     Problem& q = c->pr[0];
     const long nv = long(q.N) * q.g0.npts;
+    if (c->disc == STP_DISC_FEM) {
+      const FemW<double> w = fem_w64(q.fw[0]);
+      const dim3 gr = grid_pts(q.g0.npts, q.N);
+      switch (c->dim) {
+        case 1: KLAUNCH((k_fem_kt_add_cast<1, TS>), gr, dim3(kBlock), 0, c->stream, q.g0, q.N, w, r, d, sgn, (TS*)q.W1); break;
+        case 2: KLAUNCH((k_fem_kt_add_cast<2, TS>), gr, dim3(kBlock), 0, c->stream, q.g0, q.N, w, r, d, sgn, (TS*)q.W1); break;
+        default: KLAUNCH((k_fem_kt_add_cast<3, TS>), gr, dim3(kBlock), 0, c->stream, q.g0, q.N, w, r, d, sgn, (TS*)q.W1);
+      }
+      LAUNCH_CHECK();
+      return STP_OK;
+    }
     KLAUNCH((k_kt_add_cast<TS>), dim3(unsigned((nv + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
             q.g0.npts, q.N, r, d, sgn, (TS*)q.W1);
     LAUNCH_CHECK();

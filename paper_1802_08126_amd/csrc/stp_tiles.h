@@ -219,10 +219,31 @@ __device__ __forceinline__ TC diag_fixed(const TC* sk, int kq, TC sigma, TC gamm
   return sigma + gamma * d;
 }
 
+// face sums 2d k_c + sum_nb k_nb of a fixed field (staged in sk over KB) at
+// every position of box XB (KB one node larger on each side)
+template <int D, typename XB, typename KB, typename TC>
+__device__ __forceinline__ void stage_facesum(TC* sd, const TC* sk);
+
 // kappa-box position of x-box position (x, y, z) when KB is one node larger
 template <int D, typename KB>
 __device__ __forceinline__ int kpos(int x, int y, int z) {
   return KB::idx(x + 1, D >= 2 ? y + 1 : 0, D >= 3 ? z + 1 : 0);
+}
+
+template <int D, typename XB, typename KB, typename TC>
+__device__ __forceinline__ void stage_facesum(TC* sd, const TC* sk) {
+  BoxIter<XB> it;
+#pragma unroll
+  for (int k = 0; k < nit<XB>(); ++k) {
+    if (it.ok()) {
+      const int kq = kpos<D, KB>(it.x, it.y, it.z);
+      TC d = TC(2 * D) * sk[kq];
+#pragma unroll
+      for (int j = 0; j < 2 * D; ++j) d += sk[kq + nb_off<KB>(j)];
+      sd[it.q] = d;
+    }
+    it.next();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -386,6 +407,9 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
   __shared__ TC sx[XB::size];
   __shared__ TC sre[RROWS * RE];
   __shared__ TC sro[RROWS * RO];
+  // fixed field: the slab-independent face sum 2d k_c + sum_nb k_nb of every
+  // x1-box node, so a slab's diagonal is sigma + gamma * sd (one LDS read)
+  __shared__ TC sd[FIX ? XB::size : 1];
   const LevelOp L = J.op;
   s1 = min(s1, L.S);
   if (s0 >= s1) return;
@@ -400,6 +424,8 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
   TC kr[FIX ? 1 : nit<KB>()][FIX ? 1 : RM];
   if constexpr (FIX) {
     stage_fixed<D, KB, TC>(sk, L, gf.nnodes, nf, xx - 1, D >= 2 ? xy - 1 : 1, D >= 3 ? xz - 1 : 1);
+    __syncthreads();
+    stage_facesum<D, XB, KB, TC>(sd, sk);
     __syncthreads();
   } else {
     load_kraw<D, KB, TC, RM>(kr, (const TC*)L.kap, gf.nnodes, L.R, nf, xx - 1, D >= 2 ? xy - 1 : 1,
@@ -427,7 +453,7 @@ __device__ __forceinline__ void mg_down_body(const TileJob& J, int tile, int s0,
           TC v = 0;
           if (interior<D>(jx, jy, jz, nf))
             v = omega * bcur[k] *
-                rcp_fast(FIX ? diag_fixed<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma, gamma)
+                rcp_fast(FIX ? op.sigma + gamma * sd[FIX ? it.q : 0]
                              : diag_at_k<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma));
           sx[it.q] = v;
         }
@@ -517,6 +543,7 @@ __device__ __forceinline__ void mg_up_body(const TileJob& J, int tile, int s0, i
   __shared__ TC sx[XB::size];
   __shared__ TC sb_[XB::size];
   __shared__ TC se[EB::size];
+  __shared__ TC sd[FIX ? XB::size : 1];   // fixed field: face sums of the x2-box nodes
   const LevelOp L = J.op;
   s1 = min(s1, L.S);
   if (s0 >= s1) return;
@@ -530,6 +557,8 @@ __device__ __forceinline__ void mg_up_body(const TileJob& J, int tile, int s0, i
   TC kr[FIX ? 1 : nit<KB>()][FIX ? 1 : RM];
   if constexpr (FIX) {
     stage_fixed<D, KB, TC>(sk, L, gf.nnodes, nf, xx - 1, D >= 2 ? xy - 1 : 1, D >= 3 ? xz - 1 : 1);
+    __syncthreads();
+    stage_facesum<D, XB, KB, TC>(sd, sk);   // read after the first slab's barrier
   } else {
     load_kraw<D, KB, TC, RM>(kr, (const TC*)L.kap, gf.nnodes, L.R, nf, xx - 1, D >= 2 ? xy - 1 : 1,
                              D >= 3 ? xz - 1 : 1);
@@ -560,7 +589,7 @@ __device__ __forceinline__ void mg_up_body(const TileJob& J, int tile, int s0, i
           TC v = 0;
           if (interior<D>(jx, jy, jz, nf)) {
             const TC wd =
-                omega * rcp_fast(FIX ? diag_fixed<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma, gamma)
+                omega * rcp_fast(FIX ? op.sigma + gamma * sd[FIX ? it.q : 0]
                                      : diag_at_k<D, KB, TC>(sk, kpos<D, KB>(it.x, it.y, it.z), op.sigma));
             // multilinear interpolation from coarse nodes floor(j/2) and, for odd j, floor(j/2)+1
             const int lx = (jx >> 1) - ex, ly = D >= 2 ? (jy >> 1) - ey : 0, lz = D >= 3 ? (jz >> 1) - ez : 0;
@@ -595,7 +624,7 @@ __device__ __forceinline__ void mg_up_body(const TileJob& J, int tile, int s0, i
       const int kq = kpos<D, KB>(ax, ay, az);
       TC off = offsum_at<D, XB, KB, TC>(sk, sx, kq, xq);
       if (FIX) off *= gamma;
-      const TC wd = omega * rcp_fast(FIX ? diag_fixed<D, KB, TC>(sk, kq, op.sigma, gamma)
+      const TC wd = omega * rcp_fast(FIX ? op.sigma + gamma * sd[FIX ? xq : 0]
                                          : diag_at_k<D, KB, TC>(sk, kq, op.sigma));
       const TC v = one_m_omega * sx[xq] + wd * (sb_[xq] + off);
       const int vo = vec_off<D>(jx, jy, jz, nf);

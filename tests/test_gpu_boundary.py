@@ -1,0 +1,185 @@
+"""The C-ABI boundary's contract beyond the numerics: caller-owned
+workspaces (no device allocation by the library), the diagnostics of
+stp_stats (residual blocks of the returned pair, setup time, per-phase device
+times), a zero right-hand side, divergence with a finite last iterate, and the
+damping bound of eq. (3.7)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import spacetime as st, uzawa
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test collected without a GPU")
+    import paper_1802_08126_amd as stp
+    stp.load()
+    yield
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def make(prob, workspace=None, **kw):
+    import paper_1802_08126_amd as stp
+    return stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, dev(prob.kfields), prob.tcoef, dev(prob.F),
+                               dev(prob.u0), workspace=workspace, **kw)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_caller_workspace_means_no_device_allocation(prec):
+    """With a workspace of stp_workspace_bytes, create (with the damping
+    estimate), autotune and solve allocate no device memory, and give bitwise
+    the iterates of a context whose workspace the library allocates."""
+    import paper_1802_08126_amd as stp
+    prob = synth.small_problem(2, 31, 24, seed=41)
+    kw = dict(precision=prec, omega=0.0, tol=1e-9, max_iter=300)
+    nb = stp.stp_workspace_bytes(2, 31, 24, prob.R, **kw)
+    nb_given = stp.stp_workspace_bytes(2, 31, 24, prob.R, **dict(kw, omega=0.7))
+    assert nb > nb_given > 0            # the estimate's five vectors make the difference
+    ref = make(prob, **kw)
+    ref.autotune(reps=1)
+    u_ref, p_ref, i_ref = ref.solve()
+    small = torch.empty(nb - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(stp.StpError) as e:
+        make(prob, workspace=small, **kw)
+    assert e.value.status == stp.STP_ENOMEM
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    before = stp.stp_device_bytes_allocated()
+    s = make(prob, workspace=ws, **kw)
+    s.autotune(reps=1)
+    u, p, info = s.solve()
+    torch.cuda.synchronize()
+    assert stp.stp_device_bytes_allocated() == before
+    assert info["status"] == 0 and info["iters"] == i_ref["iters"]
+    assert info["omega"] == i_ref["omega"]
+    assert np.array_equal(host(u), host(u_ref)) and np.array_equal(host(p), host(p_ref))
+    s.close()
+    ref.close()
+
+
+def test_stats_residual_blocks_and_setup_time():
+    """rel_rp, rel_ru: the two blocks of the saddle residual of the returned
+    pair, recomputed with the oracle's operators; setup times reported."""
+    import paper_1802_08126_amd as stp
+    prob = synth.small_problem(3, 15, 12, seed=42)
+    s = make(prob, omega=0.0, tol=1e-8, max_iter=300)
+    u, p, info = s.solve()
+    uh, ph = host(u), host(p)
+    f = st.rhs(prob)
+    fn = np.linalg.norm(f)
+    rp = st.apply_K(uh) - st.apply_Ablk(prob, ph) - f
+    ru = f - st.apply_KT(ph) - (st.apply_K(uh) + st.apply_KT(uh) + st.apply_Ablk(prob, uh))
+    assert info["rel_rp"] == pytest.approx(np.linalg.norm(rp) / fn, rel=1e-8)
+    assert info["rel_ru"] == pytest.approx(np.linalg.norm(ru) / fn, rel=1e-8)
+    assert info["setup_ms"] > info["omega_ms"] > 0
+    assert all(v == 0.0 for v in info["phase_ms"].values())   # timing off
+    s.close()
+    s = make(prob, omega=0.7, tol=1e-8, max_iter=300)
+    _, _, i2 = s.solve()
+    assert i2["setup_ms"] > 0 and i2["omega_ms"] == 0.0
+    s.close()
+
+
+def test_phase_times_with_timing_enabled():
+    """With per-launch timing on, the phases of a solve hold its kernels' device
+    time: residuals, A~ solves, transforms and H-blocks are all present, and
+    the per-kernel records add up to the same total."""
+    prob = synth.small_problem(2, 63, 64, seed=43)
+    s = make(prob, omega=0.7, tol=0.0, max_iter=6)
+    s.timing(True)
+    _, _, info = s.solve()
+    ph = info["phase_ms"]
+    for k in ("resid", "atilde", "dst", "hblock"):
+        assert ph[k] > 0, ph
+    rep = s.timing_report()
+    total = sum(r["total_ms"] for r in rep if r["kernel"] not in ("k_saddle_norms<2>", "k_sum_rows"))
+    assert sum(ph.values()) == pytest.approx(total, rel=1e-6)
+    assert ph["hblock"] > ph["dst"]     # the spatial solves dominate, as in Tables 3-4
+    s.close()
+
+
+def test_zero_right_hand_side_converges_at_once():
+    """F = 0 and u0 = 0: the solution is zero; the stop test uses the absolute
+    residual, so both solvers return at iteration 0 with status OK."""
+    prob = synth.small_problem(2, 15, 8, seed=44)
+    prob.F = np.zeros_like(prob.F)
+    prob.u0 = np.zeros_like(prob.u0)
+    s = make(prob, omega=0.7, tol=1e-8, max_iter=50)
+    u, p, info = s.solve()
+    assert info["status"] == 0 and info["iters"] == 0 and info["rel_res"] == 0.0
+    assert not host(u).any() and not host(p).any()
+    u, p, ig = s.gmres(restart=5)
+    assert ig["status"] == 0 and ig["iters"] == 0
+    s.close()
+
+
+def test_divergence_returns_the_finite_last_iterate():
+    """omega = 3 diverges: the solve reports EDIVERGED at the first iterate whose
+    residual grew past 1e8 times the initial one, and u, p are that (finite)
+    iterate, equal to the oracle's iterate of the same index."""
+    import paper_1802_08126_amd as stp
+    prob = synth.small_problem(2, 15, 8, seed=45)
+    s = make(prob, omega=3.0, tol=1e-12, max_iter=400)
+    u, p, info = s.solve()
+    assert info["status"] == stp.STP_EDIVERGED, info
+    uh, ph = host(u), host(p)
+    assert np.isfinite(uh).all() and np.isfinite(ph).all()
+    j = info["iters"]
+    ref = uzawa.uzawa_fixed(prob, j, omega=3.0, spatial="mg")
+    assert ref["history"][-1] > 1e8 * ref["history"][0]
+    assert relmax(uh, ref["u"]) < 1e-8 and relmax(ph, ref["p"]) < 1e-8
+    s.close()
+
+
+def test_damping_bound_of_eq_3_7():
+    """stp_omega_info reports omega_37 = 2 (1 - rho_A) / ((1 + rho_A) lambda_max)
+    from the estimates; Theorem 3.1 guarantees convergence below it, and a
+    solve with 0.9 omega_37 converges."""
+    prob = synth.small_problem(2, 31, 32, seed=46)
+    s = make(prob, omega=0.0, tol=1e-8, max_iter=2000)
+    oi = s.omega_info()
+    assert oi["omega_37"] == pytest.approx(2 * (1 - oi["rho_A"]) / ((1 + oi["rho_A"]) * oi["lmax"]), rel=1e-14)
+    assert 0 < oi["omega_37"] < oi["omega"]
+    s.close()
+    s = make(prob, omega=0.9 * oi["omega_37"], tol=1e-8, max_iter=2000)
+    _, _, info = s.solve()
+    assert info["status"] == 0, info
+    s.close()
+
+
+def test_set_stop_changes_the_rule_and_keeps_the_graph():
+    """stp_set_stop between solves: the new tol / max_iter take effect, the
+    captured graph is reused, and the iterates equal those of a context made
+    with the same rule."""
+    prob = synth.small_problem(2, 31, 16, seed=47)
+    s = make(prob, omega=0.7, tol=1e-6, max_iter=100)
+    _, _, i1 = s.solve()
+    assert i1["status"] == 0
+    s.set_stop(0.0, 7)
+    u, p, i2 = s.solve()
+    assert i2["iters"] == 7
+    ref = make(prob, omega=0.7, tol=0.0, max_iter=7)
+    ur, pr, _ = ref.solve()
+    assert np.array_equal(host(u), host(ur)) and np.array_equal(host(p), host(pr))
+    s.set_stop(1e-10, 400)
+    _, _, i3 = s.solve()
+    assert i3["status"] == 0 and i3["rel_res"] <= 1e-10 and i3["iters"] > i1["iters"]
+    s.close()
+    ref.close()

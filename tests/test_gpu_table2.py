@@ -57,21 +57,24 @@ def gpu_count(prob, ue, scale, nu, guess):
     return j, cache
 
 
-# two cycles of this multigrid (contraction about 0.1 on tau A) stay inside
-# the range the paper prints (20-22); one cycle (about 0.3) needs more
-# iterations, equally many for every h and N within a spread of three
-@pytest.mark.parametrize("nu,lo,hi,spread", [(2, 20, 22, 2), (1, 30, 40, 3)])
-def test_table2_counts_flat_in_h_and_N(nu, lo, hi, spread):
+# Two cycles of this multigrid (contraction about 0.1 on tau A) must stay inside
+# the range the paper prints (20-22).  One cycle (about 0.3) puts omega = 0.9
+# outside the damping condition (3.7), so Theorem 3.1 gives no count for it and
+# the paper prints none for this cycle: only the robustness the paper reports is
+# checked, the counts varying by at most 10 % over h and N.
+@pytest.mark.parametrize("nu,lo,hi", [(2, 20, 22), (1, None, None)])
+def test_table2_counts_flat_in_h_and_N(nu, lo, hi):
     counts = {}
     for n in NS:
         for N in STEPS:
             prob = synth.heat2d_sine(n, N)
             ue = euler.seq_euler(prob)
             scale = st.s_norm(prob, ue)
-            j, errs = gpu_count(prob, ue, scale, nu, guess=lo + 2)
+            j, errs = gpu_count(prob, ue, scale, nu, guess=(lo or 33) + 2)
             counts[(n, N)] = j
             print(f"table2 nu={nu} h=1/{n + 1} N={N}: {j} iterations "
                   f"(err {errs[j - 1]:.2e} -> {errs[j]:.2e})", flush=True)
     vals = np.array(list(counts.values()))
-    assert vals.min() >= lo and vals.max() <= hi, counts
-    assert vals.max() - vals.min() <= spread, counts
+    if lo is not None:
+        assert vals.min() >= lo and vals.max() <= hi, counts
+    assert vals.max() - vals.min() <= 0.1 * vals.mean(), counts
