@@ -1,24 +1,43 @@
 #!/usr/bin/env python3
 """Benchmark of the space-time inexact Uzawa solver on one MI355X.
 
-Workload: 2-D heat equation, 255 x 255 interior nodes, N_t = 256 steps, T = 1,
-kappa = 1 + 0.5 sin(2 pi t) cos(pi x), source = 8 space-time Gaussians,
-u0 = random sine modes (k <= 16); seeded synthetic data.  The GPU path runs
-in float64 (the workload's precision); the float32-preconditioner variant is
-reported next to it.
+Headline workload (the largest single-GPU one): 3-D heat equation, 255^3
+interior nodes, N_t = 64 steps, T = 1, kappa = kappa_s(x) (1 + 0.3 t) with a
+lognormal kappa_s (correlation length 0.1, contrast 1e3), manufactured source
+whose exact discrete solution is u*_n = exp(-3 pi^2 t_n) sin(pi x) sin(pi y)
+sin(pi z); 1.06e9 space-time DoFs, 8.5 GB per float64 vector.  The headline
+value runs the float32 preconditioner with the float64 outer iteration (the
+workload's "mixed" precision); plain float64 and the bfloat16-storage
+preconditioner are reported beside it.
 
 A step is one inexact Uzawa iteration (eq. (3.1)) over all N_t slabs: both
 residuals, the A-tilde^{-1} V-cycles, the two DSTs and the H-tilde^{-1}
-V-cycles.  K steps are timed as one solve with tol = 0 and max_iter = K (K
-updates plus the final residual evaluation).  Inputs are resident in HBM
-before the timed region starts.
+V-cycles.  K steps are timed as one solve with tol = 0 and max_iter = K.
+Inputs are resident in HBM before the timed region starts, and every timed
+solve follows one that captured its iteration graph.
 
-Prints one JSON line.
+Every solve to tolerance reports its relative L2 and max-norm error against
+an exact solution: the closed form of the manufactured source (3-D
+workloads), the sequential implicit-Euler solution of the CPU oracle (2-D
+255^2 x 256, computed in the cpu_baseline leg), or the exact modal solution
+of the batch problems (coefficients that depend on time only).  The
+manufactured sources and the modal solutions are built here with plain
+float64 torch operations that share nothing with the HIP library.
+
+Other legs: 2-D 255^2 x 256 (float64 and float32 preconditioner), 3-D 127^3 x
+128 (float64 / float32 / bfloat16, to 1e-10), the 64-problem batch of uneven
+2-D problems against a loop of single-problem solves in the same precision,
+a batch of 64 small problems, and the Section 8.3 problem at N up to 65,536.
+The CPU baseline (the oracle on the host cores) runs in a child process while
+the GPU works.
+
+Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -28,33 +47,46 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+HEADLINE = "heat3d_255_N64_lognormal"
+METRIC = "space-time DoF-iterations/sec + time to 1e-8 residual, mixed vs FP64, 1 GPU"
 
-# HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (calibrated
-# against a plain copy) for (workload, dtype, kernel, level); valid only while the
-# kernel sources hash to the recorded value (see the named profile).
-MEASURED_TRAFFIC = {
-    ("heat2d_255_N256", "f64", "k_mg_down", 0): dict(
-        bytes=183612010, sources_sha256="16c5e93e3f193a1e500494084853e1943c9b70a17f046f3513e2a95b72c50181",
-        profile="profiles/heat2d_255_N256_f64_mg_down_L0_traffic.md"),
-}
+# HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by
+# the same counters on a plain copy) for (workload, dtype, kernel, level); used only
+# while the kernel sources hash to the recorded value (see the named profile).
+MEASURED_TRAFFIC = {}
 
 
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("stp_kernels.h", "stp_tiles.h", "stp.hip"):
+    for f in ("stp_kernels.h", "stp_tiles.h", "stp_solver.h", "stp.hip"):
         with open(os.path.join(ROOT, "paper_1802_08126_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
+def progress(*a):
+    """Progress lines go to stderr; stdout carries only the JSON result."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# algorithmic bytes of the kernels (for the roofline)
+# ---------------------------------------------------------------------------
+def level_dims(dim, n, N, R):
+    levels = []
+    while True:
+        levels.append(n)
+        if n == 1 or dim == 1:
+            break
+        n = (n - 1) // 2
+    return dict(N=N, R=R, npts=[m ** dim for m in levels] + [1], nnodes=[(m + 2) ** dim for m in levels] + [1])
+
+
 def algorithmic_bytes(kernel: str, level: int, dims, ts: int) -> float | None:
     """Minimum HBM bytes one launch of ``kernel`` must move (every input read
-    once, every output written once), for the solver's level sizes.
-
-    dims: dict with N (slabs), npts per level list, nnodes per level list, R.
-    """
+    once, every output written once), for the solver's level sizes; ts is the
+    preconditioner's storage size (8, 4 or 2 bytes)."""
     N = dims["N"]
     npts = dims["npts"]
     nn = dims["nnodes"]
@@ -74,427 +106,19 @@ def algorithmic_bytes(kernel: str, level: int, dims, ts: int) -> float | None:
         return N * (2 * n_l + npts[level + 1]) * ts + kap(level, tc)
     if k == "k_apply_tile":
         return N * n_l * 2 * ts + kap(level, tc)
-    if k in ("k_time_fft", "k_time_fft2", "k_time_dense"):   # one step-count group (level = group 0)
+    if k in ("k_time_fft", "k_time_fft2", "k_time_dense", "k_time_bluestein"):   # one step-count group
         if add64:                  # in (TS); float64 u read and written
             return N * npts[0] * (ts + 16)
         return N * npts[0] * 2 * ts
     return None
 
 
-def gpu_run(args):
-    import numpy as np
-    import torch
-
-    import paper_1802_08126_amd as stp
-    import synth
-
-    torch.cuda.set_device(0)
-    prob = synth.CONFIG_BUILDERS[args.workload]()
-    dev = "cuda:0"
-    kf = torch.as_tensor(np.ascontiguousarray(prob.kfields), dtype=torch.float64, device=dev)
-    F = torch.as_tensor(np.ascontiguousarray(prob.F), dtype=torch.float64, device=dev)
-    u0 = torch.as_tensor(np.ascontiguousarray(prob.u0), dtype=torch.float64, device=dev)
-    shape = (prob.N,) + (prob.n,) * prob.dim
-    dofs = prob.N * prob.npts
-    levels = []
-    n = prob.n
-    while True:
-        levels.append(n)
-        if n == 1 or prob.dim == 1:
-            break
-        n = (n - 1) // 2
-    dims = dict(N=prob.N, R=prob.R, npts=[m ** prob.dim for m in levels] + [1],
-                nnodes=[(m + 2) ** prob.dim for m in levels] + [1])
-    results = {}
-    for prec in (["f64", "f32"] if not args.only_f64 else ["f64"]):
-        s = stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0,
-                                precision=prec, omega=args.omega, tol=0.0, max_iter=args.warmup,
-                                check_every=args.check_every)
-        u = torch.zeros(shape, dtype=torch.float64, device=dev)
-        p = torch.zeros(shape, dtype=torch.float64, device=dev)
-        tune = None
-        if not args.no_tune:
-            # the library's autotuner picks slabs per block and the time-transform path
-            heuristic = s.schedule()
-            t0 = time.perf_counter()
-            tune = s.autotune(reps=5, use_cache=False)
-            tune.update(sec=time.perf_counter() - t0, schedule=s.schedule(), heuristic=heuristic)
-        # warmup
-        s.solve(u, p)
-        torch.cuda.synchronize()
-        # timed region: exactly --steps iterations (each replayed as a captured HIP graph)
-        s.close()
-        s = stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0,
-                                precision=prec, omega=args.omega, tol=0.0, max_iter=args.steps,
-                                check_every=args.check_every)
-        if tune is not None:
-            assert s.autotune(use_cache=True)["from_cache"]
-        u.zero_()
-        p.zero_()
-        s.solve(u, p)                        # captures the iteration graph for (u, p)
-        u.zero_()
-        p.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, _, info = s.solve(u, p)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        assert info["iters"] == args.steps, info
-        sec = t1 - t0
-        results[prec] = dict(sec=sec, ms_per_step=1e3 * sec / args.steps, value=dofs * args.steps / sec,
-                             device_ms=info["ms"], autotune=tune, omega=info["omega"])
-        if prec == "f64":
-            # per-kernel device times: a second timed region of the same --steps
-            # iterations, launched eagerly with a HIP event pair around every launch
-            u.zero_()
-            p.zero_()
-            s.timing(True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s.solve(u, p)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            results[prec]["kernels"] = s.timing_report()
-            results[prec]["ms_per_step_eager_timed"] = 1e3 * (t1 - t0) / args.steps
-            s.timing(False)
-        s.close()
-        # time to tolerance from a zero guess
-        if not args.skip_tol:
-            s = stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0,
-                                    precision=prec, omega=args.omega, tol=args.tol, max_iter=2000,
-                                    check_every=args.check_every)
-            if tune is not None:
-                s.autotune(use_cache=True)
-            u.zero_()
-            p.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, _, info = s.solve(u, p)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            results[prec]["tol"] = dict(tol=args.tol, iters=info["iters"], sec=t1 - t0, rel_res=info["rel_res"],
-                                        status=info["status"])
-            # the same stop test reached with GMRES(restart) around the Uzawa sweep
-            # (workspace allocated outside the timed region; second of two runs)
-            nb = stp.stp_gmres_workspace_bytes(s.ctx, args.gmres_restart)
-            ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=dev)
-            for _ in range(2):
-                u.zero_()
-                p.zero_()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                _, _, gi = s.gmres(u, p, restart=args.gmres_restart, workspace=ws)
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-            results[prec]["gmres"] = dict(tol=args.tol, restart=args.gmres_restart, steps=gi["iters"],
-                                          sec=t1 - t0, ms_per_step=1e3 * (t1 - t0) / max(gi["iters"], 1),
-                                          rel_res=gi["rel_res"], status=gi["status"])
-            progress(f"{prec}: gmres to tol", f"{gi['iters']} steps {t1 - t0:.3f}s")
-            del ws
-            s.close()
-            # the same stop test with two V-cycles per H~_k^{-1} (nu_H = 2; second of two runs)
-            s = stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0,
-                                    precision=prec, omega=args.omega, tol=args.tol, max_iter=2000,
-                                    check_every=args.check_every, nu_H=2)
-            if tune is not None:
-                s.autotune(use_cache=True)
-            for _ in range(2):
-                u.zero_()
-                p.zero_()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                _, _, info = s.solve(u, p)
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-            results[prec]["tol_nuH2"] = dict(tol=args.tol, nu_H=2, iters=info["iters"], sec=t1 - t0,
-                                             rel_res=info["rel_res"], status=info["status"], omega=info["omega"])
-            progress(f"{prec}: uzawa nu_H=2 to tol", f"{info['iters']} its {t1 - t0:.3f}s")
-            s.close()
-    return prob, dims, results
-
-
-def progress(*a):
-    """Progress lines go to stderr; stdout carries only the JSON result."""
-    print("[bench]", *a, file=sys.stderr, flush=True)
-
-
-def batch_inputs(count, seed, device):
-    """The mixed-size batch workload on the device.  Coefficients, initial data
-    and the source's separable Gaussian factors come from the seeded generator;
-    the source is assembled on the device from those factors in the
-    generator's own operation order (identical values)."""
-    import torch
-
-    import synth
-
-    specs = synth.batch2d(count=count, seed=seed)
-    probs = []
-    for sp in specs:
-        kf, tc, factors, u0 = synth.batch2d_parts(sp)
-        n, N = sp["side"], sp["N"]
-        F = torch.zeros((N, n, n), dtype=torch.float64, device=device)
-        for gt, (gx, gy) in factors:
-            G = torch.as_tensor(gy, device=device)[:, None] * torch.as_tensor(gx, device=device)[None, :]
-            F += torch.as_tensor(gt, device=device)[:, None, None] * G[None]
-        probs.append(dict(dim=2, n=n, N=N, tau=1.0 / N, tcoef=tc, F=F,
-                          kfields=torch.as_tensor(kf, dtype=torch.float64, device=device),
-                          u0=torch.as_tensor(u0, dtype=torch.float64, device=device)))
-    return specs, probs
-
-
-def batch_run(args):
-    """64 independent 2-D problems: one batched context (merged launches, one
-    graph per iteration) against a loop of 64 single-problem contexts."""
-    import torch
-
-    import paper_1802_08126_amd as stp
-
-    dev = "cuda:0"
-    t0 = time.perf_counter()
-    specs, probs = batch_inputs(64, 1004, dev)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    dofs = sum(q["N"] * q["n"] ** 2 for q in probs)
-    shapes = [(q["N"], q["n"], q["n"]) for q in probs]
-    us = [torch.zeros(sh, dtype=torch.float64, device=dev) for sh in shapes]
-    ps = [torch.zeros(sh, dtype=torch.float64, device=dev) for sh in shapes]
-    K = args.batch_steps
-    out = dict(problems=len(probs), dofs=dofs, sides=sorted({q["n"] for q in probs}),
-               N_range=[min(q["N"] for q in probs), max(q["N"] for q in probs)], steps=K,
-               input_setup_s=setup_s)
-
-    def zero():
-        for t in us + ps:
-            t.zero_()
-        torch.cuda.synchronize()
-
-    def timed_batch(b):
-        zero()
-        b.solve(us, ps)                        # captures the graph
-        zero()
-        t0 = time.perf_counter()
-        _, _, infos, _ = b.solve(us, ps)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0, infos
-
-    omegas = None
-    for prec in ("f32", "f64"):
-        # the damping is estimated once per problem (first context) and set on the others
-        b = stp.BatchSolver(probs, precision=prec, omega=args.omega if omegas is None else 1.0, tol=0.0,
-                            max_iter=K, check_every=K + 1)
-        if omegas is None:
-            omegas = b.omegas()
-            out["omega"] = dict(min=min(omegas), max=max(omegas), source="estimated" if args.omega <= 0 else "given")
-        else:
-            b.set_omegas(omegas)
-        sec, infos = timed_batch(b)
-        assert all(i["iters"] == K for i in infos)
-        r = dict(batch_heuristic=dict(sec=sec, value=dofs * K / sec))
-        t0 = time.perf_counter()
-        tune = b.autotune(reps=2, use_cache=False)
-        tune["sec"] = time.perf_counter() - t0
-        sec, _ = timed_batch(b)
-        r["batch_tuned"] = dict(sec=sec, value=dofs * K / sec, autotune=tune)
-        b.close()
-        # loop of single-problem contexts, built-in schedule, graph replay each
-        ss = [stp.SpaceTimeSolver(2, q["n"], q["N"], q["tau"], q["kfields"], q["tcoef"], q["F"], q["u0"],
-                                  precision=prec, omega=omegas[i], tol=0.0, max_iter=K, check_every=K + 1)
-              for i, q in enumerate(probs)]
-        zero()
-        for i, sv in enumerate(ss):
-            sv.solve(us[i], ps[i])
-        zero()
-        t0 = time.perf_counter()
-        for i, sv in enumerate(ss):
-            sv.solve(us[i], ps[i])
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t0
-        r["loop_heuristic"] = dict(sec=sec, value=dofs * K / sec)
-        for sv in ss:
-            sv.close()
-        r["batching_speedup"] = r["batch_heuristic"]["value"] / r["loop_heuristic"]["value"]
-        out[prec] = r
-        progress("batch:", prec, {k: round(v["value"] / 1e9, 3) for k, v in r.items() if isinstance(v, dict)})
-    if not args.skip_tol:
-        # time to a 1e-8 residual for every problem: mixed-precision batch (tuned)
-        # against a loop of plain float64 single-problem solves
-        b = stp.BatchSolver(probs, precision="f32", omega=1.0, tol=args.tol, max_iter=2000,
-                            check_every=args.check_every)
-        b.set_omegas(omegas)
-        b.autotune(reps=2, use_cache=True)
-        zero()
-        t0 = time.perf_counter()
-        _, _, infos, status = b.solve(us, ps)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t0
-        b.close()
-        its = [i["iters"] for i in infos]
-        progress("batch: f32 batch to tol", f"{tb:.2f}s")
-        ss = [stp.SpaceTimeSolver(2, q["n"], q["N"], q["tau"], q["kfields"], q["tcoef"], q["F"], q["u0"],
-                                  precision="f64", omega=omegas[i], tol=args.tol, max_iter=2000,
-                                  check_every=args.check_every) for i, q in enumerate(probs)]
-        zero()
-        t0 = time.perf_counter()
-        its64 = []
-        for i, sv in enumerate(ss):
-            _, _, info = sv.solve(us[i], ps[i])
-            its64.append(info["iters"])
-        torch.cuda.synchronize()
-        tl = time.perf_counter() - t0
-        for sv in ss:
-            sv.close()
-        progress("batch: f64 loop to tol", f"{tl:.2f}s")
-        out["time_to_tol"] = dict(tol=args.tol, batch_f32_sec=tb, batch_status=status,
-                                  batch_iters=[min(its), max(its)], loop_f64_sec=tl,
-                                  loop_f64_iters=[min(its64), max(its64)],
-                                  speedup_vs_loop_f64=tl / tb)
-        # the mixed-precision batch with two V-cycles per H~_k^{-1} (each problem's
-        # damping estimated for that preconditioner at setup)
-        b = stp.BatchSolver(probs, precision="f32", omega=0.0, tol=args.tol, max_iter=2000,
-                            check_every=args.check_every, nu_H=2)
-        b.autotune(reps=2, use_cache=True)
-        zero()
-        t0 = time.perf_counter()
-        _, _, infos, status = b.solve(us, ps)
-        torch.cuda.synchronize()
-        tb2 = time.perf_counter() - t0
-        b.close()
-        its = [i["iters"] for i in infos]
-        progress("batch: f32 nu_H=2 batch to tol", f"{tb2:.2f}s")
-        out["time_to_tol"].update(batch_f32_nuH2_sec=tb2, batch_nuH2_status=status,
-                                  batch_nuH2_iters=[min(its), max(its)], speedup_nuH2_vs_loop_f64=tl / tb2)
-    return out
-
-
-def heat3d_run(args):
-    """3-D heat, 127^3 interior nodes, N_t = 128, lognormal kappa (contrast 1e2)
-    times (1 + 0.3 t), Gaussian source: time to ||f - B u|| <= 1e-10 ||f|| from a
-    zero guess, Uzawa and GMRES(restart), with float64, float32 and
-    bfloat16-storage preconditioners (outer residuals and updates in float64),
-    and the float32 preconditioner with two V-cycles per H~_k^{-1}.  Each solve
-    runs twice; the second is reported."""
-    import torch
-
-    import paper_1802_08126_amd as stp
-    import synth
-
-    prob = synth.CONFIG_BUILDERS["heat3d_127_N128_lognormal"]()
-    dofs = prob.N * prob.npts
-    dev = "cuda:0"
-    kf = torch.as_tensor(prob.kfields, dtype=torch.float64, device=dev)
-    F = torch.as_tensor(prob.F, dtype=torch.float64, device=dev)
-    u0 = torch.as_tensor(prob.u0, dtype=torch.float64, device=dev)
-    shape = (prob.N,) + (prob.n,) * prob.dim
-    u = torch.zeros(shape, dtype=torch.float64, device=dev)
-    p = torch.zeros_like(u)
-    out = dict(workload="heat3d_127_N128_lognormal", dofs=dofs, tol=args.tol3d, restart=args.gmres_restart)
-    # f32_nuH2: float32 preconditioner with two V-cycles per H~_k^{-1} (nu_H = 2)
-    for key in ("f64", "f32", "bf16", "f32_nuH2"):
-        prec = key.split("_")[0]
-        s = stp.SpaceTimeSolver(prob.dim, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0, precision=prec,
-                                omega=0.0, tol=args.tol3d, max_iter=3000, check_every=args.check_every,
-                                nu_H=2 if key.endswith("nuH2") else 1)
-        s.autotune(reps=3)
-        r = dict(omega=s.omega_info()["omega"])
-        for _ in range(2):
-            u.zero_()
-            p.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, _, info = s.solve(u, p)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-        r["uzawa"] = dict(iters=info["iters"], sec=t1 - t0, rel_res=info["rel_res"], status=info["status"],
-                          dof_it_per_s=dofs * info["iters"] / (t1 - t0))
-        progress(f"3-D {key}: uzawa to tol", f"{info['iters']} its {t1 - t0:.2f}s")
-        nb = stp.stp_gmres_workspace_bytes(s.ctx, args.gmres_restart)
-        ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=dev)
-        for _ in range(2):
-            u.zero_()
-            p.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, _, gi = s.gmres(u, p, restart=args.gmres_restart, workspace=ws)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-        r["gmres"] = dict(steps=gi["iters"], sec=t1 - t0, rel_res=gi["rel_res"], status=gi["status"])
-        progress(f"3-D {key}: gmres to tol", f"{gi['iters']} steps {t1 - t0:.2f}s")
-        del ws
-        s.close()
-        out[key] = r
-    for prec in ("f32", "bf16", "f32_nuH2"):
-        out[prec]["uzawa_speedup_vs_f64"] = out["f64"]["uzawa"]["sec"] / out[prec]["uzawa"]["sec"]
-        out[prec]["best_speedup_vs_f64_uzawa"] = out["f64"]["uzawa"]["sec"] / min(out[prec]["uzawa"]["sec"],
-                                                                                   out[prec]["gmres"]["sec"])
-    return out
-
-
-def paper83_run(args):
-    """The 3-D problem of the paper's time-parallel experiments (Section 8.3,
-    Tables 3 and 4) in finite-difference form on one GPU: 15^3 interior nodes
-    (the paper's 16^3-cell mesh), T = 0.1, kappa = 1, F = 0, u0 = sin sin sin
-    (exact solution exp(-3 pi^2 t) sin sin sin); time to ||f - B u|| <= 1e-8 ||f||
-    from zero with Uzawa and GMRES(restart) for growing N (the weak-scaling
-    direction of Table 3), float64, and float32 preconditioners at the largest
-    N.  The paper's numbers (Q1 elements, hypre AMG, GMRES-accelerated Uzawa,
-    Vulcan BlueGene/Q) are context only."""
-    import torch
-
-    import paper_1802_08126_amd as stp
-    import synth
-
-    out = dict(workload="heat3d_sine_15", tol=1e-8, restart=args.gmres_restart,
-               paper_context=dict(source="Tables 3-4", machine="Vulcan BlueGene/Q", procs=4096, N=65536,
-                                  iters=22, sec_per_iter=1.87, total_sec=41.09,
-                                  method="GMRES-accelerated inexact Uzawa, Q1 FEM, hypre AMG, FFTW3"),
-               runs=[])
-    for N, prec in ((1024, "f64"), (16384, "f64"), (65536, "f64"), (65536, "f32")):
-        prob = synth.heat3d_sine(N=N)
-        dev = "cuda:0"
-        kf = torch.as_tensor(prob.kfields, dtype=torch.float64, device=dev)
-        F = torch.zeros((N,) + (prob.n,) * 3, dtype=torch.float64, device=dev)
-        u0 = torch.as_tensor(prob.u0, dtype=torch.float64, device=dev)
-        s = stp.SpaceTimeSolver(3, prob.n, N, prob.tau, kf, prob.tcoef, F, u0, precision=prec, omega=0.0,
-                                tol=1e-8, max_iter=2000, check_every=args.check_every)
-        s.autotune(reps=3)
-        r = dict(N=N, precision=prec, dofs=N * prob.npts, omega=s.omega_info()["omega"])
-        u = torch.zeros((N,) + (prob.n,) * 3, dtype=torch.float64, device=dev)
-        p = torch.zeros_like(u)
-        for _ in range(2):
-            u.zero_()
-            p.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, _, info = s.solve(u, p)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-        r["uzawa"] = dict(iters=info["iters"], sec=t1 - t0, sec_per_iter=(t1 - t0) / max(info["iters"], 1),
-                          rel_res=info["rel_res"], status=info["status"])
-        nb = stp.stp_gmres_workspace_bytes(s.ctx, args.gmres_restart)
-        ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=dev)
-        for _ in range(2):
-            u.zero_()
-            p.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, _, gi = s.gmres(u, p, restart=args.gmres_restart, workspace=ws)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-        r["gmres"] = dict(steps=gi["iters"], sec=t1 - t0, sec_per_step=(t1 - t0) / max(gi["iters"], 1),
-                          rel_res=gi["rel_res"], status=gi["status"])
-        progress(f"sec8.3 N={N} {prec}", f"uzawa {r['uzawa']['iters']} its {r['uzawa']['sec']:.2f}s, "
-                 f"gmres {gi['iters']} steps {t1 - t0:.2f}s")
-        del ws, u, p, F
-        s.close()
-        out["runs"].append(r)
-    return out
-
-
-def roofline(rep, dims, ts, steps, workload="heat2d_255_N256", dtype="f64"):
+def roofline(rep, dims, ts, workload, dtype):
     """Dominant kernel (largest summed device time) and its achieved HBM rate."""
     if not rep:
         return None, []
     rep = sorted(rep, key=lambda r: -r["total_ms"])
+    rep = [r for r in rep if not r["kernel"].startswith(("k_saddle_norms", "k_sum_rows"))]
     total = sum(r["total_ms"] for r in rep)
     top = rep[0]
     b = algorithmic_bytes(top["kernel"], top["level"], dims, ts)
@@ -509,36 +133,678 @@ def roofline(rep, dims, ts, steps, workload="heat2d_255_N256", dtype="f64"):
         traffic, src = m["bytes"], m["profile"]
     return dict(bound="hbm", kernel=top["kernel"], level=top["level"], achieved=achieved, peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic, traffic_unit="bytes per launch",
-                traffic_source=src, bytes_per_launch=b, avg_launch_us=1e3 * top["avg_ms"]), table
+                traffic_source=src, bytes_per_launch=b, avg_launch_us=1e3 * top["avg_ms"],
+                launches=top["launches"], target_frac=0.6, target_met=achieved / HBM_PEAK_GBS >= 0.6), table
 
 
-def cpu_baseline(workload, iters=3):
-    """The oracle's inexact Uzawa iteration timed on the host (``iters``
-    iterations after its setup, about 10 s on the 2-D workload)."""
+# ---------------------------------------------------------------------------
+# exact solutions (plain float64 torch; independent of the HIP library and the oracle)
+# ---------------------------------------------------------------------------
+def fd_apply_torch(kap, v, h):
+    """-div(kappa grad v) by the conservative finite-difference stencil of the
+    problem statement: kappa nodal on the (n+2)^d grid, face value the mean of
+    the two nodes it joins, v on the n^d interior nodes, zero on the boundary."""
+    import torch
+    d = kap.dim()
+    n = kap.shape[-1] - 2
+    vp = torch.nn.functional.pad(v, (1, 1) * d)
+    out = torch.zeros_like(v)
+    for a in range(d):
+        lo = [slice(1, n + 1)] * d
+        hi = [slice(1, n + 1)] * d
+        lo[a] = slice(0, n + 1)
+        hi[a] = slice(1, n + 2)
+        kf = 0.5 * (kap[tuple(lo)] + kap[tuple(hi)])          # faces j + 1/2, j = 0..n
+        flux = kf * (vp[tuple(hi)] - vp[tuple(lo)])
+        first = [slice(None)] * d
+        last = [slice(None)] * d
+        first[a] = slice(1, n + 1)
+        last[a] = slice(0, n)
+        out -= flux[tuple(first)] - flux[tuple(last)]
+    return out / (h * h)
+
+
+def manufactured_3d(n, N, seed, contrast, device):
+    """The lognormal 3-D workload with the source of u*(t,x) = exp(-3 pi^2 t) S(x),
+    S = sin(pi x) sin(pi y) sin(pi z): F_n = (u*_n - u*_{n-1}) / tau + A_n u*_n,
+    u0 = S, so the exact discrete solution is u*_n.  Built on the device, slab by slab."""
+    import numpy as np
+    import torch
+
+    import synth
+    prob = synth.heat3d_lognormal(n=n, N=N, seed=seed, contrast=contrast, source="none")
+    kf = torch.as_tensor(np.ascontiguousarray(prob.kfields), dtype=torch.float64, device=device)
+    S = torch.as_tensor(prob.u0, dtype=torch.float64, device=device)
+    AS = fd_apply_torch(kf[0], S, prob.h)
+    tau = prob.tau
+    e = np.exp(-3 * math.pi ** 2 * tau * np.arange(N + 1))
+    tc = prob.tcoef[0]
+    F = torch.empty((N, n, n, n), dtype=torch.float64, device=device)
+    for k in range(N):
+        torch.add(S * ((e[k + 1] - e[k]) / tau), AS, alpha=float(tc[k] * e[k + 1]), out=F[k])
+    del AS
+    return dict(prob=prob, kf=kf, F=F, S=S, e=e)
+
+
+def manufactured_error(u, S, e):
+    """Relative L2 and max-norm error of u (device, N x n^3) against e_n S."""
+    num = den = emax = umax = 0.0
+    for k in range(u.shape[0]):
+        ex = S * float(e[k + 1])
+        d = u[k] - ex
+        num += float((d * d).sum())
+        den += float((ex * ex).sum())
+        emax = max(emax, float(d.abs().max()))
+        umax = max(umax, float(ex.abs().max()))
+    return dict(rel_l2=math.sqrt(num / den), rel_max=emax / umax, reference="closed form")
+
+
+def modal_error(n, N, tau, kap_t, u0, factors, u):
+    """Relative L2 and max-norm error of a 2-D solution u (device, N x n x n) for
+    kappa = kappa(t) only, against the exact implicit-Euler solution: the sine
+    transform S (S_ki = sin(k pi i h)) diagonalises every A_n with eigenvalues
+    lambda_k + lambda_l, lambda_k = (4/h^2) sin^2(k pi h / 2), so each mode obeys
+    uh_n = (uh_{n-1} + tau Fh_n) / (1 + tau kappa(t_n) (lambda_k + lambda_l)).
+    F is given by its separable Gaussian factors [(g_t, [g_x, g_y])]."""
+    import numpy as np
+    import torch
+    dev = u.device
+    h = 1.0 / (n + 1)
+    k = torch.arange(1, n + 1, dtype=torch.float64, device=dev)
+    Smat = torch.sin(math.pi * h * torch.outer(k, k))
+    lam1 = (4.0 / h ** 2) * torch.sin(0.5 * math.pi * h * k) ** 2
+    lam = lam1[:, None] + lam1[None, :]                       # (ky, kx)
+    inv = (2.0 / (n + 1)) ** 2
+    uh = Smat @ torch.as_tensor(u0, dtype=torch.float64, device=dev) @ Smat.T
+    fy = [Smat @ torch.as_tensor(g[1], dtype=torch.float64, device=dev) for _, g in factors]
+    fx = [Smat @ torch.as_tensor(g[0], dtype=torch.float64, device=dev) for _, g in factors]
+    gts = np.array([gt for gt, _ in factors])                 # (count, N)
+    num = den = emax = umax = 0.0
+    for m in range(N):
+        Fh = torch.zeros((n, n), dtype=torch.float64, device=dev)
+        for i in range(len(factors)):
+            Fh += float(gts[i, m]) * torch.outer(fy[i], fx[i])
+        uh = (uh + tau * Fh) / (1.0 + tau * float(kap_t[m]) * lam)
+        ue = inv * (Smat.T @ uh @ Smat)
+        d = u[m] - ue
+        num += float((d * d).sum())
+        den += float((ue * ue).sum())
+        emax = max(emax, float(d.abs().max()))
+        umax = max(umax, float(ue.abs().max()))
+    return dict(rel_l2=math.sqrt(num / den), rel_max=emax / umax)
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on the host cores (child process)
+# ---------------------------------------------------------------------------
+def host_description():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return dict(cpu_model=model, nproc=os.cpu_count(), affinity=aff, threads=max(1, min(16, aff or 1)))
+
+
+def cpu_baseline_child(out_path, iters):
+    """The oracle timed on the host: (i) sequential implicit Euler on the 2-D
+    255^2 x 256 workload (multigrid-preconditioned CG per step to 1e-13, all
+    threads), whose solution is saved as the reference of the GPU's 2-D
+    results; (ii) ``iters`` inexact Uzawa iterations of the oracle on the same
+    workload with all threads and with one thread."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import synth
-    from oracle import uzawa
+    from oracle import euler, uzawa
 
-    prob = synth.CONFIG_BUILDERS[workload]()
-    stamps = []
+    hd = host_description()
+    T = hd["threads"]
+    prob = synth.CONFIG_BUILDERS["heat2d_255_N256"]()
+    res = dict(host=hd)
+    with threadpool_limits(limits=T):
+        t0 = time.perf_counter()
+        ue = euler.seq_euler(prob, method="cg", rtol=1e-13)
+        res["seq_euler"] = dict(sec=time.perf_counter() - t0, threads=T, steps=prob.N,
+                                dofs_per_s=prob.N * prob.npts / (time.perf_counter() - t0))
+    np.save(out_path + ".npy", ue)
+    for thr in (T, 1):
+        stamps = []
+        with threadpool_limits(limits=thr):
+            uzawa.uzawa(prob, omega=0.8, tol=0.0, max_iter=iters,
+                        callback=lambda j, u, p, r: stamps.append(time.perf_counter()))
+        sec = float(stamps[-1] - stamps[0])
+        res[f"uzawa_t{thr}"] = dict(sec=sec, iters=len(stamps) - 1, threads=thr,
+                                    value=prob.N * prob.npts * (len(stamps) - 1) / sec)
+    with open(out_path + ".json", "w") as fh:
+        json.dump(res, fh)
 
-    def cb(j, u, p, r):
-        stamps.append(time.perf_counter())
-    with threadpool_limits(limits=1):
-        uzawa.uzawa(prob, omega=0.8, tol=0.0, max_iter=iters, callback=cb)
-    sec = float(stamps[-1] - stamps[0])
-    n_it = len(stamps) - 1
-    return dict(value=prob.N * prob.npts * n_it / sec, unit="DoF-it/s", cores=1, kind="oracle",
-                sample=f"{n_it} inexact Uzawa iterations of the CPU float64 oracle (numpy, 1 thread) on "
-                       f"{workload}: {sec:.1f} s")
+
+def start_cpu_baseline(iters):
+    import multiprocessing as mp
+    import tempfile
+    path = os.path.join(tempfile.gettempdir(), f"stp_bench_oracle_{os.getpid()}")
+    ctx = mp.get_context("spawn")
+    proc = ctx.Process(target=cpu_baseline_child, args=(path, iters), daemon=True)
+    proc.start()
+    return proc, path
+
+
+def finish_cpu_baseline(proc, path, timeout):
+    import numpy as np
+    t0 = time.perf_counter()
+    while proc.is_alive() and time.perf_counter() - t0 < timeout:
+        proc.join(30)
+        if proc.is_alive():
+            progress(f"cpu baseline still running ({time.perf_counter() - t0:.0f} s)")
+    if proc.is_alive():
+        proc.terminate()
+        proc.join(10)
+        return None, None
+    try:
+        with open(path + ".json") as fh:
+            res = json.load(fh)
+        ue = np.load(path + ".npy")
+    except (OSError, ValueError):
+        return None, None
+    for ext in (".json", ".npy"):
+        try:
+            os.remove(path + ext)
+        except OSError:
+            pass
+    hd = res["host"]
+    T = hd["threads"]
+    u_all, u_one = res[f"uzawa_t{T}"], res["uzawa_t1"]
+    out = dict(value=u_all["value"], unit="DoF-it/s", cores=T, kind="oracle",
+               sample=f"{u_all['iters']} inexact Uzawa iterations of the CPU float64 oracle (numpy/scipy) on "
+                      f"heat2d_255_N256 with {T} threads: {u_all['sec']:.1f} s",
+               single_core=dict(value=u_one["value"], cores=1, sec=u_one["sec"], iters=u_one["iters"]),
+               seq_euler=dict(res["seq_euler"], note="oracle sequential implicit Euler (CG + V-cycle per "
+                                                     "step to 1e-13) on all 256 steps: the reference of "
+                                                     "heat2d_255_N256's errors"),
+               cpu_model=hd["cpu_model"], nproc=hd["nproc"], affinity=hd["affinity"],
+               concurrent_with_gpu_legs=True)
+    return out, ue
+
+
+# ---------------------------------------------------------------------------
+# GPU legs
+# ---------------------------------------------------------------------------
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def timed(s, u, p, tol, max_iter, warm=1):
+    """A solve with the given stop rule after a short one that captures the
+    iteration graph for (u, p); both start from zero.  Returns (sec, info)."""
+    s.set_stop(0.0, warm)
+    u.zero_()
+    p.zero_()
+    s.solve(u, p)
+    s.set_stop(tol, max_iter)
+    u.zero_()
+    p.zero_()
+    sync()
+    t0 = time.perf_counter()
+    _, _, info = s.solve(u, p)
+    sync()
+    return time.perf_counter() - t0, info
+
+
+def phase_split(info):
+    ph = info["phase_ms"]
+    tot = sum(ph.values())
+    return dict(ms=ph, share={k: (v / tot if tot > 0 else 0.0) for k, v in ph.items()})
+
+
+def headline_run(args):
+    """Config 5: 255^3 x 64, lognormal (contrast 1e3), manufactured source."""
+    import torch
+
+    import paper_1802_08126_amd as stp
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    inp = manufactured_3d(255, 64, 1005, 1e3, dev)
+    sync()
+    prob, kf, F, S, e = inp["prob"], inp["kf"], inp["F"], inp["S"], inp["e"]
+    progress("headline inputs", f"{time.perf_counter() - t0:.1f}s")
+    dofs = prob.N * prob.npts
+    shape = (prob.N,) + (prob.n,) * 3
+    u = torch.zeros(shape, dtype=torch.float64, device=dev)
+    p = torch.zeros_like(u)
+    dims = level_dims(3, prob.n, prob.N, prob.R)
+    out = dict(workload=HEADLINE, dofs=dofs, input_setup_s=time.perf_counter() - t0)
+    for prec in args.precisions.split(","):
+        t1 = time.perf_counter()
+        s = stp.SpaceTimeSolver(3, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, S, precision=prec, omega=0.0,
+                                tol=0.0, max_iter=args.steps, check_every=args.check_every)
+        create_s = time.perf_counter() - t1
+        tune = s.autotune(reps=2, use_cache=False)
+        r = dict(create_s=create_s, omega=s.omega_info(), autotune=tune)
+        # K timed iterations (the throughput value)
+        s.set_stop(0.0, args.warmup)
+        u.zero_()
+        p.zero_()
+        s.solve(u, p)
+        s.set_stop(0.0, args.steps)
+        u.zero_()
+        p.zero_()
+        sync()
+        t1 = time.perf_counter()
+        _, _, info = s.solve(u, p)
+        sync()
+        sec = time.perf_counter() - t1
+        assert info["iters"] == args.steps, info
+        r.update(sec=sec, ms_per_step=1e3 * sec / args.steps, value=dofs * args.steps / sec,
+                 device_ms=info["ms"], setup_ms=info["setup_ms"], omega_ms=info["omega_ms"])
+        # per-kernel and per-phase device times: the same K iterations launched
+        # eagerly with a HIP event pair around every launch
+        s.timing(True)
+        u.zero_()
+        p.zero_()
+        _, _, ti = s.solve(u, p)
+        r["kernels"] = s.timing_report()
+        r["phases"] = phase_split(ti)
+        s.timing(False)
+        # time to the metric's tolerance, and the error of that solution
+        if not args.skip_tol:
+            sec, info = timed(s, u, p, args.tol, 3000)
+            err = manufactured_error(u, S, e)
+            r["tol"] = dict(tol=args.tol, iters=info["iters"], sec=sec, rel_res=info["rel_res"],
+                            rel_rp=info["rel_rp"], rel_ru=info["rel_ru"], status=info["status"],
+                            dof_it_per_s=dofs * info["iters"] / sec, error=err)
+            progress(f"headline {prec}: to {args.tol:g}", f"{info['iters']} its {sec:.2f}s", err)
+        s.close()
+        torch.cuda.empty_cache()
+        out[prec] = r
+        progress(f"headline {prec}: {r['value']:.3e} DoF-it/s, {r['ms_per_step']:.1f} ms/step")
+    del F, u, p, kf, S
+    torch.cuda.empty_cache()
+    return prob, dims, out
+
+
+def heat2d_run(args):
+    """Config 2: 255^2 x 256, kappa = 1 + 0.5 sin(2 pi t) cos(pi x), Gaussian source."""
+    import numpy as np
+    import torch
+
+    import paper_1802_08126_amd as stp
+    import synth
+    dev = "cuda:0"
+    prob = synth.CONFIG_BUILDERS["heat2d_255_N256"]()
+    kf = torch.as_tensor(np.ascontiguousarray(prob.kfields), dtype=torch.float64, device=dev)
+    F = torch.as_tensor(np.ascontiguousarray(prob.F), dtype=torch.float64, device=dev)
+    u0 = torch.as_tensor(np.ascontiguousarray(prob.u0), dtype=torch.float64, device=dev)
+    shape = (prob.N,) + (prob.n,) * 2
+    dofs = prob.N * prob.npts
+    u = torch.zeros(shape, dtype=torch.float64, device=dev)
+    p = torch.zeros_like(u)
+    out = dict(workload="heat2d_255_N256", dofs=dofs)
+    sols = {}
+    for key in ("f64", "f32", "f32_nuH2"):
+        prec = key.split("_")[0]
+        s = stp.SpaceTimeSolver(2, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, u0, precision=prec, omega=0.0,
+                                tol=0.0, max_iter=args.steps, check_every=args.check_every,
+                                nu_H=2 if key.endswith("nuH2") else 1)
+        s.autotune(reps=3, use_cache=False)
+        r = dict(omega=s.omega_info()["omega"])
+        sec, info = timed(s, u, p, 0.0, args.steps, warm=args.warmup)
+        r.update(value=dofs * args.steps / sec, ms_per_step=1e3 * sec / args.steps)
+        sec, info = timed(s, u, p, args.tol, 2000)
+        r["tol"] = dict(tol=args.tol, iters=info["iters"], sec=sec, rel_res=info["rel_res"], status=info["status"])
+        sols[key] = u.clone()
+        # the same solve continued to a 1e-9 residual (the accuracy target of 1e-8 in the
+        # solution needs about one more decade of residual on this workload)
+        s.set_stop(args.tol / 10, 2000)
+        sync()
+        t0 = time.perf_counter()
+        _, _, info = s.solve(u, p)
+        sync()
+        r["tol"]["refine"] = dict(tol=args.tol / 10, extra_iters=info["iters"], extra_sec=time.perf_counter() - t0,
+                                  status=info["status"], rel_res=info["rel_res"])
+        sols[key + "/refine"] = u.clone()
+        if key == "f32":
+            nb = stp.stp_gmres_workspace_bytes(s.ctx, args.gmres_restart)
+            ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=dev)
+            for _ in range(2):
+                u.zero_()
+                p.zero_()
+                sync()
+                t0 = time.perf_counter()
+                _, _, gi = s.gmres(u, p, restart=args.gmres_restart, workspace=ws)
+                sync()
+                tg = time.perf_counter() - t0
+            r["gmres"] = dict(restart=args.gmres_restart, steps=gi["iters"], sec=tg, rel_res=gi["rel_res"],
+                              status=gi["status"])
+            del ws
+        s.close()
+        out[key] = r
+        progress(f"2-D {key}: to tol {r['tol']['iters']} its {r['tol']['sec']:.3f}s")
+    out["f32"]["speedup_vs_f64"] = out["f32"]["value"] / out["f64"]["value"]
+    out["f32"]["time_to_tol_speedup_vs_f64"] = out["f64"]["tol"]["sec"] / out["f32"]["tol"]["sec"]
+    del F, u, p
+    torch.cuda.empty_cache()
+    return out, sols
+
+
+def heat2d_errors(out, sols, ue):
+    """Errors of the 2-D solutions against the oracle's sequential implicit Euler."""
+    import torch
+    ref = torch.as_tensor(ue, dtype=torch.float64, device="cuda:0")
+    rn, rm = float(torch.linalg.vector_norm(ref)), float(ref.abs().max())
+    for key, u in sols.items():
+        d = u - ref
+        err = dict(rel_l2=float(torch.linalg.vector_norm(d)) / rn, rel_max=float(d.abs().max()) / rm,
+                   reference="oracle sequential Euler")
+        if key.endswith("/refine"):
+            out[key.split("/")[0]]["tol"]["refine"]["error"] = err
+        else:
+            out[key]["tol"]["error"] = err
+
+
+def heat3d_mid_run(args):
+    """Config 3: 127^3 x 128, lognormal (contrast 1e2), manufactured source, to 1e-10."""
+    import torch
+
+    import paper_1802_08126_amd as stp
+    dev = "cuda:0"
+    inp = manufactured_3d(127, 128, 1003, 1e2, dev)
+    prob, kf, F, S, e = inp["prob"], inp["kf"], inp["F"], inp["S"], inp["e"]
+    dofs = prob.N * prob.npts
+    u = torch.zeros((prob.N,) + (prob.n,) * 3, dtype=torch.float64, device=dev)
+    p = torch.zeros_like(u)
+    out = dict(workload="heat3d_127_N128_lognormal", dofs=dofs, tol=args.tol3d)
+    for key in ("f64", "f32", "bf16", "f32_nuH2"):
+        prec = key.split("_")[0]
+        s = stp.SpaceTimeSolver(3, prob.n, prob.N, prob.tau, kf, prob.tcoef, F, S, precision=prec, omega=0.0,
+                                tol=args.tol3d, max_iter=3000, check_every=args.check_every,
+                                nu_H=2 if key.endswith("nuH2") else 1)
+        s.autotune(reps=2, use_cache=False)
+        sec, info = timed(s, u, p, args.tol3d, 3000)
+        r = dict(omega=s.omega_info()["omega"],
+                 uzawa=dict(iters=info["iters"], sec=sec, rel_res=info["rel_res"], status=info["status"],
+                            dof_it_per_s=dofs * info["iters"] / sec, error=manufactured_error(u, S, e)))
+        if key == "f32":
+            nb = stp.stp_gmres_workspace_bytes(s.ctx, args.gmres_restart)
+            ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=dev)
+            u.zero_()
+            p.zero_()
+            s.gmres(u, p, restart=args.gmres_restart, workspace=ws)   # captures its graphs
+            u.zero_()
+            p.zero_()
+            sync()
+            t0 = time.perf_counter()
+            _, _, gi = s.gmres(u, p, restart=args.gmres_restart, workspace=ws)
+            sync()
+            r["gmres"] = dict(restart=args.gmres_restart, steps=gi["iters"], sec=time.perf_counter() - t0,
+                              rel_res=gi["rel_res"], status=gi["status"], error=manufactured_error(u, S, e))
+            del ws
+        s.close()
+        out[key] = r
+        progress(f"3-D 127 {key}: {info['iters']} its {sec:.2f}s", r["uzawa"]["error"])
+    for key in ("f32", "bf16", "f32_nuH2"):
+        out[key]["uzawa_speedup_vs_f64"] = out["f64"]["uzawa"]["sec"] / out[key]["uzawa"]["sec"]
+    del F, u, p
+    torch.cuda.empty_cache()
+    return out
+
+
+def batch_inputs(specs, device):
+    """Batch problems on the device.  Coefficients, initial data and the source's
+    separable Gaussian factors come from the seeded generator; the source is
+    assembled on the device from those factors in the generator's own operation
+    order (identical values)."""
+    import torch
+
+    import synth
+    probs, parts = [], []
+    for sp in specs:
+        kf, tc, factors, u0 = synth.batch2d_parts(sp)
+        n, N = sp["side"], sp["N"]
+        F = torch.zeros((N, n, n), dtype=torch.float64, device=device)
+        for gt, (gx, gy) in factors:
+            G = torch.as_tensor(gy, device=device)[:, None] * torch.as_tensor(gx, device=device)[None, :]
+            F += torch.as_tensor(gt, device=device)[:, None, None] * G[None]
+        probs.append(dict(dim=2, n=n, N=N, tau=1.0 / N, tcoef=tc, F=F,
+                          kfields=torch.as_tensor(kf, dtype=torch.float64, device=device),
+                          u0=torch.as_tensor(u0, dtype=torch.float64, device=device)))
+        parts.append((tc[0] * kf[0, 0, 0], u0, factors))
+    return probs, parts
+
+
+def batch_errors(probs, parts, us):
+    errs = [modal_error(q["n"], q["N"], q["tau"], kt, u0, fac, us[i])
+            for i, (q, (kt, u0, fac)) in enumerate(zip(probs, parts))]
+    return dict(rel_l2_max=max(e["rel_l2"] for e in errs), rel_max_max=max(e["rel_max"] for e in errs),
+                reference="exact modal solution (kappa depends on time only)")
+
+
+def batch_leg(name, specs, args, precisions_steps, precisions_tol, tune=True, tol_refine=None):
+    """A batch of independent problems in one context (merged launches, one graph
+    per iteration) against a loop of single-problem contexts, in the same
+    precision: K fixed iterations, and the time until every problem meets the
+    stop test."""
+    import torch
+
+    import paper_1802_08126_amd as stp
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    probs, parts = batch_inputs(specs, dev)
+    sync()
+    dofs = sum(q["N"] * q["n"] ** 2 for q in probs)
+    us = [torch.zeros((q["N"], q["n"], q["n"]), dtype=torch.float64, device=dev) for q in probs]
+    ps = [torch.zeros_like(x) for x in us]
+    K = args.batch_steps
+    out = dict(problems=len(probs), dofs=dofs, sides=sorted({q["n"] for q in probs}),
+               N_range=[min(q["N"] for q in probs), max(q["N"] for q in probs)], input_setup_s=time.perf_counter() - t0)
+
+    def zero():
+        for x in us + ps:
+            x.zero_()
+        sync()
+
+    def run_batch(b, tol, max_iter, warm=1):
+        b.set_stop(0.0, warm)
+        zero()
+        b.solve(us, ps)
+        b.set_stop(tol, max_iter)
+        zero()
+        t1 = time.perf_counter()
+        _, _, infos, status = b.solve(us, ps)
+        sync()
+        return time.perf_counter() - t1, infos, status
+
+    def run_loop(ss, tol, max_iter):
+        for i, sv in enumerate(ss):
+            sv.set_stop(0.0, 1)
+            sv.solve(us[i], ps[i])
+            sv.set_stop(tol, max_iter)
+        zero()
+        t1 = time.perf_counter()
+        infos = [sv.solve(us[i], ps[i])[2] for i, sv in enumerate(ss)]
+        sync()
+        return time.perf_counter() - t1, infos
+
+    omegas = None
+    for prec in sorted(set(precisions_steps) | set(precisions_tol)):
+        t1 = time.perf_counter()
+        b = stp.BatchSolver(probs, precision=prec, omega=0.0 if omegas is None else 1.0, tol=0.0, max_iter=K,
+                            check_every=args.check_every)
+        if omegas is None:
+            omegas = b.omegas()
+            out["omega"] = dict(min=min(omegas), max=max(omegas), source="estimated", create_s=time.perf_counter() - t1)
+        else:
+            b.set_omegas(omegas)
+        r = {}
+        if tune:
+            t1 = time.perf_counter()
+            tr = b.autotune(reps=2, use_cache=False)
+            r["autotune"] = dict(tr, sec=time.perf_counter() - t1)
+        ss = [stp.SpaceTimeSolver(2, q["n"], q["N"], q["tau"], q["kfields"], q["tcoef"], q["F"], q["u0"],
+                                  precision=prec, omega=omegas[i], tol=0.0, max_iter=K,
+                                  check_every=args.check_every) for i, q in enumerate(probs)]
+        if tune:
+            for sv in ss:
+                sv.autotune(reps=2, use_cache=True)
+        if prec in precisions_steps:
+            sb, _, _ = run_batch(b, 0.0, K)
+            sl, _ = run_loop(ss, 0.0, K)
+            r["steps"] = dict(K=K, batch_sec=sb, loop_sec=sl, batch_value=dofs * K / sb, loop_value=dofs * K / sl,
+                              batching_speedup=sl / sb)
+        if prec in precisions_tol:
+            sb, infos, status = run_batch(b, args.tol, 3000)
+            its = [i["iters"] for i in infos]
+            err = batch_errors(probs, parts, us)
+            rt = dict(tol=args.tol, batch_sec=sb, batch_status=status, batch_iters=[min(its), max(its)],
+                      batch_error=err)
+            if tol_refine:
+                # continue the same solve to a tighter residual (warm start)
+                b.set_stop(tol_refine, 3000)
+                t1 = time.perf_counter()
+                _, _, infos2, st2 = b.solve(us, ps)
+                sync()
+                rt["refine"] = dict(tol=tol_refine, extra_sec=time.perf_counter() - t1, status=st2,
+                                    error=batch_errors(probs, parts, us))
+            sl, infos = run_loop(ss, args.tol, 3000)
+            its = [i["iters"] for i in infos]
+            rt.update(loop_sec=sl, loop_iters=[min(its), max(its)], batching_speedup=sl / sb,
+                      loop_status=min(i["status"] for i in infos))
+            r["tol"] = rt
+        for sv in ss:
+            sv.close()
+        b.close()
+        torch.cuda.empty_cache()
+        out[prec] = r
+        progress(f"{name} {prec}:", {k: (round(v["batching_speedup"], 3) if "batching_speedup" in v else None)
+                                      for k, v in r.items() if isinstance(v, dict) and k in ("steps", "tol")})
+    return out
+
+
+def paper83_run(args):
+    """The 3-D problem of the paper's time-parallel experiments (Section 8.3,
+    Tables 3 and 4) in finite-difference form on one GPU: 15^3 interior nodes
+    (the paper's 16^3-cell mesh), T = 0.1, kappa = 1, F = 0, u0 = sin sin sin;
+    time to ||f - B u|| <= 1e-8 ||f|| from zero with Uzawa and GMRES(restart),
+    with the error against the semi-discrete modal decay.  The paper's numbers
+    (Q1 elements, hypre AMG, GMRES-accelerated Uzawa, Vulcan BlueGene/Q) are
+    context only."""
+    import numpy as np
+    import torch
+
+    import paper_1802_08126_amd as stp
+    import synth
+
+    out = dict(workload="heat3d_sine_15", tol=1e-8, restart=args.gmres_restart,
+               paper_context=dict(source="Tables 3-4", machine="Vulcan BlueGene/Q", procs=4096, N=65536,
+                                  iters=22, sec_per_iter=1.87, total_sec=41.09,
+                                  method="GMRES-accelerated inexact Uzawa, Q1 FEM, hypre AMG, FFTW3"),
+               runs=[])
+    dev = "cuda:0"
+    for N, prec in ((1024, "f64"), (65536, "f64"), (65536, "f32")):
+        prob = synth.heat3d_sine(N=N)
+        kf = torch.as_tensor(prob.kfields, dtype=torch.float64, device=dev)
+        F = torch.zeros((N,) + (prob.n,) * 3, dtype=torch.float64, device=dev)
+        u0 = torch.as_tensor(prob.u0, dtype=torch.float64, device=dev)
+        s = stp.SpaceTimeSolver(3, prob.n, N, prob.tau, kf, prob.tcoef, F, u0, precision=prec, omega=0.0,
+                                tol=1e-8, max_iter=2000, check_every=args.check_every)
+        s.autotune(reps=2)
+        u = torch.zeros((N,) + (prob.n,) * 3, dtype=torch.float64, device=dev)
+        p = torch.zeros_like(u)
+        sec, info = timed(s, u, p, 1e-8, 2000)
+        # exact discrete solution: the sine mode decays by (1 + tau lambda_1)^-n, lambda_1 = 3 (4/h^2) sin^2(pi h/2)
+        lam = 3 * (4.0 / prob.h ** 2) * math.sin(math.pi * prob.h / 2) ** 2
+        e = np.concatenate([[1.0], np.cumprod(np.full(N, 1.0 / (1.0 + prob.tau * lam)))])
+        S = torch.as_tensor(prob.u0, dtype=torch.float64, device=dev)
+        r = dict(N=N, precision=prec, dofs=N * prob.npts, omega=s.omega_info()["omega"],
+                 uzawa=dict(iters=info["iters"], sec=sec, sec_per_iter=sec / max(info["iters"], 1),
+                            rel_res=info["rel_res"], status=info["status"], error=manufactured_error(u, S, e)))
+        nb = stp.stp_gmres_workspace_bytes(s.ctx, args.gmres_restart)
+        ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            u.zero_()
+            p.zero_()
+            sync()
+            t0 = time.perf_counter()
+            _, _, gi = s.gmres(u, p, restart=args.gmres_restart, workspace=ws)
+            sync()
+            tg = time.perf_counter() - t0
+        r["gmres"] = dict(steps=gi["iters"], sec=tg, sec_per_step=tg / max(gi["iters"], 1), rel_res=gi["rel_res"],
+                          status=gi["status"])
+        progress(f"sec8.3 N={N} {prec}", f"uzawa {info['iters']} its {sec:.2f}s, gmres {gi['iters']} {tg:.2f}s")
+        del ws, u, p, F
+        s.close()
+        torch.cuda.empty_cache()
+        out["runs"].append(r)
+    return out
+
+
+def paper83_q1_run(args):
+    """The Section 8.3 problem with the paper's own discretisation: Q1
+    hexahedra on 16^3 cells (15^3 interior nodes), consistent mass matrix,
+    T = 0.1, kappa = 1, F = 0, u0 = sin sin sin at the nodes.  The sine mode is
+    a generalized eigenvector of the Q1 stiffness and mass, so the exact
+    discrete solution is (1 + tau lambda)^-n u0.  GMRES(restart) around the
+    Uzawa sweep (the paper's solver) and plain Uzawa to ||f - B u|| <= 1e-8 ||f||,
+    one V-cycle with two Jacobi sweeps per side in space; N = 1024 and 65,536
+    (the paper's 22 iterations in 41.09 s on 4096 BG/Q cores, context)."""
+    import numpy as np
+    import torch
+
+    import paper_1802_08126_amd as stp
+    n, T = 15, 0.1
+    h = 1.0 / (n + 1)
+    s1 = np.sin(np.pi * np.arange(1, n + 1) * h)
+    u0 = torch.as_tensor(np.einsum("i,j,k->ijk", s1, s1, s1), device="cuda:0")
+    m1 = (h / 3) * (2 + math.cos(math.pi * h))
+    lam = 3 * (2 / h) * (1 - math.cos(math.pi * h)) / m1
+    out = dict(workload="heat3d_q1_15", elements="Q1 hexahedra, consistent mass", tol=1e-8,
+               restart=args.gmres_restart, sweeps=2, runs=[])
+    for N, prec in ((1024, "f64"), (65536, "f64"), (65536, "f32")):
+        tau = T / N
+        kf = torch.ones((1, n + 2, n + 2, n + 2), dtype=torch.float64, device="cuda:0")
+        F = torch.zeros((N, n, n, n), dtype=torch.float64, device="cuda:0")
+        s = stp.SpaceTimeSolver(3, n, N, tau, kf, np.ones((1, N)), F, u0, disc="fem", spatial="mg", sweeps=2,
+                                precision=prec, omega=0.0, tol=1e-8, max_iter=2000, check_every=args.check_every)
+        s.autotune(reps=2)
+        e = np.concatenate([[1.0], (1.0 + tau * lam) ** -np.arange(1, N + 1)])
+        u = torch.zeros((N, n, n, n), dtype=torch.float64, device="cuda:0")
+        p = torch.zeros_like(u)
+        sec, info = timed(s, u, p, 1e-8, 2000)
+        r = dict(N=N, precision=prec, dofs=N * n ** 3, paper_dofs=2 * N * (n + 2) ** 3,
+                 omega=s.omega_info()["omega"],
+                 uzawa=dict(iters=info["iters"], sec=sec, rel_res=info["rel_res"], status=info["status"],
+                            error=manufactured_error(u, u0, e)))
+        nb = stp.stp_gmres_workspace_bytes(s.ctx, args.gmres_restart)
+        ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device="cuda:0")
+        for _ in range(2):
+            u.zero_()
+            p.zero_()
+            sync()
+            t0 = time.perf_counter()
+            _, _, gi = s.gmres(u, p, restart=args.gmres_restart, workspace=ws)
+            sync()
+            tg = time.perf_counter() - t0
+        r["gmres"] = dict(steps=gi["iters"], sec=tg, sec_per_step=tg / max(gi["iters"], 1), rel_res=gi["rel_res"],
+                          status=gi["status"], error=manufactured_error(u, u0, e))
+        progress(f"sec8.3 Q1 N={N} {prec}", f"uzawa {info['iters']} its {sec:.2f}s, gmres {gi['iters']} {tg:.2f}s",
+                 r["gmres"]["error"])
+        del ws, u, p, F
+        s.close()
+        torch.cuda.empty_cache()
+        out["runs"].append(r)
+    return out
 
 
 # ---------------------------------------------------------------------------
 # hardware-counter profiles (rocprofv3 output of this script)
 # ---------------------------------------------------------------------------
-COPY_ELEMS = 16646400   # float64 values in one slab-vector of heat2d_255_N256
+COPY_ELEMS = 16646400   # float64 values of the copy that calibrates the counters
 
 
 def copy_calibration():
@@ -553,60 +819,49 @@ def copy_calibration():
     print(json.dumps(dict(copy_bytes=COPY_ELEMS * 8, copies=3)), flush=True)
 
 
-# launches that precede a level-0 multigrid down-sweep of the 2-D float64 solver:
-# the r_p residual, the forward transform and the middle operator
-_L0_PRED = ("k_resid_tile<2, double, 0,", "k_time_fft2<double, double, 0, 0,", "k_apply_tile<")
-
-
 def _kname(r):
     return r["Kernel_Name"].split("(")[0].replace("void ", "").replace("stp::", "")
 
 
-def summarize_profile(d, steps):
-    """Markdown summary of rocprofv3 output of this script under d: the
-    --stats table (trace/), the level-0 down-sweep launches of the two timed
-    solves (graph replays, then eager launches; 3 steps + 1 each, picked by
-    their predecessor), and, when the counter passes are there, their HBM bytes
-    from FETCH_SIZE (p1/) and WRITE_SIZE (p2/) scaled by the copy calibration
-    passes (c1/, c2/).  Every run was made with --steps `steps`, --only-f64,
-    --skip-tol, --no-batch and --no-3d, so those solves are the last launches."""
+def summarize_profile(d, kernel_prefix, grid_min):
+    """Markdown summary of rocprofv3 output of this script under d: the --stats
+    table (trace/), and, when the counter passes are there, the HBM bytes per
+    launch of the kernel whose name starts with ``kernel_prefix`` and whose grid
+    has at least ``grid_min`` work-items (the finest level), from FETCH_SIZE
+    (p1/) and WRITE_SIZE (p2/) scaled by the copy calibration passes (c1/, c2/)."""
     import csv
 
     def rows(sub, f):
         with open(os.path.join(d, sub, f)) as fh:
             return list(csv.DictReader(fh))
 
-    def l0(seq):
-        sel = [b for a, b in zip(seq, seq[1:]) if b[0].startswith("k_mg_down<") and a[0].startswith(_L0_PRED)]
-        return sel[-2 * (3 * steps + 1):]
-
-    avg = lambda v: sum(v) / len(v)
+    avg = lambda v: sum(v) / len(v)  # noqa: E731
     print("## rocprofv3 --stats (run_kernel_stats.csv, all dispatches of the run)\n")
     print("| kernel | calls | avg us | min us | max us | % |\n|---|---|---|---|---|---|")
     for r in rows("trace", "run_kernel_stats.csv")[:18]:
         print(f"| `{r['Name'].split('(')[0].replace('void ', '')}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
               f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {r['Percentage']} |")
-    tr = sorted(rows("trace", "run_kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
-    t = [x[1] for x in l0([(_kname(r), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3) for r in tr])]
-    print("\n## Level-0 multigrid down-sweep\n")
-    print("Launches of `k_mg_down` that directly follow the r_p residual, the forward time transform or")
-    print("the middle operator (the level-0 down-sweeps of the three V-cycles of an iteration), in the")
-    print(f"two timed solves of {steps} iterations with the tuned schedule:\n")
-    print(f"| launches | avg us | min us | max us |\n|---|---|---|---|\n| {len(t)} | {avg(t):.1f} | {min(t):.1f} | "
-          f"{max(t):.1f} |")
+    tr = rows("trace", "run_kernel_trace.csv")
+    sel = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr
+           if _kname(r).startswith(kernel_prefix) and int(r["Grid_Size"]) >= grid_min]
+    if sel:
+        print(f"\n## `{kernel_prefix}` launches with grid >= {grid_min} work-items\n")
+        print(f"| launches | avg us | min us | max us |\n|---|---|---|---|\n| {len(sel)} | {avg(sel):.1f} | "
+              f"{min(sel):.1f} | {max(sel):.1f} |")
     if not os.path.isdir(os.path.join(d, "p1")):
         return
     res = {}
     for i, cn in ((1, "FETCH_SIZE"), (2, "WRITE_SIZE")):
-        pm = sorted(rows(f"p{i}", "run_counter_collection.csv"), key=lambda r: int(r["Dispatch_Id"]))
-        v = l0([(_kname(r), float(r["Counter_Value"])) for r in pm if r["Counter_Name"] == cn])
+        pm = rows(f"p{i}", "run_counter_collection.csv")
+        v = [float(r["Counter_Value"]) for r in pm if r["Counter_Name"] == cn and _kname(r).startswith(kernel_prefix)
+             and int(r["Grid_Size"]) >= grid_min]
         cal = [float(r["Counter_Value"]) for r in rows(f"c{i}", "run_counter_collection.csv")
                if "copy" in r["Kernel_Name"].lower() and int(r["Grid_Size"]) > 100000 and r["Counter_Name"] == cn]
         factor = COPY_ELEMS * 8 / (avg(cal) * 1024)
-        kib = avg([x[1] for x in v])
+        kib = avg(v)
         res[cn] = (len(v), kib, avg(cal), factor, kib * 1024 * factor)
     f, w = res["FETCH_SIZE"], res["WRITE_SIZE"]
-    print("\n## HBM traffic of the level-0 down-sweep\n")
+    print(f"\n## HBM traffic of `{kernel_prefix}` (grid >= {grid_min})\n")
     print(f"Calibration: a copy of {COPY_ELEMS * 8:,} bytes reads FETCH_SIZE = {f[2]:,.1f} KiB and WRITE_SIZE = "
           f"{w[2]:,.1f} KiB per dispatch, so bytes = FETCH_SIZE x 1024 x {f[3]:.3f} and WRITE_SIZE x 1024 x "
           f"{w[3]:.3f}.\n")
@@ -615,35 +870,35 @@ def summarize_profile(d, steps):
     print(f"| FETCH_SIZE (KiB, raw) | {f[1]:,.1f} |\n| WRITE_SIZE (KiB, raw) | {w[1]:,.1f} |")
     print(f"| HBM bytes read | {f[4]:,.0f} |\n| HBM bytes written | {w[4]:,.0f} |")
     print(f"| traffic (read + written) | {f[4] + w[4]:,.0f} |")
-    print(f"\nKernel sources at measurement (sha256 of stp_kernels.h + stp_tiles.h + stp.hip):\n"
+    print(f"\nKernel sources at measurement (sha256 of stp_kernels.h + stp_tiles.h + stp_solver.h + stp.hip):\n"
           f"{kernel_sources_sha256()}")
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="heat2d_255_N256")
-    ap.add_argument("--omega", type=float, default=0.0, help="Uzawa damping; <= 0: estimated by the library")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--tol3d", type=float, default=1e-10)
     ap.add_argument("--check-every", type=int, default=8)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--skip-tol", action="store_true")
-    ap.add_argument("--only-f64", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="keep the built-in schedule heuristic")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batch workload")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--gmres-restart", type=int, default=10)
-    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D lognormal time-to-tolerance runs")
-    ap.add_argument("--tol3d", type=float, default=1e-10)
+    ap.add_argument("--cpu-iters", type=int, default=3, help="oracle Uzawa iterations timed in the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-tol", action="store_true")
+    ap.add_argument("--headline-only", action="store_true", help="only the headline workload (profiling runs)")
+    ap.add_argument("--precisions", default="f32,f64,bf16",
+                    help="preconditioner precisions of the headline workload (f32 first: the headline value)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain device copy of one slab-vector (counter calibration)")
+                    help="only run a plain device copy (counter calibration)")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="only summarise rocprofv3 output under DIR (no GPU use)")
+    ap.add_argument("--kernel", default="k_mg_down<3, float", help="kernel prefix for --summarize-profile")
+    ap.add_argument("--grid-min", type=int, default=1 << 22, help="finest-level grid size for --summarize-profile")
     args = ap.parse_args()
     if args.summarize_profile:
-        summarize_profile(args.summarize_profile, args.steps)
+        summarize_profile(args.summarize_profile, args.kernel, args.grid_min)
         return
     if args.copy_calibration:
         copy_calibration()
@@ -652,57 +907,67 @@ def main():
         print("bench.py: runs on one GPU only; sharding the time slabs over several GPUs is a design, "
               "not an implementation.  Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
-    prob, dims, res = gpu_run(args)
-    progress("workload done:", args.workload)
-    r64 = res["f64"]
-    roof, table = roofline(r64.get("kernels"), dims, 8, args.steps, args.workload, "f64")
+    t_start = time.perf_counter()
+    cpu = None
+    if not args.no_cpu_baseline and not args.headline_only:
+        # started before this process touches the GPU (the child never does)
+        cpu = start_cpu_baseline(args.cpu_iters)
+        progress("cpu baseline started (child process)")
+    import torch
+    torch.cuda.set_device(0)
+    prob, dims, head = headline_run(args)
+    h32 = head["f32"]
+    roof, table = roofline(h32.get("kernels"), dims, 4, HEADLINE, "f32")
     out = {
-        "metric": "space-time DoF-iterations/sec + time to 1e-8 residual, mixed vs FP64, 1 GPU",
-        "metric_note": "value: u DoFs x Uzawa iterations / s, float64; time to 1e-8: time_to_tol_f64 "
-                       "and mixed_f32_precond.time_to_tol (one V-cycle per spatial solve, the default); "
-                       "nuH2_time_to_tol_f64 and mixed_f32_precond.nuH2_time_to_tol with two per H-block",
-        "value": r64["value"],
+        "metric": METRIC,
+        "value": h32["value"],
         "unit": "DoF-it/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r64["ms_per_step"],
+        "ms_per_step": h32["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32/f64",
+        "dtype_note": "preconditioner (V-cycles, DSTs, H-blocks) in float32; residuals, updates, dots in float64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "dim": prob.dim, "n_interior": prob.n, "N_t": prob.N,
-                   "dofs": prob.N * prob.npts, "omega": r64["omega"],
-                   "omega_source": "estimated" if args.omega <= 0 else "given", "spatial": "mg V(1,1) Jacobi",
+        "config": {"workload": HEADLINE, "dim": 3, "n_interior": prob.n, "N_t": prob.N, "dofs": prob.N * prob.npts,
+                   "kappa": "lognormal, correlation 0.1, contrast 1e3, times (1 + 0.3 t)",
+                   "source": "manufactured: exact solution exp(-3 pi^2 t) sin sin sin",
+                   "omega": h32["omega"]["omega"], "omega_source": "estimated",
+                   "spatial": "geometric multigrid V(1,1), damped Jacobi",
                    "parallelism": "all time slabs batched in every launch"},
         "roofline": roof,
-        "kernels_f64": table,
-        "ms_per_step_eager_timed": r64.get("ms_per_step_eager_timed"),
-        "autotune_f64": r64.get("autotune"),
+        "headline": {p: {k: v for k, v in head[p].items() if k != "kernels"} for p in args.precisions.split(",")},
     }
-    if "tol" in r64:
-        out["time_to_tol_f64"] = r64["tol"]
-        out["gmres_time_to_tol_f64"] = r64["gmres"]
-        out["nuH2_time_to_tol_f64"] = r64["tol_nuH2"]
-    if "f32" in res:
-        r32 = res["f32"]
-        out["mixed_f32_precond"] = {"value": r32["value"], "ms_per_step": r32["ms_per_step"],
-                                    "dtype": "f32 preconditioner / f64 outer",
-                                    "speedup_vs_f64": r32["value"] / r64["value"]}
-        if "tol" in r32:
-            out["mixed_f32_precond"]["time_to_tol"] = r32["tol"]
-            out["mixed_f32_precond"]["gmres_time_to_tol"] = r32["gmres"]
-            out["mixed_f32_precond"]["nuH2_time_to_tol"] = r32["tol_nuH2"]
-            if "tol" in r64:
-                out["mixed_f32_precond"]["time_to_tol_speedup"] = r64["tol"]["sec"] / r32["tol"]["sec"]
-    if not args.no_batch:
-        out["batch64"] = batch_run(args)
-    if not args.no_3d:
-        out["heat3d_lognormal"] = heat3d_run(args)
+    out["headline"]["kernels_f32"] = table
+    if "f64" in head:
+        out["headline"]["speedup_f32_vs_f64"] = h32["value"] / head["f64"]["value"]
+        if "bf16" in head:
+            out["headline"]["speedup_bf16_vs_f64"] = head["bf16"]["value"] / head["f64"]["value"]
+        if "tol" in h32 and "tol" in head["f64"]:
+            out["headline"]["time_to_tol_speedup_f32_vs_f64"] = head["f64"]["tol"]["sec"] / h32["tol"]["sec"]
+            if "bf16" in head:
+                out["headline"]["time_to_tol_speedup_bf16_vs_f64"] = head["f64"]["tol"]["sec"] / head["bf16"]["tol"]["sec"]
+    if not args.headline_only:
+        h2, sols = heat2d_run(args)
+        out["heat2d_255_N256"] = h2
+        out["heat3d_127_N128_lognormal"] = heat3d_mid_run(args)
+        import synth
+        out["batch64"] = batch_leg("batch64", synth.batch2d(), args, ("f32", "f64"), ("f32",),
+                                   tol_refine=1e-10)
+        small = synth.batch2d(count=64, seed=1006, sides=(31, 63), nt_range=(16, 128))
+        out["batch64_small"] = batch_leg("batch64_small", small, args, ("f32",), ("f32",), tune=False)
         out["paper_sec8_3"] = paper83_run(args)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload)
+        out["paper_sec8_3_q1"] = paper83_q1_run(args)
+        if cpu is not None:
+            progress("waiting for the cpu baseline")
+            base, ue = finish_cpu_baseline(*cpu, timeout=600)
+            if base is not None:
+                out["cpu_baseline"] = base
+                heat2d_errors(h2, sols, ue)
+    out["wall_s"] = time.perf_counter() - t_start
     print(json.dumps(out), flush=True)
 
 
