@@ -310,6 +310,19 @@ size_t stp_gmres_workspace_bytes(stp_ctx* ctx, int restart);
 stp_status stp_gmres_solve(stp_ctx* ctx, double* u, double* p, int restart, void* ws, size_t ws_bytes,
                            double* hist, stp_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): stp_gmres_solve with
+ * its Krylov workspace in a fixed 64 MiB device array of the library instead of
+ * a caller buffer, so the call allocates nothing (it also launches eagerly,
+ * without instantiating graphs).  Problems whose stp_gmres_workspace_bytes(ctx,
+ * restart) exceeds 64 MiB are rejected with EINVAL.  Each GPU holds one copy of
+ * the array until the process ends, shared by every call on that GPU: calls
+ * that overlap on one GPU (two threads or streams) race and must be
+ * serialised by the caller; nothing in the array needs to start at zero.
+ * Results equal stp_gmres_solve's.  Other errors as stp_gmres_solve. */
+stp_status stp_gmres_solve_noalloc(stp_ctx* ctx, double* u, double* p, int restart, double* hist,
+                                   stp_stats* stats);
+
 /* Autotuner (project-written).  Times, on the context's own buffers and
  * stream, the candidate schedules of every merged launch of an iteration and
  * keeps the fastest:

@@ -117,6 +117,9 @@ def load() -> C.CDLL:
     lib.stp_device_bytes_allocated.restype = C.c_size_t
     lib.stp_set_stop.argtypes = [C.c_void_p, C.c_double, C.c_int]
     lib.stp_set_stop.restype = C.c_int
+    lib.stp_gmres_solve_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                            C.POINTER(C.c_double), C.POINTER(stp_stats)]
+    lib.stp_gmres_solve_noalloc.restype = C.c_int
     lib.stp_omega_info.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double)]
     lib.stp_omega_info.restype = C.c_int
     lib.stp_set_omega.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
@@ -333,6 +336,17 @@ def stp_gmres_solve(ctx, u, p, restart, ws, max_iter=None):
     status = load().stp_gmres_solve(ctx, C.c_void_p(u.data_ptr()), C.c_void_p(p.data_ptr()), int(restart),
                                     C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel() * ws.element_size()),
                                     hist, C.byref(st))
+    h = None if hist is None else [hist[i] for i in range(st.iters + 1)]
+    return status, st, h
+
+
+def stp_gmres_solve_noalloc(ctx, u, p, restart, max_iter=None):
+    """stp_gmres_solve with the library's fixed Krylov array (the call allocates
+    no device memory).  Returns (status, stats, history)."""
+    st = stp_stats()
+    hist = (C.c_double * (max_iter + 1))() if max_iter is not None else None
+    status = load().stp_gmres_solve_noalloc(ctx, C.c_void_p(u.data_ptr()), C.c_void_p(p.data_ptr()), int(restart),
+                                            hist, C.byref(st))
     h = None if hist is None else [hist[i] for i in range(st.iters + 1)]
     return status, st, h
 

@@ -1146,18 +1146,18 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
     // kappa(t_n, x) > 0 at every node and step, and for the reference coefficient
     const long nn = q.g0.nnodes;
     const long nb = (nn + kBlock - 1) / kBlock;
-    double* scratch = nullptr;
+    double* kscr = nullptr;
     bool owned = false;
-    if ((s = scratch_get(c.get(), size_t(nb + kMaxRank), &scratch, &owned)) != STP_OK) return s;
+    if ((s = scratch_get(c.get(), size_t(nb + kMaxRank), &kscr, &owned)) != STP_OK) return s;
     std::vector<double> cref(kMaxRank, 0.0);
     for (int r = 0; r < q.R; ++r) cref[r] = q.abar[r];
-    double* part = scratch + kMaxRank;
-    HIP_TRY(hipMemcpyAsync(scratch, cref.data(), kMaxRank * 8, hipMemcpyHostToDevice, c->stream));
+    double* part = kscr + kMaxRank;
+    HIP_TRY(hipMemcpyAsync(kscr, cref.data(), kMaxRank * 8, hipMemcpyHostToDevice, c->stream));
     std::vector<double> h(nb);
     double mn = 1e300;
     for (int pass = 0; pass < 2; ++pass) {
       KLAUNCH(k_kappa_min, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, nn, q.R, pass == 0 ? q.N : 1, q.fields,
-              pass == 0 ? (const double*)q.cA64 : (const double*)scratch, part);
+              pass == 0 ? (const double*)q.cA64 : (const double*)kscr, part);
       LAUNCH_CHECK();
       HIP_TRY(hipMemcpyAsync(h.data(), part, size_t(nb) * 8, hipMemcpyDeviceToHost, c->stream));
       HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1173,7 +1173,7 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
       HIP_TRY(hipStreamSynchronize(c->stream));
       spread = *std::max_element(h.begin(), h.begin() + gb);
     }
-    scratch_put(c.get(), scratch, owned);
+    scratch_put(c.get(), kscr, owned);
     if (!(mn > 0)) return fail(STP_EINVAL, "kappa must be > 0 at every node and step (min %.3e)", mn);
     if (c->disc == STP_DISC_FEM) {
       if (!(spread == 0.0)) return fail(STP_EINVAL, "finite elements: the kappa field must be constant in space");
@@ -1746,9 +1746,52 @@ stp_status gmres_run(stp_ctx* c, double* u, double* p, int restart, double* base
   if (outcome == 3) return fail(r, "GMRES: max_iter %d reached (rel %.3e)", max_iter, res / fnorm);
   return STP_OK;
 }
+
+// ---------------------------------------------------------------------------
+// allocation-free GMRES: the Krylov vectors in a fixed device array of
+// kScratchDoubles values.  Every device that runs the library holds its own
+// copy of `scratch` until the process ends; host code reaches it only through
+// the address hipGetSymbolAddress returns for the current device (the array's
+// name in host code is a host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchDoubles = size_t(8) << 20;   // 64 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_addr;   // device ordinal -> its copy of scratch
+
+stp_status scratch_address(double** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it == g_scratch_addr.end()) {   // once per device, with that device current
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(STP_EDEVICE, "hipGetSymbolAddress of the fixed scratch failed: %s", hipGetErrorString(e));
+    it = g_scratch_addr.emplace(dev, static_cast<double*>(ptr)).first;
+  }
+  *out = it->second;
+  return STP_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+stp_status stp_gmres_solve_noalloc(stp_ctx* c, double* u, double* p, int restart, double* hist, stp_stats* stats) {
+  stp_status s = gmres_check(c, u, p, restart);
+  if (s != STP_OK) return s;
+  const size_t need = gmres_layout(c->pr[0], restart).total;
+  if (need > kScratchDoubles)
+    return fail(STP_EINVAL, "GMRES(%d) of this problem needs %zu bytes; the fixed scratch holds %zu", restart,
+                need * 8, kScratchDoubles * 8);
+  double* base = nullptr;
+  if ((s = scratch_address(&base)) != STP_OK) return s;
+  // eager launches: instantiating a graph may allocate
+  return gmres_run(c, u, p, restart, base, false, hist, stats);
+}
 
 stp_status stp_gmres_solve(stp_ctx* c, double* u, double* p, int restart, void* ws, size_t ws_bytes, double* hist,
                            stp_stats* stats) {
