@@ -59,7 +59,7 @@ MEASURED_TRAFFIC = {}
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("stp_kernels.h", "stp_tiles.h", "stp_solver.h", "stp.hip"):
+    for f in ("stp_kernels.h", "stp_tiles.h", "stp_pencil.h", "stp_solver.h", "stp.hip"):
         with open(os.path.join(ROOT, "paper_1802_08126_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -98,7 +98,7 @@ def algorithmic_bytes(kernel: str, level: int, dims, ts: int) -> float | None:
     add64 = "add64" in kernel
     if k == "k_resid_tile":        # u, p, F in; r out (the other slab's u, p rows are the same arrays)
         return N * npts[0] * (3 * 8 + ts) + kap(0, 8)
-    if k == "k_mg_down":           # b in (fine), bc out (coarse)
+    if k in ("k_mg_down", "k_mg_down_p3"):   # b in (fine), bc out (coarse), one coefficient field
         return N * (n_l + npts[level + 1]) * ts + kap(level, tc)
     if k == "k_mg_up":
         if add64:                  # b, e in; float64 p read and written
@@ -842,8 +842,13 @@ def summarize_profile(d, kernel_prefix, grid_min):
         print(f"| `{r['Name'].split('(')[0].replace('void ', '')}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
               f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {r['Percentage']} |")
     tr = rows("trace", "run_kernel_trace.csv")
+    def grid(r):
+        if "Grid_Size" in r:
+            return int(r["Grid_Size"])
+        return int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+
     sel = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr
-           if _kname(r).startswith(kernel_prefix) and int(r["Grid_Size"]) >= grid_min]
+           if _kname(r).startswith(kernel_prefix) and grid(r) >= grid_min]
     if sel:
         print(f"\n## `{kernel_prefix}` launches with grid >= {grid_min} work-items\n")
         print(f"| launches | avg us | min us | max us |\n|---|---|---|---|\n| {len(sel)} | {avg(sel):.1f} | "
@@ -870,8 +875,27 @@ def summarize_profile(d, kernel_prefix, grid_min):
     print(f"| FETCH_SIZE (KiB, raw) | {f[1]:,.1f} |\n| WRITE_SIZE (KiB, raw) | {w[1]:,.1f} |")
     print(f"| HBM bytes read | {f[4]:,.0f} |\n| HBM bytes written | {w[4]:,.0f} |")
     print(f"| traffic (read + written) | {f[4] + w[4]:,.0f} |")
-    print(f"\nKernel sources at measurement (sha256 of stp_kernels.h + stp_tiles.h + stp_solver.h + stp.hip):\n"
-          f"{kernel_sources_sha256()}")
+    if os.path.isdir(os.path.join(d, "p3")):
+        pm = rows("p3", "run_counter_collection.csv")
+        sel = {}
+        for r in pm:
+            if _kname(r).startswith(kernel_prefix) and int(r["Grid_Size"]) >= grid_min:
+                sel.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        if sel:
+            print(f"\n## Instruction counters of `{kernel_prefix}` (grid >= {grid_min}), average per launch\n")
+            print("| counter | per launch |\n|---|---|")
+            for cn in sorted(sel):
+                print(f"| {cn} | {avg(sel[cn]):,.0f} |")
+            if "SQ_WAVES" in sel:
+                waves = avg(sel["SQ_WAVES"])
+                for cn in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_LDS"):
+                    if cn in sel:
+                        print(f"| {cn} per wave | {avg(sel[cn]) / waves:,.1f} |")
+            if "SQ_WAVE_CYCLES" in sel and "SQ_WAIT_INST_ANY" in sel:
+                print(f"| waiting share of wave cycles (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) | "
+                      f"{avg(sel['SQ_WAIT_INST_ANY']) / avg(sel['SQ_WAVE_CYCLES']):.2f} |")
+    print(f"\nKernel sources at measurement (sha256 of stp_kernels.h + stp_tiles.h + stp_pencil.h + stp_solver.h + "
+          f"stp.hip):\n{kernel_sources_sha256()}")
 
 
 def main():

@@ -108,26 +108,6 @@ long tiles_up_d(int dim, int n) {
   return dim == 1 ? tiles_for<1, UpTile<1>>(n) : dim == 2 ? tiles_for<2, UpTile<2>>(n) : tiles_for<3, UpTile<3>>(n);
 }
 
-LevelOp family_op(const Problem& q, int l, int fam) {
-  LevelOp L;
-  L.kap = q.lv[l].kscaled;
-  L.R = q.R;
-  L.S = q.N;
-  if (fam == 0) {          // A family: tau_n A_n (rank 1: the field times tau a_0[n])
-    L.sig = nullptr;
-    L.c = q.cA;
-    L.cmode = q.R == 1 ? CM_SCALE : CM_SLAB;
-  } else if (fam == 1) {   // H family: mu_k I + tau A_ref (the same coefficient for every k)
-    L.sig = q.sigH;
-    L.c = q.cH;
-    L.cmode = CM_UNIFORM;
-  } else {                 // middle: (2/N) tau A_ref
-    L.sig = nullptr;
-    L.c = q.cMid;
-    L.cmode = CM_UNIFORM;
-  }
-  return L;
-}
 
 // Plan (dry run) or carve (real run) one problem's buffers.
 void plan_problem(int prec, int spatial, Problem& q, Bump& bp, bool nux, bool fem) {
@@ -144,7 +124,7 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp, bool nux, bool fe
   q.state = (DevState*)bp.take(sizeof(DevState));
   // residual partials for any slabs-per-block choice (at most one slab per block)
   q.partial = (double*)bp.take(size_t(std::max(q.resid_tiles * q.N, q.nfnorm)) * 8);
-  q.nrm = (double*)bp.take(size_t(2) * kNormBlocks * 8);
+  q.nrm = (double*)bp.take(size_t(2) * std::max(long(kNormBlocks), norm_blocks_per_slab(q.g0.npts, q.N) * N) * 8);
   q.fbind = fem ? (FemBind*)bp.take(sizeof(FemBind)) : nullptr;
   q.kap64 = (double*)bp.take(size_t(q.R) * q.g0.nnodes * 8);
   q.cA64 = (double*)bp.take(size_t(N) * kMaxRank * 8);
@@ -188,6 +168,13 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp, bool nux, bool fe
     const bool fx = fem && spatial == STP_SPATIAL_MG && l + 1 < q.lv.size();
     L.fr = fx ? bp.take(vb) : nullptr;
     L.fr2 = fx ? bp.take(vb) : nullptr;
+    for (int fam = 0; fam < 2; ++fam) {
+      const bool pen = int(l) < q.fuse_top &&
+                       pencil_level(q.dim, spatial, fem, q.R, L.n, q.lv[l + 1].n, tsb, tcb, fam);
+      L.pen[fam] = pen;
+      L.pk[fam] = pen ? bp.take(size_t(L.g.npts) * tcb) : nullptr;
+      L.pd[fam] = pen ? bp.take(size_t(L.g.npts) * tcb) : nullptr;
+    }
   }
 }
 
@@ -295,9 +282,12 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top,
   int Lmax = 0;
   for (auto& q : c->pr) Lmax = std::max(Lmax, int(q.lv.size()));
   vc.down.assign(std::max(0, Lmax - 1), Site<TileJob>());
+  vc.downp.assign(std::max(0, Lmax - 1), Site<TileJob>());
+  vc.upp.assign(std::max(0, Lmax - 1), Site<TileJob>());
   vc.up.assign(std::max(0, Lmax - 1), Site<TileJob>());
   vc.fused.assign(Lmax, Site<FuseJob>());
   vc.tri = Site<PointJob>();
+  const int pty = c->prec == STP_PREC_F64 ? PencilTY<double>::v : PencilTY<float>::v;
   for (size_t i = 0; i < c->pr.size(); ++i) {
     Problem& q = c->pr[i];
     const VTop& T = top[i];
@@ -326,9 +316,17 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top,
       d.b = (l == 0) ? T.in : q.lv[l].b;
       d.out = q.lv[l + 1].b;
       d.state = &q.state->done;
-      d.tiles = int(tiles_down_d(q.dim, q.lv[l + 1].n));
-      d.sb = sched_sb(d.tiles, q.N, c->sched.e[KN_DOWN0 + l]);
-      vc.down[l].add(d, long(d.tiles) * ((q.N + d.sb - 1) / d.sb), d.op.cmode != CM_SLAB);
+      if (q.lv[l].pen[fam]) {   // register pencils: a launch of their own, so a job's arithmetic
+        d.tiles = int(pencil_tiles(q.lv[l + 1].n, pty));   // never depends on its batch
+        d.sb = kPencilWaves;
+        d.pk = q.lv[l].pk[fam];
+        d.pd = q.lv[l].pd[fam];
+        vc.downp[l].add(d, long(d.tiles) * ((q.N + d.sb - 1) / d.sb), true);
+      } else {
+        d.tiles = int(tiles_down_d(q.dim, q.lv[l + 1].n));
+        d.sb = sched_sb(d.tiles, q.N, c->sched.e[KN_DOWN0 + l]);
+        vc.down[l].add(d, long(d.tiles) * ((q.N + d.sb - 1) / d.sb), d.op.cmode != CM_SLAB);
+      }
       TileJob u{};
       u.gf = q.lv[l].g;
       u.gc = q.lv[l + 1].g;
@@ -339,10 +337,21 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top,
       u.acc64 = (l == 0) ? T.acc64 : nullptr;
       u.addout = (l == 0 && addout) ? 1 : 0;
       u.state = d.state;
-      u.tiles = int(tiles_up_d(q.dim, q.lv[l].n));
-      u.sb = sched_sb(u.tiles, q.N, (l == 0 && acc) ? c->sched.e[KN_UPA0] : c->sched.e[KN_UP0 + l]);
-      vc.up[l].add(u, long(u.tiles) * ((q.N + u.sb - 1) / u.sb), u.op.cmode != CM_SLAB);
-      vc.up[l].epi = (l == 0 && acc) ? EPI_ADD64 : EPI_STORE;
+      // float64 keeps the tiled up-sweep: its register pencil needs 270 VGPRs (one
+      // wave per SIMD) and measured slower (11.8 vs 10.4 ms on 255^3 x 64)
+      if (q.lv[l].pen[fam] && c->prec != STP_PREC_F64) {
+        u.tiles = int(pencil_tiles(q.lv[l + 1].n, pty));
+        u.sb = kPencilWaves;
+        u.pk = q.lv[l].pk[fam];
+        u.pd = q.lv[l].pd[fam];
+        vc.upp[l].add(u, long(u.tiles) * ((q.N + u.sb - 1) / u.sb), true);
+        vc.upp[l].epi = (l == 0 && acc) ? EPI_ADD64 : EPI_STORE;
+      } else {
+        u.tiles = int(tiles_up_d(q.dim, q.lv[l].n));
+        u.sb = sched_sb(u.tiles, q.N, (l == 0 && acc) ? c->sched.e[KN_UPA0] : c->sched.e[KN_UP0 + l]);
+        vc.up[l].add(u, long(u.tiles) * ((q.N + u.sb - 1) / u.sb), u.op.cmode != CM_SLAB);
+        vc.up[l].epi = (l == 0 && acc) ? EPI_ADD64 : EPI_STORE;
+      }
     }
     FuseJob fj{};
     fj.S = q.N;
@@ -560,6 +569,8 @@ void for_each_site(Sites& S, F&& f) {
   f(S.resid[1]);
   for (auto& v : S.vc) {
     for (auto& x : v.down) f(x);
+    for (auto& x : v.downp) f(x);
+    for (auto& x : v.upp) f(x);
     for (auto& x : v.up) f(x);
     for (auto& x : v.fused) f(x);
     f(v.tri);
@@ -644,6 +655,8 @@ stp_status bind_jobs(stp_ctx* c, const std::vector<double*>& u, const std::vecto
   VCycle& A = S.vc[VC_A];
   if (!A.up.empty())
     for (auto& j : A.up[0].jobs) j.acc64 = acc_p[owner(j.state)];
+  if (!A.upp.empty())
+    for (auto& j : A.upp[0].jobs) j.acc64 = acc_p[owner(j.state)];
   if (!A.fused.empty())
     for (auto& j : A.fused[0].jobs) j.acc64 = acc_p[owner(j.state)];
   for (auto& j : A.tri.jobs) j.acc64 = acc_p[owner(j.state)];
@@ -664,6 +677,7 @@ stp_status bind_jobs(stp_ctx* c, const std::vector<double*>& u, const std::vecto
   if ((st = upload_site(c, S.resid[0])) != STP_OK) return st;
   if ((st = upload_site(c, S.resid[1])) != STP_OK) return st;
   if (!A.up.empty() && (st = upload_site(c, A.up[0])) != STP_OK) return st;
+  if (!A.upp.empty() && (st = upload_site(c, A.upp[0])) != STP_OK) return st;
   if (!A.fused.empty() && (st = upload_site(c, A.fused[0])) != STP_OK) return st;
   if ((st = upload_site(c, A.tri)) != STP_OK) return st;
   if ((st = upload_site(c, S.nu[0])) != STP_OK) return st;
@@ -1206,6 +1220,7 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
   std::vector<double*> nul(P, nullptr);
   build_sites(c.get(), nul, nul);
   if (!sites_fit(c.get())) return fail(STP_EUNSUPPORTED, "a launch exceeds the dispatch size limit");
+  if (tables_bytes(c->sites) > c->tables_bytes) return fail(STP_EDEVICE, "launch tables outgrew their reservation");
   carve_tables(c->sites, (char*)c->ws + c->tables_off);
   if ((s = upload_all(c.get())) != STP_OK) return s;
   if (c->spatial != STP_SPATIAL_NONE) {
@@ -1214,6 +1229,7 @@ stp_status stp_create_batch(stp_ctx** out, int P, const stp_grid* grids, const i
     if (!(opt.omega > 0))   // estimated: the time it took (a given omega costs nothing)
       c->t_omega_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - te).count();
     build_sites(c.get(), nul, nul);   // f from F and u0 again; omega into the transform jobs
+    if (tables_bytes(c->sites) > c->tables_bytes) return fail(STP_EDEVICE, "launch tables outgrew their reservation");
     carve_tables(c->sites, (char*)c->ws + c->tables_off);
     if ((s = upload_all(c.get())) != STP_OK) return s;
   }
@@ -1412,13 +1428,16 @@ stp_status pair_norms(stp_ctx* c, int i, const double* u, const double* p) {
     LAUNCH_CHECK();
     return STP_OK;
   }
+  const long G = norm_blocks_per_slab(q.g0.npts, q.N), cnt = G * q.N;
+  dim3 gr = grid_pts(1, q.N);
+  gr.x = unsigned(G);
   switch (c->dim) {
-    case 1: KLAUNCH(k_saddle_norms<1>, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm); break;
-    case 2: KLAUNCH(k_saddle_norms<2>, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm); break;
-    default: KLAUNCH(k_saddle_norms<3>, dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm);
+    case 1: KLAUNCH(k_saddle_norms<1>, gr, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm, cnt); break;
+    case 2: KLAUNCH(k_saddle_norms<2>, gr, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm, cnt); break;
+    default: KLAUNCH(k_saddle_norms<3>, gr, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm, cnt);
   }
   LAUNCH_CHECK();
-  KLAUNCH(k_sum_rows, dim3(2), dim3(kBlock), 0, c->stream, (const double*)q.nrm, nb, &q.state->rp2);
+  KLAUNCH(k_sum_rows, dim3(2), dim3(kBlock), 0, c->stream, (const double*)q.nrm, cnt, &q.state->rp2);
   LAUNCH_CHECK();
   return STP_OK;
 }
@@ -1932,13 +1951,23 @@ std::vector<int> knob_sbs(stp_ctx* c, int k, int e) {
     }
     if (k == KN_R0 || k == KN_R1) tiles = q.resid_tiles;
     else if (k == KN_MID) tiles = tiles_up_d(q.dim, q.n);
-    else if (k == KN_UPA0) tiles = (mg && q.fuse_top > 0) ? tiles_up_d(q.dim, q.n) : -1;
+    else if (k == KN_UPA0) {
+      tiles = (mg && q.fuse_top > 0) ? tiles_up_d(q.dim, q.n) : -1;
+      const VCycle& v = c->sites.vc[VC_A];   // register-pencil sites have a fixed shape
+      if (v.up.empty() || v.up[0].jobs.empty()) tiles = -1;
+    }
     else if (k < KN_UP0) {
       const int l = k - KN_DOWN0;
       tiles = (mg && l < q.fuse_top) ? tiles_down_d(q.dim, q.lv[l + 1].n) : -1;
+      // the knob sets the slabs per block of the tiled down-sweeps of level l;
+      // register-pencil sites have a fixed shape
+      auto tiled = [&](const VCycle& v) { return size_t(l) < v.down.size() && !v.down[l].jobs.empty(); };
+      if (!tiled(c->sites.vc[VC_A]) && !tiled(c->sites.vc[VC_H1])) tiles = -1;
     } else {
       const int l = k - KN_UP0;
       tiles = (mg && l < q.fuse_top) ? tiles_up_d(q.dim, q.lv[l].n) : -1;
+      auto tiled = [&](const VCycle& v) { return size_t(l) < v.up.size() && !v.up[l].jobs.empty(); };
+      if (!tiled(c->sites.vc[VC_A]) && !tiled(c->sites.vc[VC_H1])) tiles = -1;
     }
     if (tiles > 0) v.push_back(sched_sb(tiles, q.N, e));
   }

@@ -22,6 +22,7 @@
 #include "stp_fem.h"
 #include "stp_kernels.h"
 #include "stp_tiles.h"
+#include "stp_pencil.h"
 
 struct stp_ctx;
 
@@ -70,7 +71,25 @@ struct Level {
   void* kscaled;   // TC fields scaled by 0.5/h^2
   void* b;         // TS right-hand side of the level (levels >= 1)
   void* e;         // TS correction produced on the level (levels >= 1)
+  // register-pencil down-sweep fields of the A (0) and H (1) families: the fixed
+  // field and its face sums at the interior nodes (TC), or null
+  bool pen[2] = {false, false};   // set in the planning dry run too (null pk, pd there)
+  void* pk[2] = {nullptr, nullptr};
+  void* pd[2] = {nullptr, nullptr};
 };
+
+// 3-D multigrid levels l whose down-sweep runs as register pencils: the
+// level's family-fam operator is a fixed field times a slab scalar (always for
+// the H family, for the A family when the coefficient has rank 1), the coarse
+// level is wide enough to fill the pencils' lanes, and a slab of the fine level
+// addresses below 2 GiB (32-bit buffer offsets).
+inline bool pencil_level(int dim, int spatial, bool fem, int R, int nf, int nc, size_t tsb, size_t tcb, int fam) {
+  if (dim != 3 || spatial != STP_SPATIAL_MG || fem) return false;
+  if (fam == 0 && R != 1) return false;
+  if (nc < kPencilMinNc) return false;
+  const double bytes = double(nf) * nf * nf * double(std::max(tsb, tcb));
+  return bytes < double(1u << 31) - 65536.0;
+}
 
 struct Bump {
   char* base = nullptr;
@@ -102,7 +121,13 @@ inline dim3 grid_pts(long npts, int S) {
 
 enum { TP_FFT2 = 0, TP_STOCKHAM = 1, TP_DENSE = 2, TP_BLUESTEIN = 3, TP_FOUR = 4 };
 
-constexpr int kNormBlocks = 1024;     // blocks of the residual-norm pass after a solve
+constexpr int kNormBlocks = 1024;     // blocks of the finite-element residual-norm pass after a solve
+constexpr long kNormPartials = 65536;  // partials of the finite-difference norm pass: G blocks per slab, G N <= max(this, N)
+
+// blocks per slab of the finite-difference norm pass of N slabs of npts points
+inline long norm_blocks_per_slab(long npts, int N) {
+  return std::max(1L, std::min((npts + kBlock - 1) / kBlock, kNormPartials / std::max(N, 1)));
+}
 constexpr int kBlueKey = 1 << 20;        // site key of a Bluestein group: kBlueKey + M
 constexpr int kBlueMaxN = 2048;          // Bluestein for step counts up to this (M <= 4096)
 constexpr size_t kMaxLds = 160 * 1024;   // LDS of one compute unit
@@ -234,7 +259,7 @@ struct Problem {
   // device memory
   DevState* state = nullptr;
   double* partial = nullptr;
-  double* nrm = nullptr;        // 2 x kNormBlocks partials of the returned pair's residual norms
+  double* nrm = nullptr;        // partials of the returned pair's residual norms (two rows)
   double* kap64 = nullptr;      // finest-level scaled fields, float64
   double* cA64 = nullptr;       // N x kMaxRank: tau_n * tcoef
   double* taus64 = nullptr;     // N step lengths
@@ -259,6 +284,28 @@ struct Problem {
   std::vector<FemLevelW> fw;
   FemBind* fbind = nullptr;
 };
+
+// operator family of the V-cycles: 0 A-tilde (tau_n A_n), 1 the H-blocks, 2 the middle operator
+inline LevelOp family_op(const Problem& q, int l, int fam) {
+  LevelOp L;
+  L.kap = q.lv[l].kscaled;
+  L.R = q.R;
+  L.S = q.N;
+  if (fam == 0) {          // A family: tau_n A_n (rank 1: the field times tau a_0[n])
+    L.sig = nullptr;
+    L.c = q.cA;
+    L.cmode = q.R == 1 ? CM_SCALE : CM_SLAB;
+  } else if (fam == 1) {   // H family: mu_k I + tau A_ref (the same coefficient for every k)
+    L.sig = q.sigH;
+    L.c = q.cH;
+    L.cmode = CM_UNIFORM;
+  } else {                 // middle: (2/N) tau A_ref
+    L.sig = nullptr;
+    L.c = q.cMid;
+    L.cmode = CM_UNIFORM;
+  }
+  return L;
+}
 
 template <typename J>
 struct Site {
@@ -286,6 +333,7 @@ struct Site {
 
 struct VCycle {
   std::vector<Site<TileJob>> down, up;   // by level l = 0 .. Lmax-2
+  std::vector<Site<TileJob>> downp, upp;   // sweeps of the jobs with register-pencil fields, by level
   std::vector<Site<FuseJob>> fused;      // by fused top level index 0 .. Lmax-1
   Site<PointJob> tri;                    // exact 1-D solves
 };

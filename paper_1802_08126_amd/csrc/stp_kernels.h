@@ -422,6 +422,8 @@ struct TileJob {        // multigrid level kernels and the tile operator
   double* acc64;        // float64 target of EPI_ADD64
   const int* state;     // the problem's stop flag
   int addout;           // top-level output: 0 store, 1 add into out (up-sweep), -1 subtract from out (operator)
+  const void* pk;       // register-pencil down-sweep: fixed field and its face sums at the fine
+  const void* pd;       // level's interior nodes (TC), or null
 };
 
 struct PointJob {       // exact 1-D solves
@@ -482,6 +484,8 @@ __device__ __forceinline__ TileJob to_global(TileJob j) {
   j.out = gmem(j.out);
   j.acc64 = gmem(j.acc64);
   j.state = gmem(j.state);
+  j.pk = gmem(j.pk);
+  j.pd = gmem(j.pd);
   return j;
 }
 __device__ __forceinline__ PointJob to_global(PointJob j) {
@@ -1400,22 +1404,24 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(Geom g, TimeOp t, const
 
 // block partials of ||r_p||^2 and ||r_u||^2 of a pair (p, u), eq. (3.1):
 // r_p = K u - A p - f and r_u = f - K^T p - (K + K^T + A) u, the two blocks of
-// the saddle residual g - saddle [p; u] up to sign.  A fixed grid of G blocks
-// strides over the points; each thread walks all slabs of its points (for a
-// fixed slab the threads of a block read consecutive points).  Block b writes
-// partial[b] (r_p) and partial[G + b] (r_u).
+// the saddle residual g - saddle [p; u] up to sign.  Block (b, s) strides over the points
+// of slab s with gridDim.x blocks per slab, so a slab's stencil neighbours are
+// read while they sit in L2; it writes partial[s G + b] (r_p) and
+// partial[count + s G + b] (r_u), G = gridDim.x, count = G N.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_saddle_norms(Geom g, TimeOp t, const double* __restrict__ taus,
                                                          const double* __restrict__ F,
                                                          const double* __restrict__ u0, const double* __restrict__ p,
-                                                         const double* __restrict__ u, double* __restrict__ partial) {
+                                                         const double* __restrict__ u, double* __restrict__ partial,
+                                                         long count) {
+  const int s = slab_index();
   double vp = 0.0, vu = 0.0;
-  for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < g.npts; i += long(gridDim.x) * kBlock) {
-    int px, py, pz;
-    decode<D>(i, g.n, px, py, pz);
-    for (int s = 0; s < t.N; ++s) {
-      const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
-      const long o = long(s) * g.npts;
+  if (s < t.N) {
+    const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
+    const long o = long(s) * g.npts;
+    for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < g.npts; i += long(gridDim.x) * kBlock) {
+      int px, py, pz;
+      decode<D>(i, g.n, px, py, pz);
       double dg, offp, offu;
       stencil2<D>(p + o, u + o, i, px, py, pz, g, t.kap, op, t.R, dg, offp, offu);
       const double pc = p[o + i];
@@ -1432,10 +1438,11 @@ __global__ void __launch_bounds__(kBlock) k_saddle_norms(Geom g, TimeOp t, const
     }
   }
   const double sp = block_sum(vp);
-  if (threadIdx.x == 0) partial[blockIdx.x] = sp;
+  const long b = long(s) * gridDim.x + blockIdx.x;
+  if (threadIdx.x == 0 && s < t.N) partial[b] = sp;
   __syncthreads();   // block_sum's LDS slots are reused
   const double su = block_sum(vu);
-  if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = su;
+  if (threadIdx.x == 0 && s < t.N) partial[count + b] = su;
 }
 
 // block partials of ||f - B u||^2 over a (points, slabs) grid

@@ -197,10 +197,13 @@ struct Solver : SolverBase {
       if ((st = fused_site<D, RM>(vc.fused[0], 0)) != STP_OK) return st;
     for (int l = 0; l < nl; ++l) {
       if ((st = down_site<D, RM>(vc.down[l], l)) != STP_OK) return st;
+      if ((st = downp_site(vc.downp[l], l)) != STP_OK) return st;
       if ((st = fused_site<D, RM>(vc.fused[l + 1], l + 1)) != STP_OK) return st;
     }
-    for (int l = nl - 1; l >= 0; --l)
+    for (int l = nl - 1; l >= 0; --l) {
       if ((st = up_site<D, RM>(vc.up[l], l)) != STP_OK) return st;
+      if ((st = upp_site(vc.upp[l], l)) != STP_OK) return st;
+    }
     return STP_OK;
   }
 
@@ -215,6 +218,33 @@ struct Solver : SolverBase {
       case 2: KLAUNCH_NAMED("k_mg_down", (k_mg_down<D, TS, TC, RM, 2>), gr, bl, 0, c->stream, s.dev, nj, omegaJ()); break;
       default: KLAUNCH_NAMED("k_mg_down", (k_mg_down<D, TS, TC, RM, 0>), gr, bl, 0, c->stream, s.dev, nj, omegaJ());
     }
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
+  // register-pencil down-sweeps of level l (3-D fixed-field jobs)
+  stp_status downp_site(Site<TileJob>& s, int l) {
+    if (s.jobs.empty()) return STP_OK;
+    c->kt.level = l;
+    KLAUNCH_NAMED("k_mg_down_p3", (k_mg_down_p3<TS, TC, PencilTY<TC>::v>), dim3(unsigned(s.blocks)),
+                  dim3(kPencilThreads), 0,
+                  c->stream, s.dev, int(s.jobs.size()), omegaJ());
+    LAUNCH_CHECK();
+    return STP_OK;
+  }
+
+  // register-pencil up-sweeps of level l
+  stp_status upp_site(Site<TileJob>& s, int l) {
+    if (s.jobs.empty()) return STP_OK;
+    c->kt.level = l;
+    const dim3 gr(unsigned(s.blocks)), bl(kPencilThreads);
+    const int nj = int(s.jobs.size());
+    if (s.epi == EPI_ADD64)
+      KLAUNCH_NAMED("k_mg_up_p3<add64>", (k_mg_up_p3<TS, TC, PencilTY<TC>::v, EPI_ADD64>), gr, bl, 0, c->stream, s.dev,
+                    nj, omegaJ());
+    else
+      KLAUNCH_NAMED("k_mg_up_p3<store>", (k_mg_up_p3<TS, TC, PencilTY<TC>::v, EPI_STORE>), gr, bl, 0, c->stream,
+                    s.dev, nj, omegaJ());
     LAUNCH_CHECK();
     return STP_OK;
   }
@@ -735,6 +765,16 @@ struct Solver : SolverBase {
         LAUNCH_CHECK();
       }
     }
+    // fixed fields and face sums of the register-pencil down-sweeps
+    for (size_t l = 0; l < q.lv.size(); ++l)
+      for (int fam = 0; fam < 2; ++fam) {
+        Level& L = q.lv[l];
+        if (!L.pen[fam]) continue;
+        const long nb = std::min(4096L, (L.g.npts + kBlock - 1) / kBlock);
+        KLAUNCH((k_pencil_fields<TC>), dim3(unsigned(nb)), dim3(kBlock), 0, c->stream, L.g,
+                family_op(q, int(l), fam), (TC*)L.pk[fam], (TC*)L.pd[fam]);
+        LAUNCH_CHECK();
+      }
     return STP_OK;
   }
 };
