@@ -1429,12 +1429,12 @@ stp_status pair_norms(stp_ctx* c, int i, const double* u, const double* p) {
     return STP_OK;
   }
   const long G = norm_blocks_per_slab(q.g0.npts, q.N), cnt = G * q.N;
-  dim3 gr = grid_pts(1, q.N);
-  gr.x = unsigned(G);
+  const dim3 gr(static_cast<unsigned>(cnt));
+  const int Gi = int(G);
   switch (c->dim) {
-    case 1: KLAUNCH(k_saddle_norms<1>, gr, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm, cnt); break;
-    case 2: KLAUNCH(k_saddle_norms<2>, gr, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm, cnt); break;
-    default: KLAUNCH(k_saddle_norms<3>, gr, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm, cnt);
+    case 1: KLAUNCH(k_saddle_norms<1>, gr, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm, cnt, Gi); break;
+    case 2: KLAUNCH(k_saddle_norms<2>, gr, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm, cnt, Gi); break;
+    default: KLAUNCH(k_saddle_norms<3>, gr, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm, cnt, Gi);
   }
   LAUNCH_CHECK();
   KLAUNCH(k_sum_rows, dim3(2), dim3(kBlock), 0, c->stream, (const double*)q.nrm, cnt, &q.state->rp2);

@@ -1404,22 +1404,27 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(Geom g, TimeOp t, const
 
 // block partials of ||r_p||^2 and ||r_u||^2 of a pair (p, u), eq. (3.1):
 // r_p = K u - A p - f and r_u = f - K^T p - (K + K^T + A) u, the two blocks of
-// the saddle residual g - saddle [p; u] up to sign.  Block (b, s) strides over the points
-// of slab s with gridDim.x blocks per slab, so a slab's stencil neighbours are
-// read while they sit in L2; it writes partial[s G + b] (r_p) and
-// partial[count + s G + b] (r_u), G = gridDim.x, count = G N.
+// the saddle residual g - saddle [p; u] up to sign.  Logical block b (the
+// XCD-contiguous block_id of a 1-D grid of G N blocks) takes slab s = b / G and
+// the b % G-th contiguous chunk of its points, so the blocks of one L2 walk
+// consecutive planes of one slab and a stencil's z-neighbours are read while
+// they sit in that L2; it writes partial[b] (r_p) and partial[count + b] (r_u),
+// count = G N.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_saddle_norms(Geom g, TimeOp t, const double* __restrict__ taus,
                                                          const double* __restrict__ F,
                                                          const double* __restrict__ u0, const double* __restrict__ p,
                                                          const double* __restrict__ u, double* __restrict__ partial,
-                                                         long count) {
-  const int s = slab_index();
+                                                         long count, int G) {
+  const long b = block_id();
+  const int s = int(b / G), bx = int(b % G);
   double vp = 0.0, vu = 0.0;
-  if (s < t.N) {
+  {
     const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
     const long o = long(s) * g.npts;
-    for (long i = long(blockIdx.x) * kBlock + threadIdx.x; i < g.npts; i += long(gridDim.x) * kBlock) {
+    const long chunk = (g.npts + long(G) * kBlock - 1) / (long(G) * kBlock) * kBlock;
+    const long i1 = min(g.npts, (long(bx) + 1) * chunk);
+    for (long i = long(bx) * chunk + threadIdx.x; i < i1; i += kBlock) {
       int px, py, pz;
       decode<D>(i, g.n, px, py, pz);
       double dg, offp, offu;
@@ -1438,11 +1443,10 @@ __global__ void __launch_bounds__(kBlock) k_saddle_norms(Geom g, TimeOp t, const
     }
   }
   const double sp = block_sum(vp);
-  const long b = long(s) * gridDim.x + blockIdx.x;
-  if (threadIdx.x == 0 && s < t.N) partial[b] = sp;
+  if (threadIdx.x == 0) partial[b] = sp;
   __syncthreads();   // block_sum's LDS slots are reused
   const double su = block_sum(vu);
-  if (threadIdx.x == 0 && s < t.N) partial[count + b] = su;
+  if (threadIdx.x == 0) partial[count + b] = su;
 }
 
 // block partials of ||f - B u||^2 over a (points, slabs) grid

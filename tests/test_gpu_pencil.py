@@ -74,9 +74,13 @@ def test_pencil_precond_matches_oracle(n, N, R, which, prec):
     s.close()
 
 
-def test_pencil_uzawa_iterates_match_oracle():
+@pytest.mark.parametrize("n,N", [(63, 5), (31, 3), (127, 2)])
+def test_pencil_uzawa_iterates_match_oracle(n, N):
+    """Rank 1: both operator families on pencils (63^3: level 0; 127^3: levels
+    0 and 1; 31^3 stays on the LDS tiles); the iterates and the stop test's
+    residual match the oracle's."""
     import paper_1802_08126_amd as stp
-    prob = synth.small_problem(3, 63, 5, seed=91, R=1)
+    prob = synth.small_problem(3, n, N, seed=91 + n, R=1)
     iters = 3
     s = stp.from_problem(prob, omega=0.7, tol=0.0, max_iter=iters)
     u, p, info = s.solve()
@@ -84,6 +88,8 @@ def test_pencil_uzawa_iterates_match_oracle():
     ref = uzawa.uzawa_fixed(prob, iters, omega=0.7, spatial="mg")
     assert relmax(host(u), ref["u"]) < 1e-11
     assert relmax(host(p), ref["p"]) < 1e-11
+    # the residual of the last evaluated iterate: ||f - B u_3|| / ||f||
+    assert abs(info["rel_res"] - ref["history"][iters]) <= 1e-10 * ref["history"][iters]
     s.close()
 
 
