@@ -53,7 +53,23 @@ METRIC = "space-time DoF-iterations/sec + time to 1e-8 residual, mixed vs FP64, 
 # HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by
 # the same counters on a plain copy) for (workload, dtype, kernel, level); used only
 # while the kernel sources hash to the recorded value (see the named profile).
-MEASURED_TRAFFIC = {}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled by the copy
+# calibration), valid while the kernel sources hash to the recorded value
+_SRC_SHA = "92963d9de275356222a2ac86e0a3acd3b737b69a5d168ab65bdeb636cb61624f"
+MEASURED_TRAFFIC = {
+    ("heat3d_255_N64_lognormal", "f32", "k_resid_tile<a3>", 0): dict(
+        bytes=40_540_202_475, sources_sha256=_SRC_SHA,
+        profile="profiles/heat3d_255_N64_lognormal_f32_resid_tile_a3.md"),
+    ("heat3d_255_N64_lognormal", "f32", "k_mg_down_p3", 0): dict(
+        bytes=8_019_399_923, sources_sha256=_SRC_SHA,
+        profile="profiles/heat3d_255_N64_lognormal_f32_mg_down_p3_L0.md"),
+    ("heat3d_255_N64_lognormal", "f32", "k_mg_up_p3<store>", 0): dict(
+        bytes=13_065_061_368, sources_sha256=_SRC_SHA,
+        profile="profiles/heat3d_255_N64_lognormal_f32_mg_up_p3_store_L0.md"),
+    ("heat3d_255_N64_lognormal", "f32", "k_mg_up_p3<add64>", 0): dict(
+        bytes=27_016_559_463, sources_sha256=_SRC_SHA,
+        profile="profiles/heat3d_255_N64_lognormal_f32_mg_up_p3_add64_L0.md"),
+}
 
 
 def kernel_sources_sha256() -> str:

@@ -318,7 +318,7 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top,
       d.state = &q.state->done;
       if (q.lv[l].pen[fam]) {   // register pencils: a launch of their own, so a job's arithmetic
         d.tiles = int(pencil_tiles(q.lv[l + 1].n, pty));   // never depends on its batch
-        d.sb = kPencilWaves;
+        d.sb = kPencilSlabs;
         d.pk = q.lv[l].pk[fam];
         d.pd = q.lv[l].pd[fam];
         vc.downp[l].add(d, long(d.tiles) * ((q.N + d.sb - 1) / d.sb), true);
@@ -341,7 +341,7 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top,
       // wave per SIMD) and measured slower (11.8 vs 10.4 ms on 255^3 x 64)
       if (q.lv[l].pen[fam] && c->prec != STP_PREC_F64) {
         u.tiles = int(pencil_tiles(q.lv[l + 1].n, pty));
-        u.sb = kPencilWaves;
+        u.sb = kPencilSlabs;
         u.pk = q.lv[l].pk[fam];
         u.pd = q.lv[l].pd[fam];
         vc.upp[l].add(u, long(u.tiles) * ((q.N + u.sb - 1) / u.sb), true);

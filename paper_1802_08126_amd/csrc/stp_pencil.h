@@ -33,12 +33,17 @@
 namespace stp {
 
 constexpr int kPencilWaves = 4;     // waves (slabs) per block
+constexpr int kPencilPasses = 1;    // slabs each wave marches in turn
+constexpr int kPencilSlabs = kPencilWaves * kPencilPasses;   // slabs per block
 constexpr int kPencilThreads = 64 * kPencilWaves;
 // Block order: consecutive blocks take consecutive pencils of one slab group
-// (true: the slab groups of one pencil); measured 12 % faster on 255^3 x 64,
-// as y-neighbouring pencils of a slab share their halo rows in L2.
+// (true: the slab groups of one pencil), x-segments fastest, then y-tiles, so
+// the pencils next to each other in x and y, which share halo lines and rows,
+// run at the same time on one L2.  On 255^3 x 64 (float32, level 0) this order
+// took the down-sweep from 2.70 ms (slab groups fastest) to 2.38 (y fastest)
+// and 2.22 ms; two or more passes of slabs per wave were slower.
 constexpr bool kPencilGroupFastest = false;
-constexpr bool kPencilXFastest = false;   // pencil order: x-segments fastest (else y-tiles)
+constexpr bool kPencilXFastest = true;
 constexpr int kPencilCX = 30;       // coarse nodes per wave along x (2 * 30 + 3 lanes used)
 constexpr int kPencilTZ = 16;       // coarse planes per wave
 constexpr int kPencilMinNc = 24;    // coarser levels keep the tiled kernel (lanes would idle)
@@ -134,14 +139,14 @@ struct PencilPos {
 };
 
 template <int TY>
-__device__ __forceinline__ bool pencil_pos(const TileJob& J, PencilPos& P) {
+__device__ __forceinline__ bool pencil_pos(const TileJob& J, int pass, PencilPos& P) {
   const int S = J.op.S;
-  const int ng = (S + kPencilWaves - 1) / kPencilWaves;
+  const int ng = (S + kPencilSlabs - 1) / kPencilSlabs;
   const int lb = int(block_id() - J.block0);
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   P.lane = int(threadIdx.x) & 63;
   const int grp = kPencilGroupFastest ? lb % ng : lb / J.tiles;
-  P.s = grp * kPencilWaves + wave;
+  P.s = grp * kPencilSlabs + pass * kPencilWaves + wave;
   if (P.s >= S) return false;
   if (J.state && done_flag(J.state)) return false;
   const int nc = J.gc.n;
@@ -172,13 +177,10 @@ __device__ __forceinline__ bool pencil_pos(const TileJob& J, PencilPos& P) {
 // weighting; one wave per (pencil, slab).  Fine row t of a lane is node y =
 // 2 J0 - 2 + t (t = 0 .. 2 TY + 2), plane p is z = 2 K0 - 2 + p.
 template <typename TS, typename TC, int TY>
-__global__ void __launch_bounds__(kPencilThreads) k_mg_down_p3(const TileJob* __restrict__ jobs, int njobs, TC omega) {
+__device__ __forceinline__ void mg_down_pencil(const TileJob& J, const PencilPos& P, TC omega) {
   constexpr int NR = 2 * TY + 3;   // rows of x1, b, k and d
   constexpr int RR = 2 * TY + 1;   // rows of r (t = 1 .. RR)
-  const TileJob J = to_global(jobs[find_job(jobs, njobs)]);
   const LevelOp L = J.op;
-  PencilPos P;
-  if (!pencil_pos<TY>(J, P)) return;
   const int s = P.s, lane = P.lane, I0 = P.I0, CX = P.CX, J0 = P.J0, Jc = P.Jc, K0 = P.K0, Kc = P.Kc;
   const int nf = J.gf.n, nc = J.gc.n;
   const int x = 2 * I0 - 2 + lane;
@@ -319,6 +321,16 @@ __global__ void __launch_bounds__(kPencilThreads) k_mg_down_p3(const TileJob* __
   }
 }
 
+template <typename TS, typename TC, int TY>
+__global__ void __launch_bounds__(kPencilThreads) k_mg_down_p3(const TileJob* __restrict__ jobs, int njobs, TC omega) {
+  const TileJob J = to_global(jobs[find_job(jobs, njobs)]);
+  for (int pass = 0; pass < kPencilPasses; ++pass) {
+    PencilPos P;
+    if (!pencil_pos<TY>(J, pass, P)) return;
+    mg_down_pencil<TS, TC, TY>(J, P, omega);
+  }
+}
+
 // x2 = omega D^{-1} b + P e and x = (1 - omega) x2 + omega D^{-1} (b + gamma
 // sum_nb w x2_nb) on the fine level (P: multilinear prolongation of the
 // coarse correction e), one wave per (pencil, slab) as in the down-sweep.  A
@@ -327,14 +339,11 @@ __global__ void __launch_bounds__(kPencilThreads) k_mg_down_p3(const TileJob* __
 // store x (J.addout: add it into the output) or add it into the float64 acc64.
 // The arithmetic per fine node is that of the tiled kernel.
 template <typename TS, typename TC, int TY, int EPI>
-__global__ void __launch_bounds__(kPencilThreads) k_mg_up_p3(const TileJob* __restrict__ jobs, int njobs, TC omega) {
+__device__ __forceinline__ void mg_up_pencil(const TileJob& J, const PencilPos& P, TC omega) {
   constexpr int NR = 2 * TY + 3;   // fine rows t = 0 .. NR - 1 (node y = 2 J0 - 2 + t)
   constexpr int RR = 2 * TY + 1;   // rows that can be written (t = 1 .. RR)
   constexpr int NE = TY + 2;       // coarse rows J0 - 1 .. J0 + TY of e
-  const TileJob J = to_global(jobs[find_job(jobs, njobs)]);
   const LevelOp L = J.op;
-  PencilPos P;
-  if (!pencil_pos<TY>(J, P)) return;
   const int s = P.s, lane = P.lane, I0 = P.I0, CX = P.CX, J0 = P.J0, Jc = P.Jc, K0 = P.K0, Kc = P.Kc;
   const int nf = J.gf.n, nc = J.gc.n;
   const int x = 2 * I0 - 2 + lane;
@@ -538,6 +547,16 @@ __global__ void __launch_bounds__(kPencilThreads) k_mg_up_p3(const TileJob* __re
   for (int p0 = 1; p0 <= pend; p0 += 2) {
     if (!step(std::integral_constant<int, 0>{}, p0)) break;
     if (!step(std::integral_constant<int, 1>{}, p0)) break;
+  }
+}
+
+template <typename TS, typename TC, int TY, int EPI>
+__global__ void __launch_bounds__(kPencilThreads) k_mg_up_p3(const TileJob* __restrict__ jobs, int njobs, TC omega) {
+  const TileJob J = to_global(jobs[find_job(jobs, njobs)]);
+  for (int pass = 0; pass < kPencilPasses; ++pass) {
+    PencilPos P;
+    if (!pencil_pos<TY>(J, pass, P)) return;
+    mg_up_pencil<TS, TC, TY, EPI>(J, P, omega);
   }
 }
 
