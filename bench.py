@@ -134,7 +134,7 @@ def roofline(rep, dims, ts, workload, dtype):
     if not rep:
         return None, []
     rep = sorted(rep, key=lambda r: -r["total_ms"])
-    rep = [r for r in rep if not r["kernel"].startswith(("k_saddle_norms", "k_sum_rows"))]
+    rep = [r for r in rep if not r["kernel"].startswith(("k_pair_norms", "k_sum_rows"))]
     total = sum(r["total_ms"] for r in rep)
     top = rep[0]
     b = algorithmic_bytes(top["kernel"], top["level"], dims, ts)
@@ -143,13 +143,17 @@ def roofline(rep, dims, ts, workload, dtype):
     if b is None:
         return None, table
     achieved = b / (top["avg_ms"] * 1e-3) / 1e9
-    traffic, src = None, None
+    traffic, src, note = None, None, "no counter run recorded for this kernel and workload"
     m = MEASURED_TRAFFIC.get((workload, dtype, top["kernel"], top["level"]))
-    if m is not None and m["sources_sha256"] == kernel_sources_sha256():
-        traffic, src = m["bytes"], m["profile"]
+    if m is not None:
+        sha = kernel_sources_sha256()
+        if m["sources_sha256"] == sha:
+            traffic, src, note = m["bytes"], m["profile"], "FETCH_SIZE + WRITE_SIZE, copy-calibrated"
+        else:
+            note = f"kernel sources changed since the counters were taken (now {sha[:12]})"
     return dict(bound="hbm", kernel=top["kernel"], level=top["level"], achieved=achieved, peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic, traffic_unit="bytes per launch",
-                traffic_source=src, bytes_per_launch=b, avg_launch_us=1e3 * top["avg_ms"],
+                traffic_source=src, traffic_note=note, bytes_per_launch=b, avg_launch_us=1e3 * top["avg_ms"],
                 launches=top["launches"], target_frac=0.6, target_met=achieved / HBM_PEAK_GBS >= 0.6), table
 
 

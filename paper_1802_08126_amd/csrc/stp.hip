@@ -124,7 +124,10 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp, bool nux, bool fe
   q.state = (DevState*)bp.take(sizeof(DevState));
   // residual partials for any slabs-per-block choice (at most one slab per block)
   q.partial = (double*)bp.take(size_t(std::max(q.resid_tiles * q.N, q.nfnorm)) * 8);
-  q.nrm = (double*)bp.take(size_t(2) * std::max(long(kNormBlocks), norm_blocks_per_slab(q.g0.npts, q.N) * N) * 8);
+  // norm partials of a returned pair: one row each for r_p and r_u (FEM: one per
+  // block of its grid; else one per block of the residual tiles' default schedule)
+  q.nrm = (double*)bp.take(size_t(2) * std::max(long(kNormBlocks), q.resid_tiles * N) * 8);
+  q.njob = bp.take(sizeof(ResidJob));
   q.fbind = fem ? (FemBind*)bp.take(sizeof(FemBind)) : nullptr;
   q.kap64 = (double*)bp.take(size_t(q.R) * q.g0.nnodes * 8);
   q.cA64 = (double*)bp.take(size_t(N) * kMaxRank * 8);
@@ -1428,13 +1431,32 @@ stp_status pair_norms(stp_ctx* c, int i, const double* u, const double* p) {
     LAUNCH_CHECK();
     return STP_OK;
   }
-  const long G = norm_blocks_per_slab(q.g0.npts, q.N), cnt = G * q.N;
-  const dim3 gr(static_cast<unsigned>(cnt));
-  const int Gi = int(G);
-  switch (c->dim) {
-    case 1: KLAUNCH(k_saddle_norms<1>, gr, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm, cnt, Gi); break;
-    case 2: KLAUNCH(k_saddle_norms<2>, gr, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm, cnt, Gi); break;
-    default: KLAUNCH(k_saddle_norms<3>, gr, dim3(kBlock), 0, c->stream, q.g0, t, (const double*)q.taus64, q.F, q.u0, p, u, q.nrm, cnt, Gi);
+  // one job on the residual tiles (both operands staged per slab), slabs per
+  // block as the residual's default schedule
+  ResidJob j{};
+  j.tiles = int(q.resid_tiles);
+  j.sb = sched_sb(q.resid_tiles, q.N, 0);
+  j.g = q.g0;
+  j.t = t;
+  j.taus = q.taus64;
+  j.u = u;
+  j.p = p;
+  j.F = q.F;
+  j.u0 = q.u0;
+  j.partial = q.nrm;
+  const long cnt = q.resid_tiles * ((q.N + j.sb - 1) / j.sb);
+  HIP_TRY(hipMemcpyAsync(q.njob, &j, sizeof(ResidJob), hipMemcpyHostToDevice, c->stream));
+  const dim3 gr(static_cast<unsigned>(cnt)), bl(kBlock);
+  const bool fix = q.R == 1;
+  switch (c->dim * 10 + c->rm) {
+#define STP_PN(D, RM)                                                                                 \
+  case D * 10 + RM:                                                                                   \
+    if (fix) KLAUNCH((k_pair_norms<D, 1, 1>), gr, bl, 0, c->stream, (const ResidJob*)q.njob, 1);      \
+    else KLAUNCH((k_pair_norms<D, RM, 0>), gr, bl, 0, c->stream, (const ResidJob*)q.njob, 1);         \
+    break;
+    STP_PN(1, 1) STP_PN(1, 2) STP_PN(1, 4) STP_PN(2, 1) STP_PN(2, 2) STP_PN(2, 4) STP_PN(3, 1) STP_PN(3, 2)
+    default: STP_PN(3, 4)
+#undef STP_PN
   }
   LAUNCH_CHECK();
   KLAUNCH(k_sum_rows, dim3(2), dim3(kBlock), 0, c->stream, (const double*)q.nrm, cnt, &q.state->rp2);

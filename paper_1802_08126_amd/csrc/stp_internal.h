@@ -122,12 +122,6 @@ inline dim3 grid_pts(long npts, int S) {
 enum { TP_FFT2 = 0, TP_STOCKHAM = 1, TP_DENSE = 2, TP_BLUESTEIN = 3, TP_FOUR = 4 };
 
 constexpr int kNormBlocks = 1024;     // blocks of the finite-element residual-norm pass after a solve
-constexpr long kNormPartials = 65536;  // partials of the finite-difference norm pass: G blocks per slab, G N <= max(this, N)
-
-// blocks per slab of the finite-difference norm pass of N slabs of npts points
-inline long norm_blocks_per_slab(long npts, int N) {
-  return std::max(1L, std::min((npts + kBlock - 1) / kBlock, kNormPartials / std::max(N, 1)));
-}
 constexpr int kBlueKey = 1 << 20;        // site key of a Bluestein group: kBlueKey + M
 constexpr int kBlueMaxN = 2048;          // Bluestein for step counts up to this (M <= 4096)
 constexpr size_t kMaxLds = 160 * 1024;   // LDS of one compute unit
@@ -260,6 +254,7 @@ struct Problem {
   DevState* state = nullptr;
   double* partial = nullptr;
   double* nrm = nullptr;        // partials of the returned pair's residual norms (two rows)
+  void* njob = nullptr;         // device job of the residual-norm pass (ResidJob)
   double* kap64 = nullptr;      // finest-level scaled fields, float64
   double* cA64 = nullptr;       // N x kMaxRank: tau_n * tcoef
   double* taus64 = nullptr;     // N step lengths

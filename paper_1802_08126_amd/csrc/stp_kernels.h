@@ -1402,53 +1402,6 @@ __global__ void __launch_bounds__(kBlock) k_saddle_resid(Geom g, TimeOp t, const
   ru[o + i] = -f + (pc - pp) + (2.0 * uc - um - up) + Au;
 }
 
-// block partials of ||r_p||^2 and ||r_u||^2 of a pair (p, u), eq. (3.1):
-// r_p = K u - A p - f and r_u = f - K^T p - (K + K^T + A) u, the two blocks of
-// the saddle residual g - saddle [p; u] up to sign.  Logical block b (the
-// XCD-contiguous block_id of a 1-D grid of G N blocks) takes slab s = b / G and
-// the b % G-th contiguous chunk of its points, so the blocks of one L2 walk
-// consecutive planes of one slab and a stencil's z-neighbours are read while
-// they sit in that L2; it writes partial[b] (r_p) and partial[count + b] (r_u),
-// count = G N.
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_saddle_norms(Geom g, TimeOp t, const double* __restrict__ taus,
-                                                         const double* __restrict__ F,
-                                                         const double* __restrict__ u0, const double* __restrict__ p,
-                                                         const double* __restrict__ u, double* __restrict__ partial,
-                                                         long count, int G) {
-  const long b = block_id();
-  const int s = int(b / G), bx = int(b % G);
-  double vp = 0.0, vu = 0.0;
-  {
-    const SlabOp<double> op = load_op<double>(nullptr, t.cA, s, t.R);
-    const long o = long(s) * g.npts;
-    const long chunk = (g.npts + long(G) * kBlock - 1) / (long(G) * kBlock) * kBlock;
-    const long i1 = min(g.npts, (long(bx) + 1) * chunk);
-    for (long i = long(bx) * chunk + threadIdx.x; i < i1; i += kBlock) {
-      int px, py, pz;
-      decode<D>(i, g.n, px, py, pz);
-      double dg, offp, offu;
-      stencil2<D>(p + o, u + o, i, px, py, pz, g, t.kap, op, t.R, dg, offp, offu);
-      const double pc = p[o + i];
-      const double uc = u[o + i];
-      const double um = s > 0 ? u[o - g.npts + i] : 0.0;
-      const double up = s + 1 < t.N ? u[o + g.npts + i] : 0.0;
-      const double pp = s + 1 < t.N ? p[o + g.npts + i] : 0.0;
-      double f = taus[s] * F[o + i];
-      if (s == 0) f += u0[i];
-      const double rp = (uc - um) - (dg * pc - offp) - f;
-      const double ru = f - (pc - pp) - (2.0 * uc - um - up) - (dg * uc - offu);
-      vp += rp * rp;
-      vu += ru * ru;
-    }
-  }
-  const double sp = block_sum(vp);
-  if (threadIdx.x == 0) partial[b] = sp;
-  __syncthreads();   // block_sum's LDS slots are reused
-  const double su = block_sum(vu);
-  if (threadIdx.x == 0) partial[count + b] = su;
-}
-
 // block partials of ||f - B u||^2 over a (points, slabs) grid
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_fmBu_partial(Geom g, TimeOp t, const double* __restrict__ taus,

@@ -1087,4 +1087,142 @@ __global__ void __launch_bounds__(kBlock) k_resid_tile(const ResidJob* __restric
     resid_tile_body<D, TS, WHICH, RM, false>(J, tile, s0, s1, J.u, J.p, J.F, J.u0, (TS*)J.r, J.partial);
 }
 
+// ---------------------------------------------------------------------------
+// ||r_p||^2 and ||r_u||^2 of a pair (u, p), eq. (3.1), on the residual tiles:
+//   r_p = K u - A p - f,  r_u = f - K^T p - (K + K^T + A) u.
+// Both stencil operands (p and u) are staged per slab with their halo; a
+// block walks its slab run with u_{s-1}, u_{s+1} and p_{s+1} in registers and
+// writes partial[b] (r_p) and partial[count + b] (r_u) for its job-local
+// block b.  One pass over u, p and F after a solve.
+// ---------------------------------------------------------------------------
+template <int D, int RM, bool FIX>
+__device__ __forceinline__ void pair_norms_body(const ResidJob& J, int tile, int s0, int s1, long count) {
+  using T = UpTile<D>;
+  using KB = Box<D, T::X + 2, T::Y + 2, T::Z + 2>;
+  using TB = Box<D, T::X, T::Y, T::Z>;
+  constexpr int NT = nit<TB>();
+  __shared__ double sk[KB::size];
+  __shared__ double sp[KB::size];
+  __shared__ double su[KB::size];
+  const TimeOp t = J.t;
+  s1 = min(s1, t.N);
+  const Geom g = J.g;
+  const double* u = J.u;
+  const double* p = J.p;
+  double vp = 0.0, vu = 0.0;
+  if (s0 < s1) {
+    const int n = g.n;
+    int tx, ty, tz;
+    tile_origin<D, T>(n, tile, tx, ty, tz);
+    const int jx0 = tx * T::X + 1, jy0 = D >= 2 ? ty * T::Y + 1 : 1, jz0 = D >= 3 ? tz * T::Z + 1 : 1;
+    const int ox = jx0 - 1, oy = D >= 2 ? jy0 - 1 : 1, oz = D >= 3 ? jz0 - 1 : 1;
+    int vo[NT];
+    {
+      BoxIter<TB> it;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        const int jx = jx0 + it.x, jy = jy0 + it.y, jz = jz0 + it.z;
+        vo[k] = (it.ok() && interior<D>(jx, jy, jz, n)) ? vec_off<D>(jx, jy, jz, n) : -1;
+        it.next();
+      }
+    }
+    auto load_pts = [&](double(&v)[NT], const double* base) {
+#pragma unroll
+      for (int k = 0; k < NT; ++k) v[k] = vo[k] >= 0 ? base[vo[k]] : 0.0;
+    };
+    double kr[FIX ? 1 : nit<KB>()][FIX ? 1 : RM];
+    if constexpr (FIX) {
+      LevelOp L1{};
+      L1.kap = t.kap;
+      L1.c = t.cA;
+      L1.R = 1;
+      L1.cmode = CM_SCALE;
+      stage_fixed<D, KB, double>(sk, L1, g.nnodes, n, ox, oy, oz);
+    } else {
+      load_kraw<D, KB, double, RM>(kr, t.kap, g.nnodes, t.R, n, ox, oy, oz);
+    }
+    double pn_box[nit<KB>()], un_box[nit<KB>()];
+    prefetch_box<D, KB, double, double>(pn_box, p + long(s0) * g.npts, n, ox, oy, oz);
+    prefetch_box<D, KB, double, double>(un_box, u + long(s0) * g.npts, n, ox, oy, oz);
+    double um[NT], uk[NT], Fc[NT], Fn[NT], un[NT], pn[NT];
+    if (s0 > 0) load_pts(um, u + long(s0 - 1) * g.npts);
+    else {
+#pragma unroll
+      for (int k = 0; k < NT; ++k) um[k] = 0.0;
+    }
+    load_pts(Fc, J.F + long(s0) * g.npts);
+    for (int s = s0; s < s1; ++s) {
+      const long o = long(s) * g.npts;
+      const double tau = J.taus[s];
+      const double gamma = FIX ? t.cA[s * kMaxRank] : 1.0;
+      if constexpr (!FIX) write_kappa<KB, double, RM>(sk, kr, load_op<double>(nullptr, t.cA, s, t.R));
+      write_box<KB, double>(sp, pn_box);
+      write_box<KB, double>(su, un_box);
+      const bool more = s + 1 < t.N;
+      if (more) {
+        const long o1 = o + g.npts;
+        if (s + 1 < s1) {
+          prefetch_box<D, KB, double, double>(pn_box, p + o1, n, ox, oy, oz);
+          prefetch_box<D, KB, double, double>(un_box, u + o1, n, ox, oy, oz);
+          load_pts(Fn, J.F + o1);
+        }
+        load_pts(un, u + o1);
+        load_pts(pn, p + o1);
+      }
+      __syncthreads();
+      BoxIter<TB> it;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        if (vo[k] >= 0) {
+          const int kq = KB::idx(it.x + 1, D >= 2 ? it.y + 1 : 0, D >= 3 ? it.z + 1 : 0);
+          const double kc = sk[kq];
+          double dg = 0, offp = 0, offu = 0;
+#pragma unroll
+          for (int q = 0; q < 2 * D; ++q) {
+            const double w = kc + sk[kq + nb_off<KB>(q)];
+            dg += w;
+            offp += w * sp[kq + nb_off<KB>(q)];
+            offu += w * su[kq + nb_off<KB>(q)];
+          }
+          const double pc = sp[kq], uc = su[kq];
+          uk[k] = uc;
+          const double Ap = FIX ? gamma * (dg * pc - offp) : dg * pc - offp;
+          const double Au = FIX ? gamma * (dg * uc - offu) : dg * uc - offu;
+          double f = tau * Fc[k];
+          if (s == 0) f += J.u0[vo[k]];
+          const double up = more ? un[k] : 0.0, pp = more ? pn[k] : 0.0;
+          const double rp = (uc - um[k]) - Ap - f;
+          const double ru = f - (pc - pp) - (2.0 * uc - um[k] - up) - Au;
+          vp += rp * rp;
+          vu += ru * ru;
+        }
+        it.next();
+      }
+      __syncthreads();   // the next slab rewrites the staged boxes
+      // march: u_s (the staged centre) becomes u_{s-1}
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        um[k] = vo[k] >= 0 ? uk[k] : 0.0;
+        Fc[k] = Fn[k];
+      }
+    }
+  }
+  const long b = block_id() - J.block0;
+  const double bp = block_sum(vp);
+  if (threadIdx.x == 0) J.partial[b] = bp;
+  __syncthreads();   // block_sum's LDS slots are reused
+  const double bu = block_sum(vu);
+  if (threadIdx.x == 0) J.partial[count + b] = bu;
+}
+
+// one job per problem; count: the job's blocks (the offset of the r_u row)
+template <int D, int RM, int V>
+__global__ void __launch_bounds__(kBlock) k_pair_norms(const ResidJob* __restrict__ jobs, int njobs) {
+  int tile, s0, s1;
+  const ResidJob J = job_tile_run(jobs, njobs, 1 << 30, tile, s0, s1);
+  const long count = long(J.tiles) * ((J.t.N + J.sb - 1) / J.sb);
+  if (job_fixed(V, J.t.R == 1 ? CM_SCALE : CM_SLAB)) pair_norms_body<D, RM, true>(J, tile, s0, s1, count);
+  else pair_norms_body<D, RM, false>(J, tile, s0, s1, count);
+}
+
 }  // namespace stp
