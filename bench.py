@@ -932,6 +932,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-tol", action="store_true")
     ap.add_argument("--headline-only", action="store_true", help="only the headline workload (profiling runs)")
+    ap.add_argument("--batch-only", action="store_true", help="only the two batch legs (their own JSON line)")
     ap.add_argument("--precisions", default="f32,f64,bf16",
                     help="preconditioner precisions of the headline workload (f32 first: the headline value)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -953,12 +954,20 @@ def main():
         sys.exit(2)
     t_start = time.perf_counter()
     cpu = None
-    if not args.no_cpu_baseline and not args.headline_only:
+    if not args.no_cpu_baseline and not args.headline_only and not args.batch_only:
         # started before this process touches the GPU (the child never does)
         cpu = start_cpu_baseline(args.cpu_iters)
         progress("cpu baseline started (child process)")
     import torch
     torch.cuda.set_device(0)
+    if args.batch_only:
+        import synth
+        out = dict(batch64=batch_leg("batch64", synth.batch2d(), args, ("f32",), ("f32",)))
+        small = synth.batch2d(count=64, seed=1006, sides=(31, 63), nt_range=(16, 128))
+        out["batch64_small"] = batch_leg("batch64_small", small, args, ("f32",), ("f32",), tune=False)
+        out["wall_s"] = time.perf_counter() - t_start
+        print(json.dumps(out), flush=True)
+        return
     prob, dims, head = headline_run(args)
     hp = args.precisions.split(",")[0]   # the precision the line's value is quoted in
     h32 = head[hp]

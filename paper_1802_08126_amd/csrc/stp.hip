@@ -34,7 +34,11 @@ stp_status fail(stp_status s, const char* fmt, ...) {
 namespace stpx {
 stp_status launch_finalize(stp_ctx* c) {
   c->kt.level = 0;
-  KLAUNCH(k_finalize, dim3(unsigned(c->P)), dim3(kBlock), 0, c->stream, (const FinJob*)c->sites.fin_dev);
+  // one block per job of the table: the problems the tables cover (a batch
+  // solve drops stopped problems from them)
+  const size_t nf = c->sites.fin.size();
+  if (nf == 0) return STP_OK;
+  KLAUNCH(k_finalize, dim3(unsigned(nf)), dim3(kBlock), 0, c->stream, (const FinJob*)c->sites.fin_dev);
   LAUNCH_CHECK();
   return STP_OK;
 }
@@ -272,6 +276,9 @@ stp_status build_levels(int spatial, Problem& q) {
 // ---------------------------------------------------------------------------
 // sites of the iteration (merged launches over the batch)
 // ---------------------------------------------------------------------------
+// problem i is in the launch tables (all of them unless a solve compacted them)
+inline bool act(const stp_ctx* c, size_t i) { return c->active.empty() || c->active[i]; }
+
 // top-level input / output of a V-cycle instance for one problem
 struct VTop {
   const void* in;
@@ -292,6 +299,7 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top,
   vc.tri = Site<PointJob>();
   const int pty = c->prec == STP_PREC_F64 ? PencilTY<double>::v : PencilTY<float>::v;
   for (size_t i = 0; i < c->pr.size(); ++i) {
+    if (!act(c, i)) continue;
     Problem& q = c->pr[i];
     const VTop& T = top[i];
     if (c->spatial == STP_SPATIAL_EXACT) {
@@ -340,9 +348,12 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top,
       u.acc64 = (l == 0) ? T.acc64 : nullptr;
       u.addout = (l == 0 && addout) ? 1 : 0;
       u.state = d.state;
-      // float64 keeps the tiled up-sweep: its register pencil needs 270 VGPRs (one
-      // wave per SIMD) and measured slower (11.8 vs 10.4 ms on 255^3 x 64)
-      if (q.lv[l].pen[fam] && c->prec != STP_PREC_F64) {
+      // float32, and bfloat16 when it adds into the float64 p: the float64 up-sweep
+      // pencil needs 270 VGPRs (one wave per SIMD) and measured slower than the
+      // tiles (11.8 vs 10.4 ms on 255^3 x 64); storing bfloat16 rows it took 9.5
+      // ms against the tiles' 7.6 (adding into p: 8.9 against 9.9)
+      const bool add64 = l == 0 && acc;
+      if (q.lv[l].pen[fam] && (c->prec == STP_PREC_F32 || (c->prec == STP_PREC_BF16 && add64))) {
         u.tiles = int(pencil_tiles(q.lv[l + 1].n, pty));
         u.sb = kPencilSlabs;
         u.pk = q.lv[l].pk[fam];
@@ -414,6 +425,7 @@ void build_transforms(stp_ctx* c, std::vector<Site<TimeJob>>& sites, int mode, c
                       const std::vector<double>& alpha) {
   sites.clear();
   for (size_t i = 0; i < c->pr.size(); ++i) {
+    if (!act(c, i)) continue;
     Problem& q = c->pr[i];
     // one site per power-of-two step count up to 4096, one per Bluestein
     // length M, and one dense site for the rest
@@ -465,6 +477,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
   for (int w = 0; w < 2; ++w) {
     S.resid[w] = Site<ResidJob>();
     for (size_t i = 0; i < P; ++i) {
+      if (!act(c, i)) continue;
       Problem& q = c->pr[i];
       ResidJob j{};
       j.tiles = int(q.resid_tiles);
@@ -512,6 +525,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
       Problem& q = c->pr[i];
       topAX[i] = VTop{q.W1, q.Xnu, nullptr};
       topHX[i] = VTop{q.W2, q.Xnu, nullptr};
+      if (!act(c, i)) continue;
       const int pb = int((q.g0.npts + kBlock - 1) / kBlock);
       const int sb = pick_sb(pb, q.N);
       const long nb = long(pb) * ((q.N + sb - 1) / sb);
@@ -522,6 +536,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
     build_vcycle(c, S.vc[VC_HX], 1, topHX, false);
     build_vcycle(c, S.vc[VC_HA], 1, topH, false, true);
     for (size_t i = 0; i < P; ++i) {
+      if (!act(c, i)) continue;
       Problem& q = c->pr[i];
       TileJob j{};
       j.gf = q.g0;
@@ -537,6 +552,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
   }
   S.mid = Site<TileJob>();
   for (size_t i = 0; i < P; ++i) {
+    if (!act(c, i)) continue;
     Problem& q = c->pr[i];
     TileJob j{};
     j.gf = q.g0;
@@ -554,6 +570,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
   build_transforms(c, S.a6, 1, in6, out6, acc6, om);
   S.fin.clear();
   for (size_t i = 0; i < P; ++i) {
+    if (!act(c, i)) continue;
     Problem& q = c->pr[i];
     // finite elements: the a3 residual writes one partial per block of its (points, slabs) grid
     const long np = c->disc == STP_DISC_FEM ? q.nfnorm : q.npart;
@@ -1853,6 +1870,21 @@ static stp_status capture_iteration(stp_ctx* c) {
   return capture_graph(c, &c->gexec, [c]() { return c->impl->iteration(); });
 }
 
+// Rebuild and upload the launch tables for the problems in c->active, bound to
+// (u, p); the captured iteration graph has the old launch shapes and goes.
+static stp_status retable(stp_ctx* c, const std::vector<double*>& u, const std::vector<double*>& p) {
+  build_sites(c, u, p);
+  if (tables_bytes(c->sites) > c->tables_bytes) return fail(STP_EDEVICE, "launch tables outgrew their reservation");
+  carve_tables(c->sites, (char*)c->ws + c->tables_off);
+  stp_status s = upload_all(c);
+  if (s != STP_OK) return s;
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  return STP_OK;
+}
+
 stp_status stp_uzawa_solve_batch(stp_ctx* c, double* const* u, double* const* p, stp_stats* stats) {
   if (!c || !u || !p) return fail(STP_EINVAL, "NULL argument");
   if (c->spatial == STP_SPATIAL_NONE) return fail(STP_EUNSUPPORTED, "context created without a spatial solver");
@@ -1863,6 +1895,10 @@ stp_status stp_uzawa_solve_batch(stp_ctx* c, double* const* u, double* const* p,
     pv[i] = p[i];
   }
   stp_status s;
+  if (!c->active.empty()) {   // every problem back in the tables
+    c->active.clear();
+    if ((s = retable(c, uv, pv)) != STP_OK) return s;
+  }
   for (int i = 0; i < c->P; ++i) {
     c->state_host[i] = DevState{};
     c->state_host[i].fnorm = c->pr[i].fnorm;
@@ -1892,9 +1928,22 @@ stp_status stp_uzawa_solve_batch(stp_ctx* c, double* const* u, double* const* p,
     for (int i = 0; i < c->P; ++i) all = all && c->state_host[i].done != 0;
     if (all) break;
     if (launched >= max_launch) return fail(STP_EDEVICE, "iteration state did not terminate");
+    // batch: drop the problems that stopped since the last check from the tables
+    bool dropped = false;
+    for (int i = 0; i < c->P && c->P > 1; ++i) dropped = dropped || (act(c, i) && c->state_host[i].done != 0);
+    if (dropped) {
+      c->active.assign(c->P, 0);
+      for (int i = 0; i < c->P; ++i) c->active[i] = c->state_host[i].done == 0;
+      if ((s = retable(c, uv, pv)) != STP_OK) return s;
+      if (graph && (s = capture_iteration(c)) != STP_OK) return s;
+    }
   }
   HIP_TRY(hipEventRecord(c->ev1, c->stream));
   const size_t r1 = c->kt.recs.size();
+  if (!c->active.empty()) {   // full tables again for whatever runs next
+    c->active.clear();
+    if ((s = retable(c, uv, pv)) != STP_OK) return s;
+  }
   c->kt.phase = PH_OTHER;
   for (int i = 0; i < c->P; ++i)   // residual blocks of the returned pairs (outside the timed loop)
     if ((s = pair_norms(c, i, uv[i], pv[i])) != STP_OK) return s;

@@ -418,6 +418,10 @@ struct stp_ctx {
   KTimer kt;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // batch contexts: problems the launch tables cover (empty: all).  A solve
+  // drops stopped problems from the tables at its host checks (their blocks
+  // would only be dispatched to exit) and restores the full set at its end.
+  std::vector<char> active;
   hipGraphExec_t gexecA = nullptr, gexecH = nullptr;   // A~^{-1} cycle and H~^{-1} (GMRES preconditioner)
   Schedule sched;
   std::string sched_text;

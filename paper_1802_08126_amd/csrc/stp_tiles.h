@@ -267,6 +267,13 @@ __host__ __device__ inline long tiles_for(int n) {
   return t;
 }
 
+// 3-D tile order: x fastest, then bricks of kBrickY x kBrickZ tiles in (y, z),
+// y fastest inside a brick, so the tiles a few hundred blocks in flight on one
+// XCD cover neighbours in z as well as in y and share their halos in its L2
+// (row-major order puts the z-neighbours a whole tile plane apart).
+constexpr bool kTileBricks = false;
+constexpr int kBrickY = 4, kBrickZ = 8;
+
 template <int D, typename T>
 __device__ __forceinline__ void tile_origin(int n, int tile, int& tx, int& ty, int& tz) {
   const int ntx = (n + T::X - 1) / T::X;
@@ -274,6 +281,16 @@ __device__ __forceinline__ void tile_origin(int n, int tile, int& tx, int& ty, i
   int t = tile;
   tx = t % ntx;
   t /= ntx;
+  if (D == 3 && kTileBricks) {
+    const int ntz = (n + T::Z - 1) / T::Z;
+    const int zb = t / (nty * kBrickZ), rz0 = zb * kBrickZ, bz = min(kBrickZ, ntz - rz0);
+    const int q = t - zb * nty * kBrickZ;
+    const int yb = q / (kBrickY * bz), ry0 = yb * kBrickY, by = min(kBrickY, nty - ry0);
+    const int q2 = q - yb * kBrickY * bz;
+    ty = ry0 + q2 % by;
+    tz = rz0 + q2 / by;
+    return;
+  }
   ty = D >= 2 ? t % nty : 0;
   tz = D >= 3 ? t / nty : 0;
 }
