@@ -354,12 +354,14 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top,
       // ms against the tiles' 7.6 (adding into p: 8.9 against 9.9)
       const bool add64 = l == 0 && acc;
       if (q.lv[l].pen[fam] && (c->prec == STP_PREC_F32 || (c->prec == STP_PREC_BF16 && add64))) {
-        u.tiles = int(pencil_tiles(q.lv[l + 1].n, pty));
+        const int puty = c->prec == STP_PREC_F64 ? (add64 ? PencilUpTY<double, EPI_ADD64>::v : PencilUpTY<double, EPI_STORE>::v)
+                                                 : (add64 ? PencilUpTY<float, EPI_ADD64>::v : PencilUpTY<float, EPI_STORE>::v);
+        u.tiles = int(pencil_tiles(q.lv[l + 1].n, puty));
         u.sb = kPencilSlabs;
         u.pk = q.lv[l].pk[fam];
         u.pd = q.lv[l].pd[fam];
         vc.upp[l].add(u, long(u.tiles) * ((q.N + u.sb - 1) / u.sb), true);
-        vc.upp[l].epi = (l == 0 && acc) ? EPI_ADD64 : EPI_STORE;
+        vc.upp[l].epi = add64 ? EPI_ADD64 : EPI_STORE;
       } else {
         u.tiles = int(tiles_up_d(q.dim, q.lv[l].n));
         u.sb = sched_sb(u.tiles, q.N, (l == 0 && acc) ? c->sched.e[KN_UPA0] : c->sched.e[KN_UP0 + l]);

@@ -44,13 +44,24 @@ constexpr int kPencilThreads = 64 * kPencilWaves;
 // and 2.22 ms; two or more passes of slabs per wave were slower.
 constexpr bool kPencilGroupFastest = false;
 constexpr bool kPencilXFastest = true;
+// planes of loads in flight ahead of the down-sweep's march: one took 2.11 ms
+// against two planes' 2.22 (float32, four rows), the freed registers paying for
+// taller pencils
+constexpr int kPencilDepth = 1;
 constexpr int kPencilCX = 30;       // coarse nodes per wave along x (2 * 30 + 3 lanes used)
 constexpr int kPencilTZ = 16;       // coarse planes per wave
 constexpr int kPencilMinNc = 24;    // coarser levels keep the tiled kernel (lanes would idle)
 
+// coarse rows per pencil, set by measurement on 255^3 x 64: the down-sweep
+// (PencilTY) gains from taller pencils (fewer halo rows per owned row) while its
+// registers allow; the up-sweep storing a level (PencilUpTY, EPI_STORE) is
+// fastest at four rows, the one adding into the float64 iterate at two (its
+// extra float64 read-modify-write wants the occupancy of 144 VGPRs)
 template <typename TC> struct PencilTY;
-template <> struct PencilTY<float> { static constexpr int v = 4; };
-template <> struct PencilTY<double> { static constexpr int v = 2; };
+template <> struct PencilTY<float> { static constexpr int v = 6; };
+template <> struct PencilTY<double> { static constexpr int v = 4; };
+template <typename TC, int EPI> struct PencilUpTY { static constexpr int v = EPI == EPI_ADD64 ? 2 : 4; };
+template <int EPI> struct PencilUpTY<double, EPI> { static constexpr int v = 2; };
 
 // pencils of a level with nc coarse nodes per axis
 __host__ __device__ inline long pencil_tiles(int nc, int ty) {
@@ -145,13 +156,13 @@ __device__ __forceinline__ bool pencil_pos(const TileJob& J, int pass, PencilPos
   const int lb = int(block_id() - J.block0);
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   P.lane = int(threadIdx.x) & 63;
+  const int nc = J.gc.n;
+  const int nyt = (nc + TY - 1) / TY, nxs = (nc + kPencilCX - 1) / kPencilCX;
   const int grp = kPencilGroupFastest ? lb % ng : lb / J.tiles;
+  int t = kPencilGroupFastest ? lb / ng : lb % J.tiles;
   P.s = grp * kPencilSlabs + pass * kPencilWaves + wave;
   if (P.s >= S) return false;
   if (J.state && done_flag(J.state)) return false;
-  const int nc = J.gc.n;
-  int t = kPencilGroupFastest ? lb / ng : lb % J.tiles;
-  const int nyt = (nc + TY - 1) / TY, nxs = (nc + kPencilCX - 1) / kPencilCX;
   int xs, yt;
   if (kPencilXFastest) {
     xs = t % nxs;
@@ -249,35 +260,36 @@ __device__ __forceinline__ void mg_down_pencil(const TileJob& J, const PencilPos
       R[i] = one_m_omega * bc[r] + gamma * o;
     }
   };
-  TC Bq[2][NR], Kq[2][NR], Dq[2][NR];   // loaded planes, slot q % 2
+  constexpr int PD = kPencilDepth;
+  TC Bq[PD][NR], Kq[PD][NR], Dq[PD][NR];   // loaded planes, slot q % PD
   TC R[RR], Kp[NR], Xp[NR];
   {
-    TC b0[NR], k0[NR], d0[NR], x0[NR];
+    TC b0[NR], k0[NR], d0[NR], x0[NR], b1[NR], k1[NR], d1[NR];
     load_plane(0, b0, k0, d0);
-    load_plane(1, Bq[1], Kq[1], Dq[1]);
+    load_plane(1, b1, k1, d1);
     x1_plane(0, b0, d0, x0);
-    x1_plane(1, Bq[1], Dq[1], Xp);
-    inplane(Xp, Kq[1], x0, k0, Bq[1], R);
+    x1_plane(1, b1, d1, Xp);
+    inplane(Xp, k1, x0, k0, b1, R);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) Kp[r] = Kq[1][r];
+    for (int r = 0; r < NR; ++r) Kp[r] = k1[r];
   }
   const int pend = 2 * Kc + 1;   // r planes p = 1 .. pend
   load_plane(2, Bq[0], Kq[0], Dq[0]);
-  load_plane(3, Bq[1], Kq[1], Dq[1]);
+  if (PD == 2) load_plane(3, Bq[PD - 1], Kq[PD - 1], Dq[PD - 1]);
   TC A[RR];
 #pragma unroll
   for (int i = 0; i < RR; ++i) A[i] = TC(0);
   const bool st_lane = (lane & 1) == 0 && lane >= 2 && lane <= 2 * CX;
   const int I = I0 + ((lane - 2) >> 1);
 
-  // r plane p = p0 + u (p0 odd): plane p + 1 sits in slot (p + 1) % 2 = u % 2
+  // r plane p = p0 + u (p0 odd): plane p + 1 sits in slot (p + 1) % PD = u % PD
   auto step = [&](auto U, int p0) -> bool {
     constexpr int u = decltype(U)::value;
     const int p = p0 + u;
     if (p > pend) return false;
-    TC(&bn)[NR] = Bq[u % 2];
-    TC(&kn)[NR] = Kq[u % 2];
-    TC(&dn)[NR] = Dq[u % 2];
+    TC(&bn)[NR] = Bq[u % PD];
+    TC(&kn)[NR] = Kq[u % PD];
+    TC(&dn)[NR] = Dq[u % PD];
     TC xn[NR];
     x1_plane(p + 1, bn, dn, xn);
     TC rv[RR];
@@ -290,7 +302,7 @@ __device__ __forceinline__ void mg_down_pencil(const TileJob& J, const PencilPos
         Kp[r] = kn[r];
         Xp[r] = xn[r];
       }
-      if (p + 2 <= pend) load_plane(p + 3, bn, kn, dn);   // the slot just consumed
+      if (p + PD <= pend) load_plane(p + 1 + PD, bn, kn, dn);   // the slot just consumed
     }
     if constexpr (u % 2 == 0) {
       // odd p = 2k + 1 closes coarse plane k - 1 (weight 1/4) and opens plane k

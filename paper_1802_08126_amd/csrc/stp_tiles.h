@@ -270,8 +270,9 @@ __host__ __device__ inline long tiles_for(int n) {
 // 3-D tile order: x fastest, then bricks of kBrickY x kBrickZ tiles in (y, z),
 // y fastest inside a brick, so the tiles a few hundred blocks in flight on one
 // XCD cover neighbours in z as well as in y and share their halos in its L2
-// (row-major order puts the z-neighbours a whole tile plane apart).
-constexpr bool kTileBricks = false;
+// (row-major order puts the z-neighbours a whole tile plane apart).  On 255^3 x
+// 64 the residuals took 4-5 % less time (float32 a1 8.40 -> 8.03 ms).
+constexpr bool kTileBricks = true;
 constexpr int kBrickY = 4, kBrickZ = 8;
 
 template <int D, typename T>
