@@ -53,22 +53,19 @@ METRIC = "space-time DoF-iterations/sec + time to 1e-8 residual, mixed vs FP64, 
 # HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by
 # the same counters on a plain copy) for (workload, dtype, kernel, level); used only
 # while the kernel sources hash to the recorded value (see the named profile).
-# HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled by the copy
-# calibration), valid while the kernel sources hash to the recorded value
-_SRC_SHA = "92963d9de275356222a2ac86e0a3acd3b737b69a5d168ab65bdeb636cb61624f"
+_SRC_SHA = "bb0365dab073d14add6e257ff5957ae07551bc3654bc35fb15aab47e6da3aa6e"
+_PROF = "profiles/heat3d_255_N64_lognormal_f32_"
 MEASURED_TRAFFIC = {
-    ("heat3d_255_N64_lognormal", "f32", "k_resid_tile<a3>", 0): dict(
-        bytes=40_540_202_475, sources_sha256=_SRC_SHA,
-        profile="profiles/heat3d_255_N64_lognormal_f32_resid_tile_a3.md"),
-    ("heat3d_255_N64_lognormal", "f32", "k_mg_down_p3", 0): dict(
-        bytes=8_019_399_923, sources_sha256=_SRC_SHA,
-        profile="profiles/heat3d_255_N64_lognormal_f32_mg_down_p3_L0.md"),
-    ("heat3d_255_N64_lognormal", "f32", "k_mg_up_p3<store>", 0): dict(
-        bytes=13_065_061_368, sources_sha256=_SRC_SHA,
-        profile="profiles/heat3d_255_N64_lognormal_f32_mg_up_p3_store_L0.md"),
-    ("heat3d_255_N64_lognormal", "f32", "k_mg_up_p3<add64>", 0): dict(
-        bytes=27_016_559_463, sources_sha256=_SRC_SHA,
-        profile="profiles/heat3d_255_N64_lognormal_f32_mg_up_p3_add64_L0.md"),
+    ("heat3d_255_N64_lognormal", "f32", k, 0): dict(bytes=b, sources_sha256=_SRC_SHA, profile=_PROF + f + ".md")
+    for k, b, f in (
+        ("k_resid_tile<a3>", 41_260_725_705, "resid_tile_a3"),
+        ("k_resid_tile<a1>", 38_758_829_447, "resid_tile_a1"),
+        ("k_mg_down_p3", 11_015_001_245, "mg_down_p3_L0"),
+        ("k_mg_up_p3<store>", 13_070_000_678, "mg_up_p3_store_L0"),
+        ("k_mg_up_p3<add64>", 26_756_678_641, "mg_up_p3_add64_L0"),
+        ("k_time_fft2<a6,add64>", 21_240_800_664, "time_fft2_a6_add64"),
+        ("k_apply_tile", 10_208_739_938, "apply_tile_L0"),
+    )
 }
 
 
@@ -116,7 +113,7 @@ def algorithmic_bytes(kernel: str, level: int, dims, ts: int) -> float | None:
         return N * npts[0] * (3 * 8 + ts) + kap(0, 8)
     if k in ("k_mg_down", "k_mg_down_p3"):   # b in (fine), bc out (coarse), one coefficient field
         return N * (n_l + npts[level + 1]) * ts + kap(level, tc)
-    if k == "k_mg_up":
+    if k in ("k_mg_up", "k_mg_up_p3"):
         if add64:                  # b, e in; float64 p read and written
             return N * (n_l + npts[level + 1]) * ts + N * n_l * 16 + kap(level, tc)
         return N * (2 * n_l + npts[level + 1]) * ts + kap(level, tc)
@@ -138,19 +135,30 @@ def roofline(rep, dims, ts, workload, dtype):
     total = sum(r["total_ms"] for r in rep)
     top = rep[0]
     b = algorithmic_bytes(top["kernel"], top["level"], dims, ts)
-    table = [dict(kernel=r["kernel"], level=r["level"], launches=r["launches"], avg_us=1e3 * r["avg_ms"],
-                  share=r["total_ms"] / total) for r in rep[:12]]
+    sha = kernel_sources_sha256()
+
+    def measured(r):
+        m = MEASURED_TRAFFIC.get((workload, dtype, r["kernel"], r["level"]))
+        if m is None:
+            return None, None, "no counter run recorded for this kernel and workload"
+        if m["sources_sha256"] != sha:
+            return None, None, f"kernel sources changed since the counters were taken (now {sha[:12]})"
+        return m["bytes"], m["profile"], "FETCH_SIZE + WRITE_SIZE, copy-calibrated"
+
+    table = []
+    for r in rep[:12]:
+        e = dict(kernel=r["kernel"], level=r["level"], launches=r["launches"], avg_us=1e3 * r["avg_ms"],
+                 share=r["total_ms"] / total)
+        ab = algorithmic_bytes(r["kernel"], r["level"], dims, ts)
+        if ab is not None:
+            e["algorithmic_bytes"] = ab
+            e["frac"] = ab / (r["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+        e["traffic"] = measured(r)[0]
+        table.append(e)
     if b is None:
         return None, table
     achieved = b / (top["avg_ms"] * 1e-3) / 1e9
-    traffic, src, note = None, None, "no counter run recorded for this kernel and workload"
-    m = MEASURED_TRAFFIC.get((workload, dtype, top["kernel"], top["level"]))
-    if m is not None:
-        sha = kernel_sources_sha256()
-        if m["sources_sha256"] == sha:
-            traffic, src, note = m["bytes"], m["profile"], "FETCH_SIZE + WRITE_SIZE, copy-calibrated"
-        else:
-            note = f"kernel sources changed since the counters were taken (now {sha[:12]})"
+    traffic, src, note = measured(top)
     return dict(bound="hbm", kernel=top["kernel"], level=top["level"], achieved=achieved, peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic, traffic_unit="bytes per launch",
                 traffic_source=src, traffic_note=note, bytes_per_launch=b, avg_launch_us=1e3 * top["avg_ms"],
