@@ -941,6 +941,8 @@ def main():
     ap.add_argument("--skip-tol", action="store_true")
     ap.add_argument("--headline-only", action="store_true", help="only the headline workload (profiling runs)")
     ap.add_argument("--batch-only", action="store_true", help="only the two batch legs (their own JSON line)")
+    ap.add_argument("--leg", choices=("heat2d", "heat3d_mid"),
+                    help="only the 2-D 255^2 x 256 or the 3-D 127^3 x 128 leg (its own JSON line; profiling runs)")
     ap.add_argument("--precisions", default="f32,f64,bf16",
                     help="preconditioner precisions of the headline workload (f32 first: the headline value)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -962,7 +964,7 @@ def main():
         sys.exit(2)
     t_start = time.perf_counter()
     cpu = None
-    if not args.no_cpu_baseline and not args.headline_only and not args.batch_only:
+    if not args.no_cpu_baseline and not args.headline_only and not args.batch_only and not args.leg:
         # started before this process touches the GPU (the child never does)
         cpu = start_cpu_baseline(args.cpu_iters)
         progress("cpu baseline started (child process)")
@@ -973,6 +975,12 @@ def main():
         out = dict(batch64=batch_leg("batch64", synth.batch2d(), args, ("f32",), ("f32",)))
         small = synth.batch2d(count=64, seed=1006, sides=(31, 63), nt_range=(16, 128))
         out["batch64_small"] = batch_leg("batch64_small", small, args, ("f32",), ("f32",), tune=False)
+        out["wall_s"] = time.perf_counter() - t_start
+        print(json.dumps(out), flush=True)
+        return
+    if args.leg:
+        out = {"heat2d_255_N256": heat2d_run(args)[0]} if args.leg == "heat2d" else \
+            {"heat3d_127_N128_lognormal": heat3d_mid_run(args)}
         out["wall_s"] = time.perf_counter() - t_start
         print(json.dumps(out), flush=True)
         return
