@@ -348,14 +348,14 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top,
       u.acc64 = (l == 0) ? T.acc64 : nullptr;
       u.addout = (l == 0 && addout) ? 1 : 0;
       u.state = d.state;
-      // float32, and bfloat16 when it adds into the float64 p: the float64 up-sweep
-      // pencil needs 270 VGPRs (one wave per SIMD) and measured slower than the
-      // tiles (11.8 vs 10.4 ms on 255^3 x 64); storing bfloat16 rows it took 9.5
-      // ms against the tiles' 7.6 (adding into p: 8.9 against 9.9)
+      // float32 and bfloat16: the float64 up-sweep pencil measured slower than the
+      // tiles (two rows, 270 VGPRs: 11.1 vs 10.4 ms storing on 255^3 x 64; one row:
+      // faster at level 0, slower at level 1)
       const bool add64 = l == 0 && acc;
-      if (q.lv[l].pen[fam] && (c->prec == STP_PREC_F32 || (c->prec == STP_PREC_BF16 && add64))) {
-        const int puty = c->prec == STP_PREC_F64 ? (add64 ? PencilUpTY<double, EPI_ADD64>::v : PencilUpTY<double, EPI_STORE>::v)
-                                                 : (add64 ? PencilUpTY<float, EPI_ADD64>::v : PencilUpTY<float, EPI_STORE>::v);
+      if (q.lv[l].pen[fam] && c->prec != STP_PREC_F64) {
+        const int puty = c->prec == STP_PREC_F64    ? (add64 ? PencilUpTY<double, EPI_ADD64>::v : PencilUpTY<double, EPI_STORE>::v)
+                         : c->prec == STP_PREC_F32 ? (add64 ? PencilUpTY<float, EPI_ADD64>::v : PencilUpTY<float, EPI_STORE>::v)
+                                                   : (add64 ? PencilUpTY<bf16, EPI_ADD64>::v : PencilUpTY<bf16, EPI_STORE>::v);
         u.tiles = int(pencil_tiles(q.lv[l + 1].n, puty));
         u.sb = kPencilSlabs;
         u.pk = q.lv[l].pk[fam];

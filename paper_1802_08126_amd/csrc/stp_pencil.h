@@ -60,8 +60,12 @@ constexpr int kPencilMinNc = 24;    // coarser levels keep the tiled kernel (lan
 template <typename TC> struct PencilTY;
 template <> struct PencilTY<float> { static constexpr int v = 6; };
 template <> struct PencilTY<double> { static constexpr int v = 4; };
-template <typename TC, int EPI> struct PencilUpTY { static constexpr int v = EPI == EPI_ADD64 ? 2 : 4; };
+template <typename TS, int EPI> struct PencilUpTY { static constexpr int v = EPI == EPI_ADD64 ? 2 : 4; };
 template <int EPI> struct PencilUpTY<double, EPI> { static constexpr int v = 2; };
+// bfloat16 storage: two rows for both up-sweeps (the storing one needs 302 VGPRs
+// at four rows, one wave per SIMD, and took 9.5 ms against the tiles' 7.4; at two
+// rows, 146 VGPRs, 3.0 ms)
+template <int EPI> struct PencilUpTY<bf16, EPI> { static constexpr int v = 2; };
 
 // pencils of a level with nc coarse nodes per axis
 __host__ __device__ inline long pencil_tiles(int nc, int ty) {

@@ -240,10 +240,10 @@ struct Solver : SolverBase {
     const dim3 gr(unsigned(s.blocks)), bl(kPencilThreads);
     const int nj = int(s.jobs.size());
     if (s.epi == EPI_ADD64)
-      KLAUNCH_NAMED("k_mg_up_p3<add64>", (k_mg_up_p3<TS, TC, PencilUpTY<TC, EPI_ADD64>::v, EPI_ADD64>), gr, bl, 0, c->stream, s.dev,
+      KLAUNCH_NAMED("k_mg_up_p3<add64>", (k_mg_up_p3<TS, TC, PencilUpTY<TS, EPI_ADD64>::v, EPI_ADD64>), gr, bl, 0, c->stream, s.dev,
                     nj, omegaJ());
     else
-      KLAUNCH_NAMED("k_mg_up_p3<store>", (k_mg_up_p3<TS, TC, PencilUpTY<TC, EPI_STORE>::v, EPI_STORE>), gr, bl, 0, c->stream,
+      KLAUNCH_NAMED("k_mg_up_p3<store>", (k_mg_up_p3<TS, TC, PencilUpTY<TS, EPI_STORE>::v, EPI_STORE>), gr, bl, 0, c->stream,
                     s.dev, nj, omegaJ());
     LAUNCH_CHECK();
     return STP_OK;
