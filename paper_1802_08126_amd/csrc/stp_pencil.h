@@ -247,8 +247,8 @@ __device__ __forceinline__ void mg_down_pencil(const TileJob& J, const PencilPos
   // The residual of plane p is summed as the march reaches its terms: when x1
   // of plane p is known, R(p) = (1 - omega) b + gamma (x-, x+, y-, y+, z- face
   // terms); the z+ term completes it once x1 of plane p + 1 is known.  Only
-  // R(p), k(p) and x1(p) (Kp, Xp) cross a plane step, plus the loaded planes p + 1 and
-  // p + 2 (slot q % 2): plane p + 3 is issued as plane p + 1 is consumed, two
+  // R(p), k(p) and x1(p) (Kp, Xp) cross a plane step, plus the kPencilDepth
+  // loaded planes ahead (slot q % kPencilDepth): each is issued kPencilDepth
   // steps before its use.
   auto inplane = [&](const TC(&xc)[NR], const TC(&kc)[NR], const TC(&xm)[NR], const TC(&km)[NR],
                      const TC(&bc)[NR], TC(&R)[RR]) {
