@@ -58,13 +58,13 @@ _PROF = "profiles/heat3d_255_N64_lognormal_f32_"
 MEASURED_TRAFFIC = {
     ("heat3d_255_N64_lognormal", "f32", k, 0): dict(bytes=b, sources_sha256=_SRC_SHA, profile=_PROF + f + ".md")
     for k, b, f in (
-        ("k_resid_tile<a3>", 41_271_283_566, "resid_tile_a3"),
-        ("k_resid_tile<a1>", 38_761_220_458, "resid_tile_a1"),
+        ("k_resid_tile<a3>", 40_736_192_329, "resid_tile_a3"),
+        ("k_resid_tile<a1>", 38_414_359_668, "resid_tile_a1"),
         ("k_mg_down_p3", 11_014_274_391, "mg_down_p3_L0"),
         ("k_mg_up_p3<store>", 13_070_051_573, "mg_up_p3_store_L0"),
         ("k_mg_up_p3<add64>", 26_762_635_285, "mg_up_p3_add64_L0"),
         ("k_time_fft2<a6,add64>", 21_241_390_490, "time_fft2_a6_add64"),
-        ("k_apply_tile", 10_208_857_690, "apply_tile_L0"),
+        ("k_apply_tile", 10_140_875_205, "apply_tile_L0"),
     )
 }
 
@@ -869,12 +869,15 @@ def _kname(r):
     return r["Kernel_Name"].split("(")[0].replace("void ", "").replace("stp::", "")
 
 
-def summarize_profile(d, kernel_prefix, grid_min):
+def summarize_profile(d, kernel_prefix, grid_min, final_grid=False):
     """Markdown summary of rocprofv3 output of this script under d: the --stats
     table (trace/), and, when the counter passes are there, the HBM bytes per
     launch of the kernel whose name starts with ``kernel_prefix`` and whose grid
     has at least ``grid_min`` work-items (the finest level), from FETCH_SIZE
-    (p1/) and WRITE_SIZE (p2/) scaled by the copy calibration passes (c1/, c2/)."""
+    (p1/) and WRITE_SIZE (p2/) scaled by the copy calibration passes (c1/, c2/).
+    With ``final_grid`` only launches with the grid of the kernel's last launch
+    count: the schedule the timed iterations run, not the autotuner's
+    candidates (other slabs per block)."""
     import csv
 
     def rows(sub, f):
@@ -893,10 +896,16 @@ def summarize_profile(d, kernel_prefix, grid_min):
             return int(r["Grid_Size"])
         return int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
 
-    sel = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr
-           if _kname(r).startswith(kernel_prefix) and grid(r) >= grid_min]
+    mine = [r for r in tr if _kname(r).startswith(kernel_prefix) and grid(r) >= grid_min]
+    gsel = grid(mine[-1]) if (final_grid and mine) else None
+
+    def keep(r):
+        return _kname(r).startswith(kernel_prefix) and grid(r) >= grid_min and (gsel is None or grid(r) == gsel)
+
+    sel = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr if keep(r)]
+    what = f"grid >= {grid_min} work-items" if gsel is None else f"the grid of the timed schedule ({gsel} work-items)"
     if sel:
-        print(f"\n## `{kernel_prefix}` launches with grid >= {grid_min} work-items\n")
+        print(f"\n## `{kernel_prefix}` launches with {what}\n")
         print(f"| launches | avg us | min us | max us |\n|---|---|---|---|\n| {len(sel)} | {avg(sel):.1f} | "
               f"{min(sel):.1f} | {max(sel):.1f} |")
     if not os.path.isdir(os.path.join(d, "p1")):
@@ -904,15 +913,14 @@ def summarize_profile(d, kernel_prefix, grid_min):
     res = {}
     for i, cn in ((1, "FETCH_SIZE"), (2, "WRITE_SIZE")):
         pm = rows(f"p{i}", "run_counter_collection.csv")
-        v = [float(r["Counter_Value"]) for r in pm if r["Counter_Name"] == cn and _kname(r).startswith(kernel_prefix)
-             and int(r["Grid_Size"]) >= grid_min]
+        v = [float(r["Counter_Value"]) for r in pm if r["Counter_Name"] == cn and keep(r)]
         cal = [float(r["Counter_Value"]) for r in rows(f"c{i}", "run_counter_collection.csv")
                if "copy" in r["Kernel_Name"].lower() and int(r["Grid_Size"]) > 100000 and r["Counter_Name"] == cn]
         factor = COPY_ELEMS * 8 / (avg(cal) * 1024)
         kib = avg(v)
         res[cn] = (len(v), kib, avg(cal), factor, kib * 1024 * factor)
     f, w = res["FETCH_SIZE"], res["WRITE_SIZE"]
-    print(f"\n## HBM traffic of `{kernel_prefix}` (grid >= {grid_min})\n")
+    print(f"\n## HBM traffic of `{kernel_prefix}` ({what})\n")
     print(f"Calibration: a copy of {COPY_ELEMS * 8:,} bytes reads FETCH_SIZE = {f[2]:,.1f} KiB and WRITE_SIZE = "
           f"{w[2]:,.1f} KiB per dispatch, so bytes = FETCH_SIZE x 1024 x {f[3]:.3f} and WRITE_SIZE x 1024 x "
           f"{w[3]:.3f}.\n")
@@ -925,10 +933,10 @@ def summarize_profile(d, kernel_prefix, grid_min):
         pm = rows("p3", "run_counter_collection.csv")
         sel = {}
         for r in pm:
-            if _kname(r).startswith(kernel_prefix) and int(r["Grid_Size"]) >= grid_min:
+            if keep(r):
                 sel.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
         if sel:
-            print(f"\n## Instruction counters of `{kernel_prefix}` (grid >= {grid_min}), average per launch\n")
+            print(f"\n## Instruction counters of `{kernel_prefix}` ({what}), average per launch\n")
             print("| counter | per launch |\n|---|---|")
             for cn in sorted(sel):
                 print(f"| {cn} | {avg(sel[cn]):,.0f} |")
@@ -969,9 +977,11 @@ def main():
                     help="only summarise rocprofv3 output under DIR (no GPU use)")
     ap.add_argument("--kernel", default="k_mg_down<3, float", help="kernel prefix for --summarize-profile")
     ap.add_argument("--grid-min", type=int, default=1 << 22, help="finest-level grid size for --summarize-profile")
+    ap.add_argument("--final-grid", action="store_true",
+                    help="--summarize-profile: only launches with the grid of the kernel's last launch (timed schedule)")
     args = ap.parse_args()
     if args.summarize_profile:
-        summarize_profile(args.summarize_profile, args.kernel, args.grid_min)
+        summarize_profile(args.summarize_profile, args.kernel, args.grid_min, args.final_grid)
         return
     if args.copy_calibration:
         copy_calibration()
