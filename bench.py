@@ -869,6 +869,27 @@ def _kname(r):
     return r["Kernel_Name"].split("(")[0].replace("void ", "").replace("stp::", "")
 
 
+def copy_bandwidth(gib=4, reps=10):
+    """Practical ceiling for the rooflines: a plain device copy (torch's copy kernel)
+    between two float64 buffers of ``gib`` GiB each, far larger than the on-die
+    cache, timed with HIP events; bytes read + written per second."""
+    import torch
+    n = (gib << 30) // 8
+    a = torch.randn(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps(dict(copy_gib=gib, ms=ms, gbs=2 * n * 8 / ms / 1e6, frac_of_peak=2 * n * 8 / ms / 1e6 / HBM_PEAK_GBS)),
+          flush=True)
+
+
 def summarize_profile(d, kernel_prefix, grid_min, final_grid=False):
     """Markdown summary of rocprofv3 output of this script under d: the --stats
     table (trace/), and, when the counter passes are there, the HBM bytes per
@@ -971,6 +992,8 @@ def main():
                     help="only the 2-D 255^2 x 256 or the 3-D 127^3 x 128 leg (its own JSON line; profiling runs)")
     ap.add_argument("--precisions", default="f32,f64,bf16",
                     help="preconditioner precisions of the headline workload (f32 first: the headline value)")
+    ap.add_argument("--copy-bandwidth", action="store_true",
+                    help="time a plain 4 GiB device copy (the practical bandwidth ceiling) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy (counter calibration)")
     ap.add_argument("--summarize-profile", metavar="DIR",
@@ -985,6 +1008,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.copy_bandwidth:
+        copy_bandwidth()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: runs on one GPU only; sharding the time slabs over several GPUs is a design, "
