@@ -111,6 +111,10 @@ long tiles_down_d(int dim, int nc) {
 long tiles_up_d(int dim, int n) {
   return dim == 1 ? tiles_for<1, UpTile<1>>(n) : dim == 2 ? tiles_for<2, UpTile<2>>(n) : tiles_for<3, UpTile<3>>(n);
 }
+long tiles_resid_d(int dim, int n) {
+  return dim == 1 ? tiles_for<1, ResidTile<1>>(n) : dim == 2 ? tiles_for<2, ResidTile<2>>(n)
+                                                             : tiles_for<3, ResidTile<3>>(n);
+}
 
 
 // Plan (dry run) or carve (real run) one problem's buffers.
@@ -122,15 +126,15 @@ void plan_problem(int prec, int spatial, Problem& q, Bump& bp, bool nux, bool fe
     size_t lds;
     transform_path(q.N, tcb, q.tpath, C, lds);
   }
-  q.resid_tiles = tiles_up_d(q.dim, q.n);
+  q.resid_tiles = tiles_resid_d(q.dim, q.n);
   const dim3 gp = grid_pts(q.g0.npts, q.N);
   q.nfnorm = long(gp.x) * gp.y * gp.z;
   q.state = (DevState*)bp.take(sizeof(DevState));
   // residual partials for any slabs-per-block choice (at most one slab per block)
   q.partial = (double*)bp.take(size_t(std::max(q.resid_tiles * q.N, q.nfnorm)) * 8);
   // norm partials of a returned pair: one row each for r_p and r_u (FEM: one per
-  // block of its grid; else one per block of the residual tiles' default schedule)
-  q.nrm = (double*)bp.take(size_t(2) * std::max(long(kNormBlocks), q.resid_tiles * N) * 8);
+  // block of its grid; else one per block of the up-sweep tiles' default schedule)
+  q.nrm = (double*)bp.take(size_t(2) * std::max(long(kNormBlocks), tiles_up_d(q.dim, q.n) * N) * 8);
   q.njob = bp.take(sizeof(ResidJob));
   q.fbind = fem ? (FemBind*)bp.take(sizeof(FemBind)) : nullptr;
   q.kap64 = (double*)bp.take(size_t(q.R) * q.g0.nnodes * 8);
@@ -478,6 +482,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
   const size_t P = c->pr.size();
   for (int w = 0; w < 2; ++w) {
     S.resid[w] = Site<ResidJob>();
+    S.resid[w].threads = c->dim == 3 ? ResidTile<3>::threads : kBlock;
     for (size_t i = 0; i < P; ++i) {
       if (!act(c, i)) continue;
       Problem& q = c->pr[i];
@@ -616,7 +621,7 @@ size_t tables_bytes(Sites& S) {
 bool sites_fit(stp_ctx* c) {
   bool ok = true;
   for_each_site(c->sites, [&](auto& s) {
-    if (double(s.blocks) * kBlock > 4294967295.0) ok = false;
+    if (double(s.blocks) * std::max(s.threads, kBlock) > 4294967295.0) ok = false;
     if (s.shmem > 65536) ok = false;   // fused multigrid launches stay within the default LDS limit
   });
   return ok;
@@ -1450,11 +1455,12 @@ stp_status pair_norms(stp_ctx* c, int i, const double* u, const double* p) {
     LAUNCH_CHECK();
     return STP_OK;
   }
-  // one job on the residual tiles (both operands staged per slab), slabs per
-  // block as the residual's default schedule
+  // one job on the up-sweep's tiles (both operands staged per slab), slabs per
+  // block as the default schedule
+  const long ntl = tiles_up_d(q.dim, q.n);
   ResidJob j{};
-  j.tiles = int(q.resid_tiles);
-  j.sb = sched_sb(q.resid_tiles, q.N, 0);
+  j.tiles = int(ntl);
+  j.sb = sched_sb(ntl, q.N, 0);
   j.g = q.g0;
   j.t = t;
   j.taus = q.taus64;
@@ -1463,7 +1469,7 @@ stp_status pair_norms(stp_ctx* c, int i, const double* u, const double* p) {
   j.F = q.F;
   j.u0 = q.u0;
   j.partial = q.nrm;
-  const long cnt = q.resid_tiles * ((q.N + j.sb - 1) / j.sb);
+  const long cnt = ntl * ((q.N + j.sb - 1) / j.sb);
   HIP_TRY(hipMemcpyAsync(q.njob, &j, sizeof(ResidJob), hipMemcpyHostToDevice, c->stream));
   const dim3 gr(static_cast<unsigned>(cnt)), bl(kBlock);
   const bool fix = q.R == 1;

@@ -210,8 +210,9 @@ __device__ __forceinline__ TC diag_at(int x, int y, int z, const Geom& g, const 
 __device__ __forceinline__ int done_flag(const int* st) { return *st; }
 
 // Block-wide sum of a double (wave64 shuffles + LDS), result valid in thread 0.
+template <int NTH = kBlock>
 __device__ __forceinline__ double block_sum(double v) {
-  __shared__ double red[kBlock / 64];
+  __shared__ double red[NTH / 64];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -219,7 +220,7 @@ __device__ __forceinline__ double block_sum(double v) {
   __syncthreads();
   double s = 0;
   if (threadIdx.x == 0) {
-    for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+    for (int w = 0; w < NTH / 64; ++w) s += red[w];
   }
   return s;
 }

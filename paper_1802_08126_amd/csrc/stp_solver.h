@@ -545,7 +545,7 @@ struct Solver : SolverBase {
     Site<ResidJob>& s = c->sites.resid[WHICH];
     c->kt.level = 0;
     const char* nm = WHICH == 0 ? "k_resid_tile<a1>" : "k_resid_tile<a3>";
-    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
+    const dim3 gr(unsigned(s.blocks)), bl(ResidTile<D>::threads);
     const int nj = int(s.jobs.size());
     switch (s.variant()) {
       case 1: KLAUNCH_NAMED(nm, (k_resid_tile<D, TS, WHICH, 1, 1>), gr, bl, 0, c->stream, s.dev, nj); break;

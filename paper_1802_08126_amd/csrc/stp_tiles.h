@@ -20,8 +20,9 @@
 
 namespace stp {
 
-template <int D, int EX, int EY, int EZ>
+template <int D, int EX, int EY, int EZ, int NTH = kBlock>
 struct Box {
+  static constexpr int threads = NTH;   // threads of the block that walks the box
   static constexpr int X = EX;
   static constexpr int Y = (D >= 2 ? EY : 1);
   static constexpr int Z = (D >= 3 ? EZ : 1);
@@ -29,13 +30,13 @@ struct Box {
   __device__ static __forceinline__ int idx(int x, int y, int z) { return (z * Y + y) * X + x; }
 };
 
-// Walks the linear positions q = threadIdx.x, threadIdx.x + kBlock, ... of a
-// box, keeping (x, y, z) up to date with adds and one conditional subtract
+// Walks the linear positions q = threadIdx.x, threadIdx.x + B::threads, ... of
+// a box, keeping (x, y, z) up to date with adds and one conditional subtract
 // per axis instead of divisions.
 template <typename B>
 struct BoxIter {
-  static constexpr int DX = kBlock % B::X;
-  static constexpr int DR = kBlock / B::X;
+  static constexpr int DX = B::threads % B::X;
+  static constexpr int DR = B::threads / B::X;
   static constexpr int DY = DR % B::Y;
   static constexpr int DZ = DR / B::Y;
   int q, x, y, z;
@@ -48,7 +49,7 @@ struct BoxIter {
   }
   __device__ __forceinline__ bool ok() const { return q < B::size; }
   __device__ __forceinline__ void next() {
-    q += kBlock;
+    q += B::threads;
     x += DX;
     int cy = 0;
     if (x >= B::X) { x -= B::X; cy = 1; }
@@ -61,13 +62,13 @@ struct BoxIter {
 
 template <typename B>
 __host__ __device__ constexpr int nit() {
-  return (B::size + kBlock - 1) / kBlock;
+  return (B::size + B::threads - 1) / B::threads;
 }
 
 // Fully unrolled walk over a box (compile-time trip count); `continue` in the
 // body moves on to the next position.
 #define STP_BOX_FOR(B, it)                                                  \
-  _Pragma("unroll") for (BoxIter<B> it; it.q < int(threadIdx.x) + nit<B>() * kBlock; it.next()) \
+  _Pragma("unroll") for (BoxIter<B> it; it.q < int(threadIdx.x) + nit<B>() * B::threads; it.next()) \
     if (it.ok())
 
 // offsets of the 2d neighbours inside a box (x-, x+, y-, y+, z-, z+)
@@ -144,7 +145,7 @@ __device__ __forceinline__ void stage_kappa(TC* sk, const TC* __restrict__ kap, 
   }
 #pragma unroll
   for (int k = 0; k < NI; ++k) {
-    const int q = threadIdx.x + k * kBlock;
+    const int q = threadIdx.x + k * KB::threads;
     if (q < KB::size) sk[q] = v[k];
   }
 }
@@ -259,6 +260,17 @@ template <> struct UpTile<1> { static constexpr int X = 512, Y = 1, Z = 1; };
 template <> struct UpTile<2> { static constexpr int X = 64, Y = 16, Z = 1; };
 template <> struct UpTile<3> { static constexpr int X = 32, Y = 4, Z = 4; };
 
+// tiles of the two time-global residuals: in 3-D twice as tall in y as the
+// up-sweep's, with a block of 512 threads so each thread still keeps two points
+// in registers: a tile's operand halo is mostly read from HBM again (neighbouring
+// tiles march through their slab runs out of step), and 34 x 10 x 6 nodes per
+// 32 x 8 x 4 tile are 1.99 reads per point against 2.39 for 32 x 4 x 4.  On
+// 255^3 x 64 (float32) a1 / a3 took 7.79 / 7.96 ms against 8.01 / 8.21; 32 x 8 x 8
+// with 1024 threads (one block per CU) 7.77 / 8.36, and 32 x 8 x 4 with 256
+// threads (four points per thread, fewer waves) 7.94 / 9.56.
+template <int D> struct ResidTile : UpTile<D> { static constexpr int threads = kBlock; };
+template <> struct ResidTile<3> { static constexpr int X = 32, Y = 8, Z = 4, threads = 512; };
+
 template <int D, typename T>
 __host__ __device__ inline long tiles_for(int n) {
   long t = (n + T::X - 1) / T::X;
@@ -334,7 +346,7 @@ template <typename KB, typename TC, int RM>
 __device__ __forceinline__ void write_kappa(TC* sk, const TC (&kr)[nit<KB>()][RM], const SlabOp<TC>& op) {
 #pragma unroll
   for (int k = 0; k < nit<KB>(); ++k) {
-    const int q = threadIdx.x + k * kBlock;
+    const int q = threadIdx.x + k * KB::threads;
     if (q < KB::size) {
       TC v = op.c[0] * kr[k][0];
 #pragma unroll
@@ -348,7 +360,7 @@ template <typename B, typename TC>
 __device__ __forceinline__ void write_box(TC* sx, const TC (&v)[nit<B>()]) {
 #pragma unroll
   for (int k = 0; k < nit<B>(); ++k) {
-    const int q = threadIdx.x + k * kBlock;
+    const int q = threadIdx.x + k * B::threads;
     if (q < B::size) sx[q] = v[k];
   }
 }
@@ -977,9 +989,9 @@ __device__ __forceinline__ void resid_tile_body(const ResidJob& J, int tile, int
                                                 const double* __restrict__ u, const double* __restrict__ p,
                                                 const double* __restrict__ F, const double* __restrict__ u0,
                                                 TS* __restrict__ r, double* __restrict__ partial) {
-  using T = UpTile<D>;
-  using KB = Box<D, T::X + 2, T::Y + 2, T::Z + 2>;
-  using TB = Box<D, T::X, T::Y, T::Z>;
+  using T = ResidTile<D>;
+  using KB = Box<D, T::X + 2, T::Y + 2, T::Z + 2, T::threads>;
+  using TB = Box<D, T::X, T::Y, T::Z, T::threads>;
   constexpr int NT = nit<TB>();
   __shared__ double sk[KB::size];
   __shared__ double sx[KB::size];
@@ -1088,13 +1100,13 @@ __device__ __forceinline__ void resid_tile_body(const ResidJob& J, int tile, int
     }
   }
   if (WHICH == 1) {
-    const double bs = block_sum(e2);
+    const double bs = block_sum<ResidTile<D>::threads>(e2);
     if (threadIdx.x == 0) partial[block_id() - J.block0] = bs;
   }
 }
 
 template <int D, typename TS, int WHICH, int RM, int V>
-__global__ void __launch_bounds__(kBlock) k_resid_tile(const ResidJob* __restrict__ jobs, int njobs) {
+__global__ void __launch_bounds__(ResidTile<D>::threads) k_resid_tile(const ResidJob* __restrict__ jobs, int njobs) {
   int tile, s0, s1;
   const ResidJob J = job_tile_run(jobs, njobs, 1 << 30, tile, s0, s1);
   if (J.state && done_flag(J.state)) return;
@@ -1106,7 +1118,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_tile(const ResidJob* __restric
 }
 
 // ---------------------------------------------------------------------------
-// ||r_p||^2 and ||r_u||^2 of a pair (u, p), eq. (3.1), on the residual tiles:
+// ||r_p||^2 and ||r_u||^2 of a pair (u, p), eq. (3.1), on the up-sweep tiles:
 //   r_p = K u - A p - f,  r_u = f - K^T p - (K + K^T + A) u.
 // Both stencil operands (p and u) are staged per slab with their halo; a
 // block walks its slab run with u_{s-1}, u_{s+1} and p_{s+1} in registers and
