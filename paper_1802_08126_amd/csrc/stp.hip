@@ -111,6 +111,9 @@ long tiles_down_d(int dim, int nc) {
 long tiles_up_d(int dim, int n) {
   return dim == 1 ? tiles_for<1, UpTile<1>>(n) : dim == 2 ? tiles_for<2, UpTile<2>>(n) : tiles_for<3, UpTile<3>>(n);
 }
+long tiles_mid_d(int dim, int n) {
+  return dim == 1 ? tiles_for<1, MidTile<1>>(n) : dim == 2 ? tiles_for<2, MidTile<2>>(n) : tiles_for<3, MidTile<3>>(n);
+}
 long tiles_resid_d(int dim, int n) {
   return dim == 1 ? tiles_for<1, ResidTile<1>>(n) : dim == 2 ? tiles_for<2, ResidTile<2>>(n)
                                                              : tiles_for<3, ResidTile<3>>(n);
@@ -552,12 +555,13 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
       j.out = q.W2;                              // the cycles' right-hand side, reduced in place
       j.addout = -1;
       j.state = &q.state->done;
-      j.tiles = int(tiles_up_d(q.dim, q.n));
+      j.tiles = int(tiles_mid_d(q.dim, q.n));
       j.sb = sched_sb(j.tiles, q.N, c->sched.e[KN_MID]);
       S.nures.add(j, long(j.tiles) * ((q.N + j.sb - 1) / j.sb), j.op.cmode != CM_SLAB);
     }
   }
   S.mid = Site<TileJob>();
+  S.mid.threads = S.nures.threads = c->dim == 3 ? MidTile<3>::threads : kBlock;
   for (size_t i = 0; i < P; ++i) {
     if (!act(c, i)) continue;
     Problem& q = c->pr[i];
@@ -567,7 +571,7 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
     j.b = q.W1;                                // y = (2/N) tau A x   (W1 -> W2)
     j.out = q.W2;
     j.state = &q.state->done;
-    j.tiles = int(tiles_up_d(q.dim, q.n));
+    j.tiles = int(tiles_mid_d(q.dim, q.n));
     j.sb = sched_sb(j.tiles, q.N, c->sched.e[KN_MID]);
     S.mid.add(j, long(j.tiles) * ((q.N + j.sb - 1) / j.sb), j.op.cmode != CM_SLAB);
   }
@@ -2029,7 +2033,7 @@ std::vector<int> knob_sbs(stp_ctx* c, int k, int e) {
       continue;
     }
     if (k == KN_R0 || k == KN_R1) tiles = q.resid_tiles;
-    else if (k == KN_MID) tiles = tiles_up_d(q.dim, q.n);
+    else if (k == KN_MID) tiles = tiles_mid_d(q.dim, q.n);
     else if (k == KN_UPA0) {
       tiles = (mg && q.fuse_top > 0) ? tiles_up_d(q.dim, q.n) : -1;
       const VCycle& v = c->sites.vc[VC_A];   // register-pencil sites have a fixed shape

@@ -327,9 +327,17 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const FinJob* __restrict__ 
   const FinJob J = to_global(jobs[blockIdx.x]);
   DevState* st = J.st;
   if (st->done) return;
-  double v = 0.0;
-  for (long q = threadIdx.x; q < J.count; q += kBlock) v += J.partial[q];
-  const double s = block_sum(v);
+  // four independent partial sums per thread keep four loads in flight
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  long q = threadIdx.x;
+  for (; q + 3 * kBlock < J.count; q += 4 * kBlock) {
+    v0 += J.partial[q];
+    v1 += J.partial[q + kBlock];
+    v2 += J.partial[q + 2 * kBlock];
+    v3 += J.partial[q + 3 * kBlock];
+  }
+  for (; q < J.count; q += kBlock) v0 += J.partial[q];
+  const double s = block_sum((v0 + v1) + (v2 + v3));
   if (threadIdx.x == 0) {
     const double res = sqrt(s);
     const double rel = st->fnorm > 0 ? res / st->fnorm : res;   // f = 0: absolute residual

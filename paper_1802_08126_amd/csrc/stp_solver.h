@@ -399,7 +399,7 @@ struct Solver : SolverBase {
   stp_status apply_dr(Site<TileJob>& s) {
     if (s.jobs.empty()) return STP_OK;
     c->kt.level = 0;
-    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
+    const dim3 gr(unsigned(s.blocks)), bl(MidTile<D>::threads);
     const int nj = int(s.jobs.size());
     switch (s.variant()) {
       case 1: KLAUNCH_NAMED("k_apply_tile", (k_apply_tile<D, TS, TC, 1, 1>), gr, bl, 0, c->stream, s.dev, nj); break;

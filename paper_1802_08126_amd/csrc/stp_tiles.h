@@ -270,6 +270,9 @@ template <> struct UpTile<3> { static constexpr int X = 32, Y = 4, Z = 4; };
 // threads (four points per thread, fewer waves) 7.94 / 9.56.
 template <int D> struct ResidTile : UpTile<D> { static constexpr int threads = kBlock; };
 template <> struct ResidTile<3> { static constexpr int X = 32, Y = 8, Z = 4, threads = 512; };
+// the middle operator of the H-blocks (and the operator after the first of
+// several H cycles): the residuals' tile shape, for the same reason
+template <int D> struct MidTile : ResidTile<D> {};
 
 template <int D, typename T>
 __host__ __device__ inline long tiles_for(int n) {
@@ -920,9 +923,9 @@ __global__ void __launch_bounds__(kFuseMaxBlock) k_mg_fused(const FuseJob* __res
 template <int D, typename TS, typename TC, int RM, bool FIX>
 __device__ __forceinline__ void apply_tile_body(const TileJob& J, int tile, int s0, int s1, const TS* __restrict__ xv,
                                                 TS* __restrict__ yv) {
-  using T = UpTile<D>;
-  using KB = Box<D, T::X + 2, T::Y + 2, T::Z + 2>;
-  using TB = Box<D, T::X, T::Y, T::Z>;
+  using T = MidTile<D>;
+  using KB = Box<D, T::X + 2, T::Y + 2, T::Z + 2, T::threads>;
+  using TB = Box<D, T::X, T::Y, T::Z, T::threads>;
   __shared__ TC sk[KB::size];
   __shared__ TC sx[KB::size];
   const LevelOp L = J.op;
@@ -968,7 +971,7 @@ __device__ __forceinline__ void apply_tile_body(const TileJob& J, int tile, int 
 }
 
 template <int D, typename TS, typename TC, int RM, int V>
-__global__ void __launch_bounds__(kBlock) k_apply_tile(const TileJob* __restrict__ jobs, int njobs) {
+__global__ void __launch_bounds__(MidTile<D>::threads) k_apply_tile(const TileJob* __restrict__ jobs, int njobs) {
   int tile, s0, s1;
   const TileJob J = job_tile_run(jobs, njobs, 1 << 30, tile, s0, s1);
   if (J.state && done_flag(J.state)) return;
