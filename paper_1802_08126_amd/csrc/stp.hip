@@ -527,8 +527,9 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
   S.vc[VC_HX] = VCycle();
   S.vc[VC_HA] = VCycle();
   S.nures = Site<TileJob>();
-  S.nu[0] = Site<NuJob>();
-  S.nu[1] = Site<NuJob>();
+  S.nu[0] = Site<TileJob>();
+  S.nu[1] = Site<TileJob>();
+  S.nu[0].threads = S.nu[1].threads = c->dim == 3 ? MidTile<3>::threads : kBlock;
   if (multi_cycle(c)) {
     std::vector<VTop> topAX(P), topHX(P);
     for (size_t i = 0; i < P; ++i) {
@@ -536,11 +537,25 @@ void build_sites(stp_ctx* c, const std::vector<double*>& u, const std::vector<do
       topAX[i] = VTop{q.W1, q.Xnu, nullptr};
       topHX[i] = VTop{q.W2, q.Xnu, nullptr};
       if (!act(c, i)) continue;
-      const int pb = int((q.g0.npts + kBlock - 1) / kBlock);
-      const int sb = pick_sb(pb, q.N);
-      const long nb = long(pb) * ((q.N + sb - 1) / sb);
-      S.nu[0].add(NuJob{0, q.g0, family_op(q, 0, 0), pb, sb, q.W1, q.Xnu, nullptr, p[i], &q.state->done}, nb);
-      S.nu[1].add(NuJob{0, q.g0, family_op(q, 0, 1), pb, sb, q.W2, q.Xnu, q.W1, nullptr, &q.state->done}, nb);
+      // the operator tiles: b -= L x on the last cycle's correction x, and the
+      // output so far takes x (A: the float64 p, bound per solve; H: o)
+      TileJob j{};
+      j.gf = q.g0;
+      j.b = q.Xnu;
+      j.addout = -1;
+      j.state = &q.state->done;
+      j.tiles = int(tiles_mid_d(q.dim, q.n));
+      j.sb = sched_sb(j.tiles, q.N, c->sched.e[KN_MID]);
+      const long nb = long(j.tiles) * ((q.N + j.sb - 1) / j.sb);
+      j.op = family_op(q, 0, 0);
+      j.out = q.W1;
+      j.acc64 = p[i];
+      S.nu[0].add(j, nb, j.op.cmode != CM_SLAB);
+      j.op = family_op(q, 0, 1);
+      j.out = q.W2;
+      j.acc64 = nullptr;
+      j.acc_ts = q.W1;
+      S.nu[1].add(j, nb, j.op.cmode != CM_SLAB);
     }
     build_vcycle(c, S.vc[VC_AX], 0, topAX, false);
     build_vcycle(c, S.vc[VC_HX], 1, topHX, false);
@@ -691,7 +706,7 @@ stp_status bind_jobs(stp_ctx* c, const std::vector<double*>& u, const std::vecto
   if (!A.fused.empty())
     for (auto& j : A.fused[0].jobs) j.acc64 = acc_p[owner(j.state)];
   for (auto& j : A.tri.jobs) j.acc64 = acc_p[owner(j.state)];
-  for (auto& j : S.nu[0].jobs) j.t = acc_p[owner(j.state)];
+  for (auto& j : S.nu[0].jobs) j.acc64 = acc_p[owner(j.state)];
   for (auto& s : S.a6)
     for (auto& j : s.jobs) {
       const size_t i = owner(j.state);

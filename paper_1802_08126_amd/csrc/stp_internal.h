@@ -340,7 +340,7 @@ enum { VC_A = 0, VC_H1 = 1, VC_H2 = 2, VC_AX = 3, VC_HX = 4, VC_HA = 5 };
 struct Sites {
   Site<ResidJob> resid[2];
   VCycle vc[6];
-  Site<NuJob> nu[2];     // steps between the cycles of an application with nu > 1 (A, H)
+  Site<TileJob> nu[2];   // steps between the cycles of an application with nu > 1 (A, H): b -= L x, o += x
   Site<TileJob> nures;   // b -= L o after the first of nu_H > 1 H cycles (tiled operator)
   Site<TileJob> mid;
   std::vector<Site<TimeJob>> a4, a6;

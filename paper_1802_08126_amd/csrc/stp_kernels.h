@@ -433,6 +433,7 @@ struct TileJob {        // multigrid level kernels and the tile operator
   int addout;           // top-level output: 0 store, 1 add into out (up-sweep), -1 subtract from out (operator)
   const void* pk;       // register-pencil down-sweep: fixed field and its face sums at the fine
   const void* pd;       // level's interior nodes (TC), or null
+  void* acc_ts;         // operator between two cycles: the stored output o (TS), o += x, or null
 };
 
 struct PointJob {       // exact 1-D solves
@@ -447,19 +448,6 @@ struct PointJob {       // exact 1-D solves
   const int* state;
 };
 
-struct NuJob {          // steps between the cycles of one application (nu > 1)
-  long block0;
-  Geom g;
-  LevelOp op;           // level-0 operator of the cycles' family
-  int pblocks;          // blocks per slab run: ceil(points / kBlock)
-  int sb;               // slabs per block
-  void* b;              // cycle input, turned into the remaining residual in place (TS)
-  void* x;              // the correction of the last cycle (TS)
-  void* o;              // H family: the stored output (TS), else null
-  double* t;            // A family: the float64 accumulation target, else null
-  const int* state;
-};
-enum NuMode { NU_RES_X = 1, NU_ADD = 2 };
 
 struct TimeJob {        // transforms along the time axis
   long block0;
@@ -495,6 +483,7 @@ __device__ __forceinline__ TileJob to_global(TileJob j) {
   j.state = gmem(j.state);
   j.pk = gmem(j.pk);
   j.pd = gmem(j.pd);
+  j.acc_ts = gmem(j.acc_ts);
   return j;
 }
 __device__ __forceinline__ PointJob to_global(PointJob j) {
@@ -503,15 +492,6 @@ __device__ __forceinline__ PointJob to_global(PointJob j) {
   j.out = gmem(j.out);
   j.acc64 = gmem(j.acc64);
   j.scratch = gmem(j.scratch);
-  j.state = gmem(j.state);
-  return j;
-}
-__device__ __forceinline__ NuJob to_global(NuJob j) {
-  j.op = to_global(j.op);
-  j.b = gmem(j.b);
-  j.x = gmem(j.x);
-  j.o = gmem(j.o);
-  j.t = gmem(j.t);
   j.state = gmem(j.state);
   return j;
 }
@@ -1187,73 +1167,6 @@ __global__ void k_cast_add64(long n, const TS* __restrict__ a, double* __restric
   if (state && done_flag(state)) return;
   const long i = long(blockIdx.x) * kBlock + threadIdx.x;
   if (i < n) b[i] += ld<double>(a, i);
-}
-
-// Between two V-cycles of one application (nu > 1 cycles, each on the residual
-// the cycles before it leave) for the slab operators L_s of the job's family:
-//   b_s <- b_s - L_s x_s   (NU_RES_X)
-//   o_s <- o_s + x_s  or  t_s <- t_s + x_s (float64)   (NU_ADD)
-// A thread owns one spatial point for a run of sb slabs: the raw nodal fields
-// of its stencil are loaded once into registers and mixed per slab with the
-// slab's coefficient row.  b is read and written at the point only; x is
-// only read.
-template <int D, typename TS, typename TC, int RM>
-__global__ void __launch_bounds__(kBlock) k_nu_step(const NuJob* __restrict__ jobs, int njobs, int mode) {
-  const NuJob J = to_global(jobs[find_job(jobs, njobs)]);
-  if (J.state && done_flag(J.state)) return;
-  const int lb = int(block_id() - J.block0);
-  const int run = lb / J.pblocks;
-  const Geom g = J.g;
-  const long i = long(lb - run * J.pblocks) * kBlock + threadIdx.x;
-  if (i >= g.npts) return;
-  const LevelOp L = J.op;
-  const int s0 = run * J.sb, s1 = min(L.S, s0 + J.sb);
-  TS* b = (TS*)J.b;
-  const TS* x = (const TS*)J.x;
-  TS* o = (TS*)J.o;
-  const bool res = (mode & NU_RES_X) != 0;
-  // stencil geometry and raw fields: centre node, then the 2d faces (x-, x+, y-, y+, z-, z+)
-  int px = 0, py = 0, pz = 0;
-  decode<D>(i, g.n, px, py, pz);
-  const int n = g.n;
-  const long nn = n + 2;
-  const long node = node_of<D>(px, py, pz, n);
-  const long dnode[6] = {-1, 1, -nn, nn, -nn * nn, nn * nn};
-  const long di[6] = {-1, 1, -long(n), long(n), -long(n) * n, long(n) * n};
-  bool inside[6] = {px > 0, px < n - 1, py > 0, py < n - 1, pz > 0, pz < n - 1};
-  const TC* kap = (const TC*)L.kap;
-  TC kc[RM], kf[2 * D][RM];
-#pragma unroll
-  for (int r = 0; r < RM; ++r) {
-    const bool ok = res && r < L.R;
-    kc[r] = ok ? kap[r * g.nnodes + node] : TC(0);
-#pragma unroll
-    for (int f = 0; f < 2 * D; ++f) kf[f][r] = ok ? kap[r * g.nnodes + node + dnode[f]] : TC(0);
-  }
-  for (int s = s0; s < s1; ++s) {
-    const long k = long(s) * g.npts + i;
-    if (res) {
-      const SlabOp<TC> op = level_op<TC>(L, s);
-      TC kcs = op.c[0] * kc[0];
-#pragma unroll
-      for (int r = 1; r < RM; ++r) kcs += op.c[r] * kc[r];
-      const TS* ys = x + long(s) * g.npts;
-      TC dg = op.sigma, off = 0;
-#pragma unroll
-      for (int f = 0; f < 2 * D; ++f) {
-        TC w = kcs;
-#pragma unroll
-        for (int r = 0; r < RM; ++r) w += op.c[r] * kf[f][r];
-        dg += w;
-        if (inside[f]) off += w * ld<TC>(ys, i + di[f]);
-      }
-      st<TS, TC>(b, k, ld<TC>(b, k) - (dg * ld<TC>(ys, i) - off));
-    }
-    if (mode & NU_ADD) {
-      if (o) st<TS, TC>(o, k, ld<TC>(o, k) + ld<TC>(x, k));
-      if (J.t) J.t[k] += ld<double>(x, k);
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------

@@ -333,7 +333,7 @@ struct Solver : SolverBase {
     if (fam == 0) {
       for (int k = 1; k < nu; ++k) {
         if ((st = run_cycle(vx)) != STP_OK) return st;
-        if ((st = nu_step(fam, NU_RES_X | NU_ADD)) != STP_OK) return st;
+        if ((st = run_apply(c->sites.nu[0])) != STP_OK) return st;   // b -= L x, p += x
       }
       return run_cycle(c->sites.vc[which]);
     }
@@ -341,32 +341,9 @@ struct Solver : SolverBase {
     if ((st = run_apply(c->sites.nures)) != STP_OK) return st;   // b -= L o
     for (int k = 1; k + 1 < nu; ++k) {
       if ((st = run_cycle(vx)) != STP_OK) return st;
-      if ((st = nu_step(fam, NU_ADD | NU_RES_X)) != STP_OK) return st;
+      if ((st = run_apply(c->sites.nu[1])) != STP_OK) return st;   // b -= L x, o += x
     }
     return run_cycle(c->sites.vc[VC_HA]);
-  }
-
-  stp_status nu_step(int fam, int mode) {
-    Site<NuJob>& s = c->sites.nu[fam];
-    if (s.jobs.empty()) return STP_OK;
-    c->kt.level = 0;
-    const dim3 gr(unsigned(s.blocks)), bl(kBlock);
-    const int nj = int(s.jobs.size());
-#define STP_NU(D_, RM_) KLAUNCH_NAMED("k_nu_step", (k_nu_step<D_, TS, TC, RM_>), gr, bl, 0, c->stream, s.dev, nj, mode)
-    switch (c->dim * 10 + c->rm) {
-      case 11: STP_NU(1, 1); break;
-      case 12: STP_NU(1, 2); break;
-      case 14: STP_NU(1, 4); break;
-      case 21: STP_NU(2, 1); break;
-      case 22: STP_NU(2, 2); break;
-      case 24: STP_NU(2, 4); break;
-      case 31: STP_NU(3, 1); break;
-      case 32: STP_NU(3, 2); break;
-      default: STP_NU(3, 4);
-    }
-#undef STP_NU
-    LAUNCH_CHECK();
-    return STP_OK;
   }
 
   stp_status run_cycle(VCycle& vc) {

@@ -917,8 +917,10 @@ __global__ void __launch_bounds__(kFuseMaxBlock) k_mg_fused(const FuseJob* __res
 }
 
 // ---------------------------------------------------------------------------
-// y = L x (tile version; the middle reference operator of the H-blocks,
-// whose coefficients are the same for every slab)
+// y = L x (tile version): the middle reference operator of the H-blocks, whose
+// coefficients are the same for every slab; with addout < 0 the step between
+// two V-cycles of one application, b -= L x, and with acc_ts / acc64 also
+// o += x (H cycles) or p += x (A-tilde cycles, float64)
 // ---------------------------------------------------------------------------
 template <int D, typename TS, typename TC, int RM, bool FIX>
 __device__ __forceinline__ void apply_tile_body(const TileJob& J, int tile, int s0, int s1, const TS* __restrict__ xv,
@@ -929,6 +931,7 @@ __device__ __forceinline__ void apply_tile_body(const TileJob& J, int tile, int 
   __shared__ TC sk[KB::size];
   __shared__ TC sx[KB::size];
   const LevelOp L = J.op;
+  TS* const acc = (TS*)J.acc_ts;
   s1 = min(s1, L.S);
   if (s0 >= s1) return;
   const Geom g = J.gf;
@@ -965,6 +968,10 @@ __device__ __forceinline__ void apply_tile_body(const TileJob& J, int tile, int 
       const TC y = FIX ? sigma * sx[kq] + gamma * (dg * sx[kq] - off) : dg * sx[kq] - off;
       const int vo = vec_off<D>(jx, jy, jz, n);
       st<TS, TC>(ys, vo, J.addout < 0 ? ld<TC>(ys, vo) - y : y);
+      // between two cycles: the output so far takes the operand (o += x, or the
+      // float64 p += x of the A-tilde cycles)
+      if (acc) st<TS, TC>(acc + long(s) * g.npts, vo, ld<TC>(acc + long(s) * g.npts, vo) + sx[kq]);
+      if (J.acc64) J.acc64[long(s) * g.npts + vo] += double(sx[kq]);
     }
     __syncthreads();
   }
