@@ -360,15 +360,16 @@ void build_vcycle(stp_ctx* c, VCycle& vc, int fam, const std::vector<VTop>& top,
       // faster at level 0, slower at level 1)
       const bool add64 = l == 0 && acc;
       if (q.lv[l].pen[fam] && c->prec != STP_PREC_F64) {
-        const int puty = c->prec == STP_PREC_F64    ? (add64 ? PencilUpTY<double, EPI_ADD64>::v : PencilUpTY<double, EPI_STORE>::v)
-                         : c->prec == STP_PREC_F32 ? (add64 ? PencilUpTY<float, EPI_ADD64>::v : PencilUpTY<float, EPI_STORE>::v)
-                                                   : (add64 ? PencilUpTY<bf16, EPI_ADD64>::v : PencilUpTY<bf16, EPI_STORE>::v);
+        // the epilogue is a template parameter of the pencil kernel (one site per level
+        // holds one epilogue: the add into the output only on level 0 of the last H cycle)
+        const int epi = add64 ? EPI_ADD64 : u.addout ? EPI_ADDTS : EPI_STORE;
+        const int puty = c->prec == STP_PREC_F32 ? pencil_up_ty<float>(epi) : pencil_up_ty<bf16>(epi);
         u.tiles = int(pencil_tiles(q.lv[l + 1].n, puty));
         u.sb = kPencilSlabs;
         u.pk = q.lv[l].pk[fam];
         u.pd = q.lv[l].pd[fam];
         vc.upp[l].add(u, long(u.tiles) * ((q.N + u.sb - 1) / u.sb), true);
-        vc.upp[l].epi = add64 ? EPI_ADD64 : EPI_STORE;
+        vc.upp[l].epi = epi;
       } else {
         u.tiles = int(tiles_up_d(q.dim, q.lv[l].n));
         u.sb = sched_sb(u.tiles, q.N, (l == 0 && acc) ? c->sched.e[KN_UPA0] : c->sched.e[KN_UP0 + l]);

@@ -408,7 +408,7 @@ __device__ __forceinline__ TC slab_scale(const LevelOp& L, int s) {
 
 
 // Epilogue of the last smoothing sweep: write out, or add it into a float64 vector.
-enum Epi { EPI_STORE = 0, EPI_ADD64 = 1 };
+enum Epi { EPI_STORE = 0, EPI_ADD64 = 1, EPI_ADDTS = 2 };   // EPI_ADDTS: add into the TS output (pencils)
 
 // ---------------------------------------------------------------------------
 // merged launches

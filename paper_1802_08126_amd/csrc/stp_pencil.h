@@ -55,17 +55,23 @@ constexpr int kPencilMinNc = 24;    // coarser levels keep the tiled kernel (lan
 // coarse rows per pencil, set by measurement on 255^3 x 64: the down-sweep
 // (PencilTY) gains from taller pencils (fewer halo rows per owned row) while its
 // registers allow; the up-sweep storing a level (PencilUpTY, EPI_STORE) is
-// fastest at four rows, the one adding into the float64 iterate at two (its
-// extra float64 read-modify-write wants the occupancy of 144 VGPRs)
+// fastest at four rows, the ones adding into the float64 iterate or into their
+// output at two (the extra read-modify-write wants the occupancy of ~144 VGPRs)
 template <typename TC> struct PencilTY;
 template <> struct PencilTY<float> { static constexpr int v = 6; };
 template <> struct PencilTY<double> { static constexpr int v = 4; };
-template <typename TS, int EPI> struct PencilUpTY { static constexpr int v = EPI == EPI_ADD64 ? 2 : 4; };
+template <typename TS, int EPI> struct PencilUpTY { static constexpr int v = EPI == EPI_STORE ? 4 : 2; };
 template <int EPI> struct PencilUpTY<double, EPI> { static constexpr int v = 2; };
 // bfloat16 storage: two rows for both up-sweeps (the storing one needs 302 VGPRs
 // at four rows, one wave per SIMD, and took 9.5 ms against the tiles' 7.4; at two
 // rows, 146 VGPRs, 3.0 ms)
 template <int EPI> struct PencilUpTY<bf16, EPI> { static constexpr int v = 2; };
+// rows of the up-sweep pencil for a run-time epilogue (host-side tile counts)
+template <typename TS>
+constexpr int pencil_up_ty(int epi) {
+  return epi == EPI_STORE ? PencilUpTY<TS, EPI_STORE>::v
+         : epi == EPI_ADD64 ? PencilUpTY<TS, EPI_ADD64>::v : PencilUpTY<TS, EPI_ADDTS>::v;
+}
 
 // pencils of a level with nc coarse nodes per axis
 __host__ __device__ inline long pencil_tiles(int nc, int ty) {
@@ -352,7 +358,7 @@ __global__ void __launch_bounds__(kPencilThreads) k_mg_down_p3(const TileJob* __
 // coarse correction e), one wave per (pencil, slab) as in the down-sweep.  A
 // wave writes the fine nodes 2I - 1 and 2I of its coarse nodes I (and node n
 // when its pencil ends the axis); x2 is needed one node further.  Epilogue:
-// store x (J.addout: add it into the output) or add it into the float64 acc64.
+// store x (EPI_STORE), add it into the output (EPI_ADDTS) or into the float64 acc64 (EPI_ADD64).
 // The arithmetic per fine node is that of the tiled kernel.
 template <typename TS, typename TC, int TY, int EPI>
 __device__ __forceinline__ void mg_up_pencil(const TileJob& J, const PencilPos& P, TC omega) {
@@ -467,7 +473,7 @@ __device__ __forceinline__ void mg_up_pencil(const TileJob& J, const PencilPos& 
       if (q <= plast && r <= rlast && outx) {
         const long o = long(zb + q - 1) * nf2 + long(yb + r - 1) * nf + (x - 1);
         if (EPI == EPI_ADD64) a[i] = as[o];
-        else if (J.addout) a[i] = double(ld<TC>(os, o));
+        else if (EPI == EPI_ADDTS) a[i] = double(ld<TC>(os, o));
       }
     }
   };
@@ -499,7 +505,7 @@ __device__ __forceinline__ void mg_up_pencil(const TileJob& J, const PencilPos& 
   }
   load_plane(2, Bq[0], Kq[0], Dq[0]);
   load_plane(3, Bq[1], Kq[1], Dq[1]);
-  if (EPI == EPI_ADD64 || J.addout) load_acc(1, AC);
+  if (EPI != EPI_STORE) load_acc(1, AC);
 
   // plane p = p0 + u (p0 odd): writes plane p, computes x2 of plane q = p + 1
   // (slot q % 2 = u % 2; q even for even u, coarse plane c = q / 2)
@@ -538,8 +544,8 @@ __device__ __forceinline__ void mg_up_pencil(const TileJob& J, const PencilPos& 
         const TC v = one_m_omega * X2p[r] + WD[i] * (BB[i] + off);
         if (r <= rlast && outx) {
           const long o = po + long(yb + r - 1) * nf + (x - 1);
-          if (EPI == EPI_STORE) st<TS, TC>(os, o, J.addout ? TC(AC[i]) + v : v);
-          else as[o] = AC[i] + double(v);
+          if (EPI == EPI_ADD64) as[o] = AC[i] + double(v);
+          else st<TS, TC>(os, o, EPI == EPI_ADDTS ? TC(AC[i]) + v : v);
         }
       }
     }
@@ -556,7 +562,7 @@ __device__ __forceinline__ void mg_up_pencil(const TileJob& J, const PencilPos& 
         Kp[r] = kn[r];
       }
       if (p + 2 <= pend) load_plane(p + 3, bn, kn, dn);
-      if (EPI == EPI_ADD64 || J.addout) load_acc(p + 1, AC);
+      if (EPI != EPI_STORE) load_acc(p + 1, AC);
     }
     return true;
   };

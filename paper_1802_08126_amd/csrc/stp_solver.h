@@ -242,6 +242,9 @@ struct Solver : SolverBase {
     if (s.epi == EPI_ADD64)
       KLAUNCH_NAMED("k_mg_up_p3<add64>", (k_mg_up_p3<TS, TC, PencilUpTY<TS, EPI_ADD64>::v, EPI_ADD64>), gr, bl, 0, c->stream, s.dev,
                     nj, omegaJ());
+    else if (s.epi == EPI_ADDTS)
+      KLAUNCH_NAMED("k_mg_up_p3<addout>", (k_mg_up_p3<TS, TC, PencilUpTY<TS, EPI_ADDTS>::v, EPI_ADDTS>), gr, bl, 0,
+                    c->stream, s.dev, nj, omegaJ());
     else
       KLAUNCH_NAMED("k_mg_up_p3<store>", (k_mg_up_p3<TS, TC, PencilUpTY<TS, EPI_STORE>::v, EPI_STORE>), gr, bl, 0, c->stream,
                     s.dev, nj, omegaJ());
